@@ -1,0 +1,205 @@
+/*
+ * krt.h -- C ABI of libkrt, the MI355X (gfx950) Monte Carlo line-transfer pass.
+ *
+ * The pass follows "Kratos-linerad: GPU-accelerated Monte Carlo radiative
+ * transfer of lines with efficient imaging" (L. Wang): photon packets random-walk
+ * through a uniform Cartesian grid of line-centre opacity, bulk velocity and
+ * destruction probability; every interaction is a resonant scattering with
+ * partial frequency redistribution (Sec. 2.1.1-2.1.2, eq. riia-scatter); the
+ * packets tally the escaped spectrum, the camera-directed velocity-resolved
+ * scattering emissivity (Sec. 2.2.1, eq. scat-line) and the profile-weighted
+ * mean intensity that drives the level populations (Sec. 2.1.3).
+ *
+ * Conventions for every call:
+ *   - Return 0 (KRT_OK) or a negative status; krt_last_error() gives a message.
+ *   - Pointers named *_dev are DEVICE pointers on the context's device, owned
+ *     by the caller, never freed by the library.  Host pointers are read during
+ *     the call only.
+ *   - Work is enqueued on the HIP stream given to krt_create, in call order.
+ *     krt_mc_run and krt_levels_update synchronise that stream before they
+ *     return (they read back a status word), so outputs are ready on return.
+ *   - A context is not thread-safe; several contexts may coexist.
+ *   - Arrays over cells use cell = (k * ny + j) * nx + i (x fastest).
+ *   - Units: frequency x in Doppler widths (eq. xdef), velocities in units of
+ *     the thermal speed b, lengths in the grid's own unit.
+ */
+#ifndef KRT_H_
+#define KRT_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum krt_status {
+    KRT_OK = 0,
+    KRT_EINVAL = -1,   /* bad argument, detected on the host before any launch */
+    KRT_EHIP = -2,     /* a HIP runtime call failed */
+    KRT_EDEVICE = -3,  /* the kernels flagged an anomaly (see KRT_ST_* in counters) */
+    KRT_ESTATE = -4,   /* call out of order (e.g. run before grid/tables) */
+};
+
+/* boundary conditions per axis */
+enum { KRT_BC_VACUUM = 0, KRT_BC_PERIODIC = 1 };
+/* phase function of the re-emission about the incoming direction */
+enum { KRT_PHASE_ISO = 0, KRT_PHASE_DIPOLE = 1 };
+/* packet sources */
+enum { KRT_SRC_POINT = 0, KRT_SRC_PLANE_Z = 1, KRT_SRC_VOLUME = 2, KRT_SRC_BEAM = 3 };
+/* gas-frame emission profile */
+enum { KRT_PROF_DELTA = 0, KRT_PROF_VOIGT = 1, KRT_PROF_GAUSS = 2 };
+
+/* counters[] layout (int64) */
+enum {
+    KRT_C_EMITTED = 0, KRT_C_ESCAPED, KRT_C_DESTROYED, KRT_C_SCATTER, KRT_C_CROSS,
+    KRT_C_STUCK, KRT_C_MLP, KRT_C_STATUS, KRT_C_EMIS_DROP, KRT_C_SKIPPED_SCAT,
+    KRT_NCOUNTERS = 16
+};
+/* bits of counters[KRT_C_STATUS] */
+enum { KRT_ST_NAN = 1, KRT_ST_STUCK = 2, KRT_ST_SATURATE = 4, KRT_ST_CANCEL = 8 };
+
+typedef struct krt_ctx krt_ctx;
+
+/* Create a context on HIP device `hip_device`, enqueueing on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  *out receives the handle. */
+int krt_create(krt_ctx **out, int hip_device, void *hip_stream);
+void krt_destroy(krt_ctx *ctx);
+const char *krt_last_error(const krt_ctx *ctx);
+/* Number of compute units of the context's device (launch sizing). */
+int krt_device_cus(const krt_ctx *ctx);
+
+/* ---------------------------------------------------------------- grid --- */
+/* Uniform Cartesian grid with cell-wise constant fields (Sec. 2.2.1: the
+ * emissivity is recorded per cell of a mesh; eq. sigma0: k0 = n_l sigma_0).
+ * All field pointers are DEVICE pointers borrowed until the next upload or
+ * krt_destroy; the library copies nothing except the volume-emission weights,
+ * from which it builds an alias table (Walker/Vose) on the device.
+ * Errors: KRT_EINVAL for n <= 0, hi <= lo, bad bc, n_lines outside 1..8,
+ * k0 == NULL, or ncell >= 2^31. */
+typedef struct {
+    int32_t n[3];
+    double lo[3], hi[3];
+    int32_t bc[3];             /* KRT_BC_* per axis */
+    int32_t n_lines;           /* number of line slices in k0/eps/emis */
+    const float *k0_dev;       /* [n_lines][ncell] line-centre opacity per unit length */
+    const float *vel_dev;      /* [3][ncell] bulk velocity / b (SoA), or NULL = static */
+    const float *eps_dev;      /* [n_lines][ncell] destruction probability, or NULL = 0 */
+    const float *emis_dev;     /* [n_lines][ncell] volume emission weights, or NULL */
+} krt_grid_desc;
+int krt_grid_upload(krt_ctx *ctx, const krt_grid_desc *desc);
+
+/* --------------------------------------------------------------- tables --- */
+/* Per line: FP64 host construction of (i) the Voigt profile H(a, x) and its
+ * derivative for cubic Hermite lookup (Sec. 2.1, ph_mode 2's one-dimensional
+ * table at the run's damping parameter), (ii) the atom-velocity sampler for
+ * p(u | x) ~ exp(-u^2)/(a^2 + (x-u)^2) (Sec. 2.1.1, the USampler), stored as
+ * quantile tables of three pieces of the density, then uploaded as binary32
+ * and staged into LDS by the transport kernel.  Errors: KRT_EINVAL for
+ * a <= 0 or a > 1, phase not in KRT_PHASE_*, n_lines outside 1..8. */
+typedef struct {
+    double a;                  /* Voigt damping parameter A_ul / (4 pi nu_D) */
+    int32_t phase;             /* KRT_PHASE_ISO | KRT_PHASE_DIPOLE */
+    int32_t reserved;
+} krt_line_desc;
+int krt_tables_build(krt_ctx *ctx, const krt_line_desc *lines, int n_lines);
+
+/* ------------------------------------------------------------------ run --- */
+typedef struct {
+    int32_t line;              /* which line slice / table set to use */
+    int32_t source;            /* KRT_SRC_* */
+    double src_pos[3];         /* point / beam position; plane: z = src_pos[2] */
+    double src_dir[3];         /* beam direction (unit) */
+    int32_t src_profile;       /* KRT_PROF_* */
+    double src_x0;             /* line offset for KRT_PROF_DELTA */
+    int32_t spec_nbins;        /* escaped spectrum bins over [spec_lo, spec_hi) */
+    double spec_lo, spec_hi;
+    int32_t emis_nch;          /* emissivity channels over [ch_lo, ch_hi) (0 = off) */
+    double ch_lo, ch_hi;
+    double n_cam[3];           /* camera direction (unit) */
+    int32_t jbar;              /* 1 = tally mean intensity per cell */
+    int32_t accumulate;        /* 1 = add into the raw tallies, 0 = zero them first */
+    uint64_t packet_offset;    /* first packet id (resume / sharding) */
+    uint64_t max_events;       /* per packet; 0 = unlimited (2^32 - 2) */
+    int32_t escape_mode;       /* 0 = plain random walk */
+    int32_t wg_size;           /* launch geometry: threads per workgroup (0 = default) */
+    int32_t wg_per_cu;         /* workgroups per CU (0 = default) */
+    int32_t emis_frac_bits;    /* fixed-point bits of emissivity / jbar tallies (0 = 30) */
+    uint64_t norm_packets;     /* packets for the FP32 normalisation (0 = n_packets) */
+} krt_run_opts;
+
+/* Caller-allocated DEVICE buffers.  Raw tallies are int64 fixed point, so their
+ * sums are exact and independent of thread order and launch geometry:
+ *   spec_raw [spec_nbins + 2]   packet counts; [0] below spec_lo, [nb+1] at/above spec_hi
+ *   emis_raw [ncell][emis_nch]  sum of phase(g_cam) * 2^F over scatterings
+ *   jbar_raw [ncell]            sum of dl * H(a, x_gas) / sqrt(pi) * 2^F over segments
+ *   counters [KRT_NCOUNTERS]
+ *   packet_log [n_packets][8]   FP32 (x_lab, n_scat, outcome, n_x, n_y, n_z, cell, events)
+ * Finalised FP32 outputs (FP64 scaling), each optional:
+ *   spec  = spec_raw / (N dx_bin)                   per unit x, per emitted packet
+ *   emis  = emis_raw 2^-F / (4 pi N V_cell dx_ch)   per volume, steradian, unit x
+ *   jbar  = jbar_raw 2^-F / (4 pi N V_cell)
+ * where N is norm_packets (or n_packets). */
+typedef struct {
+    int64_t *spec_raw_dev;
+    int64_t *emis_raw_dev;
+    int64_t *jbar_raw_dev;
+    int64_t *counters_dev;
+    float *packet_log_dev;
+    float *spec_dev;
+    float *emis_dev;
+    float *jbar_dev;
+} krt_tallies;
+
+/* Run packets [packet_offset, packet_offset + n_packets) with Philox4x32-10
+ * key `seed`.  The tallies are a pure function of (grid, tables, options,
+ * seed, packet range).  Errors: KRT_EINVAL (n_packets == 0, missing required
+ * buffer, bad bins, n_cam not unit, line out of range), KRT_ESTATE (no grid or
+ * tables), KRT_EDEVICE (status bits set: NaN, stuck packets, saturation). */
+int krt_mc_run(krt_ctx *ctx, uint64_t n_packets, uint64_t seed, const krt_run_opts *opts,
+               krt_tallies *tallies);
+
+/* --------------------------------------------------------------- levels --- */
+/* Statistical equilibrium per cell (Sec. 2.1.3; eq. boltzmann for two levels,
+ * eq. eps for the destruction probability), FP64 on the device.  Levels
+ * 0..nl-1 with radiative lines l -> l+1 (l = 0..nl-2) feeding the transport.
+ * Rate matrix: A[u][l] decays, absorption Gamma_l per lower-level molecule with
+ * Gamma_l = 4 pi sqrt(pi) sigma0_l jbar_l (the track-length estimate of the
+ * absorption rate), stimulated emission (g_l/g_u) Gamma_l, collisions
+ * Cd[u][l] * ncoll downward and (g_u/g_l) exp(-(E_u - E_l)) Cd ncoll upward
+ * (detailed balance; E in units of kT); the last equation is replaced by
+ * sum_i n_i = ntot.  Outputs k0_l = n_l sigma0_l and
+ * eps_l = C_u,tot / (A[u][l] + C_u,tot) with C_u,tot the total collisional
+ * rate out of level u = l+1.  Host arrays: E[nl], g[nl], A[nl*nl], Cd[nl*nl],
+ * sigma0[nl-1].  Errors: KRT_EINVAL (nl outside 2..8, NULL arrays). */
+typedef struct {
+    int32_t n_levels;
+    const double *E, *g, *A, *Cd, *sigma0;   /* host */
+    const double *ncoll_dev, *ntot_dev;      /* device [ncell] */
+    double *pops_dev;                        /* device [ncell][nl], written */
+    float *k0_out_dev, *eps_out_dev;         /* device [nl-1][ncell], written (may be NULL) */
+} krt_levels_desc;
+int krt_levels_update(krt_ctx *ctx, const krt_levels_desc *desc,
+                      const float *jbar_dev /* [nl-1][ncell], NULL = no radiation */);
+
+/* ----------------------------------------------------------- diagnostics --- */
+/* Device-side evaluations of the individual steps, for parity tests.
+ * krt_debug_philox: out[i] = Philox4x32-10(ctr[i], key[i]); ctr [n][4],
+ *   key [n][2], out [n][4], uint32, device.
+ * krt_debug_bins: out[i] = bin of x[i] over nb bins in [lo, hi) (0 below,
+ *   nb+1 at/above, -1 NaN), the index rule of every tally.
+ * krt_debug_voigt: out[i] = H(a_line, x[i]) from the staged tables.
+ * krt_debug_upar: out[i] = u_par drawn for gas-frame frequency x from event
+ *   ev0 + i of packet `packet` (the words the transport uses). */
+int krt_debug_philox(krt_ctx *ctx, const uint32_t *ctr_dev, const uint32_t *key_dev,
+                     uint32_t *out_dev, int64_t n);
+int krt_debug_bins(krt_ctx *ctx, const float *x_dev, int64_t n, int32_t nb, double lo,
+                   double hi, int32_t *out_dev);
+int krt_debug_voigt(krt_ctx *ctx, int32_t line, const float *x_dev, int64_t n, float *out_dev);
+int krt_debug_upar(krt_ctx *ctx, int32_t line, float x, uint64_t seed, uint64_t packet,
+                   uint32_t ev0, int64_t n, float *out_dev);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KRT_H_ */

@@ -1,0 +1,477 @@
+// krt_api.hip -- the C ABI of libkrt (include/krt.h): argument validation,
+// device-side state, launches, and the per-cell statistical-equilibrium kernel.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "krt.h"
+#include "krt_internal.h"
+#include "krt_kernels.h"
+
+using namespace krt;
+
+struct krt_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int cus = 256;
+    std::string err;
+    // grid
+    bool have_grid = false;
+    krt_grid_desc grid{};
+    int64_t ncell = 0;
+    std::vector<float *> alias_prob;
+    std::vector<int *> alias_idx;
+    // tables
+    std::vector<float *> tab;
+    std::vector<krt_line_desc> lines;
+    // scratch
+    unsigned long long *work_counter = nullptr;
+    double *level_consts = nullptr;
+    int64_t *host_pinned = nullptr;
+};
+
+namespace {
+
+int fail(krt_ctx *c, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                    \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail((ctx), KRT_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+void free_grid(krt_ctx *c) {
+    for (auto p : c->alias_prob) if (p) (void)hipFree(p);
+    for (auto p : c->alias_idx) if (p) (void)hipFree(p);
+    c->alias_prob.clear();
+    c->alias_idx.clear();
+    c->have_grid = false;
+}
+
+void free_tables(krt_ctx *c) {
+    for (auto p : c->tab) if (p) (void)hipFree(p);
+    c->tab.clear();
+    c->lines.clear();
+}
+
+// Walker/Vose alias table over non-negative weights (FP64 build).
+void build_alias(const std::vector<float> &w, std::vector<float> &prob, std::vector<int> &alias) {
+    const int64_t n = (int64_t)w.size();
+    prob.assign(n, 0.0f);
+    alias.assign(n, 0);
+    double tot = 0.0;
+    for (float v : w) tot += (double)v;
+    std::vector<double> q(n);
+    std::vector<int64_t> small, large;
+    for (int64_t i = 0; i < n; ++i) {
+        q[i] = (double)w[i] * (double)n / tot;
+        (q[i] < 1.0 ? small : large).push_back(i);
+    }
+    while (!small.empty() && !large.empty()) {
+        int64_t s = small.back(); small.pop_back();
+        int64_t l = large.back();
+        prob[s] = (float)q[s];
+        alias[s] = (int)l;
+        q[l] -= 1.0 - q[s];
+        if (q[l] < 1.0) { large.pop_back(); small.push_back(l); }
+    }
+    for (int64_t i : large) { prob[i] = 1.0f; alias[i] = (int)i; }
+    for (int64_t i : small) { prob[i] = 1.0f; alias[i] = (int)i; }
+}
+
+bool valid_bins(int nb, double lo, double hi) {
+    return nb > 0 && nb < (1 << 24) && std::isfinite(lo) && std::isfinite(hi) && hi > lo;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ ctx ---
+extern "C" int krt_create(krt_ctx **out, int hip_device, void *hip_stream) {
+    if (!out) return KRT_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) return KRT_EINVAL;
+    krt_ctx *c = new krt_ctx();
+    c->device = hip_device;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    if (hipSetDevice(hip_device) != hipSuccess) { delete c; return KRT_EHIP; }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device) == hipSuccess && cus > 0)
+        c->cus = cus;
+    if (hipMalloc(&c->work_counter, sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc(&c->level_consts, sizeof(double) * 256) != hipSuccess ||
+        hipHostMalloc(&c->host_pinned, sizeof(int64_t) * 64, hipHostMallocDefault) != hipSuccess) {
+        krt_destroy(c);
+        return KRT_EHIP;
+    }
+    *out = c;
+    return KRT_OK;
+}
+
+extern "C" void krt_destroy(krt_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream); else (void)hipDeviceSynchronize();
+    free_grid(c);
+    free_tables(c);
+    if (c->work_counter) (void)hipFree(c->work_counter);
+    if (c->level_consts) (void)hipFree(c->level_consts);
+    if (c->host_pinned) (void)hipHostFree(c->host_pinned);
+    delete c;
+}
+
+extern "C" const char *krt_last_error(const krt_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+extern "C" int krt_device_cus(const krt_ctx *c) { return c ? c->cus : 0; }
+
+// ----------------------------------------------------------------- grid ---
+extern "C" int krt_grid_upload(krt_ctx *c, const krt_grid_desc *d) {
+    if (!c) return KRT_EINVAL;
+    if (!d) return fail(c, KRT_EINVAL, "grid desc is NULL");
+    int64_t ncell = 1;
+    for (int k = 0; k < 3; ++k) {
+        if (d->n[k] <= 0) return fail(c, KRT_EINVAL, "n[%d] = %d must be > 0", k, d->n[k]);
+        if (!(d->hi[k] > d->lo[k]) || !std::isfinite(d->lo[k]) || !std::isfinite(d->hi[k]))
+            return fail(c, KRT_EINVAL, "axis %d: need finite hi > lo", k);
+        if (d->bc[k] != KRT_BC_VACUUM && d->bc[k] != KRT_BC_PERIODIC)
+            return fail(c, KRT_EINVAL, "bc[%d] = %d invalid", k, d->bc[k]);
+        ncell *= d->n[k];
+    }
+    if (ncell >= (1LL << 31)) return fail(c, KRT_EINVAL, "too many cells (%lld)", (long long)ncell);
+    if (d->n_lines < 1 || d->n_lines > 8) return fail(c, KRT_EINVAL, "n_lines = %d outside 1..8", d->n_lines);
+    if (!d->k0_dev) return fail(c, KRT_EINVAL, "k0 is NULL");
+    HIPCHK(c, hipSetDevice(c->device));
+    free_grid(c);
+    c->grid = *d;
+    c->ncell = ncell;
+    c->alias_prob.assign(d->n_lines, nullptr);
+    c->alias_idx.assign(d->n_lines, nullptr);
+    if (d->emis_dev) {
+        std::vector<float> w(ncell), prob;
+        std::vector<int> alias;
+        for (int l = 0; l < d->n_lines; ++l) {
+            HIPCHK(c, hipMemcpyAsync(w.data(), d->emis_dev + (int64_t)l * ncell, sizeof(float) * ncell,
+                                     hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            double tot = 0.0;
+            for (float v : w) {
+                if (!(v >= 0.0f) || !std::isfinite(v)) return fail(c, KRT_EINVAL, "emission weights must be finite and >= 0");
+                tot += v;
+            }
+            if (!(tot > 0.0)) continue;  // no volume source for this line
+            build_alias(w, prob, alias);
+            HIPCHK(c, hipMalloc(&c->alias_prob[l], sizeof(float) * ncell));
+            HIPCHK(c, hipMalloc(&c->alias_idx[l], sizeof(int) * ncell));
+            HIPCHK(c, hipMemcpyAsync(c->alias_prob[l], prob.data(), sizeof(float) * ncell, hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(c->alias_idx[l], alias.data(), sizeof(int) * ncell, hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+        }
+    }
+    c->have_grid = true;
+    return KRT_OK;
+}
+
+// --------------------------------------------------------------- tables ---
+extern "C" int krt_tables_build(krt_ctx *c, const krt_line_desc *lines, int n_lines) {
+    if (!c) return KRT_EINVAL;
+    if (!lines || n_lines < 1 || n_lines > 8) return fail(c, KRT_EINVAL, "n_lines = %d outside 1..8", n_lines);
+    for (int l = 0; l < n_lines; ++l) {
+        if (!(lines[l].a > 0.0 && lines[l].a <= 1.0)) return fail(c, KRT_EINVAL, "line %d: a = %g outside (0, 1]", l, lines[l].a);
+        if (lines[l].phase != KRT_PHASE_ISO && lines[l].phase != KRT_PHASE_DIPOLE)
+            return fail(c, KRT_EINVAL, "line %d: phase %d invalid", l, lines[l].phase);
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    free_tables(c);
+    std::vector<float> tab;
+    for (int l = 0; l < n_lines; ++l) {
+        build_line_tables(lines[l].a, tab);
+        float *d = nullptr;
+        HIPCHK(c, hipMalloc(&d, sizeof(float) * kTabFloats));
+        c->tab.push_back(d);
+        HIPCHK(c, hipMemcpyAsync(d, tab.data(), sizeof(float) * kTabFloats, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        c->lines.push_back(lines[l]);
+    }
+    return KRT_OK;
+}
+
+// ------------------------------------------------------------------ run ---
+extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const krt_run_opts *o,
+                          krt_tallies *t) {
+    if (!c) return KRT_EINVAL;
+    if (!o || !t) return fail(c, KRT_EINVAL, "opts / tallies NULL");
+    if (!c->have_grid) return fail(c, KRT_ESTATE, "no grid uploaded");
+    if (c->tab.empty()) return fail(c, KRT_ESTATE, "no tables built");
+    if (n_packets == 0) return fail(c, KRT_EINVAL, "n_packets must be > 0");
+    if (o->line < 0 || o->line >= (int)c->tab.size() || o->line >= c->grid.n_lines)
+        return fail(c, KRT_EINVAL, "line %d out of range", o->line);
+    if (!t->spec_raw_dev || !t->counters_dev) return fail(c, KRT_EINVAL, "spec_raw and counters are required");
+    if (!valid_bins(o->spec_nbins, o->spec_lo, o->spec_hi)) return fail(c, KRT_EINVAL, "bad spectrum bins");
+    if (o->source < KRT_SRC_POINT || o->source > KRT_SRC_BEAM) return fail(c, KRT_EINVAL, "bad source %d", o->source);
+    if (o->src_profile < KRT_PROF_DELTA || o->src_profile > KRT_PROF_GAUSS) return fail(c, KRT_EINVAL, "bad profile");
+    if (o->source == KRT_SRC_VOLUME && !c->alias_prob[o->line])
+        return fail(c, KRT_EINVAL, "volume source needs emission weights for line %d", o->line);
+    if (o->source == KRT_SRC_BEAM) {
+        double nn = o->src_dir[0] * o->src_dir[0] + o->src_dir[1] * o->src_dir[1] + o->src_dir[2] * o->src_dir[2];
+        if (!(std::fabs(nn - 1.0) < 1e-6)) return fail(c, KRT_EINVAL, "src_dir must be a unit vector");
+    }
+    if (o->emis_nch < 0) return fail(c, KRT_EINVAL, "emis_nch < 0");
+    if (o->emis_nch > 0) {
+        if (!t->emis_raw_dev) return fail(c, KRT_EINVAL, "emis_nch > 0 needs emis_raw");
+        if (!valid_bins(o->emis_nch, o->ch_lo, o->ch_hi)) return fail(c, KRT_EINVAL, "bad channels");
+        double nn = o->n_cam[0] * o->n_cam[0] + o->n_cam[1] * o->n_cam[1] + o->n_cam[2] * o->n_cam[2];
+        if (!(std::fabs(nn - 1.0) < 1e-6)) return fail(c, KRT_EINVAL, "n_cam must be a unit vector");
+    }
+    if (o->jbar && !t->jbar_raw_dev) return fail(c, KRT_EINVAL, "jbar needs jbar_raw");
+    int fb = o->emis_frac_bits ? o->emis_frac_bits : 30;
+    if (fb < 8 || fb > 40) return fail(c, KRT_EINVAL, "emis_frac_bits %d outside 8..40", fb);
+    int block = o->wg_size ? o->wg_size : 512;
+    int per_cu = o->wg_per_cu ? o->wg_per_cu : 2;
+    if (block < 64 || block > 1024 || block % 64) return fail(c, KRT_EINVAL, "wg_size %d invalid", block);
+    if (per_cu < 1 || per_cu > 64) return fail(c, KRT_EINVAL, "wg_per_cu %d invalid", per_cu);
+    if (o->max_events > 0xFFFFFFFEull) return fail(c, KRT_EINVAL, "max_events too large");
+
+    HIPCHK(c, hipSetDevice(c->device));
+    const krt_grid_desc &g = c->grid;
+    const int64_t nc = c->ncell;
+    const int l = o->line;
+    const int nsb = o->spec_nbins + 2;
+    if (!o->accumulate) {
+        HIPCHK(c, launch_zero_i64(t->spec_raw_dev, nsb, c->stream));
+        HIPCHK(c, launch_zero_i64(t->counters_dev, KRT_NCOUNTERS, c->stream));
+        if (o->emis_nch > 0) HIPCHK(c, launch_zero_i64(t->emis_raw_dev, nc * o->emis_nch, c->stream));
+        if (o->jbar) HIPCHK(c, launch_zero_i64(t->jbar_raw_dev, nc, c->stream));
+    }
+    HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(c->work_counter), 1, c->stream));
+
+    RunParams P;
+    std::memset(&P, 0, sizeof(P));
+    for (int k = 0; k < 3; ++k) {
+        P.n[k] = g.n[k];
+        P.lo[k] = g.lo[k];
+        P.hi[k] = g.hi[k];
+        P.dxd[k] = (g.hi[k] - g.lo[k]) / g.n[k];
+        P.dx[k] = (float)P.dxd[k];
+        P.inv_dx[k] = (float)(1.0 / P.dxd[k]);
+        P.bc[k] = g.bc[k];
+        P.src_pos[k] = o->src_pos[k];
+        P.src_dir[k] = (float)o->src_dir[k];
+        P.n_cam[k] = (float)o->n_cam[k];
+    }
+    P.ncell = (int)nc;
+    P.k0 = g.k0_dev + (int64_t)l * nc;
+    if (g.vel_dev) { P.vx = g.vel_dev; P.vy = g.vel_dev + nc; P.vz = g.vel_dev + 2 * nc; }
+    P.eps = g.eps_dev ? g.eps_dev + (int64_t)l * nc : nullptr;
+    P.alias_prob = c->alias_prob[l];
+    P.alias_idx = c->alias_idx[l];
+    P.tab = c->tab[l];
+    P.a = (float)c->lines[l].a;
+    P.thd = (float)std::atan(kDelta / c->lines[l].a);
+    P.phase = c->lines[l].phase;
+    P.source = o->source;
+    P.src_profile = o->src_profile;
+    P.src_x0 = (float)o->src_x0;
+    P.spec_nb = o->spec_nbins;
+    P.spec_lo = o->spec_lo;
+    P.spec_hi = o->spec_hi;
+    P.spec_inv_w = (float)(o->spec_nbins / (o->spec_hi - o->spec_lo));
+    P.emis_nch = o->emis_nch;
+    P.ch_lo = o->ch_lo;
+    P.ch_hi = o->ch_hi;
+    P.ch_inv_w = o->emis_nch > 0 ? (float)(o->emis_nch / (o->ch_hi - o->ch_lo)) : 0.0f;
+    P.frac_scale = std::ldexp(1.0f, fb);
+    P.spec_raw = t->spec_raw_dev;
+    P.emis_raw = o->emis_nch > 0 ? t->emis_raw_dev : nullptr;
+    P.jbar_raw = o->jbar ? t->jbar_raw_dev : nullptr;
+    P.counters = t->counters_dev;
+    P.status = reinterpret_cast<uint32_t *>(t->counters_dev + KRT_C_STATUS);
+    P.plog = t->packet_log_dev;
+    P.n_packets = n_packets;
+    P.packet_offset = o->packet_offset;
+    P.max_events = o->max_events ? o->max_events : 0xFFFFFFFEull;
+    P.key0 = (uint32_t)seed;
+    P.key1 = (uint32_t)(seed >> 32);
+    P.work_counter = c->work_counter;
+    int grid = c->cus * per_cu;
+    HIPCHK(c, launch_transport(P, grid, block, c->stream));
+
+    // finalise (FP64 scaling -> FP32)
+    const double N = (double)(o->norm_packets ? o->norm_packets : n_packets);
+    const double vcell = P.dxd[0] * P.dxd[1] * P.dxd[2];
+    const double inv_f = std::ldexp(1.0, -fb);
+    const double four_pi = 4.0 * 3.14159265358979323846;
+    if (t->spec_dev)
+        HIPCHK(c, launch_finalize(t->spec_raw_dev, t->spec_dev, nsb, 1.0 / (N * (o->spec_hi - o->spec_lo) / o->spec_nbins), c->stream));
+    if (t->emis_dev && o->emis_nch > 0)
+        HIPCHK(c, launch_finalize(t->emis_raw_dev, t->emis_dev, nc * o->emis_nch,
+                                  inv_f / (four_pi * N * vcell * ((o->ch_hi - o->ch_lo) / o->emis_nch)), c->stream));
+    if (t->jbar_dev && o->jbar)
+        HIPCHK(c, launch_finalize(t->jbar_raw_dev, t->jbar_dev, nc, inv_f / (four_pi * N * vcell), c->stream));
+
+    HIPCHK(c, hipMemcpyAsync(c->host_pinned, t->counters_dev, sizeof(int64_t) * KRT_NCOUNTERS,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    int64_t st = c->host_pinned[KRT_C_STATUS];
+    if (st != 0) return fail(c, KRT_EDEVICE, "device status 0x%llx (nan=1 stuck=2 saturate=4)", (long long)st);
+    return KRT_OK;
+}
+
+// --------------------------------------------------------------- levels ---
+// Per-cell rate matrix, FP64 Gaussian elimination with partial pivoting.
+// consts: E[nl] g[nl] A[nl*nl] Cd[nl*nl] sigma0[nl-1]
+__global__ void levels_kernel(int nl, int64_t ncell, const double *K, const double *ncoll,
+                              const double *ntot, const float *jbar, double *pops, float *k0_out,
+                              float *eps_out) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    const double *E = K, *g = K + nl, *A = K + 2 * nl, *Cd = K + 2 * nl + nl * nl, *s0 = K + 2 * nl + 2 * nl * nl;
+    double R[8][8], M[8][8], b[8];
+    const double nc = ncoll[c];
+    for (int i = 0; i < nl; ++i)
+        for (int j = 0; j < nl; ++j) R[i][j] = 0.0;
+    for (int u = 1; u < nl; ++u)
+        for (int l = 0; l < u; ++l) {
+            double cd = Cd[u * nl + l] * nc;
+            double cu = cd * (g[u] / g[l]) * exp(-(E[u] - E[l]));
+            R[u][l] += A[u * nl + l] + cd;
+            R[l][u] += cu;
+        }
+    const double kGam = 4.0 * 3.14159265358979323846 * 1.77245385090551602730;
+    if (jbar)
+        for (int l = 0; l + 1 < nl; ++l) {
+            double G = kGam * s0[l] * (double)jbar[(int64_t)l * ncell + c];
+            R[l][l + 1] += G;
+            R[l + 1][l] += (g[l] / g[l + 1]) * G;
+        }
+    for (int i = 0; i < nl; ++i) {
+        double out = 0.0;
+        for (int j = 0; j < nl; ++j) {
+            M[i][j] = (j != i) ? R[j][i] : 0.0;
+            if (j != i) out += R[i][j];
+        }
+        M[i][i] = -out;
+        b[i] = 0.0;
+    }
+    for (int j = 0; j < nl; ++j) M[nl - 1][j] = 1.0;
+    b[nl - 1] = ntot[c];
+    for (int k = 0; k < nl; ++k) {
+        int p = k;
+        double mx = fabs(M[k][k]);
+        for (int i = k + 1; i < nl; ++i) if (fabs(M[i][k]) > mx) { mx = fabs(M[i][k]); p = i; }
+        if (p != k) {
+            for (int j = 0; j < nl; ++j) { double t = M[k][j]; M[k][j] = M[p][j]; M[p][j] = t; }
+            double t = b[k]; b[k] = b[p]; b[p] = t;
+        }
+        for (int i = k + 1; i < nl; ++i) {
+            double f = M[i][k] / M[k][k];
+            for (int j = k; j < nl; ++j) M[i][j] -= f * M[k][j];
+            b[i] -= f * b[k];
+        }
+    }
+    for (int i = nl - 1; i >= 0; --i) {
+        double s = b[i];
+        for (int j = i + 1; j < nl; ++j) s -= M[i][j] * b[j];
+        b[i] = s / M[i][i];
+    }
+    for (int i = 0; i < nl; ++i) pops[c * nl + i] = b[i];
+    for (int l = 0; l + 1 < nl; ++l) {
+        int u = l + 1;
+        if (k0_out) k0_out[(int64_t)l * ncell + c] = (float)(b[l] * s0[l]);
+        if (eps_out) {
+            double ctot = 0.0;
+            for (int j = 0; j < nl; ++j) if (j != u) {
+                double cd = (j < u) ? Cd[u * nl + j] * nc : Cd[j * nl + u] * nc * (g[j] / g[u]) * exp(-(E[j] - E[u]));
+                ctot += cd;
+            }
+            eps_out[(int64_t)l * ncell + c] = (float)(ctot / (A[u * nl + l] + ctot));
+        }
+    }
+}
+
+hipError_t krt::launch_levels(int nl, int64_t ncell, const double *consts, const double *ncoll,
+                              const double *ntot, const float *jbar, double *pops, float *k0_out,
+                              float *eps_out, hipStream_t s) {
+    int grid = (int)((ncell + 255) / 256);
+    hipLaunchKernelGGL(levels_kernel, dim3(grid), dim3(256), 0, s, nl, ncell, consts, ncoll, ntot, jbar, pops,
+                       k0_out, eps_out);
+    return hipGetLastError();
+}
+
+extern "C" int krt_levels_update(krt_ctx *c, const krt_levels_desc *d, const float *jbar_dev) {
+    if (!c) return KRT_EINVAL;
+    if (!d) return fail(c, KRT_EINVAL, "levels desc NULL");
+    if (!c->have_grid) return fail(c, KRT_ESTATE, "no grid uploaded");
+    const int nl = d->n_levels;
+    if (nl < 2 || nl > 8) return fail(c, KRT_EINVAL, "n_levels %d outside 2..8", nl);
+    if (!d->E || !d->g || !d->A || !d->Cd || !d->sigma0 || !d->ncoll_dev || !d->ntot_dev || !d->pops_dev)
+        return fail(c, KRT_EINVAL, "levels desc has NULL arrays");
+    std::vector<double> K;
+    K.insert(K.end(), d->E, d->E + nl);
+    K.insert(K.end(), d->g, d->g + nl);
+    K.insert(K.end(), d->A, d->A + nl * nl);
+    K.insert(K.end(), d->Cd, d->Cd + nl * nl);
+    K.insert(K.end(), d->sigma0, d->sigma0 + (nl - 1));
+    for (double v : K) if (!std::isfinite(v)) return fail(c, KRT_EINVAL, "non-finite level constant");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipMemcpyAsync(c->level_consts, K.data(), sizeof(double) * K.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, launch_levels(nl, c->ncell, c->level_consts, d->ncoll_dev, d->ntot_dev, jbar_dev, d->pops_dev,
+                            d->k0_out_dev, d->eps_out_dev, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return KRT_OK;
+}
+
+// ----------------------------------------------------------- diagnostics ---
+extern "C" int krt_debug_philox(krt_ctx *c, const uint32_t *ctr, const uint32_t *key, uint32_t *out, int64_t n) {
+    if (!c) return KRT_EINVAL;
+    if (!ctr || !key || !out || n <= 0) return fail(c, KRT_EINVAL, "bad philox args");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_debug_philox(ctr, key, out, n, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return KRT_OK;
+}
+
+extern "C" int krt_debug_bins(krt_ctx *c, const float *x, int64_t n, int32_t nb, double lo, double hi, int32_t *out) {
+    if (!c) return KRT_EINVAL;
+    if (!x || !out || n <= 0 || !valid_bins(nb, lo, hi)) return fail(c, KRT_EINVAL, "bad bins args");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_debug_bins(x, n, nb, lo, hi, out, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return KRT_OK;
+}
+
+extern "C" int krt_debug_voigt(krt_ctx *c, int32_t line, const float *x, int64_t n, float *out) {
+    if (!c) return KRT_EINVAL;
+    if (line < 0 || line >= (int)c->tab.size()) return fail(c, KRT_ESTATE, "line %d has no tables", line);
+    if (!x || !out || n <= 0) return fail(c, KRT_EINVAL, "bad voigt args");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_debug_voigt(c->tab[line], x, n, out, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return KRT_OK;
+}
+
+extern "C" int krt_debug_upar(krt_ctx *c, int32_t line, float x, uint64_t seed, uint64_t packet, uint32_t ev0,
+                              int64_t n, float *out) {
+    if (!c) return KRT_EINVAL;
+    if (line < 0 || line >= (int)c->tab.size()) return fail(c, KRT_ESTATE, "line %d has no tables", line);
+    if (!out || n <= 0 || !std::isfinite(x)) return fail(c, KRT_EINVAL, "bad upar args");
+    HIPCHK(c, hipSetDevice(c->device));
+    float a = (float)c->lines[line].a, thd = (float)std::atan(kDelta / c->lines[line].a);
+    HIPCHK(c, launch_debug_upar(c->tab[line], a, thd, x, (uint32_t)seed, (uint32_t)(seed >> 32), packet, ev0, n,
+                                out, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return KRT_OK;
+}

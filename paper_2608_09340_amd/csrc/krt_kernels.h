@@ -1,0 +1,81 @@
+// krt_kernels.h -- kernel parameter block and launch wrappers (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <cmath>
+#include <algorithm>
+
+namespace krt {
+
+// counter slots / status bits, as in include/krt.h
+enum {
+    KRT_C_EMITTED_I = 0, KRT_C_ESCAPED_I, KRT_C_DESTROYED_I, KRT_C_SCATTER_I, KRT_C_CROSS_I,
+    KRT_C_STUCK_I, KRT_C_MLP_I, KRT_C_STATUS_I, KRT_C_EMIS_DROP_I, KRT_C_SKIPPED_I,
+};
+#define KRT_C_EMITTED KRT_C_EMITTED_I
+#define KRT_C_ESCAPED KRT_C_ESCAPED_I
+#define KRT_C_DESTROYED KRT_C_DESTROYED_I
+#define KRT_C_SCATTER KRT_C_SCATTER_I
+#define KRT_C_CROSS KRT_C_CROSS_I
+#define KRT_C_STUCK KRT_C_STUCK_I
+#define KRT_C_EMIS_DROP KRT_C_EMIS_DROP_I
+enum { KRT_ST_NAN_BIT = 1, KRT_ST_STUCK_BIT = 2, KRT_ST_SATURATE_BIT = 4 };
+enum { KRT_SRC_POINT_I = 0, KRT_SRC_PLANE_I = 1, KRT_SRC_VOLUME_I = 2, KRT_SRC_BEAM_I = 3 };
+enum { KRT_PROF_DELTA_I = 0, KRT_PROF_VOIGT_I = 1, KRT_PROF_GAUSS_I = 2 };
+enum { KRT_PHASE_ISO_I = 0, KRT_PHASE_DIPOLE_I = 1 };
+
+// 1 / ln((300/8)^(1/15)): logarithmic row spacing of the sampler above |x| = 8
+constexpr float kRowInvLog = 4.1386840f;
+
+struct RunParams {
+    // grid
+    int n[3];
+    int ncell;
+    double lo[3], hi[3], dxd[3];
+    float dx[3], inv_dx[3];
+    int bc[3];
+    const float *k0, *vx, *vy, *vz, *eps;
+    const float *alias_prob;
+    const int *alias_idx;
+    // line
+    const float *tab;
+    float a, thd;
+    int phase;
+    // source
+    int source, src_profile;
+    float src_x0;
+    double src_pos[3];
+    float src_dir[3];
+    // tallies
+    int spec_nb;
+    double spec_lo, spec_hi;
+    float spec_inv_w;
+    int emis_nch;
+    double ch_lo, ch_hi;
+    float ch_inv_w;
+    float n_cam[3];
+    float frac_scale;  // 2^F
+    int64_t *spec_raw, *emis_raw, *jbar_raw, *counters;
+    uint32_t *status;
+    float *plog;
+    // work
+    uint64_t n_packets, packet_offset, max_events;
+    uint32_t key0, key1;
+    unsigned long long *work_counter;
+};
+
+hipError_t launch_transport(const RunParams &P, int grid, int block, hipStream_t s);
+hipError_t launch_finalize(const int64_t *raw, float *out, int64_t n, double scale, hipStream_t s);
+hipError_t launch_zero_i64(int64_t *p, int64_t n, hipStream_t s);
+hipError_t launch_debug_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out, int64_t n,
+                               hipStream_t s);
+hipError_t launch_debug_bins(const float *x, int64_t n, int nb, double lo, double hi, int32_t *out,
+                             hipStream_t s);
+hipError_t launch_debug_voigt(const float *tab, const float *x, int64_t n, float *out, hipStream_t s);
+hipError_t launch_debug_upar(const float *tab, float a, float thd, float x, uint32_t k0, uint32_t k1,
+                             uint64_t packet, uint32_t ev0, int64_t n, float *out, hipStream_t s);
+hipError_t launch_levels(int nl, int64_t ncell, const double *consts, const double *ncoll,
+                         const double *ntot, const float *jbar, double *pops, float *k0_out,
+                         float *eps_out, hipStream_t s);
+
+}  // namespace krt

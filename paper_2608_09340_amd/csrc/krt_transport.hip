@@ -1,0 +1,590 @@
+// krt_transport.hip -- gfx950 kernels of the Monte Carlo line-transfer pass.
+//
+// One photon packet per lane in a persistent wavefront pool (Sec. 2.3.2 runs
+// packets from a global work queue; here each wave refills its retired lanes
+// from one wave-aggregated atomic, so lanes stay busy while packets of very
+// different lengths finish).  Per loop iteration a lane does one flight
+// segment (to its next interaction or to the next cell face) and, on an
+// interaction, one resonant scattering.  Fields are SoA binary32 read once per
+// cell entry; the per-line Voigt and atom-velocity tables live in LDS.
+// Tallies are int64 fixed point: per-lane register caches for the current
+// cell, flushed with one atomic per (cell, channel) when the packet leaves.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "krt_internal.h"
+#include "krt_kernels.h"
+
+namespace krt {
+
+// ------------------------------------------------------------------ Philox ---
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two 32x32
+// multiplies with key schedule increments (W0, W1) between rounds.
+__device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    }
+    return c;
+}
+
+// uniform on (0,1): an odd multiple of 2^-24, exact in binary32
+__device__ __forceinline__ float u01(uint32_t w) {
+    return (float)(w >> 9) * 0x1p-23f + 0x1p-24f;
+}
+
+// ------------------------------------------------------------- fast math ---
+constexpr float kPiF = 3.14159265358979f;
+constexpr uint32_t kMaxCrossings = 1u << 30;  // per packet: a packet that never interacts is retired as stuck
+constexpr float kInvSqrtPiF = 0.564189583547756f;
+constexpr float kLn2F = 0.693147180559945f;
+__device__ __forceinline__ float f_log(float x) { return __builtin_amdgcn_logf(x) * kLn2F; }
+__device__ __forceinline__ float f_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896f); }
+__device__ __forceinline__ float f_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float f_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float f_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+// sin / cos of 2 pi r (the hardware takes revolutions)
+__device__ __forceinline__ float sin_rev(float r) { return __builtin_amdgcn_sinf(r); }
+__device__ __forceinline__ float cos_rev(float r) { return __builtin_amdgcn_cosf(r); }
+
+// ------------------------------------------------------------------- bins ---
+// Index rule shared by every tally: edges are binary32 values of
+// lo + (hi - lo) * k / nb computed in FP64; the bin is 1 + the largest k with
+// edge[k] <= x, 0 below edge[0], nb + 1 at or above edge[nb], -1 for NaN.
+__device__ __forceinline__ float bin_edge(double lo, double hi, int nb, int k) {
+    return (float)(lo + (hi - lo) * (double)k / (double)nb);
+}
+
+__device__ int bin_index(float x, int nb, double lo, double hi, float inv_w) {
+    if (!(x == x)) return -1;
+    if (x < bin_edge(lo, hi, nb, 0)) return 0;
+    if (x >= bin_edge(lo, hi, nb, nb)) return nb + 1;
+    int k = (int)((x - (float)lo) * inv_w);
+    k = max(0, min(nb - 1, k));
+    while (k > 0 && bin_edge(lo, hi, nb, k) > x) --k;
+    while (k < nb - 1 && bin_edge(lo, hi, nb, k + 1) <= x) ++k;
+    return k + 1;
+}
+
+// ----------------------------------------------------------- LDS lookups ---
+__device__ __forceinline__ float voigt_lds(const float *T, float xa) {
+    if (xa < 8.0f) {
+        float t = xa * 64.0f;
+        int i = max(0, min((int)t, kVoigtCoreN - 1));
+        float f = t - (float)i;
+        float4 c = *reinterpret_cast<const float4 *>(T + kOffVoigtCore + 4 * i);
+        return fmaf(f, fmaf(f, fmaf(f, c.w, c.z), c.y), c.x);
+    }
+    float w = 8.0f * f_rcp(xa);
+    float t = w * (float)kVoigtWingN;
+    int j = max(0, min((int)t, kVoigtWingN - 1));
+    float f = t - (float)j;
+    float4 c = *reinterpret_cast<const float4 *>(T + kOffVoigtWing + 4 * j);
+    float G = fmaf(f, fmaf(f, fmaf(f, c.w, c.z), c.y), c.x);
+    return G * w * w * (1.0f / 64.0f);
+}
+
+// Atom parallel velocity for gas-frame frequency x (Sec. 2.1.1): piece by r1,
+// quantile by r2, bilinear in (row of |x|, quantile node).
+__device__ __forceinline__ float upar_lds(const float *T, float x, float a, float thd,
+                                          float r1, float r2) {
+    float xa = fabsf(x);
+    float ps = 0.0f, plw = 1.0f;
+    if (xa < 8.0f) {
+        float pm = xa * 128.0f;
+        int im = max(0, min((int)pm, kMassN - 1));
+        float fm = pm - (float)im;
+        float2 m0 = *reinterpret_cast<const float2 *>(T + kOffMass + 2 * im);
+        float2 m1 = *reinterpret_cast<const float2 *>(T + kOffMass + 2 * im + 2);
+        ps = fmaf(fm, m1.x - m0.x, m0.x);
+        plw = fmaf(fm, m1.y - m0.y, m0.y);
+    }
+    float p;
+    if (xa < 8.0f) p = xa * 6.0f;
+    else p = fminf(48.0f + f_log(xa * 0.125f) * kRowInvLog, 63.0f);
+    int j = max(0, min((int)p, kRows - 2));
+    float fr = p - (float)j;
+    int kind = (r1 < ps) ? 0 : ((r1 < fmaf(1.0f - ps, plw, ps)) ? 1 : 2);
+    int nq = (kind == 0) ? kQS : ((kind == 1) ? kQL : kQR);
+    int off = (kind == 0) ? kOffSpike : ((kind == 1) ? kOffLeft : kOffRight);
+    float xi = (kind == 0) ? r2 : 1.0f - f_sqrt(1.0f - r2);
+    float qp = xi * (float)(nq - 1);
+    int k = max(0, min((int)qp, nq - 2));
+    float fq = qp - (float)k;
+    const float *r0 = T + off + j * nq + k;
+    float v0 = fmaf(fq, r0[1] - r0[0], r0[0]);
+    float v1 = fmaf(fq, r0[nq + 1] - r0[nq], r0[nq]);
+    float v = fmaf(fr, v1 - v0, v0);
+    float u;
+    if (kind == 0) {
+        float th = v * thd * (1.0f / (2.0f * kPiF));
+        u = xa + a * sin_rev(th) * f_rcp(cos_rev(th));
+    } else {
+        float s = (float)kDelta * f_exp(v);
+        u = (kind == 1) ? xa - s : xa + s;
+    }
+    return (x < 0.0f) ? -u : u;  // p(u | -x) = p(-u | x)
+}
+
+// Dipole phase (3/8)(1 + g^2): g = 2 sinh(asinh(4u - 2)/3).
+__device__ __forceinline__ float dipole_g(float u) {
+    float q = 4.0f * u - 2.0f;
+    float aq = fabsf(q);
+    float t = f_log(aq + f_sqrt(fmaf(aq, aq, 1.0f))) * (1.0f / 3.0f);
+    float e = f_exp(t);
+    float g = e - f_rcp(e);
+    return copysignf(g, q);
+}
+
+// --------------------------------------------------------- tally helpers ---
+__device__ __forceinline__ void atomic_add_i64(int64_t *p, int64_t v, uint32_t *status) {
+    unsigned long long old = atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)v);
+    if ((long long)old > (1LL << 62)) atomicOr(status, (uint32_t)KRT_ST_SATURATE_BIT);
+}
+
+struct EmisCache {  // four direct-mapped (channel -> fixed-point sum) slots
+    int ch[4];
+    int64_t acc[4];
+};
+
+__device__ __forceinline__ void emis_flush(EmisCache &E, int64_t *base, int nch, uint32_t *status) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        if (E.ch[s] >= 0) {
+            atomic_add_i64(base + E.ch[s], E.acc[s], status);
+            E.ch[s] = -1;
+            E.acc[s] = 0;
+        }
+    }
+}
+
+__device__ __forceinline__ void emis_add(EmisCache &E, int ch, int64_t v, int64_t *base,
+                                         uint32_t *status) {
+    int slot = ch & 3;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        if (s == slot) {
+            if (E.ch[s] != ch) {
+                if (E.ch[s] >= 0) atomic_add_i64(base + E.ch[s], E.acc[s], status);
+                E.ch[s] = ch;
+                E.acc[s] = 0;
+            }
+            E.acc[s] += v;
+        }
+    }
+}
+
+// wave-wide sum of a 64-bit value, then one atomic from the first active lane
+__device__ __forceinline__ void wave_add_counter(int64_t *dst, int64_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (__lane_id() == 0 && v != 0) atomicAdd(reinterpret_cast<unsigned long long *>(dst), (unsigned long long)v);
+}
+
+// --------------------------------------------------------------- kernel ---
+__global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
+    extern __shared__ float4 lds4[];
+    float *T = reinterpret_cast<float *>(lds4);
+    {
+        const float4 *src = reinterpret_cast<const float4 *>(P.tab);
+        for (int i = threadIdx.x; i < kTabFloats / 4; i += blockDim.x) lds4[i] = src[i];
+    }
+    __syncthreads();
+
+    const int lane = __lane_id();
+    const uint64_t lanemask_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const float a = P.a, thd = P.thd;
+
+    // lane state
+    bool have = false, done = false;
+    uint64_t pid = 0;
+    int ci = 0, cj = 0, ck = 0, cell = 0;
+    float fx = 0.f, fy = 0.f, fz = 0.f;
+    float nx = 0.f, ny = 0.f, nz = 1.f;
+    float x = 0.f, tau = 0.f;
+    uint32_t ev = 0, wa1 = 0, wa2 = 0, wa3 = 0;
+    float k0c = 0.f, vxc = 0.f, vyc = 0.f, vzc = 0.f, epsc = 0.f;
+    uint32_t nscat_pkt = 0, ncross_pkt = 0;
+    int outcome = 0;  // 1 escaped, 2 destroyed, 3 stuck
+    int64_t jacc = 0;
+    EmisCache E;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) { E.ch[s] = -1; E.acc[s] = 0; }
+    // per-lane counters
+    int64_t c_emit = 0, c_esc = 0, c_des = 0, c_scat = 0, c_cross = 0, c_stuck = 0, c_drop = 0;
+    uint32_t *status = P.status;
+    const float jscale = P.frac_scale * kInvSqrtPiF;
+
+    for (;;) {
+        // ---- refill retired lanes from the global queue -------------------
+        bool need = !have && !done;
+        uint64_t need_mask = __ballot(need);
+        if (need_mask) {
+            int cnt = __popcll(need_mask);
+            int leader = __ffsll((long long)need_mask) - 1;
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd(P.work_counter, (unsigned long long)cnt);
+            base = __shfl(base, leader, 64);
+            if (need) {
+                uint64_t idx = base + (uint64_t)__popcll(need_mask & lanemask_lt);
+                if (idx >= P.n_packets) {
+                    done = true;
+                } else {
+                    // ---- emission (event 0) ----------------------------------
+                    pid = P.packet_offset + idx;
+                    const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
+                    uint4 e0 = philox(make_uint4(0u, plo, phi, 0u), P.key0, P.key1);
+                    if (P.source == KRT_SRC_BEAM_I) {
+                        nx = P.src_dir[0]; ny = P.src_dir[1]; nz = P.src_dir[2];
+                    } else {
+                        float mu = 2.0f * u01(e0.x) - 1.0f;
+                        float st = f_sqrt(fmaxf(0.0f, 1.0f - mu * mu));
+                        float ph = u01(e0.y);
+                        nx = st * cos_rev(ph); ny = st * sin_rev(ph); nz = mu;
+                    }
+                    if (P.source == KRT_SRC_VOLUME_I) {
+                        uint4 e1 = philox(make_uint4(0u, plo, phi, 1u), P.key0, P.key1);
+                        int col = (int)__umulhi(e0.z, (uint32_t)P.ncell);
+                        cell = (u01(e0.w) < P.alias_prob[col]) ? col : P.alias_idx[col];
+                        ci = cell % P.n[0];
+                        cj = (cell / P.n[0]) % P.n[1];
+                        ck = cell / (P.n[0] * P.n[1]);
+                        fx = u01(e1.x); fy = u01(e1.y); fz = u01(e1.z);
+                    } else {
+                        int c3[3]; float f3[3];
+                        float nd[3] = {nx, ny, nz};
+                        double u2[2] = {0.0, 0.0};
+                        if (P.source == KRT_SRC_PLANE_I) {
+                            uint4 e1 = philox(make_uint4(0u, plo, phi, 1u), P.key0, P.key1);
+                            u2[0] = (double)u01(e1.x); u2[1] = (double)u01(e1.y);
+                        }
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            double X = P.src_pos[d];
+                            if (P.source == KRT_SRC_PLANE_I && d < 2) X = P.lo[d] + u2[d] * (P.hi[d] - P.lo[d]);
+                            double f = (X - P.lo[d]) / P.dxd[d];
+                            double fl = floor(f);
+                            int c = (int)fl;
+                            float fr = (float)(f - fl);
+                            if (fl == f && nd[d] < 0.0f) { c -= 1; fr = 1.0f; }
+                            if (c < 0) { c = 0; fr = 0.0f; }
+                            if (c >= P.n[d]) { c = P.n[d] - 1; fr = 1.0f; }
+                            c3[d] = c; f3[d] = fr;
+                        }
+                        ci = c3[0]; cj = c3[1]; ck = c3[2];
+                        fx = f3[0]; fy = f3[1]; fz = f3[2];
+                        cell = (ck * P.n[1] + cj) * P.n[0] + ci;
+                    }
+                    k0c = P.k0[cell];
+                    if (P.vx) { vxc = P.vx[cell]; vyc = P.vy[cell]; vzc = P.vz[cell]; }
+                    else { vxc = vyc = vzc = 0.0f; }
+                    epsc = P.eps ? P.eps[cell] : 0.0f;
+                    float xg = P.src_x0;
+                    if (P.src_profile != KRT_PROF_DELTA_I) {
+                        uint4 e2 = philox(make_uint4(0u, plo, phi, 2u), P.key0, P.key1);
+                        float rr = f_sqrt(-f_log(u01(e2.x)));
+                        float th = u01(e2.y);
+                        xg = rr * cos_rev(th);
+                        if (P.src_profile == KRT_PROF_VOIGT_I) {
+                            float c = u01(e2.z) - 0.5f;  // Cauchy(a): a tan(pi c)
+                            xg += a * sin_rev(0.5f * c) * f_rcp(cos_rev(0.5f * c));
+                        }
+                    }
+                    x = xg + nx * vxc + ny * vyc + nz * vzc;
+                    ev = 1;
+                    uint4 A = philox(make_uint4(1u, plo, phi, 0u), P.key0, P.key1);
+                    tau = -f_log(u01(A.x));
+                    wa1 = A.y; wa2 = A.z; wa3 = A.w;
+                    nscat_pkt = 0;
+                    ncross_pkt = 0;
+                    jacc = 0;
+                    have = true;
+                    c_emit += 1;
+                }
+            }
+        }
+        if (__ballot(have) == 0ull) break;
+        if (!have) continue;
+
+        // ---- one flight segment ------------------------------------------
+        float xc = x - (nx * vxc + ny * vyc + nz * vzc);
+        float H = (k0c > 0.0f) ? voigt_lds(T, fabsf(xc)) : 0.0f;
+        float kap = k0c * H;
+        float tx = (nx > 0.0f) ? (1.0f - fx) * P.dx[0] * f_rcp(nx) : ((nx < 0.0f) ? fx * P.dx[0] * f_rcp(-nx) : INFINITY);
+        float ty = (ny > 0.0f) ? (1.0f - fy) * P.dx[1] * f_rcp(ny) : ((ny < 0.0f) ? fy * P.dx[1] * f_rcp(-ny) : INFINITY);
+        float tz = (nz > 0.0f) ? (1.0f - fz) * P.dx[2] * f_rcp(nz) : ((nz < 0.0f) ? fz * P.dx[2] * f_rcp(-nz) : INFINITY);
+        int ax = 0;
+        float dmin = tx;
+        if (ty < dmin) { dmin = ty; ax = 1; }
+        if (tz < dmin) { dmin = tz; ax = 2; }
+        dmin = fmaxf(dmin, 0.0f);
+
+        if (kap > 0.0f && kap * dmin >= tau) {
+            // interaction inside the cell
+            float l = tau * f_rcp(kap);
+            fx = fminf(fmaxf(fmaf(l * nx, P.inv_dx[0], fx), 0.0f), 1.0f);
+            fy = fminf(fmaxf(fmaf(l * ny, P.inv_dx[1], fy), 0.0f), 1.0f);
+            fz = fminf(fmaxf(fmaf(l * nz, P.inv_dx[2], fz), 0.0f), 1.0f);
+            if (P.jbar_raw) jacc += (int64_t)__float2ll_rn(l * H * jscale);
+
+            // ---- resonant scattering (event ev) --------------------------
+            const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
+            bool destroyed = (P.eps != nullptr) && (u01(wa1) < epsc);
+            if (destroyed) {
+                c_des += 1;
+                outcome = 2;
+                have = false;
+            } else {
+                uint4 B = philox(make_uint4(ev, plo, phi, 1u), P.key0, P.key1);
+                float upar = upar_lds(T, xc, a, thd, u01(wa2), u01(wa3));
+                float rr = f_sqrt(-f_log(u01(B.x)));
+                float th = u01(B.y);
+                float up1 = rr * cos_rev(th), up2 = rr * sin_rev(th);
+                float g = (P.phase == KRT_PHASE_DIPOLE_I) ? dipole_g(u01(B.z)) : 2.0f * u01(B.z) - 1.0f;
+                float psi = u01(B.w);
+                float sg = f_sqrt(fmaxf(0.0f, 1.0f - g * g));
+                // orthonormal basis about n (Duff et al. 2017)
+                float sgn = copysignf(1.0f, nz);
+                float A_ = -f_rcp(sgn + nz);
+                float B_ = nx * ny * A_;
+                float e1x = 1.0f + sgn * nx * nx * A_, e1y = sgn * B_, e1z = -sgn * nx;
+                float e2x = B_, e2y = sgn + ny * ny * A_, e2z = -ny;
+                float cp = cos_rev(psi), sp = sin_rev(psi);
+                float ox = g * nx + sg * (cp * e1x + sp * e2x);
+                float oy = g * ny + sg * (cp * e1y + sp * e2y);
+                float oz = g * nz + sg * (cp * e1z + sp * e2z);
+                float rn = f_rsq(ox * ox + oy * oy + oz * oz);
+                ox *= rn; oy *= rn; oz *= rn;
+                // eq. riia-scatter
+                float xo = xc + upar * (g - 1.0f) + sg * (up1 * cp + up2 * sp);
+                if (P.emis_raw) {
+                    float gc = nx * P.n_cam[0] + ny * P.n_cam[1] + nz * P.n_cam[2];
+                    float upc = up1 * (e1x * P.n_cam[0] + e1y * P.n_cam[1] + e1z * P.n_cam[2]) +
+                                up2 * (e2x * P.n_cam[0] + e2y * P.n_cam[1] + e2z * P.n_cam[2]);
+                    float xcam = xc + upar * (gc - 1.0f) + upc +
+                                 (P.n_cam[0] * vxc + P.n_cam[1] * vyc + P.n_cam[2] * vzc);
+                    int kb = bin_index(xcam, P.emis_nch, P.ch_lo, P.ch_hi, P.ch_inv_w);
+                    if (kb >= 1 && kb <= P.emis_nch) {
+                        float wph = (P.phase == KRT_PHASE_DIPOLE_I) ? 0.75f * (1.0f + gc * gc) : 1.0f;
+                        emis_add(E, kb - 1, (int64_t)__float2ll_rn(wph * P.frac_scale),
+                                 P.emis_raw + (int64_t)cell * P.emis_nch, status);
+                    } else {
+                        c_drop += 1;
+                    }
+                }
+                nx = ox; ny = oy; nz = oz;
+                x = xo + nx * vxc + ny * vyc + nz * vzc;
+                nscat_pkt += 1;
+                c_scat += 1;
+                // next event
+                ev += 1;
+                if ((uint64_t)ev > P.max_events) {
+                    c_stuck += 1;
+                    atomicOr(status, (uint32_t)KRT_ST_STUCK_BIT);
+                    outcome = 3;
+                    have = false;
+                } else {
+                    uint4 A = philox(make_uint4(ev, plo, phi, 0u), P.key0, P.key1);
+                    tau = -f_log(u01(A.x));
+                    wa1 = A.y; wa2 = A.z; wa3 = A.w;
+                }
+            }
+        } else {
+            // cross the face of axis ax
+            tau -= kap * dmin;
+            if (P.jbar_raw) jacc += (int64_t)__float2ll_rn(dmin * H * jscale);
+            float adv = dmin;
+            if (ax != 0) fx = fminf(fmaxf(fmaf(adv * nx, P.inv_dx[0], fx), 0.0f), 1.0f);
+            if (ax != 1) fy = fminf(fmaxf(fmaf(adv * ny, P.inv_dx[1], fy), 0.0f), 1.0f);
+            if (ax != 2) fz = fminf(fmaxf(fmaf(adv * nz, P.inv_dx[2], fz), 0.0f), 1.0f);
+            c_cross += 1;
+            ncross_pkt += 1;
+            // leaving the cell: flush its register tallies
+            if (P.jbar_raw && jacc != 0) { atomic_add_i64(P.jbar_raw + cell, jacc, status); jacc = 0; }
+            if (P.emis_raw) emis_flush(E, P.emis_raw + (int64_t)cell * P.emis_nch, P.emis_nch, status);
+            bool escaped = false;
+            if (ax == 0) {
+                int st = (nx > 0.0f) ? 1 : -1;
+                ci += st; fx = (st > 0) ? 0.0f : 1.0f;
+                if (ci < 0 || ci >= P.n[0]) { if (P.bc[0]) ci = (ci < 0) ? P.n[0] - 1 : 0; else escaped = true; }
+            } else if (ax == 1) {
+                int st = (ny > 0.0f) ? 1 : -1;
+                cj += st; fy = (st > 0) ? 0.0f : 1.0f;
+                if (cj < 0 || cj >= P.n[1]) { if (P.bc[1]) cj = (cj < 0) ? P.n[1] - 1 : 0; else escaped = true; }
+            } else {
+                int st = (nz > 0.0f) ? 1 : -1;
+                ck += st; fz = (st > 0) ? 0.0f : 1.0f;
+                if (ck < 0 || ck >= P.n[2]) { if (P.bc[2]) ck = (ck < 0) ? P.n[2] - 1 : 0; else escaped = true; }
+            }
+            if (escaped) {
+                c_esc += 1;
+                int b = bin_index(x, P.spec_nb, P.spec_lo, P.spec_hi, P.spec_inv_w);
+                if (b < 0) atomicOr(status, (uint32_t)KRT_ST_NAN_BIT);
+                else atomicAdd(reinterpret_cast<unsigned long long *>(P.spec_raw + b), 1ull);
+                outcome = 1;
+                have = false;
+            } else if (ncross_pkt > kMaxCrossings) {
+                c_stuck += 1;
+                atomicOr(status, (uint32_t)KRT_ST_STUCK_BIT);
+                outcome = 3;
+                have = false;
+            } else {
+                cell = (ck * P.n[1] + cj) * P.n[0] + ci;
+                k0c = P.k0[cell];
+                if (P.vx) { vxc = P.vx[cell]; vyc = P.vy[cell]; vzc = P.vz[cell]; }
+                epsc = P.eps ? P.eps[cell] : 0.0f;
+            }
+        }
+        if (!have) {
+            // packet retired: flush the tallies of its last cell, log it
+            if (P.jbar_raw && jacc != 0) { atomic_add_i64(P.jbar_raw + cell, jacc, status); jacc = 0; }
+            if (P.emis_raw) emis_flush(E, P.emis_raw + (int64_t)cell * P.emis_nch, P.emis_nch, status);
+            if (P.plog) {
+                float *L = P.plog + 8 * (pid - P.packet_offset);
+                L[0] = x; L[1] = (float)nscat_pkt; L[2] = (float)outcome;
+                L[3] = nx; L[4] = ny; L[5] = nz;
+                L[6] = (float)cell; L[7] = (float)ev;
+            }
+            outcome = 0;
+        }
+    }
+
+    wave_add_counter(P.counters + KRT_C_EMITTED, c_emit);
+    wave_add_counter(P.counters + KRT_C_ESCAPED, c_esc);
+    wave_add_counter(P.counters + KRT_C_DESTROYED, c_des);
+    wave_add_counter(P.counters + KRT_C_SCATTER, c_scat);
+    wave_add_counter(P.counters + KRT_C_CROSS, c_cross);
+    wave_add_counter(P.counters + KRT_C_STUCK, c_stuck);
+    wave_add_counter(P.counters + KRT_C_EMIS_DROP, c_drop);
+}
+
+// -------------------------------------------------------------- finalise ---
+__global__ void finalize_kernel(const int64_t *raw, float *out, int64_t n, double scale) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) out[i] = (float)((double)raw[i] * scale);
+}
+
+__global__ void zero_i64_kernel(int64_t *p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = 0;
+}
+
+// ----------------------------------------------------------- diagnostics ---
+__global__ void debug_philox_kernel(const uint32_t *ctr, const uint32_t *key, uint32_t *out, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint4 c = make_uint4(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3]);
+    uint4 r = philox(c, key[2 * i], key[2 * i + 1]);
+    out[4 * i] = r.x; out[4 * i + 1] = r.y; out[4 * i + 2] = r.z; out[4 * i + 3] = r.w;
+}
+
+__global__ void debug_bins_kernel(const float *x, int64_t n, int nb, double lo, double hi, float inv_w,
+                                  int32_t *out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = bin_index(x[i], nb, lo, hi, inv_w);
+}
+
+__global__ void debug_voigt_kernel(const float *tab, const float *x, int64_t n, float *out) {
+    extern __shared__ float4 lds4[];
+    float *T = reinterpret_cast<float *>(lds4);
+    const float4 *src = reinterpret_cast<const float4 *>(tab);
+    for (int i = threadIdx.x; i < kTabFloats / 4; i += blockDim.x) lds4[i] = src[i];
+    __syncthreads();
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = voigt_lds(T, fabsf(x[i]));
+}
+
+__global__ void debug_upar_kernel(const float *tab, float a, float thd, float x, uint32_t k0, uint32_t k1,
+                                  uint64_t packet, uint32_t ev0, int64_t n, float *out) {
+    extern __shared__ float4 lds4[];
+    float *T = reinterpret_cast<float *>(lds4);
+    const float4 *src = reinterpret_cast<const float4 *>(tab);
+    for (int i = threadIdx.x; i < kTabFloats / 4; i += blockDim.x) lds4[i] = src[i];
+    __syncthreads();
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint4 A = philox(make_uint4(ev0 + (uint32_t)i, (uint32_t)packet, (uint32_t)(packet >> 32), 0u), k0, k1);
+    out[i] = upar_lds(T, x, a, thd, u01(A.z), u01(A.w));
+}
+
+// ---------------------------------------------------------------- launch ---
+hipError_t launch_transport(const RunParams &P, int grid, int block, hipStream_t s) {
+    size_t lds = sizeof(float) * kTabFloats;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(mc_transport_kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(mc_transport_kernel, dim3(grid), dim3(block), lds, s, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const int64_t *raw, float *out, int64_t n, double scale, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int grid = (int)std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(finalize_kernel, dim3(grid), dim3(256), 0, s, raw, out, n, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_i64(int64_t *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int grid = (int)std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(zero_i64_kernel, dim3(grid), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out, int64_t n, hipStream_t s) {
+    int grid = (int)((n + 255) / 256);
+    hipLaunchKernelGGL(debug_philox_kernel, dim3(grid), dim3(256), 0, s, ctr, key, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_bins(const float *x, int64_t n, int nb, double lo, double hi, int32_t *out, hipStream_t s) {
+    int grid = (int)((n + 255) / 256);
+    float inv_w = (float)((double)nb / (hi - lo));
+    hipLaunchKernelGGL(debug_bins_kernel, dim3(grid), dim3(256), 0, s, x, n, nb, lo, hi, inv_w, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_voigt(const float *tab, const float *x, int64_t n, float *out, hipStream_t s) {
+    size_t lds = sizeof(float) * kTabFloats;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(debug_voigt_kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    int grid = (int)((n + 255) / 256);
+    hipLaunchKernelGGL(debug_voigt_kernel, dim3(grid), dim3(256), lds, s, tab, x, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_upar(const float *tab, float a, float thd, float x, uint32_t k0, uint32_t k1,
+                             uint64_t packet, uint32_t ev0, int64_t n, float *out, hipStream_t s) {
+    size_t lds = sizeof(float) * kTabFloats;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(debug_upar_kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    int grid = (int)((n + 255) / 256);
+    hipLaunchKernelGGL(debug_upar_kernel, dim3(grid), dim3(256), lds, s, tab, a, thd, x, k0, k1, packet, ev0, n, out);
+    return hipGetLastError();
+}
+
+}  // namespace krt
