@@ -1,0 +1,163 @@
+"""Benchmark of the Monte Carlo line-transfer pass on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--packets N] [--workload sphere64]
+
+A step is one krt_mc_run over a batch of packets of the static-sphere workload
+(64^3 grid, radial line-centre depth 1e6, a = 4.7e-4, dipole phase, central
+point source, escaped spectrum 256 bins on [-80, 80), emissivity 64^3 x 32
+channels on [-24, 24) toward +x): emission, flights, resonant scatterings,
+int64 tallies and the FP32 finalise, with grid and tables already resident in
+HBM.  The default batch is the full 1e6 packets of that workload.  Warmup steps
+use 1% batches from a disjoint packet range.
+
+Prints one JSON line: whole-job scatterings/s, the ALU roofline of the
+transport kernel (HIP-event duration of that kernel, from the library), and the
+FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# VALU issue slots per scattering of the plain transport, from the step list of
+# the method (one flight segment ending in an interaction, one resonant
+# scattering, its tallies).  Quarter-rate instructions (32x32->64 integer
+# multiply, transcendental) cost 4 slots.  Itemised in the design doc.
+LEDGER = {
+    "philox_2_blocks": 2 * 10 * (2 * 4 + 4),     # 2 wide multiplies + 4 xor/add per round
+    "uniform_maps_8": 8 * 3,
+    "flight": 3 + 2 + 7 + 1 + 3 * (4 + 3) + 4 + 2 + (4 + 1) + 3 * 4,  # gas frame, Voigt, DDA, step, move
+    "tau_log": 4 + 1,
+    "upar_sampler": 12 + 15 + 8 + (4 + 4 + 4 + 3) + 4,  # pieces, row/node, bilinear, tan, sqrt map
+    "box_muller": 4 + 4 + 4 + 4 + 2,
+    "direction": 2 + 8 + 12 + 12 + (6 + 4),         # g, sincos psi, basis, rotate, renormalise
+    "frequency_update": 6 + 3,
+    "counters": 3,
+}
+LEDGER_DIPOLE = 4 * 4 + 6          # log, sqrt, exp, rcp of the dipole inversion + FMAs
+LEDGER_EMIS = 6 + 5 + 8 + 3 + 2 + 8  # camera projection, x_cam, channel, phase weight, fixed point, cache
+PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12  # 39.32 T lane-slots/s (non-packed 32-bit VALU)
+
+
+def ledger_per_scatter(dipole: bool, emis: bool) -> int:
+    return sum(LEDGER.values()) + (LEDGER_DIPOLE if dipole else 0) + (LEDGER_EMIS if emis else 0)
+
+
+def cpu_info():
+    model = platform.processor() or ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1
+
+
+def cpu_baseline(prob, seconds_target=15.0):
+    """The FP64 oracle as it stands, on all host cores, on a bounded sample."""
+    import oracle
+    model, ncpu = cpu_info()
+    threads = ncpu
+    n = threads  # first: one packet per thread to size the sample
+    t = time.perf_counter()
+    r = oracle.mc_run(prob, n, seed=0, packet_offset=1 << 40, threads=threads)
+    dt = time.perf_counter() - t
+    if dt < seconds_target / 4:
+        n2 = int(max(n, min(64 * threads, n * seconds_target / max(dt, 1e-3) * 0.8)))
+        t = time.perf_counter()
+        r = oracle.mc_run(prob, n2, seed=0, packet_offset=1 << 40, threads=threads)
+        dt = time.perf_counter() - t
+        n = n2
+    sc = r["counters"]["scatterings"]
+    return {"value": sc / dt, "unit": "scatterings/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} packets (ids from 2^40, seed 0) of the same workload, {sc} scatterings, "
+                      f"{dt:.1f} s on {threads} threads of {model}",
+            "packets_per_s": n / dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--packets", type=int, default=1_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(packets shard with one int64 all-reduce of the tallies; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2608_09340_amd import krt, workloads as W
+
+    prob = W.sphere_c1()
+    ctx = krt.Context(0)
+    T = krt.Transport(prob, ctx=ctx)
+    dipole = prob["line"]["phase"] == 1
+    emis = prob["tally"].get("emis_nch", 0) > 0
+
+    wb = max(1000, args.packets // 100)
+    for w in range(args.warmup):
+        T.run(wb, seed=args.seed, packet_offset=(1 << 36) + w * wb)
+    torch.cuda.synchronize()
+
+    scat = 0
+    kern_ms = []
+    emitted = 0
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        r = T.run(args.packets, seed=args.seed, packet_offset=s * args.packets)
+        if r["rc"] != 0:
+            raise RuntimeError(f"krt_mc_run rc={r['rc']} counters={r['counters']}")
+        scat += r["counters"]["scatterings"]
+        emitted += r["counters"]["emitted"]
+        kern_ms.append(ctx.krt_last_transport_ms())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    lps = ledger_per_scatter(dipole, emis)
+    kms = sum(kern_ms) / len(kern_ms)
+    achieved = (scat / args.steps) * lps / (kms * 1e-3) / 1e12
+    out = {
+        "metric": "scatterings/s on 1 MI355X, plain vs MLP-escape at spectrum L1<=2% vs oracle",
+        "value": scat / wall,
+        "unit": "scatterings/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "static uniform sphere 64^3, radial line-centre tau0=1e6, a=4.7e-4, "
+                               "dipole phase, central point source x=0, spectrum 256 bins [-80,80), "
+                               "emissivity 64^3 x 32 channels [-24,24) toward +x, plain random walk",
+                   "packets_per_step": args.packets, "grid": [64, 64, 64], "seed": args.seed,
+                   "mean_scatterings_per_packet": scat / max(emitted, 1)},
+        "packets_per_s": emitted / wall,
+        "transport_kernel_ms": kms,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
+                     "frac": achieved / PEAK_VALU_TOPS, "traffic": None,
+                     "ops_per_scattering": lps},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

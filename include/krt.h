@@ -68,6 +68,9 @@ void krt_destroy(krt_ctx *ctx);
 const char *krt_last_error(const krt_ctx *ctx);
 /* Number of compute units of the context's device (launch sizing). */
 int krt_device_cus(const krt_ctx *ctx);
+/* Duration in ms of the transport kernel of the last krt_mc_run, from HIP
+ * events recorded on the context's stream around that launch only. */
+double krt_last_transport_ms(const krt_ctx *ctx);
 
 /* ---------------------------------------------------------------- grid --- */
 /* Uniform Cartesian grid with cell-wise constant fields (Sec. 2.2.1: the
@@ -124,22 +127,27 @@ typedef struct {
     int32_t escape_mode;       /* 0 = plain random walk */
     int32_t wg_size;           /* launch geometry: threads per workgroup (0 = default) */
     int32_t wg_per_cu;         /* workgroups per CU (0 = default) */
-    int32_t emis_frac_bits;    /* fixed-point bits of emissivity / jbar tallies (0 = 30) */
+    int32_t emis_frac_bits;    /* fixed-point fraction bits F of the emissivity tally (0 = 20) */
+    int32_t jbar_frac_bits;    /* fraction bits of the mean-intensity tally (0 = 36) */
     uint64_t norm_packets;     /* packets for the FP32 normalisation (0 = n_packets) */
+    double luminosity;         /* photons/s carried by all N packets; scales the FP32 outputs (0 = 1) */
 } krt_run_opts;
 
 /* Caller-allocated DEVICE buffers.  Raw tallies are int64 fixed point, so their
  * sums are exact and independent of thread order and launch geometry:
  *   spec_raw [spec_nbins + 2]   packet counts; [0] below spec_lo, [nb+1] at/above spec_hi
- *   emis_raw [ncell][emis_nch]  sum of phase(g_cam) * 2^F over scatterings
- *   jbar_raw [ncell]            sum of dl * H(a, x_gas) / sqrt(pi) * 2^F over segments
+ *   emis_raw [ncell][emis_nch]  sum of round(phase(g_cam) * 2^F) over scatterings
+ *   jbar_raw [ncell]            sum of round(dl * H(a, x_gas) / sqrt(pi) * 2^Fj) over segments
+ * Each contribution is rounded to the nearest integer before it is added, so
+ * the sums are exact integers whatever the order.  A sum that passes 2^62 sets
+ * KRT_ST_SATURATE (F = 20 allows 2.9e12 unit contributions per bin).
  *   counters [KRT_NCOUNTERS]
  *   packet_log [n_packets][8]   FP32 (x_lab, n_scat, outcome, n_x, n_y, n_z, cell, events)
  * Finalised FP32 outputs (FP64 scaling), each optional:
- *   spec  = spec_raw / (N dx_bin)                   per unit x, per emitted packet
- *   emis  = emis_raw 2^-F / (4 pi N V_cell dx_ch)   per volume, steradian, unit x
- *   jbar  = jbar_raw 2^-F / (4 pi N V_cell)
- * where N is norm_packets (or n_packets). */
+ *   spec  = L spec_raw / (N dx_bin)                   per unit x
+ *   emis  = L emis_raw 2^-F / (4 pi N V_cell dx_ch)   per volume, steradian, unit x
+ *   jbar  = L jbar_raw 2^-Fj / (4 pi N V_cell)
+ * where N is norm_packets (or n_packets) and L the luminosity (or 1). */
 typedef struct {
     int64_t *spec_raw_dev;
     int64_t *emis_raw_dev;

@@ -33,6 +33,8 @@ struct krt_ctx {
     unsigned long long *work_counter = nullptr;
     double *level_consts = nullptr;
     int64_t *host_pinned = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;   // bracket the last transport launch
+    float last_ms = 0.0f;
 };
 
 namespace {
@@ -114,7 +116,8 @@ extern "C" int krt_create(krt_ctx **out, int hip_device, void *hip_stream) {
         c->cus = cus;
     if (hipMalloc(&c->work_counter, sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&c->level_consts, sizeof(double) * 256) != hipSuccess ||
-        hipHostMalloc(&c->host_pinned, sizeof(int64_t) * 64, hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc(&c->host_pinned, sizeof(int64_t) * 64, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
         krt_destroy(c);
         return KRT_EHIP;
     }
@@ -131,12 +134,16 @@ extern "C" void krt_destroy(krt_ctx *c) {
     if (c->work_counter) (void)hipFree(c->work_counter);
     if (c->level_consts) (void)hipFree(c->level_consts);
     if (c->host_pinned) (void)hipHostFree(c->host_pinned);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
     delete c;
 }
 
 extern "C" const char *krt_last_error(const krt_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
 extern "C" int krt_device_cus(const krt_ctx *c) { return c ? c->cus : 0; }
+
+extern "C" double krt_last_transport_ms(const krt_ctx *c) { return c ? (double)c->last_ms : -1.0; }
 
 // ----------------------------------------------------------------- grid ---
 extern "C" int krt_grid_upload(krt_ctx *c, const krt_grid_desc *d) {
@@ -237,8 +244,12 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
         if (!(std::fabs(nn - 1.0) < 1e-6)) return fail(c, KRT_EINVAL, "n_cam must be a unit vector");
     }
     if (o->jbar && !t->jbar_raw_dev) return fail(c, KRT_EINVAL, "jbar needs jbar_raw");
-    int fb = o->emis_frac_bits ? o->emis_frac_bits : 30;
+    int fb = o->emis_frac_bits ? o->emis_frac_bits : 20;
     if (fb < 8 || fb > 40) return fail(c, KRT_EINVAL, "emis_frac_bits %d outside 8..40", fb);
+    int fj = o->jbar_frac_bits ? o->jbar_frac_bits : 36;
+    if (fj < 8 || fj > 48) return fail(c, KRT_EINVAL, "jbar_frac_bits %d outside 8..48", fj);
+    const double lum = (o->luminosity != 0.0) ? o->luminosity : 1.0;
+    if (!(lum > 0.0) || !std::isfinite(lum)) return fail(c, KRT_EINVAL, "luminosity must be finite and > 0");
     int block = o->wg_size ? o->wg_size : 512;
     int per_cu = o->wg_per_cu ? o->wg_per_cu : 2;
     if (block < 64 || block > 1024 || block % 64) return fail(c, KRT_EINVAL, "wg_size %d invalid", block);
@@ -294,6 +305,7 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
     P.ch_hi = o->ch_hi;
     P.ch_inv_w = o->emis_nch > 0 ? (float)(o->emis_nch / (o->ch_hi - o->ch_lo)) : 0.0f;
     P.frac_scale = std::ldexp(1.0f, fb);
+    P.jbar_scale = std::ldexp(1.0f, fj);
     P.spec_raw = t->spec_raw_dev;
     P.emis_raw = o->emis_nch > 0 ? t->emis_raw_dev : nullptr;
     P.jbar_raw = o->jbar ? t->jbar_raw_dev : nullptr;
@@ -307,24 +319,27 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
     P.key1 = (uint32_t)(seed >> 32);
     P.work_counter = c->work_counter;
     int grid = c->cus * per_cu;
+    HIPCHK(c, hipEventRecord(c->ev0, c->stream));
     HIPCHK(c, launch_transport(P, grid, block, c->stream));
+    HIPCHK(c, hipEventRecord(c->ev1, c->stream));
 
     // finalise (FP64 scaling -> FP32)
     const double N = (double)(o->norm_packets ? o->norm_packets : n_packets);
     const double vcell = P.dxd[0] * P.dxd[1] * P.dxd[2];
-    const double inv_f = std::ldexp(1.0, -fb);
+    const double inv_f = std::ldexp(1.0, -fb), inv_fj = std::ldexp(1.0, -fj);
     const double four_pi = 4.0 * 3.14159265358979323846;
     if (t->spec_dev)
-        HIPCHK(c, launch_finalize(t->spec_raw_dev, t->spec_dev, nsb, 1.0 / (N * (o->spec_hi - o->spec_lo) / o->spec_nbins), c->stream));
+        HIPCHK(c, launch_finalize(t->spec_raw_dev, t->spec_dev, nsb, lum / (N * (o->spec_hi - o->spec_lo) / o->spec_nbins), c->stream));
     if (t->emis_dev && o->emis_nch > 0)
         HIPCHK(c, launch_finalize(t->emis_raw_dev, t->emis_dev, nc * o->emis_nch,
-                                  inv_f / (four_pi * N * vcell * ((o->ch_hi - o->ch_lo) / o->emis_nch)), c->stream));
+                                  lum * inv_f / (four_pi * N * vcell * ((o->ch_hi - o->ch_lo) / o->emis_nch)), c->stream));
     if (t->jbar_dev && o->jbar)
-        HIPCHK(c, launch_finalize(t->jbar_raw_dev, t->jbar_dev, nc, inv_f / (four_pi * N * vcell), c->stream));
+        HIPCHK(c, launch_finalize(t->jbar_raw_dev, t->jbar_dev, nc, lum * inv_fj / (four_pi * N * vcell), c->stream));
 
     HIPCHK(c, hipMemcpyAsync(c->host_pinned, t->counters_dev, sizeof(int64_t) * KRT_NCOUNTERS,
                              hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipEventElapsedTime(&c->last_ms, c->ev0, c->ev1));
     int64_t st = c->host_pinned[KRT_C_STATUS];
     if (st != 0) return fail(c, KRT_EDEVICE, "device status 0x%llx (nan=1 stuck=2 saturate=4)", (long long)st);
     return KRT_OK;

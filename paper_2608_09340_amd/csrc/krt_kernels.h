@@ -54,7 +54,8 @@ struct RunParams {
     double ch_lo, ch_hi;
     float ch_inv_w;
     float n_cam[3];
-    float frac_scale;  // 2^F
+    float frac_scale;  // 2^F, emissivity
+    float jbar_scale;  // 2^Fj, mean intensity
     int64_t *spec_raw, *emis_raw, *jbar_raw, *counters;
     uint32_t *status;
     float *plog;

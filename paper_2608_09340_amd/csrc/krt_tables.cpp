@@ -8,15 +8,17 @@
 //       Gauss-Legendre quadrature of H = (1/pi) int exp(-(x + a tan t)^2) dt,
 //       the Voigt integral after the substitution y = x + a tan t.
 //  (ii) The atom-velocity sampler of Sec. 2.1.1 (the USampler): the density
-//       p(u | x) ~ exp(-u^2)/(a^2 + (x-u)^2) is split, for x >= 0, at
-//       |u - x| = DELTA into a resonant piece S (|u - x| < DELTA), a left
-//       piece L (u <= x - DELTA) and a right piece R (u >= x + DELTA).  Each
-//       piece is smooth in a variable of its own, and its quantile function is
-//       tabulated on 64 rows of x (48 uniform rows on [0, 8), 16 logarithmic
-//       rows on [8, 300]); the piece probabilities are tabulated on a fine
-//       1/128 grid of x.  Tabulating quantiles rather than the cumulative
-//       distribution moves the narrow resonant peak continuously between rows.
-//       Symmetry p(u | -x) = p(-u | x) covers x < 0.
+//       p(u | x) ~ exp(-u^2)/(a^2 + (x-u)^2) is split, for x >= 0, into four
+//       pieces (see krt_internal.h): the resonant core S (|u - x| < DELTA), the
+//       Lorentz wing just below it L1, the thermal bump L2 (u <= x - SMID) and
+//       the wing above R.  Each piece has a single feature and is smooth in a
+//       variable of its own; its quantile function is tabulated on 64 rows of x
+//       (48 uniform rows on [0, 8), 16 logarithmic rows on [8, 300]) and the
+//       piece probabilities on a fine 1/128 grid of x.  Tabulating quantiles
+//       rather than the cumulative distribution moves the narrow resonant peak
+//       continuously between rows, and keeping separated features in separate
+//       pieces stops interpolation between rows from mixing them.  Symmetry
+//       p(u | -x) = p(-u | x) covers x < 0.
 //
 // Everything here is computed once per line in FP64 and rounded to binary32.
 
@@ -135,16 +137,22 @@ void hermite_coefs(double y0, double m0, double y1, double m1, float *c) {
 }
 
 // ---- sampler pieces -------------------------------------------------------
-// log-density of each piece in its own variable, with exp(-x^2) factored out
-// of S and R so that large x does not underflow.
+// density of each piece in its own variable (u-measure times the Jacobian), with
+// exp(-x^2) factored out of S and R so that large x does not underflow.
+double smid_of(double xa) { return std::max(0.5 * xa, 2.0 * kDelta); }
+
 struct Piece {
-    int kind;  // 0 = S (variable t in [-1,1]), 1 = L, 2 = R (variable l = ln(s/DELTA) >= 0)
-    double xa, a, thd;
-    double vmax;
+    int kind;  // 0 = S (t), 1 = L1 (l), 2 = L2 (u), 3 = R (l)
+    double xa, a, thd, smid;
+    double vlo, vhi;
     double dens(double v) const {
         if (kind == 0) {
             double tt = a * std::tan(v * thd);
             return std::exp(-2.0 * xa * tt - tt * tt);
+        }
+        if (kind == 2) {
+            double s = xa - v;
+            return std::exp(-v * v) / (a * a + s * s);
         }
         double s = kDelta * std::exp(v);
         if (kind == 1) {
@@ -153,15 +161,18 @@ struct Piece {
         }
         return std::exp(-2.0 * xa * s - s * s) * s / (a * a + s * s);
     }
-    double vmin() const { return kind == 0 ? -1.0 : 0.0; }
+    double vmin() const { return vlo; }
+    double vmax_() const { return vhi; }
 };
 
 Piece make_piece(int kind, double xa, double a) {
     Piece p;
     p.kind = kind; p.xa = xa; p.a = a; p.thd = std::atan(kDelta / a);
-    if (kind == 0) p.vmax = 1.0;
-    else if (kind == 1) p.vmax = std::log((xa + 7.0) / kDelta);
-    else p.vmax = std::log(7.0 / kDelta);
+    p.smid = smid_of(xa);
+    if (kind == 0) { p.vlo = -1.0; p.vhi = 1.0; }
+    else if (kind == 1) { p.vlo = 0.0; p.vhi = std::log(p.smid / kDelta); }
+    else if (kind == 2) { p.vlo = std::min(-7.0, xa - p.smid - 1.0); p.vhi = xa - p.smid; }
+    else { p.vlo = 0.0; p.vhi = std::log(7.0 / kDelta); }
     return p;
 }
 
@@ -169,7 +180,7 @@ Piece make_piece(int kind, double xa, double a) {
 double fine_cdf(const Piece &p, int nf, std::vector<double> &v, std::vector<double> &F,
                 std::vector<double> &f) {
     v.resize(nf + 1); F.resize(nf + 1); f.resize(nf + 1);
-    double lo = p.vmin(), hi = p.vmax;
+    double lo = p.vmin(), hi = p.vmax_();
     for (int i = 0; i <= nf; ++i) { v[i] = lo + (hi - lo) * i / nf; f[i] = p.dens(v[i]); }
     F[0] = 0.0;
     Fn fn = [&](double t) { return p.dens(t); };
@@ -204,7 +215,7 @@ double log_mass(const Piece &p) {
     double tot = fine_cdf(p, 256, v, F, f);
     double lm = std::log(std::max(tot, 1e-300));
     if (p.kind == 0) lm += std::log(p.thd / p.a) - p.xa * p.xa;  // dtheta = thd dt, u-measure 1/a
-    if (p.kind == 2) lm += -p.xa * p.xa;
+    if (p.kind == 3) lm += -p.xa * p.xa;
     return lm;
 }
 
@@ -241,29 +252,40 @@ void build_line_tables(double a, std::vector<float> &tab) {
             hermite_coefs(G[j], Gd[j] / kVoigtWingN, G[j + 1], Gd[j + 1] / kVoigtWingN,
                           &tab[kOffVoigtWing + 4 * j]);
     }
-    // (ii) piece probabilities on x_i = i / 128, i = 0..1024
+    // (ii) cumulative piece probabilities on x_i = i / 64, i = 0..512
     for (int i = 0; i <= kMassN; ++i) {
         double xa = i * (kXLin / kMassN);
-        double ls = log_mass(make_piece(0, xa, a));
-        double ll = log_mass(make_piece(1, xa, a));
-        double lr = log_mass(make_piece(2, xa, a));
-        double m = std::max(ls, std::max(ll, lr));
-        double es = std::exp(ls - m), el = std::exp(ll - m), er = std::exp(lr - m);
-        tab[kOffMass + 2 * i + 0] = (float)(es / (es + el + er));
-        tab[kOffMass + 2 * i + 1] = (float)(el / (el + er));
+        double lm[4], m = -1e300;
+        for (int k = 0; k < 4; ++k) { lm[k] = log_mass(make_piece(k, xa, a)); m = std::max(m, lm[k]); }
+        double e[4], tot = 0.0;
+        for (int k = 0; k < 4; ++k) { e[k] = std::exp(lm[k] - m); tot += e[k]; }
+        tab[kOffMass + 4 * i + 0] = (float)(e[0] / tot);
+        tab[kOffMass + 4 * i + 1] = (float)((e[0] + e[1]) / tot);
+        tab[kOffMass + 4 * i + 2] = (float)((e[0] + e[1] + e[2]) / tot);
+        tab[kOffMass + 4 * i + 3] = 1.0f;
     }
-    // (ii) quantile rows
+    // (ii) quantile rows.  The wing pieces use nodes dense at both ends,
+    // q = 4 xi^3 (xi < 1/2), q = 1 - 4 (1 - xi)^3 (xi >= 1/2), and their first and
+    // last nodes are the 1e-9 and 1 - 1e-9 quantiles: no interval spans a stretch
+    // of the variable that carries no probability, and the outermost intervals
+    // hold so little probability that interpolating across the Gaussian tails
+    // does not inflate the second moment of the kick.
     std::vector<double> v, F, f;
+    const int nqs[4] = {kQS, kQL1, kQL2, kQR};
+    const int offs[4] = {kOffSpike, kOffL1, kOffL2, kOffRight};
     for (int j = 0; j < kRows; ++j) {
         double xa = row_x(j);
-        for (int kind = 0; kind < 3; ++kind) {
+        for (int kind = 0; kind < 4; ++kind) {
             Piece p = make_piece(kind, xa, a);
             fine_cdf(p, 4096, v, F, f);
-            int nq = (kind == 0) ? kQS : (kind == 1 ? kQL : kQR);
-            int off = (kind == 0) ? kOffSpike : (kind == 1 ? kOffLeft : kOffRight);
+            int nq = nqs[kind], off = offs[kind];
             for (int k = 0; k < nq; ++k) {
                 double xi = (double)k / (nq - 1);
-                double q = (kind == 0) ? xi : 1.0 - (1.0 - xi) * (1.0 - xi);
+                double q;
+                if (kind == 0) q = xi;
+                else if (k == 0) q = 1e-9;
+                else if (k == nq - 1) q = 1.0 - 1e-9;
+                else q = (xi < 0.5) ? 4.0 * xi * xi * xi : 1.0 - 4.0 * (1.0 - xi) * (1.0 - xi) * (1.0 - xi);
                 tab[off + j * nq + k] = (float)fine_quantile(v, F, f, q);
             }
         }

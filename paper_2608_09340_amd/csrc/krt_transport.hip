@@ -90,30 +90,38 @@ __device__ __forceinline__ float voigt_lds(const float *T, float xa) {
     return G * w * w * (1.0f / 64.0f);
 }
 
-// Atom parallel velocity for gas-frame frequency x (Sec. 2.1.1): piece by r1,
-// quantile by r2, bilinear in (row of |x|, quantile node).
+// Atom parallel velocity for gas-frame frequency x (Sec. 2.1.1): piece by r1
+// against the cumulative piece probabilities, quantile by r2, bilinear in
+// (row of |x|, quantile node).
 __device__ __forceinline__ float upar_lds(const float *T, float x, float a, float thd,
                                           float r1, float r2) {
     float xa = fabsf(x);
-    float ps = 0.0f, plw = 1.0f;
+    float c1 = 0.0f, c2 = 0.0f, c3 = 1.0f;
     if (xa < 8.0f) {
-        float pm = xa * 128.0f;
+        float pm = xa * (float)(kMassN / 8);
         int im = max(0, min((int)pm, kMassN - 1));
         float fm = pm - (float)im;
-        float2 m0 = *reinterpret_cast<const float2 *>(T + kOffMass + 2 * im);
-        float2 m1 = *reinterpret_cast<const float2 *>(T + kOffMass + 2 * im + 2);
-        ps = fmaf(fm, m1.x - m0.x, m0.x);
-        plw = fmaf(fm, m1.y - m0.y, m0.y);
+        float4 m0 = *reinterpret_cast<const float4 *>(T + kOffMass + 4 * im);
+        float4 m1 = *reinterpret_cast<const float4 *>(T + kOffMass + 4 * im + 4);
+        c1 = fmaf(fm, m1.x - m0.x, m0.x);
+        c2 = fmaf(fm, m1.y - m0.y, m0.y);
+        c3 = fmaf(fm, m1.z - m0.z, m0.z);
     }
     float p;
     if (xa < 8.0f) p = xa * 6.0f;
     else p = fminf(48.0f + f_log(xa * 0.125f) * kRowInvLog, 63.0f);
     int j = max(0, min((int)p, kRows - 2));
     float fr = p - (float)j;
-    int kind = (r1 < ps) ? 0 : ((r1 < fmaf(1.0f - ps, plw, ps)) ? 1 : 2);
-    int nq = (kind == 0) ? kQS : ((kind == 1) ? kQL : kQR);
-    int off = (kind == 0) ? kOffSpike : ((kind == 1) ? kOffLeft : kOffRight);
-    float xi = (kind == 0) ? r2 : 1.0f - f_sqrt(1.0f - r2);
+    int kind = (r1 < c1) ? 0 : ((r1 < c2) ? 1 : ((r1 < c3) ? 2 : 3));
+    int nq = (kind == 0) ? kQS : kQL1;  // kQL1 == kQL2 == kQR
+    int off = (kind == 0) ? kOffSpike : ((kind == 1) ? kOffL1 : ((kind == 2) ? kOffL2 : kOffRight));
+    // wing pieces: nodes at q = 4 xi^3 (xi < 1/2), 1 - 4 (1 - xi)^3 (xi >= 1/2)
+    float xi = r2;
+    if (kind != 0) {
+        float t = (r2 < 0.5f) ? r2 : 1.0f - r2;
+        float cb = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(0.25f * t) * (1.0f / 3.0f));
+        xi = (r2 < 0.5f) ? cb : 1.0f - cb;
+    }
     float qp = xi * (float)(nq - 1);
     int k = max(0, min((int)qp, nq - 2));
     float fq = qp - (float)k;
@@ -125,6 +133,8 @@ __device__ __forceinline__ float upar_lds(const float *T, float x, float a, floa
     if (kind == 0) {
         float th = v * thd * (1.0f / (2.0f * kPiF));
         u = xa + a * sin_rev(th) * f_rcp(cos_rev(th));
+    } else if (kind == 2) {
+        u = v;
     } else {
         float s = (float)kDelta * f_exp(v);
         u = (kind == 1) ? xa - s : xa + s;
@@ -219,7 +229,7 @@ __global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
     // per-lane counters
     int64_t c_emit = 0, c_esc = 0, c_des = 0, c_scat = 0, c_cross = 0, c_stuck = 0, c_drop = 0;
     uint32_t *status = P.status;
-    const float jscale = P.frac_scale * kInvSqrtPiF;
+    const float jscale = P.jbar_scale * kInvSqrtPiF;
 
     for (;;) {
         // ---- refill retired lanes from the global queue -------------------

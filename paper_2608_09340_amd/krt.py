@@ -39,7 +39,8 @@ class krt_run_opts(C.Structure):
                 ("n_cam", C.c_double * 3), ("jbar", C.c_int32), ("accumulate", C.c_int32),
                 ("packet_offset", C.c_uint64), ("max_events", C.c_uint64),
                 ("escape_mode", C.c_int32), ("wg_size", C.c_int32), ("wg_per_cu", C.c_int32),
-                ("emis_frac_bits", C.c_int32), ("norm_packets", C.c_uint64)]
+                ("emis_frac_bits", C.c_int32), ("jbar_frac_bits", C.c_int32),
+                ("norm_packets", C.c_uint64), ("luminosity", C.c_double)]
 
 
 class krt_tallies(C.Structure):
@@ -56,7 +57,8 @@ class krt_levels_desc(C.Structure):
                 ("eps_out_dev", C.c_void_p)]
 
 
-EXPORTS = ["krt_create", "krt_destroy", "krt_last_error", "krt_device_cus", "krt_grid_upload",
+EXPORTS = ["krt_create", "krt_destroy", "krt_last_error", "krt_device_cus", "krt_last_transport_ms",
+           "krt_grid_upload",
            "krt_tables_build", "krt_mc_run", "krt_levels_update", "krt_debug_philox",
            "krt_debug_bins", "krt_debug_voigt", "krt_debug_upar"]
 
@@ -80,6 +82,8 @@ def load(path: str = LIB_PATH):
     L.krt_last_error.restype = C.c_char_p
     L.krt_device_cus.argtypes = [p]
     L.krt_device_cus.restype = C.c_int
+    L.krt_last_transport_ms.argtypes = [p]
+    L.krt_last_transport_ms.restype = C.c_double
     L.krt_grid_upload.argtypes = [p, C.POINTER(krt_grid_desc)]
     L.krt_tables_build.argtypes = [p, C.POINTER(krt_line_desc), C.c_int]
     L.krt_mc_run.argtypes = [p, u64, u64, C.POINTER(krt_run_opts), C.POINTER(krt_tallies)]
@@ -142,6 +146,9 @@ class Context:
     def cus(self) -> int:
         return self.L.krt_device_cus(self.h)
 
+    def krt_last_transport_ms(self) -> float:
+        return self.L.krt_last_transport_ms(self.h)
+
     # ------------------------------------------------------------- calls
     def krt_grid_upload(self, n, lo, hi, bc, k0, vel=None, eps=None, emis=None, n_lines=1):
         d = krt_grid_desc()
@@ -188,7 +195,8 @@ class Context:
 
 
 def make_opts(prob: dict, *, line=0, packet_offset=0, accumulate=False, max_events=0,
-              wg_size=0, wg_per_cu=0, emis_frac_bits=0, norm_packets=0, escape_mode=0) -> krt_run_opts:
+              wg_size=0, wg_per_cu=0, emis_frac_bits=0, jbar_frac_bits=0, norm_packets=0, escape_mode=0,
+              luminosity=0.0) -> krt_run_opts:
     """krt_run_opts from a workload problem dict (paper_2608_09340_amd.workloads)."""
     o = krt_run_opts()
     src, t = prob["source"], prob["tally"]
@@ -214,7 +222,9 @@ def make_opts(prob: dict, *, line=0, packet_offset=0, accumulate=False, max_even
     o.wg_size = int(wg_size)
     o.wg_per_cu = int(wg_per_cu)
     o.emis_frac_bits = int(emis_frac_bits)
+    o.jbar_frac_bits = int(jbar_frac_bits)
     o.norm_packets = int(norm_packets)
+    o.luminosity = float(luminosity)
     return o
 
 

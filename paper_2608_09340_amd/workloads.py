@@ -134,3 +134,86 @@ def uniform_thin_sphere(n=32, k0=1e-3, a=1e-2):
     """Optically thin uniformly emitting sphere of radius 1 (mean-intensity pin)."""
     p = sphere(n, k0, a, phase=PHASE_ISO, emis=None, source="volume", jbar=True)
     return p
+
+
+# ---------------------------------------------------------------- clouds ---
+def gaussian_random_field(n, slope=-4.0, seed=2, ncomp=1, solenoidal=False):
+    """Periodic Gaussian random field(s) on n^3 with power spectrum P(k) ~ k^slope
+    (k = 0 removed), from PCG64 white noise; solenoidal projection for vectors.
+    Returns [ncomp, n, n, n] float64 with zero mean."""
+    rng = np.random.default_rng(seed)
+    k = np.fft.fftfreq(n) * n
+    kz, ky, kx = np.meshgrid(k, k, k, indexing="ij")
+    kk = np.sqrt(kx * kx + ky * ky + kz * kz)
+    amp = np.zeros_like(kk)
+    amp[kk > 0] = kk[kk > 0] ** (slope / 2.0)
+    comps = []
+    for _ in range(ncomp):
+        w = rng.standard_normal((n, n, n))
+        comps.append(np.fft.fftn(w) * amp)
+    if solenoidal and ncomp == 3:
+        with np.errstate(invalid="ignore", divide="ignore"):
+            kh = [np.where(kk > 0, c / kk, 0.0) for c in (kx, ky, kz)]
+        dot = kh[0] * comps[0] + kh[1] * comps[1] + kh[2] * comps[2]
+        comps = [comps[i] - kh[i] * dot for i in range(3)]
+    out = np.stack([np.real(np.fft.ifftn(c)) for c in comps])
+    return out - out.mean(axis=(1, 2, 3), keepdims=True)
+
+
+def cloud_fields(n=128, sigma_lnrho=1.5, vrms3d=3.0, seed_rho=2, seed_v=3):
+    """Lognormal density (GRF, P ~ k^-4, sigma of ln rho = 1.5, mean rho = 1) and a
+    solenoidal GRF velocity (P ~ k^-4, 3-D rms 3 in thermal units), x fastest."""
+    g = gaussian_random_field(n, -4.0, seed_rho, 1)[0]
+    g = g / g.std() * sigma_lnrho
+    rho = np.exp(g)
+    rho /= rho.mean()
+    v = gaussian_random_field(n, -4.0, seed_v, 3, solenoidal=True)
+    v *= vrms3d / np.sqrt(np.mean(np.sum(v * v, axis=0)))
+    # arrays are [z][y][x] -> flatten with x fastest
+    return rho.reshape(-1), v.reshape(3, -1)
+
+
+def rotor(n_levels=5, a0=1e-3, theta=0.5, seed=4):
+    """Synthetic linear rotor: levels J = 0..L-1, g = 2J+1, E_J/kT = theta J(J+1)/2,
+    lines J+1 -> J with A = (J+1)^3 (units of A_10), frequencies ~ (J+1), so the
+    damping a_l = a0 (l+1)^2 and sigma0_l ~ g_u/g_l; downward collision rate
+    coefficients log-uniform over two decades around A_10 (per unit collider
+    density), upward by detailed balance inside the solver."""
+    rng = np.random.default_rng(seed)
+    J = np.arange(n_levels)
+    g = 2.0 * J + 1.0
+    E = theta * J * (J + 1) / 2.0
+    A = np.zeros((n_levels, n_levels))
+    for u in range(1, n_levels):
+        A[u, u - 1] = float(u) ** 3
+    Cd = np.tril(10.0 ** rng.uniform(-1.0, 1.0, (n_levels, n_levels)), -1)
+    sigma0 = np.array([(2 * l + 3) / (2 * l + 1) for l in range(n_levels - 1)], dtype=np.float64)
+    a = np.array([a0 * (l + 1) ** 2 for l in range(n_levels - 1)], dtype=np.float64)
+    return {"E": E, "g": g, "A": A, "Cd": Cd, "sigma0": sigma0, "a": a}
+
+
+def cloud_c3(n=128, packets_per_line=10_000_000):
+    """Turbulent molecular cloud on [0,1]^3 (vacuum faces for packets): density
+    and velocity fields, the rotor, collider density = rho, species density
+    n_tot = rho * n_scale with n_scale set so that the mean line-0 cell depth
+    at collisional equilibrium is 1.  Level populations, opacities and emission
+    weights are produced by the level solver itself (krt_levels_update)."""
+    rho, v = cloud_fields(n)
+    rot = rotor()
+    return {"n": [n, n, n], "lo": [0.0, 0.0, 0.0], "hi": [1.0, 1.0, 1.0], "bc": [VACUUM] * 3,
+            "rho": rho.astype(np.float64), "vel": v.astype(np.float32), "rotor": rot,
+            "ncoll": rho.astype(np.float64), "dx": 1.0 / n, "packets_per_line": packets_per_line}
+
+
+def cloud_c4(n=128, a=1e-3, tau_p70=1e2, spec=(512, -64.0, 64.0), emis=(32, -16.0, 16.0)):
+    """The turbulent cloud rescaled for the learned escape: one line, a = 1e-3,
+    eps = 0, density scaled so the 70th percentile of the line-centre cell depth
+    k0 dx is 1e2 (30% of cells in [1e2, ~1e5]); Voigt volume emission ~ rho."""
+    rho, v = cloud_fields(n)
+    dx = 1.0 / n
+    k0 = rho * (tau_p70 / np.percentile(rho, 70.0)) / dx
+    return _problem((n, n, n), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), (VACUUM,) * 3, k0, a, vel=v,
+                    emis=rho.astype(np.float32), phase=PHASE_ISO,
+                    source={"kind": SRC_VOLUME, "pos": (0.0, 0.0, 0.0), "profile": PROF_VOIGT, "x0": 0.0},
+                    tally={"spec_nbins": spec[0], "spec_lo": spec[1], "spec_hi": spec[2],
+                           "emis_nch": emis[0], "ch_lo": emis[1], "ch_hi": emis[2], "n_cam": (1.0, 0.0, 0.0)})
