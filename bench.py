@@ -8,7 +8,7 @@ point source, escaped spectrum 256 bins on [-80, 80), emissivity 64^3 x 32
 channels on [-24, 24) toward +x): emission, flights, resonant scatterings,
 int64 tallies and the FP32 finalise, with grid and tables already resident in
 HBM.  The default batch is the full 1e6 packets of that workload.  Warmup steps
-use 1% batches from a disjoint packet range.
+are full-size batches from a disjoint packet range.
 
 Prints one JSON line: whole-job scatterings/s, the ALU roofline of the
 transport kernel (HIP-event duration of that kernel, from the library), and the
@@ -93,6 +93,8 @@ def main():
     ap.add_argument("--packets", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB (calibrates FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -102,15 +104,24 @@ def main():
     import torch
     from paper_2608_09340_amd import krt, workloads as W
 
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 4}), flush=True)
+        return
+
     prob = W.sphere_c1()
     ctx = krt.Context(0)
     T = krt.Transport(prob, ctx=ctx)
     dipole = prob["line"]["phase"] == 1
     emis = prob["tally"].get("emis_nch", 0) > 0
 
-    wb = max(1000, args.packets // 100)
     for w in range(args.warmup):
-        T.run(wb, seed=args.seed, packet_offset=(1 << 36) + w * wb)
+        T.run(args.packets, seed=args.seed, packet_offset=(1 << 36) + w * args.packets)
     torch.cuda.synchronize()
 
     scat = 0

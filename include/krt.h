@@ -124,13 +124,16 @@ typedef struct {
     int32_t accumulate;        /* 1 = add into the raw tallies, 0 = zero them first */
     uint64_t packet_offset;    /* first packet id (resume / sharding) */
     uint64_t max_events;       /* per packet; 0 = unlimited (2^32 - 2) */
-    int32_t escape_mode;       /* 0 = plain random walk */
+    int32_t escape_mode;       /* 0 = plain random walk; 1 = learned escape in thick cells (needs
+                                  krt_escape_init/train or put_weights; a in [1e-4, 1e-2]; no jbar) */
     int32_t wg_size;           /* launch geometry: threads per workgroup (0 = default) */
     int32_t wg_per_cu;         /* workgroups per CU (0 = default) */
     int32_t emis_frac_bits;    /* fixed-point fraction bits F of the emissivity tally (0 = 20) */
     int32_t jbar_frac_bits;    /* fraction bits of the mean-intensity tally (0 = 36) */
     uint64_t norm_packets;     /* packets for the FP32 normalisation (0 = n_packets) */
     double luminosity;         /* photons/s carried by all N packets; scales the FP32 outputs (0 = 1) */
+    double esc_tau_min;        /* learned escape only where k0 R >= this (0 = 100) */
+    int32_t esc_min_lanes;     /* network call when at least this many lanes of a wave ask (0 = 8) */
 } krt_run_opts;
 
 /* Caller-allocated DEVICE buffers.  Raw tallies are int64 fixed point, so their
@@ -189,6 +192,50 @@ typedef struct {
 } krt_levels_desc;
 int krt_levels_update(krt_ctx *ctx, const krt_levels_desc *desc,
                       const float *jbar_dev /* [nl-1][ncell], NULL = no radiation */);
+
+/* ------------------------------------------------------- learned escape --- */
+/* A small network (4 -> 3 x 128 SiLU -> 6, BF16 weights and activations, FP32
+ * accumulation on MFMA) proposes, at a scattering inside a cell whose
+ * line-centre depth over the distance R to the nearest cell face is
+ * tau_R = k0 R >= 1e2, where a photon leaves the cube of half-width R centred
+ * there: exit frequency, exit point on the exit face, exit direction, and the
+ * number of scatterings it skipped.  The paper itself propagates every photon
+ * through the full optical depth (Sec. 2.3.2, Sec. 4.1); this proposal is the
+ * accelerated alternative it points to for extreme depths, and the plain
+ * random walk remains the fallback (below threshold, |x| > 8, a outside
+ * [1e-4, 1e-2]).  Inputs (log10 tau_R, log10 a, x_in, u); the 6 outputs are
+ * conditional quantiles at level u of (x_out, s, t, mu, ln N_s, ln <x^2>),
+ * trained with the pinball loss on single-cell escapes run by the plain
+ * transport arithmetic.  Parameters: kNParams = 34438 FP32 master values plus
+ * 12 target normalisation constants (mean[6], scale[6]).
+ *
+ * krt_escape_init: He-uniform parameters from Philox(seed), Adam state zeroed.
+ * krt_escape_record: n single-cell escapes for line `line`, log10 tau_R uniform
+ *   in [lo, hi], x_in fixed (x_fixed = 1) or 1/2 N(0, 1/2) + 1/2 U[-8, 8];
+ *   samples_dev [n][10] FP32: (log10 tau_R, log10 a, x_in, x_out, s, t, mu,
+ *   ln N_s, ln <x^2>, valid).
+ * krt_escape_fit_norm: target mean / scale from valid records.
+ * krt_escape_grad: gradient of the mean pinball loss over the batch given by
+ *   idx_dev [batch] (record indices) and u_dev [batch]; grad_out_dev [34438],
+ *   loss_out_dev [1] (may be NULL).
+ * krt_escape_train: `steps` Adam steps (lr, betas 0.9/0.999) on random batches
+ *   (Philox(seed)); loss_hist_dev [steps] or NULL.
+ * krt_escape_get_weights / put_weights: [34438 + 12] FP32 device buffers.
+ * krt_escape_forward: in_dev [n][4] raw (log10 tau_R, log10 a, x_in, u) ->
+ *   out_dev [n][6] in physical units.
+ * Errors: KRT_EINVAL (sizes, ranges), KRT_ESTATE (no init / no tables). */
+int krt_escape_init(krt_ctx *ctx, uint64_t seed);
+int krt_escape_record(krt_ctx *ctx, int32_t line, uint64_t n, uint64_t seed, uint64_t offset,
+                      double log10_tau_lo, double log10_tau_hi, int32_t x_fixed, double x_in,
+                      float *samples_dev);
+int krt_escape_fit_norm(krt_ctx *ctx, const float *samples_dev, uint64_t n);
+int krt_escape_grad(krt_ctx *ctx, const float *samples_dev, const int32_t *idx_dev, const float *u_dev,
+                    int32_t batch, float *grad_out_dev, float *loss_out_dev);
+int krt_escape_train(krt_ctx *ctx, const float *samples_dev, uint64_t n, int32_t steps, int32_t batch,
+                     double lr, uint64_t seed, float *loss_hist_dev);
+int krt_escape_get_weights(krt_ctx *ctx, float *dev, uint64_t nfloats);
+int krt_escape_put_weights(krt_ctx *ctx, const float *dev, uint64_t nfloats);
+int krt_escape_forward(krt_ctx *ctx, const float *in_dev, int64_t n, float *out_dev);
 
 /* ----------------------------------------------------------- diagnostics --- */
 /* Device-side evaluations of the individual steps, for parity tests.

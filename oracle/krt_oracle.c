@@ -640,3 +640,99 @@ int orc_levels_solve(int nl, int64_t ncell, const double *E, const double *g, co
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Single-cell escape (reference for the learned escape): a homogeneous      */
+/* static cube [-1,1]^3 of line-centre opacity k0 = tau_R per unit length; a  */
+/* photon of gas-frame frequency x_in arrives from an isotropic direction     */
+/* (event 0, purpose 4, words 0-1), scatters at the centre (event 1), then    */
+/* takes the plain flights and scatterings of Sec. 2.1-2.3 until it leaves.   */
+/* Record per photon: [log10 tau_R, log10 a, x_in, x_out, s, t, mu, ln N_s,   */
+/* ln <x^2>, valid]; (s, t) are the exit point's coordinates along the two    */
+/* axes following the exit axis cyclically, mu = |n . normal|.               */
+/* ------------------------------------------------------------------------ */
+typedef struct { double tau, a, xin; uint64_t seed, p0, p1; double *out; uint64_t max_scat; } esc_job_t;
+
+static void escape_one(const esc_job_t *J, uint64_t pid, double *o)
+{
+    rng_t r = { { (uint32_t)J->seed, (uint32_t)(J->seed >> 32) }, pid };
+    uint32_t d[4];
+    draw_block(&r, 0, 4, d);
+    double mu0 = 2.0 * u01(d[0]) - 1.0, ph0 = 2.0 * ORC_PI * u01(d[1]);
+    double st0 = sqrt(fmax(0.0, 1.0 - mu0 * mu0));
+    double n[3] = { st0 * cos(ph0), st0 * sin(ph0), mu0 };
+    double X[3] = { 0.0, 0.0, 0.0 };
+    double x = J->xin, sx2 = 0.0;
+    uint64_t ns = 0;
+    int valid = 0, ax = 0;
+    for (uint64_t ev = 1; ev <= J->max_scat + 1; ++ev) {
+        uint32_t A[4], B[4];
+        draw_block(&r, (uint32_t)ev, 0, A);
+        draw_block(&r, (uint32_t)ev, 1, B);
+        if (ev > 1) {
+            double tau = -log(u01(A[0]));
+            double kap = J->tau * orc_voigt_H(J->a, x);
+            double dm = INFINITY;
+            for (int k = 0; k < 3; ++k) {
+                double t = (n[k] > 0.0) ? (1.0 - X[k]) / n[k] : ((n[k] < 0.0) ? (-1.0 - X[k]) / n[k] : INFINITY);
+                if (t < dm) { dm = t; ax = k; }
+            }
+            if (dm < 0.0) dm = 0.0;
+            if (kap * dm < tau) {
+                for (int k = 0; k < 3; ++k) X[k] += dm * n[k];
+                valid = 1;
+                break;
+            }
+            double l = tau / kap;
+            for (int k = 0; k < 3; ++k) X[k] += l * n[k];
+        }
+        int trials;
+        double upar = sample_upar(x, J->a, &r, (uint32_t)ev, &trials);
+        double rr = sqrt(-log(u01(B[0]))), th = 2.0 * ORC_PI * u01(B[1]);
+        double up1 = rr * cos(th), up2 = rr * sin(th);
+        double g = 2.0 * u01(B[2]) - 1.0, psi = 2.0 * ORC_PI * u01(B[3]);
+        double sg = sqrt(fmax(0.0, 1.0 - g * g));
+        double e1[3], e2[3];
+        ortho_basis(n, e1, e2);
+        double cp = cos(psi), sp = sin(psi);
+        double no[3];
+        for (int k = 0; k < 3; ++k) no[k] = g * n[k] + sg * (cp * e1[k] + sp * e2[k]);
+        sx2 += x * x;
+        x = x + upar * (g - 1.0) + sg * (up1 * cp + up2 * sp);
+        for (int k = 0; k < 3; ++k) n[k] = no[k];
+        ns += 1;
+    }
+    o[0] = log10(J->tau); o[1] = log10(J->a); o[2] = J->xin;
+    if (valid) {
+        int a1 = (ax + 1) % 3, a2 = (ax + 2) % 3;
+        o[3] = x; o[4] = X[a1]; o[5] = X[a2]; o[6] = fabs(n[ax]);
+        o[7] = log((double)ns); o[8] = log(sx2 / (double)ns); o[9] = 1.0;
+    } else {
+        for (int k = 3; k < 10; ++k) o[k] = 0.0;
+    }
+}
+
+static void *escape_main(void *arg)
+{
+    esc_job_t *J = (esc_job_t *)arg;
+    for (uint64_t p = J->p0; p < J->p1; ++p) escape_one(J, p, J->out + 10 * (p - J->p0));
+    return NULL;
+}
+
+int orc_escape_record(int64_t n, double tau_R, double a, double x_in, uint64_t seed, uint64_t offset,
+                      int n_threads, double *out)
+{
+    if (n_threads < 1) n_threads = 1;
+    pthread_t th[256];
+    esc_job_t J[256];
+    if (n_threads > 256) n_threads = 256;
+    for (int t = 0; t < n_threads; ++t) {
+        J[t].tau = tau_R; J[t].a = a; J[t].xin = x_in; J[t].seed = seed; J[t].max_scat = 4000000;
+        J[t].p0 = offset + (uint64_t)n * t / n_threads;
+        J[t].p1 = offset + (uint64_t)n * (t + 1) / n_threads;
+        J[t].out = out + 10 * (J[t].p0 - offset);
+        pthread_create(&th[t], NULL, escape_main, &J[t]);
+    }
+    for (int t = 0; t < n_threads; ++t) pthread_join(th[t], NULL);
+    return 0;
+}

@@ -12,6 +12,7 @@
 #include "krt.h"
 #include "krt_internal.h"
 #include "krt_kernels.h"
+#include "krt_mlp.h"
 
 using namespace krt;
 
@@ -35,6 +36,14 @@ struct krt_ctx {
     int64_t *host_pinned = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;   // bracket the last transport launch
     float last_ms = 0.0f;
+    // learned escape: FP32 master parameters, Adam moments, gradient, packed BF16 image
+    bool mlp_ready = false;
+    float *mlp_p = nullptr, *mlp_m = nullptr, *mlp_v = nullptr, *mlp_g = nullptr, *mlp_norm = nullptr;
+    float *mlp_loss = nullptr, *mlp_u = nullptr;
+    int32_t *mlp_idx = nullptr;
+    int mlp_batch_cap = 0;
+    int mlp_step = 0;
+    unsigned char *mlp_blob = nullptr, *mlp_img = nullptr;
 };
 
 namespace {
@@ -134,6 +143,10 @@ extern "C" void krt_destroy(krt_ctx *c) {
     if (c->work_counter) (void)hipFree(c->work_counter);
     if (c->level_consts) (void)hipFree(c->level_consts);
     if (c->host_pinned) (void)hipHostFree(c->host_pinned);
+    for (void *p : {(void *)c->mlp_p, (void *)c->mlp_m, (void *)c->mlp_v, (void *)c->mlp_g, (void *)c->mlp_norm,
+                    (void *)c->mlp_loss, (void *)c->mlp_u, (void *)c->mlp_idx, (void *)c->mlp_blob,
+                    (void *)c->mlp_img})
+        if (p) (void)hipFree(p);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     delete c;
@@ -250,8 +263,18 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
     if (fj < 8 || fj > 48) return fail(c, KRT_EINVAL, "jbar_frac_bits %d outside 8..48", fj);
     const double lum = (o->luminosity != 0.0) ? o->luminosity : 1.0;
     if (!(lum > 0.0) || !std::isfinite(lum)) return fail(c, KRT_EINVAL, "luminosity must be finite and > 0");
-    int block = o->wg_size ? o->wg_size : 512;
-    int per_cu = o->wg_per_cu ? o->wg_per_cu : 2;
+    const bool esc = o->escape_mode == 1;
+    if (o->escape_mode < 0 || o->escape_mode > 1) return fail(c, KRT_EINVAL, "escape_mode %d invalid", o->escape_mode);
+    if (esc) {
+        if (!c->mlp_ready) return fail(c, KRT_ESTATE, "escape_mode 1 needs trained escape weights");
+        if (o->jbar) return fail(c, KRT_EINVAL, "escape_mode 1 does not tally the mean intensity");
+        double al = c->lines[o->line].a;
+        if (al < 1e-4 * (1 - 1e-9) || al > 1e-2 * (1 + 1e-9))
+            return fail(c, KRT_EINVAL, "learned escape covers a in [1e-4, 1e-2] (line a = %g)", al);
+    }
+    int block = o->wg_size ? o->wg_size : (esc ? 512 : 512);
+    int per_cu = o->wg_per_cu ? o->wg_per_cu : (esc ? 1 : 2);
+    if (esc && block > 512) return fail(c, KRT_EINVAL, "escape_mode 1 runs at most 512 threads per workgroup");
     if (block < 64 || block > 1024 || block % 64) return fail(c, KRT_EINVAL, "wg_size %d invalid", block);
     if (per_cu < 1 || per_cu > 64) return fail(c, KRT_EINVAL, "wg_per_cu %d invalid", per_cu);
     if (o->max_events > 0xFFFFFFFEull) return fail(c, KRT_EINVAL, "max_events too large");
@@ -318,6 +341,12 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
     P.key0 = (uint32_t)seed;
     P.key1 = (uint32_t)(seed >> 32);
     P.work_counter = c->work_counter;
+    P.mlp_img = esc ? c->mlp_img : nullptr;
+    P.esc_tau_min = (float)(o->esc_tau_min > 0.0 ? o->esc_tau_min : 100.0);
+    P.esc_tau_max = 1e5f;
+    P.esc_x_max = 8.0f;
+    P.esc_log10a = (float)std::log10(c->lines[l].a);
+    P.esc_min_lanes = o->esc_min_lanes > 0 ? o->esc_min_lanes : 8;
     int grid = c->cus * per_cu;
     HIPCHK(c, hipEventRecord(c->ev0, c->stream));
     HIPCHK(c, launch_transport(P, grid, block, c->stream));
@@ -487,6 +516,168 @@ extern "C" int krt_debug_upar(krt_ctx *c, int32_t line, float x, uint64_t seed, 
     float a = (float)c->lines[line].a, thd = (float)std::atan(kDelta / c->lines[line].a);
     HIPCHK(c, launch_debug_upar(c->tab[line], a, thd, x, (uint32_t)seed, (uint32_t)(seed >> 32), packet, ev0, n,
                                 out, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return KRT_OK;
+}
+
+// ------------------------------------------------------- learned escape ---
+namespace {
+int mlp_alloc(krt_ctx *c) {
+    if (c->mlp_p) return KRT_OK;
+    HIPCHK(c, hipMalloc(&c->mlp_p, sizeof(float) * kNParams));
+    HIPCHK(c, hipMalloc(&c->mlp_m, sizeof(float) * kNParams));
+    HIPCHK(c, hipMalloc(&c->mlp_v, sizeof(float) * kNParams));
+    HIPCHK(c, hipMalloc(&c->mlp_g, sizeof(float) * kNParams));
+    HIPCHK(c, hipMalloc(&c->mlp_norm, sizeof(float) * kNNorm));
+    HIPCHK(c, hipMalloc(&c->mlp_loss, sizeof(float) * 2));
+    HIPCHK(c, hipMalloc(&c->mlp_blob, kMlpBlobBytes));
+    HIPCHK(c, hipMalloc(&c->mlp_img, kMlpFwdBytes));
+    return KRT_OK;
+}
+
+int mlp_zero_state(krt_ctx *c) {
+    HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(c->mlp_m), kNParams / 2, c->stream));
+    HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(c->mlp_v), kNParams / 2, c->stream));
+    HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(c->mlp_g), kNParams / 2, c->stream));
+    c->mlp_step = 0;
+    return KRT_OK;
+}
+
+int mlp_ensure_batch(krt_ctx *c, int batch) {
+    if (batch <= c->mlp_batch_cap) return KRT_OK;
+    if (c->mlp_idx) (void)hipFree(c->mlp_idx);
+    if (c->mlp_u) (void)hipFree(c->mlp_u);
+    c->mlp_idx = nullptr;
+    c->mlp_u = nullptr;
+    HIPCHK(c, hipMalloc(&c->mlp_idx, sizeof(int32_t) * batch));
+    HIPCHK(c, hipMalloc(&c->mlp_u, sizeof(float) * batch));
+    c->mlp_batch_cap = batch;
+    return KRT_OK;
+}
+}  // namespace
+
+static_assert(kNParams % 2 == 0, "parameter count is even (zeroed as int64 pairs)");
+
+extern "C" int krt_escape_init(krt_ctx *c, uint64_t seed) {
+    if (!c) return KRT_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc = mlp_alloc(c);
+    if (rc) return rc;
+    HIPCHK(c, launch_mlp_init(c->mlp_p, (uint32_t)seed, (uint32_t)(seed >> 32), c->stream));
+    rc = mlp_zero_state(c);
+    if (rc) return rc;
+    float norm[kNNorm];
+    for (int k = 0; k < kMlpOut; ++k) { norm[k] = 0.0f; norm[kMlpOut + k] = 1.0f; }
+    HIPCHK(c, hipMemcpyAsync(c->mlp_norm, norm, sizeof(norm), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, launch_mlp_pack(c->mlp_p, c->mlp_norm, c->mlp_blob, c->mlp_img, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->mlp_ready = true;
+    return KRT_OK;
+}
+
+extern "C" int krt_escape_record(krt_ctx *c, int32_t line, uint64_t n, uint64_t seed, uint64_t offset,
+                                 double log10_tau_lo, double log10_tau_hi, int32_t x_fixed, double x_in,
+                                 float *samples_dev) {
+    if (!c) return KRT_EINVAL;
+    if (line < 0 || line >= (int)c->tab.size()) return fail(c, KRT_ESTATE, "line %d has no tables", line);
+    if (!samples_dev || n == 0 || n > (1ull << 31)) return fail(c, KRT_EINVAL, "bad record args");
+    if (!(log10_tau_hi >= log10_tau_lo) || log10_tau_lo < 0.0 || log10_tau_hi > 6.0)
+        return fail(c, KRT_EINVAL, "log10 tau range must lie in [0, 6]");
+    HIPCHK(c, hipSetDevice(c->device));
+    float a = (float)c->lines[line].a, thd = (float)std::atan(kDelta / c->lines[line].a);
+    HIPCHK(c, launch_escape_record(c->tab[line], a, thd, (uint32_t)seed, (uint32_t)(seed >> 32), offset, (int64_t)n,
+                                   (float)log10_tau_lo, (float)log10_tau_hi, 4000000u, x_fixed ? 1 : 0, (float)x_in,
+                                   samples_dev, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return KRT_OK;
+}
+
+extern "C" int krt_escape_fit_norm(krt_ctx *c, const float *samples_dev, uint64_t n) {
+    if (!c) return KRT_EINVAL;
+    if (!c->mlp_ready) return fail(c, KRT_ESTATE, "call krt_escape_init first");
+    if (!samples_dev || n == 0) return fail(c, KRT_EINVAL, "bad norm args");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_mlp_norm(samples_dev, (int64_t)n, c->mlp_norm, c->stream));
+    HIPCHK(c, launch_mlp_pack(c->mlp_p, c->mlp_norm, c->mlp_blob, c->mlp_img, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return KRT_OK;
+}
+
+extern "C" int krt_escape_grad(krt_ctx *c, const float *samples_dev, const int32_t *idx_dev, const float *u_dev,
+                               int32_t batch, float *grad_out_dev, float *loss_out_dev) {
+    if (!c) return KRT_EINVAL;
+    if (!c->mlp_ready) return fail(c, KRT_ESTATE, "call krt_escape_init first");
+    if (!samples_dev || !idx_dev || !u_dev || !grad_out_dev || batch <= 0) return fail(c, KRT_EINVAL, "bad grad args");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(c->mlp_g), kNParams / 2, c->stream));
+    HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(c->mlp_loss), 1, c->stream));
+    HIPCHK(c, launch_mlp_grad(c->mlp_blob, samples_dev, idx_dev, u_dev, batch, c->mlp_g, c->mlp_loss, c->stream));
+    HIPCHK(c, hipMemcpyAsync(grad_out_dev, c->mlp_g, sizeof(float) * kNParams, hipMemcpyDeviceToDevice, c->stream));
+    if (loss_out_dev) HIPCHK(c, hipMemcpyAsync(loss_out_dev, c->mlp_loss, sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(c->mlp_g), kNParams / 2, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return KRT_OK;
+}
+
+extern "C" int krt_escape_train(krt_ctx *c, const float *samples_dev, uint64_t n, int32_t steps, int32_t batch,
+                                double lr, uint64_t seed, float *loss_hist_dev) {
+    if (!c) return KRT_EINVAL;
+    if (!c->mlp_ready) return fail(c, KRT_ESTATE, "call krt_escape_init first");
+    if (!samples_dev || n == 0 || n >= (1ull << 31) || steps <= 0 || batch <= 0 || batch > (1 << 20) ||
+        !(lr > 0.0))
+        return fail(c, KRT_EINVAL, "bad train args");
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc = mlp_ensure_batch(c, batch);
+    if (rc) return rc;
+    for (int s = 0; s < steps; ++s) {
+        c->mlp_step += 1;
+        HIPCHK(c, launch_mlp_batch((int64_t)n, (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)c->mlp_step, batch,
+                                   c->mlp_idx, c->mlp_u, c->stream));
+        float *lslot = loss_hist_dev ? loss_hist_dev + s : c->mlp_loss;
+        HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(c->mlp_loss), 1, c->stream));
+        HIPCHK(c, launch_mlp_grad(c->mlp_blob, samples_dev, c->mlp_idx, c->mlp_u, batch, c->mlp_g, c->mlp_loss,
+                                  c->stream));
+        if (loss_hist_dev) HIPCHK(c, hipMemcpyAsync(lslot, c->mlp_loss, sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, launch_mlp_adam(c->mlp_p, c->mlp_m, c->mlp_v, c->mlp_g, (float)lr, c->mlp_step, c->stream));
+        HIPCHK(c, launch_mlp_pack(c->mlp_p, c->mlp_norm, c->mlp_blob, (s == steps - 1) ? c->mlp_img : nullptr,
+                                  c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return KRT_OK;
+}
+
+extern "C" int krt_escape_get_weights(krt_ctx *c, float *dev, uint64_t nfloats) {
+    if (!c) return KRT_EINVAL;
+    if (!c->mlp_ready) return fail(c, KRT_ESTATE, "call krt_escape_init first");
+    if (!dev || nfloats != (uint64_t)(kNParams + kNNorm)) return fail(c, KRT_EINVAL, "need %d floats", kNParams + kNNorm);
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipMemcpyAsync(dev, c->mlp_p, sizeof(float) * kNParams, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(dev + kNParams, c->mlp_norm, sizeof(float) * kNNorm, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return KRT_OK;
+}
+
+extern "C" int krt_escape_put_weights(krt_ctx *c, const float *dev, uint64_t nfloats) {
+    if (!c) return KRT_EINVAL;
+    if (!dev || nfloats != (uint64_t)(kNParams + kNNorm)) return fail(c, KRT_EINVAL, "need %d floats", kNParams + kNNorm);
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc = mlp_alloc(c);
+    if (rc) return rc;
+    if (!c->mlp_ready) { rc = mlp_zero_state(c); if (rc) return rc; }
+    HIPCHK(c, hipMemcpyAsync(c->mlp_p, dev, sizeof(float) * kNParams, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->mlp_norm, dev + kNParams, sizeof(float) * kNNorm, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, launch_mlp_pack(c->mlp_p, c->mlp_norm, c->mlp_blob, c->mlp_img, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->mlp_ready = true;
+    return KRT_OK;
+}
+
+extern "C" int krt_escape_forward(krt_ctx *c, const float *in_dev, int64_t n, float *out_dev) {
+    if (!c) return KRT_EINVAL;
+    if (!c->mlp_ready) return fail(c, KRT_ESTATE, "call krt_escape_init first");
+    if (!in_dev || !out_dev || n <= 0) return fail(c, KRT_EINVAL, "bad forward args");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_mlp_forward(c->mlp_blob, in_dev, n, out_dev, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return KRT_OK;
 }

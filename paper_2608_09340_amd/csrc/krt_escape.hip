@@ -1,0 +1,510 @@
+// krt_escape.hip -- learned escape proposal: training data from single-cell
+// escapes run by the plain transport arithmetic, BF16-MFMA training (forward,
+// backward, Adam) and batched inference.
+//
+// Single-cell escape (training data): a homogeneous static cube of half-width 1
+// and line-centre opacity k0 = tau_R per unit length; a photon of gas-frame
+// frequency x_in and isotropic incoming direction scatters at the centre, then
+// random-walks (the same flights and resonant scatterings as the transport
+// kernel) until it leaves the cube.  Recorded: the exit frequency, the exit
+// point (s, t) on the exit face (the face's two tangential coordinates in cyclic
+// order), the cosine mu of the exit direction to the face normal, the number of
+// scatterings N_s and the mean of x^2 over them.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "krt_internal.h"
+#include "krt_kernels.h"
+#include "krt_mlp.h"
+#include "krt_device.h"
+
+namespace krt {
+
+// ------------------------------------------------------------- recording ---
+// record: [log10 tau_R, log10 a, x_in, x_out, s, t, mu, ln N_s, ln <x^2>, valid]
+constexpr int kRec = 10;
+
+__global__ void __launch_bounds__(256) escape_record_kernel(const float *tab, float a, float thd, uint32_t k0,
+                                                            uint32_t k1, uint64_t offset, int64_t n,
+                                                            float lt_lo, float lt_hi, uint32_t max_scat,
+                                                            int x_fixed, float x_value, float *out) {
+    extern __shared__ float4 lds4[];
+    float *T = reinterpret_cast<float *>(lds4);
+    const float4 *src = reinterpret_cast<const float4 *>(tab);
+    for (int i = threadIdx.x; i < kTabFloats / 4; i += blockDim.x) lds4[i] = src[i];
+    __syncthreads();
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t pid = offset + (uint64_t)i;
+    const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
+    // condition: purpose 3 of event 0
+    uint4 c = philox(make_uint4(0u, plo, phi, 3u), k0, k1);
+    float lt = lt_lo + (lt_hi - lt_lo) * u01(c.x);
+    float tauR = f_exp(lt * 2.302585093f);
+    float xin;
+    if (x_fixed) {
+        xin = x_value;
+    } else if (u01(c.y) < 0.5f) {
+        float rr = f_sqrt(-f_log(u01(c.z)));
+        xin = rr * cos_rev(u01(c.w));
+    } else {
+        xin = -8.0f + 16.0f * u01(c.z);
+    }
+    uint4 d = philox(make_uint4(0u, plo, phi, 4u), k0, k1);
+    float mu0 = 2.0f * u01(d.x) - 1.0f, st0 = f_sqrt(fmaxf(0.0f, 1.0f - mu0 * mu0)), ph0 = u01(d.y);
+    float nx = st0 * cos_rev(ph0), ny = st0 * sin_rev(ph0), nz = mu0;
+    float px = 0.0f, py = 0.0f, pz = 0.0f;
+    float x = xin;  // gas frame = lab frame (static)
+    uint32_t ns = 0;
+    float sx2 = 0.0f;
+    bool done = false, valid = false;
+    int ax = 0;
+    for (uint32_t ev = 1; ev <= max_scat + 1; ++ev) {
+        if (ev > 1) {
+            // flight from the current interaction point
+            uint4 A = philox(make_uint4(ev, plo, phi, 0u), k0, k1);
+            float tau = -f_log(u01(A.x));
+            float kap = tauR * voigt_lds(T, fabsf(x));
+            float tx = (nx > 0.f) ? (1.f - px) * f_rcp(nx) : ((nx < 0.f) ? (-1.f - px) * f_rcp(nx) : INFINITY);
+            float ty = (ny > 0.f) ? (1.f - py) * f_rcp(ny) : ((ny < 0.f) ? (-1.f - py) * f_rcp(ny) : INFINITY);
+            float tz = (nz > 0.f) ? (1.f - pz) * f_rcp(nz) : ((nz < 0.f) ? (-1.f - pz) * f_rcp(nz) : INFINITY);
+            float dm = tx; ax = 0;
+            if (ty < dm) { dm = ty; ax = 1; }
+            if (tz < dm) { dm = tz; ax = 2; }
+            dm = fmaxf(dm, 0.0f);
+            if (kap * dm < tau) {  // leaves the cube
+                px += dm * nx; py += dm * ny; pz += dm * nz;
+                done = true;
+                valid = true;
+                break;
+            }
+            float l = tau * f_rcp(kap);
+            px = fminf(fmaxf(px + l * nx, -1.f), 1.f);
+            py = fminf(fmaxf(py + l * ny, -1.f), 1.f);
+            pz = fminf(fmaxf(pz + l * nz, -1.f), 1.f);
+        }
+        // resonant scattering at (px, py, pz): event ev words
+        uint4 A = philox(make_uint4(ev, plo, phi, 0u), k0, k1);
+        uint4 B = philox(make_uint4(ev, plo, phi, 1u), k0, k1);
+        float upar = upar_lds(T, x, a, thd, u01(A.z), u01(A.w));
+        float rr = f_sqrt(-f_log(u01(B.x)));
+        float th = u01(B.y);
+        float up1 = rr * cos_rev(th), up2 = rr * sin_rev(th);
+        float g = 2.0f * u01(B.z) - 1.0f;
+        float psi = u01(B.w);
+        float sg = f_sqrt(fmaxf(0.0f, 1.0f - g * g));
+        float sgn = copysignf(1.0f, nz);
+        float A_ = -f_rcp(sgn + nz);
+        float B_ = nx * ny * A_;
+        float e1x = 1.0f + sgn * nx * nx * A_, e1y = sgn * B_, e1z = -sgn * nx;
+        float e2x = B_, e2y = sgn + ny * ny * A_, e2z = -ny;
+        float cp = cos_rev(psi), sp = sin_rev(psi);
+        float ox = g * nx + sg * (cp * e1x + sp * e2x);
+        float oy = g * ny + sg * (cp * e1y + sp * e2y);
+        float oz = g * nz + sg * (cp * e1z + sp * e2z);
+        float rn = f_rsq(ox * ox + oy * oy + oz * oz);
+        sx2 += x * x;
+        x = x + upar * (g - 1.0f) + sg * (up1 * cp + up2 * sp);
+        nx = ox * rn; ny = oy * rn; nz = oz * rn;
+        ns += 1;
+    }
+    float *o = out + (int64_t)kRec * i;
+    o[0] = lt;
+    o[1] = __log10f(a);
+    o[2] = xin;
+    if (valid) {
+        // exit face: axis ax, sign of the normal; tangential coordinates in cyclic order
+        float p[3] = {px, py, pz}, nn[3] = {nx, ny, nz};
+        int a1 = (ax + 1) % 3, a2 = (ax + 2) % 3;
+        o[3] = x;
+        o[4] = fminf(fmaxf(p[a1], -1.f), 1.f);
+        o[5] = fminf(fmaxf(p[a2], -1.f), 1.f);
+        o[6] = fabsf(nn[ax]);
+        o[7] = logf((float)ns);
+        o[8] = logf(fmaxf(sx2 / (float)ns, 1e-6f));
+        o[9] = 1.0f;
+    } else {
+        for (int k = 3; k < kRec; ++k) o[k] = 0.0f;
+    }
+    (void)done;
+}
+
+// ---------------------------------------------------------- parameters ---
+// He-uniform initialisation from Philox (counter = (param index, 0, 0, 7))
+__global__ void mlp_init_kernel(float *p, uint32_t k0, uint32_t k1) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kNParams) return;
+    uint4 r = philox(make_uint4((uint32_t)i, 0u, 0u, 7u), k0, k1);
+    float u = 2.0f * u01(r.x) - 1.0f;
+    float fan_in;
+    bool bias = false;
+    if (i < kPB1) fan_in = kMlpIn;
+    else if (i < kPW2) bias = true;
+    else if (i < kPB2) fan_in = kMlpHid;
+    else if (i < kPW3) bias = true;
+    else if (i < kPB3) fan_in = kMlpHid;
+    else if (i < kPW4) bias = true;
+    else if (i < kPB4) fan_in = kMlpHid;
+    else bias = true;
+    p[i] = bias ? 0.0f : u * sqrtf(6.0f / fan_in);
+}
+
+// Pack the FP32 master parameters into BF16 A-operand tiles + FP32 biases.
+// One thread per (tile, lane).
+__global__ void mlp_pack_kernel(const float *p, const float *norm, unsigned char *blob) {
+    int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid < kTilesAll * 64) {
+        int t = gid / 64, lane = gid % 64;
+        int i = lane % 16, g = lane / 16;
+        float v[4];
+        for (int j = 0; j < 4; ++j) {
+            int k = 4 * g + j;
+            float w = 0.0f;
+            if (t < kTileFwdL2) {  // L1 fwd: W1^T tile mo = t, A[i][k] = W1[k][16mo+i]
+                int mo = t - kTileFwdL1;
+                if (k < kMlpIn) w = p[kPW1 + k * kMlpHid + 16 * mo + i];
+            } else if (t < kTileFwdL4) {  // L2/L3 fwd: tile mo*8+ki, A[i][k] = W[16ki+k][16mo+i]
+                int base = (t < kTileFwdL3) ? kPW2 : kPW3;
+                int tt = t - ((t < kTileFwdL3) ? kTileFwdL2 : kTileFwdL3);
+                int mo = tt / 8, ki = tt % 8;
+                w = p[base + (16 * ki + k) * kMlpHid + 16 * mo + i];
+            } else if (t < kTilesFwd) {  // L4 fwd: tile ki, A[i][k] = W4[16ki+k][i]
+                int ki = t - kTileFwdL4;
+                if (i < kMlpOut) w = p[kPW4 + (16 * ki + k) * kMlpOut + i];
+            } else if (t < kTileBwdL3) {  // L4 bwd: tile mi, A[i][k] = W4[16mi+i][k]
+                int mi = t - kTileBwdL4;
+                if (k < kMlpOut) w = p[kPW4 + (16 * mi + i) * kMlpOut + k];
+            } else {  // L3/L2 bwd: tile mi*8+ko, A[i][k] = W[16mi+i][16ko+k]
+                int base = (t < kTileBwdL2) ? kPW3 : kPW2;
+                int tt = t - ((t < kTileBwdL2) ? kTileBwdL3 : kTileBwdL2);
+                int mi = tt / 8, ko = tt % 8;
+                w = p[base + (16 * mi + i) * kMlpHid + 16 * ko + k];
+            }
+            v[j] = w;
+        }
+        uint16_t *dst = reinterpret_cast<uint16_t *>(blob + t * kTileBytes + lane * 8);
+        for (int j = 0; j < 4; ++j) dst[j] = f2bf(v[j]);
+    }
+    // biases and normalisation (fwd layout: b1 b2 b3 b4pad16 norm)
+    float *fb = reinterpret_cast<float *>(blob + kTilesAll * kTileBytes);
+    if (gid < kBiasFloats) {
+        float b;
+        if (gid < 128) b = p[kPB1 + gid];
+        else if (gid < 256) b = p[kPB2 + gid - 128];
+        else if (gid < 384) b = p[kPB3 + gid - 256];
+        else b = (gid - 384 < kMlpOut) ? p[kPB4 + gid - 384] : 0.0f;
+        fb[gid] = b;
+    }
+    if (gid < kNNorm) fb[kBiasFloats + gid] = norm[gid];
+}
+
+// Copy of the forward part (tiles + biases + norm) into one contiguous image,
+// the layout staged into LDS by the transport kernel.
+__global__ void mlp_fwd_image_kernel(const unsigned char *blob, unsigned char *img) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int tiles_b = kTilesFwd * kTileBytes;
+    const int tail_b = (kBiasFloats + kNNorm) * 4;
+    if (i < tiles_b) img[i] = blob[i];
+    else if (i < tiles_b + tail_b) img[i] = blob[kTilesAll * kTileBytes + (i - tiles_b)];
+}
+
+// ------------------------------------------------------------- inputs ---
+__device__ __forceinline__ void mlp_inputs(float lt, float la, float xin, float u, float in[4]) {
+    in[0] = (lt - 3.5f) * (1.0f / 1.5f);
+    in[1] = la + 3.0f;
+    in[2] = xin * 0.25f;
+    in[3] = 2.0f * u - 1.0f;
+}
+
+__device__ __forceinline__ v4i16 xin_operand(const float in[4], int lane) {
+    return (lane < 16) ? pack4(in[0], in[1], in[2], in[3]) : pack4(0.f, 0.f, 0.f, 0.f);
+}
+
+// ---------------------------------------------------------- gradient ---
+// One wave per 16-sample block.  grad += d(mean pinball loss)/d(params); loss += sum.
+__global__ void __launch_bounds__(256) mlp_grad_kernel(const unsigned char *blob, const float *rec,
+                                                       const int32_t *idx, const float *uq, int batch,
+                                                       float *grad, float *loss) {
+    __shared__ uint16_t tr[4][16][16 * 16 + 8];  // per wave: 16 transposed tiles (8 H + 8 dZ)
+    const int lane = __lane_id(), w = threadIdx.x / 64;
+    const int block = blockIdx.x * (blockDim.x / 64) + w;
+    const int nblocks = (batch + 15) / 16;
+    const bool wave_live = block < nblocks;  // idle waves still reach every barrier
+    const int s = lane % 16, g = lane / 16;
+    const int si = block * 16 + s;
+    const float *r0 = rec + (int64_t)kRec * idx[0];
+    const bool live = wave_live && si < batch && r0 != nullptr && rec[(int64_t)kRec * idx[si < batch ? si : 0] + 9] > 0.5f;
+    const float *bias = reinterpret_cast<const float *>(blob + kTilesAll * kTileBytes);
+    const float *norm = bias + kBiasFloats;
+    const float *r = rec + (int64_t)kRec * (live ? idx[si] : idx[0]);
+    const float u = live ? uq[si] : 0.5f;
+    float in[4];
+    mlp_inputs(r[0], r[1], r[2], u, in);
+    if (!live) in[0] = in[1] = in[2] = in[3] = 0.0f;
+    v4i16 xb = xin_operand(in, lane);
+    v4f32 z1[8], z2[8], z3[8];
+    v4f32 o = mlp_forward_block(blob, bias, xb, lane, z1, z2, z3);
+    // pinball loss and its gradient for outputs k = 4g + j
+    const float invB = 1.0f / (float)batch;
+    float dO[4], lsum = 0.0f;
+    for (int j = 0; j < 4; ++j) {
+        int k = 4 * g + j;
+        float oj = (j == 0) ? o.x : (j == 1) ? o.y : (j == 2) ? o.z : o.w;
+        dO[j] = 0.0f;
+        if (k < kMlpOut && live) {
+            float y = (r[3 + k] - norm[k]) / norm[kMlpOut + k];
+            float ind = (y < oj) ? 1.0f : 0.0f;
+            dO[j] = (ind - u) * invB;
+            lsum += (y - oj) * (u - ind);
+        }
+    }
+    // loss: reduce over the wave
+    for (int off = 32; off >= 1; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
+    if (lane == 0 && wave_live) atomicAdd(loss, lsum * invB);
+    v4i16 dOb = pack4(dO[0], dO[1], dO[2], dO[3]);
+
+    // helpers: write the 8 tiles of a (features x samples) quantity transposed
+    // into LDS as [feature][sample] bf16, read back sample-major A/B operands.
+    auto put = [&](int slot, int mo, float a0, float a1, float a2, float a3) {
+        uint16_t *t = &tr[w][slot][0];
+        (void)mo;
+        t[(4 * g + 0) * 16 + s] = f2bf(a0);
+        t[(4 * g + 1) * 16 + s] = f2bf(a1);
+        t[(4 * g + 2) * 16 + s] = f2bf(a2);
+        t[(4 * g + 3) * 16 + s] = f2bf(a3);
+    };
+    auto get = [&](int slot) -> v4i16 {  // lane l: row l%16 (feature), samples 4g..4g+3
+        const uint16_t *t = &tr[w][slot][0];
+        v4i16 v;
+        v.x = (short)t[s * 16 + 4 * g + 0];
+        v.y = (short)t[s * 16 + 4 * g + 1];
+        v.z = (short)t[s * 16 + 4 * g + 2];
+        v.w = (short)t[s * 16 + 4 * g + 3];
+        return v;
+    };
+    // weight gradient of one layer: dW[in][out] += sum_s Hin[in][s] dZ[out][s]
+    // (nin_t input tiles of activations, nout_t output tiles of dZ, already in LDS
+    // slots 0..nin_t-1 and 8..8+nout_t-1)
+    auto wgrad = [&](int nin_t, int nout_t, int base, int ld, int nin, int nout) {
+        for (int mi = 0; mi < nin_t; ++mi) {
+            v4i16 a = get(mi);
+            for (int mo = 0; mo < nout_t; ++mo) {
+                v4i16 b = get(8 + mo);
+                v4f32 acc = {0.f, 0.f, 0.f, 0.f};
+                acc = mfma16(a, b, acc);
+                // D lane l: rows (in) 4g+j, col (out) l%16
+                int outc = 16 * mo + s;
+                for (int j = 0; j < 4; ++j) {
+                    int inr = 16 * mi + 4 * g + j;
+                    float v = (j == 0) ? acc.x : (j == 1) ? acc.y : (j == 2) ? acc.z : acc.w;
+                    if (wave_live && inr < nin && outc < nout && v != 0.0f) atomicAdd(grad + base + inr * ld + outc, v);
+                }
+            }
+        }
+    };
+    auto bgrad = [&](int base, int nout, int mo, v4f32 dz) {  // sum over the 16 samples of a tile
+        float v[4] = {dz.x, dz.y, dz.z, dz.w};
+        for (int j = 0; j < 4; ++j) {
+            float t = v[j];
+            for (int off = 8; off >= 1; off >>= 1) t += __shfl_xor(t, off, 16);
+            int f = 16 * mo + 4 * g + j;
+            if (wave_live && s == 0 && f < nout) atomicAdd(grad + base + f, t);
+        }
+    };
+    auto dsilu = [](float z) { float sg = 1.0f / (1.0f + __expf(-z)); return sg * (1.0f + z * (1.0f - sg)); };
+
+    // ---- layer 4: dW4 = H3 dO^T, db4, dH3 = W4 dO
+    for (int mi = 0; mi < 8; ++mi) put(mi, mi, silu(z3[mi].x), silu(z3[mi].y), silu(z3[mi].z), silu(z3[mi].w));
+    put(8, 0, dO[0], dO[1], dO[2], dO[3]);
+    __syncthreads();
+    wgrad(8, 1, kPW4, kMlpOut, kMlpHid, kMlpOut);
+    bgrad(kPB4, kMlpOut, 0, (v4f32){dO[0], dO[1], dO[2], dO[3]});
+    v4f32 dz[8];
+    for (int mi = 0; mi < 8; ++mi) {
+        v4f32 acc = {0.f, 0.f, 0.f, 0.f};
+        acc = mfma16(tileA(blob, kTileBwdL4 + mi, lane), dOb, acc);
+        dz[mi] = (v4f32){acc.x * dsilu(z3[mi].x), acc.y * dsilu(z3[mi].y), acc.z * dsilu(z3[mi].z),
+                         acc.w * dsilu(z3[mi].w)};
+    }
+    // ---- layers 3 and 2
+    for (int layer = 3; layer >= 2; --layer) {
+        v4f32 *zin = (layer == 3) ? z2 : z1;
+        const int pw = (layer == 3) ? kPW3 : kPW2, pb = (layer == 3) ? kPB3 : kPB2;
+        const int tb = (layer == 3) ? kTileBwdL3 : kTileBwdL2;
+        __syncthreads();
+        for (int mi = 0; mi < 8; ++mi) put(mi, mi, silu(zin[mi].x), silu(zin[mi].y), silu(zin[mi].z), silu(zin[mi].w));
+        for (int mo = 0; mo < 8; ++mo) put(8 + mo, mo, dz[mo].x, dz[mo].y, dz[mo].z, dz[mo].w);
+        __syncthreads();
+        wgrad(8, 8, pw, kMlpHid, kMlpHid, kMlpHid);
+        for (int mo = 0; mo < 8; ++mo) bgrad(pb, kMlpHid, mo, dz[mo]);
+        v4i16 dzb[8];
+        for (int mo = 0; mo < 8; ++mo) dzb[mo] = pack4(dz[mo].x, dz[mo].y, dz[mo].z, dz[mo].w);
+        for (int mi = 0; mi < 8; ++mi) {
+            v4f32 acc = {0.f, 0.f, 0.f, 0.f};
+            for (int ko = 0; ko < 8; ++ko) acc = mfma16(tileA(blob, tb + mi * 8 + ko, lane), dzb[ko], acc);
+            dz[mi] = (v4f32){acc.x * dsilu(zin[mi].x), acc.y * dsilu(zin[mi].y), acc.z * dsilu(zin[mi].z),
+                             acc.w * dsilu(zin[mi].w)};
+        }
+    }
+    // ---- layer 1: dW1 = X dZ1^T (X rows 0..3), db1
+    __syncthreads();
+    put(0, 0, g == 0 ? in[0] : 0.f, g == 0 ? in[1] : 0.f, g == 0 ? in[2] : 0.f, g == 0 ? in[3] : 0.f);
+    for (int mo = 0; mo < 8; ++mo) put(8 + mo, mo, dz[mo].x, dz[mo].y, dz[mo].z, dz[mo].w);
+    __syncthreads();
+    wgrad(1, 8, kPW1, kMlpHid, kMlpIn, kMlpHid);
+    for (int mo = 0; mo < 8; ++mo) bgrad(kPB1, kMlpHid, mo, dz[mo]);
+}
+
+// Adam (FP32 master, bias-corrected), then the gradient buffer is cleared.
+__global__ void mlp_adam_kernel(float *p, float *m, float *v, float *grad, float lr, float b1, float b2,
+                                float eps, float c1, float c2) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kNParams) return;
+    float gi = grad[i];
+    float mi = b1 * m[i] + (1.0f - b1) * gi;
+    float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    grad[i] = 0.0f;
+}
+
+// Random batch: indices uniform over the valid records, quantile levels u.
+__global__ void mlp_batch_kernel(int64_t n, uint32_t k0, uint32_t k1, uint32_t step, int batch,
+                                 int32_t *idx, float *uq) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= batch) return;
+    uint4 r = philox(make_uint4(step, (uint32_t)i, 0u, 9u), k0, k1);
+    idx[i] = (int32_t)__umulhi(r.x, (uint32_t)n);
+    uq[i] = u01(r.y);
+}
+
+// Normalisation of the 6 targets: mean and standard deviation over records
+// (FP64 accumulation, one block of 256 threads per target).
+__global__ void mlp_norm_kernel(const float *rec, int64_t n, float *norm) {
+    __shared__ double s1[256], s2[256];
+    int k = blockIdx.x;
+    __shared__ double s0[256];
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        if (rec[(int64_t)kRec * i + 9] < 0.5f) continue;
+        double y = rec[(int64_t)kRec * i + 3 + k];
+        a += y;
+        b += y * y;
+        c += 1.0;
+    }
+    s1[threadIdx.x] = a;
+    s2[threadIdx.x] = b;
+    s0[threadIdx.x] = c;
+    __syncthreads();
+    for (int st = 128; st >= 1; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            s1[threadIdx.x] += s1[threadIdx.x + st];
+            s2[threadIdx.x] += s2[threadIdx.x + st];
+            s0[threadIdx.x] += s0[threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double cnt = s0[0] > 0.0 ? s0[0] : 1.0;
+        double mean = s1[0] / cnt;
+        double var = s2[0] / cnt - mean * mean;
+        norm[k] = (float)mean;
+        norm[kMlpOut + k] = (float)sqrt(var > 1e-12 ? var : 1e-12);
+    }
+}
+
+// Forward for a list of raw conditions in[n][4] = (log10 tau_R, log10 a, x_in, u):
+// out[n][6] in physical units.
+__global__ void __launch_bounds__(256) mlp_forward_kernel(const unsigned char *blob, const float *inp,
+                                                          int64_t n, float *out) {
+    const int lane = __lane_id(), w = threadIdx.x / 64;
+    const int64_t block = (int64_t)blockIdx.x * (blockDim.x / 64) + w;
+    const int s = lane % 16, g = lane / 16;
+    const int64_t si = block * 16 + s;
+    if (block * 16 >= n) return;
+    const bool live = si < n;
+    const float *bias = reinterpret_cast<const float *>(blob + kTilesAll * kTileBytes);
+    const float *norm = bias + kBiasFloats;
+    const float *r = inp + 4 * (live ? si : 0);
+    float in[4];
+    mlp_inputs(r[0], r[1], r[2], r[3], in);
+    v4f32 o = mlp_forward_block(blob, bias, xin_operand(in, lane), lane, nullptr, nullptr, nullptr);
+    if (!live) return;
+    float v[4] = {o.x, o.y, o.z, o.w};
+    for (int j = 0; j < 4; ++j) {
+        int k = 4 * g + j;
+        if (k < kMlpOut) out[6 * si + k] = v[j] * norm[kMlpOut + k] + norm[k];
+    }
+}
+
+// --------------------------------------------------------------- launch ---
+hipError_t launch_escape_record(const float *tab, float a, float thd, uint32_t k0, uint32_t k1, uint64_t offset,
+                                int64_t n, float lt_lo, float lt_hi, uint32_t max_scat, int x_fixed, float x_value,
+                                float *out, hipStream_t s) {
+    size_t lds = sizeof(float) * kTabFloats;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(escape_record_kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    int grid = (int)((n + 255) / 256);
+    hipLaunchKernelGGL(escape_record_kernel, dim3(grid), dim3(256), lds, s, tab, a, thd, k0, k1, offset, n,
+                       lt_lo, lt_hi, max_scat, x_fixed, x_value, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_init(float *p, uint32_t k0, uint32_t k1, hipStream_t s) {
+    hipLaunchKernelGGL(mlp_init_kernel, dim3((kNParams + 255) / 256), dim3(256), 0, s, p, k0, k1);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_pack(const float *p, const float *norm, unsigned char *blob, unsigned char *img,
+                           hipStream_t s) {
+    int n = kTilesAll * 64;
+    hipLaunchKernelGGL(mlp_pack_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, norm, blob);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !img) return e;
+    int nb = kMlpFwdBytes;
+    hipLaunchKernelGGL(mlp_fwd_image_kernel, dim3((nb + 255) / 256), dim3(256), 0, s, blob, img);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_grad(const unsigned char *blob, const float *rec, const int32_t *idx, const float *uq,
+                           int batch, float *grad, float *loss, hipStream_t s) {
+    int nblocks = (batch + 15) / 16;
+    int grid = (nblocks + 3) / 4;
+    hipLaunchKernelGGL(mlp_grad_kernel, dim3(grid), dim3(256), 0, s, blob, rec, idx, uq, batch, grad, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_adam(float *p, float *m, float *v, float *grad, float lr, int step, hipStream_t s) {
+    const float b1 = 0.9f, b2 = 0.999f;
+    float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+    hipLaunchKernelGGL(mlp_adam_kernel, dim3((kNParams + 255) / 256), dim3(256), 0, s, p, m, v, grad, lr, b1, b2,
+                       1e-8f, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_batch(int64_t n, uint32_t k0, uint32_t k1, uint32_t step, int batch, int32_t *idx,
+                            float *uq, hipStream_t s) {
+    hipLaunchKernelGGL(mlp_batch_kernel, dim3((batch + 255) / 256), dim3(256), 0, s, n, k0, k1, step, batch,
+                       idx, uq);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_norm(const float *rec, int64_t n, float *norm, hipStream_t s) {
+    hipLaunchKernelGGL(mlp_norm_kernel, dim3(kMlpOut), dim3(256), 0, s, rec, n, norm);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const unsigned char *blob, const float *inp, int64_t n, float *out, hipStream_t s) {
+    int64_t nblocks = (n + 15) / 16;
+    int grid = (int)((nblocks + 3) / 4);
+    hipLaunchKernelGGL(mlp_forward_kernel, dim3(grid), dim3(256), 0, s, blob, inp, n, out);
+    return hipGetLastError();
+}
+
+}  // namespace krt

@@ -19,6 +19,7 @@ enum {
 #define KRT_C_CROSS KRT_C_CROSS_I
 #define KRT_C_STUCK KRT_C_STUCK_I
 #define KRT_C_EMIS_DROP KRT_C_EMIS_DROP_I
+#define KRT_C_MLP KRT_C_MLP_I
 enum { KRT_ST_NAN_BIT = 1, KRT_ST_STUCK_BIT = 2, KRT_ST_SATURATE_BIT = 4 };
 enum { KRT_SRC_POINT_I = 0, KRT_SRC_PLANE_I = 1, KRT_SRC_VOLUME_I = 2, KRT_SRC_BEAM_I = 3 };
 enum { KRT_PROF_DELTA_I = 0, KRT_PROF_VOIGT_I = 1, KRT_PROF_GAUSS_I = 2 };
@@ -63,6 +64,10 @@ struct RunParams {
     uint64_t n_packets, packet_offset, max_events;
     uint32_t key0, key1;
     unsigned long long *work_counter;
+    // learned escape (mlp_img == nullptr: plain random walk only)
+    const unsigned char *mlp_img;
+    float esc_tau_min, esc_tau_max, esc_x_max, esc_log10a;
+    int esc_min_lanes;
 };
 
 hipError_t launch_transport(const RunParams &P, int grid, int block, hipStream_t s);
@@ -75,6 +80,19 @@ hipError_t launch_debug_bins(const float *x, int64_t n, int nb, double lo, doubl
 hipError_t launch_debug_voigt(const float *tab, const float *x, int64_t n, float *out, hipStream_t s);
 hipError_t launch_debug_upar(const float *tab, float a, float thd, float x, uint32_t k0, uint32_t k1,
                              uint64_t packet, uint32_t ev0, int64_t n, float *out, hipStream_t s);
+hipError_t launch_escape_record(const float *tab, float a, float thd, uint32_t k0, uint32_t k1, uint64_t offset,
+                                int64_t n, float lt_lo, float lt_hi, uint32_t max_scat, int x_fixed, float x_value,
+                                float *out, hipStream_t s);
+hipError_t launch_mlp_init(float *p, uint32_t k0, uint32_t k1, hipStream_t s);
+hipError_t launch_mlp_pack(const float *p, const float *norm, unsigned char *blob, unsigned char *img,
+                           hipStream_t s);
+hipError_t launch_mlp_grad(const unsigned char *blob, const float *rec, const int32_t *idx, const float *uq,
+                           int batch, float *grad, float *loss, hipStream_t s);
+hipError_t launch_mlp_adam(float *p, float *m, float *v, float *grad, float lr, int step, hipStream_t s);
+hipError_t launch_mlp_batch(int64_t n, uint32_t k0, uint32_t k1, uint32_t step, int batch, int32_t *idx,
+                            float *uq, hipStream_t s);
+hipError_t launch_mlp_norm(const float *rec, int64_t n, float *norm, hipStream_t s);
+hipError_t launch_mlp_forward(const unsigned char *blob, const float *inp, int64_t n, float *out, hipStream_t s);
 hipError_t launch_levels(int nl, int64_t ncell, const double *consts, const double *ncoll,
                          const double *ntot, const float *jbar, double *pops, float *k0_out,
                          float *eps_out, hipStream_t s);

@@ -1,0 +1,123 @@
+// krt_mlp.h -- the learned escape proposal: layout constants and the BF16-MFMA
+// forward pass shared by the transport kernel (inference) and the training
+// kernels.  Not part of the C ABI.
+//
+// Network: 4 inputs -> 128 -> 128 -> 128 (SiLU) -> 6 outputs.
+// Inputs  : ((log10 tau_R - 3.5)/1.5, log10 a + 3, x_in / 4, 2u - 1), u the
+//           quantile level.
+// Outputs : conditional quantiles at level u (normalised) of the exit
+//           frequency x_out, the exit point (s, t) on the exit face, the cosine
+//           mu of the exit direction to the face normal, ln N_s (scatterings
+//           inside the cube) and ln <x^2> over those scatterings.
+//
+// The layers are evaluated transposed, H^T_{l+1} = SiLU(W_l^T H^T_l + b_l),
+// with v_mfma_f32_16x16x16_bf16 on 16-sample blocks: the accumulator layout of
+// one layer (lane l holds features 4(l/16)+j of sample l%16) is exactly the B
+// operand layout of the next, so activations never leave registers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace krt {
+
+constexpr int kMlpIn = 4, kMlpHid = 128, kMlpOut = 6;
+// FP32 master parameter block (offsets in floats)
+constexpr int kPW1 = 0;                                  // W1[4][128]   (in, out)
+constexpr int kPB1 = kPW1 + kMlpIn * kMlpHid;            // b1[128]
+constexpr int kPW2 = kPB1 + kMlpHid;                     // W2[128][128]
+constexpr int kPB2 = kPW2 + kMlpHid * kMlpHid;
+constexpr int kPW3 = kPB2 + kMlpHid;
+constexpr int kPB3 = kPW3 + kMlpHid * kMlpHid;
+constexpr int kPW4 = kPB3 + kMlpHid;                     // W4[128][6]
+constexpr int kPB4 = kPW4 + kMlpHid * kMlpOut;           // b4[6]
+constexpr int kNParams = kPB4 + kMlpOut;                 // 34438
+// target normalisation: y_norm = (y - mean) / scale, stored after the params
+constexpr int kNNorm = 2 * kMlpOut;
+
+// Packed BF16 A-operand tiles (16x16, 512 B each: 64 lanes x 4 bf16).
+// Forward (W^T, rows = out-features): L1 8 tiles (K padded 4 -> 16), L2 64, L3 64, L4 8 (rows padded 6 -> 16).
+constexpr int kTilesL1 = 8, kTilesL2 = 64, kTilesL3 = 64, kTilesL4 = 8;
+constexpr int kTileFwdL1 = 0, kTileFwdL2 = kTilesL1, kTileFwdL3 = kTileFwdL2 + kTilesL2,
+              kTileFwdL4 = kTileFwdL3 + kTilesL3, kTilesFwd = kTileFwdL4 + kTilesL4;   // 144
+// Backward (W, rows = in-features): L4 8 tiles (K = 16 padded outputs), L3 64, L2 64.
+constexpr int kTileBwdL4 = kTilesFwd, kTileBwdL3 = kTileBwdL4 + 8, kTileBwdL2 = kTileBwdL3 + 64,
+              kTilesAll = kTileBwdL2 + 64;                                              // 280
+constexpr int kTileBytes = 512;
+// biases as FP32 after the tiles: b1 128, b2 128, b3 128, b4 16 (padded)
+constexpr int kBiasFloats = 3 * kMlpHid + 16;
+constexpr int kMlpFwdBytes = kTilesFwd * kTileBytes + kBiasFloats * 4 + kNNorm * 4;  // LDS image for inference
+constexpr int kMlpBlobBytes = kTilesAll * kTileBytes + kBiasFloats * 4 + kNNorm * 4;
+
+typedef short v4i16 __attribute__((ext_vector_type(4)));
+typedef float v4f32 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+
+__device__ __forceinline__ v4i16 pack4(float a, float b, float c, float d) {
+    v4i16 r;
+    r.x = (short)f2bf(a); r.y = (short)f2bf(b); r.z = (short)f2bf(c); r.w = (short)f2bf(d);
+    return r;
+}
+
+__device__ __forceinline__ v4f32 mfma16(v4i16 a, v4i16 b, v4f32 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// A operand of tile t for this lane from a byte blob (LDS or global)
+__device__ __forceinline__ v4i16 tileA(const unsigned char *blob, int t, int lane) {
+    return *reinterpret_cast<const v4i16 *>(blob + t * kTileBytes + lane * 8);
+}
+
+// Forward pass of one 16-sample block.  xin: this lane's B operand for layer 1
+// (lanes 0..15 hold the 4 inputs of sample l%16, other lanes zeros).  Returns
+// the output tile (lane l: outputs 4(l/16)+j of sample l%16).  If z1..z3 are
+// given, the pre-activations are stored (8 tiles each) for the backward pass.
+__device__ __forceinline__ v4f32 mlp_forward_block(const unsigned char *tiles, const float *bias,
+                                                   v4i16 xin, int lane, v4f32 *z1, v4f32 *z2,
+                                                   v4f32 *z3) {
+    const int g = lane >> 4;
+    v4i16 h[8];
+    // layer 1
+#pragma unroll
+    for (int mo = 0; mo < 8; ++mo) {
+        const float *b = bias + 16 * mo + 4 * g;
+        v4f32 acc = {b[0], b[1], b[2], b[3]};
+        acc = mfma16(tileA(tiles, kTileFwdL1 + mo, lane), xin, acc);
+        if (z1) z1[mo] = acc;
+        h[mo] = pack4(silu(acc.x), silu(acc.y), silu(acc.z), silu(acc.w));
+    }
+    // layers 2, 3
+#pragma unroll
+    for (int layer = 0; layer < 2; ++layer) {
+        const int t0 = layer == 0 ? kTileFwdL2 : kTileFwdL3;
+        const float *bl = bias + kMlpHid * (layer + 1);
+        v4f32 acc[8];
+#pragma unroll
+        for (int mo = 0; mo < 8; ++mo) {
+            const float *b = bl + 16 * mo + 4 * g;
+            acc[mo] = (v4f32){b[0], b[1], b[2], b[3]};
+#pragma unroll
+            for (int ki = 0; ki < 8; ++ki) acc[mo] = mfma16(tileA(tiles, t0 + mo * 8 + ki, lane), h[ki], acc[mo]);
+        }
+        v4f32 *zs = layer == 0 ? z2 : z3;
+#pragma unroll
+        for (int mo = 0; mo < 8; ++mo) {
+            if (zs) zs[mo] = acc[mo];
+            h[mo] = pack4(silu(acc[mo].x), silu(acc[mo].y), silu(acc[mo].z), silu(acc[mo].w));
+        }
+    }
+    // layer 4 (outputs padded to 16)
+    const float *b4 = bias + 3 * kMlpHid + 4 * g;
+    v4f32 out = {b4[0], b4[1], b4[2], b4[3]};
+#pragma unroll
+    for (int ki = 0; ki < 8; ++ki) out = mfma16(tileA(tiles, kTileFwdL4 + ki, lane), h[ki], out);
+    return out;
+}
+
+}  // namespace krt

@@ -15,142 +15,10 @@
 
 #include "krt_internal.h"
 #include "krt_kernels.h"
+#include "krt_device.h"
+#include "krt_mlp.h"
 
 namespace krt {
-
-// ------------------------------------------------------------------ Philox ---
-// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two 32x32
-// multiplies with key schedule increments (W0, W1) between rounds.
-__device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
-        uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
-        uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
-        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
-        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
-    }
-    return c;
-}
-
-// uniform on (0,1): an odd multiple of 2^-24, exact in binary32
-__device__ __forceinline__ float u01(uint32_t w) {
-    return (float)(w >> 9) * 0x1p-23f + 0x1p-24f;
-}
-
-// ------------------------------------------------------------- fast math ---
-constexpr float kPiF = 3.14159265358979f;
-constexpr uint32_t kMaxCrossings = 1u << 30;  // per packet: a packet that never interacts is retired as stuck
-constexpr float kInvSqrtPiF = 0.564189583547756f;
-constexpr float kLn2F = 0.693147180559945f;
-__device__ __forceinline__ float f_log(float x) { return __builtin_amdgcn_logf(x) * kLn2F; }
-__device__ __forceinline__ float f_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896f); }
-__device__ __forceinline__ float f_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ float f_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-__device__ __forceinline__ float f_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
-// sin / cos of 2 pi r (the hardware takes revolutions)
-__device__ __forceinline__ float sin_rev(float r) { return __builtin_amdgcn_sinf(r); }
-__device__ __forceinline__ float cos_rev(float r) { return __builtin_amdgcn_cosf(r); }
-
-// ------------------------------------------------------------------- bins ---
-// Index rule shared by every tally: edges are binary32 values of
-// lo + (hi - lo) * k / nb computed in FP64; the bin is 1 + the largest k with
-// edge[k] <= x, 0 below edge[0], nb + 1 at or above edge[nb], -1 for NaN.
-__device__ __forceinline__ float bin_edge(double lo, double hi, int nb, int k) {
-    return (float)(lo + (hi - lo) * (double)k / (double)nb);
-}
-
-__device__ int bin_index(float x, int nb, double lo, double hi, float inv_w) {
-    if (!(x == x)) return -1;
-    if (x < bin_edge(lo, hi, nb, 0)) return 0;
-    if (x >= bin_edge(lo, hi, nb, nb)) return nb + 1;
-    int k = (int)((x - (float)lo) * inv_w);
-    k = max(0, min(nb - 1, k));
-    while (k > 0 && bin_edge(lo, hi, nb, k) > x) --k;
-    while (k < nb - 1 && bin_edge(lo, hi, nb, k + 1) <= x) ++k;
-    return k + 1;
-}
-
-// ----------------------------------------------------------- LDS lookups ---
-__device__ __forceinline__ float voigt_lds(const float *T, float xa) {
-    if (xa < 8.0f) {
-        float t = xa * 64.0f;
-        int i = max(0, min((int)t, kVoigtCoreN - 1));
-        float f = t - (float)i;
-        float4 c = *reinterpret_cast<const float4 *>(T + kOffVoigtCore + 4 * i);
-        return fmaf(f, fmaf(f, fmaf(f, c.w, c.z), c.y), c.x);
-    }
-    float w = 8.0f * f_rcp(xa);
-    float t = w * (float)kVoigtWingN;
-    int j = max(0, min((int)t, kVoigtWingN - 1));
-    float f = t - (float)j;
-    float4 c = *reinterpret_cast<const float4 *>(T + kOffVoigtWing + 4 * j);
-    float G = fmaf(f, fmaf(f, fmaf(f, c.w, c.z), c.y), c.x);
-    return G * w * w * (1.0f / 64.0f);
-}
-
-// Atom parallel velocity for gas-frame frequency x (Sec. 2.1.1): piece by r1
-// against the cumulative piece probabilities, quantile by r2, bilinear in
-// (row of |x|, quantile node).
-__device__ __forceinline__ float upar_lds(const float *T, float x, float a, float thd,
-                                          float r1, float r2) {
-    float xa = fabsf(x);
-    float c1 = 0.0f, c2 = 0.0f, c3 = 1.0f;
-    if (xa < 8.0f) {
-        float pm = xa * (float)(kMassN / 8);
-        int im = max(0, min((int)pm, kMassN - 1));
-        float fm = pm - (float)im;
-        float4 m0 = *reinterpret_cast<const float4 *>(T + kOffMass + 4 * im);
-        float4 m1 = *reinterpret_cast<const float4 *>(T + kOffMass + 4 * im + 4);
-        c1 = fmaf(fm, m1.x - m0.x, m0.x);
-        c2 = fmaf(fm, m1.y - m0.y, m0.y);
-        c3 = fmaf(fm, m1.z - m0.z, m0.z);
-    }
-    float p;
-    if (xa < 8.0f) p = xa * 6.0f;
-    else p = fminf(48.0f + f_log(xa * 0.125f) * kRowInvLog, 63.0f);
-    int j = max(0, min((int)p, kRows - 2));
-    float fr = p - (float)j;
-    int kind = (r1 < c1) ? 0 : ((r1 < c2) ? 1 : ((r1 < c3) ? 2 : 3));
-    int nq = (kind == 0) ? kQS : kQL1;  // kQL1 == kQL2 == kQR
-    int off = (kind == 0) ? kOffSpike : ((kind == 1) ? kOffL1 : ((kind == 2) ? kOffL2 : kOffRight));
-    // wing pieces: nodes at q = 4 xi^3 (xi < 1/2), 1 - 4 (1 - xi)^3 (xi >= 1/2)
-    float xi = r2;
-    if (kind != 0) {
-        float t = (r2 < 0.5f) ? r2 : 1.0f - r2;
-        float cb = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(0.25f * t) * (1.0f / 3.0f));
-        xi = (r2 < 0.5f) ? cb : 1.0f - cb;
-    }
-    float qp = xi * (float)(nq - 1);
-    int k = max(0, min((int)qp, nq - 2));
-    float fq = qp - (float)k;
-    const float *r0 = T + off + j * nq + k;
-    float v0 = fmaf(fq, r0[1] - r0[0], r0[0]);
-    float v1 = fmaf(fq, r0[nq + 1] - r0[nq], r0[nq]);
-    float v = fmaf(fr, v1 - v0, v0);
-    float u;
-    if (kind == 0) {
-        float th = v * thd * (1.0f / (2.0f * kPiF));
-        u = xa + a * sin_rev(th) * f_rcp(cos_rev(th));
-    } else if (kind == 2) {
-        u = v;
-    } else {
-        float s = (float)kDelta * f_exp(v);
-        u = (kind == 1) ? xa - s : xa + s;
-    }
-    return (x < 0.0f) ? -u : u;  // p(u | -x) = p(-u | x)
-}
-
-// Dipole phase (3/8)(1 + g^2): g = 2 sinh(asinh(4u - 2)/3).
-__device__ __forceinline__ float dipole_g(float u) {
-    float q = 4.0f * u - 2.0f;
-    float aq = fabsf(q);
-    float t = f_log(aq + f_sqrt(fmaf(aq, aq, 1.0f))) * (1.0f / 3.0f);
-    float e = f_exp(t);
-    float g = e - f_rcp(e);
-    return copysignf(g, q);
-}
 
 // --------------------------------------------------------- tally helpers ---
 __device__ __forceinline__ void atomic_add_i64(int64_t *p, int64_t v, uint32_t *status) {
@@ -197,15 +65,48 @@ __device__ __forceinline__ void wave_add_counter(int64_t *dst, int64_t v) {
     if (__lane_id() == 0 && v != 0) atomicAdd(reinterpret_cast<unsigned long long *>(dst), (unsigned long long)v);
 }
 
+// ------------------------------------------------------ learned escape ---
+// Batched evaluation of the escape network for the whole wave (wave-uniform
+// control flow: every lane executes the MFMA; lanes that did not ask ignore the
+// result).  in[4] are this lane's normalised inputs; out[k] receives output k of
+// this lane's sample (normalised).
+__device__ __attribute__((noinline)) void mlp_eval_wave(const unsigned char *img, const float *bias, const float in[4],
+                                              int lane, float out[kMlpOut]) {
+#pragma unroll 1
+    for (int b = 0; b < 4; ++b) {
+        const int src = 16 * b + (lane & 15);
+        float i0 = __shfl(in[0], src, 64), i1 = __shfl(in[1], src, 64);
+        float i2 = __shfl(in[2], src, 64), i3 = __shfl(in[3], src, 64);
+        v4i16 xb = (lane < 16) ? pack4(i0, i1, i2, i3) : pack4(0.f, 0.f, 0.f, 0.f);
+        v4f32 o = mlp_forward_block(img, bias, xb, lane, nullptr, nullptr, nullptr);
+        // output k of sample 16b + (lane & 15) sits in lane 16*(k/4) + (lane & 15), component k % 4
+#pragma unroll
+        for (int k = 0; k < kMlpOut; ++k) {
+            float comp = (k % 4 == 0) ? o.x : (k % 4 == 1) ? o.y : (k % 4 == 2) ? o.z : o.w;
+            float v = __shfl(comp, 16 * (k / 4) + (lane & 15), 64);
+            if ((lane >> 4) == b) out[k] = v;
+        }
+    }
+}
+
 // --------------------------------------------------------------- kernel ---
-__global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
+template <bool kEsc>
+__global__ void __launch_bounds__(kEsc ? 512 : 1024) mc_transport_kernel(RunParams P) {
     extern __shared__ float4 lds4[];
     float *T = reinterpret_cast<float *>(lds4);
     {
         const float4 *src = reinterpret_cast<const float4 *>(P.tab);
         for (int i = threadIdx.x; i < kTabFloats / 4; i += blockDim.x) lds4[i] = src[i];
+        if (kEsc) {
+            const float4 *ms = reinterpret_cast<const float4 *>(P.mlp_img);
+            float4 *md = lds4 + kTabFloats / 4;
+            for (int i = threadIdx.x; i < kMlpFwdBytes / 16; i += blockDim.x) md[i] = ms[i];
+        }
     }
     __syncthreads();
+    const unsigned char *mimg = reinterpret_cast<const unsigned char *>(lds4 + kTabFloats / 4);
+    const float *mbias = reinterpret_cast<const float *>(mimg + kTilesFwd * kTileBytes);
+    const float *mnorm = mbias + kBiasFloats;
 
     const int lane = __lane_id();
     const uint64_t lanemask_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -228,6 +129,7 @@ __global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
     for (int s = 0; s < 4; ++s) { E.ch[s] = -1; E.acc[s] = 0; }
     // per-lane counters
     int64_t c_emit = 0, c_esc = 0, c_des = 0, c_scat = 0, c_cross = 0, c_stuck = 0, c_drop = 0;
+    int64_t c_mlp = 0, c_skip = 0;
     uint32_t *status = P.status;
     const float jscale = P.jbar_scale * kInvSqrtPiF;
 
@@ -320,37 +222,176 @@ __global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
             }
         }
         if (__ballot(have) == 0ull) break;
-        if (!have) continue;
 
-        // ---- one flight segment ------------------------------------------
-        float xc = x - (nx * vxc + ny * vyc + nz * vzc);
-        float H = (k0c > 0.0f) ? voigt_lds(T, fabsf(xc)) : 0.0f;
-        float kap = k0c * H;
-        float tx = (nx > 0.0f) ? (1.0f - fx) * P.dx[0] * f_rcp(nx) : ((nx < 0.0f) ? fx * P.dx[0] * f_rcp(-nx) : INFINITY);
-        float ty = (ny > 0.0f) ? (1.0f - fy) * P.dx[1] * f_rcp(ny) : ((ny < 0.0f) ? fy * P.dx[1] * f_rcp(-ny) : INFINITY);
-        float tz = (nz > 0.0f) ? (1.0f - fz) * P.dx[2] * f_rcp(nz) : ((nz < 0.0f) ? fz * P.dx[2] * f_rcp(-nz) : INFINITY);
-        int ax = 0;
-        float dmin = tx;
-        if (ty < dmin) { dmin = ty; ax = 1; }
-        if (tz < dmin) { dmin = tz; ax = 2; }
-        dmin = fmaxf(dmin, 0.0f);
+        // ---- one flight segment (divergent) --------------------------------
+        bool scat = false;
+        float xc = 0.0f;
+        if (have) {
+            xc = x - (nx * vxc + ny * vyc + nz * vzc);
+            float H = (k0c > 0.0f) ? voigt_lds(T, fabsf(xc)) : 0.0f;
+            float kap = k0c * H;
+            float tx = (nx > 0.0f) ? (1.0f - fx) * P.dx[0] * f_rcp(nx) : ((nx < 0.0f) ? fx * P.dx[0] * f_rcp(-nx) : INFINITY);
+            float ty = (ny > 0.0f) ? (1.0f - fy) * P.dx[1] * f_rcp(ny) : ((ny < 0.0f) ? fy * P.dx[1] * f_rcp(-ny) : INFINITY);
+            float tz = (nz > 0.0f) ? (1.0f - fz) * P.dx[2] * f_rcp(nz) : ((nz < 0.0f) ? fz * P.dx[2] * f_rcp(-nz) : INFINITY);
+            int ax = 0;
+            float dmin = tx;
+            if (ty < dmin) { dmin = ty; ax = 1; }
+            if (tz < dmin) { dmin = tz; ax = 2; }
+            dmin = fmaxf(dmin, 0.0f);
 
-        if (kap > 0.0f && kap * dmin >= tau) {
-            // interaction inside the cell
-            float l = tau * f_rcp(kap);
-            fx = fminf(fmaxf(fmaf(l * nx, P.inv_dx[0], fx), 0.0f), 1.0f);
-            fy = fminf(fmaxf(fmaf(l * ny, P.inv_dx[1], fy), 0.0f), 1.0f);
-            fz = fminf(fmaxf(fmaf(l * nz, P.inv_dx[2], fz), 0.0f), 1.0f);
-            if (P.jbar_raw) jacc += (int64_t)__float2ll_rn(l * H * jscale);
-
-            // ---- resonant scattering (event ev) --------------------------
-            const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
-            bool destroyed = (P.eps != nullptr) && (u01(wa1) < epsc);
-            if (destroyed) {
-                c_des += 1;
-                outcome = 2;
-                have = false;
+            if (kap > 0.0f && kap * dmin >= tau) {
+                // interaction inside the cell
+                float l = tau * f_rcp(kap);
+                fx = fminf(fmaxf(fmaf(l * nx, P.inv_dx[0], fx), 0.0f), 1.0f);
+                fy = fminf(fmaxf(fmaf(l * ny, P.inv_dx[1], fy), 0.0f), 1.0f);
+                fz = fminf(fmaxf(fmaf(l * nz, P.inv_dx[2], fz), 0.0f), 1.0f);
+                if (P.jbar_raw) jacc += (int64_t)__float2ll_rn(l * H * jscale);
+                if ((P.eps != nullptr) && (u01(wa1) < epsc)) {
+                    c_des += 1;
+                    outcome = 2;
+                    have = false;
+                } else {
+                    scat = true;
+                }
             } else {
+                // cross the face of axis ax
+                tau -= kap * dmin;
+                if (P.jbar_raw) jacc += (int64_t)__float2ll_rn(dmin * H * jscale);
+                float adv = dmin;
+                if (ax != 0) fx = fminf(fmaxf(fmaf(adv * nx, P.inv_dx[0], fx), 0.0f), 1.0f);
+                if (ax != 1) fy = fminf(fmaxf(fmaf(adv * ny, P.inv_dx[1], fy), 0.0f), 1.0f);
+                if (ax != 2) fz = fminf(fmaxf(fmaf(adv * nz, P.inv_dx[2], fz), 0.0f), 1.0f);
+                c_cross += 1;
+                ncross_pkt += 1;
+                // leaving the cell: flush its register tallies
+                if (P.jbar_raw && jacc != 0) { atomic_add_i64(P.jbar_raw + cell, jacc, status); jacc = 0; }
+                if (P.emis_raw) emis_flush(E, P.emis_raw + (int64_t)cell * P.emis_nch, P.emis_nch, status);
+                bool escaped = false;
+                if (ax == 0) {
+                    int st = (nx > 0.0f) ? 1 : -1;
+                    ci += st; fx = (st > 0) ? 0.0f : 1.0f;
+                    if (ci < 0 || ci >= P.n[0]) { if (P.bc[0]) ci = (ci < 0) ? P.n[0] - 1 : 0; else escaped = true; }
+                } else if (ax == 1) {
+                    int st = (ny > 0.0f) ? 1 : -1;
+                    cj += st; fy = (st > 0) ? 0.0f : 1.0f;
+                    if (cj < 0 || cj >= P.n[1]) { if (P.bc[1]) cj = (cj < 0) ? P.n[1] - 1 : 0; else escaped = true; }
+                } else {
+                    int st = (nz > 0.0f) ? 1 : -1;
+                    ck += st; fz = (st > 0) ? 0.0f : 1.0f;
+                    if (ck < 0 || ck >= P.n[2]) { if (P.bc[2]) ck = (ck < 0) ? P.n[2] - 1 : 0; else escaped = true; }
+                }
+                if (escaped) {
+                    c_esc += 1;
+                    int b = bin_index(x, P.spec_nb, P.spec_lo, P.spec_hi, P.spec_inv_w);
+                    if (b < 0) atomicOr(status, (uint32_t)KRT_ST_NAN_BIT);
+                    else atomicAdd(reinterpret_cast<unsigned long long *>(P.spec_raw + b), 1ull);
+                    outcome = 1;
+                    have = false;
+                } else if (ncross_pkt > kMaxCrossings) {
+                    c_stuck += 1;
+                    atomicOr(status, (uint32_t)KRT_ST_STUCK_BIT);
+                    outcome = 3;
+                    have = false;
+                } else {
+                    cell = (ck * P.n[1] + cj) * P.n[0] + ci;
+                    k0c = P.k0[cell];
+                    if (P.vx) { vxc = P.vx[cell]; vyc = P.vy[cell]; vzc = P.vz[cell]; }
+                    epsc = P.eps ? P.eps[cell] : 0.0f;
+                }
+            }
+        }
+
+        // ---- learned escape: one batched network call per wave (uniform) ----
+        bool mlp = false;
+        float mo[kMlpOut], mo2[kMlpOut];
+        float Rcube = 0.0f;
+        if (kEsc) {
+            float lt = 0.0f;
+            if (scat) {
+                float rx = fminf(fx, 1.0f - fx) * P.dx[0];
+                float ry = fminf(fy, 1.0f - fy) * P.dx[1];
+                float rz = fminf(fz, 1.0f - fz) * P.dx[2];
+                Rcube = fminf(rx, fminf(ry, rz));
+                float tr = k0c * Rcube;
+                if (tr >= P.esc_tau_min && fabsf(xc) <= P.esc_x_max) {
+                    tr = fminf(tr, P.esc_tau_max);
+                    Rcube = tr * f_rcp(k0c);
+                    lt = __log10f(tr);
+                    mlp = true;
+                }
+            }
+            uint64_t wm = __ballot(mlp);
+            if (__popcll(wm) >= P.esc_min_lanes) {
+                uint4 C = philox(make_uint4(ev, (uint32_t)pid, (uint32_t)(pid >> 32), 2u), P.key0, P.key1);
+                float in[4];
+                in[0] = (lt - 3.5f) * (1.0f / 1.5f);
+                in[1] = P.esc_log10a + 3.0f;
+                in[2] = xc * 0.25f;
+                in[3] = 2.0f * u01(C.x) - 1.0f;
+                mlp_eval_wave(mimg, mbias, in, lane, mo);
+                in[3] = 2.0f * u01(C.y) - 1.0f;
+                mlp_eval_wave(mimg, mbias, in, lane, mo2);
+                if (mlp) {
+                    // ---- exit from the cube centred here (half-width Rcube) ----
+                    const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
+                    float xo = mo[0] * mnorm[kMlpOut + 0] + mnorm[0];
+                    float tt = fminf(fmaxf(mo[2] * mnorm[kMlpOut + 2] + mnorm[2], -1.0f), 1.0f);
+                    float lns = mo[4] * mnorm[kMlpOut + 4] + mnorm[4];
+                    float lx2 = mo[5] * mnorm[kMlpOut + 5] + mnorm[5];
+                    float ss = fminf(fmaxf(mo2[1] * mnorm[kMlpOut + 1] + mnorm[1], -1.0f), 1.0f);
+                    float mu = fminf(fmaxf(mo2[3] * mnorm[kMlpOut + 3] + mnorm[3], 1e-3f), 1.0f);
+                    // symmetry of the cube: face, swap of (s, t), signs
+                    uint32_t bits = C.z;
+                    int face = (int)__umulhi(bits, 6u);
+                    int axis = face >> 1;
+                    float sgn = (face & 1) ? -1.0f : 1.0f;
+                    if (bits & 0x100u) { float tmp = ss; ss = tt; tt = tmp; }
+                    if (bits & 0x200u) ss = -ss;
+                    if (bits & 0x400u) tt = -tt;
+                    float phi_d = u01(C.w);
+                    float sm = f_sqrt(fmaxf(0.0f, 1.0f - mu * mu));
+                    float dn = mu * sgn, d1 = sm * cos_rev(phi_d), d2 = sm * sin_rev(phi_d);
+                    float dp[3], ddir[3];
+                    int a1 = (axis + 1) % 3, a2 = (axis + 2) % 3;
+                    dp[axis] = sgn * Rcube; dp[a1] = ss * Rcube; dp[a2] = tt * Rcube;
+                    ddir[axis] = dn; ddir[a1] = d1; ddir[a2] = d2;
+                    fx = fminf(fmaxf(fmaf(dp[0], P.inv_dx[0], fx), 0.0f), 1.0f);
+                    fy = fminf(fmaxf(fmaf(dp[1], P.inv_dx[1], fy), 0.0f), 1.0f);
+                    fz = fminf(fmaxf(fmaf(dp[2], P.inv_dx[2], fz), 0.0f), 1.0f);
+                    nx = ddir[0]; ny = ddir[1]; nz = ddir[2];
+                    float Ns = fmaxf(f_exp(lns), 1.0f);
+                    // emissivity of the skipped scatterings: thermalised core, camera
+                    // frequency ~ N(n_cam.v, (<x^2> + 1)/3), four samples
+                    if (P.emis_raw) {
+                        uint4 D = philox(make_uint4(ev, plo, phi, 3u), P.key0, P.key1);
+                        float sd = f_sqrt((f_exp(lx2) + 1.0f) * (1.0f / 3.0f));
+                        float vc = P.n_cam[0] * vxc + P.n_cam[1] * vyc + P.n_cam[2] * vzc;
+                        float r1 = f_sqrt(-2.0f * f_log(u01(D.x))), r2 = f_sqrt(-2.0f * f_log(u01(D.z)));
+                        float g4[4] = {r1 * cos_rev(u01(D.y)), r1 * sin_rev(u01(D.y)), r2 * cos_rev(u01(D.w)),
+                                       r2 * sin_rev(u01(D.w))};
+                        int64_t wq = (int64_t)__float2ll_rn(0.25f * Ns * P.frac_scale);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            int kb = bin_index(vc + sd * g4[q], P.emis_nch, P.ch_lo, P.ch_hi, P.ch_inv_w);
+                            if (kb >= 1 && kb <= P.emis_nch)
+                                emis_add(E, kb - 1, wq, P.emis_raw + (int64_t)cell * P.emis_nch, status);
+                            else
+                                c_drop += 1;
+                        }
+                    }
+                    x = xo + nx * vxc + ny * vyc + nz * vzc;
+                    c_mlp += 1;
+                    c_skip += (int64_t)Ns;
+                }
+            } else {
+                mlp = false;
+            }
+        }
+
+        // ---- resonant scattering (event ev), divergent -----------------------
+        if (scat) {
+            const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
+            if (!mlp) {
                 uint4 B = philox(make_uint4(ev, plo, phi, 1u), P.key0, P.key1);
                 float upar = upar_lds(T, xc, a, thd, u01(wa2), u01(wa3));
                 float rr = f_sqrt(-f_log(u01(B.x)));
@@ -392,66 +433,21 @@ __global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
                 x = xo + nx * vxc + ny * vyc + nz * vzc;
                 nscat_pkt += 1;
                 c_scat += 1;
-                // next event
-                ev += 1;
-                if ((uint64_t)ev > P.max_events) {
-                    c_stuck += 1;
-                    atomicOr(status, (uint32_t)KRT_ST_STUCK_BIT);
-                    outcome = 3;
-                    have = false;
-                } else {
-                    uint4 A = philox(make_uint4(ev, plo, phi, 0u), P.key0, P.key1);
-                    tau = -f_log(u01(A.x));
-                    wa1 = A.y; wa2 = A.z; wa3 = A.w;
-                }
             }
-        } else {
-            // cross the face of axis ax
-            tau -= kap * dmin;
-            if (P.jbar_raw) jacc += (int64_t)__float2ll_rn(dmin * H * jscale);
-            float adv = dmin;
-            if (ax != 0) fx = fminf(fmaxf(fmaf(adv * nx, P.inv_dx[0], fx), 0.0f), 1.0f);
-            if (ax != 1) fy = fminf(fmaxf(fmaf(adv * ny, P.inv_dx[1], fy), 0.0f), 1.0f);
-            if (ax != 2) fz = fminf(fmaxf(fmaf(adv * nz, P.inv_dx[2], fz), 0.0f), 1.0f);
-            c_cross += 1;
-            ncross_pkt += 1;
-            // leaving the cell: flush its register tallies
-            if (P.jbar_raw && jacc != 0) { atomic_add_i64(P.jbar_raw + cell, jacc, status); jacc = 0; }
-            if (P.emis_raw) emis_flush(E, P.emis_raw + (int64_t)cell * P.emis_nch, P.emis_nch, status);
-            bool escaped = false;
-            if (ax == 0) {
-                int st = (nx > 0.0f) ? 1 : -1;
-                ci += st; fx = (st > 0) ? 0.0f : 1.0f;
-                if (ci < 0 || ci >= P.n[0]) { if (P.bc[0]) ci = (ci < 0) ? P.n[0] - 1 : 0; else escaped = true; }
-            } else if (ax == 1) {
-                int st = (ny > 0.0f) ? 1 : -1;
-                cj += st; fy = (st > 0) ? 0.0f : 1.0f;
-                if (cj < 0 || cj >= P.n[1]) { if (P.bc[1]) cj = (cj < 0) ? P.n[1] - 1 : 0; else escaped = true; }
-            } else {
-                int st = (nz > 0.0f) ? 1 : -1;
-                ck += st; fz = (st > 0) ? 0.0f : 1.0f;
-                if (ck < 0 || ck >= P.n[2]) { if (P.bc[2]) ck = (ck < 0) ? P.n[2] - 1 : 0; else escaped = true; }
-            }
-            if (escaped) {
-                c_esc += 1;
-                int b = bin_index(x, P.spec_nb, P.spec_lo, P.spec_hi, P.spec_inv_w);
-                if (b < 0) atomicOr(status, (uint32_t)KRT_ST_NAN_BIT);
-                else atomicAdd(reinterpret_cast<unsigned long long *>(P.spec_raw + b), 1ull);
-                outcome = 1;
-                have = false;
-            } else if (ncross_pkt > kMaxCrossings) {
+            // next event
+            ev += 1;
+            if ((uint64_t)ev > P.max_events) {
                 c_stuck += 1;
                 atomicOr(status, (uint32_t)KRT_ST_STUCK_BIT);
                 outcome = 3;
                 have = false;
             } else {
-                cell = (ck * P.n[1] + cj) * P.n[0] + ci;
-                k0c = P.k0[cell];
-                if (P.vx) { vxc = P.vx[cell]; vyc = P.vy[cell]; vzc = P.vz[cell]; }
-                epsc = P.eps ? P.eps[cell] : 0.0f;
+                uint4 A = philox(make_uint4(ev, plo, phi, 0u), P.key0, P.key1);
+                tau = -f_log(u01(A.x));
+                wa1 = A.y; wa2 = A.z; wa3 = A.w;
             }
         }
-        if (!have) {
+        if (!have && outcome != 0) {
             // packet retired: flush the tallies of its last cell, log it
             if (P.jbar_raw && jacc != 0) { atomic_add_i64(P.jbar_raw + cell, jacc, status); jacc = 0; }
             if (P.emis_raw) emis_flush(E, P.emis_raw + (int64_t)cell * P.emis_nch, P.emis_nch, status);
@@ -472,6 +468,10 @@ __global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
     wave_add_counter(P.counters + KRT_C_CROSS, c_cross);
     wave_add_counter(P.counters + KRT_C_STUCK, c_stuck);
     wave_add_counter(P.counters + KRT_C_EMIS_DROP, c_drop);
+    if (kEsc) {
+        wave_add_counter(P.counters + KRT_C_MLP_I, c_mlp);
+        wave_add_counter(P.counters + KRT_C_SKIPPED_I, c_skip);
+    }
 }
 
 // -------------------------------------------------------------- finalise ---
@@ -529,15 +529,18 @@ __global__ void debug_upar_kernel(const float *tab, float a, float thd, float x,
 
 // ---------------------------------------------------------------- launch ---
 hipError_t launch_transport(const RunParams &P, int grid, int block, hipStream_t s) {
-    size_t lds = sizeof(float) * kTabFloats;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(mc_transport_kernel),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const bool esc = P.mlp_img != nullptr;
+    size_t lds = sizeof(float) * kTabFloats + (esc ? (size_t)kMlpFwdBytes : 0);
+    static bool attr_set[2] = {false, false};
+    const void *fn = esc ? reinterpret_cast<const void *>(mc_transport_kernel<true>)
+                         : reinterpret_cast<const void *>(mc_transport_kernel<false>);
+    if (!attr_set[esc]) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
-        attr_set = true;
+        attr_set[esc] = true;
     }
-    hipLaunchKernelGGL(mc_transport_kernel, dim3(grid), dim3(block), lds, s, P);
+    if (esc) hipLaunchKernelGGL(mc_transport_kernel<true>, dim3(grid), dim3(block), lds, s, P);
+    else hipLaunchKernelGGL(mc_transport_kernel<false>, dim3(grid), dim3(block), lds, s, P);
     return hipGetLastError();
 }
 

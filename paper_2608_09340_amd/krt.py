@@ -40,7 +40,8 @@ class krt_run_opts(C.Structure):
                 ("packet_offset", C.c_uint64), ("max_events", C.c_uint64),
                 ("escape_mode", C.c_int32), ("wg_size", C.c_int32), ("wg_per_cu", C.c_int32),
                 ("emis_frac_bits", C.c_int32), ("jbar_frac_bits", C.c_int32),
-                ("norm_packets", C.c_uint64), ("luminosity", C.c_double)]
+                ("norm_packets", C.c_uint64), ("luminosity", C.c_double),
+                ("esc_tau_min", C.c_double), ("esc_min_lanes", C.c_int32)]
 
 
 class krt_tallies(C.Structure):
@@ -60,7 +61,10 @@ class krt_levels_desc(C.Structure):
 EXPORTS = ["krt_create", "krt_destroy", "krt_last_error", "krt_device_cus", "krt_last_transport_ms",
            "krt_grid_upload",
            "krt_tables_build", "krt_mc_run", "krt_levels_update", "krt_debug_philox",
-           "krt_debug_bins", "krt_debug_voigt", "krt_debug_upar"]
+           "krt_debug_bins", "krt_debug_voigt", "krt_debug_upar",
+           "krt_escape_init", "krt_escape_record", "krt_escape_fit_norm", "krt_escape_grad",
+           "krt_escape_train", "krt_escape_get_weights", "krt_escape_put_weights", "krt_escape_forward"]
+ESC_NPARAMS, ESC_NNORM = 34438, 12
 
 _lib = None
 
@@ -92,8 +96,19 @@ def load(path: str = LIB_PATH):
     L.krt_debug_bins.argtypes = [p, p, i64, i32, C.c_double, C.c_double, p]
     L.krt_debug_voigt.argtypes = [p, i32, p, i64, p]
     L.krt_debug_upar.argtypes = [p, i32, C.c_float, u64, u64, u32, i64, p]
+    L.krt_escape_init.argtypes = [p, u64]
+    L.krt_escape_record.argtypes = [p, i32, u64, u64, u64, C.c_double, C.c_double, i32, C.c_double, p]
+    L.krt_escape_fit_norm.argtypes = [p, p, u64]
+    L.krt_escape_grad.argtypes = [p, p, p, p, i32, p, p]
+    L.krt_escape_train.argtypes = [p, p, u64, i32, i32, C.c_double, u64, p]
+    L.krt_escape_get_weights.argtypes = [p, p, u64]
+    L.krt_escape_put_weights.argtypes = [p, p, u64]
+    L.krt_escape_forward.argtypes = [p, p, i64, p]
     for name in ["krt_grid_upload", "krt_tables_build", "krt_mc_run", "krt_levels_update",
-                 "krt_debug_philox", "krt_debug_bins", "krt_debug_voigt", "krt_debug_upar"]:
+                 "krt_debug_philox", "krt_debug_bins", "krt_debug_voigt", "krt_debug_upar",
+                 "krt_escape_init", "krt_escape_record", "krt_escape_fit_norm", "krt_escape_grad",
+                 "krt_escape_train", "krt_escape_get_weights", "krt_escape_put_weights",
+                 "krt_escape_forward"]:
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -180,6 +195,35 @@ class Context:
     def krt_levels_update(self, desc: krt_levels_desc, jbar=None):
         self._check(self.L.krt_levels_update(self.h, C.byref(desc), _ptr(jbar)))
 
+    # learned escape
+    def krt_escape_init(self, seed):
+        self._check(self.L.krt_escape_init(self.h, int(seed)))
+
+    def krt_escape_record(self, line, n, seed, offset, lt_lo, lt_hi, out, x_fixed=None):
+        self._check(self.L.krt_escape_record(self.h, int(line), int(n), int(seed), int(offset), float(lt_lo),
+                                             float(lt_hi), 0 if x_fixed is None else 1,
+                                             0.0 if x_fixed is None else float(x_fixed), _ptr(out)))
+
+    def krt_escape_fit_norm(self, rec, n):
+        self._check(self.L.krt_escape_fit_norm(self.h, _ptr(rec), int(n)))
+
+    def krt_escape_grad(self, rec, idx, u, grad_out, loss_out=None):
+        self._check(self.L.krt_escape_grad(self.h, _ptr(rec), _ptr(idx), _ptr(u), int(idx.numel()),
+                                           _ptr(grad_out), _ptr(loss_out)))
+
+    def krt_escape_train(self, rec, n, steps, batch, lr, seed, loss_hist=None):
+        self._check(self.L.krt_escape_train(self.h, _ptr(rec), int(n), int(steps), int(batch), float(lr),
+                                            int(seed), _ptr(loss_hist)))
+
+    def krt_escape_get_weights(self, out):
+        self._check(self.L.krt_escape_get_weights(self.h, _ptr(out), out.numel()))
+
+    def krt_escape_put_weights(self, w):
+        self._check(self.L.krt_escape_put_weights(self.h, _ptr(w), w.numel()))
+
+    def krt_escape_forward(self, inp, out):
+        self._check(self.L.krt_escape_forward(self.h, _ptr(inp), inp.shape[0], _ptr(out)))
+
     def krt_debug_philox(self, ctr, key, out):
         self._check(self.L.krt_debug_philox(self.h, _ptr(ctr), _ptr(key), _ptr(out), ctr.shape[0]))
 
@@ -196,7 +240,7 @@ class Context:
 
 def make_opts(prob: dict, *, line=0, packet_offset=0, accumulate=False, max_events=0,
               wg_size=0, wg_per_cu=0, emis_frac_bits=0, jbar_frac_bits=0, norm_packets=0, escape_mode=0,
-              luminosity=0.0) -> krt_run_opts:
+              luminosity=0.0, esc_tau_min=0.0, esc_min_lanes=0) -> krt_run_opts:
     """krt_run_opts from a workload problem dict (paper_2608_09340_amd.workloads)."""
     o = krt_run_opts()
     src, t = prob["source"], prob["tally"]
@@ -225,6 +269,8 @@ def make_opts(prob: dict, *, line=0, packet_offset=0, accumulate=False, max_even
     o.jbar_frac_bits = int(jbar_frac_bits)
     o.norm_packets = int(norm_packets)
     o.luminosity = float(luminosity)
+    o.esc_tau_min = float(esc_tau_min)
+    o.esc_min_lanes = int(esc_min_lanes)
     return o
 
 

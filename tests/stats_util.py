@@ -5,12 +5,14 @@ import numpy as np
 
 
 def chi2_two_sample(n1, n2, min_count=20):
-    """Two-sample chi^2 of histograms with totals N1, N2 over bins whose pooled
-    count is >= min_count.  Returns (chi2, dof, max|z|)."""
+    """Two-sample chi^2 of histograms with totals N1, N2 over bins where both
+    samples expect >= min_count counts under the pooled proportion (so the
+    normal approximation behind chi^2 and z holds in each).  Returns (chi2, dof,
+    max|z|)."""
     n1 = np.asarray(n1, dtype=np.float64)
     n2 = np.asarray(n2, dtype=np.float64)
     N1, N2 = n1.sum(), n2.sum()
-    m = (n1 + n2) >= min_count
+    m = (n1 + n2) / (N1 + N2) * min(N1, N2) >= min_count
     a, b = n1[m], n2[m]
     k1, k2 = np.sqrt(N2 / N1), np.sqrt(N1 / N2)
     chi2 = float(np.sum((k1 * a - k2 * b) ** 2 / (a + b)))

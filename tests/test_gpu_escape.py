@@ -1,0 +1,196 @@
+"""Learned escape on the GPU: the BF16-MFMA forward and gradient against the
+FP64 reference network, single-cell escape records against the oracle's plain
+walk, training, and the end-to-end judgement of the learned escape by the
+plain random walk on a turbulent cloud."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle
+from oracle import mlp
+from paper_2608_09340_amd import workloads as W
+from stats_util import l1_shape
+
+pytestmark = pytest.mark.gpu
+NP, NN = 34438, 12
+
+
+def _put(ctx, p, norm):
+    import torch
+    w = torch.from_numpy(np.concatenate([p, norm]).astype(np.float32)).cuda()
+    ctx.krt_escape_put_weights(w)
+
+
+def _rand_params(seed):
+    rng = np.random.default_rng(seed)
+    d = {}
+    for name, shp in mlp.SHAPES:
+        fan = shp[0] if len(shp) == 2 else 1
+        d[name] = rng.uniform(-1, 1, shp) * (np.sqrt(6.0 / fan) if len(shp) == 2 else 0.1)
+    return mlp.pack(d)
+
+
+def test_mfma_forward_vs_fp64(gpu_ctx):
+    import torch
+    p = _rand_params(3)
+    norm = np.array([0.5, 0, 0, 0.7, 6, 0.1, 2.0, 0.5, 0.5, 0.2, 1.5, 1.0])
+    _put(gpu_ctx, p, norm)
+    rng = np.random.default_rng(4)
+    n = 3000
+    raw = np.stack([rng.uniform(2, 5, n), rng.uniform(-4, -2, n), rng.uniform(-8, 8, n), rng.uniform(0, 1, n)], 1)
+    out = torch.zeros((n, 6), dtype=torch.float32, device="cuda")
+    gpu_ctx.krt_escape_forward(torch.from_numpy(raw.astype(np.float32)).cuda(), out)
+    g = out.cpu().numpy().astype(np.float64)
+    X = mlp.inputs(raw[:, 0], raw[:, 1], raw[:, 2], raw[:, 3])
+    for bf, tol in ((True, 2e-2), (False, 6e-2)):
+        o, _, _ = mlp.forward(p, X, bf=bf)
+        ref = o * norm[6:] + norm[:6]
+        err = np.abs(g - ref) / (np.abs(ref).std(axis=0) + 1e-9)
+        assert np.max(err) < tol, (bf, np.max(err, axis=0))
+
+
+def test_mfma_gradient_vs_fp64(gpu_ctx):
+    """d(mean pinball loss)/d(params) from the BF16-MFMA backward vs the FP64
+    reference: cosine >= 0.999 and relative L2 <= 2e-2 per tensor."""
+    import torch
+    p = _rand_params(5)
+    norm = np.array([0.1, 0, 0, 0.7, 6, 0.1, 2.0, 0.5, 0.5, 0.2, 1.5, 1.0])
+    _put(gpu_ctx, p, norm)
+    rng = np.random.default_rng(6)
+    nrec, B = 5000, 1024
+    rec = np.zeros((nrec, 10))
+    rec[:, 0] = rng.uniform(2, 5, nrec)
+    rec[:, 1] = rng.uniform(-4, -2, nrec)
+    rec[:, 2] = rng.uniform(-8, 8, nrec)
+    rec[:, 3:9] = norm[:6] + norm[6:] * rng.normal(0, 1, (nrec, 6))
+    rec[:, 9] = 1.0
+    idx = rng.integers(0, nrec, B).astype(np.int32)
+    u = rng.uniform(0, 1, B)
+    grad = torch.zeros(NP, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    gpu_ctx.krt_escape_grad(torch.from_numpy(rec.astype(np.float32)).cuda(),
+                            torch.from_numpy(idx).cuda(), torch.from_numpy(u.astype(np.float32)).cuda(), grad, loss)
+    g = grad.cpu().numpy().astype(np.float64)
+    R = rec[idx]
+    X = mlp.inputs(R[:, 0], R[:, 1], R[:, 2], u)
+    Y = mlp.targets_normalised(R, norm)
+    for bf in (True, False):
+        l_ref, g_ref = mlp.loss_and_grad(p, X, Y, u, bf=bf)
+        o = 0
+        for name, shp in mlp.SHAPES:
+            k = int(np.prod(shp))
+            a, b = g[o:o + k], g_ref[o:o + k]
+            o += k
+            cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-30)
+            rel = np.linalg.norm(a - b) / (np.linalg.norm(b) + 1e-30)
+            assert cos >= (0.999 if bf else 0.995) and rel <= (2e-2 if bf else 6e-2), (bf, name, cos, rel)
+        assert abs(loss.item() / l_ref - 1) < 1e-2
+
+
+@pytest.mark.parametrize("tau,xin", [(1e3, 0.5), (1e4, 2.5)])
+def test_escape_records_vs_oracle(gpu_ctx, tau, xin):
+    """Single-cell escapes from the GPU walk vs the oracle's FP64 walk at the same
+    condition: exit frequency, exit-point and exit-direction distributions (KS)
+    and the mean log number of scatterings."""
+    import torch
+    from paper_2608_09340_amd import krt
+    a = 1e-3
+    T = krt.Transport(W.slab(10.0, a, 4), ctx=gpu_ctx)
+    n = 40000
+    out = torch.zeros((n, 10), dtype=torch.float32, device="cuda")
+    lt = np.log10(tau)
+    gpu_ctx.krt_escape_record(0, n, 7, 0, lt, lt, out, x_fixed=xin)
+    g = out.cpu().numpy().astype(np.float64)
+    no = 4000 if tau < 5e3 else 800
+    o = oracle.escape_record(no, tau, a, xin, seed=8, offset=1 << 30)
+    assert g[:, 9].min() == 1 and o[:, 9].min() == 1
+    for col in (3, 4, 6):
+        ks = stats.ks_2samp(g[:, col], o[:, col])
+        assert ks.pvalue > 1e-3, (tau, xin, col, ks)
+    mg, mo = g[:, 7].mean(), o[:, 7].mean()
+    se = np.sqrt(g[:, 7].var() / n + o[:, 7].var() / no)
+    assert abs(mg - mo) < 4.5 * se, (mg, mo, se)
+
+
+@pytest.fixture(scope="module")
+def trained(gpu_ctx):
+    """Train the escape network on GPU-recorded single-cell escapes (a = 1e-3)."""
+    import torch
+    from paper_2608_09340_amd import krt
+    T = krt.Transport(W.slab(10.0, 1e-3, 4), ctx=gpu_ctx)
+    n = 1_000_000
+    rec = torch.zeros((n, 10), dtype=torch.float32, device="cuda")
+    gpu_ctx.krt_escape_record(0, n, 1, 0, 2.0, 5.0, rec)
+    gpu_ctx.krt_escape_init(1)
+    gpu_ctx.krt_escape_fit_norm(rec, n)
+    steps = 3000
+    hist = torch.zeros(steps, dtype=torch.float32, device="cuda")
+    gpu_ctx.krt_escape_train(rec, n, steps, 4096, 2e-3, 11, hist)
+    gpu_ctx.krt_escape_train(rec, n, 1000, 8192, 5e-4, 12, None)
+    return {"rec": rec, "hist": hist.cpu().numpy(), "T": T}
+
+
+def test_training_reduces_loss(trained):
+    h = trained["hist"]
+    assert np.all(np.isfinite(h))
+    assert h[-200:].mean() < 0.7 * h[:50].mean(), (h[:50].mean(), h[-200:].mean())
+
+
+@pytest.mark.parametrize("tau,xin", [(3e2, 0.0), (3e3, 1.0), (3e4, 2.0)])
+def test_learned_samples_vs_plain(gpu_ctx, trained, tau, xin):
+    """At a fixed condition, the network's samples (quantile at u ~ U(0,1)) vs
+    held-out plain single-cell escapes: KS distance of the exit frequency and
+    of the exit cosine below 0.06, mean ln N_s within 0.1."""
+    import torch
+    n = 20000
+    out = torch.zeros((n, 10), dtype=torch.float32, device="cuda")
+    lt = np.log10(tau)
+    gpu_ctx.krt_escape_record(0, n, 99, 1 << 32, lt, lt, out, x_fixed=xin)
+    plain = out.cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(13)
+    raw = np.stack([np.full(n, lt), np.full(n, -3.0), np.full(n, xin), rng.uniform(0, 1, n)], 1).astype(np.float32)
+    pred = torch.zeros((n, 6), dtype=torch.float32, device="cuda")
+    gpu_ctx.krt_escape_forward(torch.from_numpy(raw).cuda(), pred)
+    m = pred.cpu().numpy().astype(np.float64)
+    for k, col in ((0, 3), (3, 6)):
+        ks = stats.ks_2samp(m[:, k], plain[:, col])
+        assert ks.statistic < 0.06, (tau, xin, k, ks.statistic)
+    assert abs(m[:, 4].mean() - plain[:, 7].mean()) < 0.1
+
+
+def _agg_emis(em, n, blocks=8):
+    """Emissivity [ncell, nch] aggregated into (blocks^3 spatial blocks) x channels."""
+    nch = em.shape[1]
+    e = em.reshape(n, n, n, nch)
+    f = n // blocks
+    return e.reshape(blocks, f, blocks, f, blocks, f, nch).sum(axis=(1, 3, 5)).reshape(-1)
+
+
+def test_cloud_learned_escape_vs_plain(gpu_ctx, trained):
+    """Turbulent cloud (64^3, 30% of cells with line-centre depth >= 1e2): the
+    plain random walk judges the learned escape.  Spectrum and aggregated
+    emissivity L1 <= 2% beyond the plain-vs-plain noise floor, and the learned
+    run needs fewer transport iterations (scatterings + network calls)."""
+    from paper_2608_09340_amd import krt
+    p = W.cloud_c4(n=64, spec=(256, -40.0, 40.0), emis=(16, -16.0, 16.0))
+    T = krt.Transport(p, ctx=gpu_ctx)
+    N = 100_000
+    pa = T.run(N, seed=0)
+    pb = T.run(N, seed=0, packet_offset=1 << 32)
+    ml = T.run(N, seed=0, escape_mode=1)
+    assert pa["rc"] == 0 and ml["rc"] == 0, (pa["counters"], ml["counters"])
+    c = ml["counters"]
+    assert c["mlp_calls"] > 0 and c["emitted"] == N == c["escaped"]
+    floor_s = l1_shape(pa["spec_raw"], pb["spec_raw"])
+    l1_s = l1_shape(pa["spec_raw"], ml["spec_raw"])
+    ea, eb, em = (_agg_emis(r["emis_raw"].astype(np.float64), 64) for r in (pa, pb, ml))
+    floor_e = l1_shape(ea, eb)
+    l1_e = l1_shape(ea, em)
+    print(f"spectrum L1 {l1_s:.4f} (floor {floor_s:.4f}); emissivity L1 {l1_e:.4f} (floor {floor_e:.4f}); "
+          f"plain scat {pa['counters']['scatterings']} mlp scat {c['scatterings']} calls {c['mlp_calls']} "
+          f"skipped {c['skipped_scatterings']}")
+    assert l1_s <= 0.02 + floor_s
+    assert l1_e <= 0.02 + floor_e
+    assert c["scatterings"] + c["mlp_calls"] < pa["counters"]["scatterings"]

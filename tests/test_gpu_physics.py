@@ -91,27 +91,29 @@ def test_thin_moving_slab_closed_form(gpu_ctx):
     """Sec. 3.3 / eq. thin-slab: optically thin slab moving at v_z = b, beam in
     the slab plane, camera along the normal (g = 0).  The volume-integrated
     emissivity per channel is the channel integral of the R_IIA kernel at
-    g = 0 (Doppler limit pi^-1/2 exp(-x_out^2)) shifted by the bulk motion;
-    shape within 0.4% and integral within 2% of the paper's tolerances."""
+    g = 0 (Doppler limit pi^-1/2 exp(-x_out^2)) shifted by the bulk motion.
+    Shape within 0.4% in L1 and integral within 2% (the paper's tolerances),
+    every channel within 4.5 sigma of Poisson noise."""
     from paper_2608_09340_amd import krt
     a = 0.01
     p = W.thin_moving_slab(tau=0.01, a=a, vz=1.0)
     T = krt.Transport(p, ctx=gpu_ctx)
-    N = 20_000_000
+    N = 200_000_000
     r = T.run(N, seed=9)
     em = r["emis_raw"].sum(axis=0) * 2.0 ** -20
     nb, lo, hi = 32, -5.0, 5.0
     edges = np.array([np.float32(lo + (hi - lo) * k / nb) for k in range(nb + 1)], dtype=np.float64)
     # lab frame x_cam = x_gas + n_cam.v = x_gas + 1: gas-frame channel edges shift by -1
     prob = Q.riia_channel_probs(0.0, a, 0.0, edges - 1.0)
-    # the expected number of first scatterings: 1 - exp(-tau H(a,0)) over the beam path
     H0 = Q.voigt_scipy(a, 0.0)
     n_first = N * (1 - np.exp(-0.01 * H0))
     shape = em / em.sum()
     ref = prob / prob.sum()
-    peak = ref > 0.1 * ref.max()
-    assert np.max(np.abs(shape[peak] - ref[peak]) / ref[peak]) < 0.02
-    assert np.abs(shape - ref).sum() < 0.004 * 4
+    expect = ref * em.sum()
+    m = expect > 50
+    z = (em[m] - expect[m]) / np.sqrt(expect[m])
+    assert np.max(np.abs(z)) < 4.5, np.max(np.abs(z))
+    assert np.abs(shape - ref).sum() < 0.004
     assert abs(em.sum() / n_first - 1) < 0.02
     # peak at v = -v_z: x_lab = +1 in this convention (x = -v/b)
     centres = 0.5 * (edges[1:] + edges[:-1])
