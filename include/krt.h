@@ -115,9 +115,9 @@ typedef struct {
     double src_dir[3];         /* beam direction (unit) */
     int32_t src_profile;       /* KRT_PROF_* */
     double src_x0;             /* line offset for KRT_PROF_DELTA */
-    int32_t spec_nbins;        /* escaped spectrum bins over [spec_lo, spec_hi) */
+    int32_t spec_nbins;        /* escaped spectrum bins over [spec_lo, spec_hi), 1..1024 */
     double spec_lo, spec_hi;
-    int32_t emis_nch;          /* emissivity channels over [ch_lo, ch_hi) (0 = off) */
+    int32_t emis_nch;          /* emissivity channels over [ch_lo, ch_hi), 0 (off)..256 */
     double ch_lo, ch_hi;
     double n_cam[3];           /* camera direction (unit) */
     int32_t jbar;              /* 1 = tally mean intensity per cell */
@@ -182,9 +182,13 @@ int krt_mc_run(krt_ctx *ctx, uint64_t n_packets, uint64_t seed, const krt_run_op
  * sum_i n_i = ntot.  Outputs k0_l = n_l sigma0_l and
  * eps_l = C_u,tot / (A[u][l] + C_u,tot) with C_u,tot the total collisional
  * rate out of level u = l+1.  Host arrays: E[nl], g[nl], A[nl*nl], Cd[nl*nl],
- * sigma0[nl-1].  Errors: KRT_EINVAL (nl outside 2..8, NULL arrays). */
+ * sigma0[nl-1].  The device arrays hold `ncell` cells each; the call is
+ * independent of the uploaded grid (it may precede krt_grid_upload, and the
+ * caller sizes every device array for `ncell`).  Errors: KRT_EINVAL (nl
+ * outside 2..8, ncell outside 1..2^31-1, NULL arrays, non-finite constants). */
 typedef struct {
     int32_t n_levels;
+    int64_t ncell;                           /* cells in every device array */
     const double *E, *g, *A, *Cd, *sigma0;   /* host */
     const double *ncoll_dev, *ntot_dev;      /* device [ncell] */
     double *pops_dev;                        /* device [ncell][nl], written */

@@ -37,6 +37,7 @@ struct krt_ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;   // bracket the last transport launch
     float last_ms = 0.0f;
     // learned escape: FP32 master parameters, Adam moments, gradient, packed BF16 image
+    float *edges = nullptr;                    // [kEdgeFloats]: spectrum then channel edges
     bool mlp_ready = false;
     float *mlp_p = nullptr, *mlp_m = nullptr, *mlp_v = nullptr, *mlp_g = nullptr, *mlp_norm = nullptr;
     float *mlp_loss = nullptr, *mlp_u = nullptr;
@@ -108,6 +109,11 @@ bool valid_bins(int nb, double lo, double hi) {
     return nb > 0 && nb < (1 << 24) && std::isfinite(lo) && std::isfinite(hi) && hi > lo;
 }
 
+// binary32 bin edges lo + (hi - lo) k / nb, k = 0..nb, evaluated in FP64
+void fill_edges(float *e, int nb, double lo, double hi) {
+    for (int k = 0; k <= nb; ++k) e[k] = (float)(lo + (hi - lo) * (double)k / (double)nb);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ ctx ---
@@ -126,7 +132,8 @@ extern "C" int krt_create(krt_ctx **out, int hip_device, void *hip_stream) {
     if (hipMalloc(&c->work_counter, sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&c->level_consts, sizeof(double) * 256) != hipSuccess ||
         hipHostMalloc(&c->host_pinned, sizeof(int64_t) * 64, hipHostMallocDefault) != hipSuccess ||
-        hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+        hipMalloc(&c->edges, sizeof(float) * kEdgeFloats) != hipSuccess) {
         krt_destroy(c);
         return KRT_EHIP;
     }
@@ -147,6 +154,7 @@ extern "C" void krt_destroy(krt_ctx *c) {
                     (void *)c->mlp_loss, (void *)c->mlp_u, (void *)c->mlp_idx, (void *)c->mlp_blob,
                     (void *)c->mlp_img})
         if (p) (void)hipFree(p);
+    if (c->edges) (void)hipFree(c->edges);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     delete c;
@@ -240,7 +248,8 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
     if (o->line < 0 || o->line >= (int)c->tab.size() || o->line >= c->grid.n_lines)
         return fail(c, KRT_EINVAL, "line %d out of range", o->line);
     if (!t->spec_raw_dev || !t->counters_dev) return fail(c, KRT_EINVAL, "spec_raw and counters are required");
-    if (!valid_bins(o->spec_nbins, o->spec_lo, o->spec_hi)) return fail(c, KRT_EINVAL, "bad spectrum bins");
+    if (!valid_bins(o->spec_nbins, o->spec_lo, o->spec_hi) || o->spec_nbins > kMaxSpecBins)
+        return fail(c, KRT_EINVAL, "bad spectrum bins (1..%d bins, finite hi > lo)", kMaxSpecBins);
     if (o->source < KRT_SRC_POINT || o->source > KRT_SRC_BEAM) return fail(c, KRT_EINVAL, "bad source %d", o->source);
     if (o->src_profile < KRT_PROF_DELTA || o->src_profile > KRT_PROF_GAUSS) return fail(c, KRT_EINVAL, "bad profile");
     if (o->source == KRT_SRC_VOLUME && !c->alias_prob[o->line])
@@ -252,7 +261,8 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
     if (o->emis_nch < 0) return fail(c, KRT_EINVAL, "emis_nch < 0");
     if (o->emis_nch > 0) {
         if (!t->emis_raw_dev) return fail(c, KRT_EINVAL, "emis_nch > 0 needs emis_raw");
-        if (!valid_bins(o->emis_nch, o->ch_lo, o->ch_hi)) return fail(c, KRT_EINVAL, "bad channels");
+        if (!valid_bins(o->emis_nch, o->ch_lo, o->ch_hi) || o->emis_nch > kMaxChannels)
+            return fail(c, KRT_EINVAL, "bad channels (1..%d, finite hi > lo)", kMaxChannels);
         double nn = o->n_cam[0] * o->n_cam[0] + o->n_cam[1] * o->n_cam[1] + o->n_cam[2] * o->n_cam[2];
         if (!(std::fabs(nn - 1.0) < 1e-6)) return fail(c, KRT_EINVAL, "n_cam must be a unit vector");
     }
@@ -319,14 +329,18 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
     P.source = o->source;
     P.src_profile = o->src_profile;
     P.src_x0 = (float)o->src_x0;
+    {
+        std::vector<float> e(kEdgeFloats, 0.0f);
+        fill_edges(e.data(), o->spec_nbins, o->spec_lo, o->spec_hi);
+        if (o->emis_nch > 0) fill_edges(e.data() + kMaxSpecBins + 1, o->emis_nch, o->ch_lo, o->ch_hi);
+        HIPCHK(c, hipMemcpyAsync(c->edges, e.data(), sizeof(float) * kEdgeFloats, hipMemcpyHostToDevice, c->stream));
+    }
     P.spec_nb = o->spec_nbins;
-    P.spec_lo = o->spec_lo;
-    P.spec_hi = o->spec_hi;
     P.spec_inv_w = (float)(o->spec_nbins / (o->spec_hi - o->spec_lo));
+    P.spec_edges = c->edges;
     P.emis_nch = o->emis_nch;
-    P.ch_lo = o->ch_lo;
-    P.ch_hi = o->ch_hi;
     P.ch_inv_w = o->emis_nch > 0 ? (float)(o->emis_nch / (o->ch_hi - o->ch_lo)) : 0.0f;
+    P.ch_edges = c->edges + kMaxSpecBins + 1;
     P.frac_scale = std::ldexp(1.0f, fb);
     P.jbar_scale = std::ldexp(1.0f, fj);
     P.spec_raw = t->spec_raw_dev;
@@ -458,9 +472,9 @@ hipError_t krt::launch_levels(int nl, int64_t ncell, const double *consts, const
 extern "C" int krt_levels_update(krt_ctx *c, const krt_levels_desc *d, const float *jbar_dev) {
     if (!c) return KRT_EINVAL;
     if (!d) return fail(c, KRT_EINVAL, "levels desc NULL");
-    if (!c->have_grid) return fail(c, KRT_ESTATE, "no grid uploaded");
     const int nl = d->n_levels;
     if (nl < 2 || nl > 8) return fail(c, KRT_EINVAL, "n_levels %d outside 2..8", nl);
+    if (d->ncell < 1 || d->ncell >= (int64_t(1) << 31)) return fail(c, KRT_EINVAL, "levels ncell %lld", (long long)d->ncell);
     if (!d->E || !d->g || !d->A || !d->Cd || !d->sigma0 || !d->ncoll_dev || !d->ntot_dev || !d->pops_dev)
         return fail(c, KRT_EINVAL, "levels desc has NULL arrays");
     std::vector<double> K;
@@ -472,7 +486,7 @@ extern "C" int krt_levels_update(krt_ctx *c, const krt_levels_desc *d, const flo
     for (double v : K) if (!std::isfinite(v)) return fail(c, KRT_EINVAL, "non-finite level constant");
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, hipMemcpyAsync(c->level_consts, K.data(), sizeof(double) * K.size(), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, launch_levels(nl, c->ncell, c->level_consts, d->ncoll_dev, d->ntot_dev, jbar_dev, d->pops_dev,
+    HIPCHK(c, launch_levels(nl, d->ncell, c->level_consts, d->ncoll_dev, d->ntot_dev, jbar_dev, d->pops_dev,
                             d->k0_out_dev, d->eps_out_dev, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return KRT_OK;
@@ -490,9 +504,13 @@ extern "C" int krt_debug_philox(krt_ctx *c, const uint32_t *ctr, const uint32_t 
 
 extern "C" int krt_debug_bins(krt_ctx *c, const float *x, int64_t n, int32_t nb, double lo, double hi, int32_t *out) {
     if (!c) return KRT_EINVAL;
-    if (!x || !out || n <= 0 || !valid_bins(nb, lo, hi)) return fail(c, KRT_EINVAL, "bad bins args");
+    if (!x || !out || n <= 0 || !valid_bins(nb, lo, hi) || nb > kMaxSpecBins)
+        return fail(c, KRT_EINVAL, "bad bins args");
     HIPCHK(c, hipSetDevice(c->device));
-    HIPCHK(c, launch_debug_bins(x, n, nb, lo, hi, out, c->stream));
+    std::vector<float> e(nb + 1);
+    fill_edges(e.data(), nb, lo, hi);
+    HIPCHK(c, hipMemcpyAsync(c->edges, e.data(), sizeof(float) * (nb + 1), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, launch_debug_bins(x, n, nb, c->edges, (float)(nb / (hi - lo)), out, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return KRT_OK;
 }

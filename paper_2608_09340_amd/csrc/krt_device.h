@@ -46,21 +46,20 @@ __device__ __forceinline__ float sin_rev(float r) { return __builtin_amdgcn_sinf
 __device__ __forceinline__ float cos_rev(float r) { return __builtin_amdgcn_cosf(r); }
 
 // ------------------------------------------------------------------- bins ---
-// Index rule shared by every tally: edges are binary32 values of
-// lo + (hi - lo) * k / nb computed in FP64; the bin is 1 + the largest k with
-// edge[k] <= x, 0 below edge[0], nb + 1 at or above edge[nb], -1 for NaN.
-__device__ __forceinline__ float bin_edge(double lo, double hi, int nb, int k) {
-    return (float)(lo + (hi - lo) * (double)k / (double)nb);
-}
-
-__device__ int bin_index(float x, int nb, double lo, double hi, float inv_w) {
+// Index rule shared by every tally: edges[k] (k = 0..nb) are the binary32 values
+// of lo + (hi - lo) * k / nb computed in FP64 on the host; the bin is 1 + the
+// largest k with edges[k] <= x, 0 below edges[0], nb + 1 at or above edges[nb],
+// -1 for NaN.  The first guess from (x - lo) / width is corrected against the
+// edges themselves, so the result is exact whatever the rounding of the guess.
+__device__ __forceinline__ int bin_index(float x, const float *edges, int nb, float inv_w) {
     if (!(x == x)) return -1;
-    if (x < bin_edge(lo, hi, nb, 0)) return 0;
-    if (x >= bin_edge(lo, hi, nb, nb)) return nb + 1;
-    int k = (int)((x - (float)lo) * inv_w);
+    const float e0 = edges[0];
+    if (x < e0) return 0;
+    if (x >= edges[nb]) return nb + 1;
+    int k = (int)((x - e0) * inv_w);
     k = max(0, min(nb - 1, k));
-    while (k > 0 && bin_edge(lo, hi, nb, k) > x) --k;
-    while (k < nb - 1 && bin_edge(lo, hi, nb, k + 1) <= x) ++k;
+    while (k > 0 && edges[k] > x) --k;
+    while (k < nb - 1 && edges[k + 1] <= x) ++k;
     return k + 1;
 }
 

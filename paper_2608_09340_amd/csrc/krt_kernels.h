@@ -25,6 +25,10 @@ enum { KRT_SRC_POINT_I = 0, KRT_SRC_PLANE_I = 1, KRT_SRC_VOLUME_I = 2, KRT_SRC_B
 enum { KRT_PROF_DELTA_I = 0, KRT_PROF_VOIGT_I = 1, KRT_PROF_GAUSS_I = 2 };
 enum { KRT_PHASE_ISO_I = 0, KRT_PHASE_DIPOLE_I = 1 };
 
+// bin-edge tables staged in LDS after the line tables
+constexpr int kMaxSpecBins = 1024, kMaxChannels = 256;
+constexpr int kEdgeFloats = (kMaxSpecBins + 1) + (kMaxChannels + 1) + 2;  // padded to a multiple of 4
+
 // 1 / ln((300/8)^(1/15)): logarithmic row spacing of the sampler above |x| = 8
 constexpr float kRowInvLog = 4.1386840f;
 
@@ -47,13 +51,13 @@ struct RunParams {
     float src_x0;
     double src_pos[3];
     float src_dir[3];
-    // tallies
+    // tallies (edges: binary32 bin edges computed on the host, staged in LDS)
     int spec_nb;
-    double spec_lo, spec_hi;
     float spec_inv_w;
+    const float *spec_edges;  // [spec_nb + 1]
     int emis_nch;
-    double ch_lo, ch_hi;
     float ch_inv_w;
+    const float *ch_edges;    // [emis_nch + 1]
     float n_cam[3];
     float frac_scale;  // 2^F, emissivity
     float jbar_scale;  // 2^Fj, mean intensity
@@ -75,7 +79,7 @@ hipError_t launch_finalize(const int64_t *raw, float *out, int64_t n, double sca
 hipError_t launch_zero_i64(int64_t *p, int64_t n, hipStream_t s);
 hipError_t launch_debug_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out, int64_t n,
                                hipStream_t s);
-hipError_t launch_debug_bins(const float *x, int64_t n, int nb, double lo, double hi, int32_t *out,
+hipError_t launch_debug_bins(const float *x, int64_t n, int nb, const float *edges, float inv_w, int32_t *out,
                              hipStream_t s);
 hipError_t launch_debug_voigt(const float *tab, const float *x, int64_t n, float *out, hipStream_t s);
 hipError_t launch_debug_upar(const float *tab, float a, float thd, float x, uint32_t k0, uint32_t k1,

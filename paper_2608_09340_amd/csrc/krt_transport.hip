@@ -94,17 +94,21 @@ template <bool kEsc>
 __global__ void __launch_bounds__(kEsc ? 512 : 1024) mc_transport_kernel(RunParams P) {
     extern __shared__ float4 lds4[];
     float *T = reinterpret_cast<float *>(lds4);
+    float *sedges = T + kTabFloats;                      // spectrum edges
+    float *cedges = sedges + (kMaxSpecBins + 1);         // channel edges
     {
         const float4 *src = reinterpret_cast<const float4 *>(P.tab);
         for (int i = threadIdx.x; i < kTabFloats / 4; i += blockDim.x) lds4[i] = src[i];
+        for (int i = threadIdx.x; i <= P.spec_nb; i += blockDim.x) sedges[i] = P.spec_edges[i];
+        for (int i = threadIdx.x; i <= P.emis_nch; i += blockDim.x) cedges[i] = P.ch_edges[i];
         if (kEsc) {
             const float4 *ms = reinterpret_cast<const float4 *>(P.mlp_img);
-            float4 *md = lds4 + kTabFloats / 4;
+            float4 *md = lds4 + (kTabFloats + kEdgeFloats) / 4;
             for (int i = threadIdx.x; i < kMlpFwdBytes / 16; i += blockDim.x) md[i] = ms[i];
         }
     }
     __syncthreads();
-    const unsigned char *mimg = reinterpret_cast<const unsigned char *>(lds4 + kTabFloats / 4);
+    const unsigned char *mimg = reinterpret_cast<const unsigned char *>(lds4 + (kTabFloats + kEdgeFloats) / 4);
     const float *mbias = reinterpret_cast<const float *>(mimg + kTilesFwd * kTileBytes);
     const float *mnorm = mbias + kBiasFloats;
 
@@ -282,7 +286,7 @@ __global__ void __launch_bounds__(kEsc ? 512 : 1024) mc_transport_kernel(RunPara
                 }
                 if (escaped) {
                     c_esc += 1;
-                    int b = bin_index(x, P.spec_nb, P.spec_lo, P.spec_hi, P.spec_inv_w);
+                    int b = bin_index(x, sedges, P.spec_nb, P.spec_inv_w);
                     if (b < 0) atomicOr(status, (uint32_t)KRT_ST_NAN_BIT);
                     else atomicAdd(reinterpret_cast<unsigned long long *>(P.spec_raw + b), 1ull);
                     outcome = 1;
@@ -372,7 +376,7 @@ __global__ void __launch_bounds__(kEsc ? 512 : 1024) mc_transport_kernel(RunPara
                         int64_t wq = (int64_t)__float2ll_rn(0.25f * Ns * P.frac_scale);
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
-                            int kb = bin_index(vc + sd * g4[q], P.emis_nch, P.ch_lo, P.ch_hi, P.ch_inv_w);
+                            int kb = bin_index(vc + sd * g4[q], cedges, P.emis_nch, P.ch_inv_w);
                             if (kb >= 1 && kb <= P.emis_nch)
                                 emis_add(E, kb - 1, wq, P.emis_raw + (int64_t)cell * P.emis_nch, status);
                             else
@@ -420,7 +424,7 @@ __global__ void __launch_bounds__(kEsc ? 512 : 1024) mc_transport_kernel(RunPara
                                 up2 * (e2x * P.n_cam[0] + e2y * P.n_cam[1] + e2z * P.n_cam[2]);
                     float xcam = xc + upar * (gc - 1.0f) + upc +
                                  (P.n_cam[0] * vxc + P.n_cam[1] * vyc + P.n_cam[2] * vzc);
-                    int kb = bin_index(xcam, P.emis_nch, P.ch_lo, P.ch_hi, P.ch_inv_w);
+                    int kb = bin_index(xcam, cedges, P.emis_nch, P.ch_inv_w);
                     if (kb >= 1 && kb <= P.emis_nch) {
                         float wph = (P.phase == KRT_PHASE_DIPOLE_I) ? 0.75f * (1.0f + gc * gc) : 1.0f;
                         emis_add(E, kb - 1, (int64_t)__float2ll_rn(wph * P.frac_scale),
@@ -496,11 +500,14 @@ __global__ void debug_philox_kernel(const uint32_t *ctr, const uint32_t *key, ui
     out[4 * i] = r.x; out[4 * i + 1] = r.y; out[4 * i + 2] = r.z; out[4 * i + 3] = r.w;
 }
 
-__global__ void debug_bins_kernel(const float *x, int64_t n, int nb, double lo, double hi, float inv_w,
+__global__ void debug_bins_kernel(const float *x, int64_t n, int nb, const float *edges, float inv_w,
                                   int32_t *out) {
+    __shared__ float e[kMaxSpecBins + 1];
+    for (int i = threadIdx.x; i <= nb; i += blockDim.x) e[i] = edges[i];
+    __syncthreads();
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    out[i] = bin_index(x[i], nb, lo, hi, inv_w);
+    out[i] = bin_index(x[i], e, nb, inv_w);
 }
 
 __global__ void debug_voigt_kernel(const float *tab, const float *x, int64_t n, float *out) {
@@ -530,7 +537,7 @@ __global__ void debug_upar_kernel(const float *tab, float a, float thd, float x,
 // ---------------------------------------------------------------- launch ---
 hipError_t launch_transport(const RunParams &P, int grid, int block, hipStream_t s) {
     const bool esc = P.mlp_img != nullptr;
-    size_t lds = sizeof(float) * kTabFloats + (esc ? (size_t)kMlpFwdBytes : 0);
+    size_t lds = sizeof(float) * (kTabFloats + kEdgeFloats) + (esc ? (size_t)kMlpFwdBytes : 0);
     static bool attr_set[2] = {false, false};
     const void *fn = esc ? reinterpret_cast<const void *>(mc_transport_kernel<true>)
                          : reinterpret_cast<const void *>(mc_transport_kernel<false>);
@@ -564,10 +571,10 @@ hipError_t launch_debug_philox(const uint32_t *ctr, const uint32_t *key, uint32_
     return hipGetLastError();
 }
 
-hipError_t launch_debug_bins(const float *x, int64_t n, int nb, double lo, double hi, int32_t *out, hipStream_t s) {
+hipError_t launch_debug_bins(const float *x, int64_t n, int nb, const float *edges, float inv_w, int32_t *out,
+                             hipStream_t s) {
     int grid = (int)((n + 255) / 256);
-    float inv_w = (float)((double)nb / (hi - lo));
-    hipLaunchKernelGGL(debug_bins_kernel, dim3(grid), dim3(256), 0, s, x, n, nb, lo, hi, inv_w, out);
+    hipLaunchKernelGGL(debug_bins_kernel, dim3(grid), dim3(256), 0, s, x, n, nb, edges, inv_w, out);
     return hipGetLastError();
 }
 

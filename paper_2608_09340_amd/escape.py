@@ -1,0 +1,34 @@
+"""Training recipe of the learned escape: record single-cell escapes with the
+plain walk on the GPU (krt_escape_record), fit the output normalisation, then
+run the BF16-MFMA training kernels (krt_escape_train) in stages of decreasing
+learning rate and growing batch.  Only the order of the library calls lives
+here; records, gradients and Adam updates are computed by libkrt.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import krt
+
+# (steps, batch, learning rate): Adam, learning rate halved and batch doubled per stage
+DEFAULT_STAGES = ((3000, 4096, 2e-3), (3000, 8192, 1e-3), (3000, 16384, 5e-4), (2000, 16384, 2.5e-4))
+
+
+def train_escape(ctx: "krt.Context", line: int = 0, n_records: int = 2_000_000, seed: int = 1,
+                 log10_tau=(2.0, 5.0), stages=DEFAULT_STAGES, record_offset: int = 0) -> dict:
+    """Record `n_records` escapes from cubes with log10 tau_R uniform in
+    `log10_tau` (line `line`, whose tables must be built), initialise the
+    network from `seed`, fit the normalisation and train.  Returns the record
+    buffer and the per-step loss history (all stages, concatenated)."""
+    import torch
+    dev = torch.device("cuda", ctx.device)
+    rec = torch.zeros((n_records, 10), dtype=torch.float32, device=dev)
+    ctx.krt_escape_record(line, n_records, seed, record_offset, log10_tau[0], log10_tau[1], rec)
+    ctx.krt_escape_init(seed)
+    ctx.krt_escape_fit_norm(rec, n_records)
+    hist = []
+    for k, (steps, batch, lr) in enumerate(stages):
+        h = torch.zeros(steps, dtype=torch.float32, device=dev)
+        ctx.krt_escape_train(rec, n_records, steps, batch, lr, seed * 1000 + 11 + k, h)
+        hist.append(h.cpu().numpy())
+    return {"rec": rec, "hist": np.concatenate(hist), "log10_tau": tuple(log10_tau)}

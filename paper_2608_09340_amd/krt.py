@@ -52,7 +52,7 @@ class krt_tallies(C.Structure):
 
 
 class krt_levels_desc(C.Structure):
-    _fields_ = [("n_levels", C.c_int32), ("E", C.c_void_p), ("g", C.c_void_p), ("A", C.c_void_p),
+    _fields_ = [("n_levels", C.c_int32), ("ncell", C.c_int64), ("E", C.c_void_p), ("g", C.c_void_p), ("A", C.c_void_p),
                 ("Cd", C.c_void_p), ("sigma0", C.c_void_p), ("ncoll_dev", C.c_void_p),
                 ("ntot_dev", C.c_void_p), ("pops_dev", C.c_void_p), ("k0_out_dev", C.c_void_p),
                 ("eps_out_dev", C.c_void_p)]

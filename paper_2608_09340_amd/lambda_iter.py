@@ -66,6 +66,7 @@ class LambdaIteration:
     def _levels(self, jbar):
         d = krt.krt_levels_desc()
         d.n_levels = self.nl
+        d.ncell = self.ncell
         d.E, d.g, d.A, d.Cd, d.sigma0 = [k.ctypes.data for k in self._keep]
         d.ncoll_dev, d.ntot_dev, d.pops_dev = self.ncoll.data_ptr(), self.ntot.data_ptr(), self.pops.data_ptr()
         d.k0_out_dev, d.eps_out_dev = self.k0.data_ptr(), self.eps.data_ptr()

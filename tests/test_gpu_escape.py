@@ -116,29 +116,26 @@ def test_escape_records_vs_oracle(gpu_ctx, tau, xin):
 
 @pytest.fixture(scope="module")
 def trained(gpu_ctx):
-    """Train the escape network on GPU-recorded single-cell escapes (a = 1e-3)."""
-    import torch
+    """Train the escape network on GPU-recorded single-cell escapes (a = 1e-3,
+    log10 tau_R uniform in [1, 5]) with the staged default recipe."""
     from paper_2608_09340_amd import krt
+    from paper_2608_09340_amd.escape import train_escape
     T = krt.Transport(W.slab(10.0, 1e-3, 4), ctx=gpu_ctx)
-    n = 1_000_000
-    rec = torch.zeros((n, 10), dtype=torch.float32, device="cuda")
-    gpu_ctx.krt_escape_record(0, n, 1, 0, 2.0, 5.0, rec)
-    gpu_ctx.krt_escape_init(1)
-    gpu_ctx.krt_escape_fit_norm(rec, n)
-    steps = 3000
-    hist = torch.zeros(steps, dtype=torch.float32, device="cuda")
-    gpu_ctx.krt_escape_train(rec, n, steps, 4096, 2e-3, 11, hist)
-    gpu_ctx.krt_escape_train(rec, n, 1000, 8192, 5e-4, 12, None)
-    return {"rec": rec, "hist": hist.cpu().numpy(), "T": T}
+    r = train_escape(gpu_ctx, 0, n_records=2_000_000, seed=1, log10_tau=(1.0, 5.0))
+    r["T"] = T
+    return r
 
 
 def test_training_reduces_loss(trained):
+    """The pinball loss falls well below its value at initialisation and keeps
+    falling after the first hundred steps (later stages lower it further)."""
     h = trained["hist"]
     assert np.all(np.isfinite(h))
-    assert h[-200:].mean() < 0.7 * h[:50].mean(), (h[:50].mean(), h[-200:].mean())
+    early, mid, late = h[:5].mean(), h[50:100].mean(), h[-200:].mean()
+    assert late < 0.6 * early and late < mid, (early, mid, late)
 
 
-@pytest.mark.parametrize("tau,xin", [(3e2, 0.0), (3e3, 1.0), (3e4, 2.0)])
+@pytest.mark.parametrize("tau,xin", [(3e1, 0.0), (3e2, 0.0), (3e3, 1.0), (3e4, 2.0)])
 def test_learned_samples_vs_plain(gpu_ctx, trained, tau, xin):
     """At a fixed condition, the network's samples (quantile at u ~ U(0,1)) vs
     held-out plain single-cell escapes: KS distance of the exit frequency and
@@ -154,9 +151,9 @@ def test_learned_samples_vs_plain(gpu_ctx, trained, tau, xin):
     pred = torch.zeros((n, 6), dtype=torch.float32, device="cuda")
     gpu_ctx.krt_escape_forward(torch.from_numpy(raw).cuda(), pred)
     m = pred.cpu().numpy().astype(np.float64)
-    for k, col in ((0, 3), (3, 6)):
-        ks = stats.ks_2samp(m[:, k], plain[:, col])
-        assert ks.statistic < 0.06, (tau, xin, k, ks.statistic)
+    ks = {k: stats.ks_2samp(m[:, k], plain[:, col]).statistic for k, col in ((0, 3), (1, 4), (2, 5), (3, 6))}
+    print(f"tau={tau} x_in={xin} KS x_out {ks[0]:.4f} s {ks[1]:.4f} t {ks[2]:.4f} mu {ks[3]:.4f}")
+    assert ks[0] < 0.06 and ks[3] < 0.06, (tau, xin, ks)
     assert abs(m[:, 4].mean() - plain[:, 7].mean()) < 0.1
 
 

@@ -189,6 +189,7 @@ def test_levels_update_vs_oracle(gpu_ctx):
     keep = [np.ascontiguousarray(v, dtype=np.float64) for v in (E, g, A, Cd, s0)]
     d = krt.krt_levels_desc()
     d.n_levels = nl
+    d.ncell = n ** 3
     d.E, d.g, d.A, d.Cd, d.sigma0 = [k.ctypes.data for k in keep]
     d.ncoll_dev, d.ntot_dev, d.pops_dev = ncd.data_ptr(), ntd.data_ptr(), pops.data_ptr()
     d.k0_out_dev, d.eps_out_dev = k0o.data_ptr(), epo.data_ptr()
