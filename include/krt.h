@@ -133,7 +133,11 @@ typedef struct {
     uint64_t norm_packets;     /* packets for the FP32 normalisation (0 = n_packets) */
     double luminosity;         /* photons/s carried by all N packets; scales the FP32 outputs (0 = 1) */
     double esc_tau_min;        /* learned escape only where k0 R >= this (0 = 100) */
-    int32_t esc_min_lanes;     /* network call when at least this many lanes of a wave ask (0 = 8) */
+    int32_t esc_min_lanes;     /* network call when at least this many lanes of a wave ask (0 = 8);
+                                  one suffices once the packet pool is exhausted.  Which
+                                  scatterings take the network then depends on the packets
+                                  sharing a wave, so escape_mode = 1 tallies are statistically,
+                                  not bitwise, independent of launch geometry */
 } krt_run_opts;
 
 /* Caller-allocated DEVICE buffers.  Raw tallies are int64 fixed point, so their

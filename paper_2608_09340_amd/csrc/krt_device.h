@@ -35,6 +35,7 @@ __device__ __forceinline__ float u01(uint32_t w) {
 constexpr float kPiF = 3.14159265358979f;
 constexpr uint32_t kMaxCrossings = 1u << 30;  // per packet: a packet that never interacts is retired as stuck
 constexpr float kInvSqrtPiF = 0.564189583547756f;
+constexpr float kInvSqrt2F = 0.707106781186547524f;
 constexpr float kLn2F = 0.693147180559945f;
 __device__ __forceinline__ float f_log(float x) { return __builtin_amdgcn_logf(x) * kLn2F; }
 __device__ __forceinline__ float f_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896f); }

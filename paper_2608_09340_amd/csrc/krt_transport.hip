@@ -324,8 +324,12 @@ __global__ void __launch_bounds__(kEsc ? 512 : 1024) mc_transport_kernel(RunPara
                     mlp = true;
                 }
             }
-            uint64_t wm = __ballot(mlp);
-            if (__popcll(wm) >= P.esc_min_lanes) {
+            // once the packet pool is exhausted (some lane of this wave is done) a
+            // single asking lane suffices: the wave lives only as long as its
+            // slowest packet, and a call cuts that packet's walk
+            const uint64_t wm = __ballot(mlp);
+            const int need_lanes = (__ballot(done) != 0ull) ? 1 : P.esc_min_lanes;
+            if (__popcll(wm) >= need_lanes) {
                 uint4 C = philox(make_uint4(ev, (uint32_t)pid, (uint32_t)(pid >> 32), 2u), P.key0, P.key1);
                 float in[4];
                 in[0] = (lt - 3.5f) * (1.0f / 1.5f);
@@ -365,23 +369,29 @@ __global__ void __launch_bounds__(kEsc ? 512 : 1024) mc_transport_kernel(RunPara
                     nx = ddir[0]; ny = ddir[1]; nz = ddir[2];
                     float Ns = fmaxf(f_exp(lns), 1.0f);
                     // emissivity of the skipped scatterings: thermalised core, camera
-                    // frequency ~ N(n_cam.v, (<x^2> + 1)/3), four samples
+                    // frequency ~ N(n_cam.v, (<x^2> + 1)/3), integrated exactly over the
+                    // channels (no sampling noise); mass outside the channels is dropped
                     if (P.emis_raw) {
-                        uint4 D = philox(make_uint4(ev, plo, phi, 3u), P.key0, P.key1);
-                        float sd = f_sqrt((f_exp(lx2) + 1.0f) * (1.0f / 3.0f));
-                        float vc = P.n_cam[0] * vxc + P.n_cam[1] * vyc + P.n_cam[2] * vzc;
-                        float r1 = f_sqrt(-2.0f * f_log(u01(D.x))), r2 = f_sqrt(-2.0f * f_log(u01(D.z)));
-                        float g4[4] = {r1 * cos_rev(u01(D.y)), r1 * sin_rev(u01(D.y)), r2 * cos_rev(u01(D.w)),
-                                       r2 * sin_rev(u01(D.w))};
-                        int64_t wq = (int64_t)__float2ll_rn(0.25f * Ns * P.frac_scale);
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            int kb = bin_index(vc + sd * g4[q], cedges, P.emis_nch, P.ch_inv_w);
-                            if (kb >= 1 && kb <= P.emis_nch)
-                                emis_add(E, kb - 1, wq, P.emis_raw + (int64_t)cell * P.emis_nch, status);
-                            else
-                                c_drop += 1;
+                        const float sd = f_sqrt((f_exp(lx2) + 1.0f) * (1.0f / 3.0f));
+                        const float vc = P.n_cam[0] * vxc + P.n_cam[1] * vyc + P.n_cam[2] * vzc;
+                        const float isd = kInvSqrt2F * f_rcp(sd);
+                        const float W = Ns * P.frac_scale;
+                        int kb0 = bin_index(vc - 6.0f * sd, cedges, P.emis_nch, P.ch_inv_w);
+                        int kb1 = bin_index(vc + 6.0f * sd, cedges, P.emis_nch, P.ch_inv_w);
+                        kb0 = max(kb0, 1);
+                        kb1 = min(kb1, P.emis_nch);
+                        float cdf_lo = 0.5f * (1.0f + erff((cedges[kb0 - 1] - vc) * isd));
+                        float inside = 0.0f;
+                        int64_t *ebase = P.emis_raw + (int64_t)cell * P.emis_nch;
+                        for (int kb = kb0; kb <= kb1; ++kb) {
+                            float cdf_hi = 0.5f * (1.0f + erff((cedges[kb] - vc) * isd));
+                            float fr = cdf_hi - cdf_lo;
+                            cdf_lo = cdf_hi;
+                            inside += fr;
+                            int64_t wq = (int64_t)__float2ll_rn(W * fr);
+                            if (wq != 0) emis_add(E, kb - 1, wq, ebase, status);
                         }
+                        c_drop += (int64_t)__float2ll_rn(Ns * fmaxf(0.0f, 1.0f - inside));
                     }
                     x = xo + nx * vxc + ny * vyc + nz * vzc;
                     c_mlp += 1;
