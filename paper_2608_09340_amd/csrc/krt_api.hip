@@ -282,8 +282,9 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
         if (al < 1e-4 * (1 - 1e-9) || al > 1e-2 * (1 + 1e-9))
             return fail(c, KRT_EINVAL, "learned escape covers a in [1e-4, 1e-2] (line a = %g)", al);
     }
-    int block = o->wg_size ? o->wg_size : (esc ? 512 : 512);
-    int per_cu = o->wg_per_cu ? o->wg_per_cu : (esc ? 1 : 2);
+    // default: 16 waves per CU, one copy of the LDS tables per CU
+    int block = o->wg_size ? o->wg_size : (esc ? 512 : 1024);
+    int per_cu = o->wg_per_cu ? o->wg_per_cu : 1;
     if (esc && block > 512) return fail(c, KRT_EINVAL, "escape_mode 1 runs at most 512 threads per workgroup");
     if (block < 64 || block > 1024 || block % 64) return fail(c, KRT_EINVAL, "wg_size %d invalid", block);
     if (per_cu < 1 || per_cu > 64) return fail(c, KRT_EINVAL, "wg_per_cu %d invalid", per_cu);

@@ -311,7 +311,7 @@ __global__ void __launch_bounds__(256) mlp_grad_kernel(const unsigned char *blob
             if (wave_live && s == 0 && f < nout) atomicAdd(grad + base + f, t);
         }
     };
-    auto dsilu = [](float z) { float sg = 1.0f / (1.0f + __expf(-z)); return sg * (1.0f + z * (1.0f - sg)); };
+    auto dsilu = [](float z) { float sg = sigmoid_f(z); return sg * (1.0f + z * (1.0f - sg)); };
 
     // ---- layer 4: dW4 = H3 dO^T, db4, dH3 = W4 dO
     for (int mi = 0; mi < 8; ++mi) put(mi, mi, silu(z3[mi].x), silu(z3[mi].y), silu(z3[mi].z), silu(z3[mi].w));

@@ -57,7 +57,12 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
     return (uint16_t)(u >> 16);
 }
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+// logistic(z) from the hardware exp2 and reciprocal (about 1 ulp each; the
+// activations are stored as bfloat16, 8 significant bits)
+__device__ __forceinline__ float sigmoid_f(float z) {
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.44269504088896f * z));
+}
+__device__ __forceinline__ float silu(float z) { return z * sigmoid_f(z); }
 
 __device__ __forceinline__ v4i16 pack4(float a, float b, float c, float d) {
     v4i16 r;

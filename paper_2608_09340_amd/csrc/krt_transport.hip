@@ -66,25 +66,46 @@ __device__ __forceinline__ void wave_add_counter(int64_t *dst, int64_t v) {
 }
 
 // ------------------------------------------------------ learned escape ---
-// Batched evaluation of the escape network for the whole wave (wave-uniform
-// control flow: every lane executes the MFMA; lanes that did not ask ignore the
-// result).  in[4] are this lane's normalised inputs; out[k] receives output k of
-// this lane's sample (normalised).
+// Lane index of the k-th set bit (k counted from 0) of m; k < popcount(m).
+__device__ __forceinline__ int nth_set_lane(uint64_t m, int k) {
+    int pos = 0;
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        const uint64_t low = (w == 64) ? m : (m & ((1ull << w) - 1ull));
+        const int c = __popcll(low);
+        if (k >= c) { k -= c; m >>= w; pos += w; }
+        else m = low;
+    }
+    return pos;
+}
+
+// Batched evaluation of the escape network for the lanes of the wave set in
+// `ask` (wave-uniform control flow: every lane executes the MFMA).  The asking
+// lanes are packed in rank order into blocks of 16 samples, so a call costs
+// ceil(popcount(ask) / 16) block evaluations.  in[4] are this lane's
+// normalised inputs; an asking lane receives its 6 normalised outputs in out[].
 __device__ __attribute__((noinline)) void mlp_eval_wave(const unsigned char *img, const float *bias, const float in[4],
-                                              int lane, float out[kMlpOut]) {
+                                              int lane, uint64_t ask, float out[kMlpOut]) {
+    const int nask = __popcll(ask);
+    const int nblk = (nask + 15) >> 4;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int rank = __popcll(ask & lt);
+    const bool mine = (ask >> lane) & 1ull;
 #pragma unroll 1
-    for (int b = 0; b < 4; ++b) {
-        const int src = 16 * b + (lane & 15);
+    for (int b = 0; b < nblk; ++b) {
+        // block position p = lane & 15 holds the asker of rank 16 b + p (if any)
+        const int r = 16 * b + (lane & 15);
+        const int src = (r < nask) ? nth_set_lane(ask, r) : lane;
         float i0 = __shfl(in[0], src, 64), i1 = __shfl(in[1], src, 64);
         float i2 = __shfl(in[2], src, 64), i3 = __shfl(in[3], src, 64);
-        v4i16 xb = (lane < 16) ? pack4(i0, i1, i2, i3) : pack4(0.f, 0.f, 0.f, 0.f);
+        v4i16 xb = (lane < 16 && r < nask) ? pack4(i0, i1, i2, i3) : pack4(0.f, 0.f, 0.f, 0.f);
         v4f32 o = mlp_forward_block(img, bias, xb, lane, nullptr, nullptr, nullptr);
-        // output k of sample 16b + (lane & 15) sits in lane 16*(k/4) + (lane & 15), component k % 4
+        // output k of block position p sits in lane 16*(k/4) + p, component k % 4
 #pragma unroll
         for (int k = 0; k < kMlpOut; ++k) {
             float comp = (k % 4 == 0) ? o.x : (k % 4 == 1) ? o.y : (k % 4 == 2) ? o.z : o.w;
-            float v = __shfl(comp, 16 * (k / 4) + (lane & 15), 64);
-            if ((lane >> 4) == b) out[k] = v;
+            float v = __shfl(comp, 16 * (k / 4) + (rank & 15), 64);
+            if (mine && (rank >> 4) == b) out[k] = v;
         }
     }
 }
@@ -336,9 +357,9 @@ __global__ void __launch_bounds__(kEsc ? 512 : 1024) mc_transport_kernel(RunPara
                 in[1] = P.esc_log10a + 3.0f;
                 in[2] = xc * 0.25f;
                 in[3] = 2.0f * u01(C.x) - 1.0f;
-                mlp_eval_wave(mimg, mbias, in, lane, mo);
+                mlp_eval_wave(mimg, mbias, in, lane, wm, mo);
                 in[3] = 2.0f * u01(C.y) - 1.0f;
-                mlp_eval_wave(mimg, mbias, in, lane, mo2);
+                mlp_eval_wave(mimg, mbias, in, lane, wm, mo2);
                 if (mlp) {
                     // ---- exit from the cube centred here (half-width Rcube) ----
                     const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
