@@ -127,7 +127,7 @@ typedef struct {
     int32_t escape_mode;       /* 0 = plain random walk; 1 = learned escape in thick cells (needs
                                   krt_escape_init/train or put_weights; a in [1e-4, 1e-2]; no jbar) */
     int32_t wg_size;           /* launch geometry: threads per workgroup (0 = 1024; 512 with
-                                  escape_mode 1, which allows at most 512) */
+                                  escape_mode 1) */
     int32_t wg_per_cu;         /* workgroups per CU (0 = 1) */
     int32_t emis_frac_bits;    /* fixed-point fraction bits F of the emissivity tally (0 = 20) */
     int32_t jbar_frac_bits;    /* fraction bits of the mean-intensity tally (0 = 36) */
@@ -212,10 +212,12 @@ int krt_levels_update(krt_ctx *ctx, const krt_levels_desc *desc,
  * through the full optical depth (Sec. 2.3.2, Sec. 4.1); this proposal is the
  * accelerated alternative it points to for extreme depths, and the plain
  * random walk remains the fallback (below threshold, |x| > 8, a outside
- * [1e-4, 1e-2]).  Inputs (log10 tau_R, log10 a, x_in, u); the 6 outputs are
- * conditional quantiles at level u of (x_out, s, t, mu, ln N_s, ln <x^2>),
- * trained with the pinball loss on single-cell escapes run by the plain
- * transport arithmetic.  Parameters: kNParams = 34438 FP32 master values plus
+ * [1e-4, 1e-2]).  Inputs (log10 tau_R, log10 a, x_in, u); outputs 0-3 and 5
+ * are conditional quantiles at level u of (x_out, s, t, mu, -, ln <x^2>)
+ * trained with the pinball loss, output 4 is ln E[N_s | tau_R, a, x_in]
+ * trained with the log-deviance e^d - 1 - d, d = ln N_s - output (so the
+ * skipped scatterings are deposited with their expected count), all on
+ * single-cell escapes run by the plain transport arithmetic.  Parameters: kNParams = 34438 FP32 master values plus
  * 12 target normalisation constants (mean[6], scale[6]).
  *
  * krt_escape_init: He-uniform parameters from Philox(seed), Adam state zeroed.

@@ -2,9 +2,13 @@
 
 Same parameter layout as the GPU (one flat vector): W1[4][128], b1[128],
 W2[128][128], b2, W3[128][128], b3, W4[128][6], b4[6]; activations SiLU;
-outputs are conditional quantiles trained with the pinball loss
-rho_u(y - o) = (y - o)(u - 1{y < o}) averaged over the batch and summed over
-the 6 outputs.  Inputs are normalised as ((log10 tau - 3.5)/1.5, log10 a + 3,
+outputs 0-3 and 5 are conditional quantiles trained with the pinball loss
+rho_u(y - o) = (y - o)(u - 1{y < o}); output 4 is ln E[N_s | condition],
+trained with the scaled log-deviance f(d) / s4, d = s4 (y4 - o4), where
+f(d) = e^d - 1 - d (continued linearly beyond d = 4, so a rare very long
+escape cannot dominate a batch), whose minimiser satisfies E[e^(y - m)] = 1,
+i.e. e^m = E[N_s].  Losses are averaged over the batch and summed over the
+outputs.  Inputs are normalised as ((log10 tau - 3.5)/1.5, log10 a + 3,
 x_in / 4, 2u - 1).  The manual backward pass is pinned by finite differences
 (tests/test_oracle_mlp.py).  ``bf16=True`` rounds weights and activations to
 bfloat16 (round to nearest even) where the GPU kernels do, to separate the
@@ -71,18 +75,35 @@ def forward(p, X, bf=False):
     return out, cache, W
 
 
-def pinball(out, Y, u):
-    """mean over the batch of the summed pinball losses, and dL/dout."""
+DEV_CLAMP = 4.0
+N_OUT = 4  # index of the ln E[N_s] output
+
+
+def deviance(d):
+    """f(d) = e^d - 1 - d for d <= 4, its tangent continuation beyond; and f'(d)."""
+    d = np.asarray(d, dtype=np.float64)
+    dc = np.minimum(d, DEV_CLAMP)
+    f = np.exp(dc) - 1.0 - dc + (np.exp(DEV_CLAMP) - 1.0) * np.maximum(d - DEV_CLAMP, 0.0)
+    return f, np.exp(dc) - 1.0
+
+
+def pinball(out, Y, u, s4=1.0):
+    """Mean over the batch of the summed per-output losses, and dL/dout.
+    Outputs other than 4: pinball at level u.  Output 4: f(s4 (y - o)) / s4."""
     B = out.shape[0]
     ind = (Y < out).astype(np.float64)
-    loss = np.sum((Y - out) * (u[:, None] - ind)) / B
+    lk = (Y - out) * (u[:, None] - ind)
     dout = (ind - u[:, None]) / B
-    return loss, dout
+    f, fp = deviance(s4 * (Y[:, N_OUT] - out[:, N_OUT]))
+    lk[:, N_OUT] = f / s4
+    dout[:, N_OUT] = -fp / B
+    return float(np.sum(lk) / B), dout
 
 
-def loss_and_grad(p, X, Y, u, bf=False):
+def loss_and_grad(p, X, Y, u, bf=False, s4=1.0):
+    """s4: the target scale of output 4 (norm[6 + 4])."""
     out, c, W = forward(p, X, bf)
-    loss, d = pinball(out, Y, u)
+    loss, d = pinball(out, Y, u, s4)
     g = {"W4": c["h3"].T @ d, "b4": d.sum(0)}
     dh = d @ W["W4"].T
     for i in (3, 2, 1):

@@ -285,7 +285,6 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
     // default: 16 waves per CU, one copy of the LDS tables per CU
     int block = o->wg_size ? o->wg_size : (esc ? 512 : 1024);
     int per_cu = o->wg_per_cu ? o->wg_per_cu : 1;
-    if (esc && block > 512) return fail(c, KRT_EINVAL, "escape_mode 1 runs at most 512 threads per workgroup");
     if (block < 64 || block > 1024 || block % 64) return fail(c, KRT_EINVAL, "wg_size %d invalid", block);
     if (per_cu < 1 || per_cu > 64) return fail(c, KRT_EINVAL, "wg_per_cu %d invalid", per_cu);
     if (o->max_events > 0xFFFFFFFEull) return fail(c, KRT_EINVAL, "max_events too large");

@@ -221,7 +221,8 @@ __device__ __forceinline__ v4i16 xin_operand(const float in[4], int lane) {
 }
 
 // ---------------------------------------------------------- gradient ---
-// One wave per 16-sample block.  grad += d(mean pinball loss)/d(params); loss += sum.
+// One wave per 16-sample block.  grad += d(mean loss)/d(params); loss += sum.
+// Outputs other than ln N_s: pinball loss at level u; ln N_s: log-deviance.
 __global__ void __launch_bounds__(256) mlp_grad_kernel(const unsigned char *blob, const float *rec,
                                                        const int32_t *idx, const float *uq, int batch,
                                                        float *grad, float *loss) {
@@ -253,9 +254,20 @@ __global__ void __launch_bounds__(256) mlp_grad_kernel(const unsigned char *blob
         dO[j] = 0.0f;
         if (k < kMlpOut && live) {
             float y = (r[3 + k] - norm[k]) / norm[kMlpOut + k];
-            float ind = (y < oj) ? 1.0f : 0.0f;
-            dO[j] = (ind - u) * invB;
-            lsum += (y - oj) * (u - ind);
+            if (k == kMlpOutLogN) {
+                // ln E[N_s]: scaled log-deviance f(d) / s4, d = s4 (y - o),
+                // f(d) = e^d - 1 - d, continued linearly beyond d = kDevClamp
+                const float s4 = norm[kMlpOut + k];
+                const float d = s4 * (y - oj);
+                const float dc = fminf(d, kDevClamp);
+                const float ed = __expf(dc);
+                dO[j] = (1.0f - ed) * invB;
+                lsum += (ed - 1.0f - dc + (__expf(kDevClamp) - 1.0f) * fmaxf(d - kDevClamp, 0.0f)) / s4;
+            } else {
+                float ind = (y < oj) ? 1.0f : 0.0f;
+                dO[j] = (ind - u) * invB;
+                lsum += (y - oj) * (u - ind);
+            }
         }
     }
     // loss: reduce over the wave

@@ -112,7 +112,7 @@ __device__ __attribute__((noinline)) void mlp_eval_wave(const unsigned char *img
 
 // --------------------------------------------------------------- kernel ---
 template <bool kEsc>
-__global__ void __launch_bounds__(kEsc ? 512 : 1024) mc_transport_kernel(RunParams P) {
+__global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
     extern __shared__ float4 lds4[];
     float *T = reinterpret_cast<float *>(lds4);
     float *sedges = T + kTabFloats;                      // spectrum edges
@@ -388,7 +388,7 @@ __global__ void __launch_bounds__(kEsc ? 512 : 1024) mc_transport_kernel(RunPara
                     fy = fminf(fmaxf(fmaf(dp[1], P.inv_dx[1], fy), 0.0f), 1.0f);
                     fz = fminf(fmaxf(fmaf(dp[2], P.inv_dx[2], fz), 0.0f), 1.0f);
                     nx = ddir[0]; ny = ddir[1]; nz = ddir[2];
-                    float Ns = fmaxf(f_exp(lns), 1.0f);
+                    float Ns = fmaxf(f_exp(lns), 1.0f);  // E[N_s | condition]
                     // emissivity of the skipped scatterings: thermalised core, camera
                     // frequency ~ N(n_cam.v, (<x^2> + 1)/3), integrated exactly over the
                     // channels (no sampling noise); mass outside the channels is dropped
@@ -416,7 +416,7 @@ __global__ void __launch_bounds__(kEsc ? 512 : 1024) mc_transport_kernel(RunPara
                     }
                     x = xo + nx * vxc + ny * vyc + nz * vzc;
                     c_mlp += 1;
-                    c_skip += (int64_t)Ns;
+                    c_skip += (int64_t)__float2ll_rn(Ns);
                 }
             } else {
                 mlp = false;

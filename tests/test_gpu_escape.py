@@ -77,7 +77,7 @@ def test_mfma_gradient_vs_fp64(gpu_ctx):
     X = mlp.inputs(R[:, 0], R[:, 1], R[:, 2], u)
     Y = mlp.targets_normalised(R, norm)
     for bf in (True, False):
-        l_ref, g_ref = mlp.loss_and_grad(p, X, Y, u, bf=bf)
+        l_ref, g_ref = mlp.loss_and_grad(p, X, Y, u, bf=bf, s4=norm[6 + mlp.N_OUT])
         o = 0
         for name, shp in mlp.SHAPES:
             k = int(np.prod(shp))
@@ -139,7 +139,7 @@ def test_training_reduces_loss(trained):
 def test_learned_samples_vs_plain(gpu_ctx, trained, tau, xin):
     """At a fixed condition, the network's samples (quantile at u ~ U(0,1)) vs
     held-out plain single-cell escapes: KS distance of the exit frequency and
-    of the exit cosine below 0.06, mean ln N_s within 0.1."""
+    of the exit cosine below 0.06, ln E[N_s] within 0.05."""
     import torch
     n = 20000
     out = torch.zeros((n, 10), dtype=torch.float32, device="cuda")
@@ -154,7 +154,10 @@ def test_learned_samples_vs_plain(gpu_ctx, trained, tau, xin):
     ks = {k: stats.ks_2samp(m[:, k], plain[:, col]).statistic for k, col in ((0, 3), (1, 4), (2, 5), (3, 6))}
     print(f"tau={tau} x_in={xin} KS x_out {ks[0]:.4f} s {ks[1]:.4f} t {ks[2]:.4f} mu {ks[3]:.4f}")
     assert ks[0] < 0.06 and ks[3] < 0.06, (tau, xin, ks)
-    assert abs(m[:, 4].mean() - plain[:, 7].mean()) < 0.1
+    # output 4 is ln E[N_s]: against the log of the plain mean count (5%)
+    ln_mean = np.log(np.mean(np.exp(plain[:, 7])))
+    print(f"   ln E[N_s]: learned {m[:, 4].mean():.4f} (spread {m[:, 4].std():.1e}) plain {ln_mean:.4f}")
+    assert abs(m[:, 4].mean() - ln_mean) < 0.05
 
 
 def _agg_emis(em, n, blocks=8):
@@ -188,6 +191,9 @@ def test_cloud_learned_escape_vs_plain(gpu_ctx, trained):
     print(f"spectrum L1 {l1_s:.4f} (floor {floor_s:.4f}); emissivity L1 {l1_e:.4f} (floor {floor_e:.4f}); "
           f"plain scat {pa['counters']['scatterings']} mlp scat {c['scatterings']} calls {c['mlp_calls']} "
           f"skipped {c['skipped_scatterings']}")
+    tot = em.sum() / ea.sum()
+    print(f"emissivity total learned / plain {tot:.4f}")
     assert l1_s <= 0.02 + floor_s
     assert l1_e <= 0.02 + floor_e
+    assert abs(tot - 1.0) < 0.02
     assert c["scatterings"] + c["mlp_calls"] < pa["counters"]["scatterings"]

@@ -19,7 +19,9 @@ def _setup(seed=0, B=64):
 
 def test_backward_matches_finite_differences():
     p, X, Y, u = _setup()
-    _, g = mlp.loss_and_grad(p, X, Y, u)
+    Y[:3, mlp.N_OUT] += 3.0  # some samples beyond the deviance clamp (s4 d > 4)
+    s4 = 1.7
+    _, g = mlp.loss_and_grad(p, X, Y, u, s4=s4)
     rng = np.random.default_rng(1)
     idx = rng.choice(mlp.NPARAMS, 200, replace=False)
     h = 1e-6
@@ -28,7 +30,7 @@ def test_backward_matches_finite_differences():
         pp, pm = p.copy(), p.copy()
         pp[i] += h
         pm[i] -= h
-        fd.append((mlp.loss_and_grad(pp, X, Y, u)[0] - mlp.loss_and_grad(pm, X, Y, u)[0]) / (2 * h))
+        fd.append((mlp.loss_and_grad(pp, X, Y, u, s4=s4)[0] - mlp.loss_and_grad(pm, X, Y, u, s4=s4)[0]) / (2 * h))
     fd = np.array(fd)
     assert np.allclose(g[idx], fd, rtol=1e-5, atol=1e-9)
 
@@ -41,6 +43,19 @@ def test_pinball_quantile_property():
         grid = np.linspace(0, 5, 2001)
         L = [np.mean((y - q) * (u - (y < q))) for q in grid]
         assert abs(grid[int(np.argmin(L))] - np.quantile(y, u)) < 0.01
+
+
+def test_deviance_minimiser_is_log_mean():
+    """The minimiser m of the mean log-deviance E f(y - m) over samples y = ln N
+    is ln E[N] (not the mean or a quantile of ln N), for a skewed N."""
+    rng = np.random.default_rng(4)
+    N = 1.0 + rng.exponential(50.0, 200001)
+    y = np.log(N)
+    grid = np.linspace(2.0, 6.0, 4001)
+    L = [np.mean(mlp.deviance(y - m)[0]) for m in grid]
+    m = grid[int(np.argmin(L))]
+    assert abs(m - np.log(N.mean())) < 2e-3
+    assert abs(m - y.mean()) > 0.3
 
 
 def test_bf16_rounding():
