@@ -126,19 +126,19 @@ typedef struct {
     uint64_t max_events;       /* per packet; 0 = unlimited (2^32 - 2) */
     int32_t escape_mode;       /* 0 = plain random walk; 1 = learned escape in thick cells (needs
                                   krt_escape_init/train or put_weights; a in [1e-4, 1e-2]; no jbar) */
-    int32_t wg_size;           /* launch geometry: threads per workgroup (0 = 1024; 512 with
-                                  escape_mode 1) */
+    int32_t wg_size;           /* launch geometry: threads per workgroup (0 = 1024) */
     int32_t wg_per_cu;         /* workgroups per CU (0 = 1) */
     int32_t emis_frac_bits;    /* fixed-point fraction bits F of the emissivity tally (0 = 20) */
     int32_t jbar_frac_bits;    /* fraction bits of the mean-intensity tally (0 = 36) */
     uint64_t norm_packets;     /* packets for the FP32 normalisation (0 = n_packets) */
     double luminosity;         /* photons/s carried by all N packets; scales the FP32 outputs (0 = 1) */
     double esc_tau_min;        /* learned escape only where k0 R >= this (0 = 100) */
-    int32_t esc_min_lanes;     /* network call when at least this many lanes of a wave ask (0 = 8);
-                                  one suffices once the packet pool is exhausted.  Which
-                                  scatterings take the network then depends on the packets
+    int32_t esc_min_lanes;     /* network call when at least this many lanes of a wave ask (0 = 8).
+                                  Which scatterings take the network then depends on the packets
                                   sharing a wave, so escape_mode = 1 tallies are statistically,
                                   not bitwise, independent of launch geometry */
+    int32_t esc_tail_lanes;    /* as esc_min_lanes once the packet pool is exhausted (0 = 1):
+                                  the wave then lives only as long as its slowest packet */
 } krt_run_opts;
 
 /* Caller-allocated DEVICE buffers.  Raw tallies are int64 fixed point, so their

@@ -4,7 +4,8 @@ Same parameter layout as the GPU (one flat vector): W1[4][128], b1[128],
 W2[128][128], b2, W3[128][128], b3, W4[128][6], b4[6]; activations SiLU;
 outputs 0-3 and 5 are conditional quantiles trained with the pinball loss
 rho_u(y - o) = (y - o)(u - 1{y < o}); output 4 is ln E[N_s | condition],
-trained with the scaled log-deviance f(d) / s4, d = s4 (y4 - o4), where
+trained with the weighted, scaled log-deviance w f(d) / s4 (w = 1/4),
+d = s4 (y4 - o4), where
 f(d) = e^d - 1 - d (continued linearly beyond d = 4, so a rare very long
 escape cannot dominate a batch), whose minimiser satisfies E[e^(y - m)] = 1,
 i.e. e^m = E[N_s].  Losses are averaged over the batch and summed over the
@@ -76,6 +77,7 @@ def forward(p, X, bf=False):
 
 
 DEV_CLAMP = 4.0
+DEV_WEIGHT = 0.25
 N_OUT = 4  # index of the ln E[N_s] output
 
 
@@ -89,14 +91,14 @@ def deviance(d):
 
 def pinball(out, Y, u, s4=1.0):
     """Mean over the batch of the summed per-output losses, and dL/dout.
-    Outputs other than 4: pinball at level u.  Output 4: f(s4 (y - o)) / s4."""
+    Outputs other than 4: pinball at level u.  Output 4: w f(s4 (y - o)) / s4."""
     B = out.shape[0]
     ind = (Y < out).astype(np.float64)
     lk = (Y - out) * (u[:, None] - ind)
     dout = (ind - u[:, None]) / B
     f, fp = deviance(s4 * (Y[:, N_OUT] - out[:, N_OUT]))
-    lk[:, N_OUT] = f / s4
-    dout[:, N_OUT] = -fp / B
+    lk[:, N_OUT] = DEV_WEIGHT * f / s4
+    dout[:, N_OUT] = -DEV_WEIGHT * fp / B
     return float(np.sum(lk) / B), dout
 
 

@@ -283,7 +283,7 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
             return fail(c, KRT_EINVAL, "learned escape covers a in [1e-4, 1e-2] (line a = %g)", al);
     }
     // default: 16 waves per CU, one copy of the LDS tables per CU
-    int block = o->wg_size ? o->wg_size : (esc ? 512 : 1024);
+    int block = o->wg_size ? o->wg_size : 1024;
     int per_cu = o->wg_per_cu ? o->wg_per_cu : 1;
     if (block < 64 || block > 1024 || block % 64) return fail(c, KRT_EINVAL, "wg_size %d invalid", block);
     if (per_cu < 1 || per_cu > 64) return fail(c, KRT_EINVAL, "wg_per_cu %d invalid", per_cu);
@@ -361,6 +361,7 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
     P.esc_x_max = 8.0f;
     P.esc_log10a = (float)std::log10(c->lines[l].a);
     P.esc_min_lanes = o->esc_min_lanes > 0 ? o->esc_min_lanes : 8;
+    P.esc_tail_lanes = o->esc_tail_lanes > 0 ? o->esc_tail_lanes : 1;
     int grid = c->cus * per_cu;
     HIPCHK(c, hipEventRecord(c->ev0, c->stream));
     HIPCHK(c, launch_transport(P, grid, block, c->stream));

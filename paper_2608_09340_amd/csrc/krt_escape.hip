@@ -255,14 +255,14 @@ __global__ void __launch_bounds__(256) mlp_grad_kernel(const unsigned char *blob
         if (k < kMlpOut && live) {
             float y = (r[3 + k] - norm[k]) / norm[kMlpOut + k];
             if (k == kMlpOutLogN) {
-                // ln E[N_s]: scaled log-deviance f(d) / s4, d = s4 (y - o),
+                // ln E[N_s]: weighted, scaled log-deviance w f(d) / s4, d = s4 (y - o),
                 // f(d) = e^d - 1 - d, continued linearly beyond d = kDevClamp
                 const float s4 = norm[kMlpOut + k];
                 const float d = s4 * (y - oj);
                 const float dc = fminf(d, kDevClamp);
                 const float ed = __expf(dc);
-                dO[j] = (1.0f - ed) * invB;
-                lsum += (ed - 1.0f - dc + (__expf(kDevClamp) - 1.0f) * fmaxf(d - kDevClamp, 0.0f)) / s4;
+                dO[j] = kDevWeight * (1.0f - ed) * invB;
+                lsum += kDevWeight * (ed - 1.0f - dc + (__expf(kDevClamp) - 1.0f) * fmaxf(d - kDevClamp, 0.0f)) / s4;
             } else {
                 float ind = (y < oj) ? 1.0f : 0.0f;
                 dO[j] = (ind - u) * invB;

@@ -24,6 +24,7 @@ constexpr int kMlpIn = 4, kMlpHid = 128, kMlpOut = 6;
 // output 4 is ln E[N_s] (log-deviance loss, clamp of its exponent); the others are quantiles
 constexpr int kMlpOutLogN = 4;
 constexpr float kDevClamp = 4.0f;
+constexpr float kDevWeight = 0.25f;  // weight of the ln N_s loss beside the five pinball losses
 // FP32 master parameter block (offsets in floats)
 constexpr int kPW1 = 0;                                  // W1[4][128]   (in, out)
 constexpr int kPB1 = kPW1 + kMlpIn * kMlpHid;            // b1[128]

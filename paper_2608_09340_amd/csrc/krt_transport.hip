@@ -345,11 +345,10 @@ __global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
                     mlp = true;
                 }
             }
-            // once the packet pool is exhausted (some lane of this wave is done) a
-            // single asking lane suffices: the wave lives only as long as its
-            // slowest packet, and a call cuts that packet's walk
+            // once the packet pool is exhausted (some lane of this wave is done) the
+            // wave lives only as long as its slowest packet: fewer asking lanes suffice
             const uint64_t wm = __ballot(mlp);
-            const int need_lanes = (__ballot(done) != 0ull) ? 1 : P.esc_min_lanes;
+            const int need_lanes = (__ballot(done) != 0ull) ? P.esc_tail_lanes : P.esc_min_lanes;
             if (__popcll(wm) >= need_lanes) {
                 uint4 C = philox(make_uint4(ev, (uint32_t)pid, (uint32_t)(pid >> 32), 2u), P.key0, P.key1);
                 float in[4];
