@@ -203,22 +203,28 @@ int krt_levels_update(krt_ctx *ctx, const krt_levels_desc *desc,
                       const float *jbar_dev /* [nl-1][ncell], NULL = no radiation */);
 
 /* ------------------------------------------------------- learned escape --- */
-/* A small network (4 -> 3 x 128 SiLU -> 6, BF16 weights and activations, FP32
+/* A small network (4 -> 3 x 128 SiLU -> 8, BF16 weights and activations, FP32
  * accumulation on MFMA) proposes, at a scattering inside a cell whose
  * line-centre depth over the distance R to the nearest cell face is
- * tau_R = k0 R >= 1e2, where a photon leaves the cube of half-width R centred
- * there: exit frequency, exit point on the exit face, exit direction, and the
- * number of scatterings it skipped.  The paper itself propagates every photon
- * through the full optical depth (Sec. 2.3.2, Sec. 4.1); this proposal is the
- * accelerated alternative it points to for extreme depths, and the plain
- * random walk remains the fallback (below threshold, |x| > 8, a outside
- * [1e-4, 1e-2]).  Inputs (log10 tau_R, log10 a, x_in, u); outputs 0-3 and 5
- * are conditional quantiles at level u of (x_out, s, t, mu, -, ln <x^2>)
- * trained with the pinball loss, output 4 is ln E[N_s | tau_R, a, x_in]
- * trained with the log-deviance e^d - 1 - d, d = ln N_s - output (so the
- * skipped scatterings are deposited with their expected count), all on
- * single-cell escapes run by the plain transport arithmetic.  Parameters: kNParams = 34438 FP32 master values plus
- * 12 target normalisation constants (mean[6], scale[6]).
+ * tau_R = k0 R >= esc_tau_min, where a photon leaves the cube of half-width R
+ * centred there: exit frequency, exit point on the exit face, exit direction,
+ * and the expected number of scatterings it skipped.  The paper itself
+ * propagates every photon through the full optical depth (Sec. 2.3.2,
+ * Sec. 4.1); this proposal is the accelerated alternative it points to for
+ * extreme depths, and the plain random walk remains the fallback (below
+ * threshold, |x| > 8, a outside [1e-4, 1e-2]); above tau_R = 1e5 the cube is
+ * shrunk to that depth.
+ * Inputs (log10 tau_R, log10 a, x_in, u).  Outputs: 0 quantile at level u of
+ * x_out given x_out >= 0; 1, 2 quantiles of the exit point (s, t); 3 of the
+ * exit cosine mu; 4 ln E[N_s | tau_R, a, x_in]; 5 quantile of ln <x^2>;
+ * 6 logit P(x_out >= 0); 7 quantile of -x_out given x_out < 0.  The bimodal
+ * exit frequency is drawn as a two-component mixture: side from output 6,
+ * magnitude from output 0 or 7.  Losses: pinball for the quantiles (0 and 7
+ * only on records of their side), log-deviance e^d - 1 - d (d = ln N_s -
+ * output) for output 4, logistic for output 6; trained on single-cell
+ * escapes run by the plain transport arithmetic.  Parameters: kNParams =
+ * 34696 FP32 master values plus 16 target normalisation constants
+ * (mean[8], scale[8]).
  *
  * krt_escape_init: He-uniform parameters from Philox(seed), Adam state zeroed.
  * krt_escape_record: n single-cell escapes for line `line`, log10 tau_R uniform
@@ -226,14 +232,14 @@ int krt_levels_update(krt_ctx *ctx, const krt_levels_desc *desc,
  *   samples_dev [n][10] FP32: (log10 tau_R, log10 a, x_in, x_out, s, t, mu,
  *   ln N_s, ln <x^2>, valid).
  * krt_escape_fit_norm: target mean / scale from valid records.
- * krt_escape_grad: gradient of the mean pinball loss over the batch given by
- *   idx_dev [batch] (record indices) and u_dev [batch]; grad_out_dev [34438],
+ * krt_escape_grad: gradient of the mean loss over the batch given by
+ *   idx_dev [batch] (record indices) and u_dev [batch]; grad_out_dev [34696],
  *   loss_out_dev [1] (may be NULL).
  * krt_escape_train: `steps` Adam steps (lr, betas 0.9/0.999) on random batches
  *   (Philox(seed)); loss_hist_dev [steps] or NULL.
- * krt_escape_get_weights / put_weights: [34438 + 12] FP32 device buffers.
+ * krt_escape_get_weights / put_weights: [34696 + 16] FP32 device buffers.
  * krt_escape_forward: in_dev [n][4] raw (log10 tau_R, log10 a, x_in, u) ->
- *   out_dev [n][6] in physical units.
+ *   out_dev [n][8] in physical units (output 6 as a logit).
  * Errors: KRT_EINVAL (sizes, ranges), KRT_ESTATE (no init / no tables). */
 int krt_escape_init(krt_ctx *ctx, uint64_t seed);
 int krt_escape_record(krt_ctx *ctx, int32_t line, uint64_t n, uint64_t seed, uint64_t offset,

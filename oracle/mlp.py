@@ -1,16 +1,31 @@
 """FP64 CPU reference of the escape network -- TEST INFRASTRUCTURE.
 
 Same parameter layout as the GPU (one flat vector): W1[4][128], b1[128],
-W2[128][128], b2, W3[128][128], b3, W4[128][6], b4[6]; activations SiLU;
-outputs 0-3 and 5 are conditional quantiles trained with the pinball loss
-rho_u(y - o) = (y - o)(u - 1{y < o}); output 4 is ln E[N_s | condition],
-trained with the weighted, scaled log-deviance w f(d) / s4 (w = 1/4),
-d = s4 (y4 - o4), where
+W2[128][128], b2, W3[128][128], b3, W4[128][8], b4[8]; activations SiLU.
+Inputs are normalised as ((log10 tau - 3.5)/1.5, log10 a + 3, x_in / 4, 2u - 1).
+
+Outputs (index: meaning, loss), for a record with exit frequency x:
+  0: quantile at level u of x given x >= 0     pinball, only records with x >= 0
+  1: quantile of s (exit point, first axis)      pinball
+  2: quantile of t (exit point, second axis)     pinball
+  3: quantile of mu (exit cosine to the normal)  pinball
+  4: ln E[N_s | condition]                       weighted log-deviance (below)
+  5: quantile of ln <x^2> over the scatterings   pinball
+  6: logit P(x >= 0 | condition)                 logistic (Bernoulli) loss
+  7: quantile of -x given x < 0                  pinball, only records with x < 0
+The exit frequency is bimodal (blue and red peaks with an empty core between
+them), so one smooth quantile function of the signed x would fill the gap;
+the two one-sided quantiles and the side probability form a two-component
+mixture whose components are each unimodal.
+
+Pinball loss: rho_u(y - o) = (y - o)(u - 1{y < o}).  Output 4 uses the scaled
+log-deviance w f(d) / s4 with w = 1/4, d = s4 (y4 - o4) and
 f(d) = e^d - 1 - d (continued linearly beyond d = 4, so a rare very long
-escape cannot dominate a batch), whose minimiser satisfies E[e^(y - m)] = 1,
-i.e. e^m = E[N_s].  Losses are averaged over the batch and summed over the
-outputs.  Inputs are normalised as ((log10 tau - 3.5)/1.5, log10 a + 3,
-x_in / 4, 2u - 1).  The manual backward pass is pinned by finite differences
+escape cannot dominate a batch); its minimiser satisfies E[e^(y - m)] = 1,
+i.e. e^m = E[N_s].  Output 6 uses softplus(o) - b o with b = 1{x >= 0}, whose
+minimiser is the logit of P(x >= 0).  Every loss is averaged over the whole
+batch (masked samples contribute zero) and the outputs' losses are summed.
+The manual backward pass is pinned by finite differences
 (tests/test_oracle_mlp.py).  ``bf16=True`` rounds weights and activations to
 bfloat16 (round to nearest even) where the GPU kernels do, to separate the
 arithmetic error of the kernels from the storage format.
@@ -19,10 +34,15 @@ from __future__ import annotations
 
 import numpy as np
 
-NIN, NH, NOUT = 4, 128, 6
+NIN, NH, NOUT = 4, 128, 8
 SHAPES = [("W1", (NIN, NH)), ("b1", (NH,)), ("W2", (NH, NH)), ("b2", (NH,)),
           ("W3", (NH, NH)), ("b3", (NH,)), ("W4", (NH, NOUT)), ("b4", (NOUT,))]
 NPARAMS = sum(int(np.prod(s)) for _, s in SHAPES)
+NNORM = 2 * NOUT
+O_XPOS, O_S, O_T, O_MU, O_LOGN, O_LOGX2, O_LOGIT, O_XNEG = range(NOUT)
+N_OUT = O_LOGN
+DEV_CLAMP = 4.0
+DEV_WEIGHT = 0.25
 
 
 def unpack(p):
@@ -76,11 +96,6 @@ def forward(p, X, bf=False):
     return out, cache, W
 
 
-DEV_CLAMP = 4.0
-DEV_WEIGHT = 0.25
-N_OUT = 4  # index of the ln E[N_s] output
-
-
 def deviance(d):
     """f(d) = e^d - 1 - d for d <= 4, its tangent continuation beyond; and f'(d)."""
     d = np.asarray(d, dtype=np.float64)
@@ -89,23 +104,31 @@ def deviance(d):
     return f, np.exp(dc) - 1.0
 
 
-def pinball(out, Y, u, s4=1.0):
+def losses(out, Y, u, s4=1.0):
     """Mean over the batch of the summed per-output losses, and dL/dout.
-    Outputs other than 4: pinball at level u.  Output 4: w f(s4 (y - o)) / s4."""
+    Y: normalised targets (NaN where an output is masked for that sample);
+    Y[:, 6] is the side label b in {0, 1}."""
     B = out.shape[0]
-    ind = (Y < out).astype(np.float64)
-    lk = (Y - out) * (u[:, None] - ind)
+    live = ~np.isnan(Y)
+    Yz = np.where(live, Y, 0.0)
+    ind = (Yz < out).astype(np.float64)
+    lk = (Yz - out) * (u[:, None] - ind)
     dout = (ind - u[:, None]) / B
-    f, fp = deviance(s4 * (Y[:, N_OUT] - out[:, N_OUT]))
-    lk[:, N_OUT] = DEV_WEIGHT * f / s4
-    dout[:, N_OUT] = -DEV_WEIGHT * fp / B
+    f, fp = deviance(s4 * (Yz[:, O_LOGN] - out[:, O_LOGN]))
+    lk[:, O_LOGN] = DEV_WEIGHT * f / s4
+    dout[:, O_LOGN] = -DEV_WEIGHT * fp / B
+    o6, b = out[:, O_LOGIT], Yz[:, O_LOGIT]
+    lk[:, O_LOGIT] = np.logaddexp(0.0, o6) - b * o6
+    dout[:, O_LOGIT] = (1.0 / (1.0 + np.exp(-o6)) - b) / B
+    lk = np.where(live, lk, 0.0)
+    dout = np.where(live, dout, 0.0)
     return float(np.sum(lk) / B), dout
 
 
 def loss_and_grad(p, X, Y, u, bf=False, s4=1.0):
-    """s4: the target scale of output 4 (norm[6 + 4])."""
+    """s4: the target scale of output 4 (norm[NOUT + 4])."""
     out, c, W = forward(p, X, bf)
-    loss, d = pinball(out, Y, u, s4)
+    loss, d = losses(out, Y, u, s4)
     g = {"W4": c["h3"].T @ d, "b4": d.sum(0)}
     dh = d @ W["W4"].T
     for i in (3, 2, 1):
@@ -116,7 +139,20 @@ def loss_and_grad(p, X, Y, u, bf=False, s4=1.0):
     return loss, pack(g)
 
 
+def raw_targets(rec):
+    """Records [.., x_out, s, t, mu, lnNs, lnx2, valid] -> per-output physical
+    targets [B, 8] (NaN where masked; column 6 is the side label)."""
+    x = rec[:, 3].astype(np.float64)
+    pos = x >= 0.0
+    y = np.full((rec.shape[0], NOUT), np.nan)
+    y[:, O_XPOS] = np.where(pos, x, np.nan)
+    y[:, O_S:O_LOGX2 + 1] = rec[:, 4:9]
+    y[:, O_LOGIT] = pos.astype(np.float64)
+    y[:, O_XNEG] = np.where(pos, np.nan, -x)
+    return y
+
+
 def targets_normalised(rec, norm):
-    """Records [.., x_out, s, t, mu, lnNs, lnx2, valid] -> normalised targets."""
-    y = rec[:, 3:9].astype(np.float64)
-    return (y - norm[:NOUT]) / norm[NOUT:]
+    """Normalised targets: (raw - mean) / scale; the side label stays 0/1
+    (its normalisation is fixed at mean 0, scale 1)."""
+    return (raw_targets(rec) - norm[:NOUT]) / norm[NOUT:]

@@ -222,7 +222,8 @@ __device__ __forceinline__ v4i16 xin_operand(const float in[4], int lane) {
 
 // ---------------------------------------------------------- gradient ---
 // One wave per 16-sample block.  grad += d(mean loss)/d(params); loss += sum.
-// Outputs other than ln N_s: pinball loss at level u; ln N_s: log-deviance.
+// Quantile outputs: pinball loss at level u (the two one-sided exit-frequency
+// quantiles only on records of their side); ln N_s: log-deviance; side: logistic.
 __global__ void __launch_bounds__(256) mlp_grad_kernel(const unsigned char *blob, const float *rec,
                                                        const int32_t *idx, const float *uq, int batch,
                                                        float *grad, float *loss) {
@@ -245,29 +246,46 @@ __global__ void __launch_bounds__(256) mlp_grad_kernel(const unsigned char *blob
     v4i16 xb = xin_operand(in, lane);
     v4f32 z1[8], z2[8], z3[8];
     v4f32 o = mlp_forward_block(blob, bias, xb, lane, z1, z2, z3);
-    // pinball loss and its gradient for outputs k = 4g + j
+    // per-output losses and their gradients for outputs k = 4g + j
     const float invB = 1.0f / (float)batch;
+    const float xo = r[3];
     float dO[4], lsum = 0.0f;
     for (int j = 0; j < 4; ++j) {
         int k = 4 * g + j;
         float oj = (j == 0) ? o.x : (j == 1) ? o.y : (j == 2) ? o.z : o.w;
         dO[j] = 0.0f;
-        if (k < kMlpOut && live) {
-            float y = (r[3 + k] - norm[k]) / norm[kMlpOut + k];
-            if (k == kMlpOutLogN) {
-                // ln E[N_s]: weighted, scaled log-deviance w f(d) / s4, d = s4 (y - o),
-                // f(d) = e^d - 1 - d, continued linearly beyond d = kDevClamp
-                const float s4 = norm[kMlpOut + k];
-                const float d = s4 * (y - oj);
-                const float dc = fminf(d, kDevClamp);
-                const float ed = __expf(dc);
-                dO[j] = kDevWeight * (1.0f - ed) * invB;
-                lsum += kDevWeight * (ed - 1.0f - dc + (__expf(kDevClamp) - 1.0f) * fmaxf(d - kDevClamp, 0.0f)) / s4;
-            } else {
-                float ind = (y < oj) ? 1.0f : 0.0f;
-                dO[j] = (ind - u) * invB;
-                lsum += (y - oj) * (u - ind);
-            }
+        if (k >= kMlpOut || !live) continue;
+        if (k == kOutLogit) {
+            // side of the exit frequency: logistic loss, label 1{x_out >= 0}
+            const float b = (xo >= 0.0f) ? 1.0f : 0.0f;
+            dO[j] = (sigmoid_f(oj) - b) * invB;
+            lsum += fmaxf(oj, 0.0f) + __logf(1.0f + __expf(-fabsf(oj))) - b * oj;
+            continue;
+        }
+        float raw;
+        if (k == kOutXPos) {
+            if (xo < 0.0f) continue;  // one-sided: only records on this side
+            raw = xo;
+        } else if (k == kOutXNeg) {
+            if (xo >= 0.0f) continue;
+            raw = -xo;
+        } else {
+            raw = r[3 + k];
+        }
+        const float y = (raw - norm[k]) / norm[kMlpOut + k];
+        if (k == kOutLogN) {
+            // ln E[N_s]: weighted, scaled log-deviance w f(d) / s4, d = s4 (y - o),
+            // f(d) = e^d - 1 - d, continued linearly beyond d = kDevClamp
+            const float s4 = norm[kMlpOut + k];
+            const float d = s4 * (y - oj);
+            const float dc = fminf(d, kDevClamp);
+            const float ed = __expf(dc);
+            dO[j] = kDevWeight * (1.0f - ed) * invB;
+            lsum += kDevWeight * (ed - 1.0f - dc + (__expf(kDevClamp) - 1.0f) * fmaxf(d - kDevClamp, 0.0f)) / s4;
+        } else {
+            const float ind = (y < oj) ? 1.0f : 0.0f;
+            dO[j] = (ind - u) * invB;
+            lsum += (y - oj) * (u - ind);
         }
     }
     // loss: reduce over the wave
@@ -391,19 +409,26 @@ __global__ void mlp_batch_kernel(int64_t n, uint32_t k0, uint32_t k1, uint32_t s
     uq[i] = u01(r.y);
 }
 
-// Normalisation of the 6 targets: mean and standard deviation over records
-// (FP64 accumulation, one block of 256 threads per target).
+// Normalisation of the 8 targets: mean and standard deviation over the valid
+// records of each output's own target (the one-sided exit frequencies over the
+// records of their side; the side logit keeps mean 0, scale 1), FP64
+// accumulation, one block of 256 threads per output.
 __global__ void mlp_norm_kernel(const float *rec, int64_t n, float *norm) {
-    __shared__ double s1[256], s2[256];
-    int k = blockIdx.x;
-    __shared__ double s0[256];
+    __shared__ double s0[256], s1[256], s2[256];
+    const int k = blockIdx.x;
     double a = 0.0, b = 0.0, c = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-        if (rec[(int64_t)kRec * i + 9] < 0.5f) continue;
-        double y = rec[(int64_t)kRec * i + 3 + k];
-        a += y;
-        b += y * y;
-        c += 1.0;
+    if (k != kOutLogit) {
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+            const float *r = rec + (int64_t)kRec * i;
+            if (r[9] < 0.5f) continue;
+            double y;
+            if (k == kOutXPos) { if (r[3] < 0.0f) continue; y = r[3]; }
+            else if (k == kOutXNeg) { if (r[3] >= 0.0f) continue; y = -r[3]; }
+            else y = r[3 + k];
+            a += y;
+            b += y * y;
+            c += 1.0;
+        }
     }
     s1[threadIdx.x] = a;
     s2[threadIdx.x] = b;
@@ -418,11 +443,15 @@ __global__ void mlp_norm_kernel(const float *rec, int64_t n, float *norm) {
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        double cnt = s0[0] > 0.0 ? s0[0] : 1.0;
-        double mean = s1[0] / cnt;
-        double var = s2[0] / cnt - mean * mean;
-        norm[k] = (float)mean;
-        norm[kMlpOut + k] = (float)sqrt(var > 1e-12 ? var : 1e-12);
+        if (k == kOutLogit || s0[0] < 1.0) {
+            norm[k] = 0.0f;
+            norm[kMlpOut + k] = 1.0f;
+        } else {
+            const double mean = s1[0] / s0[0];
+            const double var = s2[0] / s0[0] - mean * mean;
+            norm[k] = (float)mean;
+            norm[kMlpOut + k] = (float)sqrt(var > 1e-12 ? var : 1e-12);
+        }
     }
 }
 
@@ -446,7 +475,7 @@ __global__ void __launch_bounds__(256) mlp_forward_kernel(const unsigned char *b
     float v[4] = {o.x, o.y, o.z, o.w};
     for (int j = 0; j < 4; ++j) {
         int k = 4 * g + j;
-        if (k < kMlpOut) out[6 * si + k] = v[j] * norm[kMlpOut + k] + norm[k];
+        if (k < kMlpOut) out[kMlpOut * si + k] = v[j] * norm[kMlpOut + k] + norm[k];
     }
 }
 

@@ -2,13 +2,18 @@
 // forward pass shared by the transport kernel (inference) and the training
 // kernels.  Not part of the C ABI.
 //
-// Network: 4 inputs -> 128 -> 128 -> 128 (SiLU) -> 6 outputs.
+// Network: 4 inputs -> 128 -> 128 -> 128 (SiLU) -> 8 outputs.
 // Inputs  : ((log10 tau_R - 3.5)/1.5, log10 a + 3, x_in / 4, 2u - 1), u the
 //           quantile level.
-// Outputs : conditional quantiles at level u (normalised) of the exit
-//           frequency x_out, the exit point (s, t) on the exit face, the cosine
-//           mu of the exit direction to the face normal, ln N_s (scatterings
-//           inside the cube) and ln <x^2> over those scatterings.
+// Outputs (normalised): 0 quantile at level u of x_out given x_out >= 0;
+//           1, 2 quantiles of the exit point (s, t) on the exit face; 3 of the
+//           cosine mu of the exit direction to the face normal; 4 ln E[N_s]
+//           (scatterings inside the cube); 5 quantile of ln <x^2> over those
+//           scatterings; 6 logit P(x_out >= 0); 7 quantile of -x_out given
+//           x_out < 0.  The exit frequency is bimodal, so it is drawn as a
+//           two-component mixture (side, then a one-sided quantile): a single
+//           smooth quantile function of the signed x_out would fill the empty
+//           line core between the peaks.
 //
 // The layers are evaluated transposed, H^T_{l+1} = SiLU(W_l^T H^T_l + b_l),
 // with v_mfma_f32_16x16x16_bf16 on 16-sample blocks: the accumulator layout of
@@ -20,11 +25,13 @@
 
 namespace krt {
 
-constexpr int kMlpIn = 4, kMlpHid = 128, kMlpOut = 6;
-// output 4 is ln E[N_s] (log-deviance loss, clamp of its exponent); the others are quantiles
-constexpr int kMlpOutLogN = 4;
+constexpr int kMlpIn = 4, kMlpHid = 128, kMlpOut = 8;
+// output indices
+constexpr int kOutXPos = 0, kOutS = 1, kOutT = 2, kOutMu = 3, kOutLogN = 4, kOutLogX2 = 5, kOutLogit = 6,
+              kOutXNeg = 7;
+// ln E[N_s]: weighted log-deviance loss with its exponent clamped
 constexpr float kDevClamp = 4.0f;
-constexpr float kDevWeight = 0.25f;  // weight of the ln N_s loss beside the five pinball losses
+constexpr float kDevWeight = 0.25f;
 // FP32 master parameter block (offsets in floats)
 constexpr int kPW1 = 0;                                  // W1[4][128]   (in, out)
 constexpr int kPB1 = kPW1 + kMlpIn * kMlpHid;            // b1[128]
@@ -32,14 +39,15 @@ constexpr int kPW2 = kPB1 + kMlpHid;                     // W2[128][128]
 constexpr int kPB2 = kPW2 + kMlpHid * kMlpHid;
 constexpr int kPW3 = kPB2 + kMlpHid;
 constexpr int kPB3 = kPW3 + kMlpHid * kMlpHid;
-constexpr int kPW4 = kPB3 + kMlpHid;                     // W4[128][6]
-constexpr int kPB4 = kPW4 + kMlpHid * kMlpOut;           // b4[6]
-constexpr int kNParams = kPB4 + kMlpOut;                 // 34438
+constexpr int kPW4 = kPB3 + kMlpHid;                     // W4[128][8]
+constexpr int kPB4 = kPW4 + kMlpHid * kMlpOut;           // b4[8]
+constexpr int kNParams = kPB4 + kMlpOut;                 // 34696
 // target normalisation: y_norm = (y - mean) / scale, stored after the params
+// (output 6, the side logit, has mean 0 and scale 1)
 constexpr int kNNorm = 2 * kMlpOut;
 
 // Packed BF16 A-operand tiles (16x16, 512 B each: 64 lanes x 4 bf16).
-// Forward (W^T, rows = out-features): L1 8 tiles (K padded 4 -> 16), L2 64, L3 64, L4 8 (rows padded 6 -> 16).
+// Forward (W^T, rows = out-features): L1 8 tiles (K padded 4 -> 16), L2 64, L3 64, L4 8 (rows padded 8 -> 16).
 constexpr int kTilesL1 = 8, kTilesL2 = 64, kTilesL3 = 64, kTilesL4 = 8;
 constexpr int kTileFwdL1 = 0, kTileFwdL2 = kTilesL1, kTileFwdL3 = kTileFwdL2 + kTilesL2,
               kTileFwdL4 = kTileFwdL3 + kTilesL3, kTilesFwd = kTileFwdL4 + kTilesL4;   // 144

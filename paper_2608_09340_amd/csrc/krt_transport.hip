@@ -362,12 +362,18 @@ __global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
                 if (mlp) {
                     // ---- exit from the cube centred here (half-width Rcube) ----
                     const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
-                    float xo = mo[0] * mnorm[kMlpOut + 0] + mnorm[0];
-                    float tt = fminf(fmaxf(mo[2] * mnorm[kMlpOut + 2] + mnorm[2], -1.0f), 1.0f);
-                    float lns = mo[4] * mnorm[kMlpOut + 4] + mnorm[4];
-                    float lx2 = mo[5] * mnorm[kMlpOut + 5] + mnorm[5];
-                    float ss = fminf(fmaxf(mo2[1] * mnorm[kMlpOut + 1] + mnorm[1], -1.0f), 1.0f);
-                    float mu = fminf(fmaxf(mo2[3] * mnorm[kMlpOut + 3] + mnorm[3], 1e-3f), 1.0f);
+                    // exit frequency: side from the learned P(x_out >= 0) and a word of
+                    // purpose 3, magnitude from that side's quantile at level u1
+                    uint4 D = philox(make_uint4(ev, plo, phi, 3u), P.key0, P.key1);
+                    const bool pos = u01(D.x) < sigmoid_f(mo[kOutLogit]);
+                    const int ko = pos ? kOutXPos : kOutXNeg;
+                    const float mag = fmaxf(mo[ko] * mnorm[kMlpOut + ko] + mnorm[ko], 0.0f);
+                    float xo = pos ? mag : -mag;
+                    float tt = fminf(fmaxf(mo[kOutT] * mnorm[kMlpOut + kOutT] + mnorm[kOutT], -1.0f), 1.0f);
+                    float lns = mo[kOutLogN] * mnorm[kMlpOut + kOutLogN] + mnorm[kOutLogN];
+                    float lx2 = mo[kOutLogX2] * mnorm[kMlpOut + kOutLogX2] + mnorm[kOutLogX2];
+                    float ss = fminf(fmaxf(mo2[kOutS] * mnorm[kMlpOut + kOutS] + mnorm[kOutS], -1.0f), 1.0f);
+                    float mu = fminf(fmaxf(mo2[kOutMu] * mnorm[kMlpOut + kOutMu] + mnorm[kOutMu], 1e-3f), 1.0f);
                     // symmetry of the cube: face, swap of (s, t), signs
                     uint32_t bits = C.z;
                     int face = (int)__umulhi(bits, 6u);

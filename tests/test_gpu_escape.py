@@ -14,7 +14,7 @@ from paper_2608_09340_amd import workloads as W
 from stats_util import l1_shape
 
 pytestmark = pytest.mark.gpu
-NP, NN = 34438, 12
+NP, NN, NO = mlp.NPARAMS, mlp.NNORM, mlp.NOUT
 
 
 def _put(ctx, p, norm):
@@ -35,18 +35,18 @@ def _rand_params(seed):
 def test_mfma_forward_vs_fp64(gpu_ctx):
     import torch
     p = _rand_params(3)
-    norm = np.array([0.5, 0, 0, 0.7, 6, 0.1, 2.0, 0.5, 0.5, 0.2, 1.5, 1.0])
+    norm = np.array([2.5, 0, 0, 0.7, 6, 0.1, 0.0, 2.4, 1.5, 0.5, 0.5, 0.2, 1.5, 1.0, 1.0, 1.4])
     _put(gpu_ctx, p, norm)
     rng = np.random.default_rng(4)
     n = 3000
     raw = np.stack([rng.uniform(2, 5, n), rng.uniform(-4, -2, n), rng.uniform(-8, 8, n), rng.uniform(0, 1, n)], 1)
-    out = torch.zeros((n, 6), dtype=torch.float32, device="cuda")
+    out = torch.zeros((n, NO), dtype=torch.float32, device="cuda")
     gpu_ctx.krt_escape_forward(torch.from_numpy(raw.astype(np.float32)).cuda(), out)
     g = out.cpu().numpy().astype(np.float64)
     X = mlp.inputs(raw[:, 0], raw[:, 1], raw[:, 2], raw[:, 3])
     for bf, tol in ((True, 2e-2), (False, 6e-2)):
         o, _, _ = mlp.forward(p, X, bf=bf)
-        ref = o * norm[6:] + norm[:6]
+        ref = o * norm[NO:] + norm[:NO]
         err = np.abs(g - ref) / (np.abs(ref).std(axis=0) + 1e-9)
         assert np.max(err) < tol, (bf, np.max(err, axis=0))
 
@@ -56,7 +56,7 @@ def test_mfma_gradient_vs_fp64(gpu_ctx):
     reference: cosine >= 0.999 and relative L2 <= 2e-2 per tensor."""
     import torch
     p = _rand_params(5)
-    norm = np.array([0.1, 0, 0, 0.7, 6, 0.1, 2.0, 0.5, 0.5, 0.2, 1.5, 1.0])
+    norm = np.array([2.5, 0, 0, 0.7, 6, 0.1, 0.0, 2.4, 1.5, 0.5, 0.5, 0.2, 1.5, 1.0, 1.0, 1.4])
     _put(gpu_ctx, p, norm)
     rng = np.random.default_rng(6)
     nrec, B = 5000, 1024
@@ -64,7 +64,8 @@ def test_mfma_gradient_vs_fp64(gpu_ctx):
     rec[:, 0] = rng.uniform(2, 5, nrec)
     rec[:, 1] = rng.uniform(-4, -2, nrec)
     rec[:, 2] = rng.uniform(-8, 8, nrec)
-    rec[:, 3:9] = norm[:6] + norm[6:] * rng.normal(0, 1, (nrec, 6))
+    rec[:, 3] = rng.choice([-1.0, 1.0], nrec) * np.abs(2.5 + 1.5 * rng.normal(0, 1, nrec))
+    rec[:, 4:9] = norm[1:6] + norm[NO + 1:NO + 6] * rng.normal(0, 1, (nrec, 5))
     rec[:, 9] = 1.0
     idx = rng.integers(0, nrec, B).astype(np.int32)
     u = rng.uniform(0, 1, B)
@@ -77,7 +78,7 @@ def test_mfma_gradient_vs_fp64(gpu_ctx):
     X = mlp.inputs(R[:, 0], R[:, 1], R[:, 2], u)
     Y = mlp.targets_normalised(R, norm)
     for bf in (True, False):
-        l_ref, g_ref = mlp.loss_and_grad(p, X, Y, u, bf=bf, s4=norm[6 + mlp.N_OUT])
+        l_ref, g_ref = mlp.loss_and_grad(p, X, Y, u, bf=bf, s4=norm[NO + mlp.O_LOGN])
         o = 0
         for name, shp in mlp.SHAPES:
             k = int(np.prod(shp))
@@ -148,12 +149,23 @@ def test_learned_samples_vs_plain(gpu_ctx, trained, tau, xin):
     plain = out.cpu().numpy().astype(np.float64)
     rng = np.random.default_rng(13)
     raw = np.stack([np.full(n, lt), np.full(n, -3.0), np.full(n, xin), rng.uniform(0, 1, n)], 1).astype(np.float32)
-    pred = torch.zeros((n, 6), dtype=torch.float32, device="cuda")
+    pred = torch.zeros((n, NO), dtype=torch.float32, device="cuda")
     gpu_ctx.krt_escape_forward(torch.from_numpy(raw).cuda(), pred)
     m = pred.cpu().numpy().astype(np.float64)
-    ks = {k: stats.ks_2samp(m[:, k], plain[:, col]).statistic for k, col in ((0, 3), (1, 4), (2, 5), (3, 6))}
-    print(f"tau={tau} x_in={xin} KS x_out {ks[0]:.4f} s {ks[1]:.4f} t {ks[2]:.4f} mu {ks[3]:.4f}")
+    # exit frequency from the mixture head: side, then that side's quantile
+    pos = rng.uniform(0, 1, n) < 1.0 / (1.0 + np.exp(-m[:, mlp.O_LOGIT]))
+    xo = np.where(pos, np.maximum(m[:, mlp.O_XPOS], 0.0), -np.maximum(m[:, mlp.O_XNEG], 0.0))
+    ks = {0: stats.ks_2samp(xo, plain[:, 3]).statistic}
+    ks.update({k: stats.ks_2samp(m[:, k], plain[:, col]).statistic for k, col in ((1, 4), (2, 5), (3, 6))})
+    # histogram L1 of the exit frequency (bins of 0.25), against the plain-vs-plain floor
+    edges = np.linspace(-12, 12, 97)
+    hp = np.histogram(plain[:, 3], edges)[0]
+    hm = np.histogram(xo, edges)[0]
+    l1 = np.abs(hp / n - hm / n).sum()
+    print(f"tau={tau} x_in={xin} KS x_out {ks[0]:.4f} s {ks[1]:.4f} t {ks[2]:.4f} mu {ks[3]:.4f} "
+          f"x_out L1 {l1:.4f} P(x>=0) learned {pos.mean():.3f} plain {(plain[:, 3] >= 0).mean():.3f}")
     assert ks[0] < 0.06 and ks[3] < 0.06, (tau, xin, ks)
+    assert l1 < 0.1, l1
     # output 4 is ln E[N_s]: against the log of the plain mean count (5%)
     ln_mean = np.log(np.mean(np.exp(plain[:, 7])))
     print(f"   ln E[N_s]: learned {m[:, 4].mean():.4f} (spread {m[:, 4].std():.1e}) plain {ln_mean:.4f}")

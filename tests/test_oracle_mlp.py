@@ -1,6 +1,7 @@
 """Pins of the FP64 reference network used to check the GPU training kernels:
-its manual backward pass against central finite differences of its own loss,
-and the pinball loss against its definition."""
+its manual backward pass against central finite differences of its own loss
+(with masked one-sided outputs and the side label), and each loss against the
+statistic it must estimate (quantile, log of the mean, logit)."""
 from __future__ import annotations
 
 import numpy as np
@@ -14,6 +15,11 @@ def _setup(seed=0, B=64):
     X = rng.normal(0, 1, (B, mlp.NIN))
     Y = rng.normal(0, 1, (B, mlp.NOUT))
     u = rng.uniform(0, 1, B)
+    # side label and one-sided masks as the records give them
+    pos = rng.uniform(0, 1, B) < 0.5
+    Y[:, mlp.O_LOGIT] = pos
+    Y[~pos, mlp.O_XPOS] = np.nan
+    Y[pos, mlp.O_XNEG] = np.nan
     return p, X, Y, u
 
 
@@ -56,6 +62,27 @@ def test_deviance_minimiser_is_log_mean():
     m = grid[int(np.argmin(L))]
     assert abs(m - np.log(N.mean())) < 2e-3
     assert abs(m - y.mean()) > 0.3
+
+
+def test_logistic_minimiser_is_logit():
+    """The minimiser of the mean logistic loss over labels b ~ Bernoulli(q) is logit(q)."""
+    rng = np.random.default_rng(5)
+    b = (rng.uniform(0, 1, 100001) < 0.3).astype(float)
+    grid = np.linspace(-3, 3, 6001)
+    L = [np.mean(np.logaddexp(0.0, o) - b * o) for o in grid]
+    o = grid[int(np.argmin(L))]
+    assert abs(o - np.log(b.mean() / (1 - b.mean()))) < 2e-3
+
+
+def test_raw_targets_masks():
+    rec = np.zeros((3, 10))
+    rec[:, 3] = [1.5, -2.0, 0.0]
+    rec[:, 4:9] = np.arange(15).reshape(3, 5)
+    y = mlp.raw_targets(rec)
+    assert y[0, mlp.O_XPOS] == 1.5 and np.isnan(y[0, mlp.O_XNEG]) and y[0, mlp.O_LOGIT] == 1
+    assert np.isnan(y[1, mlp.O_XPOS]) and y[1, mlp.O_XNEG] == 2.0 and y[1, mlp.O_LOGIT] == 0
+    assert y[2, mlp.O_XPOS] == 0.0 and y[2, mlp.O_LOGIT] == 1
+    assert np.all(y[:, 1:6] == rec[:, 4:9])
 
 
 def test_bf16_rounding():
