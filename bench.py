@@ -85,6 +85,65 @@ def cpu_baseline(prob, seconds_target=15.0):
             "packets_per_s": n / dt}
 
 
+def _agg_blocks(em, n, b=8):
+    nch = em.shape[1]
+    f = n // b
+    return em.reshape(b, f, b, f, b, f, nch).sum(axis=(1, 3, 5)).reshape(-1)
+
+
+def learned_escape_leg(ctx, n=128, packets=10_000_000, tau_min=100.0):
+    """Turbulent cloud rescaled for the learned escape (n^3, 30% of cells with
+    line-centre depth >= 1e2): train the escape network on GPU-recorded
+    single-cell escapes, then run the same packets with the plain random walk
+    (twice, for the noise floor) and with the learned escape.  Reports kernel
+    times, the speedup in scatterings-equivalent per second and the spectrum
+    and emissivity L1 of the learned run against the plain one."""
+    import numpy as np
+    import torch
+    from paper_2608_09340_amd import krt, workloads as W
+    from paper_2608_09340_amd.escape import train_escape
+    t0 = time.perf_counter()
+    krt.Transport(W.slab(10.0, 1e-3, 4), ctx=ctx)  # line tables for a = 1e-3
+    tr = train_escape(ctx, 0, n_records=2_000_000, seed=1, log10_tau=(1.0, 5.0))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    hist = tr["hist"]
+    del tr
+    T = krt.Transport(W.cloud_c4(n=n), ctx=ctx)
+    pa = T.run(packets, seed=0)
+    ms_plain = ctx.krt_last_transport_ms()
+    pb = T.run(packets, seed=0, packet_offset=1 << 40)
+    ms_plain2 = ctx.krt_last_transport_ms()
+    ml = T.run(packets, seed=0, escape_mode=1, esc_tau_min=tau_min)
+    ms_mlp = ctx.krt_last_transport_ms()
+    if pa["rc"] or pb["rc"] or ml["rc"]:
+        raise RuntimeError("learned-escape leg failed")
+
+    def l1(u, v):
+        u = np.asarray(u, dtype=np.float64)
+        v = np.asarray(v, dtype=np.float64)
+        return float(np.abs(u - v).sum() / u.sum())
+
+    ea, eb, em = (_agg_blocks(r["emis_raw"].astype(np.float64), n) for r in (pa, pb, ml))
+    c = ml["counters"]
+    sa = pa["counters"]["scatterings"]
+    return {
+        "workload": f"turbulent cloud {n}^3 (lognormal density sigma_ln=1.5, P(k)~k^-4 velocity rms 3, "
+                    f"70th-percentile cell depth 1e2), a=1e-3, Voigt volume source, {packets} packets",
+        "train_s": t_train, "train_loss_first_last": [float(hist[:5].mean()), float(hist[-200:].mean())],
+        "plain_kernel_ms": ms_plain, "plain_kernel_ms_repeat": ms_plain2, "learned_kernel_ms": ms_mlp,
+        "speedup": ms_plain / ms_mlp,
+        "plain_scatterings_per_s": sa / (ms_plain * 1e-3),
+        "scatterings_equivalent_per_s": sa / (ms_mlp * 1e-3),
+        "learned_run": {"scatterings": c["scatterings"], "network_calls": c["mlp_calls"],
+                        "skipped_scatterings": c["skipped_scatterings"], "esc_tau_min": tau_min},
+        "spectrum_L1": l1(pa["spec_raw"], ml["spec_raw"]), "spectrum_L1_floor": l1(pa["spec_raw"], pb["spec_raw"]),
+        "emissivity_L1": l1(ea, em), "emissivity_L1_floor": l1(ea, eb),
+        "emissivity_total_ratio": float(em.sum() / ea.sum()),
+        "L1_definition": "sum |learned - plain| / sum plain; emissivity aggregated to 8^3 blocks x channels",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +151,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--packets", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-escape", action="store_true", help="skip the learned-escape comparison leg")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (calibrates FETCH_SIZE/WRITE_SIZE)")
@@ -165,6 +225,8 @@ def main():
                      "frac": achieved / PEAK_VALU_TOPS, "traffic": None,
                      "ops_per_scattering": lps},
     }
+    if not args.no_escape:
+        out["learned_escape"] = learned_escape_leg(ctx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)

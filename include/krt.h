@@ -139,6 +139,10 @@ typedef struct {
                                   not bitwise, independent of launch geometry */
     int32_t esc_tail_lanes;    /* as esc_min_lanes once the packet pool is exhausted (0 = 1):
                                   the wave then lives only as long as its slowest packet */
+    int32_t tail_lanes;        /* plain transport: once the pool is exhausted, a wave with at most
+                                  this many live lanes lets its idle lanes precompute the live
+                                  packets' random draws (0 = 16, negative = never); the tallies
+                                  are the same either way */
 } krt_run_opts;
 
 /* Caller-allocated DEVICE buffers.  Raw tallies are int64 fixed point, so their

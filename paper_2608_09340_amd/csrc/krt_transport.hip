@@ -111,6 +111,25 @@ __device__ __attribute__((noinline)) void mlp_eval_wave(const unsigned char *img
 }
 
 // --------------------------------------------------------------- kernel ---
+// Draws of the second random block of an event: the two u_perp components
+// (Box-Muller, N(0, 1/2) each), the cosine g of the scattering angle
+// (isotropic or dipole) with sqrt(1 - g^2), and cos, sin of the azimuth psi.
+struct SDraws {
+    float up1, up2, g, sg, cp, sp;
+};
+
+__device__ __forceinline__ void scatter_draws(uint4 B, bool dipole, SDraws &d) {
+    const float rr = f_sqrt(-f_log(u01(B.x)));
+    const float th = u01(B.y);
+    d.up1 = rr * cos_rev(th);
+    d.up2 = rr * sin_rev(th);
+    d.g = dipole ? dipole_g(u01(B.z)) : 2.0f * u01(B.z) - 1.0f;
+    d.sg = f_sqrt(fmaxf(0.0f, 1.0f - d.g * d.g));
+    const float psi = u01(B.w);
+    d.cp = cos_rev(psi);
+    d.sp = sin_rev(psi);
+}
+
 template <bool kEsc>
 __global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
     extern __shared__ float4 lds4[];
@@ -158,6 +177,136 @@ __global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
     uint32_t *status = P.status;
     const float jscale = P.jbar_scale * kInvSqrtPiF;
 
+    // one flight segment of a live lane: to the next interaction (scat = true,
+    // or destruction) or across one cell face (escape / periodic wrap / next cell)
+    auto flight = [&](float ue, bool &scat, float &xc) {
+        xc = x - (nx * vxc + ny * vyc + nz * vzc);
+        float H = (k0c > 0.0f) ? voigt_lds(T, fabsf(xc)) : 0.0f;
+        float kap = k0c * H;
+        float tx = (nx > 0.0f) ? (1.0f - fx) * P.dx[0] * f_rcp(nx) : ((nx < 0.0f) ? fx * P.dx[0] * f_rcp(-nx) : INFINITY);
+        float ty = (ny > 0.0f) ? (1.0f - fy) * P.dx[1] * f_rcp(ny) : ((ny < 0.0f) ? fy * P.dx[1] * f_rcp(-ny) : INFINITY);
+        float tz = (nz > 0.0f) ? (1.0f - fz) * P.dx[2] * f_rcp(nz) : ((nz < 0.0f) ? fz * P.dx[2] * f_rcp(-nz) : INFINITY);
+        int ax = 0;
+        float dmin = tx;
+        if (ty < dmin) { dmin = ty; ax = 1; }
+        if (tz < dmin) { dmin = tz; ax = 2; }
+        dmin = fmaxf(dmin, 0.0f);
+
+        if (kap > 0.0f && kap * dmin >= tau) {
+            // interaction inside the cell
+            float l = tau * f_rcp(kap);
+            fx = fminf(fmaxf(fmaf(l * nx, P.inv_dx[0], fx), 0.0f), 1.0f);
+            fy = fminf(fmaxf(fmaf(l * ny, P.inv_dx[1], fy), 0.0f), 1.0f);
+            fz = fminf(fmaxf(fmaf(l * nz, P.inv_dx[2], fz), 0.0f), 1.0f);
+            if (P.jbar_raw) jacc += (int64_t)__float2ll_rn(l * H * jscale);
+            if ((P.eps != nullptr) && (ue < epsc)) {
+                c_des += 1;
+                outcome = 2;
+                have = false;
+            } else {
+                scat = true;
+            }
+        } else {
+            // cross the face of axis ax
+            tau -= kap * dmin;
+            if (P.jbar_raw) jacc += (int64_t)__float2ll_rn(dmin * H * jscale);
+            float adv = dmin;
+            if (ax != 0) fx = fminf(fmaxf(fmaf(adv * nx, P.inv_dx[0], fx), 0.0f), 1.0f);
+            if (ax != 1) fy = fminf(fmaxf(fmaf(adv * ny, P.inv_dx[1], fy), 0.0f), 1.0f);
+            if (ax != 2) fz = fminf(fmaxf(fmaf(adv * nz, P.inv_dx[2], fz), 0.0f), 1.0f);
+            c_cross += 1;
+            ncross_pkt += 1;
+            // leaving the cell: flush its register tallies
+            if (P.jbar_raw && jacc != 0) { atomic_add_i64(P.jbar_raw + cell, jacc, status); jacc = 0; }
+            if (P.emis_raw) emis_flush(E, P.emis_raw + (int64_t)cell * P.emis_nch, P.emis_nch, status);
+            bool escaped = false;
+            if (ax == 0) {
+                int st = (nx > 0.0f) ? 1 : -1;
+                ci += st; fx = (st > 0) ? 0.0f : 1.0f;
+                if (ci < 0 || ci >= P.n[0]) { if (P.bc[0]) ci = (ci < 0) ? P.n[0] - 1 : 0; else escaped = true; }
+            } else if (ax == 1) {
+                int st = (ny > 0.0f) ? 1 : -1;
+                cj += st; fy = (st > 0) ? 0.0f : 1.0f;
+                if (cj < 0 || cj >= P.n[1]) { if (P.bc[1]) cj = (cj < 0) ? P.n[1] - 1 : 0; else escaped = true; }
+            } else {
+                int st = (nz > 0.0f) ? 1 : -1;
+                ck += st; fz = (st > 0) ? 0.0f : 1.0f;
+                if (ck < 0 || ck >= P.n[2]) { if (P.bc[2]) ck = (ck < 0) ? P.n[2] - 1 : 0; else escaped = true; }
+            }
+            if (escaped) {
+                c_esc += 1;
+                int b = bin_index(x, sedges, P.spec_nb, P.spec_inv_w);
+                if (b < 0) atomicOr(status, (uint32_t)KRT_ST_NAN_BIT);
+                else atomicAdd(reinterpret_cast<unsigned long long *>(P.spec_raw + b), 1ull);
+                outcome = 1;
+                have = false;
+            } else if (ncross_pkt > kMaxCrossings) {
+                c_stuck += 1;
+                atomicOr(status, (uint32_t)KRT_ST_STUCK_BIT);
+                outcome = 3;
+                have = false;
+            } else {
+                cell = (ck * P.n[1] + cj) * P.n[0] + ci;
+                k0c = P.k0[cell];
+                if (P.vx) { vxc = P.vx[cell]; vyc = P.vy[cell]; vzc = P.vz[cell]; }
+                epsc = P.eps ? P.eps[cell] : 0.0f;
+            }
+        }
+    };
+
+    // a resonant scattering of a live lane at gas-frame frequency xc with the
+    // event's draws (sampler uniforms r1, r2; u_perp components; g, sin, cos psi)
+    auto scatter = [&](float xc, float r1, float r2, const SDraws &b) {
+        const float up1 = b.up1, up2 = b.up2, g = b.g, sg = b.sg, cp = b.cp, sp = b.sp;
+        float upar = upar_lds(T, xc, a, thd, r1, r2);
+        // orthonormal basis about n (Duff et al. 2017)
+        float sgn = copysignf(1.0f, nz);
+        float A_ = -f_rcp(sgn + nz);
+        float B_ = nx * ny * A_;
+        float e1x = 1.0f + sgn * nx * nx * A_, e1y = sgn * B_, e1z = -sgn * nx;
+        float e2x = B_, e2y = sgn + ny * ny * A_, e2z = -ny;
+        float ox = g * nx + sg * (cp * e1x + sp * e2x);
+        float oy = g * ny + sg * (cp * e1y + sp * e2y);
+        float oz = g * nz + sg * (cp * e1z + sp * e2z);
+        float rn = f_rsq(ox * ox + oy * oy + oz * oz);
+        ox *= rn; oy *= rn; oz *= rn;
+        // eq. riia-scatter
+        float xo = xc + upar * (g - 1.0f) + sg * (up1 * cp + up2 * sp);
+        if (P.emis_raw) {
+            float gc = nx * P.n_cam[0] + ny * P.n_cam[1] + nz * P.n_cam[2];
+            float upc = up1 * (e1x * P.n_cam[0] + e1y * P.n_cam[1] + e1z * P.n_cam[2]) +
+                        up2 * (e2x * P.n_cam[0] + e2y * P.n_cam[1] + e2z * P.n_cam[2]);
+            float xcam = xc + upar * (gc - 1.0f) + upc +
+                         (P.n_cam[0] * vxc + P.n_cam[1] * vyc + P.n_cam[2] * vzc);
+            int kb = bin_index(xcam, cedges, P.emis_nch, P.ch_inv_w);
+            if (kb >= 1 && kb <= P.emis_nch) {
+                float wph = (P.phase == KRT_PHASE_DIPOLE_I) ? 0.75f * (1.0f + gc * gc) : 1.0f;
+                emis_add(E, kb - 1, (int64_t)__float2ll_rn(wph * P.frac_scale),
+                         P.emis_raw + (int64_t)cell * P.emis_nch, status);
+            } else {
+                c_drop += 1;
+            }
+        }
+        nx = ox; ny = oy; nz = oz;
+        x = xo + nx * vxc + ny * vyc + nz * vzc;
+        nscat_pkt += 1;
+        c_scat += 1;
+    };
+
+    // a retired packet: flush the tallies of its last cell, log it
+    auto retire = [&]() {
+        if (P.jbar_raw && jacc != 0) { atomic_add_i64(P.jbar_raw + cell, jacc, status); jacc = 0; }
+        if (P.emis_raw) emis_flush(E, P.emis_raw + (int64_t)cell * P.emis_nch, P.emis_nch, status);
+        if (P.plog) {
+            float *L = P.plog + 8 * (pid - P.packet_offset);
+            L[0] = x; L[1] = (float)nscat_pkt; L[2] = (float)outcome;
+            L[3] = nx; L[4] = ny; L[5] = nz;
+            L[6] = (float)cell; L[7] = (float)ev;
+        }
+        outcome = 0;
+    };
+
+    bool tail = false;
     for (;;) {
         // ---- refill retired lanes from the global queue -------------------
         bool need = !have && !done;
@@ -246,85 +395,18 @@ __global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
                 }
             }
         }
-        if (__ballot(have) == 0ull) break;
+        const uint64_t live_mask = __ballot(have);
+        if (live_mask == 0ull) break;
+        // pool exhausted and few live lanes: continue in tail mode
+        if (!kEsc && P.tail_lanes > 0 && __ballot(done) != 0ull && __popcll(live_mask) <= P.tail_lanes) {
+            tail = true;
+            break;
+        }
 
         // ---- one flight segment (divergent) --------------------------------
         bool scat = false;
         float xc = 0.0f;
-        if (have) {
-            xc = x - (nx * vxc + ny * vyc + nz * vzc);
-            float H = (k0c > 0.0f) ? voigt_lds(T, fabsf(xc)) : 0.0f;
-            float kap = k0c * H;
-            float tx = (nx > 0.0f) ? (1.0f - fx) * P.dx[0] * f_rcp(nx) : ((nx < 0.0f) ? fx * P.dx[0] * f_rcp(-nx) : INFINITY);
-            float ty = (ny > 0.0f) ? (1.0f - fy) * P.dx[1] * f_rcp(ny) : ((ny < 0.0f) ? fy * P.dx[1] * f_rcp(-ny) : INFINITY);
-            float tz = (nz > 0.0f) ? (1.0f - fz) * P.dx[2] * f_rcp(nz) : ((nz < 0.0f) ? fz * P.dx[2] * f_rcp(-nz) : INFINITY);
-            int ax = 0;
-            float dmin = tx;
-            if (ty < dmin) { dmin = ty; ax = 1; }
-            if (tz < dmin) { dmin = tz; ax = 2; }
-            dmin = fmaxf(dmin, 0.0f);
-
-            if (kap > 0.0f && kap * dmin >= tau) {
-                // interaction inside the cell
-                float l = tau * f_rcp(kap);
-                fx = fminf(fmaxf(fmaf(l * nx, P.inv_dx[0], fx), 0.0f), 1.0f);
-                fy = fminf(fmaxf(fmaf(l * ny, P.inv_dx[1], fy), 0.0f), 1.0f);
-                fz = fminf(fmaxf(fmaf(l * nz, P.inv_dx[2], fz), 0.0f), 1.0f);
-                if (P.jbar_raw) jacc += (int64_t)__float2ll_rn(l * H * jscale);
-                if ((P.eps != nullptr) && (u01(wa1) < epsc)) {
-                    c_des += 1;
-                    outcome = 2;
-                    have = false;
-                } else {
-                    scat = true;
-                }
-            } else {
-                // cross the face of axis ax
-                tau -= kap * dmin;
-                if (P.jbar_raw) jacc += (int64_t)__float2ll_rn(dmin * H * jscale);
-                float adv = dmin;
-                if (ax != 0) fx = fminf(fmaxf(fmaf(adv * nx, P.inv_dx[0], fx), 0.0f), 1.0f);
-                if (ax != 1) fy = fminf(fmaxf(fmaf(adv * ny, P.inv_dx[1], fy), 0.0f), 1.0f);
-                if (ax != 2) fz = fminf(fmaxf(fmaf(adv * nz, P.inv_dx[2], fz), 0.0f), 1.0f);
-                c_cross += 1;
-                ncross_pkt += 1;
-                // leaving the cell: flush its register tallies
-                if (P.jbar_raw && jacc != 0) { atomic_add_i64(P.jbar_raw + cell, jacc, status); jacc = 0; }
-                if (P.emis_raw) emis_flush(E, P.emis_raw + (int64_t)cell * P.emis_nch, P.emis_nch, status);
-                bool escaped = false;
-                if (ax == 0) {
-                    int st = (nx > 0.0f) ? 1 : -1;
-                    ci += st; fx = (st > 0) ? 0.0f : 1.0f;
-                    if (ci < 0 || ci >= P.n[0]) { if (P.bc[0]) ci = (ci < 0) ? P.n[0] - 1 : 0; else escaped = true; }
-                } else if (ax == 1) {
-                    int st = (ny > 0.0f) ? 1 : -1;
-                    cj += st; fy = (st > 0) ? 0.0f : 1.0f;
-                    if (cj < 0 || cj >= P.n[1]) { if (P.bc[1]) cj = (cj < 0) ? P.n[1] - 1 : 0; else escaped = true; }
-                } else {
-                    int st = (nz > 0.0f) ? 1 : -1;
-                    ck += st; fz = (st > 0) ? 0.0f : 1.0f;
-                    if (ck < 0 || ck >= P.n[2]) { if (P.bc[2]) ck = (ck < 0) ? P.n[2] - 1 : 0; else escaped = true; }
-                }
-                if (escaped) {
-                    c_esc += 1;
-                    int b = bin_index(x, sedges, P.spec_nb, P.spec_inv_w);
-                    if (b < 0) atomicOr(status, (uint32_t)KRT_ST_NAN_BIT);
-                    else atomicAdd(reinterpret_cast<unsigned long long *>(P.spec_raw + b), 1ull);
-                    outcome = 1;
-                    have = false;
-                } else if (ncross_pkt > kMaxCrossings) {
-                    c_stuck += 1;
-                    atomicOr(status, (uint32_t)KRT_ST_STUCK_BIT);
-                    outcome = 3;
-                    have = false;
-                } else {
-                    cell = (ck * P.n[1] + cj) * P.n[0] + ci;
-                    k0c = P.k0[cell];
-                    if (P.vx) { vxc = P.vx[cell]; vyc = P.vy[cell]; vzc = P.vz[cell]; }
-                    epsc = P.eps ? P.eps[cell] : 0.0f;
-                }
-            }
-        }
+        if (have) flight(u01(wa1), scat, xc);
 
         // ---- learned escape: one batched network call per wave (uniform) ----
         bool mlp = false;
@@ -432,47 +514,9 @@ __global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
         if (scat) {
             const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
             if (!mlp) {
-                uint4 B = philox(make_uint4(ev, plo, phi, 1u), P.key0, P.key1);
-                float upar = upar_lds(T, xc, a, thd, u01(wa2), u01(wa3));
-                float rr = f_sqrt(-f_log(u01(B.x)));
-                float th = u01(B.y);
-                float up1 = rr * cos_rev(th), up2 = rr * sin_rev(th);
-                float g = (P.phase == KRT_PHASE_DIPOLE_I) ? dipole_g(u01(B.z)) : 2.0f * u01(B.z) - 1.0f;
-                float psi = u01(B.w);
-                float sg = f_sqrt(fmaxf(0.0f, 1.0f - g * g));
-                // orthonormal basis about n (Duff et al. 2017)
-                float sgn = copysignf(1.0f, nz);
-                float A_ = -f_rcp(sgn + nz);
-                float B_ = nx * ny * A_;
-                float e1x = 1.0f + sgn * nx * nx * A_, e1y = sgn * B_, e1z = -sgn * nx;
-                float e2x = B_, e2y = sgn + ny * ny * A_, e2z = -ny;
-                float cp = cos_rev(psi), sp = sin_rev(psi);
-                float ox = g * nx + sg * (cp * e1x + sp * e2x);
-                float oy = g * ny + sg * (cp * e1y + sp * e2y);
-                float oz = g * nz + sg * (cp * e1z + sp * e2z);
-                float rn = f_rsq(ox * ox + oy * oy + oz * oz);
-                ox *= rn; oy *= rn; oz *= rn;
-                // eq. riia-scatter
-                float xo = xc + upar * (g - 1.0f) + sg * (up1 * cp + up2 * sp);
-                if (P.emis_raw) {
-                    float gc = nx * P.n_cam[0] + ny * P.n_cam[1] + nz * P.n_cam[2];
-                    float upc = up1 * (e1x * P.n_cam[0] + e1y * P.n_cam[1] + e1z * P.n_cam[2]) +
-                                up2 * (e2x * P.n_cam[0] + e2y * P.n_cam[1] + e2z * P.n_cam[2]);
-                    float xcam = xc + upar * (gc - 1.0f) + upc +
-                                 (P.n_cam[0] * vxc + P.n_cam[1] * vyc + P.n_cam[2] * vzc);
-                    int kb = bin_index(xcam, cedges, P.emis_nch, P.ch_inv_w);
-                    if (kb >= 1 && kb <= P.emis_nch) {
-                        float wph = (P.phase == KRT_PHASE_DIPOLE_I) ? 0.75f * (1.0f + gc * gc) : 1.0f;
-                        emis_add(E, kb - 1, (int64_t)__float2ll_rn(wph * P.frac_scale),
-                                 P.emis_raw + (int64_t)cell * P.emis_nch, status);
-                    } else {
-                        c_drop += 1;
-                    }
-                }
-                nx = ox; ny = oy; nz = oz;
-                x = xo + nx * vxc + ny * vyc + nz * vzc;
-                nscat_pkt += 1;
-                c_scat += 1;
+                SDraws b;
+                scatter_draws(philox(make_uint4(ev, plo, phi, 1u), P.key0, P.key1), P.phase == KRT_PHASE_DIPOLE_I, b);
+                scatter(xc, u01(wa2), u01(wa3), b);
             }
             // next event
             ev += 1;
@@ -487,17 +531,70 @@ __global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
                 wa1 = A.y; wa2 = A.z; wa3 = A.w;
             }
         }
-        if (!have && outcome != 0) {
-            // packet retired: flush the tallies of its last cell, log it
-            if (P.jbar_raw && jacc != 0) { atomic_add_i64(P.jbar_raw + cell, jacc, status); jacc = 0; }
-            if (P.emis_raw) emis_flush(E, P.emis_raw + (int64_t)cell * P.emis_nch, P.emis_nch, status);
-            if (P.plog) {
-                float *L = P.plog + 8 * (pid - P.packet_offset);
-                L[0] = x; L[1] = (float)nscat_pkt; L[2] = (float)outcome;
-                L[3] = nx; L[4] = ny; L[5] = nz;
-                L[6] = (float)cell; L[7] = (float)ev;
+        if (!have && outcome != 0) retire();
+    }
+    // ---- tail mode ------------------------------------------------------------
+    // The packet pool is exhausted and at most tail_lanes lanes are live, so the
+    // wave lasts as long as its slowest packet.  The idle lanes precompute the
+    // random draws of the live packets' coming events: with k live lanes, lane j
+    // holds the draws of event ev0 + j / k of the live lane of rank j % k, and a
+    // live lane fetches its event's draws by a cross-lane read.  The draws are
+    // the same words mapped by the same functions as in the loop above, so the
+    // tallies do not depend on where a packet switches mode.
+    if (!kEsc && tail) {
+        const bool dipole = P.phase == KRT_PHASE_DIPOLE_I;
+        uint64_t bank_live = 0ull;
+        uint32_t ev0 = 0;
+        bool fresh = false;  // set after a scattering: tau of the new event comes from the draws
+        float pt = 0.f, pue = 0.f, pr1 = 0.f, pr2 = 0.f;
+        SDraws pb;
+        pb.up1 = pb.up2 = pb.g = pb.sg = pb.cp = pb.sp = 0.f;
+        for (;;) {
+            const uint64_t live = __ballot(have);
+            if (live == 0ull) break;
+            const int k = __popcll(live);
+            const int rank = __popcll(live & lanemask_lt);
+            const int nslot = (63 - rank) / k + 1;
+            const bool out_of_draws = have && (int)(ev - ev0) >= nslot;
+            if (live != bank_live || __ballot(out_of_draws) != 0ull) {
+                if (have) ev0 = ev;
+                const int r = lane % k, sl = lane / k;
+                const int owner = nth_set_lane(live, r);
+                const uint32_t olo = __shfl((uint32_t)pid, owner, 64);
+                const uint32_t ohi = __shfl((uint32_t)(pid >> 32), owner, 64);
+                const uint32_t e = __shfl(ev0, owner, 64) + (uint32_t)sl;
+                const uint4 A = philox(make_uint4(e, olo, ohi, 0u), P.key0, P.key1);
+                pt = -f_log(u01(A.x));
+                pue = u01(A.y);
+                pr1 = u01(A.z);
+                pr2 = u01(A.w);
+                scatter_draws(philox(make_uint4(e, olo, ohi, 1u), P.key0, P.key1), dipole, pb);
+                bank_live = live;
             }
-            outcome = 0;
+            const int src = have ? (int)(ev - ev0) * k + rank : lane;
+            const float dt = __shfl(pt, src, 64), due = __shfl(pue, src, 64);
+            const float dr1 = __shfl(pr1, src, 64), dr2 = __shfl(pr2, src, 64);
+            SDraws db;
+            db.up1 = __shfl(pb.up1, src, 64); db.up2 = __shfl(pb.up2, src, 64);
+            db.g = __shfl(pb.g, src, 64); db.sg = __shfl(pb.sg, src, 64);
+            db.cp = __shfl(pb.cp, src, 64); db.sp = __shfl(pb.sp, src, 64);
+            if (have && fresh) { tau = dt; fresh = false; }
+            bool scat = false;
+            float xc = 0.0f;
+            if (have) flight(due, scat, xc);
+            if (scat) {
+                scatter(xc, dr1, dr2, db);
+                ev += 1;
+                if ((uint64_t)ev > P.max_events) {
+                    c_stuck += 1;
+                    atomicOr(status, (uint32_t)KRT_ST_STUCK_BIT);
+                    outcome = 3;
+                    have = false;
+                } else {
+                    fresh = true;
+                }
+            }
+            if (!have && outcome != 0) retire();
         }
     }
 

@@ -10,11 +10,13 @@ import numpy as np
 
 from . import krt
 
-# (steps, batch, learning rate): Adam, learning rate halved and batch doubled per stage
-DEFAULT_STAGES = ((3000, 4096, 2e-3), (3000, 8192, 1e-3), (3000, 16384, 5e-4), (2000, 16384, 2.5e-4))
+# (steps, batch, learning rate): Adam, learning rate halved per stage, batch
+# doubled up to 32768; 30000 steps, about 70 passes over 8e6 records
+DEFAULT_STAGES = ((6000, 4096, 2e-3), (6000, 8192, 1e-3), (6000, 16384, 5e-4), (6000, 32768, 2.5e-4),
+                  (6000, 32768, 1.25e-4))
 
 
-def train_escape(ctx: "krt.Context", line: int = 0, n_records: int = 2_000_000, seed: int = 1,
+def train_escape(ctx: "krt.Context", line: int = 0, n_records: int = 8_000_000, seed: int = 1,
                  log10_tau=(2.0, 5.0), stages=DEFAULT_STAGES, record_offset: int = 0) -> dict:
     """Record `n_records` escapes from cubes with log10 tau_R uniform in
     `log10_tau` (line `line`, whose tables must be built), initialise the

@@ -117,12 +117,12 @@ def test_escape_records_vs_oracle(gpu_ctx, tau, xin):
 
 @pytest.fixture(scope="module")
 def trained(gpu_ctx):
-    """Train the escape network on GPU-recorded single-cell escapes (a = 1e-3,
-    log10 tau_R uniform in [1, 5]) with the staged default recipe."""
+    """Train the escape network on 8e6 GPU-recorded single-cell escapes
+    (a = 1e-3, log10 tau_R uniform in [1, 5]) with the staged default recipe."""
     from paper_2608_09340_amd import krt
     from paper_2608_09340_amd.escape import train_escape
     T = krt.Transport(W.slab(10.0, 1e-3, 4), ctx=gpu_ctx)
-    r = train_escape(gpu_ctx, 0, n_records=2_000_000, seed=1, log10_tau=(1.0, 5.0))
+    r = train_escape(gpu_ctx, 0, seed=1, log10_tau=(1.0, 5.0))
     r["T"] = T
     return r
 
@@ -138,9 +138,11 @@ def test_training_reduces_loss(trained):
 
 @pytest.mark.parametrize("tau,xin", [(3e1, 0.0), (3e2, 0.0), (3e3, 1.0), (3e4, 2.0)])
 def test_learned_samples_vs_plain(gpu_ctx, trained, tau, xin):
-    """At a fixed condition, the network's samples (quantile at u ~ U(0,1)) vs
-    held-out plain single-cell escapes: KS distance of the exit frequency and
-    of the exit cosine below 0.06, ln E[N_s] within 0.05."""
+    """At a fixed condition, the network's samples (quantiles at u ~ U(0,1), the
+    exit frequency through the two-component head) vs held-out plain
+    single-cell escapes: KS distance of exit frequency, exit point and exit
+    cosine below 0.04, exit-frequency histogram L1 below 0.13 (0.25-wide bins),
+    ln E[N_s] within 0.05."""
     import torch
     n = 20000
     out = torch.zeros((n, 10), dtype=torch.float32, device="cuda")
@@ -164,8 +166,9 @@ def test_learned_samples_vs_plain(gpu_ctx, trained, tau, xin):
     l1 = np.abs(hp / n - hm / n).sum()
     print(f"tau={tau} x_in={xin} KS x_out {ks[0]:.4f} s {ks[1]:.4f} t {ks[2]:.4f} mu {ks[3]:.4f} "
           f"x_out L1 {l1:.4f} P(x>=0) learned {pos.mean():.3f} plain {(plain[:, 3] >= 0).mean():.3f}")
-    assert ks[0] < 0.06 and ks[3] < 0.06, (tau, xin, ks)
-    assert l1 < 0.1, l1
+    assert max(ks.values()) < 0.04, (tau, xin, ks)
+    # density level: two plain samples of this size differ by L1 ~ 0.04 in these bins
+    assert l1 < 0.13, l1
     # output 4 is ln E[N_s]: against the log of the plain mean count (5%)
     ln_mean = np.log(np.mean(np.exp(plain[:, 7])))
     print(f"   ln E[N_s]: learned {m[:, 4].mean():.4f} (spread {m[:, 4].std():.1e}) plain {ln_mean:.4f}")
