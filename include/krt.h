@@ -141,7 +141,7 @@ typedef struct {
                                   the wave then lives only as long as its slowest packet */
     int32_t tail_lanes;        /* plain transport: once the pool is exhausted, a wave with at most
                                   this many live lanes lets its idle lanes precompute the live
-                                  packets' random draws (0 = 16, negative = never); the tallies
+                                  packets' random draws (0 = 32, negative = never); the tallies
                                   are the same either way */
 } krt_run_opts;
 
