@@ -51,6 +51,42 @@ def ledger_per_scatter(dipole: bool, emis: bool) -> int:
     return sum(LEDGER.values()) + (LEDGER_DIPOLE if dipole else 0) + (LEDGER_EMIS if emis else 0)
 
 
+# Sources compiled into the transport kernel; the HBM traffic measured by the
+# profiler (profiles/mc_transport_sphere64.md) is reported only while these are
+# byte-identical to the ones it was measured on.
+KERNEL_SOURCES = ["krt_transport.hip", "krt_device.h", "krt_kernels.h", "krt_mlp.h", "krt_internal.h"]
+PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "mc_transport_sphere64.md")
+
+
+def kernel_source_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2608_09340_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def profiled_traffic():
+    """HBM bytes per transport launch from the committed counter summary, or
+    None when the kernel sources changed since it was taken."""
+    try:
+        kv = {}
+        for line in open(PROFILE_SUMMARY):
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                kv[k.strip()] = v.strip().strip("`")
+        if kv.get("kernel_source_sha256") != kernel_source_sha256():
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def cpu_info():
     model = platform.processor() or ""
     try:
@@ -79,6 +115,7 @@ def cpu_baseline(prob, seconds_target=15.0):
         dt = time.perf_counter() - t
         n = n2
     sc = r["counters"]["scatterings"]
+    log(f"cpu baseline: {n} packets in {dt:.1f} s")
     return {"value": sc / dt, "unit": "scatterings/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} packets (ids from 2^40, seed 0) of the same workload, {sc} scatterings, "
                       f"{dt:.1f} s on {threads} threads of {model}",
@@ -109,6 +146,7 @@ def learned_escape_leg(ctx, n=128, packets=10_000_000, tau_min=100.0):
     t_train = time.perf_counter() - t0
     hist = tr["hist"]
     del tr
+    log(f"learned escape: trained in {t_train:.1f} s")
     T = krt.Transport(W.cloud_c4(n=n), ctx=ctx)
     pa = T.run(packets, seed=0)
     ms_plain = ctx.krt_last_transport_ms()
@@ -116,6 +154,7 @@ def learned_escape_leg(ctx, n=128, packets=10_000_000, tau_min=100.0):
     ms_plain2 = ctx.krt_last_transport_ms()
     ml = T.run(packets, seed=0, escape_mode=1, esc_tau_min=tau_min)
     ms_mlp = ctx.krt_last_transport_ms()
+    log(f"learned escape: plain {ms_plain:.0f} / {ms_plain2:.0f} ms, learned {ms_mlp:.0f} ms")
     if pa["rc"] or pb["rc"] or ml["rc"]:
         raise RuntimeError("learned-escape leg failed")
 
@@ -182,6 +221,7 @@ def main():
 
     for w in range(args.warmup):
         T.run(args.packets, seed=args.seed, packet_offset=(1 << 36) + w * args.packets)
+        log(f"warmup step {w} done: {ctx.krt_last_transport_ms():.0f} ms")
     torch.cuda.synchronize()
 
     scat = 0
@@ -195,6 +235,7 @@ def main():
         scat += r["counters"]["scatterings"]
         emitted += r["counters"]["emitted"]
         kern_ms.append(ctx.krt_last_transport_ms())
+        log(f"timed step {s} done: {kern_ms[-1]:.0f} ms")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
@@ -222,7 +263,7 @@ def main():
         "packets_per_s": emitted / wall,
         "transport_kernel_ms": kms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
-                     "frac": achieved / PEAK_VALU_TOPS, "traffic": None,
+                     "frac": achieved / PEAK_VALU_TOPS, "traffic": profiled_traffic(),
                      "ops_per_scattering": lps},
     }
     if not args.no_escape:
