@@ -369,3 +369,45 @@ def test_levels_lte_and_numpy():
     M[-1, :] = 1.0
     b = np.zeros(nl); b[-1] = 2.0
     assert np.allclose(pops[0], np.linalg.solve(M, b), rtol=1e-12)
+
+
+# ------------------------------------------------------- escape records --
+def _exit_geometry(n):
+    """Brute-force ray geometry: a straight ray from the centre of the cube
+    [-1, 1]^3 along n leaves through the face of the largest |n_i|; exit point
+    (s, t) = the other two components / |n_ax| in cyclic order, cosine |n_ax|."""
+    ax = np.argmax(np.abs(n), axis=1)
+    rows = np.arange(len(n))
+    na = np.abs(n[rows, ax])
+    s = n[rows, (ax + 1) % 3] / na
+    t = n[rows, (ax + 2) % 3] / na
+    return s, t, na
+
+
+def test_escape_record_thin_cube_is_ray_geometry():
+    """tau_R -> 0: after the scattering at the centre the photon leaves the cube
+    unscattered, so N_s = 1 and (s, t, mu) follow the straight-ray geometry of
+    an isotropic direction (KS against numpy directions)."""
+    from scipy import stats
+    n = 20000
+    rec = oracle.escape_record(n, 1e-5, 1e-3, 0.0, seed=3)
+    assert np.all(rec[:, 9] == 1.0)
+    assert np.all(rec[:, 7] == 0.0)  # ln N_s = 0: one scattering
+    rng = np.random.default_rng(5)
+    v = rng.normal(size=(200000, 3))
+    v /= np.linalg.norm(v, axis=1)[:, None]
+    s, t, mu = _exit_geometry(v)
+    for col, ref in ((4, s), (5, t), (6, mu)):
+        assert stats.ks_2samp(rec[:, col], ref).pvalue > 1e-3, col
+
+
+def test_escape_record_symmetries_and_bounds():
+    """At depth tau_R = 50 with x_in = 0: the exit point is symmetric about the
+    face centre, the exit frequency symmetric about 0, every record valid with
+    N_s >= 1 and the exit point on the face."""
+    rec = oracle.escape_record(4000, 50.0, 1e-3, 0.0, seed=4)
+    assert np.all(rec[:, 9] == 1.0) and np.all(rec[:, 7] >= 0.0)
+    assert np.all(np.abs(rec[:, 4:6]) <= 1.0) and np.all((rec[:, 6] > 0) & (rec[:, 6] <= 1.0))
+    se = 1.0 / np.sqrt(len(rec))
+    for col in (3, 4, 5):
+        assert abs(rec[:, col].mean()) < 5 * rec[:, col].std() * se, col
