@@ -227,29 +227,37 @@ int krt_levels_update(krt_ctx *ctx, const krt_levels_desc *desc,
  * only on records of their side), log-deviance e^d - 1 - d (d = ln N_s -
  * output) for output 4, logistic for output 6; trained on single-cell
  * escapes run by the plain transport arithmetic.  Parameters: kNParams =
- * 34696 FP32 master values plus 16 target normalisation constants
- * (mean[8], scale[8]).
+ * 34696 FP32 master values plus 48 constants: target normalisation mean[8],
+ * scale[8], and 32 additive calibration terms of ln E[N_s] per 0.125-wide bin
+ * of log10 tau_R over [1, 5] (clamped at the ends).
  *
  * krt_escape_init: He-uniform parameters from Philox(seed), Adam state zeroed.
  * krt_escape_record: n single-cell escapes for line `line`, log10 tau_R uniform
  *   in [lo, hi], x_in fixed (x_fixed = 1) or 1/2 N(0, 1/2) + 1/2 U[-8, 8];
  *   samples_dev [n][10] FP32: (log10 tau_R, log10 a, x_in, x_out, s, t, mu,
  *   ln N_s, ln <x^2>, valid).
- * krt_escape_fit_norm: target mean / scale from valid records.
+ * krt_escape_fit_norm: target mean / scale from valid records; clears the
+ *   calibration.
+ * krt_escape_calibrate: per log10 tau_R bin with at least 100 valid records,
+ *   the calibration term ln(sum N_s / sum exp(network ln E[N_s])) over the
+ *   records (a network quantile level drawn per record), so that the
+ *   predicted mean count is unbiased bin by bin; other bins get 0.
  * krt_escape_grad: gradient of the mean loss over the batch given by
  *   idx_dev [batch] (record indices) and u_dev [batch]; grad_out_dev [34696],
  *   loss_out_dev [1] (may be NULL).
  * krt_escape_train: `steps` Adam steps (lr, betas 0.9/0.999) on random batches
  *   (Philox(seed)); loss_hist_dev [steps] or NULL.
- * krt_escape_get_weights / put_weights: [34696 + 16] FP32 device buffers.
+ * krt_escape_get_weights / put_weights: [34696 + 48] FP32 device buffers.
  * krt_escape_forward: in_dev [n][4] raw (log10 tau_R, log10 a, x_in, u) ->
- *   out_dev [n][8] in physical units (output 6 as a logit).
+ *   out_dev [n][8] in physical units (output 6 as a logit, output 4 with its
+ *   calibration term).
  * Errors: KRT_EINVAL (sizes, ranges), KRT_ESTATE (no init / no tables). */
 int krt_escape_init(krt_ctx *ctx, uint64_t seed);
 int krt_escape_record(krt_ctx *ctx, int32_t line, uint64_t n, uint64_t seed, uint64_t offset,
                       double log10_tau_lo, double log10_tau_hi, int32_t x_fixed, double x_in,
                       float *samples_dev);
 int krt_escape_fit_norm(krt_ctx *ctx, const float *samples_dev, uint64_t n);
+int krt_escape_calibrate(krt_ctx *ctx, const float *samples_dev, uint64_t n);
 int krt_escape_grad(krt_ctx *ctx, const float *samples_dev, const int32_t *idx_dev, const float *u_dev,
                     int32_t batch, float *grad_out_dev, float *loss_out_dev);
 int krt_escape_train(krt_ctx *ctx, const float *samples_dev, uint64_t n, int32_t steps, int32_t batch,

@@ -45,6 +45,7 @@ struct krt_ctx {
     int mlp_batch_cap = 0;
     int mlp_step = 0;
     unsigned char *mlp_blob = nullptr, *mlp_img = nullptr;
+    double *mlp_calsum = nullptr;
 };
 
 namespace {
@@ -152,7 +153,7 @@ extern "C" void krt_destroy(krt_ctx *c) {
     if (c->host_pinned) (void)hipHostFree(c->host_pinned);
     for (void *p : {(void *)c->mlp_p, (void *)c->mlp_m, (void *)c->mlp_v, (void *)c->mlp_g, (void *)c->mlp_norm,
                     (void *)c->mlp_loss, (void *)c->mlp_u, (void *)c->mlp_idx, (void *)c->mlp_blob,
-                    (void *)c->mlp_img})
+                    (void *)c->mlp_img, (void *)c->mlp_calsum})
         if (p) (void)hipFree(p);
     if (c->edges) (void)hipFree(c->edges);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -546,6 +547,7 @@ int mlp_alloc(krt_ctx *c) {
     if (c->mlp_p) return KRT_OK;
     HIPCHK(c, hipMalloc(&c->mlp_p, sizeof(float) * kNParams));
     HIPCHK(c, hipMalloc(&c->mlp_m, sizeof(float) * kNParams));
+    HIPCHK(c, hipMalloc(&c->mlp_calsum, sizeof(double) * 3 * kNCal));
     HIPCHK(c, hipMalloc(&c->mlp_v, sizeof(float) * kNParams));
     HIPCHK(c, hipMalloc(&c->mlp_g, sizeof(float) * kNParams));
     HIPCHK(c, hipMalloc(&c->mlp_norm, sizeof(float) * kNNorm));
@@ -587,7 +589,8 @@ extern "C" int krt_escape_init(krt_ctx *c, uint64_t seed) {
     rc = mlp_zero_state(c);
     if (rc) return rc;
     float norm[kNNorm];
-    for (int k = 0; k < kMlpOut; ++k) { norm[k] = 0.0f; norm[kMlpOut + k] = 1.0f; }
+    for (int k = 0; k < kNNorm; ++k) norm[k] = 0.0f;
+    for (int k = 0; k < kMlpOut; ++k) norm[kMlpOut + k] = 1.0f;
     HIPCHK(c, hipMemcpyAsync(c->mlp_norm, norm, sizeof(norm), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, launch_mlp_pack(c->mlp_p, c->mlp_norm, c->mlp_blob, c->mlp_img, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -618,6 +621,21 @@ extern "C" int krt_escape_fit_norm(krt_ctx *c, const float *samples_dev, uint64_
     if (!samples_dev || n == 0) return fail(c, KRT_EINVAL, "bad norm args");
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, launch_mlp_norm(samples_dev, (int64_t)n, c->mlp_norm, c->stream));
+    // a new normalisation invalidates the calibration of ln E[N_s]
+    static_assert(kMlpOut % 2 == 0 && kNCal % 2 == 0, "calibration block is int64-aligned");
+    HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(c->mlp_norm + 2 * kMlpOut), kNCal / 2, c->stream));
+    HIPCHK(c, launch_mlp_pack(c->mlp_p, c->mlp_norm, c->mlp_blob, c->mlp_img, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return KRT_OK;
+}
+
+extern "C" int krt_escape_calibrate(krt_ctx *c, const float *samples_dev, uint64_t n) {
+    if (!c) return KRT_EINVAL;
+    if (!c->mlp_ready) return fail(c, KRT_ESTATE, "call krt_escape_init first");
+    if (!samples_dev || n == 0 || n >= (1ull << 31)) return fail(c, KRT_EINVAL, "bad calibration args");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(c->mlp_calsum), 3 * kNCal, c->stream));
+    HIPCHK(c, launch_mlp_calib(c->mlp_blob, samples_dev, (int64_t)n, c->mlp_calsum, c->mlp_norm, c->stream));
     HIPCHK(c, launch_mlp_pack(c->mlp_p, c->mlp_norm, c->mlp_blob, c->mlp_img, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return KRT_OK;

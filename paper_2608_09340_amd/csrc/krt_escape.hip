@@ -456,7 +456,7 @@ __global__ void mlp_norm_kernel(const float *rec, int64_t n, float *norm) {
 }
 
 // Forward for a list of raw conditions in[n][4] = (log10 tau_R, log10 a, x_in, u):
-// out[n][6] in physical units.
+// out[n][8] in physical units (ln E[N_s] with its calibration term).
 __global__ void __launch_bounds__(256) mlp_forward_kernel(const unsigned char *blob, const float *inp,
                                                           int64_t n, float *out) {
     const int lane = __lane_id(), w = threadIdx.x / 64;
@@ -475,8 +475,54 @@ __global__ void __launch_bounds__(256) mlp_forward_kernel(const unsigned char *b
     float v[4] = {o.x, o.y, o.z, o.w};
     for (int j = 0; j < 4; ++j) {
         int k = 4 * g + j;
-        if (k < kMlpOut) out[kMlpOut * si + k] = v[j] * norm[kMlpOut + k] + norm[k];
+        if (k < kMlpOut)
+            out[kMlpOut * si + k] = v[j] * norm[kMlpOut + k] + norm[k] +
+                                    ((k == kOutLogN) ? norm[2 * kMlpOut + cal_bin(r[0])] : 0.0f);
     }
+}
+
+// Calibration sums over valid records: per bin of log10 tau_R, the number of
+// records, sum N_s and sum exp(network ln E[N_s]) (without calibration), FP64.
+// One wave per 16-record block; block partial sums in LDS, then global atomics.
+__global__ void __launch_bounds__(256) mlp_calib_kernel(const unsigned char *blob, const float *rec, int64_t n,
+                                                        double *sums) {
+    __shared__ double ls[3 * kNCal];
+    for (int i = threadIdx.x; i < 3 * kNCal; i += blockDim.x) ls[i] = 0.0;
+    __syncthreads();
+    const int lane = __lane_id(), w = threadIdx.x / 64;
+    const int64_t block = (int64_t)blockIdx.x * (blockDim.x / 64) + w;
+    const int s = lane % 16, g = lane / 16;
+    const int64_t si = block * 16 + s;
+    if (block * 16 < n) {  // wave-uniform
+        const float *r = rec + (int64_t)kRec * (si < n ? si : 0);
+        const bool live = si < n && r[9] > 0.5f;
+        const float *bias = reinterpret_cast<const float *>(blob + kTilesAll * kTileBytes);
+        const float *norm = bias + kBiasFloats;
+        // quantile level as the transport draws it: uniform, from Philox(record index)
+        const uint4 q = philox(make_uint4((uint32_t)si, (uint32_t)(si >> 32), 0u, 9u), 0x6C1Bu, 0x5EEDu);
+        float in[4];
+        mlp_inputs(r[0], r[1], r[2], u01(q.x), in);
+        v4f32 o = mlp_forward_block(blob, bias, xin_operand(in, lane), lane, nullptr, nullptr, nullptr);
+        // output 4 sits in lane group g = 1, component 0
+        if (live && g == 1) {
+            const int b = cal_bin(r[0]);
+            const double pred = exp((double)(o.x * norm[kMlpOut + kOutLogN] + norm[kOutLogN]));
+            atomicAdd(&ls[b], 1.0);
+            atomicAdd(&ls[kNCal + b], exp((double)r[7]));
+            atomicAdd(&ls[2 * kNCal + b], pred);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 3 * kNCal; i += blockDim.x)
+        if (ls[i] != 0.0) atomicAdd(&sums[i], ls[i]);
+}
+
+// cal[b] = ln(sum N_s / sum predicted) for bins with at least 100 records, else 0
+__global__ void mlp_calib_finish_kernel(const double *sums, float *norm) {
+    const int b = threadIdx.x;
+    if (b >= kNCal) return;
+    const double cnt = sums[b], sn = sums[kNCal + b], sp = sums[2 * kNCal + b];
+    norm[2 * kMlpOut + b] = (cnt >= 100.0 && sn > 0.0 && sp > 0.0) ? (float)log(sn / sp) : 0.0f;
 }
 
 // --------------------------------------------------------------- launch ---
@@ -533,6 +579,16 @@ hipError_t launch_mlp_batch(int64_t n, uint32_t k0, uint32_t k1, uint32_t step, 
                             float *uq, hipStream_t s) {
     hipLaunchKernelGGL(mlp_batch_kernel, dim3((batch + 255) / 256), dim3(256), 0, s, n, k0, k1, step, batch,
                        idx, uq);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_calib(const unsigned char *blob, const float *rec, int64_t n, double *sums, float *norm,
+                            hipStream_t s) {
+    int64_t blocks = (n + 63) / 64;  // 4 waves of 16 records per block
+    hipLaunchKernelGGL(mlp_calib_kernel, dim3((unsigned)blocks), dim3(256), 0, s, blob, rec, n, sums);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(mlp_calib_finish_kernel, dim3(1), dim3(64), 0, s, sums, norm);
     return hipGetLastError();
 }
 

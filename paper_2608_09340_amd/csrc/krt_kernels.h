@@ -98,6 +98,8 @@ hipError_t launch_mlp_adam(float *p, float *m, float *v, float *grad, float lr, 
 hipError_t launch_mlp_batch(int64_t n, uint32_t k0, uint32_t k1, uint32_t step, int batch, int32_t *idx,
                             float *uq, hipStream_t s);
 hipError_t launch_mlp_norm(const float *rec, int64_t n, float *norm, hipStream_t s);
+hipError_t launch_mlp_calib(const unsigned char *blob, const float *rec, int64_t n, double *sums, float *norm,
+                            hipStream_t s);
 hipError_t launch_mlp_forward(const unsigned char *blob, const float *inp, int64_t n, float *out, hipStream_t s);
 hipError_t launch_levels(int nl, int64_t ncell, const double *consts, const double *ncoll,
                          const double *ntot, const float *jbar, double *pops, float *k0_out,

@@ -43,8 +43,15 @@ constexpr int kPW4 = kPB3 + kMlpHid;                     // W4[128][8]
 constexpr int kPB4 = kPW4 + kMlpHid * kMlpOut;           // b4[8]
 constexpr int kNParams = kPB4 + kMlpOut;                 // 34696
 // target normalisation: y_norm = (y - mean) / scale, stored after the params
-// (output 6, the side logit, has mean 0 and scale 1)
-constexpr int kNNorm = 2 * kMlpOut;
+// (output 6, the side logit, has mean 0 and scale 1), followed by the
+// calibration of ln E[N_s]: an additive term per bin of log10 tau_R
+constexpr int kNCal = 32;
+constexpr float kCalLo = 1.0f, kCalInvW = 8.0f;  // bins of 0.125 in log10 tau_R from 1 to 5
+constexpr int kNNorm = 2 * kMlpOut + kNCal;
+
+__device__ __forceinline__ int cal_bin(float lt) {
+    return min(max((int)((lt - kCalLo) * kCalInvW), 0), kNCal - 1);
+}
 
 // Packed BF16 A-operand tiles (16x16, 512 B each: 64 lanes x 4 bf16).
 // Forward (W^T, rows = out-features): L1 8 tiles (K padded 4 -> 16), L2 64, L3 64, L4 8 (rows padded 8 -> 16).

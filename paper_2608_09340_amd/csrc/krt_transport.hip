@@ -452,7 +452,8 @@ __global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
                     const float mag = fmaxf(mo[ko] * mnorm[kMlpOut + ko] + mnorm[ko], 0.0f);
                     float xo = pos ? mag : -mag;
                     float tt = fminf(fmaxf(mo[kOutT] * mnorm[kMlpOut + kOutT] + mnorm[kOutT], -1.0f), 1.0f);
-                    float lns = mo[kOutLogN] * mnorm[kMlpOut + kOutLogN] + mnorm[kOutLogN];
+                    float lns = mo[kOutLogN] * mnorm[kMlpOut + kOutLogN] + mnorm[kOutLogN] +
+                                mnorm[2 * kMlpOut + cal_bin(lt)];
                     float lx2 = mo[kOutLogX2] * mnorm[kMlpOut + kOutLogX2] + mnorm[kOutLogX2];
                     float ss = fminf(fmaxf(mo2[kOutS] * mnorm[kMlpOut + kOutS] + mnorm[kOutS], -1.0f), 1.0f);
                     float mu = fminf(fmaxf(mo2[kOutMu] * mnorm[kMlpOut + kOutMu] + mnorm[kOutMu], 1e-3f), 1.0f);

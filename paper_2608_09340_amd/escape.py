@@ -1,7 +1,8 @@
 """Training recipe of the learned escape: record single-cell escapes with the
 plain walk on the GPU (krt_escape_record), fit the output normalisation, then
 run the BF16-MFMA training kernels (krt_escape_train) in stages of decreasing
-learning rate and growing batch.  Only the order of the library calls lives
+learning rate and growing batch, then calibrate the mean scattering count
+(krt_escape_calibrate).  Only the order of the library calls lives
 here; records, gradients and Adam updates are computed by libkrt.
 """
 from __future__ import annotations
@@ -20,8 +21,10 @@ def train_escape(ctx: "krt.Context", line: int = 0, n_records: int = 8_000_000, 
                  log10_tau=(2.0, 5.0), stages=DEFAULT_STAGES, record_offset: int = 0) -> dict:
     """Record `n_records` escapes from cubes with log10 tau_R uniform in
     `log10_tau` (line `line`, whose tables must be built), initialise the
-    network from `seed`, fit the normalisation and train.  Returns the record
-    buffer and the per-step loss history (all stages, concatenated)."""
+    network from `seed`, fit the normalisation, train, and calibrate the
+    predicted mean scattering count per log10 tau_R bin on the records.
+    Returns the record buffer and the per-step loss history (all stages,
+    concatenated)."""
     import torch
     dev = torch.device("cuda", ctx.device)
     rec = torch.zeros((n_records, 10), dtype=torch.float32, device=dev)
@@ -33,4 +36,5 @@ def train_escape(ctx: "krt.Context", line: int = 0, n_records: int = 8_000_000, 
         h = torch.zeros(steps, dtype=torch.float32, device=dev)
         ctx.krt_escape_train(rec, n_records, steps, batch, lr, seed * 1000 + 11 + k, h)
         hist.append(h.cpu().numpy())
+    ctx.krt_escape_calibrate(rec, n_records)
     return {"rec": rec, "hist": np.concatenate(hist), "log10_tau": tuple(log10_tau)}

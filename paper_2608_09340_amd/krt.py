@@ -63,9 +63,9 @@ EXPORTS = ["krt_create", "krt_destroy", "krt_last_error", "krt_device_cus", "krt
            "krt_grid_upload",
            "krt_tables_build", "krt_mc_run", "krt_levels_update", "krt_debug_philox",
            "krt_debug_bins", "krt_debug_voigt", "krt_debug_upar",
-           "krt_escape_init", "krt_escape_record", "krt_escape_fit_norm", "krt_escape_grad",
+           "krt_escape_init", "krt_escape_record", "krt_escape_fit_norm", "krt_escape_calibrate", "krt_escape_grad",
            "krt_escape_train", "krt_escape_get_weights", "krt_escape_put_weights", "krt_escape_forward"]
-ESC_NPARAMS, ESC_NNORM, ESC_NOUT = 34696, 16, 8
+ESC_NPARAMS, ESC_NNORM, ESC_NOUT, ESC_NCAL = 34696, 48, 8, 32
 
 _lib = None
 
@@ -100,6 +100,7 @@ def load(path: str = LIB_PATH):
     L.krt_escape_init.argtypes = [p, u64]
     L.krt_escape_record.argtypes = [p, i32, u64, u64, u64, C.c_double, C.c_double, i32, C.c_double, p]
     L.krt_escape_fit_norm.argtypes = [p, p, u64]
+    L.krt_escape_calibrate.argtypes = [p, p, u64]
     L.krt_escape_grad.argtypes = [p, p, p, p, i32, p, p]
     L.krt_escape_train.argtypes = [p, p, u64, i32, i32, C.c_double, u64, p]
     L.krt_escape_get_weights.argtypes = [p, p, u64]
@@ -107,7 +108,8 @@ def load(path: str = LIB_PATH):
     L.krt_escape_forward.argtypes = [p, p, i64, p]
     for name in ["krt_grid_upload", "krt_tables_build", "krt_mc_run", "krt_levels_update",
                  "krt_debug_philox", "krt_debug_bins", "krt_debug_voigt", "krt_debug_upar",
-                 "krt_escape_init", "krt_escape_record", "krt_escape_fit_norm", "krt_escape_grad",
+                 "krt_escape_init", "krt_escape_record", "krt_escape_fit_norm", "krt_escape_calibrate",
+                 "krt_escape_grad",
                  "krt_escape_train", "krt_escape_get_weights", "krt_escape_put_weights",
                  "krt_escape_forward"]:
         getattr(L, name).restype = C.c_int
@@ -207,6 +209,9 @@ class Context:
 
     def krt_escape_fit_norm(self, rec, n):
         self._check(self.L.krt_escape_fit_norm(self.h, _ptr(rec), int(n)))
+
+    def krt_escape_calibrate(self, rec, n):
+        self._check(self.L.krt_escape_calibrate(self.h, _ptr(rec), int(n)))
 
     def krt_escape_grad(self, rec, idx, u, grad_out, loss_out=None):
         self._check(self.L.krt_escape_grad(self.h, _ptr(rec), _ptr(idx), _ptr(u), int(idx.numel()),

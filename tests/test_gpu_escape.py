@@ -14,12 +14,15 @@ from paper_2608_09340_amd import workloads as W
 from stats_util import l1_shape
 
 pytestmark = pytest.mark.gpu
-NP, NN, NO = mlp.NPARAMS, mlp.NNORM, mlp.NOUT
+NP, NO = mlp.NPARAMS, mlp.NOUT
+
+
+NCAL = 32  # calibration terms of ln E[N_s] stored after the normalisation
 
 
 def _put(ctx, p, norm):
     import torch
-    w = torch.from_numpy(np.concatenate([p, norm]).astype(np.float32)).cuda()
+    w = torch.from_numpy(np.concatenate([p, norm, np.zeros(NCAL)]).astype(np.float32)).cuda()
     ctx.krt_escape_put_weights(w)
 
 
@@ -134,6 +137,31 @@ def test_training_reduces_loss(trained):
     assert np.all(np.isfinite(h))
     early, mid, late = h[:5].mean(), h[50:100].mean(), h[-200:].mean()
     assert late < 0.6 * early and late < mid, (early, mid, late)
+
+
+def test_calibration_unbiased_per_bin(gpu_ctx, trained):
+    """After krt_escape_calibrate, the forward pass's calibrated E[N_s] summed
+    over the records of each log10 tau_R bin equals the records' sum of N_s
+    (the calibration's defining property; FP32 outputs, so within 1e-3)."""
+    import torch
+    rec = trained["rec"][:400_000]
+    r = rec.cpu().numpy().astype(np.float64)
+    gpu_ctx.krt_escape_calibrate(rec, rec.shape[0])
+    n = rec.shape[0]
+    inp = rec[:, :4].clone()
+    inp[:, 3] = torch.rand(n, device=rec.device)
+    out = torch.zeros((n, NO), dtype=torch.float32, device=rec.device)
+    gpu_ctx.krt_escape_forward(inp.contiguous(), out)
+    pred = np.exp(out[:, mlp.O_LOGN].cpu().numpy().astype(np.float64))
+    b = np.clip(((r[:, 0] - 1.0) * 8.0).astype(int), 0, 31)
+    for k in range(32):
+        m = b == k
+        if m.sum() < 1000:
+            continue
+        ratio = pred[m].sum() / np.exp(r[m, 7]).sum()
+        assert abs(ratio - 1.0) < 0.02, (k, ratio)
+    # the full training set again, so later tests see the fixture's calibration
+    gpu_ctx.krt_escape_calibrate(trained["rec"], trained["rec"].shape[0])
 
 
 @pytest.mark.parametrize("tau,xin", [(3e1, 0.0), (3e2, 0.0), (3e3, 1.0), (3e4, 2.0)])
