@@ -139,6 +139,10 @@ typedef struct {
                                   not bitwise, independent of launch geometry */
     int32_t esc_tail_lanes;    /* as esc_min_lanes once the packet pool is exhausted (0 = 1):
                                   the wave then lives only as long as its slowest packet */
+    int32_t esc_evals;         /* network evaluations per learned escape: 4 (0 = 4) draws the exit
+                                  frequency, the two exit-point coordinates and the exit cosine at
+                                  independent quantile levels; 2 shares the levels of (|x_out|, t)
+                                  and of (s, mu) */
     int32_t tail_lanes;        /* plain transport: once the pool is exhausted, a wave with at most
                                   this many live lanes lets its idle lanes precompute the live
                                   packets' random draws (0 = 32, negative = never); the tallies

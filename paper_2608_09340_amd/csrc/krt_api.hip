@@ -363,6 +363,7 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
     P.esc_log10a = (float)std::log10(c->lines[l].a);
     P.esc_min_lanes = o->esc_min_lanes > 0 ? o->esc_min_lanes : 8;
     P.esc_tail_lanes = o->esc_tail_lanes > 0 ? o->esc_tail_lanes : 1;
+    P.esc_evals = o->esc_evals == 2 ? 2 : 4;
     P.tail_lanes = o->tail_lanes == 0 ? 32 : (o->tail_lanes < 0 ? 0 : std::min(o->tail_lanes, 64));
     int grid = c->cus * per_cu;
     HIPCHK(c, hipEventRecord(c->ev0, c->stream));

@@ -73,6 +73,7 @@ struct RunParams {
     float esc_tau_min, esc_tau_max, esc_x_max, esc_log10a;
     int esc_min_lanes;
     int esc_tail_lanes;
+    int esc_evals;
     int tail_lanes;
 };
 

@@ -441,22 +441,32 @@ __global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
                 mlp_eval_wave(mimg, mbias, in, lane, wm, mo);
                 in[3] = 2.0f * u01(C.y) - 1.0f;
                 mlp_eval_wave(mimg, mbias, in, lane, wm, mo2);
+                // independent quantile levels for t and mu (two more evaluations)
+                const uint4 D = philox(make_uint4(ev, (uint32_t)pid, (uint32_t)(pid >> 32), 3u), P.key0, P.key1);
+                const bool indep = P.esc_evals != 2;
+                float mo3[kMlpOut], mo4[kMlpOut];
+                if (indep) {
+                    in[3] = 2.0f * u01(D.y) - 1.0f;
+                    mlp_eval_wave(mimg, mbias, in, lane, wm, mo3);
+                    in[3] = 2.0f * u01(D.z) - 1.0f;
+                    mlp_eval_wave(mimg, mbias, in, lane, wm, mo4);
+                }
                 if (mlp) {
                     // ---- exit from the cube centred here (half-width Rcube) ----
-                    const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
                     // exit frequency: side from the learned P(x_out >= 0) and a word of
                     // purpose 3, magnitude from that side's quantile at level u1
-                    uint4 D = philox(make_uint4(ev, plo, phi, 3u), P.key0, P.key1);
                     const bool pos = u01(D.x) < sigmoid_f(mo[kOutLogit]);
                     const int ko = pos ? kOutXPos : kOutXNeg;
                     const float mag = fmaxf(mo[ko] * mnorm[kMlpOut + ko] + mnorm[ko], 0.0f);
                     float xo = pos ? mag : -mag;
-                    float tt = fminf(fmaxf(mo[kOutT] * mnorm[kMlpOut + kOutT] + mnorm[kOutT], -1.0f), 1.0f);
+                    const float ot = indep ? mo3[kOutT] : mo[kOutT];
+                    const float omu = indep ? mo4[kOutMu] : mo2[kOutMu];
+                    float tt = fminf(fmaxf(ot * mnorm[kMlpOut + kOutT] + mnorm[kOutT], -1.0f), 1.0f);
                     float lns = mo[kOutLogN] * mnorm[kMlpOut + kOutLogN] + mnorm[kOutLogN] +
                                 mnorm[2 * kMlpOut + cal_bin(lt)];
                     float lx2 = mo[kOutLogX2] * mnorm[kMlpOut + kOutLogX2] + mnorm[kOutLogX2];
                     float ss = fminf(fmaxf(mo2[kOutS] * mnorm[kMlpOut + kOutS] + mnorm[kOutS], -1.0f), 1.0f);
-                    float mu = fminf(fmaxf(mo2[kOutMu] * mnorm[kMlpOut + kOutMu] + mnorm[kOutMu], 1e-3f), 1.0f);
+                    float mu = fminf(fmaxf(omu * mnorm[kMlpOut + kOutMu] + mnorm[kOutMu], 1e-3f), 1.0f);
                     // symmetry of the cube: face, swap of (s, t), signs
                     uint32_t bits = C.z;
                     int face = (int)__umulhi(bits, 6u);
