@@ -141,7 +141,7 @@ def learned_escape_leg(ctx, n=128, packets=10_000_000, tau_min=100.0):
     from paper_2608_09340_amd.escape import train_escape
     t0 = time.perf_counter()
     krt.Transport(W.slab(10.0, 1e-3, 4), ctx=ctx)  # line tables for a = 1e-3
-    tr = train_escape(ctx, 0, n_records=2_000_000, seed=1, log10_tau=(1.0, 5.0))
+    tr = train_escape(ctx, 0, seed=1, log10_tau=(1.0, 5.0))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     hist = tr["hist"]

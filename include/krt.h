@@ -231,9 +231,10 @@ int krt_levels_update(krt_ctx *ctx, const krt_levels_desc *desc,
  * only on records of their side), log-deviance e^d - 1 - d (d = ln N_s -
  * output) for output 4, logistic for output 6; trained on single-cell
  * escapes run by the plain transport arithmetic.  Parameters: kNParams =
- * 34696 FP32 master values plus 48 constants: target normalisation mean[8],
- * scale[8], and 32 additive calibration terms of ln E[N_s] per 0.125-wide bin
- * of log10 tau_R over [1, 5] (clamped at the ends).
+ * 34696 FP32 master values plus 272 constants: target normalisation mean[8],
+ * scale[8], and 256 additive calibration terms of ln E[N_s], one per bin of
+ * (log10 tau_R in 32 bins of 0.125 over [1, 5], clamped; |x_in| in 8 bins with
+ * edges 0, .5, 1, 1.5, 2, 3, 4, 6), index = tau bin * 8 + x bin.
  *
  * krt_escape_init: He-uniform parameters from Philox(seed), Adam state zeroed.
  * krt_escape_record: n single-cell escapes for line `line`, log10 tau_R uniform
@@ -242,7 +243,7 @@ int krt_levels_update(krt_ctx *ctx, const krt_levels_desc *desc,
  *   ln N_s, ln <x^2>, valid).
  * krt_escape_fit_norm: target mean / scale from valid records; clears the
  *   calibration.
- * krt_escape_calibrate: per log10 tau_R bin with at least 100 valid records,
+ * krt_escape_calibrate: per (log10 tau_R, |x_in|) bin with at least 100 valid records,
  *   the calibration term ln(sum N_s / sum exp(network ln E[N_s])) over the
  *   records (a network quantile level drawn per record), so that the
  *   predicted mean count is unbiased bin by bin; other bins get 0.
@@ -251,7 +252,7 @@ int krt_levels_update(krt_ctx *ctx, const krt_levels_desc *desc,
  *   loss_out_dev [1] (may be NULL).
  * krt_escape_train: `steps` Adam steps (lr, betas 0.9/0.999) on random batches
  *   (Philox(seed)); loss_hist_dev [steps] or NULL.
- * krt_escape_get_weights / put_weights: [34696 + 48] FP32 device buffers.
+ * krt_escape_get_weights / put_weights: [34696 + 272] FP32 device buffers.
  * krt_escape_forward: in_dev [n][4] raw (log10 tau_R, log10 a, x_in, u) ->
  *   out_dev [n][8] in physical units (output 6 as a logit, output 4 with its
  *   calibration term).

@@ -477,11 +477,11 @@ __global__ void __launch_bounds__(256) mlp_forward_kernel(const unsigned char *b
         int k = 4 * g + j;
         if (k < kMlpOut)
             out[kMlpOut * si + k] = v[j] * norm[kMlpOut + k] + norm[k] +
-                                    ((k == kOutLogN) ? norm[2 * kMlpOut + cal_bin(r[0])] : 0.0f);
+                                    ((k == kOutLogN) ? norm[2 * kMlpOut + cal_bin(r[0], r[2])] : 0.0f);
     }
 }
 
-// Calibration sums over valid records: per bin of log10 tau_R, the number of
+// Calibration sums over valid records: per bin of (log10 tau_R, |x_in|), the number of
 // records, sum N_s and sum exp(network ln E[N_s]) (without calibration), FP64.
 // One wave per 16-record block; block partial sums in LDS, then global atomics.
 __global__ void __launch_bounds__(256) mlp_calib_kernel(const unsigned char *blob, const float *rec, int64_t n,
@@ -505,7 +505,7 @@ __global__ void __launch_bounds__(256) mlp_calib_kernel(const unsigned char *blo
         v4f32 o = mlp_forward_block(blob, bias, xin_operand(in, lane), lane, nullptr, nullptr, nullptr);
         // output 4 sits in lane group g = 1, component 0
         if (live && g == 1) {
-            const int b = cal_bin(r[0]);
+            const int b = cal_bin(r[0], r[2]);
             const double pred = exp((double)(o.x * norm[kMlpOut + kOutLogN] + norm[kOutLogN]));
             atomicAdd(&ls[b], 1.0);
             atomicAdd(&ls[kNCal + b], exp((double)r[7]));
@@ -519,7 +519,7 @@ __global__ void __launch_bounds__(256) mlp_calib_kernel(const unsigned char *blo
 
 // cal[b] = ln(sum N_s / sum predicted) for bins with at least 100 records, else 0
 __global__ void mlp_calib_finish_kernel(const double *sums, float *norm) {
-    const int b = threadIdx.x;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= kNCal) return;
     const double cnt = sums[b], sn = sums[kNCal + b], sp = sums[2 * kNCal + b];
     norm[2 * kMlpOut + b] = (cnt >= 100.0 && sn > 0.0 && sp > 0.0) ? (float)log(sn / sp) : 0.0f;
@@ -588,7 +588,7 @@ hipError_t launch_mlp_calib(const unsigned char *blob, const float *rec, int64_t
     hipLaunchKernelGGL(mlp_calib_kernel, dim3((unsigned)blocks), dim3(256), 0, s, blob, rec, n, sums);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(mlp_calib_finish_kernel, dim3(1), dim3(64), 0, s, sums, norm);
+    hipLaunchKernelGGL(mlp_calib_finish_kernel, dim3((kNCal + 255) / 256), dim3(256), 0, s, sums, norm);
     return hipGetLastError();
 }
 

@@ -44,13 +44,17 @@ constexpr int kPB4 = kPW4 + kMlpHid * kMlpOut;           // b4[8]
 constexpr int kNParams = kPB4 + kMlpOut;                 // 34696
 // target normalisation: y_norm = (y - mean) / scale, stored after the params
 // (output 6, the side logit, has mean 0 and scale 1), followed by the
-// calibration of ln E[N_s]: an additive term per bin of log10 tau_R
-constexpr int kNCal = 32;
+// calibration of ln E[N_s]: an additive term per bin of (log10 tau_R, |x_in|)
+constexpr int kNCalT = 32, kNCalX = 8, kNCal = kNCalT * kNCalX;
 constexpr float kCalLo = 1.0f, kCalInvW = 8.0f;  // bins of 0.125 in log10 tau_R from 1 to 5
 constexpr int kNNorm = 2 * kMlpOut + kNCal;
 
-__device__ __forceinline__ int cal_bin(float lt) {
-    return min(max((int)((lt - kCalLo) * kCalInvW), 0), kNCal - 1);
+// |x_in| bins: [0, .5), [.5, 1), [1, 1.5), [1.5, 2), [2, 3), [3, 4), [4, 6), [6, inf)
+__device__ __forceinline__ int cal_bin(float lt, float xin) {
+    const int bt = min(max((int)((lt - kCalLo) * kCalInvW), 0), kNCalT - 1);
+    const float ax = fabsf(xin);
+    const int bx = (ax < 2.0f) ? min((int)(ax * 2.0f), 3) : (ax < 4.0f ? 3 + (int)(ax - 1.0f) : (ax < 6.0f ? 6 : 7));
+    return bt * kNCalX + bx;
 }
 
 // Packed BF16 A-operand tiles (16x16, 512 B each: 64 lanes x 4 bf16).

@@ -463,7 +463,7 @@ __global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
                     const float omu = indep ? mo4[kOutMu] : mo2[kOutMu];
                     float tt = fminf(fmaxf(ot * mnorm[kMlpOut + kOutT] + mnorm[kOutT], -1.0f), 1.0f);
                     float lns = mo[kOutLogN] * mnorm[kMlpOut + kOutLogN] + mnorm[kOutLogN] +
-                                mnorm[2 * kMlpOut + cal_bin(lt)];
+                                mnorm[2 * kMlpOut + cal_bin(lt, xc)];
                     float lx2 = mo[kOutLogX2] * mnorm[kMlpOut + kOutLogX2] + mnorm[kOutLogX2];
                     float ss = fminf(fmaxf(mo2[kOutS] * mnorm[kMlpOut + kOutS] + mnorm[kOutS], -1.0f), 1.0f);
                     float mu = fminf(fmaxf(omu * mnorm[kMlpOut + kOutMu] + mnorm[kOutMu], 1e-3f), 1.0f);

@@ -65,7 +65,7 @@ EXPORTS = ["krt_create", "krt_destroy", "krt_last_error", "krt_device_cus", "krt
            "krt_debug_bins", "krt_debug_voigt", "krt_debug_upar",
            "krt_escape_init", "krt_escape_record", "krt_escape_fit_norm", "krt_escape_calibrate", "krt_escape_grad",
            "krt_escape_train", "krt_escape_get_weights", "krt_escape_put_weights", "krt_escape_forward"]
-ESC_NPARAMS, ESC_NNORM, ESC_NOUT, ESC_NCAL = 34696, 48, 8, 32
+ESC_NPARAMS, ESC_NNORM, ESC_NOUT, ESC_NCAL = 34696, 272, 8, 256
 
 _lib = None
 

@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 NP, NO = mlp.NPARAMS, mlp.NOUT
 
 
-NCAL = 32  # calibration terms of ln E[N_s] stored after the normalisation
+NCAL = 256  # calibration terms of ln E[N_s] stored after the normalisation
 
 
 def _put(ctx, p, norm):
@@ -141,10 +141,10 @@ def test_training_reduces_loss(trained):
 
 def test_calibration_unbiased_per_bin(gpu_ctx, trained):
     """After krt_escape_calibrate, the forward pass's calibrated E[N_s] summed
-    over the records of each log10 tau_R bin equals the records' sum of N_s
+    over the records of each (log10 tau_R, |x_in|) bin equals the records' sum of N_s
     (the calibration's defining property; FP32 outputs, so within 1e-3)."""
     import torch
-    rec = trained["rec"][:400_000]
+    rec = trained["rec"][:2_000_000]
     r = rec.cpu().numpy().astype(np.float64)
     gpu_ctx.krt_escape_calibrate(rec, rec.shape[0])
     n = rec.shape[0]
@@ -153,8 +153,11 @@ def test_calibration_unbiased_per_bin(gpu_ctx, trained):
     out = torch.zeros((n, NO), dtype=torch.float32, device=rec.device)
     gpu_ctx.krt_escape_forward(inp.contiguous(), out)
     pred = np.exp(out[:, mlp.O_LOGN].cpu().numpy().astype(np.float64))
-    b = np.clip(((r[:, 0] - 1.0) * 8.0).astype(int), 0, 31)
-    for k in range(32):
+    ax = np.abs(r[:, 2])
+    bx = np.where(ax < 2.0, np.minimum((ax * 2.0).astype(int), 3),
+                  np.where(ax < 4.0, 3 + (ax - 1.0).astype(int), np.where(ax < 6.0, 6, 7)))
+    b = np.clip(((r[:, 0] - 1.0) * 8.0).astype(int), 0, 31) * 8 + bx
+    for k in range(256):
         m = b == k
         if m.sum() < 1000:
             continue
