@@ -183,6 +183,48 @@ def learned_escape_leg(ctx, n=128, packets=10_000_000, tau_min=100.0):
     }
 
 
+def expanding_sphere_leg(ctx, packets=10_000_000):
+    """128^3 homologously expanding sphere (v = 20 r, tau0 = 1e5, a = 1e-3, isotropic
+    R_IIA, Voigt volume source; 512-bin spectrum, 128^3 x 64-channel emissivity)."""
+    from paper_2608_09340_amd import krt, workloads as W
+    T = krt.Transport(W.expanding_sphere_c2(), ctx=ctx)
+    r = T.run(packets, seed=0)
+    ms = ctx.krt_last_transport_ms()
+    if r["rc"]:
+        raise RuntimeError("expanding-sphere leg failed")
+    c = r["counters"]
+    log(f"expanding sphere: {ms:.0f} ms")
+    return {"workload": "expanding sphere 128^3, v = 20 r, tau0=1e5, a=1e-3, isotropic R_IIA, Voigt volume "
+                        f"source, spectrum 512 bins, emissivity 128^3 x 64 channels, {packets} packets",
+            "kernel_ms": ms, "scatterings": c["scatterings"], "scatterings_per_s": c["scatterings"] / (ms * 1e-3),
+            "packets_per_s": packets / (ms * 1e-3), "crossings": c["crossings"]}
+
+
+def lambda_leg(ctx, n=128, packets=10_000_000):
+    """One Lambda-iteration cycle on the 128^3 turbulent cloud with the 5-level
+    rotor: transport of each of the 4 lines with the mean-intensity tally, then
+    the FP64 level solve of every cell."""
+    import torch
+    from paper_2608_09340_amd import workloads as W
+    from paper_2608_09340_amd.lambda_iter import LambdaIteration
+    lam = LambdaIteration(W.cloud_c3(n=n), ctx)
+    runs = [lam.transport_line(l, packets, seed=l) for l in range(lam.nlines)]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    lam._levels(lam.jbar)
+    torch.cuda.synchronize()
+    t_lev = time.perf_counter() - t
+    if any(r["rc"] for r in runs):
+        raise RuntimeError("lambda leg failed")
+    log(f"lambda iteration: {sum(r['kernel_ms'] for r in runs):.0f} ms transport")
+    return {"workload": f"turbulent cloud {n}^3, 5-level rotor, 4 lines, {packets} packets per line, "
+                        "one transport + level-solve cycle",
+            "transport_kernel_ms_per_line": [r["kernel_ms"] for r in runs],
+            "scatterings_per_line": [r["counters"]["scatterings"] for r in runs],
+            "destroyed_per_line": [r["counters"]["destroyed"] for r in runs],
+            "level_solve_ms": t_lev * 1e3, "cells": lam.ncell}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -191,6 +233,7 @@ def main():
     ap.add_argument("--packets", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-escape", action="store_true", help="skip the learned-escape comparison leg")
+    ap.add_argument("--no-extra", action="store_true", help="skip the expanding-sphere and Lambda-iteration legs")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (calibrates FETCH_SIZE/WRITE_SIZE)")
@@ -266,6 +309,9 @@ def main():
                      "frac": achieved / PEAK_VALU_TOPS, "traffic": profiled_traffic(),
                      "ops_per_scattering": lps},
     }
+    if not args.no_extra:
+        out["expanding_sphere"] = expanding_sphere_leg(ctx)
+        out["lambda_iteration"] = lambda_leg(ctx)
     if not args.no_escape:
         out["learned_escape"] = learned_escape_leg(ctx)
     if not args.no_cpu_baseline:
