@@ -99,7 +99,7 @@ def cpu_info():
     return model, os.cpu_count() or 1
 
 
-def cpu_baseline(prob, seconds_target=15.0):
+def cpu_baseline(prob, seconds_target=40.0):
     """The FP64 oracle as it stands, on all host cores, on a bounded sample."""
     import oracle
     model, ncpu = cpu_info()
