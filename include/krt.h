@@ -147,11 +147,6 @@ typedef struct {
                                   this many live lanes lets its idle lanes precompute the live
                                   packets' random draws (0 = 32, negative = never); the tallies
                                   are the same either way */
-    int32_t compact_lanes;     /* plain transport with 1024-lane workgroups: once the pool is
-                                  exhausted, a wave other than the first four of its workgroup
-                                  with at most this many live packets hands them to those four
-                                  (one per SIMD) through LDS and ends (0 = off, at most 32); the
-                                  tallies are the same either way */
 } krt_run_opts;
 
 /* Caller-allocated DEVICE buffers.  Raw tallies are int64 fixed point, so their

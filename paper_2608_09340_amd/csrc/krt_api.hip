@@ -365,7 +365,6 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
     P.esc_tail_lanes = o->esc_tail_lanes > 0 ? o->esc_tail_lanes : 1;
     P.esc_evals = o->esc_evals == 2 ? 2 : 4;
     P.tail_lanes = o->tail_lanes == 0 ? 32 : (o->tail_lanes < 0 ? 0 : std::min(o->tail_lanes, 64));
-    P.compact_lanes = o->compact_lanes == 0 ? 0 : (o->compact_lanes < 0 ? 0 : std::min(o->compact_lanes, kCompactMaxLanes));
     int grid = c->cus * per_cu;
     HIPCHK(c, hipEventRecord(c->ev0, c->stream));
     HIPCHK(c, launch_transport(P, grid, block, c->stream));

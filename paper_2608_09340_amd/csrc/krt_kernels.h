@@ -32,11 +32,6 @@ constexpr int kEdgeFloats = (kMaxSpecBins + 1) + (kMaxChannels + 1) + 2;  // pad
 // 1 / ln((300/8)^(1/15)): logarithmic row spacing of the sampler above |x| = 8
 constexpr float kRowInvLog = 4.1386840f;
 
-// tail compaction: keeper waves per 16-wave workgroup, packet state words per
-// LDS queue slot, largest hand-over size; LDS per CU
-constexpr int kKeepers = 4, kQWords = 19, kCompactMaxLanes = 32;
-constexpr size_t kLdsBytes = 160 * 1024;
-
 struct RunParams {
     // grid
     int n[3];
@@ -80,7 +75,6 @@ struct RunParams {
     int esc_tail_lanes;
     int esc_evals;
     int tail_lanes;
-    int compact_lanes;
 };
 
 hipError_t launch_transport(const RunParams &P, int grid, int block, hipStream_t s);

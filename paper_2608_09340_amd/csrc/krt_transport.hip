@@ -147,24 +147,6 @@ __global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
             for (int i = threadIdx.x; i < kMlpFwdBytes / 16; i += blockDim.x) md[i] = ms[i];
         }
     }
-    // Tail compaction (plain transport, 16-wave workgroups): once the packet pool
-    // is exhausted, a wave other than the first four (one per SIMD, the keepers)
-    // with at most compact_lanes live packets hands them to the keepers through
-    // an LDS queue and ends, so the last packets of the workgroup run in waves
-    // that do not share a SIMD.  Queue: kQWords state words per slot (SoA), a
-    // ready flag per slot, counters [0] slots reserved, [1] slots claimed,
-    // [2] waves other than the keepers still running.
-    const int wid = threadIdx.x >> 6;
-    const bool compact = !kEsc && P.compact_lanes > 0 && blockDim.x == 1024;
-    const bool keeper = wid < kKeepers;
-    const int qslots = compact ? ((int)(blockDim.x >> 6) - kKeepers) * P.compact_lanes : 0;
-    uint32_t *lq = reinterpret_cast<uint32_t *>(T + kTabFloats + kEdgeFloats);
-    uint32_t *qready = lq + kQWords * qslots;
-    uint32_t *qctr = qready + qslots;
-    if (compact) {
-        for (int i = threadIdx.x; i < qslots; i += blockDim.x) qready[i] = 0u;
-        if (threadIdx.x == 0) { qctr[0] = 0u; qctr[1] = 0u; qctr[2] = (blockDim.x >> 6) - kKeepers; }
-    }
     __syncthreads();
     const unsigned char *mimg = reinterpret_cast<const unsigned char *>(lds4 + (kTabFloats + kEdgeFloats) / 4);
     const float *mbias = reinterpret_cast<const float *>(mimg + kTilesFwd * kTileBytes);
@@ -413,91 +395,10 @@ __global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
                 }
             }
         }
-        // ---- tail compaction: keepers take packets handed over by other waves ----
-        bool pending = false;  // a keeper may still receive packets
-        if (compact && keeper && __ballot(done) != 0ull) {
-            const uint64_t free_mask = __ballot(!have);
-            uint32_t h = 0, n = 0;
-            if (lane == 0) {
-                for (int tries = 0; tries < 64; ++tries) {
-                    h = __hip_atomic_load(&qctr[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    const uint32_t t = __hip_atomic_load(&qctr[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    n = min(t - h, (uint32_t)__popcll(free_mask));
-                    if (n == 0u) break;
-                    if (atomicCAS(&qctr[1], h, h + n) == h) break;
-                    n = 0u;
-                }
-            }
-            h = __shfl(h, 0, 64);
-            n = __shfl(n, 0, 64);
-            const uint32_t frank = (uint32_t)__popcll(free_mask & lanemask_lt);
-            if (!have && frank < n) {
-                const int sl = (int)(h + frank);
-                // the slot was reserved by a wave that is writing it: bounded wait
-                while (__hip_atomic_load(&qready[sl], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == 0u)
-                    __builtin_amdgcn_s_sleep(1);
-                pid = (uint64_t)lq[0 * qslots + sl] | ((uint64_t)lq[1 * qslots + sl] << 32);
-                ev = lq[2 * qslots + sl];
-                ci = (int)lq[3 * qslots + sl]; cj = (int)lq[4 * qslots + sl]; ck = (int)lq[5 * qslots + sl];
-                fx = __uint_as_float(lq[6 * qslots + sl]); fy = __uint_as_float(lq[7 * qslots + sl]);
-                fz = __uint_as_float(lq[8 * qslots + sl]);
-                nx = __uint_as_float(lq[9 * qslots + sl]); ny = __uint_as_float(lq[10 * qslots + sl]);
-                nz = __uint_as_float(lq[11 * qslots + sl]);
-                x = __uint_as_float(lq[12 * qslots + sl]); tau = __uint_as_float(lq[13 * qslots + sl]);
-                wa1 = lq[14 * qslots + sl]; wa2 = lq[15 * qslots + sl]; wa3 = lq[16 * qslots + sl];
-                nscat_pkt = lq[17 * qslots + sl]; ncross_pkt = lq[18 * qslots + sl];
-                cell = (ck * P.n[1] + cj) * P.n[0] + ci;
-                k0c = P.k0[cell];
-                if (P.vx) { vxc = P.vx[cell]; vyc = P.vy[cell]; vzc = P.vz[cell]; }
-                else { vxc = vyc = vzc = 0.0f; }
-                epsc = P.eps ? P.eps[cell] : 0.0f;
-                jacc = 0;
-                outcome = 0;
-                have = true;
-            }
-            pending = __hip_atomic_load(&qctr[2], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != 0u ||
-                      __hip_atomic_load(&qctr[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) !=
-                          __hip_atomic_load(&qctr[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            pending = __ballot(pending) != 0ull;  // wave-uniform
-        }
-
         const uint64_t live_mask = __ballot(have);
-        if (live_mask == 0ull) {
-            if (pending) {  // a keeper waits for packets still to be handed over
-                __builtin_amdgcn_s_sleep(8);
-                continue;
-            }
-            break;
-        }
-        // ---- tail compaction: a sparse wave other than the keepers hands over ----
-        if (compact && !keeper && __ballot(done) != 0ull && __popcll(live_mask) <= P.compact_lanes) {
-            const int leader = __ffsll((long long)live_mask) - 1;
-            uint32_t base = 0;
-            if (lane == leader) base = atomicAdd(&qctr[0], (uint32_t)__popcll(live_mask));
-            base = __shfl(base, leader, 64);
-            if (have) {
-                // the register tallies of the current cell go to memory first
-                if (P.jbar_raw && jacc != 0) { atomic_add_i64(P.jbar_raw + cell, jacc, status); jacc = 0; }
-                if (P.emis_raw) emis_flush(E, P.emis_raw + (int64_t)cell * P.emis_nch, P.emis_nch, status);
-                const int sl = (int)(base + (uint32_t)__popcll(live_mask & lanemask_lt));
-                lq[0 * qslots + sl] = (uint32_t)pid; lq[1 * qslots + sl] = (uint32_t)(pid >> 32);
-                lq[2 * qslots + sl] = ev;
-                lq[3 * qslots + sl] = (uint32_t)ci; lq[4 * qslots + sl] = (uint32_t)cj; lq[5 * qslots + sl] = (uint32_t)ck;
-                lq[6 * qslots + sl] = __float_as_uint(fx); lq[7 * qslots + sl] = __float_as_uint(fy);
-                lq[8 * qslots + sl] = __float_as_uint(fz);
-                lq[9 * qslots + sl] = __float_as_uint(nx); lq[10 * qslots + sl] = __float_as_uint(ny);
-                lq[11 * qslots + sl] = __float_as_uint(nz);
-                lq[12 * qslots + sl] = __float_as_uint(x); lq[13 * qslots + sl] = __float_as_uint(tau);
-                lq[14 * qslots + sl] = wa1; lq[15 * qslots + sl] = wa2; lq[16 * qslots + sl] = wa3;
-                lq[17 * qslots + sl] = nscat_pkt; lq[18 * qslots + sl] = ncross_pkt;
-                __hip_atomic_store(&qready[sl], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-                have = false;
-            }
-            break;
-        }
+        if (live_mask == 0ull) break;
         // pool exhausted and few live lanes: continue in tail mode
-        if (!kEsc && P.tail_lanes > 0 && !pending && __ballot(done) != 0ull &&
-            __popcll(live_mask) <= P.tail_lanes) {
+        if (!kEsc && P.tail_lanes > 0 && __ballot(done) != 0ull && __popcll(live_mask) <= P.tail_lanes) {
             tail = true;
             break;
         }
@@ -708,9 +609,6 @@ __global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
         }
     }
 
-    if (compact && !keeper && __lane_id() == 0)
-        __hip_atomic_fetch_add(&qctr[2], 0xFFFFFFFFu, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-
     wave_add_counter(P.counters + KRT_C_EMITTED, c_emit);
     wave_add_counter(P.counters + KRT_C_ESCAPED, c_esc);
     wave_add_counter(P.counters + KRT_C_DESTROYED, c_des);
@@ -784,16 +682,11 @@ __global__ void debug_upar_kernel(const float *tab, float a, float thd, float x,
 hipError_t launch_transport(const RunParams &P, int grid, int block, hipStream_t s) {
     const bool esc = P.mlp_img != nullptr;
     size_t lds = sizeof(float) * (kTabFloats + kEdgeFloats) + (esc ? (size_t)kMlpFwdBytes : 0);
-    if (!esc && P.compact_lanes > 0 && block == 1024) {
-        const size_t qslots = (size_t)(block / 64 - kKeepers) * (size_t)P.compact_lanes;
-        lds += sizeof(uint32_t) * ((kQWords + 1) * qslots + 4);
-    }
-    if (lds > kLdsBytes) return hipErrorInvalidValue;
     static bool attr_set[2] = {false, false};
     const void *fn = esc ? reinterpret_cast<const void *>(mc_transport_kernel<true>)
                          : reinterpret_cast<const void *>(mc_transport_kernel<false>);
     if (!attr_set[esc]) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_set[esc] = true;
     }

@@ -42,8 +42,7 @@ class krt_run_opts(C.Structure):
                 ("emis_frac_bits", C.c_int32), ("jbar_frac_bits", C.c_int32),
                 ("norm_packets", C.c_uint64), ("luminosity", C.c_double),
                 ("esc_tau_min", C.c_double), ("esc_min_lanes", C.c_int32),
-                ("esc_tail_lanes", C.c_int32), ("esc_evals", C.c_int32), ("tail_lanes", C.c_int32),
-                ("compact_lanes", C.c_int32)]
+                ("esc_tail_lanes", C.c_int32), ("esc_evals", C.c_int32), ("tail_lanes", C.c_int32)]
 
 
 class krt_tallies(C.Structure):
@@ -248,7 +247,7 @@ class Context:
 def make_opts(prob: dict, *, line=0, packet_offset=0, accumulate=False, max_events=0,
               wg_size=0, wg_per_cu=0, emis_frac_bits=0, jbar_frac_bits=0, norm_packets=0, escape_mode=0,
               luminosity=0.0, esc_tau_min=0.0, esc_min_lanes=0, esc_tail_lanes=0,
-              esc_evals=0, tail_lanes=0, compact_lanes=0) -> krt_run_opts:
+              esc_evals=0, tail_lanes=0) -> krt_run_opts:
     """krt_run_opts from a workload problem dict (paper_2608_09340_amd.workloads)."""
     o = krt_run_opts()
     src, t = prob["source"], prob["tally"]
@@ -282,7 +281,6 @@ def make_opts(prob: dict, *, line=0, packet_offset=0, accumulate=False, max_even
     o.esc_tail_lanes = int(esc_tail_lanes)
     o.esc_evals = int(esc_evals)
     o.tail_lanes = int(tail_lanes)
-    o.compact_lanes = int(compact_lanes)
     return o
 
 
