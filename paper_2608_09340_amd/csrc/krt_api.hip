@@ -343,6 +343,7 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
     P.ch_inv_w = o->emis_nch > 0 ? (float)(o->emis_nch / (o->ch_hi - o->ch_lo)) : 0.0f;
     P.ch_edges = c->edges + kMaxSpecBins + 1;
     P.frac_scale = std::ldexp(1.0f, fb);
+    P.emis_w32 = fb <= 30 ? 1 : 0;
     P.jbar_scale = std::ldexp(1.0f, fj);
     P.spec_raw = t->spec_raw_dev;
     P.emis_raw = o->emis_nch > 0 ? t->emis_raw_dev : nullptr;
@@ -369,6 +370,10 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
     HIPCHK(c, hipEventRecord(c->ev0, c->stream));
     HIPCHK(c, launch_transport(P, grid, block, c->stream));
     HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+    // integer tallies that left [0, 2^62] (the transport's atomics return nothing)
+    HIPCHK(c, launch_saturation_check(t->spec_raw_dev, nsb, P.status, c->stream));
+    if (o->emis_nch > 0) HIPCHK(c, launch_saturation_check(t->emis_raw_dev, nc * o->emis_nch, P.status, c->stream));
+    if (o->jbar) HIPCHK(c, launch_saturation_check(t->jbar_raw_dev, nc, P.status, c->stream));
 
     // finalise (FP64 scaling -> FP32)
     const double N = (double)(o->norm_packets ? o->norm_packets : n_packets);

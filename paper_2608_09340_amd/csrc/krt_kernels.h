@@ -75,11 +75,13 @@ struct RunParams {
     int esc_tail_lanes;
     int esc_evals;
     int tail_lanes;
+    int emis_w32;  // emissivity contributions fit 32 bits (fraction bits <= 30)
 };
 
 hipError_t launch_transport(const RunParams &P, int grid, int block, hipStream_t s);
 hipError_t launch_finalize(const int64_t *raw, float *out, int64_t n, double scale, hipStream_t s);
 hipError_t launch_zero_i64(int64_t *p, int64_t n, hipStream_t s);
+hipError_t launch_saturation_check(const int64_t *p, int64_t n, uint32_t *status, hipStream_t s);
 hipError_t launch_debug_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out, int64_t n,
                                hipStream_t s);
 hipError_t launch_debug_bins(const float *x, int64_t n, int nb, const float *edges, float inv_w, int32_t *out,

@@ -21,35 +21,41 @@
 namespace krt {
 
 // --------------------------------------------------------- tally helpers ---
-__device__ __forceinline__ void atomic_add_i64(int64_t *p, int64_t v, uint32_t *status) {
-    unsigned long long old = atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)v);
-    if ((long long)old > (1LL << 62)) atomicOr(status, (uint32_t)KRT_ST_SATURATE_BIT);
+// Integer tally atomics return nothing, so a wave never waits on them; sums
+// past 2^62 are detected after the launch (saturation_check_kernel).
+__device__ __forceinline__ void tally_add_i64(int64_t *p, int64_t v) {
+    atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)v);
 }
 
-struct EmisCache {  // four direct-mapped (channel -> fixed-point sum) slots
+// Four direct-mapped (channel -> fixed-point sum) slots, slot = channel & 3; a
+// slot is written back only when another channel takes it or the packet leaves
+// the cell.
+struct EmisCache {
     int ch[4];
     int64_t acc[4];
 };
 
-__device__ __forceinline__ void emis_flush(EmisCache &E, int64_t *base, int nch, uint32_t *status) {
+__device__ __forceinline__ void emis_reset(EmisCache &E) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) { E.ch[s] = -1; E.acc[s] = 0; }
+}
+
+__device__ __forceinline__ void emis_flush(EmisCache &E, int64_t *base) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-        if (E.ch[s] >= 0) {
-            atomic_add_i64(base + E.ch[s], E.acc[s], status);
-            E.ch[s] = -1;
-            E.acc[s] = 0;
-        }
+        if (E.ch[s] >= 0) tally_add_i64(base + E.ch[s], E.acc[s]);
+        E.ch[s] = -1;
+        E.acc[s] = 0;
     }
 }
 
-__device__ __forceinline__ void emis_add(EmisCache &E, int ch, int64_t v, int64_t *base,
-                                         uint32_t *status) {
-    int slot = ch & 3;
+__device__ __forceinline__ void emis_add(EmisCache &E, int ch, int64_t v, int64_t *base) {
+    const int slot = ch & 3;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         if (s == slot) {
             if (E.ch[s] != ch) {
-                if (E.ch[s] >= 0) atomic_add_i64(base + E.ch[s], E.acc[s], status);
+                if (E.ch[s] >= 0) tally_add_i64(base + E.ch[s], E.acc[s]);
                 E.ch[s] = ch;
                 E.acc[s] = 0;
             }
@@ -169,8 +175,7 @@ __global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
     int outcome = 0;  // 1 escaped, 2 destroyed, 3 stuck
     int64_t jacc = 0;
     EmisCache E;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) { E.ch[s] = -1; E.acc[s] = 0; }
+    emis_reset(E);
     // per-lane counters
     int64_t c_emit = 0, c_esc = 0, c_des = 0, c_scat = 0, c_cross = 0, c_stuck = 0, c_drop = 0;
     int64_t c_mlp = 0, c_skip = 0;
@@ -217,8 +222,8 @@ __global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
             c_cross += 1;
             ncross_pkt += 1;
             // leaving the cell: flush its register tallies
-            if (P.jbar_raw && jacc != 0) { atomic_add_i64(P.jbar_raw + cell, jacc, status); jacc = 0; }
-            if (P.emis_raw) emis_flush(E, P.emis_raw + (int64_t)cell * P.emis_nch, P.emis_nch, status);
+            if (P.jbar_raw && jacc != 0) { tally_add_i64(P.jbar_raw + cell, jacc); jacc = 0; }
+            if (P.emis_raw) emis_flush(E, P.emis_raw + (int64_t)cell * P.emis_nch);
             bool escaped = false;
             if (ax == 0) {
                 int st = (nx > 0.0f) ? 1 : -1;
@@ -281,8 +286,10 @@ __global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
             int kb = bin_index(xcam, cedges, P.emis_nch, P.ch_inv_w);
             if (kb >= 1 && kb <= P.emis_nch) {
                 float wph = (P.phase == KRT_PHASE_DIPOLE_I) ? 0.75f * (1.0f + gc * gc) : 1.0f;
-                emis_add(E, kb - 1, (int64_t)__float2ll_rn(wph * P.frac_scale),
-                         P.emis_raw + (int64_t)cell * P.emis_nch, status);
+                // contributions below 2^32 (F <= 30) convert through 32 bits
+                const float wf = wph * P.frac_scale;
+                const int64_t wq = P.emis_w32 ? (int64_t)__float2uint_rn(wf) : (int64_t)__float2ll_rn(wf);
+                emis_add(E, kb - 1, wq, P.emis_raw + (int64_t)cell * P.emis_nch);
             } else {
                 c_drop += 1;
             }
@@ -295,8 +302,8 @@ __global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
 
     // a retired packet: flush the tallies of its last cell, log it
     auto retire = [&]() {
-        if (P.jbar_raw && jacc != 0) { atomic_add_i64(P.jbar_raw + cell, jacc, status); jacc = 0; }
-        if (P.emis_raw) emis_flush(E, P.emis_raw + (int64_t)cell * P.emis_nch, P.emis_nch, status);
+        if (P.jbar_raw && jacc != 0) { tally_add_i64(P.jbar_raw + cell, jacc); jacc = 0; }
+        if (P.emis_raw) emis_flush(E, P.emis_raw + (int64_t)cell * P.emis_nch);
         if (P.plog) {
             float *L = P.plog + 8 * (pid - P.packet_offset);
             L[0] = x; L[1] = (float)nscat_pkt; L[2] = (float)outcome;
@@ -508,7 +515,7 @@ __global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
                             cdf_lo = cdf_hi;
                             inside += fr;
                             int64_t wq = (int64_t)__float2ll_rn(W * fr);
-                            if (wq != 0) emis_add(E, kb - 1, wq, ebase, status);
+                            if (wq != 0) emis_add(E, kb - 1, wq, ebase);
                         }
                         c_drop += (int64_t)__float2ll_rn(Ns * fmaxf(0.0f, 1.0f - inside));
                     }
@@ -629,6 +636,15 @@ __global__ void finalize_kernel(const int64_t *raw, float *out, int64_t n, doubl
     for (; i < n; i += stride) out[i] = (float)((double)raw[i] * scale);
 }
 
+// Sets the saturation bit if any integer tally left [0, 2^62].
+__global__ void saturation_check_kernel(const int64_t *p, int64_t n, uint32_t *status) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    for (; i < n; i += stride) bad |= (p[i] < 0) || (p[i] > (int64_t(1) << 62));
+    if (__ballot(bad) != 0ull && __lane_id() == 0) atomicOr(status, (uint32_t)KRT_ST_SATURATE_BIT);
+}
+
 __global__ void zero_i64_kernel(int64_t *p, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -699,6 +715,13 @@ hipError_t launch_finalize(const int64_t *raw, float *out, int64_t n, double sca
     if (n <= 0) return hipSuccess;
     int grid = (int)std::min<int64_t>((n + 255) / 256, 65536);
     hipLaunchKernelGGL(finalize_kernel, dim3(grid), dim3(256), 0, s, raw, out, n, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_saturation_check(const int64_t *p, int64_t n, uint32_t *status, hipStream_t s) {
+    if (n <= 0 || !p) return hipSuccess;
+    int grid = (int)std::min<int64_t>((n + 255) / 256, 16384);
+    hipLaunchKernelGGL(saturation_check_kernel, dim3(grid), dim3(256), 0, s, p, n, status);
     return hipGetLastError();
 }
 

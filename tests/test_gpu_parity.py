@@ -196,3 +196,21 @@ def test_thin_box_per_packet(gpu_ctx):
     ho = np.bincount(o[:, 1].astype(int), minlength=8)[:6]
     chi2, dof, zmax = chi2_two_sample(hg, ho, min_count=10)
     assert zmax < 4.5, (hg, ho)
+
+
+def test_tally_saturation_is_reported(gpu_ctx):
+    """An emissivity bin pushed past 2^62 (fraction bits 40, one thick cell, a
+    few channels) makes krt_mc_run return KRT_EDEVICE with the saturation bit
+    set; the same run at the default 20 bits is clean."""
+    from paper_2608_09340_amd import krt
+    p = W._problem((1, 1, 1), (-1.0,) * 3, (1.0,) * 3, (0, 0, 0), np.array([2000.0]), 1e-2,
+                   source={"kind": W.SRC_POINT, "pos": (0.0, 0.0, 0.0), "profile": W.PROF_DELTA, "x0": 0.0},
+                   tally={"spec_nbins": 16, "spec_lo": -16.0, "spec_hi": 16.0, "emis_nch": 4, "ch_lo": -2.0,
+                          "ch_hi": 2.0, "n_cam": (1.0, 0.0, 0.0)})
+    T = krt.Transport(p, ctx=gpu_ctx)
+    ok = T.run(20000, seed=1)
+    assert ok["rc"] == 0 and ok["counters"]["status"] == 0
+    assert ok["emis_raw"].max() > (1 << 22)  # > 2^22 contributions in one channel
+    bad = T.run(20000, seed=1, emis_frac_bits=40)
+    assert bad["rc"] == krt.KRT_EDEVICE
+    assert bad["counters"]["status"] & 4
