@@ -282,6 +282,18 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
+    # imaging pass over the step's emissivity toward the camera (+x)
+    T.image(axis=0)
+    img_ms = []
+    for _ in range(5):
+        T.image(axis=0)
+        img_ms.append(ctx.krt_last_image_ms())
+    nx, ny, nz = T.n
+    ncell, nch = T.ncell, T.nch
+    img_bytes = ncell * nch * 4 + ncell * 4 + ny * nz * nch * 4  # emissivity, k0 (static medium), image
+    img_t = min(img_ms) * 1e-3
+    log(f"imaging: {min(img_ms):.3f} ms")
+
     lps = ledger_per_scatter(dipole, emis)
     kms = sum(kern_ms) / len(kern_ms)
     achieved = (scat / args.steps) * lps / (kms * 1e-3) / 1e12
@@ -308,6 +320,12 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
                      "frac": achieved / PEAK_VALU_TOPS, "traffic": profiled_traffic(),
                      "ops_per_scattering": lps},
+    }
+    out["imaging"] = {
+        "what": f"ray-traced image toward +x of the step's emissivity, {ny}x{nz} pixels x {nch} channels",
+        "kernel_ms": min(img_ms),
+        "roofline": {"bound": "hbm", "achieved": img_bytes / img_t / 1e9, "peak": 8000.0, "unit": "GB/s",
+                     "frac": img_bytes / img_t / 8e12, "bytes_per_launch": img_bytes},
     }
     if not args.no_extra:
         out["expanding_sphere"] = expanding_sphere_leg(ctx)

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkrt.so")
-SOURCES = ["krt_api.hip", "krt_transport.hip", "krt_escape.hip", "krt_tables.cpp"]
+SOURCES = ["krt_api.hip", "krt_transport.hip", "krt_escape.hip", "krt_image.hip", "krt_tables.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # packed-FP32 VALU forms are disabled for all device code

@@ -46,6 +46,7 @@ struct krt_ctx {
     int mlp_step = 0;
     unsigned char *mlp_blob = nullptr, *mlp_img = nullptr;
     double *mlp_calsum = nullptr;
+    float last_image_ms = 0.0f;
 };
 
 namespace {
@@ -396,6 +397,47 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
     if (st != 0) return fail(c, KRT_EDEVICE, "device status 0x%llx (nan=1 stuck=2 saturate=4)", (long long)st);
     return KRT_OK;
 }
+
+// -------------------------------------------------------------- imaging ---
+extern "C" int krt_image(krt_ctx *c, const krt_image_desc *d) {
+    if (!c) return KRT_EINVAL;
+    if (!d) return fail(c, KRT_EINVAL, "image desc NULL");
+    if (!c->have_grid) return fail(c, KRT_ESTATE, "no grid uploaded");
+    if (d->line < 0 || d->line >= (int)c->tab.size() || d->line >= c->grid.n_lines)
+        return fail(c, KRT_ESTATE, "line %d has no tables or no opacity slice", d->line);
+    if (d->axis < 0 || d->axis > 5) return fail(c, KRT_EINVAL, "axis %d outside 0..5", d->axis);
+    if (d->nch < 1 || d->nch > 256) return fail(c, KRT_EINVAL, "nch %d outside 1..256", d->nch);
+    if (!(d->ch_hi > d->ch_lo)) return fail(c, KRT_EINVAL, "empty channel range");
+    if (!d->emis_dev || !d->image_dev) return fail(c, KRT_EINVAL, "image desc has NULL arrays");
+    const krt_grid_desc &g = c->grid;
+    ImageParams Q{};
+    Q.d = d->axis % 3;
+    Q.sgn = d->axis < 3 ? 1 : -1;
+    Q.sgnf = (float)Q.sgn;
+    for (int k = 0; k < 3; ++k) Q.n[k] = g.n[k];
+    Q.dl = (float)((g.hi[Q.d] - g.lo[Q.d]) / g.n[Q.d]);
+    if (Q.d == 0) { Q.n0 = g.n[1]; Q.npix = (int64_t)g.n[1] * g.n[2]; Q.stride = 1; }
+    else if (Q.d == 1) { Q.n0 = g.n[0]; Q.npix = (int64_t)g.n[0] * g.n[2]; Q.stride = g.n[0]; }
+    else { Q.n0 = g.n[0]; Q.npix = (int64_t)g.n[0] * g.n[1]; Q.stride = (int64_t)g.n[0] * g.n[1]; }
+    Q.nch = d->nch;
+    Q.ch_lo = (float)d->ch_lo;
+    Q.ch_w = (float)((d->ch_hi - d->ch_lo) / d->nch);
+    Q.tab = c->tab[d->line];
+    Q.k0 = g.k0_dev + (int64_t)d->line * c->ncell;
+    Q.vel_axis = g.vel_dev ? g.vel_dev + (int64_t)Q.d * c->ncell : nullptr;
+    Q.emis = d->emis_dev;
+    Q.srcf = d->src_dev;
+    Q.out = d->image_dev;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+    HIPCHK(c, launch_image(Q, c->stream));
+    HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipEventElapsedTime(&c->last_image_ms, c->ev0, c->ev1));
+    return KRT_OK;
+}
+
+extern "C" float krt_last_image_ms(const krt_ctx *c) { return c ? c->last_image_ms : -1.0f; }
 
 // --------------------------------------------------------------- levels ---
 // Per-cell rate matrix, FP64 Gaussian elimination with partial pivoting.

@@ -32,6 +32,21 @@ constexpr int kEdgeFloats = (kMaxSpecBins + 1) + (kMaxChannels + 1) + 2;  // pad
 // 1 / ln((300/8)^(1/15)): logarithmic row spacing of the sampler above |x| = 8
 constexpr float kRowInvLog = 4.1386840f;
 
+// imaging pass (krt_image.hip)
+struct ImageParams {
+    const float *tab;       // table set of the line (Voigt core and wing used)
+    const float *k0;        // [ncell] line-centre opacity of the line
+    const float *vel_axis;  // [ncell] velocity component along the camera axis, or null
+    const float *emis;      // [ncell][nch]
+    const float *srcf;      // [ncell][nch] or null
+    float *out;             // [npix][nch]
+    int64_t npix, stride;
+    int n[3];
+    int d, sgn, n0, nch;
+    float sgnf, dl, ch_lo, ch_w;
+};
+hipError_t launch_image(const ImageParams &Q, hipStream_t s);
+
 struct RunParams {
     // grid
     int n[3];

@@ -59,12 +59,19 @@ class krt_levels_desc(C.Structure):
                 ("eps_out_dev", C.c_void_p)]
 
 
+class krt_image_desc(C.Structure):
+    _fields_ = [("line", C.c_int32), ("axis", C.c_int32), ("nch", C.c_int32), ("ch_lo", C.c_double),
+                ("ch_hi", C.c_double), ("emis_dev", C.c_void_p), ("src_dev", C.c_void_p),
+                ("image_dev", C.c_void_p)]
+
+
 EXPORTS = ["krt_create", "krt_destroy", "krt_last_error", "krt_device_cus", "krt_last_transport_ms",
            "krt_grid_upload",
            "krt_tables_build", "krt_mc_run", "krt_levels_update", "krt_debug_philox",
            "krt_debug_bins", "krt_debug_voigt", "krt_debug_upar",
            "krt_escape_init", "krt_escape_record", "krt_escape_fit_norm", "krt_escape_calibrate", "krt_escape_grad",
-           "krt_escape_train", "krt_escape_get_weights", "krt_escape_put_weights", "krt_escape_forward"]
+           "krt_escape_train", "krt_escape_get_weights", "krt_escape_put_weights", "krt_escape_forward",
+           "krt_image", "krt_last_image_ms"]
 ESC_NPARAMS, ESC_NNORM, ESC_NOUT, ESC_NCAL = 34696, 272, 8, 256
 
 _lib = None
@@ -106,12 +113,15 @@ def load(path: str = LIB_PATH):
     L.krt_escape_get_weights.argtypes = [p, p, u64]
     L.krt_escape_put_weights.argtypes = [p, p, u64]
     L.krt_escape_forward.argtypes = [p, p, i64, p]
+    L.krt_image.argtypes = [p, C.POINTER(krt_image_desc)]
+    L.krt_last_image_ms.argtypes = [p]
+    L.krt_last_image_ms.restype = C.c_float
     for name in ["krt_grid_upload", "krt_tables_build", "krt_mc_run", "krt_levels_update",
                  "krt_debug_philox", "krt_debug_bins", "krt_debug_voigt", "krt_debug_upar",
                  "krt_escape_init", "krt_escape_record", "krt_escape_fit_norm", "krt_escape_calibrate",
                  "krt_escape_grad",
                  "krt_escape_train", "krt_escape_get_weights", "krt_escape_put_weights",
-                 "krt_escape_forward"]:
+                 "krt_escape_forward", "krt_image"]:
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -230,6 +240,12 @@ class Context:
     def krt_escape_forward(self, inp, out):
         self._check(self.L.krt_escape_forward(self.h, _ptr(inp), inp.shape[0], _ptr(out)))
 
+    def krt_image(self, desc: krt_image_desc):
+        self._check(self.L.krt_image(self.h, C.byref(desc)))
+
+    def krt_last_image_ms(self) -> float:
+        return float(self.L.krt_last_image_ms(self.h))
+
     def krt_debug_philox(self, ctr, key, out):
         self._check(self.L.krt_debug_philox(self.h, _ptr(ctr), _ptr(key), _ptr(out), ctr.shape[0]))
 
@@ -332,6 +348,22 @@ class Transport:
         t.emis_dev = None if self.emis is None else self.emis.data_ptr()
         t.jbar_dev = None if self.jbar is None else self.jbar.data_ptr()
         return t
+
+    def image(self, axis: int = 0, line: int = 0, src=None):
+        """Ray-traced image toward the camera axis from the emissivity of the last run
+        (its FP32 finalised form); returns a [npix][nch] device tensor."""
+        t = self.prob["tally"]
+        nx, ny, nz = self.n
+        npix = {0: ny * nz, 1: nx * nz, 2: nx * ny}[axis % 3]
+        out = self.torch.zeros((npix, self.nch), dtype=self.torch.float32, device=self.dev)
+        d = krt_image_desc()
+        d.line, d.axis, d.nch = int(line), int(axis), int(self.nch)
+        d.ch_lo, d.ch_hi = float(t["ch_lo"]), float(t["ch_hi"])
+        d.emis_dev = self.emis.data_ptr()
+        d.src_dev = None if src is None else src.data_ptr()
+        d.image_dev = out.data_ptr()
+        self.ctx.krt_image(d)
+        return out
 
     def run(self, n_packets: int, seed: int = 0, packet_log: bool = False, **kw) -> dict:
         opts = make_opts(self.prob, **kw)

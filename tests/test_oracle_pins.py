@@ -411,3 +411,69 @@ def test_escape_record_symmetries_and_bounds():
     se = 1.0 / np.sqrt(len(rec))
     for col in (3, 4, 5):
         assert abs(rec[:, col].mean()) < 5 * rec[:, col].std() * se, col
+
+
+# ------------------------------------------------------------- imaging --
+def _img_grid(n, seed=0, tau=1.0, vmax=0.0):
+    rng = np.random.default_rng(seed)
+    nc = n[0] * n[1] * n[2]
+    k0 = tau * rng.uniform(0.5, 1.5, nc)
+    vel = vmax * rng.normal(size=(3, nc)) if vmax else None
+    return k0, vel
+
+
+def test_imaging_thin_limit_is_column_sum():
+    """k0 -> 0: the image is the column integral of the emissivity, sum j dl."""
+    from oracle import imaging
+    n = (3, 4, 5)
+    rng = np.random.default_rng(1)
+    emis = rng.uniform(0, 1, (60, 6))
+    k0 = np.full(60, 1e-14)
+    for axis, d in ((0, 0), (1, 1), (2, 2), (4, 1)):
+        I = imaging.image(n, (0, 0, 0), (1.5, 2.0, 2.5), k0, None, 1e-2, emis, -3.0, 3.0, axis)
+        E = emis.reshape(5, 4, 3, 6)
+        dl = 0.5
+        col = E.sum(axis=2 - d) * dl  # sum over the ray axis (array axes are z, y, x)
+        if d == 0:
+            ref = col.reshape(-1, 6)              # (z, y): pixel k * ny + j
+        elif d == 1:
+            ref = col.reshape(-1, 6)              # (z, x): pixel k * nx + i
+        else:
+            ref = col.reshape(-1, 6)              # (y, x): pixel j * nx + i
+        assert np.allclose(I, ref, rtol=1e-12), axis
+
+
+def test_imaging_uniform_column_closed_form():
+    """Uniform static column of depth tau_k with constant source S_k = j / alpha:
+    I = S (1 - e^{-tau_k}) (the formal solution integrated exactly), both
+    camera senses."""
+    from oracle import imaging, voigt_H
+    n = (7, 1, 1)
+    a, k0v = 1e-2, 0.8
+    xk = -2.0 + (np.arange(8) + 0.5) * 0.5
+    alpha = k0v * voigt_H(a, xk)
+    S = np.linspace(0.5, 2.0, 8)
+    emis = np.tile(S * alpha, (7, 1))
+    for axis in (0, 3):
+        I = imaging.image(n, (0, 0, 0), (7.0, 1.0, 1.0), np.full(7, k0v), None, a, emis, -2.0, 2.0, axis)
+        ref = S * (1 - np.exp(-alpha * 7.0))
+        assert np.allclose(I[0], ref, rtol=1e-12)
+
+
+def test_imaging_order_and_velocity_shift():
+    """Two cells along x: emission in the far cell is attenuated by the near
+    cell's opacity at that cell's gas-frame channel frequency x_k - v_x."""
+    from oracle import imaging, voigt_H
+    a = 1e-2
+    k0 = np.array([0.0, 2.0])          # far cell empty (camera +x): near cell = cell 1
+    vel = np.zeros((3, 2))
+    vel[0, 1] = 1.5
+    emis = np.zeros((2, 4))
+    emis[0] = 1.0                      # far cell emits, thin
+    I = imaging.image((2, 1, 1), (0, 0, 0), (2.0, 1.0, 1.0), k0, vel, a, emis, -2.0, 2.0, 0)
+    xk = -2.0 + (np.arange(4) + 0.5)
+    ref = 1.0 * np.exp(-2.0 * voigt_H(a, xk - 1.5))
+    assert np.allclose(I[0], ref, rtol=1e-12)
+    # camera -x: the emitting cell is now the near one, nothing in front of it
+    I2 = imaging.image((2, 1, 1), (0, 0, 0), (2.0, 1.0, 1.0), k0, vel, a, emis, -2.0, 2.0, 3)
+    assert np.allclose(I2[0], 1.0, rtol=1e-12)
