@@ -194,10 +194,20 @@ def expanding_sphere_leg(ctx, packets=10_000_000):
         raise RuntimeError("expanding-sphere leg failed")
     c = r["counters"]
     log(f"expanding sphere: {ms:.0f} ms")
+    T.image(axis=0)
+    im = []
+    for _ in range(3):
+        T.image(axis=0)
+        im.append(ctx.krt_last_image_ms())
+    nb = T.ncell * T.nch * 4 + T.ncell * 8 + T.n[1] * T.n[2] * T.nch * 4  # emissivity, k0 + v_x, image
+    t_im = min(im) * 1e-3
     return {"workload": "expanding sphere 128^3, v = 20 r, tau0=1e5, a=1e-3, isotropic R_IIA, Voigt volume "
                         f"source, spectrum 512 bins, emissivity 128^3 x 64 channels, {packets} packets",
             "kernel_ms": ms, "scatterings": c["scatterings"], "scatterings_per_s": c["scatterings"] / (ms * 1e-3),
-            "packets_per_s": packets / (ms * 1e-3), "crossings": c["crossings"]}
+            "packets_per_s": packets / (ms * 1e-3), "crossings": c["crossings"],
+            "imaging": {"what": "image toward +x, 128x128 pixels x 64 channels", "kernel_ms": min(im),
+                        "roofline": {"bound": "hbm", "achieved": nb / t_im / 1e9, "peak": 8000.0, "unit": "GB/s",
+                                     "frac": nb / t_im / 8e12, "bytes_per_launch": nb}}}
 
 
 def lambda_leg(ctx, n=128, packets=10_000_000):

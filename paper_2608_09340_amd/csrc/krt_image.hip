@@ -20,6 +20,7 @@
 namespace krt {
 
 constexpr int kImgVoigtFloats = kOffVoigtWing + 4 * kVoigtWingN;  // core and wing of H(a, x)
+constexpr int kImgChunk = 8;                                        // cells loaded ahead
 
 __global__ void __launch_bounds__(256) image_kernel(ImageParams Q) {
     __shared__ float4 tv4[kImgVoigtFloats / 4];
@@ -41,19 +42,35 @@ __global__ void __launch_bounds__(256) image_kernel(ImageParams Q) {
     const float xk = Q.ch_lo + ((float)c + 0.5f) * Q.ch_w;
     const float *vd = Q.vel_axis;  // velocity component along the camera axis, or null
     float I = 0.0f;
-    for (int t = 0; t < nl; ++t) {
-        const int s = (Q.sgn > 0) ? t : nl - 1 - t;  // far side first
-        const int64_t cell = cell0 + (int64_t)s * Q.stride;
-        const float k0 = Q.k0[cell];
-        const float xg = xk - (vd ? Q.sgnf * vd[cell] : 0.0f);
-        const float H = (k0 > 0.0f) ? voigt_lds(TV, fabsf(xg)) : 0.0f;
-        const float dtau = k0 * H * Q.dl;
-        const float att = f_exp(-dtau);
-        // (1 - e^{-dtau}) / dtau, with its series below 1e-3
-        const float frac = (dtau < 1e-3f) ? 1.0f - dtau * (0.5f - dtau * (1.0f / 6.0f)) : (1.0f - att) * f_rcp(dtau);
-        const float j = Q.emis[cell * Q.nch + c];
-        I = fmaf(I, att, j * Q.dl * frac);
-        if (Q.srcf) I = fmaf(Q.srcf[cell * Q.nch + c], dtau * frac, I);
+    // the loads of kImgChunk cells are issued together, then the cells are
+    // folded in order: the march is a dependent chain, its memory is not
+    for (int t0 = 0; t0 < nl; t0 += kImgChunk) {
+        float k0v[kImgChunk], vv[kImgChunk], jv[kImgChunk], sv[kImgChunk];
+#pragma unroll
+        for (int u = 0; u < kImgChunk; ++u) {
+            const int t = t0 + u;
+            k0v[u] = 0.0f; vv[u] = 0.0f; jv[u] = 0.0f; sv[u] = 0.0f;
+            if (t < nl) {
+                const int s = (Q.sgn > 0) ? t : nl - 1 - t;  // far side first
+                const int64_t cell = cell0 + (int64_t)s * Q.stride;
+                k0v[u] = Q.k0[cell];
+                if (vd) vv[u] = vd[cell];
+                jv[u] = Q.emis[cell * Q.nch + c];
+                if (Q.srcf) sv[u] = Q.srcf[cell * Q.nch + c];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kImgChunk; ++u) {
+            if (t0 + u >= nl) break;
+            const float xg = xk - Q.sgnf * vv[u];
+            const float H = (k0v[u] > 0.0f) ? voigt_lds(TV, fabsf(xg)) : 0.0f;
+            const float dtau = k0v[u] * H * Q.dl;
+            const float att = f_exp(-dtau);
+            // (1 - e^{-dtau}) / dtau, with its series below 1e-3
+            const float frac = (dtau < 1e-3f) ? 1.0f - dtau * (0.5f - dtau * (1.0f / 6.0f)) : (1.0f - att) * f_rcp(dtau);
+            I = fmaf(I, att, jv[u] * Q.dl * frac);
+            I = fmaf(sv[u], dtau * frac, I);
+        }
     }
     Q.out[tid] = I;
 }
