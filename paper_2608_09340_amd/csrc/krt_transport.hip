@@ -124,6 +124,14 @@ struct SDraws {
     float up1, up2, g, sg, cp, sp;
 };
 
+// A prepared scattering: outgoing direction and gas-frame frequency, the
+// emissivity channel (1-based, out of range = dropped) and its contribution.
+struct ScatPrep {
+    float ox, oy, oz, xo;
+    int kb;
+    int64_t wq;
+};
+
 __device__ __forceinline__ void scatter_draws(uint4 B, bool dipole, SDraws &d) {
     const float rr = f_sqrt(-f_log(u01(B.x)));
     const float th = u01(B.y);
@@ -259,9 +267,13 @@ __global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
         }
     };
 
-    // a resonant scattering of a live lane at gas-frame frequency xc with the
+    // A resonant scattering of a live lane at gas-frame frequency xc with the
     // event's draws (sampler uniforms r1, r2; u_perp components; g, sin, cos psi)
-    auto scatter = [&](float xc, float r1, float r2, const SDraws &b) {
+    // depends only on xc, the direction and the draws, not on where the flight
+    // ends: it is prepared before the flight resolves (so the sampler's LDS
+    // lookups overlap the flight's) and committed if the flight ends in a
+    // scattering.
+    auto prepare = [&](float xc, float r1, float r2, const SDraws &b, ScatPrep &q) {
         const float up1 = b.up1, up2 = b.up2, g = b.g, sg = b.sg, cp = b.cp, sp = b.sp;
         float upar = upar_lds(T, xc, a, thd, r1, r2);
         // orthonormal basis about n (Duff et al. 2017)
@@ -274,28 +286,33 @@ __global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
         float oy = g * ny + sg * (cp * e1y + sp * e2y);
         float oz = g * nz + sg * (cp * e1z + sp * e2z);
         float rn = f_rsq(ox * ox + oy * oy + oz * oz);
-        ox *= rn; oy *= rn; oz *= rn;
+        q.ox = ox * rn; q.oy = oy * rn; q.oz = oz * rn;
         // eq. riia-scatter
-        float xo = xc + upar * (g - 1.0f) + sg * (up1 * cp + up2 * sp);
+        q.xo = xc + upar * (g - 1.0f) + sg * (up1 * cp + up2 * sp);
+        q.kb = -1;
+        q.wq = 0;
         if (P.emis_raw) {
             float gc = nx * P.n_cam[0] + ny * P.n_cam[1] + nz * P.n_cam[2];
             float upc = up1 * (e1x * P.n_cam[0] + e1y * P.n_cam[1] + e1z * P.n_cam[2]) +
                         up2 * (e2x * P.n_cam[0] + e2y * P.n_cam[1] + e2z * P.n_cam[2]);
             float xcam = xc + upar * (gc - 1.0f) + upc +
                          (P.n_cam[0] * vxc + P.n_cam[1] * vyc + P.n_cam[2] * vzc);
-            int kb = bin_index(xcam, cedges, P.emis_nch, P.ch_inv_w);
-            if (kb >= 1 && kb <= P.emis_nch) {
-                float wph = (P.phase == KRT_PHASE_DIPOLE_I) ? 0.75f * (1.0f + gc * gc) : 1.0f;
-                // contributions below 2^32 (F <= 30) convert through 32 bits
-                const float wf = wph * P.frac_scale;
-                const int64_t wq = P.emis_w32 ? (int64_t)__float2uint_rn(wf) : (int64_t)__float2ll_rn(wf);
-                emis_add(E, kb - 1, wq, P.emis_raw + (int64_t)cell * P.emis_nch);
-            } else {
-                c_drop += 1;
-            }
+            q.kb = bin_index(xcam, cedges, P.emis_nch, P.ch_inv_w);
+            float wph = (P.phase == KRT_PHASE_DIPOLE_I) ? 0.75f * (1.0f + gc * gc) : 1.0f;
+            // contributions below 2^32 (F <= 30) convert through 32 bits
+            const float wf = wph * P.frac_scale;
+            q.wq = P.emis_w32 ? (int64_t)__float2uint_rn(wf) : (int64_t)__float2ll_rn(wf);
         }
-        nx = ox; ny = oy; nz = oz;
-        x = xo + nx * vxc + ny * vyc + nz * vzc;
+    };
+    auto commit = [&](const ScatPrep &q) {
+        if (P.emis_raw) {
+            if (q.kb >= 1 && q.kb <= P.emis_nch)
+                emis_add(E, q.kb - 1, q.wq, P.emis_raw + (int64_t)cell * P.emis_nch);
+            else
+                c_drop += 1;
+        }
+        nx = q.ox; ny = q.oy; nz = q.oz;
+        x = q.xo + nx * vxc + ny * vyc + nz * vzc;
         nscat_pkt += 1;
         c_scat += 1;
     };
@@ -413,7 +430,15 @@ __global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
         // ---- one flight segment (divergent) --------------------------------
         bool scat = false;
         float xc = 0.0f;
-        if (have) flight(u01(wa1), scat, xc);
+        ScatPrep q;
+        if (have) {
+            const float xg = x - (nx * vxc + ny * vyc + nz * vzc);
+            SDraws b;
+            scatter_draws(philox(make_uint4(ev, (uint32_t)pid, (uint32_t)(pid >> 32), 1u), P.key0, P.key1),
+                          P.phase == KRT_PHASE_DIPOLE_I, b);
+            prepare(xg, u01(wa2), u01(wa3), b, q);
+            flight(u01(wa1), scat, xc);
+        }
 
         // ---- learned escape: one batched network call per wave (uniform) ----
         bool mlp = false;
@@ -531,11 +556,7 @@ __global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
         // ---- resonant scattering (event ev), divergent -----------------------
         if (scat) {
             const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
-            if (!mlp) {
-                SDraws b;
-                scatter_draws(philox(make_uint4(ev, plo, phi, 1u), P.key0, P.key1), P.phase == KRT_PHASE_DIPOLE_I, b);
-                scatter(xc, u01(wa2), u01(wa3), b);
-            }
+            if (!mlp) commit(q);
             // next event
             ev += 1;
             if ((uint64_t)ev > P.max_events) {
@@ -599,9 +620,13 @@ __global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
             if (have && fresh) { tau = dt; fresh = false; }
             bool scat = false;
             float xc = 0.0f;
-            if (have) flight(due, scat, xc);
+            ScatPrep q;
+            if (have) {
+                prepare(x - (nx * vxc + ny * vyc + nz * vzc), dr1, dr2, db, q);
+                flight(due, scat, xc);
+            }
             if (scat) {
-                scatter(xc, dr1, dr2, db);
+                commit(q);
                 ev += 1;
                 if ((uint64_t)ev > P.max_events) {
                     c_stuck += 1;
