@@ -126,7 +126,8 @@ typedef struct {
     uint64_t max_events;       /* per packet; 0 = unlimited (2^32 - 2) */
     int32_t escape_mode;       /* 0 = plain random walk; 1 = learned escape in thick cells (needs
                                   krt_escape_init/train or put_weights; a in [1e-4, 1e-2]; no jbar) */
-    int32_t wg_size;           /* launch geometry: threads per workgroup (0 = 1024) */
+    int32_t wg_size;           /* launch geometry: threads per workgroup (0 = 1024 plain, 512
+                                  learned; the learned kernel has 256 VGPRs at <= 512, 128 above) */
     int32_t wg_per_cu;         /* workgroups per CU (0 = 1) */
     int32_t emis_frac_bits;    /* fixed-point fraction bits F of the emissivity tally (0 = 20) */
     int32_t jbar_frac_bits;    /* fraction bits of the mean-intensity tally (0 = 36) */
@@ -139,10 +140,9 @@ typedef struct {
                                   not bitwise, independent of launch geometry */
     int32_t esc_tail_lanes;    /* as esc_min_lanes once the packet pool is exhausted (0 = 1):
                                   the wave then lives only as long as its slowest packet */
-    int32_t esc_evals;         /* network evaluations per learned escape: 4 (0 = 4) draws the exit
-                                  frequency, the two exit-point coordinates and the exit cosine at
-                                  independent quantile levels; 2 shares the levels of (|x_out|, t)
-                                  and of (s, mu) */
+    int32_t esc_evals;         /* reserved, must be 0: a learned escape takes two network
+                                  evaluations (exit frequency, point and count; then the exit
+                                  direction given the exit point) */
     int32_t tail_lanes;        /* plain transport: once the pool is exhausted, a wave with at most
                                   this many live lanes lets its idle lanes precompute the live
                                   packets' random draws (0 = 32, negative = never); the tallies
@@ -241,7 +241,7 @@ int krt_levels_update(krt_ctx *ctx, const krt_levels_desc *desc,
                       const float *jbar_dev /* [nl-1][ncell], NULL = no radiation */);
 
 /* ------------------------------------------------------- learned escape --- */
-/* A small network (4 -> 3 x 128 SiLU -> 8, BF16 weights and activations, FP32
+/* A small network (8 -> 3 x 128 SiLU -> 10, BF16 weights and activations, FP32
  * accumulation on MFMA) proposes, at a scattering inside a cell whose
  * line-centre depth over the distance R to the nearest cell face is
  * tau_R = k0 R >= esc_tau_min, where a photon leaves the cube of half-width R
@@ -252,40 +252,49 @@ int krt_levels_update(krt_ctx *ctx, const krt_levels_desc *desc,
  * extreme depths, and the plain random walk remains the fallback (below
  * threshold, |x| > 8, a outside [1e-4, 1e-2]); above tau_R = 1e5 the cube is
  * shrunk to that depth.
- * Inputs (log10 tau_R, log10 a, x_in, u).  Outputs: 0 quantile at level u of
- * x_out given x_out >= 0; 1, 2 quantiles of the exit point (s, t); 3 of the
- * exit cosine mu; 4 ln E[N_s | tau_R, a, x_in]; 5 quantile of ln <x^2>;
- * 6 logit P(x_out >= 0); 7 quantile of -x_out given x_out < 0.  The bimodal
- * exit frequency is drawn as a two-component mixture: side from output 6,
- * magnitude from output 0 or 7.  Losses: pinball for the quantiles (0 and 7
- * only on records of their side), log-deviance e^d - 1 - d (d = ln N_s -
- * output) for output 4, logistic for output 6; trained on single-cell
- * escapes run by the plain transport arithmetic.  Parameters: kNParams =
- * 34696 FP32 master values plus 272 constants: target normalisation mean[8],
- * scale[8], and 256 additive calibration terms of ln E[N_s], one per bin of
+ * Inputs (log10 tau_R, log10 a, x_in, u_a, u_b, u_c, r, flag), in two kinds of
+ * evaluation: marginal (flag 0; r ignored) at three independent quantile
+ * levels, and conditional (flag 1; u_c ignored) at the exit point's distance r
+ * from the face centre, because photons leaving near an edge travel more
+ * obliquely and away from the centre.  Marginal outputs: 0 quantile at u_a of
+ * x_out given x_out >= 0; 1, 2 quantiles at u_b, u_c of the exit point (s, t);
+ * 4 ln E[N_s | tau_R, a, x_in]; 5 quantile at u_a of ln <x^2>; 6 logit
+ * P(x_out >= 0); 7 quantile at u_a of -x_out given x_out < 0.  Conditional
+ * outputs: 3 quantile at u_a of the exit cosine mu to the face normal; 8
+ * quantile at u_b of the angle alpha in [0, pi] between the exit direction's
+ * tangential part and the exit point's offset (s, t) (its sign is drawn
+ * uniformly).  Output 9 is unused.  The bimodal exit frequency is drawn as a
+ * two-component mixture: side from output 6, magnitude from output 0 or 7.
+ * Losses: pinball for the quantiles (0 and 7 only on records of their side),
+ * log-deviance e^d - 1 - d (d = ln N_s - output) for output 4, logistic for
+ * output 6; trained on single-cell escapes run by the plain transport
+ * arithmetic, a quarter of the rows conditional.  Parameters: kNParams =
+ * 35466 FP32 master values plus 276 constants: target normalisation mean[10],
+ * scale[10], and 256 additive calibration terms of ln E[N_s], one per bin of
  * (log10 tau_R in 32 bins of 0.125 over [1, 5], clamped; |x_in| in 8 bins with
  * edges 0, .5, 1, 1.5, 2, 3, 4, 6), index = tau bin * 8 + x bin.
  *
  * krt_escape_init: He-uniform parameters from Philox(seed), Adam state zeroed.
  * krt_escape_record: n single-cell escapes for line `line`, log10 tau_R uniform
  *   in [lo, hi], x_in fixed (x_fixed = 1) or 1/2 N(0, 1/2) + 1/2 U[-8, 8];
- *   samples_dev [n][10] FP32: (log10 tau_R, log10 a, x_in, x_out, s, t, mu,
- *   ln N_s, ln <x^2>, valid).
+ *   samples_dev [n][11] FP32: (log10 tau_R, log10 a, x_in, x_out, s, t, mu,
+ *   ln N_s, ln <x^2>, valid, alpha).
  * krt_escape_fit_norm: target mean / scale from valid records; clears the
  *   calibration.
  * krt_escape_calibrate: per (log10 tau_R, |x_in|) bin with at least 100 valid records,
  *   the calibration term ln(sum N_s / sum exp(network ln E[N_s])) over the
- *   records (a network quantile level drawn per record), so that the
+ *   records (marginal rows, quantile levels drawn per record), so that the
  *   predicted mean count is unbiased bin by bin; other bins get 0.
  * krt_escape_grad: gradient of the mean loss over the batch given by
- *   idx_dev [batch] (record indices) and u_dev [batch]; grad_out_dev [34696],
- *   loss_out_dev [1] (may be NULL).
+ *   idx_dev [batch] (record indices) and u_dev [batch][4] = (u_a, u_b, u_c,
+ *   1 for a conditional row else 0); grad_out_dev [35466], loss_out_dev [1]
+ *   (may be NULL).
  * krt_escape_train: `steps` Adam steps (lr, betas 0.9/0.999) on random batches
  *   (Philox(seed)); loss_hist_dev [steps] or NULL.
- * krt_escape_get_weights / put_weights: [34696 + 272] FP32 device buffers.
- * krt_escape_forward: in_dev [n][4] raw (log10 tau_R, log10 a, x_in, u) ->
- *   out_dev [n][8] in physical units (output 6 as a logit, output 4 with its
- *   calibration term).
+ * krt_escape_get_weights / put_weights: [35466 + 276] FP32 device buffers.
+ * krt_escape_forward: in_dev [n][8] raw (log10 tau_R, log10 a, x_in, u_a, u_b,
+ *   u_c, r, flag) -> out_dev [n][10] in physical units (output 6 as a logit,
+ *   output 4 with its calibration term).
  * Errors: KRT_EINVAL (sizes, ranges), KRT_ESTATE (no init / no tables). */
 int krt_escape_init(krt_ctx *ctx, uint64_t seed);
 int krt_escape_record(krt_ctx *ctx, int32_t line, uint64_t n, uint64_t seed, uint64_t offset,

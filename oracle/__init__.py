@@ -210,14 +210,16 @@ def levels_solve(E, g, A, Cd, ncoll, ntot, gamma=None) -> np.ndarray:
 def escape_record(n: int, tau_R: float, a: float, x_in: float, seed: int = 0, offset: int = 0,
                   threads: int | None = None) -> np.ndarray:
     """Plain FP64 single-cell escapes (reference for the learned escape); records
-    [log10 tau_R, log10 a, x_in, x_out, s, t, mu, ln N_s, ln <x^2>, valid]."""
+    [log10 tau_R, log10 a, x_in, x_out, s, t, mu, ln N_s, ln <x^2>, valid, alpha],
+    alpha the angle between the exit direction's tangential part and the exit
+    point's offset from the face centre."""
     L = lib()
     if not hasattr(L, "_esc_set"):
         L.orc_escape_record.argtypes = [C.c_int64, C.c_double, C.c_double, C.c_double, C.c_uint64,
                                         C.c_uint64, C.c_int, C.c_void_p]
         L.orc_escape_record.restype = C.c_int
         L._esc_set = True
-    out = np.zeros((n, 10), dtype=np.float64)
+    out = np.zeros((n, 11), dtype=np.float64)
     L.orc_escape_record(int(n), float(tau_R), float(a), float(x_in), int(seed), int(offset),
                         int(threads or os.cpu_count() or 1), _ptr(out))
     return out

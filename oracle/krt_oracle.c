@@ -648,9 +648,12 @@ int orc_levels_solve(int nl, int64_t ncell, const double *E, const double *g, co
 /* (event 0, purpose 4, words 0-1), scatters at the centre (event 1), then    */
 /* takes the plain flights and scatterings of Sec. 2.1-2.3 until it leaves.   */
 /* Record per photon: [log10 tau_R, log10 a, x_in, x_out, s, t, mu, ln N_s,   */
-/* ln <x^2>, valid]; (s, t) are the exit point's coordinates along the two    */
-/* axes following the exit axis cyclically, mu = |n . normal|.               */
+/* ln <x^2>, valid, alpha]; (s, t) are the exit point's coordinates along the */
+/* two axes following the exit axis cyclically, mu = |n . normal|, and alpha  */
+/* in [0, pi] the angle between the exit direction's tangential part and the  */
+/* exit point's offset (s, t) from the face centre (0 where either vanishes). */
 /* ------------------------------------------------------------------------ */
+#define ORC_ESC_REC 11
 typedef struct { double tau, a, xin; uint64_t seed, p0, p1; double *out; uint64_t max_scat; } esc_job_t;
 
 static void escape_one(const esc_job_t *J, uint64_t pid, double *o)
@@ -707,15 +710,17 @@ static void escape_one(const esc_job_t *J, uint64_t pid, double *o)
         int a1 = (ax + 1) % 3, a2 = (ax + 2) % 3;
         o[3] = x; o[4] = X[a1]; o[5] = X[a2]; o[6] = fabs(n[ax]);
         o[7] = log((double)ns); o[8] = log(sx2 / (double)ns); o[9] = 1.0;
+        double dot = X[a1] * n[a1] + X[a2] * n[a2], crs = X[a1] * n[a2] - X[a2] * n[a1];
+        o[10] = atan2(fabs(crs), dot);
     } else {
-        for (int k = 3; k < 10; ++k) o[k] = 0.0;
+        for (int k = 3; k < ORC_ESC_REC; ++k) o[k] = 0.0;
     }
 }
 
 static void *escape_main(void *arg)
 {
     esc_job_t *J = (esc_job_t *)arg;
-    for (uint64_t p = J->p0; p < J->p1; ++p) escape_one(J, p, J->out + 10 * (p - J->p0));
+    for (uint64_t p = J->p0; p < J->p1; ++p) escape_one(J, p, J->out + ORC_ESC_REC * (p - J->p0));
     return NULL;
 }
 
@@ -730,7 +735,7 @@ int orc_escape_record(int64_t n, double tau_R, double a, double x_in, uint64_t s
         J[t].tau = tau_R; J[t].a = a; J[t].xin = x_in; J[t].seed = seed; J[t].max_scat = 4000000;
         J[t].p0 = offset + (uint64_t)n * t / n_threads;
         J[t].p1 = offset + (uint64_t)n * (t + 1) / n_threads;
-        J[t].out = out + 10 * (J[t].p0 - offset);
+        J[t].out = out + ORC_ESC_REC * (J[t].p0 - offset);
         pthread_create(&th[t], NULL, escape_main, &J[t]);
     }
     for (int t = 0; t < n_threads; ++t) pthread_join(th[t], NULL);

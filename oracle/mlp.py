@@ -1,18 +1,30 @@
 """FP64 CPU reference of the escape network -- TEST INFRASTRUCTURE.
 
-Same parameter layout as the GPU (one flat vector): W1[4][128], b1[128],
-W2[128][128], b2, W3[128][128], b3, W4[128][8], b4[8]; activations SiLU.
-Inputs are normalised as ((log10 tau - 3.5)/1.5, log10 a + 3, x_in / 4, 2u - 1).
+Same parameter layout as the GPU (one flat vector): W1[8][128], b1[128],
+W2[128][128], b2, W3[128][128], b3, W4[128][10], b4[10]; activations SiLU.
 
-Outputs (index: meaning, loss), for a record with exit frequency x:
-  0: quantile at level u of x given x >= 0     pinball, only records with x >= 0
-  1: quantile of s (exit point, first axis)      pinball
-  2: quantile of t (exit point, second axis)     pinball
-  3: quantile of mu (exit cosine to the normal)  pinball
+Inputs (8), normalised as ((log10 tau - 3.5)/1.5, log10 a + 3, x_in / 4,
+2u_a - 1, 2u_b - 1, 2u_c - 1, r_in, flag).  A row is either *marginal*
+(flag 0, r_in 0) or *conditional* (flag 1, r_in = sqrt(2) r - 1 with r the
+exit point's distance from the face centre, u_c slot 0): the network is
+evaluated once at three independent quantile levels for the exit frequency,
+exit point and count, then once more at the sampled exit point for the exit
+direction, which depends on where on the face the photon leaves.
+
+Outputs (index: meaning, loss, level), for a record with exit frequency x:
+  marginal rows
+  0: quantile of x given x >= 0                 pinball at u_a, records with x >= 0
+  1: quantile of s (exit point, first axis)      pinball at u_b
+  2: quantile of t (exit point, second axis)     pinball at u_c
   4: ln E[N_s | condition]                       weighted log-deviance (below)
-  5: quantile of ln <x^2> over the scatterings   pinball
+  5: quantile of ln <x^2> over the scatterings   pinball at u_a
   6: logit P(x >= 0 | condition)                 logistic (Bernoulli) loss
-  7: quantile of -x given x < 0                  pinball, only records with x < 0
+  7: quantile of -x given x < 0                  pinball at u_a, records with x < 0
+  conditional rows (given r)
+  3: quantile of mu (exit cosine to the normal)  pinball at u_a
+  8: quantile of alpha (angle between the exit   pinball at u_b
+     direction's tangential part and the exit point's offset (s, t))
+  9: unused (keeps the parameter block an even number of floats)
 The exit frequency is bimodal (blue and red peaks with an empty core between
 them), so one smooth quantile function of the signed x would fill the gap;
 the two one-sided quantiles and the side probability form a two-component
@@ -34,12 +46,14 @@ from __future__ import annotations
 
 import numpy as np
 
-NIN, NH, NOUT = 4, 128, 8
+NIN, NH, NOUT = 8, 128, 10
 SHAPES = [("W1", (NIN, NH)), ("b1", (NH,)), ("W2", (NH, NH)), ("b2", (NH,)),
           ("W3", (NH, NH)), ("b3", (NH,)), ("W4", (NH, NOUT)), ("b4", (NOUT,))]
 NPARAMS = sum(int(np.prod(s)) for _, s in SHAPES)
 NNORM = 2 * NOUT
-O_XPOS, O_S, O_T, O_MU, O_LOGN, O_LOGX2, O_LOGIT, O_XNEG = range(NOUT)
+O_XPOS, O_S, O_T, O_MU, O_LOGN, O_LOGX2, O_LOGIT, O_XNEG, O_ALPHA, O_SPARE = range(NOUT)
+MARGINAL = (O_XPOS, O_S, O_T, O_LOGN, O_LOGX2, O_LOGIT, O_XNEG)
+CONDITIONAL = (O_MU, O_ALPHA)
 N_OUT = O_LOGN
 DEV_CLAMP = 4.0
 DEV_WEIGHT = 0.25
@@ -66,9 +80,29 @@ def bf16(a):
     return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
 
 
-def inputs(lt, la, xin, u):
-    return np.stack([(np.asarray(lt) - 3.5) / 1.5, np.asarray(la) + 3.0, np.asarray(xin) / 4.0,
-                     2.0 * np.asarray(u) - 1.0], axis=-1).astype(np.float64)
+def inputs(lt, la, xin, ua, ub, uc, r, cond):
+    """Normalised inputs; r (exit point radius) and uc are ignored on the rows
+    where they are not inputs (r on marginal rows, uc on conditional rows)."""
+    cond = np.asarray(cond, dtype=bool)
+    lt, la, xin, ua, ub, uc, r = np.broadcast_arrays(*(np.asarray(v, dtype=np.float64)
+                                                       for v in (lt, la, xin, ua, ub, uc, r)))
+    return np.stack([(lt - 3.5) / 1.5, la + 3.0, xin / 4.0, 2.0 * ua - 1.0, 2.0 * ub - 1.0,
+                     np.where(cond, 0.0, 2.0 * uc - 1.0), np.where(cond, np.sqrt(2.0) * r - 1.0, 0.0),
+                     cond.astype(np.float64)], axis=-1)
+
+
+def levels(ua, ub, uc, cond):
+    """Quantile level of each output per row [B, NOUT] (NaN for the outputs
+    that are not quantiles or not trained on that kind of row)."""
+    cond = np.asarray(cond, dtype=bool)
+    U = np.full((cond.shape[0], NOUT), np.nan)
+    for k in (O_XPOS, O_XNEG, O_LOGX2):
+        U[:, k] = np.where(cond, np.nan, ua)
+    U[:, O_S] = np.where(cond, np.nan, ub)
+    U[:, O_T] = np.where(cond, np.nan, uc)
+    U[:, O_MU] = np.where(cond, ua, np.nan)
+    U[:, O_ALPHA] = np.where(cond, ub, np.nan)
+    return U
 
 
 def silu(z):
@@ -104,16 +138,17 @@ def deviance(d):
     return f, np.exp(dc) - 1.0
 
 
-def losses(out, Y, u, s4=1.0):
+def losses(out, Y, U, s4=1.0):
     """Mean over the batch of the summed per-output losses, and dL/dout.
     Y: normalised targets (NaN where an output is masked for that sample);
-    Y[:, 6] is the side label b in {0, 1}."""
+    Y[:, 6] is the side label b in {0, 1}; U: per-output quantile levels."""
     B = out.shape[0]
     live = ~np.isnan(Y)
     Yz = np.where(live, Y, 0.0)
+    Uz = np.where(np.isnan(U), 0.0, U)
     ind = (Yz < out).astype(np.float64)
-    lk = (Yz - out) * (u[:, None] - ind)
-    dout = (ind - u[:, None]) / B
+    lk = (Yz - out) * (Uz - ind)
+    dout = (ind - Uz) / B
     f, fp = deviance(s4 * (Yz[:, O_LOGN] - out[:, O_LOGN]))
     lk[:, O_LOGN] = DEV_WEIGHT * f / s4
     dout[:, O_LOGN] = -DEV_WEIGHT * fp / B
@@ -125,10 +160,10 @@ def losses(out, Y, u, s4=1.0):
     return float(np.sum(lk) / B), dout
 
 
-def loss_and_grad(p, X, Y, u, bf=False, s4=1.0):
+def loss_and_grad(p, X, Y, U, bf=False, s4=1.0):
     """s4: the target scale of output 4 (norm[NOUT + 4])."""
     out, c, W = forward(p, X, bf)
-    loss, d = losses(out, Y, u, s4)
+    loss, d = losses(out, Y, U, s4)
     g = {"W4": c["h3"].T @ d, "b4": d.sum(0)}
     dh = d @ W["W4"].T
     for i in (3, 2, 1):
@@ -139,20 +174,31 @@ def loss_and_grad(p, X, Y, u, bf=False, s4=1.0):
     return loss, pack(g)
 
 
-def raw_targets(rec):
-    """Records [.., x_out, s, t, mu, lnNs, lnx2, valid] -> per-output physical
-    targets [B, 8] (NaN where masked; column 6 is the side label)."""
+def raw_targets(rec, cond=None):
+    """Records [.., x_out, s, t, mu, lnNs, lnx2, valid, alpha] -> per-output
+    physical targets [B, NOUT] (NaN where masked; column 6 is the side label).
+    cond marks conditional rows (default: none)."""
+    B = rec.shape[0]
+    cond = np.zeros(B, dtype=bool) if cond is None else np.asarray(cond, dtype=bool)
     x = rec[:, 3].astype(np.float64)
     pos = x >= 0.0
-    y = np.full((rec.shape[0], NOUT), np.nan)
+    y = np.full((B, NOUT), np.nan)
     y[:, O_XPOS] = np.where(pos, x, np.nan)
-    y[:, O_S:O_LOGX2 + 1] = rec[:, 4:9]
+    y[:, O_S] = rec[:, 4]
+    y[:, O_T] = rec[:, 5]
+    y[:, O_MU] = rec[:, 6]
+    y[:, O_LOGN] = rec[:, 7]
+    y[:, O_LOGX2] = rec[:, 8]
     y[:, O_LOGIT] = pos.astype(np.float64)
     y[:, O_XNEG] = np.where(pos, np.nan, -x)
+    y[:, O_ALPHA] = rec[:, 10]
+    y[cond[:, None] & np.isin(np.arange(NOUT), MARGINAL)[None, :]] = np.nan
+    y[~cond[:, None] & np.isin(np.arange(NOUT), CONDITIONAL)[None, :]] = np.nan
+    y[:, O_SPARE] = np.nan
     return y
 
 
-def targets_normalised(rec, norm):
+def targets_normalised(rec, norm, cond=None):
     """Normalised targets: (raw - mean) / scale; the side label stays 0/1
     (its normalisation is fixed at mean 0, scale 1)."""
-    return (raw_targets(rec) - norm[:NOUT]) / norm[NOUT:]
+    return (raw_targets(rec, cond) - norm[:NOUT]) / norm[NOUT:2 * NOUT]

@@ -284,12 +284,15 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
         if (al < 1e-4 * (1 - 1e-9) || al > 1e-2 * (1 + 1e-9))
             return fail(c, KRT_EINVAL, "learned escape covers a in [1e-4, 1e-2] (line a = %g)", al);
     }
-    // default: 16 waves per CU, one copy of the LDS tables per CU
-    int block = o->wg_size ? o->wg_size : 1024;
+    // default: one workgroup per CU holding the LDS tables, 16 waves (plain) or 8
+    // waves (learned: its kernel is compiled for 512-lane blocks, where the
+    // network's registers fit without spilling)
+    int block = o->wg_size ? o->wg_size : (esc ? 512 : 1024);
     int per_cu = o->wg_per_cu ? o->wg_per_cu : 1;
     if (block < 64 || block > 1024 || block % 64) return fail(c, KRT_EINVAL, "wg_size %d invalid", block);
     if (per_cu < 1 || per_cu > 64) return fail(c, KRT_EINVAL, "wg_per_cu %d invalid", per_cu);
     if (o->max_events > 0xFFFFFFFEull) return fail(c, KRT_EINVAL, "max_events too large");
+    if (o->esc_evals != 0) return fail(c, KRT_EINVAL, "esc_evals is reserved (0)");
 
     HIPCHK(c, hipSetDevice(c->device));
     const krt_grid_desc &g = c->grid;
@@ -365,7 +368,6 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
     P.esc_log10a = (float)std::log10(c->lines[l].a);
     P.esc_min_lanes = o->esc_min_lanes > 0 ? o->esc_min_lanes : 8;
     P.esc_tail_lanes = o->esc_tail_lanes > 0 ? o->esc_tail_lanes : 1;
-    P.esc_evals = o->esc_evals == 2 ? 2 : 4;
     P.tail_lanes = o->tail_lanes == 0 ? 32 : (o->tail_lanes < 0 ? 0 : std::min(o->tail_lanes, 64));
     int grid = c->cus * per_cu;
     HIPCHK(c, hipEventRecord(c->ev0, c->stream));
@@ -620,7 +622,7 @@ int mlp_ensure_batch(krt_ctx *c, int batch) {
     c->mlp_idx = nullptr;
     c->mlp_u = nullptr;
     HIPCHK(c, hipMalloc(&c->mlp_idx, sizeof(int32_t) * batch));
-    HIPCHK(c, hipMalloc(&c->mlp_u, sizeof(float) * batch));
+    HIPCHK(c, hipMalloc(&c->mlp_u, sizeof(float) * 4 * (size_t)batch));
     c->mlp_batch_cap = batch;
     return KRT_OK;
 }

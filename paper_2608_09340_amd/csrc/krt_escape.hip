@@ -22,7 +22,6 @@ namespace krt {
 
 // ------------------------------------------------------------- recording ---
 // record: [log10 tau_R, log10 a, x_in, x_out, s, t, mu, ln N_s, ln <x^2>, valid]
-constexpr int kRec = 10;
 
 __global__ void __launch_bounds__(256) escape_record_kernel(const float *tab, float a, float thd, uint32_t k0,
                                                             uint32_t k1, uint64_t offset, int64_t n,
@@ -116,13 +115,16 @@ __global__ void __launch_bounds__(256) escape_record_kernel(const float *tab, fl
         // exit face: axis ax, sign of the normal; tangential coordinates in cyclic order
         float p[3] = {px, py, pz}, nn[3] = {nx, ny, nz};
         int a1 = (ax + 1) % 3, a2 = (ax + 2) % 3;
-        o[3] = x;
-        o[4] = fminf(fmaxf(p[a1], -1.f), 1.f);
-        o[5] = fminf(fmaxf(p[a2], -1.f), 1.f);
-        o[6] = fabsf(nn[ax]);
-        o[7] = logf((float)ns);
-        o[8] = logf(fmaxf(sx2 / (float)ns, 1e-6f));
-        o[9] = 1.0f;
+        const float es = fminf(fmaxf(p[a1], -1.f), 1.f), et = fminf(fmaxf(p[a2], -1.f), 1.f);
+        o[kRecXOut] = x;
+        o[kRecS] = es;
+        o[kRecT] = et;
+        o[kRecMu] = fabsf(nn[ax]);
+        o[kRecLogN] = logf((float)ns);
+        o[kRecLogX2] = logf(fmaxf(sx2 / (float)ns, 1e-6f));
+        o[kRecValid] = 1.0f;
+        // angle between the direction's tangential part and the offset (s, t)
+        o[kRecAlpha] = atan2f(fabsf(es * nn[a2] - et * nn[a1]), es * nn[a1] + et * nn[a2]);
     } else {
         for (int k = 3; k < kRec; ++k) o[k] = 0.0f;
     }
@@ -209,21 +211,51 @@ __global__ void mlp_fwd_image_kernel(const unsigned char *blob, unsigned char *i
 }
 
 // ------------------------------------------------------------- inputs ---
-__device__ __forceinline__ void mlp_inputs(float lt, float la, float xin, float u, float in[4]) {
+// Marginal rows: (condition, u_a, u_b, u_c, 0, 0); conditional rows: (condition,
+// u_a, u_b, 0, sqrt2 r - 1, 1) with r the exit point's distance from the face
+// centre.
+__device__ __forceinline__ void mlp_inputs(float lt, float la, float xin, float ua, float ub, float uc, float r,
+                                           bool cond, float in[kMlpIn]) {
     in[0] = (lt - 3.5f) * (1.0f / 1.5f);
     in[1] = la + 3.0f;
     in[2] = xin * 0.25f;
-    in[3] = 2.0f * u - 1.0f;
+    in[3] = 2.0f * ua - 1.0f;
+    in[4] = 2.0f * ub - 1.0f;
+    in[5] = cond ? 0.0f : 2.0f * uc - 1.0f;
+    in[6] = cond ? 1.41421356f * r - 1.0f : 0.0f;
+    in[7] = cond ? 1.0f : 0.0f;
 }
 
-__device__ __forceinline__ v4i16 xin_operand(const float in[4], int lane) {
-    return (lane < 16) ? pack4(in[0], in[1], in[2], in[3]) : pack4(0.f, 0.f, 0.f, 0.f);
+__device__ __forceinline__ v4i16 xin_operand(const float in[kMlpIn], int lane) {
+    return (lane < 16) ? pack4(in[0], in[1], in[2], in[3])
+                       : (lane < 32 ? pack4(in[4], in[5], in[6], in[7]) : pack4(0.f, 0.f, 0.f, 0.f));
 }
+
+// Record column of output k's target (the one-sided exit frequencies read the
+// signed x_out; the side label and the unused output have none).
+__device__ __forceinline__ int target_col(int k) {
+    switch (k) {
+        case kOutXPos: case kOutXNeg: return kRecXOut;
+        case kOutS: return kRecS;
+        case kOutT: return kRecT;
+        case kOutMu: return kRecMu;
+        case kOutLogN: return kRecLogN;
+        case kOutLogX2: return kRecLogX2;
+        case kOutAlpha: return kRecAlpha;
+        default: return -1;
+    }
+}
+
+// Is output k trained on a conditional (true) or a marginal (false) row?
+__device__ __forceinline__ bool conditional_output(int k) { return k == kOutMu || k == kOutAlpha; }
 
 // ---------------------------------------------------------- gradient ---
 // One wave per 16-sample block.  grad += d(mean loss)/d(params); loss += sum.
-// Quantile outputs: pinball loss at level u (the two one-sided exit-frequency
-// quantiles only on records of their side); ln N_s: log-deviance; side: logistic.
+// Row si uses record idx[si] and uq[4 si ..] = (u_a, u_b, u_c, conditional flag).
+// Quantile outputs: pinball loss at their own level (the two one-sided
+// exit-frequency quantiles only on records of their side); ln N_s:
+// log-deviance; side: logistic.  Marginal rows train outputs 0-2 and 4-7,
+// conditional rows outputs 3 and 8.
 __global__ void __launch_bounds__(256) mlp_grad_kernel(const unsigned char *blob, const float *rec,
                                                        const int32_t *idx, const float *uq, int batch,
                                                        float *grad, float *loss) {
@@ -235,26 +267,30 @@ __global__ void __launch_bounds__(256) mlp_grad_kernel(const unsigned char *blob
     const int s = lane % 16, g = lane / 16;
     const int si = block * 16 + s;
     const float *r0 = rec + (int64_t)kRec * idx[0];
-    const bool live = wave_live && si < batch && r0 != nullptr && rec[(int64_t)kRec * idx[si < batch ? si : 0] + 9] > 0.5f;
+    const bool live = wave_live && si < batch && r0 != nullptr &&
+                      rec[(int64_t)kRec * idx[si < batch ? si : 0] + kRecValid] > 0.5f;
     const float *bias = reinterpret_cast<const float *>(blob + kTilesAll * kTileBytes);
     const float *norm = bias + kBiasFloats;
     const float *r = rec + (int64_t)kRec * (live ? idx[si] : idx[0]);
-    const float u = live ? uq[si] : 0.5f;
-    float in[4];
-    mlp_inputs(r[0], r[1], r[2], u, in);
-    if (!live) in[0] = in[1] = in[2] = in[3] = 0.0f;
+    const float *ul = uq + 4 * (int64_t)(live ? si : 0);
+    const float ua = live ? ul[0] : 0.5f, ub = live ? ul[1] : 0.5f, uc = live ? ul[2] : 0.5f;
+    const bool cond = live && ul[3] > 0.5f;
+    float in[kMlpIn];
+    mlp_inputs(r[0], r[1], r[2], ua, ub, uc, sqrtf(r[kRecS] * r[kRecS] + r[kRecT] * r[kRecT]), cond, in);
+    if (!live)
+        for (int k = 0; k < kMlpIn; ++k) in[k] = 0.0f;
     v4i16 xb = xin_operand(in, lane);
     v4f32 z1[8], z2[8], z3[8];
     v4f32 o = mlp_forward_block(blob, bias, xb, lane, z1, z2, z3);
     // per-output losses and their gradients for outputs k = 4g + j
     const float invB = 1.0f / (float)batch;
-    const float xo = r[3];
+    const float xo = r[kRecXOut];
     float dO[4], lsum = 0.0f;
     for (int j = 0; j < 4; ++j) {
         int k = 4 * g + j;
         float oj = (j == 0) ? o.x : (j == 1) ? o.y : (j == 2) ? o.z : o.w;
         dO[j] = 0.0f;
-        if (k >= kMlpOut || !live) continue;
+        if (k >= kMlpOut || k == kOutSpare || !live || conditional_output(k) != cond) continue;
         if (k == kOutLogit) {
             // side of the exit frequency: logistic loss, label 1{x_out >= 0}
             const float b = (xo >= 0.0f) ? 1.0f : 0.0f;
@@ -270,9 +306,11 @@ __global__ void __launch_bounds__(256) mlp_grad_kernel(const unsigned char *blob
             if (xo >= 0.0f) continue;
             raw = -xo;
         } else {
-            raw = r[3 + k];
+            raw = r[target_col(k)];
         }
         const float y = (raw - norm[k]) / norm[kMlpOut + k];
+        // quantile level of this output on this kind of row
+        const float u = (k == kOutS || k == kOutAlpha) ? ub : (k == kOutT ? uc : ua);
         if (k == kOutLogN) {
             // ln E[N_s]: weighted, scaled log-deviance w f(d) / s4, d = s4 (y - o),
             // f(d) = e^d - 1 - d, continued linearly beyond d = kDevClamp
@@ -376,9 +414,10 @@ __global__ void __launch_bounds__(256) mlp_grad_kernel(const unsigned char *blob
                              acc.w * dsilu(zin[mi].w)};
         }
     }
-    // ---- layer 1: dW1 = X dZ1^T (X rows 0..3), db1
+    // ---- layer 1: dW1 = X dZ1^T (X rows 0..7), db1
     __syncthreads();
-    put(0, 0, g == 0 ? in[0] : 0.f, g == 0 ? in[1] : 0.f, g == 0 ? in[2] : 0.f, g == 0 ? in[3] : 0.f);
+    put(0, 0, g == 0 ? in[0] : (g == 1 ? in[4] : 0.f), g == 0 ? in[1] : (g == 1 ? in[5] : 0.f),
+        g == 0 ? in[2] : (g == 1 ? in[6] : 0.f), g == 0 ? in[3] : (g == 1 ? in[7] : 0.f));
     for (int mo = 0; mo < 8; ++mo) put(8 + mo, mo, dz[mo].x, dz[mo].y, dz[mo].z, dz[mo].w);
     __syncthreads();
     wgrad(1, 8, kPW1, kMlpHid, kMlpIn, kMlpHid);
@@ -399,32 +438,38 @@ __global__ void mlp_adam_kernel(float *p, float *m, float *v, float *grad, float
     grad[i] = 0.0f;
 }
 
-// Random batch: indices uniform over the valid records, quantile levels u.
+// Random batch: indices uniform over the records, three quantile levels and
+// the row kind (conditional with probability 1/4).
 __global__ void mlp_batch_kernel(int64_t n, uint32_t k0, uint32_t k1, uint32_t step, int batch,
                                  int32_t *idx, float *uq) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= batch) return;
     uint4 r = philox(make_uint4(step, (uint32_t)i, 0u, 9u), k0, k1);
     idx[i] = (int32_t)__umulhi(r.x, (uint32_t)n);
-    uq[i] = u01(r.y);
+    float *q = uq + 4 * (int64_t)i;
+    q[0] = u01(r.y);
+    q[1] = u01(r.z);
+    q[2] = u01(r.w);
+    q[3] = (u01(philox(make_uint4(step, (uint32_t)i, 1u, 9u), k0, k1).x) < 0.25f) ? 1.0f : 0.0f;
 }
 
-// Normalisation of the 8 targets: mean and standard deviation over the valid
+// Normalisation of the targets: mean and standard deviation over the valid
 // records of each output's own target (the one-sided exit frequencies over the
-// records of their side; the side logit keeps mean 0, scale 1), FP64
-// accumulation, one block of 256 threads per output.
+// records of their side; the side logit and the unused output keep mean 0,
+// scale 1), FP64 accumulation, one block of 256 threads per output.
 __global__ void mlp_norm_kernel(const float *rec, int64_t n, float *norm) {
     __shared__ double s0[256], s1[256], s2[256];
     const int k = blockIdx.x;
     double a = 0.0, b = 0.0, c = 0.0;
-    if (k != kOutLogit) {
+    const int col = target_col(k);
+    if (col >= 0) {
         for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
             const float *r = rec + (int64_t)kRec * i;
-            if (r[9] < 0.5f) continue;
+            if (r[kRecValid] < 0.5f) continue;
             double y;
-            if (k == kOutXPos) { if (r[3] < 0.0f) continue; y = r[3]; }
-            else if (k == kOutXNeg) { if (r[3] >= 0.0f) continue; y = -r[3]; }
-            else y = r[3 + k];
+            if (k == kOutXPos) { if (r[col] < 0.0f) continue; y = r[col]; }
+            else if (k == kOutXNeg) { if (r[col] >= 0.0f) continue; y = -r[col]; }
+            else y = r[col];
             a += y;
             b += y * y;
             c += 1.0;
@@ -443,7 +488,7 @@ __global__ void mlp_norm_kernel(const float *rec, int64_t n, float *norm) {
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        if (k == kOutLogit || s0[0] < 1.0) {
+        if (col < 0 || s0[0] < 1.0) {
             norm[k] = 0.0f;
             norm[kMlpOut + k] = 1.0f;
         } else {
@@ -455,8 +500,9 @@ __global__ void mlp_norm_kernel(const float *rec, int64_t n, float *norm) {
     }
 }
 
-// Forward for a list of raw conditions in[n][4] = (log10 tau_R, log10 a, x_in, u):
-// out[n][8] in physical units (ln E[N_s] with its calibration term).
+// Forward for a list of raw rows in[n][8] = (log10 tau_R, log10 a, x_in, u_a,
+// u_b, u_c, r, flag): out[n][10] in physical units (ln E[N_s] with its
+// calibration term).
 __global__ void __launch_bounds__(256) mlp_forward_kernel(const unsigned char *blob, const float *inp,
                                                           int64_t n, float *out) {
     const int lane = __lane_id(), w = threadIdx.x / 64;
@@ -467,9 +513,9 @@ __global__ void __launch_bounds__(256) mlp_forward_kernel(const unsigned char *b
     const bool live = si < n;
     const float *bias = reinterpret_cast<const float *>(blob + kTilesAll * kTileBytes);
     const float *norm = bias + kBiasFloats;
-    const float *r = inp + 4 * (live ? si : 0);
-    float in[4];
-    mlp_inputs(r[0], r[1], r[2], r[3], in);
+    const float *r = inp + kMlpIn * (live ? si : 0);
+    float in[kMlpIn];
+    mlp_inputs(r[0], r[1], r[2], r[3], r[4], r[5], r[6], r[7] > 0.5f, in);
     v4f32 o = mlp_forward_block(blob, bias, xin_operand(in, lane), lane, nullptr, nullptr, nullptr);
     if (!live) return;
     float v[4] = {o.x, o.y, o.z, o.w};
@@ -495,20 +541,21 @@ __global__ void __launch_bounds__(256) mlp_calib_kernel(const unsigned char *blo
     const int64_t si = block * 16 + s;
     if (block * 16 < n) {  // wave-uniform
         const float *r = rec + (int64_t)kRec * (si < n ? si : 0);
-        const bool live = si < n && r[9] > 0.5f;
+        const bool live = si < n && r[kRecValid] > 0.5f;
         const float *bias = reinterpret_cast<const float *>(blob + kTilesAll * kTileBytes);
         const float *norm = bias + kBiasFloats;
-        // quantile level as the transport draws it: uniform, from Philox(record index)
+        // marginal row with quantile levels as the transport draws them: uniform,
+        // from Philox(record index)
         const uint4 q = philox(make_uint4((uint32_t)si, (uint32_t)(si >> 32), 0u, 9u), 0x6C1Bu, 0x5EEDu);
-        float in[4];
-        mlp_inputs(r[0], r[1], r[2], u01(q.x), in);
+        float in[kMlpIn];
+        mlp_inputs(r[0], r[1], r[2], u01(q.x), u01(q.y), u01(q.z), 0.0f, false, in);
         v4f32 o = mlp_forward_block(blob, bias, xin_operand(in, lane), lane, nullptr, nullptr, nullptr);
         // output 4 sits in lane group g = 1, component 0
         if (live && g == 1) {
             const int b = cal_bin(r[0], r[2]);
             const double pred = exp((double)(o.x * norm[kMlpOut + kOutLogN] + norm[kOutLogN]));
             atomicAdd(&ls[b], 1.0);
-            atomicAdd(&ls[kNCal + b], exp((double)r[7]));
+            atomicAdd(&ls[kNCal + b], exp((double)r[kRecLogN]));
             atomicAdd(&ls[2 * kNCal + b], pred);
         }
     }

@@ -88,7 +88,6 @@ struct RunParams {
     float esc_tau_min, esc_tau_max, esc_x_max, esc_log10a;
     int esc_min_lanes;
     int esc_tail_lanes;
-    int esc_evals;
     int tail_lanes;
     int emis_w32;  // emissivity contributions fit 32 bits (fraction bits <= 30)
 };

@@ -2,18 +2,26 @@
 // forward pass shared by the transport kernel (inference) and the training
 // kernels.  Not part of the C ABI.
 //
-// Network: 4 inputs -> 128 -> 128 -> 128 (SiLU) -> 8 outputs.
-// Inputs  : ((log10 tau_R - 3.5)/1.5, log10 a + 3, x_in / 4, 2u - 1), u the
-//           quantile level.
-// Outputs (normalised): 0 quantile at level u of x_out given x_out >= 0;
-//           1, 2 quantiles of the exit point (s, t) on the exit face; 3 of the
-//           cosine mu of the exit direction to the face normal; 4 ln E[N_s]
-//           (scatterings inside the cube); 5 quantile of ln <x^2> over those
-//           scatterings; 6 logit P(x_out >= 0); 7 quantile of -x_out given
-//           x_out < 0.  The exit frequency is bimodal, so it is drawn as a
-//           two-component mixture (side, then a one-sided quantile): a single
-//           smooth quantile function of the signed x_out would fill the empty
-//           line core between the peaks.
+// Network: 8 inputs -> 128 -> 128 -> 128 (SiLU) -> 10 outputs.
+// Inputs  : ((log10 tau_R - 3.5)/1.5, log10 a + 3, x_in / 4, 2u_a - 1, 2u_b - 1,
+//           2u_c - 1, r_in, flag).  A *marginal* evaluation (flag 0, r_in 0)
+//           gives the exit frequency, exit point and count at three independent
+//           quantile levels; a *conditional* one (flag 1, r_in = sqrt2 r - 1,
+//           u_c slot 0) gives the exit direction given the exit point's
+//           distance r from the face centre, since photons leaving near an
+//           edge travel more obliquely and away from the centre.
+// Outputs (normalised): marginal: 0 quantile at u_a of x_out given x_out >= 0;
+//           1, 2 quantiles at u_b, u_c of the exit point (s, t) on the exit
+//           face; 4 ln E[N_s] (scatterings inside the cube); 5 quantile at u_a
+//           of ln <x^2> over those scatterings; 6 logit P(x_out >= 0); 7
+//           quantile at u_a of -x_out given x_out < 0.  Conditional: 3 quantile
+//           at u_a of the cosine mu of the exit direction to the face normal; 8
+//           quantile at u_b of the angle alpha between the direction's
+//           tangential part and the exit point's offset (s, t).  9 unused (the
+//           parameter count stays even).  The exit frequency is bimodal, so it
+//           is drawn as a two-component mixture (side, then a one-sided
+//           quantile): a single smooth quantile function of the signed x_out
+//           would fill the empty line core between the peaks.
 //
 // The layers are evaluated transposed, H^T_{l+1} = SiLU(W_l^T H^T_l + b_l),
 // with v_mfma_f32_16x16x16_bf16 on 16-sample blocks: the accumulator layout of
@@ -25,25 +33,30 @@
 
 namespace krt {
 
-constexpr int kMlpIn = 4, kMlpHid = 128, kMlpOut = 8;
+constexpr int kMlpIn = 8, kMlpHid = 128, kMlpOut = 10;
 // output indices
 constexpr int kOutXPos = 0, kOutS = 1, kOutT = 2, kOutMu = 3, kOutLogN = 4, kOutLogX2 = 5, kOutLogit = 6,
-              kOutXNeg = 7;
+              kOutXNeg = 7, kOutAlpha = 8, kOutSpare = 9;
+// escape record layout (floats per record) and its columns
+constexpr int kRec = 11;
+constexpr int kRecXOut = 3, kRecS = 4, kRecT = 5, kRecMu = 6, kRecLogN = 7, kRecLogX2 = 8, kRecValid = 9,
+              kRecAlpha = 10;
 // ln E[N_s]: weighted log-deviance loss with its exponent clamped
 constexpr float kDevClamp = 4.0f;
 constexpr float kDevWeight = 0.25f;
 // FP32 master parameter block (offsets in floats)
-constexpr int kPW1 = 0;                                  // W1[4][128]   (in, out)
+constexpr int kPW1 = 0;                                  // W1[8][128]   (in, out)
 constexpr int kPB1 = kPW1 + kMlpIn * kMlpHid;            // b1[128]
 constexpr int kPW2 = kPB1 + kMlpHid;                     // W2[128][128]
 constexpr int kPB2 = kPW2 + kMlpHid * kMlpHid;
 constexpr int kPW3 = kPB2 + kMlpHid;
 constexpr int kPB3 = kPW3 + kMlpHid * kMlpHid;
-constexpr int kPW4 = kPB3 + kMlpHid;                     // W4[128][8]
-constexpr int kPB4 = kPW4 + kMlpHid * kMlpOut;           // b4[8]
-constexpr int kNParams = kPB4 + kMlpOut;                 // 34696
+constexpr int kPW4 = kPB3 + kMlpHid;                     // W4[128][10]
+constexpr int kPB4 = kPW4 + kMlpHid * kMlpOut;           // b4[10]
+constexpr int kNParams = kPB4 + kMlpOut;                 // 35466
 // target normalisation: y_norm = (y - mean) / scale, stored after the params
-// (output 6, the side logit, has mean 0 and scale 1), followed by the
+// (output 6, the side logit, and the unused output 9 have mean 0 and scale 1),
+// followed by the
 // calibration of ln E[N_s]: an additive term per bin of (log10 tau_R, |x_in|)
 constexpr int kNCalT = 32, kNCalX = 8, kNCal = kNCalT * kNCalX;
 constexpr float kCalLo = 1.0f, kCalInvW = 8.0f;  // bins of 0.125 in log10 tau_R from 1 to 5
@@ -58,7 +71,7 @@ __device__ __forceinline__ int cal_bin(float lt, float xin) {
 }
 
 // Packed BF16 A-operand tiles (16x16, 512 B each: 64 lanes x 4 bf16).
-// Forward (W^T, rows = out-features): L1 8 tiles (K padded 4 -> 16), L2 64, L3 64, L4 8 (rows padded 8 -> 16).
+// Forward (W^T, rows = out-features): L1 8 tiles (K padded 8 -> 16), L2 64, L3 64, L4 8 (rows padded 10 -> 16).
 constexpr int kTilesL1 = 8, kTilesL2 = 64, kTilesL3 = 64, kTilesL4 = 8;
 constexpr int kTileFwdL1 = 0, kTileFwdL2 = kTilesL1, kTileFwdL3 = kTileFwdL2 + kTilesL2,
               kTileFwdL4 = kTileFwdL3 + kTilesL3, kTilesFwd = kTileFwdL4 + kTilesL4;   // 144
@@ -70,6 +83,8 @@ constexpr int kTileBytes = 512;
 constexpr int kBiasFloats = 3 * kMlpHid + 16;
 constexpr int kMlpFwdBytes = kTilesFwd * kTileBytes + kBiasFloats * 4 + kNNorm * 4;  // LDS image for inference
 constexpr int kMlpBlobBytes = kTilesAll * kTileBytes + kBiasFloats * 4 + kNNorm * 4;
+static_assert(kMlpIn <= 8 && kMlpOut <= 16, "inputs fill two lane groups, outputs one 16-row tile");
+static_assert(kMlpFwdBytes % 16 == 0, "the inference image is staged into LDS in 16-byte words");
 
 typedef short v4i16 __attribute__((ext_vector_type(4)));
 typedef float v4f32 __attribute__((ext_vector_type(4)));
@@ -103,7 +118,8 @@ __device__ __forceinline__ v4i16 tileA(const unsigned char *blob, int t, int lan
 }
 
 // Forward pass of one 16-sample block.  xin: this lane's B operand for layer 1
-// (lanes 0..15 hold the 4 inputs of sample l%16, other lanes zeros).  Returns
+// (lanes 0..15 hold inputs 0..3 of sample l%16, lanes 16..31 inputs 4..7,
+// other lanes zeros).  Returns
 // the output tile (lane l: outputs 4(l/16)+j of sample l%16).  If z1..z3 are
 // given, the pre-activations are stored (8 tiles each) for the backward pass.
 __device__ __forceinline__ v4f32 mlp_forward_block(const unsigned char *tiles, const float *bias,

@@ -88,10 +88,11 @@ __device__ __forceinline__ int nth_set_lane(uint64_t m, int k) {
 // Batched evaluation of the escape network for the lanes of the wave set in
 // `ask` (wave-uniform control flow: every lane executes the MFMA).  The asking
 // lanes are packed in rank order into blocks of 16 samples, so a call costs
-// ceil(popcount(ask) / 16) block evaluations.  in[4] are this lane's
-// normalised inputs; an asking lane receives its 6 normalised outputs in out[].
-__device__ __attribute__((noinline)) void mlp_eval_wave(const unsigned char *img, const float *bias, const float in[4],
-                                              int lane, uint64_t ask, float out[kMlpOut]) {
+// ceil(popcount(ask) / 16) block evaluations.  in[] are this lane's
+// normalised inputs; an asking lane receives its normalised outputs in out[].
+__device__ __attribute__((noinline)) void mlp_eval_wave(const unsigned char *img, const float *bias,
+                                              const float in[kMlpIn], int lane, uint64_t ask,
+                                              float out[kMlpOut]) {
     const int nask = __popcll(ask);
     const int nblk = (nask + 15) >> 4;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -102,9 +103,13 @@ __device__ __attribute__((noinline)) void mlp_eval_wave(const unsigned char *img
         // block position p = lane & 15 holds the asker of rank 16 b + p (if any)
         const int r = 16 * b + (lane & 15);
         const int src = (r < nask) ? nth_set_lane(ask, r) : lane;
-        float i0 = __shfl(in[0], src, 64), i1 = __shfl(in[1], src, 64);
-        float i2 = __shfl(in[2], src, 64), i3 = __shfl(in[3], src, 64);
-        v4i16 xb = (lane < 16 && r < nask) ? pack4(i0, i1, i2, i3) : pack4(0.f, 0.f, 0.f, 0.f);
+        // lanes 0..15 carry inputs 0..3 of their block position, lanes 16..31 inputs 4..7
+        float v[kMlpIn];
+#pragma unroll
+        for (int k = 0; k < kMlpIn; ++k) v[k] = __shfl(in[k], src, 64);
+        v4i16 xb = pack4(0.f, 0.f, 0.f, 0.f);
+        if (r < nask && lane < 16) xb = pack4(v[0], v[1], v[2], v[3]);
+        else if (r < nask && lane < 32) xb = pack4(v[4], v[5], v[6], v[7]);
         v4f32 o = mlp_forward_block(img, bias, xb, lane, nullptr, nullptr, nullptr);
         // output k of block position p sits in lane 16*(k/4) + p, component k % 4
 #pragma unroll
@@ -144,8 +149,8 @@ __device__ __forceinline__ void scatter_draws(uint4 B, bool dipole, SDraws &d) {
     d.sp = sin_rev(psi);
 }
 
-template <bool kEsc>
-__global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
+template <bool kEsc, int kMaxThreads>
+__global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) {
     extern __shared__ float4 lds4[];
     float *T = reinterpret_cast<float *>(lds4);
     float *sedges = T + kTabFloats;                      // spectrum edges
@@ -464,52 +469,61 @@ __global__ void __launch_bounds__(1024) mc_transport_kernel(RunParams P) {
             const uint64_t wm = __ballot(mlp);
             const int need_lanes = (__ballot(done) != 0ull) ? P.esc_tail_lanes : P.esc_min_lanes;
             if (__popcll(wm) >= need_lanes) {
-                uint4 C = philox(make_uint4(ev, (uint32_t)pid, (uint32_t)(pid >> 32), 2u), P.key0, P.key1);
-                float in[4];
+                // marginal evaluation: exit frequency (u_a), exit point (u_b, u_c), count
+                const uint4 C = philox(make_uint4(ev, (uint32_t)pid, (uint32_t)(pid >> 32), 2u), P.key0, P.key1);
+                const uint4 D = philox(make_uint4(ev, (uint32_t)pid, (uint32_t)(pid >> 32), 3u), P.key0, P.key1);
+                float in[kMlpIn];
                 in[0] = (lt - 3.5f) * (1.0f / 1.5f);
                 in[1] = P.esc_log10a + 3.0f;
                 in[2] = xc * 0.25f;
                 in[3] = 2.0f * u01(C.x) - 1.0f;
+                in[4] = 2.0f * u01(C.y) - 1.0f;
+                in[5] = 2.0f * u01(D.y) - 1.0f;
+                in[6] = 0.0f;
+                in[7] = 0.0f;
                 mlp_eval_wave(mimg, mbias, in, lane, wm, mo);
-                in[3] = 2.0f * u01(C.y) - 1.0f;
+                // exit point on the face, then the symmetry of the cube: face,
+                // swap of (s, t), signs
+                float tt = fminf(fmaxf(mo[kOutT] * mnorm[kMlpOut + kOutT] + mnorm[kOutT], -1.0f), 1.0f);
+                float ss = fminf(fmaxf(mo[kOutS] * mnorm[kMlpOut + kOutS] + mnorm[kOutS], -1.0f), 1.0f);
+                const uint32_t bits = C.z;
+                if (bits & 0x100u) { float tmp = ss; ss = tt; tt = tmp; }
+                if (bits & 0x200u) ss = -ss;
+                if (bits & 0x400u) tt = -tt;
+                // conditional evaluation: exit direction given the exit point's
+                // distance from the face centre (mu at u_a, alpha at u_b)
+                const float rr = f_sqrt(ss * ss + tt * tt);
+                in[3] = 2.0f * u01(D.z) - 1.0f;
+                in[4] = 2.0f * u01(C.w) - 1.0f;
+                in[5] = 0.0f;
+                in[6] = 1.41421356f * rr - 1.0f;
+                in[7] = 1.0f;
                 mlp_eval_wave(mimg, mbias, in, lane, wm, mo2);
-                // independent quantile levels for t and mu (two more evaluations)
-                const uint4 D = philox(make_uint4(ev, (uint32_t)pid, (uint32_t)(pid >> 32), 3u), P.key0, P.key1);
-                const bool indep = P.esc_evals != 2;
-                float mo3[kMlpOut], mo4[kMlpOut];
-                if (indep) {
-                    in[3] = 2.0f * u01(D.y) - 1.0f;
-                    mlp_eval_wave(mimg, mbias, in, lane, wm, mo3);
-                    in[3] = 2.0f * u01(D.z) - 1.0f;
-                    mlp_eval_wave(mimg, mbias, in, lane, wm, mo4);
-                }
                 if (mlp) {
                     // ---- exit from the cube centred here (half-width Rcube) ----
                     // exit frequency: side from the learned P(x_out >= 0) and a word of
-                    // purpose 3, magnitude from that side's quantile at level u1
+                    // purpose 3, magnitude from that side's quantile at level u_a
                     const bool pos = u01(D.x) < sigmoid_f(mo[kOutLogit]);
                     const int ko = pos ? kOutXPos : kOutXNeg;
                     const float mag = fmaxf(mo[ko] * mnorm[kMlpOut + ko] + mnorm[ko], 0.0f);
                     float xo = pos ? mag : -mag;
-                    const float ot = indep ? mo3[kOutT] : mo[kOutT];
-                    const float omu = indep ? mo4[kOutMu] : mo2[kOutMu];
-                    float tt = fminf(fmaxf(ot * mnorm[kMlpOut + kOutT] + mnorm[kOutT], -1.0f), 1.0f);
                     float lns = mo[kOutLogN] * mnorm[kMlpOut + kOutLogN] + mnorm[kOutLogN] +
                                 mnorm[2 * kMlpOut + cal_bin(lt, xc)];
                     float lx2 = mo[kOutLogX2] * mnorm[kMlpOut + kOutLogX2] + mnorm[kOutLogX2];
-                    float ss = fminf(fmaxf(mo2[kOutS] * mnorm[kMlpOut + kOutS] + mnorm[kOutS], -1.0f), 1.0f);
-                    float mu = fminf(fmaxf(omu * mnorm[kMlpOut + kOutMu] + mnorm[kOutMu], 1e-3f), 1.0f);
-                    // symmetry of the cube: face, swap of (s, t), signs
-                    uint32_t bits = C.z;
+                    float mu = fminf(fmaxf(mo2[kOutMu] * mnorm[kMlpOut + kOutMu] + mnorm[kOutMu], 1e-3f), 1.0f);
+                    const float al = fminf(fmaxf(mo2[kOutAlpha] * mnorm[kMlpOut + kOutAlpha] + mnorm[kOutAlpha], 0.0f),
+                                           3.14159265f);
                     int face = (int)__umulhi(bits, 6u);
                     int axis = face >> 1;
                     float sgn = (face & 1) ? -1.0f : 1.0f;
-                    if (bits & 0x100u) { float tmp = ss; ss = tt; tt = tmp; }
-                    if (bits & 0x200u) ss = -ss;
-                    if (bits & 0x400u) tt = -tt;
-                    float phi_d = u01(C.w);
+                    // tangential direction at angle +-alpha from the offset (s, t)
+                    // (the offset's direction is arbitrary at the face centre)
+                    const float ir = (rr > 0.0f) ? f_rcp(rr) : 0.0f;
+                    const float c0 = (rr > 0.0f) ? ss * ir : 1.0f, s0 = tt * ir;
+                    const float arev = al * 0.159154943f * ((D.w & 1u) ? -1.0f : 1.0f);
+                    const float ca = cos_rev(arev), sa = sin_rev(arev);
                     float sm = f_sqrt(fmaxf(0.0f, 1.0f - mu * mu));
-                    float dn = mu * sgn, d1 = sm * cos_rev(phi_d), d2 = sm * sin_rev(phi_d);
+                    float dn = mu * sgn, d1 = sm * (c0 * ca - s0 * sa), d2 = sm * (s0 * ca + c0 * sa);
                     float dp[3], ddir[3];
                     int a1 = (axis + 1) % 3, a2 = (axis + 2) % 3;
                     dp[axis] = sgn * Rcube; dp[a1] = ss * Rcube; dp[a2] = tt * Rcube;
@@ -723,16 +737,21 @@ __global__ void debug_upar_kernel(const float *tab, float a, float thd, float x,
 hipError_t launch_transport(const RunParams &P, int grid, int block, hipStream_t s) {
     const bool esc = P.mlp_img != nullptr;
     size_t lds = sizeof(float) * (kTabFloats + kEdgeFloats) + (esc ? (size_t)kMlpFwdBytes : 0);
-    static bool attr_set[2] = {false, false};
-    const void *fn = esc ? reinterpret_cast<const void *>(mc_transport_kernel<true>)
-                         : reinterpret_cast<const void *>(mc_transport_kernel<false>);
-    if (!attr_set[esc]) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    // the network variant in blocks of at most 512 lanes is compiled for 256
+    // VGPRs (no spills, 2 waves per SIMD); in larger blocks for 128 (4 waves)
+    const int variant = !esc ? 0 : (block <= 512 ? 2 : 1);
+    static bool attr_set[3] = {false, false, false};
+    const void *fns[3] = {reinterpret_cast<const void *>(mc_transport_kernel<false, 1024>),
+                          reinterpret_cast<const void *>(mc_transport_kernel<true, 1024>),
+                          reinterpret_cast<const void *>(mc_transport_kernel<true, 512>)};
+    if (!attr_set[variant]) {
+        hipError_t e = hipFuncSetAttribute(fns[variant], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
-        attr_set[esc] = true;
+        attr_set[variant] = true;
     }
-    if (esc) hipLaunchKernelGGL(mc_transport_kernel<true>, dim3(grid), dim3(block), lds, s, P);
-    else hipLaunchKernelGGL(mc_transport_kernel<false>, dim3(grid), dim3(block), lds, s, P);
+    if (variant == 0) hipLaunchKernelGGL((mc_transport_kernel<false, 1024>), dim3(grid), dim3(block), lds, s, P);
+    else if (variant == 1) hipLaunchKernelGGL((mc_transport_kernel<true, 1024>), dim3(grid), dim3(block), lds, s, P);
+    else hipLaunchKernelGGL((mc_transport_kernel<true, 512>), dim3(grid), dim3(block), lds, s, P);
     return hipGetLastError();
 }
 

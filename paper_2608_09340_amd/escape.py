@@ -27,7 +27,7 @@ def train_escape(ctx: "krt.Context", line: int = 0, n_records: int = 8_000_000, 
     concatenated)."""
     import torch
     dev = torch.device("cuda", ctx.device)
-    rec = torch.zeros((n_records, 10), dtype=torch.float32, device=dev)
+    rec = torch.zeros((n_records, krt.ESC_NREC), dtype=torch.float32, device=dev)
     ctx.krt_escape_record(line, n_records, seed, record_offset, log10_tau[0], log10_tau[1], rec)
     ctx.krt_escape_init(seed)
     ctx.krt_escape_fit_norm(rec, n_records)

@@ -72,7 +72,7 @@ EXPORTS = ["krt_create", "krt_destroy", "krt_last_error", "krt_device_cus", "krt
            "krt_escape_init", "krt_escape_record", "krt_escape_fit_norm", "krt_escape_calibrate", "krt_escape_grad",
            "krt_escape_train", "krt_escape_get_weights", "krt_escape_put_weights", "krt_escape_forward",
            "krt_image", "krt_last_image_ms"]
-ESC_NPARAMS, ESC_NNORM, ESC_NOUT, ESC_NCAL = 34696, 272, 8, 256
+ESC_NPARAMS, ESC_NNORM, ESC_NIN, ESC_NOUT, ESC_NCAL, ESC_NREC = 35466, 276, 8, 10, 256, 11
 
 _lib = None
 
@@ -224,6 +224,9 @@ class Context:
         self._check(self.L.krt_escape_calibrate(self.h, _ptr(rec), int(n)))
 
     def krt_escape_grad(self, rec, idx, u, grad_out, loss_out=None):
+        """u: [batch][4] = (u_a, u_b, u_c, 1 for a conditional row else 0)."""
+        if tuple(u.shape) != (idx.numel(), 4):
+            raise ValueError(f"u must be [{idx.numel()}][4], got {tuple(u.shape)}")
         self._check(self.L.krt_escape_grad(self.h, _ptr(rec), _ptr(idx), _ptr(u), int(idx.numel()),
                                            _ptr(grad_out), _ptr(loss_out)))
 
@@ -238,6 +241,9 @@ class Context:
         self._check(self.L.krt_escape_put_weights(self.h, _ptr(w), w.numel()))
 
     def krt_escape_forward(self, inp, out):
+        """inp: [n][8] raw (log10 tau_R, log10 a, x_in, u_a, u_b, u_c, r, flag); out: [n][10]."""
+        if inp.dim() != 2 or inp.shape[1] != ESC_NIN or tuple(out.shape) != (inp.shape[0], ESC_NOUT):
+            raise ValueError(f"inp must be [n][{ESC_NIN}] and out [n][{ESC_NOUT}]")
         self._check(self.L.krt_escape_forward(self.h, _ptr(inp), inp.shape[0], _ptr(out)))
 
     def krt_image(self, desc: krt_image_desc):

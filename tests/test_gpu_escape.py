@@ -35,58 +35,89 @@ def _rand_params(seed):
     return mlp.pack(d)
 
 
+# target normalisation (mean[10], scale[10]) for the synthetic checks
+NORM = np.array([2.5, 0, 0, 0.7, 6, 0.1, 0.0, 2.4, 1.0, 0.0,
+                 1.5, 0.5, 0.5, 0.2, 1.5, 1.0, 1.0, 1.4, 0.6, 1.0])
+
+
+def _raw_rows(rng, n, cond):
+    """Raw forward rows (log10 tau_R, log10 a, x_in, u_a, u_b, u_c, r, flag)."""
+    return np.stack([rng.uniform(2, 5, n), rng.uniform(-4, -2, n), rng.uniform(-8, 8, n), rng.uniform(0, 1, n),
+                     rng.uniform(0, 1, n), rng.uniform(0, 1, n), rng.uniform(0, np.sqrt(2), n),
+                     cond.astype(np.float64)], 1)
+
+
 def test_mfma_forward_vs_fp64(gpu_ctx):
+    """BF16-MFMA forward of marginal and conditional rows vs the FP64 network
+    (with and without bfloat16 rounding of weights and activations)."""
     import torch
     p = _rand_params(3)
-    norm = np.array([2.5, 0, 0, 0.7, 6, 0.1, 0.0, 2.4, 1.5, 0.5, 0.5, 0.2, 1.5, 1.0, 1.0, 1.4])
-    _put(gpu_ctx, p, norm)
+    _put(gpu_ctx, p, NORM)
     rng = np.random.default_rng(4)
     n = 3000
-    raw = np.stack([rng.uniform(2, 5, n), rng.uniform(-4, -2, n), rng.uniform(-8, 8, n), rng.uniform(0, 1, n)], 1)
+    cond = rng.uniform(0, 1, n) < 0.4
+    raw = _raw_rows(rng, n, cond)
     out = torch.zeros((n, NO), dtype=torch.float32, device="cuda")
     gpu_ctx.krt_escape_forward(torch.from_numpy(raw.astype(np.float32)).cuda(), out)
     g = out.cpu().numpy().astype(np.float64)
-    X = mlp.inputs(raw[:, 0], raw[:, 1], raw[:, 2], raw[:, 3])
-    for bf, tol in ((True, 2e-2), (False, 6e-2)):
+    X = mlp.inputs(*(raw[:, k] for k in range(7)), cond)
+    # errors relative to each output's spread over the samples.  bf16 storage
+    # of weights and activations alone moves these outputs by 2.4-4.1% of their
+    # spread against FP64 (the emulation vs the unrounded network), so the
+    # unrounded comparison allows twice that; against the emulation only the
+    # accumulation order and rounding flips of activations remain (below 3%).
+    # A wrong input lane or layer is O(1)
+    for bf, tol in ((True, 3e-2), (False, 8e-2)):
         o, _, _ = mlp.forward(p, X, bf=bf)
-        ref = o * norm[NO:] + norm[:NO]
+        ref = o * NORM[NO:] + NORM[:NO]
         err = np.abs(g - ref) / (np.abs(ref).std(axis=0) + 1e-9)
         assert np.max(err) < tol, (bf, np.max(err, axis=0))
 
 
 def test_mfma_gradient_vs_fp64(gpu_ctx):
-    """d(mean pinball loss)/d(params) from the BF16-MFMA backward vs the FP64
-    reference: cosine >= 0.999 and relative L2 <= 2e-2 per tensor."""
+    """d(mean loss)/d(params) from the BF16-MFMA backward vs the FP64 reference
+    on a batch of marginal and conditional rows, each output at its own
+    quantile level: cosine >= 0.999 and relative L2 <= 2e-2 per tensor."""
     import torch
     p = _rand_params(5)
-    norm = np.array([2.5, 0, 0, 0.7, 6, 0.1, 0.0, 2.4, 1.5, 0.5, 0.5, 0.2, 1.5, 1.0, 1.0, 1.4])
+    norm = NORM
     _put(gpu_ctx, p, norm)
     rng = np.random.default_rng(6)
     nrec, B = 5000, 1024
-    rec = np.zeros((nrec, 10))
+    rec = np.zeros((nrec, 11))
     rec[:, 0] = rng.uniform(2, 5, nrec)
     rec[:, 1] = rng.uniform(-4, -2, nrec)
     rec[:, 2] = rng.uniform(-8, 8, nrec)
     rec[:, 3] = rng.choice([-1.0, 1.0], nrec) * np.abs(2.5 + 1.5 * rng.normal(0, 1, nrec))
-    rec[:, 4:9] = norm[1:6] + norm[NO + 1:NO + 6] * rng.normal(0, 1, (nrec, 5))
+    rec[:, 4:6] = rng.uniform(-1, 1, (nrec, 2))
+    rec[:, 6:9] = norm[3:6] + norm[NO + 3:NO + 6] * rng.normal(0, 1, (nrec, 3))
     rec[:, 9] = 1.0
+    rec[:, 10] = rng.uniform(0, np.pi, nrec)
     idx = rng.integers(0, nrec, B).astype(np.int32)
-    u = rng.uniform(0, 1, B)
+    ua, ub, uc = rng.uniform(0, 1, (3, B))
+    cond = rng.uniform(0, 1, B) < 0.25
+    u = np.stack([ua, ub, uc, cond.astype(np.float64)], 1)
     grad = torch.zeros(NP, dtype=torch.float32, device="cuda")
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
     gpu_ctx.krt_escape_grad(torch.from_numpy(rec.astype(np.float32)).cuda(),
                             torch.from_numpy(idx).cuda(), torch.from_numpy(u.astype(np.float32)).cuda(), grad, loss)
     g = grad.cpu().numpy().astype(np.float64)
-    R = rec[idx]
-    X = mlp.inputs(R[:, 0], R[:, 1], R[:, 2], u)
-    Y = mlp.targets_normalised(R, norm)
+    R = rec[idx].astype(np.float32).astype(np.float64)
+    X = mlp.inputs(R[:, 0], R[:, 1], R[:, 2], ua, ub, uc, np.hypot(R[:, 4], R[:, 5]), cond)
+    Y = mlp.targets_normalised(R, norm, cond)
+    U = mlp.levels(ua, ub, uc, cond)
     for bf in (True, False):
-        l_ref, g_ref = mlp.loss_and_grad(p, X, Y, u, bf=bf, s4=norm[NO + mlp.O_LOGN])
+        l_ref, g_ref = mlp.loss_and_grad(p, X, Y, U, bf=bf, s4=norm[NO + mlp.O_LOGN])
         o = 0
         for name, shp in mlp.SHAPES:
             k = int(np.prod(shp))
             a, b = g[o:o + k], g_ref[o:o + k]
             o += k
+            if name == "W4" or name == "b4":  # the unused output's column gets no gradient on either side
+                a = a.reshape(-1, NO)[:, :mlp.O_SPARE]
+                b = b.reshape(-1, NO)[:, :mlp.O_SPARE]
+                assert np.all(g[o - k:o].reshape(-1, NO)[:, mlp.O_SPARE] == 0.0)
+                a, b = a.reshape(-1), b.reshape(-1)
             cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-30)
             rel = np.linalg.norm(a - b) / (np.linalg.norm(b) + 1e-30)
             assert cos >= (0.999 if bf else 0.995) and rel <= (2e-2 if bf else 6e-2), (bf, name, cos, rel)
@@ -96,21 +127,22 @@ def test_mfma_gradient_vs_fp64(gpu_ctx):
 @pytest.mark.parametrize("tau,xin", [(1e3, 0.5), (1e4, 2.5)])
 def test_escape_records_vs_oracle(gpu_ctx, tau, xin):
     """Single-cell escapes from the GPU walk vs the oracle's FP64 walk at the same
-    condition: exit frequency, exit-point and exit-direction distributions (KS)
-    and the mean log number of scatterings."""
+    condition: exit frequency, exit-point and exit-direction distributions (KS,
+    including the alignment angle of the direction with the exit point) and
+    the mean log number of scatterings."""
     import torch
     from paper_2608_09340_amd import krt
     a = 1e-3
     T = krt.Transport(W.slab(10.0, a, 4), ctx=gpu_ctx)
     n = 40000
-    out = torch.zeros((n, 10), dtype=torch.float32, device="cuda")
+    out = torch.zeros((n, krt.ESC_NREC), dtype=torch.float32, device="cuda")
     lt = np.log10(tau)
     gpu_ctx.krt_escape_record(0, n, 7, 0, lt, lt, out, x_fixed=xin)
     g = out.cpu().numpy().astype(np.float64)
     no = 4000 if tau < 5e3 else 800
     o = oracle.escape_record(no, tau, a, xin, seed=8, offset=1 << 30)
     assert g[:, 9].min() == 1 and o[:, 9].min() == 1
-    for col in (3, 4, 6):
+    for col in (3, 4, 6, 10):
         ks = stats.ks_2samp(g[:, col], o[:, col])
         assert ks.pvalue > 1e-3, (tau, xin, col, ks)
     mg, mo = g[:, 7].mean(), o[:, 7].mean()
@@ -148,8 +180,9 @@ def test_calibration_unbiased_per_bin(gpu_ctx, trained):
     r = rec.cpu().numpy().astype(np.float64)
     gpu_ctx.krt_escape_calibrate(rec, rec.shape[0])
     n = rec.shape[0]
-    inp = rec[:, :4].clone()
-    inp[:, 3] = torch.rand(n, device=rec.device)
+    inp = torch.zeros((n, 8), dtype=torch.float32, device=rec.device)  # marginal rows
+    inp[:, :3] = rec[:, :3]
+    inp[:, 3:6] = torch.rand((n, 3), device=rec.device)
     out = torch.zeros((n, NO), dtype=torch.float32, device=rec.device)
     gpu_ctx.krt_escape_forward(inp.contiguous(), out)
     pred = np.exp(out[:, mlp.O_LOGN].cpu().numpy().astype(np.float64))
@@ -169,35 +202,55 @@ def test_calibration_unbiased_per_bin(gpu_ctx, trained):
 
 @pytest.mark.parametrize("tau,xin", [(3e1, 0.0), (3e2, 0.0), (3e3, 1.0), (3e4, 2.0)])
 def test_learned_samples_vs_plain(gpu_ctx, trained, tau, xin):
-    """At a fixed condition, the network's samples (quantiles at u ~ U(0,1), the
-    exit frequency through the two-component head) vs held-out plain
-    single-cell escapes: KS distance of exit frequency, exit point and exit
-    cosine below 0.04, exit-frequency histogram L1 below 0.13 (0.25-wide bins),
-    ln E[N_s] within 0.08."""
+    """At a fixed condition, the network's samples drawn as the transport draws
+    them (a marginal evaluation at three independent levels, then a
+    conditional one at the sampled exit point) vs held-out plain single-cell
+    escapes: KS distance of exit frequency, exit point, exit cosine and the
+    direction's alignment angle below 0.04; the mean alignment angle per band of
+    exit-point radius within 0.08 of the plain one (the correlation of
+    direction and exit point); exit-frequency histogram L1 below 0.13
+    (0.25-wide bins); ln E[N_s] within 0.08."""
     import torch
+    from paper_2608_09340_amd import krt
     n = 20000
-    out = torch.zeros((n, 10), dtype=torch.float32, device="cuda")
+    out = torch.zeros((n, krt.ESC_NREC), dtype=torch.float32, device="cuda")
     lt = np.log10(tau)
     gpu_ctx.krt_escape_record(0, n, 99, 1 << 32, lt, lt, out, x_fixed=xin)
     plain = out.cpu().numpy().astype(np.float64)
     rng = np.random.default_rng(13)
-    raw = np.stack([np.full(n, lt), np.full(n, -3.0), np.full(n, xin), rng.uniform(0, 1, n)], 1).astype(np.float32)
+    ua, ub, uc = rng.uniform(0, 1, (3, n))
+    raw = np.stack([np.full(n, lt), np.full(n, -3.0), np.full(n, xin), ua, ub, uc, np.zeros(n), np.zeros(n)], 1)
     pred = torch.zeros((n, NO), dtype=torch.float32, device="cuda")
-    gpu_ctx.krt_escape_forward(torch.from_numpy(raw).cuda(), pred)
+    gpu_ctx.krt_escape_forward(torch.from_numpy(raw.astype(np.float32)).cuda(), pred)
     m = pred.cpu().numpy().astype(np.float64)
+    s_l, t_l = np.clip(m[:, mlp.O_S], -1, 1), np.clip(m[:, mlp.O_T], -1, 1)
+    r_l = np.hypot(s_l, t_l)
+    raw2 = np.stack([np.full(n, lt), np.full(n, -3.0), np.full(n, xin), rng.uniform(0, 1, n), rng.uniform(0, 1, n),
+                     np.zeros(n), r_l, np.ones(n)], 1)
+    gpu_ctx.krt_escape_forward(torch.from_numpy(raw2.astype(np.float32)).cuda(), pred)
+    m2 = pred.cpu().numpy().astype(np.float64)
+    mu_l = np.clip(m2[:, mlp.O_MU], 1e-3, 1.0)
+    al_l = np.clip(m2[:, mlp.O_ALPHA], 0.0, np.pi)
     # exit frequency from the mixture head: side, then that side's quantile
     pos = rng.uniform(0, 1, n) < 1.0 / (1.0 + np.exp(-m[:, mlp.O_LOGIT]))
     xo = np.where(pos, np.maximum(m[:, mlp.O_XPOS], 0.0), -np.maximum(m[:, mlp.O_XNEG], 0.0))
-    ks = {0: stats.ks_2samp(xo, plain[:, 3]).statistic}
-    ks.update({k: stats.ks_2samp(m[:, k], plain[:, col]).statistic for k, col in ((1, 4), (2, 5), (3, 6))})
+    ks = {"x_out": stats.ks_2samp(xo, plain[:, 3]).statistic, "s": stats.ks_2samp(s_l, plain[:, 4]).statistic,
+          "t": stats.ks_2samp(t_l, plain[:, 5]).statistic, "mu": stats.ks_2samp(mu_l, plain[:, 6]).statistic,
+          "alpha": stats.ks_2samp(al_l, plain[:, 10]).statistic}
     # histogram L1 of the exit frequency (bins of 0.25), against the plain-vs-plain floor
     edges = np.linspace(-12, 12, 97)
     hp = np.histogram(plain[:, 3], edges)[0]
     hm = np.histogram(xo, edges)[0]
     l1 = np.abs(hp / n - hm / n).sum()
-    print(f"tau={tau} x_in={xin} KS x_out {ks[0]:.4f} s {ks[1]:.4f} t {ks[2]:.4f} mu {ks[3]:.4f} "
-          f"x_out L1 {l1:.4f} P(x>=0) learned {pos.mean():.3f} plain {(plain[:, 3] >= 0).mean():.3f}")
+    r_p = np.hypot(plain[:, 4], plain[:, 5])
+    bands = [(0.0, 0.4), (0.4, 0.8), (0.8, 1.5)]
+    al_band = [(al_l[(r_l >= lo) & (r_l < hi)].mean(), plain[(r_p >= lo) & (r_p < hi), 10].mean()) for lo, hi in bands]
+    print(f"tau={tau} x_in={xin} KS " + " ".join(f"{k} {v:.4f}" for k, v in ks.items()) +
+          f" x_out L1 {l1:.4f} P(x>=0) learned {pos.mean():.3f} plain {(plain[:, 3] >= 0).mean():.3f}"
+          f" mean alpha by r band (learned, plain) " + " ".join(f"({a:.3f}, {b:.3f})" for a, b in al_band))
     assert max(ks.values()) < 0.04, (tau, xin, ks)
+    for a_l, a_p in al_band:
+        assert abs(a_l - a_p) < 0.08, al_band
     # density level: two plain samples of this size differ by L1 ~ 0.04 in these bins
     assert l1 < 0.13, l1
     # output 4 is ln E[N_s]: against the log of the plain mean count (8%)
@@ -217,12 +270,15 @@ def _agg_emis(em, n, blocks=8):
 def test_cloud_learned_escape_vs_plain(gpu_ctx, trained):
     """Turbulent cloud (64^3, 30% of cells with line-centre depth >= 1e2): the
     plain random walk judges the learned escape.  Spectrum and aggregated
-    emissivity L1 <= 2% beyond the plain-vs-plain noise floor, and the learned
-    run needs fewer transport iterations (scatterings + network calls)."""
+    emissivity L1 <= 2% beyond the plain-vs-plain noise floor, total emissivity
+    within 2%, and the learned run needs fewer transport iterations
+    (scatterings + network calls).  1e6 packets: the per-packet scattering
+    count is heavy-tailed (packets trapped in the thickest cells), so with 1e5
+    two plain runs already differ by about 2% in total."""
     from paper_2608_09340_amd import krt
     p = W.cloud_c4(n=64, spec=(256, -40.0, 40.0), emis=(16, -16.0, 16.0))
     T = krt.Transport(p, ctx=gpu_ctx)
-    N = 100_000
+    N = 1_000_000
     pa = T.run(N, seed=0)
     pb = T.run(N, seed=0, packet_offset=1 << 32)
     ml = T.run(N, seed=0, escape_mode=1)
@@ -238,8 +294,37 @@ def test_cloud_learned_escape_vs_plain(gpu_ctx, trained):
           f"plain scat {pa['counters']['scatterings']} mlp scat {c['scatterings']} calls {c['mlp_calls']} "
           f"skipped {c['skipped_scatterings']}")
     tot = em.sum() / ea.sum()
-    print(f"emissivity total learned / plain {tot:.4f}")
+    print(f"emissivity total learned / plain {tot:.4f} (plain / plain {eb.sum() / ea.sum():.4f})")
     assert l1_s <= 0.02 + floor_s
     assert l1_e <= 0.02 + floor_e
     assert abs(tot - 1.0) < 0.02
     assert c["scatterings"] + c["mlp_calls"] < pa["counters"]["scatterings"]
+
+
+@pytest.mark.parametrize("tau_min", [100.0, 740.0])
+def test_chained_escapes_single_cell_count(gpu_ctx, trained, tau_min):
+    """One thick cell (line-centre depth 3000 across, a = 1e-3) with the source
+    off centre, so a packet takes several network calls and plain walks between
+    them: the learned run's total emissivity (skipped scatterings included)
+    matches the plain walk's within 1.2%.  This needs the exit direction drawn
+    given the exit point: with an azimuth independent of it the total is about
+    2% high, since real photons leave near an edge heading away from the face
+    centre."""
+    from paper_2608_09340_amd import krt
+    p = W._problem((1, 1, 1), (-1.0,) * 3, (1.0,) * 3, (0, 0, 0), np.array([1500.0]), 1e-3,
+                   source={"kind": W.SRC_POINT, "pos": (0.5, 0.3, 0.1), "profile": W.PROF_DELTA, "x0": 0.0},
+                   tally={"spec_nbins": 128, "spec_lo": -16.0, "spec_hi": 16.0, "emis_nch": 32, "ch_lo": -8.0,
+                          "ch_hi": 8.0, "n_cam": (1.0, 0.0, 0.0)})
+    T = krt.Transport(p, ctx=gpu_ctx)
+    N = 100_000
+    pa = T.run(N, seed=0)
+    pb = T.run(N, seed=0, packet_offset=1 << 32)
+    ml = T.run(N, seed=0, escape_mode=1, esc_tau_min=tau_min, esc_min_lanes=1, esc_tail_lanes=1)
+    assert pa["rc"] == 0 and ml["rc"] == 0
+    ea, eb, em = (r["emis_raw"][0].astype(np.float64).sum() for r in (pa, pb, ml))
+    c = ml["counters"]
+    print(f"tau_min {tau_min}: calls/pkt {c['mlp_calls'] / N:.3f} learned/plain {em / ea:.4f} "
+          f"(plain/plain {eb / ea:.4f}) spectrum L1 {l1_shape(pa['spec_raw'], ml['spec_raw']):.4f} "
+          f"(floor {l1_shape(pa['spec_raw'], pb['spec_raw']):.4f})")
+    assert c["mlp_calls"] > N
+    assert abs(em / ea - 1.0) < 0.012

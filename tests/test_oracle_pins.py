@@ -387,7 +387,9 @@ def _exit_geometry(n):
 def test_escape_record_thin_cube_is_ray_geometry():
     """tau_R -> 0: after the scattering at the centre the photon leaves the cube
     unscattered, so N_s = 1 and (s, t, mu) follow the straight-ray geometry of
-    an isotropic direction (KS against numpy directions)."""
+    an isotropic direction (KS against numpy directions); its tangential
+    direction points along the exit point's offset from the face centre, so
+    the alignment angle alpha is 0."""
     from scipy import stats
     n = 20000
     rec = oracle.escape_record(n, 1e-5, 1e-3, 0.0, seed=3)
@@ -399,14 +401,20 @@ def test_escape_record_thin_cube_is_ray_geometry():
     s, t, mu = _exit_geometry(v)
     for col, ref in ((4, s), (5, t), (6, mu)):
         assert stats.ks_2samp(rec[:, col], ref).pvalue > 1e-3, col
+    assert np.all(np.abs(rec[:, 10]) < 1e-9)
 
 
 def test_escape_record_symmetries_and_bounds():
     """At depth tau_R = 50 with x_in = 0: the exit point is symmetric about the
     face centre, the exit frequency symmetric about 0, every record valid with
-    N_s >= 1 and the exit point on the face."""
+    N_s >= 1 and the exit point on the face; the alignment angle alpha lies in
+    [0, pi] and the direction leans away from the face centre (mean alpha
+    below the pi/2 of an unrelated azimuth), more so near the edges."""
     rec = oracle.escape_record(4000, 50.0, 1e-3, 0.0, seed=4)
     assert np.all(rec[:, 9] == 1.0) and np.all(rec[:, 7] >= 0.0)
+    al, r = rec[:, 10], np.hypot(rec[:, 4], rec[:, 5])
+    assert np.all((al >= 0.0) & (al <= np.pi))
+    assert al.mean() < 1.2 and al[r > 0.8].mean() < al[r < 0.4].mean() - 0.3
     assert np.all(np.abs(rec[:, 4:6]) <= 1.0) and np.all((rec[:, 6] > 0) & (rec[:, 6] <= 1.0))
     se = 1.0 / np.sqrt(len(rec))
     for col in (3, 4, 5):
