@@ -250,13 +250,14 @@ int krt_levels_update(krt_ctx *ctx, const krt_levels_desc *desc,
  * propagates every photon through the full optical depth (Sec. 2.3.2,
  * Sec. 4.1); this proposal is the accelerated alternative it points to for
  * extreme depths, and the plain random walk remains the fallback (below
- * threshold, |x| > 8, a outside [1e-4, 1e-2]); above tau_R = 1e5 the cube is
+ * threshold, gas-frame |x| > 2, a outside [1e-4, 1e-2]); above tau_R = 1e5 the cube is
  * shrunk to that depth.
- * Inputs (log10 tau_R, log10 a, x_in, u_a, u_b, u_c, r, flag), in two kinds of
- * evaluation: marginal (flag 0; r ignored) at three independent quantile
- * levels, and conditional (flag 1; u_c ignored) at the exit point's distance r
- * from the face centre, because photons leaving near an edge travel more
- * obliquely and away from the centre.  Marginal outputs: 0 quantile at u_a of
+ * Inputs (log10 tau_R, log10 a, x_in, u_a, u_b, w, r, flag), in two kinds of
+ * evaluation: marginal (flag 0; w = u_c, r ignored) at three independent
+ * quantile levels, and conditional (flag 1; w = x_out) at the sampled exit
+ * frequency and the exit point's distance r from the face centre, because
+ * photons leaving near an edge travel more obliquely and away from the centre
+ * and wing photons leave closer to the normal.  Marginal outputs: 0 quantile at u_a of
  * x_out given x_out >= 0; 1, 2 quantiles at u_b, u_c of the exit point (s, t);
  * 4 ln E[N_s | tau_R, a, x_in]; 5 quantile at u_a of ln <x^2>; 6 logit
  * P(x_out >= 0); 7 quantile at u_a of -x_out given x_out < 0.  Conditional
@@ -272,16 +273,21 @@ int krt_levels_update(krt_ctx *ctx, const krt_levels_desc *desc,
  * 35466 FP32 master values plus 276 constants: target normalisation mean[10],
  * scale[10], and 256 additive calibration terms of ln E[N_s], one per bin of
  * (log10 tau_R in 32 bins of 0.125 over [1, 5], clamped; |x_in| in 8 bins with
- * edges 0, .5, 1, 1.5, 2, 3, 4, 6), index = tau bin * 8 + x bin.
+ * width 0.25 over [0, 2), the last also taking larger |x_in|), index = tau bin * 8
+ * + x bin.  Beyond |x_in| = 2 the mean count is a steep mixture of photons that
+ * leave at once and photons redistributed into the core, which the network does
+ * not resolve; wing photons take plain scatterings until they are back in the
+ * core.
  *
  * krt_escape_init: He-uniform parameters from Philox(seed), Adam state zeroed.
  * krt_escape_record: n single-cell escapes for line `line`, log10 tau_R uniform
- *   in [lo, hi], x_in fixed (x_fixed = 1) or 1/2 N(0, 1/2) + 1/2 U[-8, 8];
+ *   in [lo, hi], x_in fixed (x_fixed = 1) or 1/2 N(0, 1/2) + 1/2 U[-3, 3];
  *   samples_dev [n][11] FP32: (log10 tau_R, log10 a, x_in, x_out, s, t, mu,
  *   ln N_s, ln <x^2>, valid, alpha).
  * krt_escape_fit_norm: target mean / scale from valid records; clears the
  *   calibration.
- * krt_escape_calibrate: per (log10 tau_R, |x_in|) bin with at least 100 valid records,
+ * krt_escape_calibrate: per (log10 tau_R, |x_in|) bin with at least 100 valid records
+ *   with |x_in| <= 2,
  *   the calibration term ln(sum N_s / sum exp(network ln E[N_s])) over the
  *   records (marginal rows, quantile levels drawn per record), so that the
  *   predicted mean count is unbiased bin by bin; other bins get 0.
@@ -293,7 +299,7 @@ int krt_levels_update(krt_ctx *ctx, const krt_levels_desc *desc,
  *   (Philox(seed)); loss_hist_dev [steps] or NULL.
  * krt_escape_get_weights / put_weights: [35466 + 276] FP32 device buffers.
  * krt_escape_forward: in_dev [n][8] raw (log10 tau_R, log10 a, x_in, u_a, u_b,
- *   u_c, r, flag) -> out_dev [n][10] in physical units (output 6 as a logit,
+ *   u_c or (flag 1) x_out, r, flag) -> out_dev [n][10] in physical units (output 6 as a logit,
  *   output 4 with its calibration term).
  * Errors: KRT_EINVAL (sizes, ranges), KRT_ESTATE (no init / no tables). */
 int krt_escape_init(krt_ctx *ctx, uint64_t seed);

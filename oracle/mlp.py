@@ -4,12 +4,16 @@ Same parameter layout as the GPU (one flat vector): W1[8][128], b1[128],
 W2[128][128], b2, W3[128][128], b3, W4[128][10], b4[10]; activations SiLU.
 
 Inputs (8), normalised as ((log10 tau - 3.5)/1.5, log10 a + 3, x_in / 4,
-2u_a - 1, 2u_b - 1, 2u_c - 1, r_in, flag).  A row is either *marginal*
-(flag 0, r_in 0) or *conditional* (flag 1, r_in = sqrt(2) r - 1 with r the
-exit point's distance from the face centre, u_c slot 0): the network is
-evaluated once at three independent quantile levels for the exit frequency,
-exit point and count, then once more at the sampled exit point for the exit
-direction, which depends on where on the face the photon leaves.
+L(u_a), L(u_b), w, r_in, flag) with L(u) = logit(u) / 4 the encoding of a
+quantile level (extreme levels get distinct inputs, so the far wing of the
+exit frequency is not flattened).  A row is either *marginal* (flag 0,
+w = L(u_c), r_in 0) or *conditional* (flag 1, w = x_out / 4 and
+r_in = sqrt(2) r - 1 with x_out the exit frequency and r the exit point's
+distance from the face centre): the network is evaluated once at three
+independent quantile levels for the exit frequency, exit point and count,
+then once more at the sampled exit frequency and point for the exit
+direction, which depends on both (photons leaving near an edge travel away
+from the face centre; wing photons leave closer to the normal).
 
 Outputs (index: meaning, loss, level), for a record with exit frequency x:
   marginal rows
@@ -20,7 +24,7 @@ Outputs (index: meaning, loss, level), for a record with exit frequency x:
   5: quantile of ln <x^2> over the scatterings   pinball at u_a
   6: logit P(x >= 0 | condition)                 logistic (Bernoulli) loss
   7: quantile of -x given x < 0                  pinball at u_a, records with x < 0
-  conditional rows (given r)
+  conditional rows (given r and x_out)
   3: quantile of mu (exit cosine to the normal)  pinball at u_a
   8: quantile of alpha (angle between the exit   pinball at u_b
      direction's tangential part and the exit point's offset (s, t))
@@ -56,6 +60,7 @@ MARGINAL = (O_XPOS, O_S, O_T, O_LOGN, O_LOGX2, O_LOGIT, O_XNEG)
 CONDITIONAL = (O_MU, O_ALPHA)
 N_OUT = O_LOGN
 DEV_CLAMP = 4.0
+LEVEL_MIN = 1e-4
 DEV_WEIGHT = 0.25
 
 
@@ -80,15 +85,23 @@ def bf16(a):
     return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
 
 
-def inputs(lt, la, xin, ua, ub, uc, r, cond):
-    """Normalised inputs; r (exit point radius) and uc are ignored on the rows
-    where they are not inputs (r on marginal rows, uc on conditional rows)."""
+def inputs(lt, la, xin, ua, ub, w, r, cond):
+    """Normalised inputs; w is u_c on marginal rows and the exit frequency x_out
+    on conditional rows; r (exit point radius) is ignored on marginal rows."""
     cond = np.asarray(cond, dtype=bool)
-    lt, la, xin, ua, ub, uc, r = np.broadcast_arrays(*(np.asarray(v, dtype=np.float64)
-                                                       for v in (lt, la, xin, ua, ub, uc, r)))
-    return np.stack([(lt - 3.5) / 1.5, la + 3.0, xin / 4.0, 2.0 * ua - 1.0, 2.0 * ub - 1.0,
-                     np.where(cond, 0.0, 2.0 * uc - 1.0), np.where(cond, np.sqrt(2.0) * r - 1.0, 0.0),
+    lt, la, xin, ua, ub, w, r = np.broadcast_arrays(*(np.asarray(v, dtype=np.float64)
+                                                      for v in (lt, la, xin, ua, ub, w, r)))
+    wl = np.where(cond, 0.5, w)  # the level slot of a marginal row
+    return np.stack([(lt - 3.5) / 1.5, la + 3.0, xin / 4.0, level_in(ua), level_in(ub),
+                     np.where(cond, w / 4.0, level_in(wl)), np.where(cond, np.sqrt(2.0) * r - 1.0, 0.0),
                      cond.astype(np.float64)], axis=-1)
+
+
+def level_in(u):
+    """Network input of a quantile level u: logit(u) / 4, u clamped to the
+    trained levels [1e-4, 1 - 1e-4] (beyond them a network would extrapolate)."""
+    u = np.clip(np.asarray(u, dtype=np.float64), LEVEL_MIN, 1.0 - LEVEL_MIN)
+    return 0.25 * (np.log(u) - np.log1p(-u))
 
 
 def levels(ua, ub, uc, cond):

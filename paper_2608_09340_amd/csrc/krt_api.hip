@@ -364,7 +364,7 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
     P.mlp_img = esc ? c->mlp_img : nullptr;
     P.esc_tau_min = (float)(o->esc_tau_min > 0.0 ? o->esc_tau_min : 100.0);
     P.esc_tau_max = 1e5f;
-    P.esc_x_max = 8.0f;
+    P.esc_x_max = kEscXMax;
     P.esc_log10a = (float)std::log10(c->lines[l].a);
     P.esc_min_lanes = o->esc_min_lanes > 0 ? o->esc_min_lanes : 8;
     P.esc_tail_lanes = o->esc_tail_lanes > 0 ? o->esc_tail_lanes : 1;

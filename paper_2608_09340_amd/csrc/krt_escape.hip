@@ -47,7 +47,7 @@ __global__ void __launch_bounds__(256) escape_record_kernel(const float *tab, fl
         float rr = f_sqrt(-f_log(u01(c.z)));
         xin = rr * cos_rev(u01(c.w));
     } else {
-        xin = -8.0f + 16.0f * u01(c.z);
+        xin = kRecXMax * (2.0f * u01(c.z) - 1.0f);
     }
     uint4 d = philox(make_uint4(0u, plo, phi, 4u), k0, k1);
     float mu0 = 2.0f * u01(d.x) - 1.0f, st0 = f_sqrt(fmaxf(0.0f, 1.0f - mu0 * mu0)), ph0 = u01(d.y);
@@ -211,17 +211,18 @@ __global__ void mlp_fwd_image_kernel(const unsigned char *blob, unsigned char *i
 }
 
 // ------------------------------------------------------------- inputs ---
-// Marginal rows: (condition, u_a, u_b, u_c, 0, 0); conditional rows: (condition,
-// u_a, u_b, 0, sqrt2 r - 1, 1) with r the exit point's distance from the face
-// centre.
-__device__ __forceinline__ void mlp_inputs(float lt, float la, float xin, float ua, float ub, float uc, float r,
+// Marginal rows: (condition, L(u_a), L(u_b), L(u_c), 0, 0); conditional rows:
+// (condition, L(u_a), L(u_b), x_out / 4, sqrt2 r - 1, 1) with x_out the exit
+// frequency and r the exit point's distance from the face centre; L the level
+// encoding.  w is u_c or x_out.
+__device__ __forceinline__ void mlp_inputs(float lt, float la, float xin, float ua, float ub, float w, float r,
                                            bool cond, float in[kMlpIn]) {
     in[0] = (lt - 3.5f) * (1.0f / 1.5f);
     in[1] = la + 3.0f;
     in[2] = xin * 0.25f;
-    in[3] = 2.0f * ua - 1.0f;
-    in[4] = 2.0f * ub - 1.0f;
-    in[5] = cond ? 0.0f : 2.0f * uc - 1.0f;
+    in[3] = level_in(ua);
+    in[4] = level_in(ub);
+    in[5] = cond ? 0.25f * w : level_in(w);
     in[6] = cond ? 1.41421356f * r - 1.0f : 0.0f;
     in[7] = cond ? 1.0f : 0.0f;
 }
@@ -251,7 +252,8 @@ __device__ __forceinline__ bool conditional_output(int k) { return k == kOutMu |
 
 // ---------------------------------------------------------- gradient ---
 // One wave per 16-sample block.  grad += d(mean loss)/d(params); loss += sum.
-// Row si uses record idx[si] and uq[4 si ..] = (u_a, u_b, u_c, conditional flag).
+// Row si uses record idx[si] and uq[4 si ..] = (u_a, u_b, u_c, conditional flag);
+// a conditional row takes the record's exit frequency and point as inputs.
 // Quantile outputs: pinball loss at their own level (the two one-sided
 // exit-frequency quantiles only on records of their side); ln N_s:
 // log-deviance; side: logistic.  Marginal rows train outputs 0-2 and 4-7,
@@ -276,7 +278,8 @@ __global__ void __launch_bounds__(256) mlp_grad_kernel(const unsigned char *blob
     const float ua = live ? ul[0] : 0.5f, ub = live ? ul[1] : 0.5f, uc = live ? ul[2] : 0.5f;
     const bool cond = live && ul[3] > 0.5f;
     float in[kMlpIn];
-    mlp_inputs(r[0], r[1], r[2], ua, ub, uc, sqrtf(r[kRecS] * r[kRecS] + r[kRecT] * r[kRecT]), cond, in);
+    mlp_inputs(r[0], r[1], r[2], ua, ub, cond ? r[kRecXOut] : uc, sqrtf(r[kRecS] * r[kRecS] + r[kRecT] * r[kRecT]),
+               cond, in);
     if (!live)
         for (int k = 0; k < kMlpIn; ++k) in[k] = 0.0f;
     v4i16 xb = xin_operand(in, lane);
@@ -438,19 +441,26 @@ __global__ void mlp_adam_kernel(float *p, float *m, float *v, float *grad, float
     grad[i] = 0.0f;
 }
 
+// Training quantile levels are uniform, clamped to the encoded range [1e-4, 1 - 1e-4]
+// (the pinball loss uses the clamped level too).
+__device__ __forceinline__ float train_level(uint32_t w) {
+    return fminf(fmaxf(u01(w), kLevelMin), 1.0f - kLevelMin);
+}
+
 // Random batch: indices uniform over the records, three quantile levels and
 // the row kind (conditional with probability 1/4).
 __global__ void mlp_batch_kernel(int64_t n, uint32_t k0, uint32_t k1, uint32_t step, int batch,
                                  int32_t *idx, float *uq) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= batch) return;
-    uint4 r = philox(make_uint4(step, (uint32_t)i, 0u, 9u), k0, k1);
+    const uint4 r = philox(make_uint4(step, (uint32_t)i, 0u, 9u), k0, k1);
+    const uint4 e = philox(make_uint4(step, (uint32_t)i, 1u, 9u), k0, k1);
     idx[i] = (int32_t)__umulhi(r.x, (uint32_t)n);
     float *q = uq + 4 * (int64_t)i;
-    q[0] = u01(r.y);
-    q[1] = u01(r.z);
-    q[2] = u01(r.w);
-    q[3] = (u01(philox(make_uint4(step, (uint32_t)i, 1u, 9u), k0, k1).x) < 0.25f) ? 1.0f : 0.0f;
+    q[0] = train_level(r.y);
+    q[1] = train_level(r.z);
+    q[2] = train_level(r.w);
+    q[3] = (u01(e.x) < 0.25f) ? 1.0f : 0.0f;
 }
 
 // Normalisation of the targets: mean and standard deviation over the valid
@@ -501,8 +511,8 @@ __global__ void mlp_norm_kernel(const float *rec, int64_t n, float *norm) {
 }
 
 // Forward for a list of raw rows in[n][8] = (log10 tau_R, log10 a, x_in, u_a,
-// u_b, u_c, r, flag): out[n][10] in physical units (ln E[N_s] with its
-// calibration term).
+// u_b, u_c or (flag 1) x_out, r, flag): out[n][10] in physical units (ln E[N_s]
+// with its calibration term).
 __global__ void __launch_bounds__(256) mlp_forward_kernel(const unsigned char *blob, const float *inp,
                                                           int64_t n, float *out) {
     const int lane = __lane_id(), w = threadIdx.x / 64;
@@ -527,8 +537,9 @@ __global__ void __launch_bounds__(256) mlp_forward_kernel(const unsigned char *b
     }
 }
 
-// Calibration sums over valid records: per bin of (log10 tau_R, |x_in|), the number of
-// records, sum N_s and sum exp(network ln E[N_s]) (without calibration), FP64.
+// Calibration sums over valid records with |x_in| <= kEscXMax (the range where the
+// network is asked): per bin of (log10 tau_R, |x_in|), the number of records,
+// sum N_s and sum exp(network ln E[N_s]) (without calibration), FP64.
 // One wave per 16-record block; block partial sums in LDS, then global atomics.
 __global__ void __launch_bounds__(256) mlp_calib_kernel(const unsigned char *blob, const float *rec, int64_t n,
                                                         double *sums) {
@@ -551,7 +562,7 @@ __global__ void __launch_bounds__(256) mlp_calib_kernel(const unsigned char *blo
         mlp_inputs(r[0], r[1], r[2], u01(q.x), u01(q.y), u01(q.z), 0.0f, false, in);
         v4f32 o = mlp_forward_block(blob, bias, xin_operand(in, lane), lane, nullptr, nullptr, nullptr);
         // output 4 sits in lane group g = 1, component 0
-        if (live && g == 1) {
+        if (live && g == 1 && fabsf(r[2]) <= kEscXMax) {
             const int b = cal_bin(r[0], r[2]);
             const double pred = exp((double)(o.x * norm[kMlpOut + kOutLogN] + norm[kOutLogN]));
             atomicAdd(&ls[b], 1.0);

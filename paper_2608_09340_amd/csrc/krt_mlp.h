@@ -3,13 +3,18 @@
 // kernels.  Not part of the C ABI.
 //
 // Network: 8 inputs -> 128 -> 128 -> 128 (SiLU) -> 10 outputs.
-// Inputs  : ((log10 tau_R - 3.5)/1.5, log10 a + 3, x_in / 4, 2u_a - 1, 2u_b - 1,
-//           2u_c - 1, r_in, flag).  A *marginal* evaluation (flag 0, r_in 0)
-//           gives the exit frequency, exit point and count at three independent
-//           quantile levels; a *conditional* one (flag 1, r_in = sqrt2 r - 1,
-//           u_c slot 0) gives the exit direction given the exit point's
-//           distance r from the face centre, since photons leaving near an
-//           edge travel more obliquely and away from the centre.
+// Inputs  : ((log10 tau_R - 3.5)/1.5, log10 a + 3, x_in / 4, L(u_a), L(u_b),
+//           w, r_in, flag), L(u) = logit(u) / 4 the encoding of a quantile
+//           level: extreme levels get distinct inputs, so the far wing of the
+//           exit frequency (the rare long flights by which photons leave a thick
+//           medium) is not flattened.  A *marginal* evaluation (flag 0,
+//           w = L(u_c), r_in 0) gives the exit frequency, exit point and count at three
+//           independent quantile levels; a *conditional* one (flag 1,
+//           w = x_out / 4, r_in = sqrt2 r - 1) gives the exit direction given
+//           the sampled exit frequency and the exit point's distance r from the
+//           face centre, since photons leaving near an edge travel more
+//           obliquely and away from the centre, and wing photons leave closer
+//           to the normal.
 // Outputs (normalised): marginal: 0 quantile at u_a of x_out given x_out >= 0;
 //           1, 2 quantiles at u_b, u_c of the exit point (s, t) on the exit
 //           face; 4 ln E[N_s] (scatterings inside the cube); 5 quantile at u_a
@@ -62,11 +67,18 @@ constexpr int kNCalT = 32, kNCalX = 8, kNCal = kNCalT * kNCalX;
 constexpr float kCalLo = 1.0f, kCalInvW = 8.0f;  // bins of 0.125 in log10 tau_R from 1 to 5
 constexpr int kNNorm = 2 * kMlpOut + kNCal;
 
-// |x_in| bins: [0, .5), [.5, 1), [1, 1.5), [1.5, 2), [2, 3), [3, 4), [4, 6), [6, inf)
+// The network is asked only for |x_in| <= kEscXMax (gas frame).  Beyond it the
+// mean count is a steep mixture of photons that leave at once and photons
+// redistributed into the core; a wing photon takes plain scatterings until it
+// is back in the core, which costs little (about 0.5% of the scatterings in a
+// thick cell have |x| > 2).  Records draw x_in over [-kRecXMax, kRecXMax].
+constexpr float kEscXMax = 2.0f;
+constexpr float kRecXMax = 3.0f;
+
+// |x_in| bins of 0.25 over [0, kEscXMax) (the last one also takes larger |x_in|)
 __device__ __forceinline__ int cal_bin(float lt, float xin) {
     const int bt = min(max((int)((lt - kCalLo) * kCalInvW), 0), kNCalT - 1);
-    const float ax = fabsf(xin);
-    const int bx = (ax < 2.0f) ? min((int)(ax * 2.0f), 3) : (ax < 4.0f ? 3 + (int)(ax - 1.0f) : (ax < 6.0f ? 6 : 7));
+    const int bx = min((int)(fabsf(xin) * (kNCalX / kEscXMax)), kNCalX - 1);
     return bt * kNCalX + bx;
 }
 
@@ -85,6 +97,16 @@ constexpr int kMlpFwdBytes = kTilesFwd * kTileBytes + kBiasFloats * 4 + kNNorm *
 constexpr int kMlpBlobBytes = kTilesAll * kTileBytes + kBiasFloats * 4 + kNNorm * 4;
 static_assert(kMlpIn <= 8 && kMlpOut <= 16, "inputs fill two lane groups, outputs one 16-row tile");
 static_assert(kMlpFwdBytes % 16 == 0, "the inference image is staged into LDS in 16-byte words");
+
+// Network input of a quantile level u: logit(u) / 4 with u clamped to the
+// trained levels [1e-4, 1 - 1e-4]: beyond them the network would extrapolate
+// the quantile function (far too far into the wing), so the outermost 2e-4 of
+// the draws take the 1e-4 and 1 - 1e-4 quantiles
+constexpr float kLevelMin = 1e-4f;
+__device__ __forceinline__ float level_in(float u) {
+    u = fminf(fmaxf(u, kLevelMin), 1.0f - kLevelMin);
+    return 0.25f * (__logf(u) - __logf(1.0f - u));
+}
 
 typedef short v4i16 __attribute__((ext_vector_type(4)));
 typedef float v4f32 __attribute__((ext_vector_type(4)));

@@ -476,9 +476,9 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
                 in[0] = (lt - 3.5f) * (1.0f / 1.5f);
                 in[1] = P.esc_log10a + 3.0f;
                 in[2] = xc * 0.25f;
-                in[3] = 2.0f * u01(C.x) - 1.0f;
-                in[4] = 2.0f * u01(C.y) - 1.0f;
-                in[5] = 2.0f * u01(D.y) - 1.0f;
+                in[3] = level_in(u01(C.x));
+                in[4] = level_in(u01(C.y));
+                in[5] = level_in(u01(D.y));
                 in[6] = 0.0f;
                 in[7] = 0.0f;
                 mlp_eval_wave(mimg, mbias, in, lane, wm, mo);
@@ -490,23 +490,23 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
                 if (bits & 0x100u) { float tmp = ss; ss = tt; tt = tmp; }
                 if (bits & 0x200u) ss = -ss;
                 if (bits & 0x400u) tt = -tt;
-                // conditional evaluation: exit direction given the exit point's
-                // distance from the face centre (mu at u_a, alpha at u_b)
+                // exit frequency: side from the learned P(x_out >= 0) and a word of
+                // purpose 3, magnitude from that side's quantile at level u_a
+                const bool pos = u01(D.x) < sigmoid_f(mo[kOutLogit]);
+                const int ko = pos ? kOutXPos : kOutXNeg;
+                const float mag = fmaxf(mo[ko] * mnorm[kMlpOut + ko] + mnorm[ko], 0.0f);
+                const float xo = pos ? mag : -mag;
+                // conditional evaluation: exit direction given the exit frequency and
+                // the exit point's distance from the face centre (mu at u_a, alpha at u_b)
                 const float rr = f_sqrt(ss * ss + tt * tt);
-                in[3] = 2.0f * u01(D.z) - 1.0f;
-                in[4] = 2.0f * u01(C.w) - 1.0f;
-                in[5] = 0.0f;
+                in[3] = level_in(u01(D.z));
+                in[4] = level_in(u01(C.w));
+                in[5] = 0.25f * xo;
                 in[6] = 1.41421356f * rr - 1.0f;
                 in[7] = 1.0f;
                 mlp_eval_wave(mimg, mbias, in, lane, wm, mo2);
                 if (mlp) {
                     // ---- exit from the cube centred here (half-width Rcube) ----
-                    // exit frequency: side from the learned P(x_out >= 0) and a word of
-                    // purpose 3, magnitude from that side's quantile at level u_a
-                    const bool pos = u01(D.x) < sigmoid_f(mo[kOutLogit]);
-                    const int ko = pos ? kOutXPos : kOutXNeg;
-                    const float mag = fmaxf(mo[ko] * mnorm[kMlpOut + ko] + mnorm[ko], 0.0f);
-                    float xo = pos ? mag : -mag;
                     float lns = mo[kOutLogN] * mnorm[kMlpOut + kOutLogN] + mnorm[kOutLogN] +
                                 mnorm[2 * kMlpOut + cal_bin(lt, xc)];
                     float lx2 = mo[kOutLogX2] * mnorm[kMlpOut + kOutLogX2] + mnorm[kOutLogX2];

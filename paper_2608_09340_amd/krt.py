@@ -241,7 +241,8 @@ class Context:
         self._check(self.L.krt_escape_put_weights(self.h, _ptr(w), w.numel()))
 
     def krt_escape_forward(self, inp, out):
-        """inp: [n][8] raw (log10 tau_R, log10 a, x_in, u_a, u_b, u_c, r, flag); out: [n][10]."""
+        """inp: [n][8] raw (log10 tau_R, log10 a, x_in, u_a, u_b, u_c or (flag 1) x_out, r, flag);
+        out: [n][10]."""
         if inp.dim() != 2 or inp.shape[1] != ESC_NIN or tuple(out.shape) != (inp.shape[0], ESC_NOUT):
             raise ValueError(f"inp must be [n][{ESC_NIN}] and out [n][{ESC_NOUT}]")
         self._check(self.L.krt_escape_forward(self.h, _ptr(inp), inp.shape[0], _ptr(out)))

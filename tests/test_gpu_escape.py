@@ -103,7 +103,7 @@ def test_mfma_gradient_vs_fp64(gpu_ctx):
                             torch.from_numpy(idx).cuda(), torch.from_numpy(u.astype(np.float32)).cuda(), grad, loss)
     g = grad.cpu().numpy().astype(np.float64)
     R = rec[idx].astype(np.float32).astype(np.float64)
-    X = mlp.inputs(R[:, 0], R[:, 1], R[:, 2], ua, ub, uc, np.hypot(R[:, 4], R[:, 5]), cond)
+    X = mlp.inputs(R[:, 0], R[:, 1], R[:, 2], ua, ub, np.where(cond, R[:, 3], uc), np.hypot(R[:, 4], R[:, 5]), cond)
     Y = mlp.targets_normalised(R, norm, cond)
     U = mlp.levels(ua, ub, uc, cond)
     for bf in (True, False):
@@ -163,17 +163,19 @@ def trained(gpu_ctx):
 
 
 def test_training_reduces_loss(trained):
-    """The pinball loss falls well below its value at initialisation and keeps
-    falling after the first hundred steps (later stages lower it further)."""
+    """The loss falls well below its value at initialisation and keeps falling
+    after the first hundred steps (later stages lower it further).  The
+    quantile outputs' pinball losses do not fall to zero: even the true
+    quantiles leave the spread of the escapes about them."""
     h = trained["hist"]
     assert np.all(np.isfinite(h))
     early, mid, late = h[:5].mean(), h[50:100].mean(), h[-200:].mean()
-    assert late < 0.6 * early and late < mid, (early, mid, late)
+    assert late < 0.8 * early and late < mid < early, (early, mid, late)
 
 
 def test_calibration_unbiased_per_bin(gpu_ctx, trained):
     """After krt_escape_calibrate, the forward pass's calibrated E[N_s] summed
-    over the records of each (log10 tau_R, |x_in|) bin equals the records' sum of N_s
+    over the records (|x_in| <= 2) of each (log10 tau_R, |x_in|) bin equals the records' sum of N_s
     (the calibration's defining property; FP32 outputs, so within 1e-3)."""
     import torch
     rec = trained["rec"][:2_000_000]
@@ -187,9 +189,9 @@ def test_calibration_unbiased_per_bin(gpu_ctx, trained):
     gpu_ctx.krt_escape_forward(inp.contiguous(), out)
     pred = np.exp(out[:, mlp.O_LOGN].cpu().numpy().astype(np.float64))
     ax = np.abs(r[:, 2])
-    bx = np.where(ax < 2.0, np.minimum((ax * 2.0).astype(int), 3),
-                  np.where(ax < 4.0, 3 + (ax - 1.0).astype(int), np.where(ax < 6.0, 6, 7)))
+    bx = np.minimum((ax * 4.0).astype(int), 7)  # 0.25-wide |x_in| bins over [0, 2]
     b = np.clip(((r[:, 0] - 1.0) * 8.0).astype(int), 0, 31) * 8 + bx
+    b[ax > 2.0] = -1  # the network is asked only for |x_in| <= 2
     for k in range(256):
         m = b == k
         if m.sum() < 1000:
@@ -208,7 +210,8 @@ def test_learned_samples_vs_plain(gpu_ctx, trained, tau, xin):
     escapes: KS distance of exit frequency, exit point, exit cosine and the
     direction's alignment angle below 0.04; the mean alignment angle per band of
     exit-point radius within 0.08 of the plain one (the correlation of
-    direction and exit point); exit-frequency histogram L1 below 0.13
+    direction and exit point) and the rank correlation of exit cosine and
+    |x_out| within 0.05 of the plain one; exit-frequency histogram L1 below 0.13
     (0.25-wide bins); ln E[N_s] within 0.08."""
     import torch
     from paper_2608_09340_amd import krt
@@ -225,15 +228,15 @@ def test_learned_samples_vs_plain(gpu_ctx, trained, tau, xin):
     m = pred.cpu().numpy().astype(np.float64)
     s_l, t_l = np.clip(m[:, mlp.O_S], -1, 1), np.clip(m[:, mlp.O_T], -1, 1)
     r_l = np.hypot(s_l, t_l)
+    # exit frequency from the mixture head: side, then that side's quantile
+    pos = rng.uniform(0, 1, n) < 1.0 / (1.0 + np.exp(-m[:, mlp.O_LOGIT]))
+    xo = np.where(pos, np.maximum(m[:, mlp.O_XPOS], 0.0), -np.maximum(m[:, mlp.O_XNEG], 0.0))
     raw2 = np.stack([np.full(n, lt), np.full(n, -3.0), np.full(n, xin), rng.uniform(0, 1, n), rng.uniform(0, 1, n),
-                     np.zeros(n), r_l, np.ones(n)], 1)
+                     xo, r_l, np.ones(n)], 1)
     gpu_ctx.krt_escape_forward(torch.from_numpy(raw2.astype(np.float32)).cuda(), pred)
     m2 = pred.cpu().numpy().astype(np.float64)
     mu_l = np.clip(m2[:, mlp.O_MU], 1e-3, 1.0)
     al_l = np.clip(m2[:, mlp.O_ALPHA], 0.0, np.pi)
-    # exit frequency from the mixture head: side, then that side's quantile
-    pos = rng.uniform(0, 1, n) < 1.0 / (1.0 + np.exp(-m[:, mlp.O_LOGIT]))
-    xo = np.where(pos, np.maximum(m[:, mlp.O_XPOS], 0.0), -np.maximum(m[:, mlp.O_XNEG], 0.0))
     ks = {"x_out": stats.ks_2samp(xo, plain[:, 3]).statistic, "s": stats.ks_2samp(s_l, plain[:, 4]).statistic,
           "t": stats.ks_2samp(t_l, plain[:, 5]).statistic, "mu": stats.ks_2samp(mu_l, plain[:, 6]).statistic,
           "alpha": stats.ks_2samp(al_l, plain[:, 10]).statistic}
@@ -242,13 +245,18 @@ def test_learned_samples_vs_plain(gpu_ctx, trained, tau, xin):
     hp = np.histogram(plain[:, 3], edges)[0]
     hm = np.histogram(xo, edges)[0]
     l1 = np.abs(hp / n - hm / n).sum()
+    # exit cosine against |x_out| (wing photons leave closer to the normal)
+    rho_l = stats.spearmanr(np.abs(xo), mu_l).statistic
+    rho_p = stats.spearmanr(np.abs(plain[:, 3]), plain[:, 6]).statistic
     r_p = np.hypot(plain[:, 4], plain[:, 5])
     bands = [(0.0, 0.4), (0.4, 0.8), (0.8, 1.5)]
     al_band = [(al_l[(r_l >= lo) & (r_l < hi)].mean(), plain[(r_p >= lo) & (r_p < hi), 10].mean()) for lo, hi in bands]
     print(f"tau={tau} x_in={xin} KS " + " ".join(f"{k} {v:.4f}" for k, v in ks.items()) +
           f" x_out L1 {l1:.4f} P(x>=0) learned {pos.mean():.3f} plain {(plain[:, 3] >= 0).mean():.3f}"
-          f" mean alpha by r band (learned, plain) " + " ".join(f"({a:.3f}, {b:.3f})" for a, b in al_band))
+          f" mean alpha by r band (learned, plain) " + " ".join(f"({a:.3f}, {b:.3f})" for a, b in al_band) +
+          f" rank corr(|x_out|, mu) learned {rho_l:.3f} plain {rho_p:.3f}")
     assert max(ks.values()) < 0.04, (tau, xin, ks)
+    assert abs(rho_l - rho_p) < 0.05, (rho_l, rho_p)
     for a_l, a_p in al_band:
         assert abs(a_l - a_p) < 0.08, al_band
     # density level: two plain samples of this size differ by L1 ~ 0.04 in these bins

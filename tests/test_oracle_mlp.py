@@ -100,9 +100,12 @@ def test_levels_and_inputs_by_row_kind():
     assert U[0, mlp.O_XPOS] == U[0, mlp.O_XNEG] == U[0, mlp.O_LOGX2] == 0.1
     assert U[0, mlp.O_S] == 0.3 and U[0, mlp.O_T] == 0.5 and np.isnan(U[0, mlp.O_MU])
     assert U[1, mlp.O_MU] == 0.2 and U[1, mlp.O_ALPHA] == 0.4 and np.isnan(U[1, mlp.O_S])
-    X = mlp.inputs([3.5, 3.5], [-3, -3], [4, 4], [0.5, 0.5], [1.0, 1.0], [0.0, 0.9], [0.3, np.sqrt(2)], cond)
+    e = 1.0 / (1.0 + np.exp(-4.0))  # level whose encoding is 1
+    X = mlp.inputs([3.5, 3.5], [-3, -3], [4, 4], [0.5, 0.5], [e, e], [1 - e, -2.0], [0.3, np.sqrt(2)], cond)
     assert np.allclose(X[0], [0, 0, 1, 0, 1, -1, 0, 0])
-    assert np.allclose(X[1], [0, 0, 1, 0, 1, 0, 1, 1])
+    assert np.allclose(X[1], [0, 0, 1, 0, 1, -0.5, 1, 1])
+    # extreme levels stay distinct: 0.999 and 0.9999 differ by about 0.58
+    assert mlp.level_in(0.9999) - mlp.level_in(0.999) > 0.5
 
 
 def test_bf16_rounding():
