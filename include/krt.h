@@ -185,19 +185,23 @@ int krt_mc_run(krt_ctx *ctx, uint64_t n_packets, uint64_t seed, const krt_run_op
 
 /* -------------------------------------------------------------- imaging --- */
 /* Deterministic ray-tracing imaging pass (Sec. 2.2.2, eq. imaging-formal,
- * eq. imaging-alphas without absorption): along lines of sight parallel to a
+ * eq. imaging-alphas): along lines of sight parallel to a
  * grid axis toward the camera, for every channel k and from the far side of
  * the grid to the camera, cell by cell
  *   I <- I exp(-dtau_k) + (j_k / alpha_k + S_emis,k) (1 - exp(-dtau_k)),
- *   alpha_k = k0 H(a, x_k - n_cam.v), dtau_k = alpha_k dl,
+ *   alpha_k = k0 H(a, x_k - n_cam.v) + kappa_abs, dtau_k = alpha_k dl,
  * x_k the lab-frame centre of channel k over [ch_lo, ch_hi), k0 and v the
- * uploaded grid fields of `line`, H from that line's tables, dl the cell width
+ * uploaded grid fields of `line`, kappa_abs an optional grey (channel-
+ * independent) absorption coefficient per cell, e.g. dust, in the units of k0
+ * (the Monte Carlo pass samples scattering only and the absorption enters
+ * here: the paper's two-step scheme), H from that line's tables, dl the cell width
  * along the axis.  The scattering term is evaluated as j_k dl (1 - e^-dtau)/dtau,
  * finite as dtau -> 0.  j is the emissivity krt_mc_run finalised toward the
  * same camera (n_cam = the axis).  Pixels are the cells of the plane normal to
  * the axis, the lower remaining axis fastest: axis x -> pixel k*ny + j,
  * y -> k*nx + i, z -> j*nx + i.  Device arrays, caller-owned:
- *   emis_dev [ncell][nch], src_dev [ncell][nch] or NULL, image_dev [npix][nch].
+ *   emis_dev [ncell][nch], src_dev [ncell][nch] or NULL, kabs_dev [ncell] or
+ *   NULL (no absorption), image_dev [npix][nch].
  * Errors: KRT_EINVAL (axis, nch outside 1..256, empty range, NULL arrays),
  * KRT_ESTATE (no grid, no tables or opacity slice for the line). */
 typedef struct {
@@ -208,6 +212,7 @@ typedef struct {
     const float *emis_dev;
     const float *src_dev;
     float *image_dev;
+    const float *kabs_dev;     /* absorption coefficient per cell (units of k0), or NULL */
 } krt_image_desc;
 int krt_image(krt_ctx *ctx, const krt_image_desc *desc);
 /* Duration in ms of the last krt_image kernel (HIP events on the library stream). */

@@ -5,11 +5,13 @@ camera on one of the six grid axes (Sec. 2.2.2, eq. imaging-formal and
 eq. imaging-alphas), cell by cell from the far side of the grid to the camera:
 
     I_out,k = I_in,k exp(-dtau_k) + S_k (1 - exp(-dtau_k)),
-    dtau_k  = alpha_k dl,  alpha_k = k0 H(a, x_k),  S_k = j_k / alpha_k + S_emis,k,
+    dtau_k  = alpha_k dl,  alpha_k = k0 H(a, x_k) + kappa_abs,  S_k = j_k / alpha_k + S_emis,k,
 
 with x_k the centre of channel k (lab frame) moved to the cell's gas frame,
 x_k - n_cam . v (the sign convention of the transport), dl the cell width
-along the ray and no absorption.  For alpha_k dl -> 0 the scattering term is
+along the ray and kappa_abs an optional grey absorption coefficient per cell
+(the Monte Carlo pass scatters only; absorption enters here).  For
+alpha_k dl -> 0 the scattering term is
 j_k dl (the limit of j (1 - e^{-dtau}) / alpha).  H(a, x) is the oracle's
 Faddeeva-based Voigt function.  Pixels are the grid cells of the plane
 normal to the axis, ordered with the lower remaining axis fastest; the output
@@ -24,16 +26,18 @@ from . import voigt_H
 AXES = {0: (0, 1), 1: (1, 1), 2: (2, 1), 3: (0, -1), 4: (1, -1), 5: (2, -1)}
 
 
-def image(n, lo, hi, k0, vel, a, emis, ch_lo, ch_hi, axis, src=None):
+def image(n, lo, hi, k0, vel, a, emis, ch_lo, ch_hi, axis, src=None, kabs=None):
     """n[3], lo[3], hi[3]; k0 [ncell]; vel [3][ncell] or None; emis [ncell][nch];
     axis 0..5 = +x, +y, +z, -x, -y, -z (the camera direction); src [ncell][nch]
-    emission source function or None.  Returns I [npix][nch] (FP64)."""
+    emission source function or None; kabs [ncell] absorption coefficient or
+    None.  Returns I [npix][nch] (FP64)."""
     n = [int(v) for v in n]
     nx, ny, nz = n
     nch = emis.shape[1]
     d, sgn = AXES[int(axis)]
     dl = (hi[d] - lo[d]) / n[d]
     k0 = np.asarray(k0, dtype=np.float64).reshape(nz, ny, nx)
+    ka = np.zeros((nz, ny, nx)) if kabs is None else np.asarray(kabs, dtype=np.float64).reshape(nz, ny, nx)
     E = np.asarray(emis, dtype=np.float64).reshape(nz, ny, nx, nch)
     S0 = None if src is None else np.asarray(src, dtype=np.float64).reshape(nz, ny, nx, nch)
     ncam = np.zeros(3)
@@ -51,6 +55,7 @@ def image(n, lo, hi, k0, vel, a, emis, ch_lo, ch_hi, axis, src=None):
     else:
         perm = (1, 2, 0)   # (y, x, z): pixels (j, i), i fastest
     k0p = np.transpose(k0, perm)
+    kap = np.transpose(ka, perm)
     vp = np.transpose(vdot, perm)
     Ep = np.transpose(E, perm + (3,))
     Sp = None if S0 is None else np.transpose(S0, perm + (3,))
@@ -60,7 +65,7 @@ def image(n, lo, hi, k0, vel, a, emis, ch_lo, ch_hi, axis, src=None):
     for s in order:  # from the far side toward the camera
         xg = xk[None, None, :] - vp[:, :, s][:, :, None]
         H = voigt_H(a, xg.reshape(-1)).reshape(xg.shape)
-        alpha = k0p[:, :, s][:, :, None] * H
+        alpha = k0p[:, :, s][:, :, None] * H + kap[:, :, s][:, :, None]
         dtau = alpha * dl
         att = np.exp(-dtau)
         # j (1 - e^{-dtau}) / alpha written as j dl (1 - e^{-dtau}) / dtau, finite at dtau -> 0

@@ -429,6 +429,7 @@ extern "C" int krt_image(krt_ctx *c, const krt_image_desc *d) {
     Q.vel_axis = g.vel_dev ? g.vel_dev + (int64_t)Q.d * c->ncell : nullptr;
     Q.emis = d->emis_dev;
     Q.srcf = d->src_dev;
+    Q.kabs = d->kabs_dev;
     Q.out = d->image_dev;
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, hipEventRecord(c->ev0, c->stream));

@@ -5,7 +5,8 @@
 //
 // Per cell and channel k, from the far side of the grid to the camera:
 //   I <- I exp(-dtau_k) + j_k dl (1 - exp(-dtau_k)) / dtau_k + S_emis,k (1 - exp(-dtau_k)),
-//   dtau_k = k0 H(a, x_k - n_cam.v) dl   (eq. imaging-alphas without absorption),
+//   dtau_k = (k0 H(a, x_k - n_cam.v) + kappa_abs) dl   (eq. imaging-alphas; kappa_abs
+//   an optional grey absorption, zero when absent),
 // with x_k the lab-frame centre of channel k.  One lane per (pixel, channel):
 // the lanes of a pixel read its cells' fields at one address (broadcast) and
 // the emissivity of consecutive channels from consecutive addresses, so the
@@ -45,16 +46,17 @@ __global__ void __launch_bounds__(256) image_kernel(ImageParams Q) {
     // the loads of kImgChunk cells are issued together, then the cells are
     // folded in order: the march is a dependent chain, its memory is not
     for (int t0 = 0; t0 < nl; t0 += kImgChunk) {
-        float k0v[kImgChunk], vv[kImgChunk], jv[kImgChunk], sv[kImgChunk];
+        float k0v[kImgChunk], vv[kImgChunk], jv[kImgChunk], sv[kImgChunk], av[kImgChunk];
 #pragma unroll
         for (int u = 0; u < kImgChunk; ++u) {
             const int t = t0 + u;
-            k0v[u] = 0.0f; vv[u] = 0.0f; jv[u] = 0.0f; sv[u] = 0.0f;
+            k0v[u] = 0.0f; vv[u] = 0.0f; jv[u] = 0.0f; sv[u] = 0.0f; av[u] = 0.0f;
             if (t < nl) {
                 const int s = (Q.sgn > 0) ? t : nl - 1 - t;  // far side first
                 const int64_t cell = cell0 + (int64_t)s * Q.stride;
                 k0v[u] = Q.k0[cell];
                 if (vd) vv[u] = vd[cell];
+                if (Q.kabs) av[u] = Q.kabs[cell];
                 jv[u] = Q.emis[cell * Q.nch + c];
                 if (Q.srcf) sv[u] = Q.srcf[cell * Q.nch + c];
             }
@@ -64,7 +66,7 @@ __global__ void __launch_bounds__(256) image_kernel(ImageParams Q) {
             if (t0 + u >= nl) break;
             const float xg = xk - Q.sgnf * vv[u];
             const float H = (k0v[u] > 0.0f) ? voigt_lds(TV, fabsf(xg)) : 0.0f;
-            const float dtau = k0v[u] * H * Q.dl;
+            const float dtau = fmaf(k0v[u], H, av[u]) * Q.dl;
             const float att = f_exp(-dtau);
             // (1 - e^{-dtau}) / dtau, with its series below 1e-3
             const float frac = (dtau < 1e-3f) ? 1.0f - dtau * (0.5f - dtau * (1.0f / 6.0f)) : (1.0f - att) * f_rcp(dtau);

@@ -39,6 +39,7 @@ struct ImageParams {
     const float *vel_axis;  // [ncell] velocity component along the camera axis, or null
     const float *emis;      // [ncell][nch]
     const float *srcf;      // [ncell][nch] or null
+    const float *kabs;      // [ncell] grey absorption coefficient, or null
     float *out;             // [npix][nch]
     int64_t npix, stride;
     int n[3];

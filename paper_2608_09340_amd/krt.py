@@ -62,7 +62,7 @@ class krt_levels_desc(C.Structure):
 class krt_image_desc(C.Structure):
     _fields_ = [("line", C.c_int32), ("axis", C.c_int32), ("nch", C.c_int32), ("ch_lo", C.c_double),
                 ("ch_hi", C.c_double), ("emis_dev", C.c_void_p), ("src_dev", C.c_void_p),
-                ("image_dev", C.c_void_p)]
+                ("image_dev", C.c_void_p), ("kabs_dev", C.c_void_p)]
 
 
 EXPORTS = ["krt_create", "krt_destroy", "krt_last_error", "krt_device_cus", "krt_last_transport_ms",
@@ -356,9 +356,11 @@ class Transport:
         t.jbar_dev = None if self.jbar is None else self.jbar.data_ptr()
         return t
 
-    def image(self, axis: int = 0, line: int = 0, src=None):
+    def image(self, axis: int = 0, line: int = 0, src=None, kabs=None):
         """Ray-traced image toward the camera axis from the emissivity of the last run
-        (its FP32 finalised form); returns a [npix][nch] device tensor."""
+        (its FP32 finalised form), with an optional emission source function
+        src [ncell][nch] and grey absorption coefficient kabs [ncell] (device
+        FP32); returns a [npix][nch] device tensor."""
         t = self.prob["tally"]
         nx, ny, nz = self.n
         npix = {0: ny * nz, 1: nx * nz, 2: nx * ny}[axis % 3]
@@ -368,6 +370,7 @@ class Transport:
         d.ch_lo, d.ch_hi = float(t["ch_lo"]), float(t["ch_hi"])
         d.emis_dev = self.emis.data_ptr()
         d.src_dev = None if src is None else src.data_ptr()
+        d.kabs_dev = None if kabs is None else kabs.data_ptr()
         d.image_dev = out.data_ptr()
         self.ctx.krt_image(d)
         return out

@@ -1,7 +1,9 @@
 """Ray-tracing imaging pass on the GPU (krt_image) against the FP64 oracle of
 the formal solution: ragged grids, every camera axis, moving media, optical
-depths from thin to thick, with and without an emission source function; and
-sampled columns of a full-size (64^3 x 32) image of a Monte Carlo emissivity."""
+depths from thin to thick, with and without an emission source function and
+a grey absorption; sampled columns of a full-size (64^3 x 32) image of a Monte
+Carlo emissivity; the thin moving slab's closed form and Neufeld's peak
+positions through the whole chain (transport, emissivity, image)."""
 from __future__ import annotations
 
 import numpy as np
@@ -21,8 +23,8 @@ def _grid_problem(n, k0, vel, a, nch, ch):
 
 
 @pytest.mark.parametrize("axis", [0, 1, 2, 3, 4, 5])
-@pytest.mark.parametrize("with_src", [False, True])
-def test_image_vs_oracle(gpu_ctx, axis, with_src):
+@pytest.mark.parametrize("with_src,with_abs", [(False, False), (True, False), (True, True)])
+def test_image_vs_oracle(gpu_ctx, axis, with_src, with_abs):
     import torch
     from paper_2608_09340_amd import krt
     n = (12, 9, 7)
@@ -35,17 +37,20 @@ def test_image_vs_oracle(gpu_ctx, axis, with_src):
     T = krt.Transport(_grid_problem(n, k0, vel, a, nch, ch), ctx=gpu_ctx)
     emis = rng.uniform(0, 1, (nc, nch)).astype(np.float32)
     src = rng.uniform(0, 0.5, (nc, nch)).astype(np.float32) if with_src else None
+    kabs = (10.0 ** rng.uniform(-2, 1.3, nc) / 0.1).astype(np.float32) if with_abs else None
     e_d = torch.from_numpy(emis).cuda()
     s_d = None if src is None else torch.from_numpy(src).cuda()
+    a_d = None if kabs is None else torch.from_numpy(kabs).cuda()
     npix = {0: n[1] * n[2], 1: n[0] * n[2], 2: n[0] * n[1]}[axis % 3]
     out = torch.zeros((npix, nch), dtype=torch.float32, device="cuda")
     d = krt.krt_image_desc()
     d.line, d.axis, d.nch, d.ch_lo, d.ch_hi = 0, axis, nch, ch[0], ch[1]
     d.emis_dev, d.src_dev, d.image_dev = e_d.data_ptr(), (None if s_d is None else s_d.data_ptr()), out.data_ptr()
+    d.kabs_dev = None if a_d is None else a_d.data_ptr()
     gpu_ctx.krt_image(d)
     g = out.cpu().numpy().astype(np.float64)
     ref = oimg.image(n, (0.0, 0.0, 0.0), (1.2, 0.9, 0.7), k0.astype(np.float32), vel.astype(np.float32), a,
-                     emis, ch[0], ch[1], axis, src=src)
+                     emis, ch[0], ch[1], axis, src=src, kabs=kabs)
     scale = np.abs(ref).max()
     assert np.max(np.abs(g - ref)) < 2e-5 * scale, np.max(np.abs(g - ref)) / scale
     assert np.allclose(g, ref, rtol=2e-4, atol=1e-6 * scale)
@@ -75,3 +80,73 @@ def test_image_full_size_sampled_columns(gpu_ctx):
     g = img[pix]
     scale = np.abs(ref).max()
     assert np.allclose(g, ref, rtol=2e-4, atol=1e-6 * scale), np.max(np.abs(g - ref)) / scale
+
+
+def test_thin_moving_slab_image_closed_form(gpu_ctx):
+    """Sec. 3.3 / eq. thin-slab through the imaging pass: the optically thin
+    slab moving at v_z = b, lit in its plane, imaged face-on (camera along +z,
+    g = 0).  The image summed over pixels (times pixel area and channel width,
+    in units of L / (4 pi N)) is the channel integral of the R_IIA kernel at
+    g = 0 shifted by the bulk motion, times the factor (1 - e^-dtau)/dtau of
+    the formal solution across the slab: shape within 0.4% in L1 and integral
+    within 2% of the number of first scatterings (the paper's tolerances)."""
+    from scipy.special import wofz
+    import quad_util as Q
+    from paper_2608_09340_amd import krt
+    a, tau, vz = 0.01, 0.01, 1.0
+    p = W.thin_moving_slab(tau=tau, a=a, vz=vz)
+    T = krt.Transport(p, ctx=gpu_ctx)
+    N = 200_000_000
+    r = T.run(N, seed=9)
+    assert r["rc"] == 0
+    img = T.image(axis=2).cpu().numpy().astype(np.float64)  # 4 pixels (x cells) x 32 channels
+    nb, lo, hi = 32, -5.0, 5.0
+    dx_ch = (hi - lo) / nb
+    pix_area = 0.5 * 2.0  # dx * dy of a pixel column (4 x 1 cells over [-1, 1]^2)
+    spec = img.sum(axis=0) * pix_area * dx_ch * 4.0 * np.pi * N  # scatterings toward the camera per channel
+    edges = np.array([np.float32(lo + (hi - lo) * k / nb) for k in range(nb + 1)], dtype=np.float64)
+    centres = lo + (np.arange(nb) + 0.5) * dx_ch
+    prob = Q.riia_channel_probs(0.0, a, 0.0, edges - vz)
+    # the formal solution across the slab (dl = 2, k0 = tau / 2 per unit length) at the channel centre
+    dtau = (tau / 2.0) * np.real(wofz(np.abs(centres - vz) + 1j * a)) * 2.0
+    att = -np.expm1(-dtau) / dtau
+    ref = prob * att
+    H0 = np.real(wofz(1j * a))
+    n_first = N * (1 - np.exp(-tau * H0))
+    shape, rshape = spec / spec.sum(), ref / ref.sum()
+    print(f"image thin slab: L1 {np.abs(shape - rshape).sum():.5f} integral {spec.sum() / (n_first * ref.sum() / prob.sum()):.4f}")
+    assert np.abs(shape - rshape).sum() < 0.004
+    assert abs(spec.sum() / (n_first * ref.sum() / prob.sum()) - 1) < 0.02
+
+
+@pytest.mark.parametrize("tau0", [1e4, 1e5])
+def test_slab_image_peaks_neufeld(gpu_ctx, tau0):
+    """Sec. 3.5 imaging of thick profiles: a static slab (|z| <= 1, periodic in
+    x and y, line-centre depth tau0 midplane to face, a = 0.01, plane source at
+    z = 0) imaged face-on; the image's blue and red peaks lie within 10% of the
+    +-1.066 (a tau0)^(1/3) of Neufeld's solution, and the image is symmetric."""
+    from paper_2608_09340_amd import krt
+    a = 0.01
+    xp = 1.066 * (a * tau0) ** (1.0 / 3.0)
+    nch, lim = 64, 3.0 * xp
+    p = W._problem((1, 1, 16), (-1.0, -1.0, -1.0), (1.0, 1.0, 1.0), (W.PERIODIC, W.PERIODIC, W.VACUUM),
+                   np.full(16, tau0), a,
+                   source={"kind": W.SRC_PLANE, "pos": (0.0, 0.0, 0.0), "profile": W.PROF_DELTA, "x0": 0.0},
+                   tally={"spec_nbins": 64, "spec_lo": -lim, "spec_hi": lim, "emis_nch": nch, "ch_lo": -lim,
+                          "ch_hi": lim, "n_cam": (0.0, 0.0, 1.0)})
+    T = krt.Transport(p, ctx=gpu_ctx)
+    r = T.run(100_000, seed=3)
+    assert r["rc"] == 0
+    img = T.image(axis=2).cpu().numpy().astype(np.float64)[0]
+    w = 2 * lim / nch
+    c = -lim + (np.arange(nch) + 0.5) * w
+
+    def peak(sl):
+        k = sl.start + int(np.argmax(img[sl]))
+        y0, y1, y2 = img[k - 1], img[k], img[k + 1]  # parabola through the maximum and its neighbours
+        return c[k] + 0.5 * w * (y0 - y2) / (y0 - 2 * y1 + y2)
+
+    blue, red = peak(slice(nch // 2, nch - 1)), peak(slice(1, nch // 2))
+    print(f"tau0 {tau0:g}: image peaks {red:.3f} {blue:.3f}, Neufeld +-{xp:.3f}")
+    assert abs(blue / xp - 1) < 0.10 and abs(-red / xp - 1) < 0.10
+    assert np.abs(img - img[::-1]).sum() / img.sum() < 0.05

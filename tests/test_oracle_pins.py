@@ -466,6 +466,26 @@ def test_imaging_uniform_column_closed_form():
         I = imaging.image(n, (0, 0, 0), (7.0, 1.0, 1.0), np.full(7, k0v), None, a, emis, -2.0, 2.0, axis)
         ref = S * (1 - np.exp(-alpha * 7.0))
         assert np.allclose(I[0], ref, rtol=1e-12)
+    # grey absorption kappa: total opacity alpha + kappa, source j / (alpha + kappa)
+    kap = 0.3
+    I = imaging.image(n, (0, 0, 0), (7.0, 1.0, 1.0), np.full(7, k0v), None, a, emis, -2.0, 2.0, 0,
+                      kabs=np.full(7, kap))
+    ref = S * alpha / (alpha + kap) * (1 - np.exp(-(alpha + kap) * 7.0))
+    assert np.allclose(I[0], ref, rtol=1e-12)
+
+
+def test_imaging_absorber_in_front_attenuates():
+    """Emission only in the far cell, a pure absorber (no line opacity, no
+    emission) in the other cells: the image is the far cell's output times
+    exp(-kappa L_front) exactly, in every channel."""
+    from oracle import imaging
+    n = (5, 1, 1)
+    emis = np.zeros((5, 6))
+    emis[0] = np.linspace(1.0, 2.0, 6)  # far side for the +x camera is cell 0
+    k0 = np.zeros(5)
+    kabs = np.array([0.0, 0.2, 0.5, 0.1, 0.7])
+    I = imaging.image(n, (0, 0, 0), (5.0, 1.0, 1.0), k0, None, 1e-2, emis, -1.0, 1.0, 0, kabs=kabs)
+    assert np.allclose(I[0], emis[0] * 1.0 * np.exp(-kabs[1:].sum()), rtol=1e-12)
 
 
 def test_imaging_order_and_velocity_shift():
