@@ -223,6 +223,30 @@ def expanding_sphere_leg(ctx, packets=10_000_000):
                                      "frac": nb / t_im / 8e12, "bytes_per_launch": nb}}}
 
 
+def profile_mode_leg(ctx, packets=10_000_000):
+    """The paper's opacity-profile modes as an A/B on the expanding sphere:
+    tables in LDS (production), the same tables read from global memory
+    (identical tallies; the cost of the table placement), and the analytic
+    blended profile (the exact redistribution with an inconsistent opacity:
+    its spectrum L1 against the tabulated profile)."""
+    import numpy as np
+    from paper_2608_09340_amd import krt, workloads as W
+    T = krt.Transport(W.expanding_sphere_c2(), ctx=ctx)
+    res, spec = {}, {}
+    for name, mode in (("lds_tables", 0), ("global_tables", 1), ("analytic_profile", 2)):
+        r = T.run(packets, seed=0, profile_mode=mode)
+        if r["rc"]:
+            raise RuntimeError(f"profile mode {mode} failed")
+        res[name] = {"kernel_ms": ctx.krt_last_transport_ms(), "scatterings": r["counters"]["scatterings"]}
+        spec[name] = r["spec_raw"].astype(np.float64)
+        log(f"profile mode {mode}: {res[name]['kernel_ms']:.0f} ms")
+    s0 = spec["lds_tables"]
+    res["global_tables"]["identical_spectrum"] = bool(np.array_equal(s0, spec["global_tables"]))
+    res["analytic_profile"]["spectrum_L1_vs_tables"] = float(np.abs(spec["analytic_profile"] - s0).sum() / s0.sum())
+    res["workload"] = f"expanding sphere 128^3 (as above), {packets} packets, seed 0"
+    return res
+
+
 def lambda_leg(ctx, n=128, packets=10_000_000):
     """One Lambda-iteration cycle on the 128^3 turbulent cloud with the 5-level
     rotor: transport of each of the 4 lines with the mean-intensity tally, then
@@ -352,6 +376,7 @@ def main():
     }
     if not args.no_extra:
         out["expanding_sphere"] = expanding_sphere_leg(ctx)
+        out["profile_modes"] = profile_mode_leg(ctx)
         out["lambda_iteration"] = lambda_leg(ctx)
     if not args.no_escape:
         out["learned_escape"] = learned_escape_leg(ctx)

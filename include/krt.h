@@ -147,6 +147,14 @@ typedef struct {
                                   this many live lanes lets its idle lanes precompute the live
                                   packets' random draws (0 = 32, negative = never); the tallies
                                   are the same either way */
+    int32_t profile_mode;      /* opacity profile of the flights (Sec. 2.3.1, the paper's profile
+                                  modes; plain walk only): 0 tables in LDS (production); 1 the
+                                  same tables read from global memory (identical tallies, an A/B
+                                  of the table placement); 2 analytic blend of the Doppler core
+                                  exp(-u^2) and the damping wing a / (sqrt(pi)(u^2 + a^2)) by
+                                  w = (1 + tanh(2|u| - 2 u0)) / 2, u0 where the two cross, with
+                                  the exact redistribution: a demonstration of why the profile
+                                  must match the sampler, not for production */
 } krt_run_opts;
 
 /* Caller-allocated DEVICE buffers.  Raw tallies are int64 fixed point, so their
@@ -334,6 +342,9 @@ int krt_debug_philox(krt_ctx *ctx, const uint32_t *ctr_dev, const uint32_t *key_
                      uint32_t *out_dev, int64_t n);
 int krt_debug_bins(krt_ctx *ctx, const float *x_dev, int64_t n, int32_t nb, double lo,
                    double hi, int32_t *out_dev);
+/* krt_debug_voigt_analytic: out[i] = the analytic profile of profile_mode 2 at
+ * x[i] for damping a (u0 from a as krt_mc_run computes it); device arrays. */
+int krt_debug_voigt_analytic(krt_ctx *ctx, double a, const float *x, int64_t n, float *out);
 int krt_debug_voigt(krt_ctx *ctx, int32_t line, const float *x_dev, int64_t n, float *out_dev);
 int krt_debug_upar(krt_ctx *ctx, int32_t line, float x, uint64_t seed, uint64_t packet,
                    uint32_t ev0, int64_t n, float *out_dev);

@@ -240,6 +240,20 @@ extern "C" int krt_tables_build(krt_ctx *c, const krt_line_desc *lines, int n_li
 }
 
 // ------------------------------------------------------------------ run ---
+// Crossing point u0 > 1 of the Doppler core exp(-u^2) and the damping wing
+// a / (sqrt(pi) (u^2 + a^2)) (the centre of the analytic profile's switch), by
+// bisection in FP64: core - wing is positive at u = 1 and negative at u = 10
+// for damping 0 < a < 1 (the range of lines this library tabulates).
+static double voigt_crossing(double a) {
+    auto f = [a](double u) { return std::exp(-u * u) - a / (std::sqrt(M_PI) * (u * u + a * a)); };
+    double lo = 1.0, hi = 10.0;
+    for (int k = 0; k < 200; ++k) {
+        const double m = 0.5 * (lo + hi);
+        (f(m) > 0.0 ? lo : hi) = m;
+    }
+    return 0.5 * (lo + hi);
+}
+
 extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const krt_run_opts *o,
                           krt_tallies *t) {
     if (!c) return KRT_EINVAL;
@@ -293,6 +307,8 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
     if (per_cu < 1 || per_cu > 64) return fail(c, KRT_EINVAL, "wg_per_cu %d invalid", per_cu);
     if (o->max_events > 0xFFFFFFFEull) return fail(c, KRT_EINVAL, "max_events too large");
     if (o->esc_evals != 0) return fail(c, KRT_EINVAL, "esc_evals is reserved (0)");
+    if (o->profile_mode < 0 || o->profile_mode > 2) return fail(c, KRT_EINVAL, "profile_mode %d", o->profile_mode);
+    if (o->profile_mode != 0 && esc) return fail(c, KRT_EINVAL, "profile_mode %d is for the plain walk", o->profile_mode);
 
     HIPCHK(c, hipSetDevice(c->device));
     const krt_grid_desc &g = c->grid;
@@ -369,6 +385,8 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
     P.esc_min_lanes = o->esc_min_lanes > 0 ? o->esc_min_lanes : 8;
     P.esc_tail_lanes = o->esc_tail_lanes > 0 ? o->esc_tail_lanes : 1;
     P.tail_lanes = o->tail_lanes == 0 ? 32 : (o->tail_lanes < 0 ? 0 : std::min(o->tail_lanes, 64));
+    P.profile_mode = o->profile_mode;
+    P.voigt_u0 = (float)voigt_crossing(c->lines[l].a);
     int grid = c->cus * per_cu;
     HIPCHK(c, hipEventRecord(c->ev0, c->stream));
     HIPCHK(c, launch_transport(P, grid, block, c->stream));
@@ -565,6 +583,15 @@ extern "C" int krt_debug_bins(krt_ctx *c, const float *x, int64_t n, int32_t nb,
     fill_edges(e.data(), nb, lo, hi);
     HIPCHK(c, hipMemcpyAsync(c->edges, e.data(), sizeof(float) * (nb + 1), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, launch_debug_bins(x, n, nb, c->edges, (float)(nb / (hi - lo)), out, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return KRT_OK;
+}
+
+extern "C" int krt_debug_voigt_analytic(krt_ctx *c, double a, const float *x, int64_t n, float *out) {
+    if (!c) return KRT_EINVAL;
+    if (!x || !out || n <= 0 || !(a > 0.0 && a < 1.0)) return fail(c, KRT_EINVAL, "bad voigt args");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_debug_voigt_analytic((float)a, (float)voigt_crossing(a), x, n, out, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return KRT_OK;
 }

@@ -82,6 +82,19 @@ __device__ __forceinline__ float voigt_lds(const float *T, float xa) {
     return G * w * w * (1.0f / 64.0f);
 }
 
+// Analytic approximation of H(a, u) that blends the Doppler core exp(-u^2) and
+// the damping wing a / (sqrt(pi) (u^2 + a^2)) with the switch
+// w = (1 + tanh(2|u| - 2 u0)) / 2 centred at the crossing point u0 of the two
+// asymptotes (Sec. 2.3.1, the third profile mode).  Accurate in the core and
+// the wing, rough between them: offered to show why the opacity profile must
+// be the one the redistribution sampler assumes, not for production runs.
+__device__ __forceinline__ float voigt_analytic(float a, float u0, float ua) {
+    const float core = f_exp(-ua * ua);
+    const float wing = a * kInvSqrtPiF * f_rcp(fmaf(ua, ua, a * a));
+    const float w = 0.5f * (1.0f + tanhf(2.0f * (ua - u0)));
+    return fmaf(w, wing - core, core);
+}
+
 // Atom parallel velocity for gas-frame frequency x (Sec. 2.1.1): piece by r1
 // against the cumulative piece probabilities, quantile by r2, bilinear in
 // (row of |x|, quantile node).

@@ -91,6 +91,10 @@ struct RunParams {
     int esc_tail_lanes;
     int tail_lanes;
     int emis_w32;  // emissivity contributions fit 32 bits (fraction bits <= 30)
+    // opacity profile of the flights: 0 LDS tables, 1 the same tables read from
+    // global memory, 2 analytic blend (voigt_analytic, crossing point voigt_u0)
+    int profile_mode;
+    float voigt_u0;
 };
 
 hipError_t launch_transport(const RunParams &P, int grid, int block, hipStream_t s);
@@ -102,6 +106,7 @@ hipError_t launch_debug_philox(const uint32_t *ctr, const uint32_t *key, uint32_
 hipError_t launch_debug_bins(const float *x, int64_t n, int nb, const float *edges, float inv_w, int32_t *out,
                              hipStream_t s);
 hipError_t launch_debug_voigt(const float *tab, const float *x, int64_t n, float *out, hipStream_t s);
+hipError_t launch_debug_voigt_analytic(float a, float u0, const float *x, int64_t n, float *out, hipStream_t s);
 hipError_t launch_debug_upar(const float *tab, float a, float thd, float x, uint32_t k0, uint32_t k1,
                              uint64_t packet, uint32_t ev0, int64_t n, float *out, hipStream_t s);
 hipError_t launch_escape_record(const float *tab, float a, float thd, uint32_t k0, uint32_t k1, uint64_t offset,

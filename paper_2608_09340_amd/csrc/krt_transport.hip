@@ -149,11 +149,15 @@ __device__ __forceinline__ void scatter_draws(uint4 B, bool dipole, SDraws &d) {
     d.sp = sin_rev(psi);
 }
 
-template <bool kEsc, int kMaxThreads>
+// kProf: 0 tables in LDS (production); 1 the same tables read from global
+// memory (the workgroup still stages them, so occupancy is unchanged and only
+// the memory space of the lookups differs); 2 analytic opacity profile in the
+// flights, tables for the redistribution.
+template <bool kEsc, int kMaxThreads, int kProf = 0>
 __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) {
     extern __shared__ float4 lds4[];
-    float *T = reinterpret_cast<float *>(lds4);
-    float *sedges = T + kTabFloats;                      // spectrum edges
+    const float *T = (kProf == 1) ? P.tab : reinterpret_cast<const float *>(lds4);
+    float *sedges = reinterpret_cast<float *>(lds4) + kTabFloats;  // spectrum edges
     float *cedges = sedges + (kMaxSpecBins + 1);         // channel edges
     {
         const float4 *src = reinterpret_cast<const float4 *>(P.tab);
@@ -199,7 +203,8 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
     // or destruction) or across one cell face (escape / periodic wrap / next cell)
     auto flight = [&](float ue, bool &scat, float &xc) {
         xc = x - (nx * vxc + ny * vyc + nz * vzc);
-        float H = (k0c > 0.0f) ? voigt_lds(T, fabsf(xc)) : 0.0f;
+        float H = (k0c > 0.0f) ? ((kProf == 2) ? voigt_analytic(a, P.voigt_u0, fabsf(xc)) : voigt_lds(T, fabsf(xc)))
+                               : 0.0f;
         float kap = k0c * H;
         float tx = (nx > 0.0f) ? (1.0f - fx) * P.dx[0] * f_rcp(nx) : ((nx < 0.0f) ? fx * P.dx[0] * f_rcp(-nx) : INFINITY);
         float ty = (ny > 0.0f) ? (1.0f - fy) * P.dx[1] * f_rcp(ny) : ((ny < 0.0f) ? fy * P.dx[1] * f_rcp(-ny) : INFINITY);
@@ -720,6 +725,12 @@ __global__ void debug_voigt_kernel(const float *tab, const float *x, int64_t n, 
     out[i] = voigt_lds(T, fabsf(x[i]));
 }
 
+__global__ void debug_voigt_analytic_kernel(float a, float u0, const float *x, int64_t n, float *out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = voigt_analytic(a, u0, fabsf(x[i]));
+}
+
 __global__ void debug_upar_kernel(const float *tab, float a, float thd, float x, uint32_t k0, uint32_t k1,
                                   uint64_t packet, uint32_t ev0, int64_t n, float *out) {
     extern __shared__ float4 lds4[];
@@ -738,20 +749,27 @@ hipError_t launch_transport(const RunParams &P, int grid, int block, hipStream_t
     const bool esc = P.mlp_img != nullptr;
     size_t lds = sizeof(float) * (kTabFloats + kEdgeFloats) + (esc ? (size_t)kMlpFwdBytes : 0);
     // the network variant in blocks of at most 512 lanes is compiled for 256
-    // VGPRs (no spills, 2 waves per SIMD); in larger blocks for 128 (4 waves)
-    const int variant = !esc ? 0 : (block <= 512 ? 2 : 1);
-    static bool attr_set[3] = {false, false, false};
-    const void *fns[3] = {reinterpret_cast<const void *>(mc_transport_kernel<false, 1024>),
+    // VGPRs (no spills, 2 waves per SIMD); in larger blocks for 128 (4 waves).
+    // Profile modes 1 and 2 exist for the plain walk only.
+    const int variant = esc ? (block <= 512 ? 2 : 1) : (P.profile_mode == 1 ? 3 : (P.profile_mode == 2 ? 4 : 0));
+    static bool attr_set[5] = {false, false, false, false, false};
+    const void *fns[5] = {reinterpret_cast<const void *>(mc_transport_kernel<false, 1024>),
                           reinterpret_cast<const void *>(mc_transport_kernel<true, 1024>),
-                          reinterpret_cast<const void *>(mc_transport_kernel<true, 512>)};
+                          reinterpret_cast<const void *>(mc_transport_kernel<true, 512>),
+                          reinterpret_cast<const void *>(mc_transport_kernel<false, 1024, 1>),
+                          reinterpret_cast<const void *>(mc_transport_kernel<false, 1024, 2>)};
     if (!attr_set[variant]) {
         hipError_t e = hipFuncSetAttribute(fns[variant], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_set[variant] = true;
     }
-    if (variant == 0) hipLaunchKernelGGL((mc_transport_kernel<false, 1024>), dim3(grid), dim3(block), lds, s, P);
-    else if (variant == 1) hipLaunchKernelGGL((mc_transport_kernel<true, 1024>), dim3(grid), dim3(block), lds, s, P);
-    else hipLaunchKernelGGL((mc_transport_kernel<true, 512>), dim3(grid), dim3(block), lds, s, P);
+    switch (variant) {
+        case 0: hipLaunchKernelGGL((mc_transport_kernel<false, 1024>), dim3(grid), dim3(block), lds, s, P); break;
+        case 1: hipLaunchKernelGGL((mc_transport_kernel<true, 1024>), dim3(grid), dim3(block), lds, s, P); break;
+        case 2: hipLaunchKernelGGL((mc_transport_kernel<true, 512>), dim3(grid), dim3(block), lds, s, P); break;
+        case 3: hipLaunchKernelGGL((mc_transport_kernel<false, 1024, 1>), dim3(grid), dim3(block), lds, s, P); break;
+        default: hipLaunchKernelGGL((mc_transport_kernel<false, 1024, 2>), dim3(grid), dim3(block), lds, s, P); break;
+    }
     return hipGetLastError();
 }
 
@@ -766,6 +784,13 @@ hipError_t launch_saturation_check(const int64_t *p, int64_t n, uint32_t *status
     if (n <= 0 || !p) return hipSuccess;
     int grid = (int)std::min<int64_t>((n + 255) / 256, 16384);
     hipLaunchKernelGGL(saturation_check_kernel, dim3(grid), dim3(256), 0, s, p, n, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_voigt_analytic(float a, float u0, const float *x, int64_t n, float *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(debug_voigt_analytic_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, u0, x, n,
+                       out);
     return hipGetLastError();
 }
 

@@ -42,7 +42,8 @@ class krt_run_opts(C.Structure):
                 ("emis_frac_bits", C.c_int32), ("jbar_frac_bits", C.c_int32),
                 ("norm_packets", C.c_uint64), ("luminosity", C.c_double),
                 ("esc_tau_min", C.c_double), ("esc_min_lanes", C.c_int32),
-                ("esc_tail_lanes", C.c_int32), ("esc_evals", C.c_int32), ("tail_lanes", C.c_int32)]
+                ("esc_tail_lanes", C.c_int32), ("esc_evals", C.c_int32), ("tail_lanes", C.c_int32),
+                ("profile_mode", C.c_int32)]
 
 
 class krt_tallies(C.Structure):
@@ -68,7 +69,7 @@ class krt_image_desc(C.Structure):
 EXPORTS = ["krt_create", "krt_destroy", "krt_last_error", "krt_device_cus", "krt_last_transport_ms",
            "krt_grid_upload",
            "krt_tables_build", "krt_mc_run", "krt_levels_update", "krt_debug_philox",
-           "krt_debug_bins", "krt_debug_voigt", "krt_debug_upar",
+           "krt_debug_bins", "krt_debug_voigt", "krt_debug_voigt_analytic", "krt_debug_upar",
            "krt_escape_init", "krt_escape_record", "krt_escape_fit_norm", "krt_escape_calibrate", "krt_escape_grad",
            "krt_escape_train", "krt_escape_get_weights", "krt_escape_put_weights", "krt_escape_forward",
            "krt_image", "krt_last_image_ms"]
@@ -103,6 +104,7 @@ def load(path: str = LIB_PATH):
     L.krt_debug_philox.argtypes = [p, p, p, p, i64]
     L.krt_debug_bins.argtypes = [p, p, i64, i32, C.c_double, C.c_double, p]
     L.krt_debug_voigt.argtypes = [p, i32, p, i64, p]
+    L.krt_debug_voigt_analytic.argtypes = [p, C.c_double, p, i64, p]
     L.krt_debug_upar.argtypes = [p, i32, C.c_float, u64, u64, u32, i64, p]
     L.krt_escape_init.argtypes = [p, u64]
     L.krt_escape_record.argtypes = [p, i32, u64, u64, u64, C.c_double, C.c_double, i32, C.c_double, p]
@@ -117,7 +119,7 @@ def load(path: str = LIB_PATH):
     L.krt_last_image_ms.argtypes = [p]
     L.krt_last_image_ms.restype = C.c_float
     for name in ["krt_grid_upload", "krt_tables_build", "krt_mc_run", "krt_levels_update",
-                 "krt_debug_philox", "krt_debug_bins", "krt_debug_voigt", "krt_debug_upar",
+                 "krt_debug_philox", "krt_debug_bins", "krt_debug_voigt", "krt_debug_voigt_analytic", "krt_debug_upar",
                  "krt_escape_init", "krt_escape_record", "krt_escape_fit_norm", "krt_escape_calibrate",
                  "krt_escape_grad",
                  "krt_escape_train", "krt_escape_get_weights", "krt_escape_put_weights",
@@ -259,6 +261,9 @@ class Context:
     def krt_debug_bins(self, x, nb, lo, hi, out):
         self._check(self.L.krt_debug_bins(self.h, _ptr(x), x.numel(), int(nb), float(lo), float(hi), _ptr(out)))
 
+    def krt_debug_voigt_analytic(self, a, x, out):
+        self._check(self.L.krt_debug_voigt_analytic(self.h, float(a), _ptr(x), x.numel(), _ptr(out)))
+
     def krt_debug_voigt(self, line, x, out):
         self._check(self.L.krt_debug_voigt(self.h, int(line), _ptr(x), x.numel(), _ptr(out)))
 
@@ -270,7 +275,7 @@ class Context:
 def make_opts(prob: dict, *, line=0, packet_offset=0, accumulate=False, max_events=0,
               wg_size=0, wg_per_cu=0, emis_frac_bits=0, jbar_frac_bits=0, norm_packets=0, escape_mode=0,
               luminosity=0.0, esc_tau_min=0.0, esc_min_lanes=0, esc_tail_lanes=0,
-              esc_evals=0, tail_lanes=0) -> krt_run_opts:
+              esc_evals=0, tail_lanes=0, profile_mode=0) -> krt_run_opts:
     """krt_run_opts from a workload problem dict (paper_2608_09340_amd.workloads)."""
     o = krt_run_opts()
     src, t = prob["source"], prob["tally"]
@@ -303,6 +308,7 @@ def make_opts(prob: dict, *, line=0, packet_offset=0, accumulate=False, max_even
     o.esc_min_lanes = int(esc_min_lanes)
     o.esc_tail_lanes = int(esc_tail_lanes)
     o.esc_evals = int(esc_evals)
+    o.profile_mode = int(profile_mode)
     o.tail_lanes = int(tail_lanes)
     return o
 
