@@ -126,8 +126,9 @@ typedef struct {
     uint64_t max_events;       /* per packet; 0 = unlimited (2^32 - 2) */
     int32_t escape_mode;       /* 0 = plain random walk; 1 = learned escape in thick cells (needs
                                   krt_escape_init/train or put_weights; a in [1e-4, 1e-2]; no jbar) */
-    int32_t wg_size;           /* launch geometry: threads per workgroup (0 = 1024 plain, 512
-                                  learned; the learned kernel has 256 VGPRs at <= 512, 128 above) */
+    int32_t wg_size;           /* launch geometry: threads per workgroup (0 = 1024 plain, 768
+                                  learned; the learned kernel is built for 256 VGPRs at <= 512
+                                  lanes, 168 at <= 768, 128 above) */
     int32_t wg_per_cu;         /* workgroups per CU (0 = 1) */
     int32_t emis_frac_bits;    /* fixed-point fraction bits F of the emissivity tally (0 = 20) */
     int32_t jbar_frac_bits;    /* fraction bits of the mean-intensity tally (0 = 36) */

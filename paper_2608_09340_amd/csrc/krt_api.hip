@@ -298,10 +298,10 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
         if (al < 1e-4 * (1 - 1e-9) || al > 1e-2 * (1 + 1e-9))
             return fail(c, KRT_EINVAL, "learned escape covers a in [1e-4, 1e-2] (line a = %g)", al);
     }
-    // default: one workgroup per CU holding the LDS tables, 16 waves (plain) or 8
-    // waves (learned: its kernel is compiled for 512-lane blocks, where the
-    // network's registers fit without spilling)
-    int block = o->wg_size ? o->wg_size : (esc ? 512 : 1024);
+    // default: one workgroup per CU holding the LDS tables, 16 waves (plain) or 12
+    // waves (learned: compiled for 768-lane blocks, 168 VGPRs and 3 waves per
+    // SIMD, the measured best between spilling at 4 waves and idling at 2)
+    int block = o->wg_size ? o->wg_size : (esc ? 768 : 1024);
     int per_cu = o->wg_per_cu ? o->wg_per_cu : 1;
     if (block < 64 || block > 1024 || block % 64) return fail(c, KRT_EINVAL, "wg_size %d invalid", block);
     if (per_cu < 1 || per_cu > 64) return fail(c, KRT_EINVAL, "wg_per_cu %d invalid", per_cu);

@@ -748,16 +748,19 @@ __global__ void debug_upar_kernel(const float *tab, float a, float thd, float x,
 hipError_t launch_transport(const RunParams &P, int grid, int block, hipStream_t s) {
     const bool esc = P.mlp_img != nullptr;
     size_t lds = sizeof(float) * (kTabFloats + kEdgeFloats) + (esc ? (size_t)kMlpFwdBytes : 0);
-    // the network variant in blocks of at most 512 lanes is compiled for 256
-    // VGPRs (no spills, 2 waves per SIMD); in larger blocks for 128 (4 waves).
+    // the network variant is compiled for the block size: up to 512 lanes 256
+    // VGPRs (no spills, 2 waves per SIMD), up to 768 lanes 168 VGPRs (a few
+    // spills, 3 waves; the default), above that 128 (4 waves, heavy spills).
     // Profile modes 1 and 2 exist for the plain walk only.
-    const int variant = esc ? (block <= 512 ? 2 : 1) : (P.profile_mode == 1 ? 3 : (P.profile_mode == 2 ? 4 : 0));
-    static bool attr_set[5] = {false, false, false, false, false};
-    const void *fns[5] = {reinterpret_cast<const void *>(mc_transport_kernel<false, 1024>),
+    const int variant = esc ? (block <= 512 ? 2 : (block <= 768 ? 5 : 1))
+                            : (P.profile_mode == 1 ? 3 : (P.profile_mode == 2 ? 4 : 0));
+    static bool attr_set[6] = {false, false, false, false, false, false};
+    const void *fns[6] = {reinterpret_cast<const void *>(mc_transport_kernel<false, 1024>),
                           reinterpret_cast<const void *>(mc_transport_kernel<true, 1024>),
                           reinterpret_cast<const void *>(mc_transport_kernel<true, 512>),
                           reinterpret_cast<const void *>(mc_transport_kernel<false, 1024, 1>),
-                          reinterpret_cast<const void *>(mc_transport_kernel<false, 1024, 2>)};
+                          reinterpret_cast<const void *>(mc_transport_kernel<false, 1024, 2>),
+                          reinterpret_cast<const void *>(mc_transport_kernel<true, 768>)};
     if (!attr_set[variant]) {
         hipError_t e = hipFuncSetAttribute(fns[variant], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -768,6 +771,7 @@ hipError_t launch_transport(const RunParams &P, int grid, int block, hipStream_t
         case 1: hipLaunchKernelGGL((mc_transport_kernel<true, 1024>), dim3(grid), dim3(block), lds, s, P); break;
         case 2: hipLaunchKernelGGL((mc_transport_kernel<true, 512>), dim3(grid), dim3(block), lds, s, P); break;
         case 3: hipLaunchKernelGGL((mc_transport_kernel<false, 1024, 1>), dim3(grid), dim3(block), lds, s, P); break;
+        case 5: hipLaunchKernelGGL((mc_transport_kernel<true, 768>), dim3(grid), dim3(block), lds, s, P); break;
         default: hipLaunchKernelGGL((mc_transport_kernel<false, 1024, 2>), dim3(grid), dim3(block), lds, s, P); break;
     }
     return hipGetLastError();
