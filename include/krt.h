@@ -284,8 +284,12 @@ int krt_levels_update(krt_ctx *ctx, const krt_levels_desc *desc,
  * log-deviance e^d - 1 - d (d = ln N_s - output) for output 4, logistic for
  * output 6; trained on single-cell escapes run by the plain transport
  * arithmetic, a quarter of the rows conditional.  Parameters: kNParams =
- * 35466 FP32 master values plus 276 constants: target normalisation mean[10],
- * scale[10], and 256 additive calibration terms of ln E[N_s], one per bin of
+ * 35466 FP32 master values plus 280 constants: target normalisation mean[10],
+ * scale[10], 256 additive calibration terms of ln E[N_s], then the range
+ * (min, max) of log10 a over the records the normalisation was fitted on and
+ * 2 floats of padding.  krt_mc_run refuses escape_mode 1 for a line whose
+ * log10 a lies outside that range by more than 0.01 (KRT_EINVAL): the network
+ * is not used at damping values it has not seen.  The calibration terms are one per bin of
  * (log10 tau_R in 32 bins of 0.125 over [1, 5], clamped; |x_in| in 8 bins with
  * width 0.25 over [0, 2), the last also taking larger |x_in|), index = tau bin * 8
  * + x bin.  Beyond |x_in| = 2 the mean count is a steep mixture of photons that
@@ -298,8 +302,8 @@ int krt_levels_update(krt_ctx *ctx, const krt_levels_desc *desc,
  *   in [lo, hi], x_in fixed (x_fixed = 1) or 1/2 N(0, 1/2) + 1/2 U[-3, 3];
  *   samples_dev [n][11] FP32: (log10 tau_R, log10 a, x_in, x_out, s, t, mu,
  *   ln N_s, ln <x^2>, valid, alpha).
- * krt_escape_fit_norm: target mean / scale from valid records; clears the
- *   calibration.
+ * krt_escape_fit_norm: target mean / scale and the log10 a range from valid
+ *   records; clears the calibration.
  * krt_escape_calibrate: per (log10 tau_R, |x_in|) bin with at least 100 valid records
  *   with |x_in| <= 2,
  *   the calibration term ln(sum N_s / sum exp(network ln E[N_s])) over the
@@ -311,7 +315,7 @@ int krt_levels_update(krt_ctx *ctx, const krt_levels_desc *desc,
  *   (may be NULL).
  * krt_escape_train: `steps` Adam steps (lr, betas 0.9/0.999) on random batches
  *   (Philox(seed)); loss_hist_dev [steps] or NULL.
- * krt_escape_get_weights / put_weights: [35466 + 276] FP32 device buffers.
+ * krt_escape_get_weights / put_weights: [35466 + 280] FP32 device buffers.
  * krt_escape_forward: in_dev [n][8] raw (log10 tau_R, log10 a, x_in, u_a, u_b,
  *   u_c or (flag 1) x_out, r, flag) -> out_dev [n][10] in physical units (output 6 as a logit,
  *   output 4 with its calibration term).

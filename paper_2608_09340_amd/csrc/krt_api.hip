@@ -39,6 +39,7 @@ struct krt_ctx {
     // learned escape: FP32 master parameters, Adam moments, gradient, packed BF16 image
     float *edges = nullptr;                    // [kEdgeFloats]: spectrum then channel edges
     bool mlp_ready = false;
+    float esc_la_lo = 1.0f, esc_la_hi = -1.0f;  // log10 a range the network was fitted on (empty: none)
     float *mlp_p = nullptr, *mlp_m = nullptr, *mlp_v = nullptr, *mlp_g = nullptr, *mlp_norm = nullptr;
     float *mlp_loss = nullptr, *mlp_u = nullptr;
     int32_t *mlp_idx = nullptr;
@@ -297,6 +298,11 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
         double al = c->lines[o->line].a;
         if (al < 1e-4 * (1 - 1e-9) || al > 1e-2 * (1 + 1e-9))
             return fail(c, KRT_EINVAL, "learned escape covers a in [1e-4, 1e-2] (line a = %g)", al);
+        // the network is used only at damping values it was fitted on (0.01 dex of slack)
+        const double la = std::log10(al);
+        if (la < c->esc_la_lo - 0.01 || la > c->esc_la_hi + 0.01)
+            return fail(c, KRT_EINVAL, "escape network fitted on log10 a in [%g, %g], line has %g", c->esc_la_lo,
+                        c->esc_la_hi, la);
     }
     // default: one workgroup per CU holding the LDS tables, 16 waves (plain) or 12
     // waves (learned: compiled for 768-lane blocks, 168 VGPRs and 3 waves per
@@ -658,6 +664,17 @@ int mlp_ensure_batch(krt_ctx *c, int batch) {
 
 static_assert(kNParams % 2 == 0, "parameter count is even (zeroed as int64 pairs)");
 
+// Host copy of the log10 a range stored in the normalisation block (after a
+// fit or a weight upload); synchronises the library stream.
+static int read_a_range(krt_ctx *c) {
+    float r[2];
+    HIPCHK(c, hipMemcpyAsync(r, c->mlp_norm + kNormARange, sizeof(r), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->esc_la_lo = r[0];
+    c->esc_la_hi = r[1];
+    return KRT_OK;
+}
+
 extern "C" int krt_escape_init(krt_ctx *c, uint64_t seed) {
     if (!c) return KRT_EINVAL;
     HIPCHK(c, hipSetDevice(c->device));
@@ -669,6 +686,10 @@ extern "C" int krt_escape_init(krt_ctx *c, uint64_t seed) {
     float norm[kNNorm];
     for (int k = 0; k < kNNorm; ++k) norm[k] = 0.0f;
     for (int k = 0; k < kMlpOut; ++k) norm[kMlpOut + k] = 1.0f;
+    norm[kNormARange] = 1.0f;  // empty range until krt_escape_fit_norm
+    norm[kNormARange + 1] = -1.0f;
+    c->esc_la_lo = 1.0f;
+    c->esc_la_hi = -1.0f;
     HIPCHK(c, hipMemcpyAsync(c->mlp_norm, norm, sizeof(norm), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, launch_mlp_pack(c->mlp_p, c->mlp_norm, c->mlp_blob, c->mlp_img, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -703,8 +724,7 @@ extern "C" int krt_escape_fit_norm(krt_ctx *c, const float *samples_dev, uint64_
     static_assert(kMlpOut % 2 == 0 && kNCal % 2 == 0, "calibration block is int64-aligned");
     HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(c->mlp_norm + 2 * kMlpOut), kNCal / 2, c->stream));
     HIPCHK(c, launch_mlp_pack(c->mlp_p, c->mlp_norm, c->mlp_blob, c->mlp_img, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    return KRT_OK;
+    return read_a_range(c);
 }
 
 extern "C" int krt_escape_calibrate(krt_ctx *c, const float *samples_dev, uint64_t n) {
@@ -783,9 +803,8 @@ extern "C" int krt_escape_put_weights(krt_ctx *c, const float *dev, uint64_t nfl
     HIPCHK(c, hipMemcpyAsync(c->mlp_p, dev, sizeof(float) * kNParams, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->mlp_norm, dev + kNParams, sizeof(float) * kNNorm, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, launch_mlp_pack(c->mlp_p, c->mlp_norm, c->mlp_blob, c->mlp_img, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
     c->mlp_ready = true;
-    return KRT_OK;
+    return read_a_range(c);
 }
 
 extern "C" int krt_escape_forward(krt_ctx *c, const float *in_dev, int64_t n, float *out_dev) {

@@ -466,11 +466,39 @@ __global__ void mlp_batch_kernel(int64_t n, uint32_t k0, uint32_t k1, uint32_t s
 // Normalisation of the targets: mean and standard deviation over the valid
 // records of each output's own target (the one-sided exit frequencies over the
 // records of their side; the side logit and the unused output keep mean 0,
-// scale 1), FP64 accumulation, one block of 256 threads per output.
+// scale 1), FP64 accumulation, one block of 256 threads per output; one more
+// block records the range of log10 a over the valid records.
 __global__ void mlp_norm_kernel(const float *rec, int64_t n, float *norm) {
     __shared__ double s0[256], s1[256], s2[256];
     const int k = blockIdx.x;
     double a = 0.0, b = 0.0, c = 0.0;
+    if (k == kMlpOut) {
+        // the range of log10 a over the valid records
+        float lo = 1e30f, hi = -1e30f;
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+            const float *r = rec + (int64_t)kRec * i;
+            if (r[kRecValid] < 0.5f) continue;
+            lo = fminf(lo, r[1]);
+            hi = fmaxf(hi, r[1]);
+        }
+        s1[threadIdx.x] = lo;
+        s2[threadIdx.x] = hi;
+        __syncthreads();
+        for (int st = 128; st >= 1; st >>= 1) {
+            if ((int)threadIdx.x < st) {
+                s1[threadIdx.x] = fmin(s1[threadIdx.x], s1[threadIdx.x + st]);
+                s2[threadIdx.x] = fmax(s2[threadIdx.x], s2[threadIdx.x + st]);
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            norm[kNormARange] = (float)s1[0];
+            norm[kNormARange + 1] = (float)s2[0];
+            norm[kNormARange + 2] = 0.0f;
+            norm[kNormARange + 3] = 0.0f;
+        }
+        return;
+    }
     const int col = target_col(k);
     if (col >= 0) {
         for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
@@ -651,7 +679,7 @@ hipError_t launch_mlp_calib(const unsigned char *blob, const float *rec, int64_t
 }
 
 hipError_t launch_mlp_norm(const float *rec, int64_t n, float *norm, hipStream_t s) {
-    hipLaunchKernelGGL(mlp_norm_kernel, dim3(kMlpOut), dim3(256), 0, s, rec, n, norm);
+    hipLaunchKernelGGL(mlp_norm_kernel, dim3(kMlpOut + 1), dim3(256), 0, s, rec, n, norm);
     return hipGetLastError();
 }
 

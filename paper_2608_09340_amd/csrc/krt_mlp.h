@@ -65,7 +65,10 @@ constexpr int kNParams = kPB4 + kMlpOut;                 // 35466
 // calibration of ln E[N_s]: an additive term per bin of (log10 tau_R, |x_in|)
 constexpr int kNCalT = 32, kNCalX = 8, kNCal = kNCalT * kNCalX;
 constexpr float kCalLo = 1.0f, kCalInvW = 8.0f;  // bins of 0.125 in log10 tau_R from 1 to 5
-constexpr int kNNorm = 2 * kMlpOut + kNCal;
+// then the range of log10 a of the training records (min, max; a network is
+// used only at damping values inside it) and two floats of padding
+constexpr int kNormARange = 2 * kMlpOut + kNCal;
+constexpr int kNNorm = 2 * kMlpOut + kNCal + 4;
 
 // The network is asked only for |x_in| <= kEscXMax (gas frame).  Beyond it the
 // mean count is a steep mixture of photons that leave at once and photons

@@ -18,17 +18,23 @@ DEFAULT_STAGES = ((6000, 4096, 2e-3), (6000, 8192, 1e-3), (6000, 16384, 5e-4), (
 
 
 def train_escape(ctx: "krt.Context", line: int = 0, n_records: int = 8_000_000, seed: int = 1,
-                 log10_tau=(2.0, 5.0), stages=DEFAULT_STAGES, record_offset: int = 0) -> dict:
+                 log10_tau=(2.0, 5.0), stages=DEFAULT_STAGES, record_offset: int = 0, lines=None) -> dict:
     """Record `n_records` escapes from cubes with log10 tau_R uniform in
-    `log10_tau` (line `line`, whose tables must be built), initialise the
-    network from `seed`, fit the normalisation, train, and calibrate the
-    predicted mean scattering count per log10 tau_R bin on the records.
-    Returns the record buffer and the per-step loss history (all stages,
-    concatenated)."""
+    `log10_tau` (line `line`, or split evenly over `lines` to cover several
+    damping values, whose tables must be built), initialise the network from
+    `seed`, fit the normalisation (and the log10 a range the network may then
+    be used on), train, and calibrate the predicted mean scattering count per
+    (log10 tau_R, |x_in|) bin on the records.  Returns the record buffer and
+    the per-step loss history (all stages, concatenated)."""
     import torch
     dev = torch.device("cuda", ctx.device)
+    lines = [line] if lines is None else [int(v) for v in lines]
     rec = torch.zeros((n_records, krt.ESC_NREC), dtype=torch.float32, device=dev)
-    ctx.krt_escape_record(line, n_records, seed, record_offset, log10_tau[0], log10_tau[1], rec)
+    bounds = np.linspace(0, n_records, len(lines) + 1).astype(np.int64)
+    for k, ln in enumerate(lines):
+        b0, b1 = int(bounds[k]), int(bounds[k + 1])
+        # disjoint packet ranges, so records of different lines are independent
+        ctx.krt_escape_record(ln, b1 - b0, seed, record_offset + b0, log10_tau[0], log10_tau[1], rec[b0:b1])
     ctx.krt_escape_init(seed)
     ctx.krt_escape_fit_norm(rec, n_records)
     hist = []

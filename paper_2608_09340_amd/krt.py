@@ -73,7 +73,7 @@ EXPORTS = ["krt_create", "krt_destroy", "krt_last_error", "krt_device_cus", "krt
            "krt_escape_init", "krt_escape_record", "krt_escape_fit_norm", "krt_escape_calibrate", "krt_escape_grad",
            "krt_escape_train", "krt_escape_get_weights", "krt_escape_put_weights", "krt_escape_forward",
            "krt_image", "krt_last_image_ms"]
-ESC_NPARAMS, ESC_NNORM, ESC_NIN, ESC_NOUT, ESC_NCAL, ESC_NREC = 35466, 276, 8, 10, 256, 11
+ESC_NPARAMS, ESC_NNORM, ESC_NIN, ESC_NOUT, ESC_NCAL, ESC_NREC = 35466, 280, 8, 10, 256, 11
 
 _lib = None
 

@@ -18,11 +18,12 @@ NP, NO = mlp.NPARAMS, mlp.NOUT
 
 
 NCAL = 256  # calibration terms of ln E[N_s] stored after the normalisation
+NTAIL = 4   # then the trained log10 a range and padding
 
 
 def _put(ctx, p, norm):
     import torch
-    w = torch.from_numpy(np.concatenate([p, norm, np.zeros(NCAL)]).astype(np.float32)).cuda()
+    w = torch.from_numpy(np.concatenate([p, norm, np.zeros(NCAL + NTAIL)]).astype(np.float32)).cuda()
     ctx.krt_escape_put_weights(w)
 
 
@@ -336,3 +337,21 @@ def test_chained_escapes_single_cell_count(gpu_ctx, trained, tau_min):
           f"(floor {l1_shape(pa['spec_raw'], pb['spec_raw']):.4f})")
     assert c["mlp_calls"] > N
     assert abs(em / ea - 1.0) < 0.012
+
+
+def test_escape_refused_outside_trained_damping(gpu_ctx, trained):
+    """The fixture's network was fitted on records at a = 1e-3 only: the
+    normalisation block carries that log10 a range, and a learned run on a line
+    with a = 1e-2 (inside the API's [1e-4, 1e-2] but never seen) is refused
+    instead of extrapolated; a = 1e-3 is accepted."""
+    import torch
+    from paper_2608_09340_amd import krt
+    w = torch.zeros(krt.ESC_NPARAMS + krt.ESC_NNORM, dtype=torch.float32, device="cuda")
+    gpu_ctx.krt_escape_get_weights(w)
+    lo, hi = w[krt.ESC_NPARAMS + 2 * NO + NCAL:krt.ESC_NPARAMS + 2 * NO + NCAL + 2].cpu().numpy()
+    assert abs(lo + 3.0) < 1e-5 and abs(hi + 3.0) < 1e-5, (lo, hi)
+    T = krt.Transport(W.cube(n=4, tau0=1e3, a=1e-2), ctx=gpu_ctx)
+    with pytest.raises(Exception, match="fitted on log10 a"):
+        T.run(1000, seed=0, escape_mode=1)
+    T3 = krt.Transport(W.cube(n=4, tau0=1e3, a=1e-3), ctx=gpu_ctx)
+    assert T3.run(1000, seed=0, escape_mode=1)["rc"] == 0
