@@ -218,6 +218,12 @@ def expanding_sphere_leg(ctx, packets=10_000_000):
                         f"source, spectrum 512 bins, emissivity 128^3 x 64 channels, {packets} packets",
             "kernel_ms": ms, "scatterings": c["scatterings"], "scatterings_per_s": c["scatterings"] / (ms * 1e-3),
             "packets_per_s": packets / (ms * 1e-3), "crossings": c["crossings"],
+            # the same VALU ledger as the headline (isotropic, emissivity tally): this
+            # workload has no long-packet tail, so it shows the transport's bulk rate
+            "roofline": {"bound": "alu", "achieved": c["scatterings"] * ledger_per_scatter(False, True) / (ms * 1e-3) / 1e12,
+                         "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
+                         "frac": c["scatterings"] * ledger_per_scatter(False, True) / (ms * 1e-3) / 1e12 / PEAK_VALU_TOPS,
+                         "ops_per_scattering": ledger_per_scatter(False, True)},
             "imaging": {"what": "image toward +x, 128x128 pixels x 64 channels", "kernel_ms": min(im),
                         "roofline": {"bound": "hbm", "achieved": nb / t_im / 1e9, "peak": 8000.0, "unit": "GB/s",
                                      "frac": nb / t_im / 8e12, "bytes_per_launch": nb}}}
