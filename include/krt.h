@@ -89,6 +89,17 @@ typedef struct {
     const float *vel_dev;      /* [3][ncell] bulk velocity / b (SoA), or NULL = static */
     const float *eps_dev;      /* [n_lines][ncell] destruction probability, or NULL = 0 */
     const float *emis_dev;     /* [n_lines][ncell] volume emission weights, or NULL */
+    /* Per-cell temperature as classes (frequencies are in units of the local
+     * Doppler width, Sec. 2.1): tclass_dev [ncell] class of each cell, or NULL
+     * (every cell at the reference width b_ref, the default).  Class k has
+     * Doppler width b_k = tclass_bratio[k] b_ref (0.05..20): in its cells the
+     * gas-frame frequency is (x - n.v) b_ref / b_k, the damping a b_ref / b_k
+     * and each class gets its own exact table set; velocities, spectra and
+     * channels stay in reference units, k0 is the cell's own line-centre
+     * opacity.  Plain walk with profile_mode 0 only. */
+    const uint8_t *tclass_dev;
+    int32_t n_tclass;          /* 1..8 when tclass_dev is set */
+    double tclass_bratio[8];
 } krt_grid_desc;
 int krt_grid_upload(krt_ctx *ctx, const krt_grid_desc *desc);
 

@@ -34,7 +34,7 @@ def build(force: bool = False) -> str:
 class OrcProblem(C.Structure):
     _fields_ = [
         ("n", C.c_int32 * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("bc", C.c_int32 * 3),
-        ("k0", C.c_void_p), ("vel", C.c_void_p), ("eps", C.c_void_p), ("emis", C.c_void_p),
+        ("k0", C.c_void_p), ("vel", C.c_void_p), ("eps", C.c_void_p), ("emis", C.c_void_p), ("bratio", C.c_void_p),
         ("a", C.c_double), ("phase", C.c_int32), ("source", C.c_int32), ("src_pos", C.c_double * 3),
         ("src_dir", C.c_double * 3),
         ("src_profile", C.c_int32), ("src_x0", C.c_double),
@@ -146,6 +146,14 @@ def mc_run(prob: dict, n_packets: int, seed: int = 0, packet_offset: int = 0,
     P.vel = None if vel is None else vel.ctypes.data
     P.eps = None if eps is None else eps.ctypes.data
     P.emis = None if emis is None else emis.ctypes.data
+    # per-cell Doppler width b_cell / b_ref: an explicit per-cell array, or
+    # temperature classes (class index per cell and the ratio of each class)
+    br = g.get("bratio")
+    if br is None and g.get("tclass") is not None:
+        br = np.asarray(g["tclass_bratio"], dtype=np.float32)[np.asarray(g["tclass"]).reshape(-1)]
+    br = None if br is None else np.ascontiguousarray(br, dtype=np.float32).reshape(-1)
+    assert br is None or br.size == ncell
+    P.bratio = None if br is None else br.ctypes.data
     ln = prob["line"]
     P.a = float(ln["a"])
     P.phase = int(ln.get("phase", 0))

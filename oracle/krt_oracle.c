@@ -296,7 +296,8 @@ typedef struct {
     const float *vel;          /* [3][ncell], may be NULL (static) */
     const float *eps;          /* [ncell], may be NULL */
     const float *emis;         /* [ncell] volume emission weights, may be NULL */
-    double a;
+    const float *bratio;       /* [ncell] Doppler width b_cell / b_ref, may be NULL (all 1) */
+    double a;                  /* damping at b_ref; a cell's is a b_ref / b_cell */
     int32_t phase;             /* 0 isotropic, 1 dipole */
     int32_t source;            /* 0 point, 1 plane z = src_pos[2], 2 volume, 3 beam */
     double src_pos[3];
@@ -383,6 +384,10 @@ static void run_packet(worker_t *W, uint64_t pid)
     int64_t cl = cell_lin(P, c);
     double vc[3] = { 0, 0, 0 };
     if (P->vel) for (int d = 0; d < 3; ++d) vc[d] = P->vel[(int64_t)d * ncell + cl];
+    /* per-cell temperature (Sec. 2.1: frequencies in units of the local Doppler
+     * width): s = b_ref / b_cell scales the gas-frame frequency and the damping */
+    double sc = P->bratio ? 1.0 / (double)P->bratio[cl] : 1.0;
+    double ac = P->a * sc;
 
     /* gas-frame emission frequency */
     double xg;
@@ -390,8 +395,9 @@ static void run_packet(worker_t *W, uint64_t pid)
     else {
         double rr = sqrt(-log(u01(w2[0]))), th = 2.0 * ORC_PI * u01(w2[1]);
         double gsn = rr * cos(th);           /* N(0, 1/2) */
-        if (P->src_profile == 1) xg = gsn + P->a * tan(ORC_PI * (u01(w2[2]) - 0.5)); /* Voigt = Gauss (*) Cauchy */
+        if (P->src_profile == 1) xg = gsn + ac * tan(ORC_PI * (u01(w2[2]) - 0.5)); /* Voigt = Gauss (*) Cauchy */
         else xg = gsn;
+        xg /= sc;  /* the profile is in the emitting cell's Doppler units */
     }
     double x = xg + n[0] * vc[0] + n[1] * vc[1] + n[2] * vc[2];
     W->cnt[C_EMITTED] += 1;
@@ -409,8 +415,8 @@ static void run_packet(worker_t *W, uint64_t pid)
         int escaped = 0;
         for (;;) {
             double k0 = P->k0[cl];
-            double xc = x - (n[0] * vc[0] + n[1] * vc[1] + n[2] * vc[2]);
-            double H = (k0 > 0.0) ? orc_voigt_H(P->a, xc) : 0.0;
+            double xc = (x - (n[0] * vc[0] + n[1] * vc[1] + n[2] * vc[2])) * sc;
+            double H = (k0 > 0.0) ? orc_voigt_H(ac, xc) : 0.0;
             double kap = k0 * H;
             /* distance to the cell boundary */
             double dmin = INFINITY; int ax = -1;
@@ -446,16 +452,18 @@ static void run_packet(worker_t *W, uint64_t pid)
             }
             cl = cell_lin(P, c);
             if (P->vel) for (int d = 0; d < 3; ++d) vc[d] = P->vel[(int64_t)d * ncell + cl];
+            sc = P->bratio ? 1.0 / (double)P->bratio[cl] : 1.0;
+            ac = P->a * sc;
         }
         if (escaped) { outcome = 1; break; }
-        /* ---- scattering ---- */
-        double xc = x - (n[0] * vc[0] + n[1] * vc[1] + n[2] * vc[2]);
+        /* ---- scattering (in the cell's Doppler units) ---- */
+        double xc = (x - (n[0] * vc[0] + n[1] * vc[1] + n[2] * vc[2])) * sc;
         if (P->eps) {
             double e = P->eps[cl];
             if (u01(A[1]) < e) { outcome = 2; break; }
         }
         int trials;
-        double upar = sample_upar(xc, P->a, &r, (uint32_t)ev, &trials);
+        double upar = sample_upar(xc, ac, &r, (uint32_t)ev, &trials);
         if (trials < 0) { W->cnt[C_STATUS] |= 4; outcome = 3; break; }
         W->cnt[C_TRIALS] += trials;
         /* perpendicular atom velocity: two N(0, 1/2) components (Box-Muller) */
@@ -478,7 +486,7 @@ static void run_packet(worker_t *W, uint64_t pid)
             double upc = up1 * (e1[0] * P->n_cam[0] + e1[1] * P->n_cam[1] + e1[2] * P->n_cam[2])
                        + up2 * (e2[0] * P->n_cam[0] + e2[1] * P->n_cam[1] + e2[2] * P->n_cam[2]);
             double xcam = xc + upar * (gc - 1.0) + upc;
-            double xcam_lab = xcam + (P->n_cam[0] * vc[0] + P->n_cam[1] * vc[1] + P->n_cam[2] * vc[2]);
+            double xcam_lab = xcam / sc + (P->n_cam[0] * vc[0] + P->n_cam[1] * vc[1] + P->n_cam[2] * vc[2]);
             int k = bin_index((float)xcam_lab, P->emis_nch, P->ch_lo, P->ch_hi);
             if (k >= 1 && k <= P->emis_nch) {
                 double wph = (P->phase == 1) ? 0.75 * (1.0 + gc * gc) : 1.0;
@@ -486,7 +494,7 @@ static void run_packet(worker_t *W, uint64_t pid)
             }
         }
         for (int d = 0; d < 3; ++d) n[d] = nout[d];
-        x = xo + (n[0] * vc[0] + n[1] * vc[1] + n[2] * vc[2]);
+        x = xo / sc + (n[0] * vc[0] + n[1] * vc[1] + n[2] * vc[2]);
         nscat += 1;
     }
     if (outcome == 0) { outcome = 3; W->cnt[C_STUCK] += 1; W->cnt[C_STATUS] |= 2; }

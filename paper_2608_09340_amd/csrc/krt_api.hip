@@ -2,6 +2,7 @@
 // device-side state, launches, and the per-cell statistical-equilibrium kernel.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -29,6 +30,12 @@ struct krt_ctx {
     std::vector<int *> alias_idx;
     // tables
     std::vector<float *> tab;
+    // temperature classes: table sets [class][kTabFloats] and per-class
+    // parameters for the line they were built for (cache key: line, ratios, a)
+    float *cls_tab = nullptr;
+    float4 *cls_par = nullptr;
+    int cls_line = -1;
+    double cls_key[9] = {0};
     std::vector<krt_line_desc> lines;
     // scratch
     unsigned long long *work_counter = nullptr;
@@ -81,6 +88,32 @@ void free_tables(krt_ctx *c) {
     for (auto p : c->tab) if (p) (void)hipFree(p);
     c->tab.clear();
     c->lines.clear();
+    c->cls_line = -1;  // class tables follow the line tables
+}
+
+// Table sets of the grid's temperature classes for line l (damping
+// a_l b_ref / b_k per class), rebuilt only when the line or the ratios change.
+static int ensure_class_tables(krt_ctx *c, int l) {
+    const krt_grid_desc &g = c->grid;
+    double key[9];
+    key[0] = c->lines[l].a;
+    for (int k = 0; k < 8; ++k) key[k + 1] = k < g.n_tclass ? g.tclass_bratio[k] : 0.0;
+    if (c->cls_line == l && std::equal(key, key + 9, c->cls_key)) return KRT_OK;
+    if (!c->cls_tab) HIPCHK(c, hipMalloc(&c->cls_tab, sizeof(float) * 8 * (size_t)kTabFloats));
+    if (!c->cls_par) HIPCHK(c, hipMalloc(&c->cls_par, sizeof(float4) * 8));
+    std::vector<float> tab;
+    float4 par[8];
+    for (int k = 0; k < g.n_tclass; ++k) {
+        const double s = 1.0 / g.tclass_bratio[k], ak = c->lines[l].a * s;
+        build_line_tables(ak, tab);
+        HIPCHK(c, hipMemcpy(c->cls_tab + (size_t)k * kTabFloats, tab.data(), sizeof(float) * kTabFloats,
+                            hipMemcpyHostToDevice));
+        par[k] = make_float4((float)s, (float)ak, (float)std::atan(kDelta / ak), (float)g.tclass_bratio[k]);
+    }
+    HIPCHK(c, hipMemcpy(c->cls_par, par, sizeof(float4) * g.n_tclass, hipMemcpyHostToDevice));
+    c->cls_line = l;
+    std::copy(key, key + 9, c->cls_key);
+    return KRT_OK;
 }
 
 // Walker/Vose alias table over non-negative weights (FP64 build).
@@ -150,6 +183,8 @@ extern "C" void krt_destroy(krt_ctx *c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream); else (void)hipDeviceSynchronize();
     free_grid(c);
     free_tables(c);
+    if (c->cls_tab) (void)hipFree(c->cls_tab);
+    if (c->cls_par) (void)hipFree(c->cls_par);
     if (c->work_counter) (void)hipFree(c->work_counter);
     if (c->level_consts) (void)hipFree(c->level_consts);
     if (c->host_pinned) (void)hipHostFree(c->host_pinned);
@@ -185,9 +220,16 @@ extern "C" int krt_grid_upload(krt_ctx *c, const krt_grid_desc *d) {
     if (ncell >= (1LL << 31)) return fail(c, KRT_EINVAL, "too many cells (%lld)", (long long)ncell);
     if (d->n_lines < 1 || d->n_lines > 8) return fail(c, KRT_EINVAL, "n_lines = %d outside 1..8", d->n_lines);
     if (!d->k0_dev) return fail(c, KRT_EINVAL, "k0 is NULL");
+    if (d->tclass_dev) {
+        if (d->n_tclass < 1 || d->n_tclass > 8) return fail(c, KRT_EINVAL, "n_tclass = %d outside 1..8", d->n_tclass);
+        for (int k = 0; k < d->n_tclass; ++k)
+            if (!(d->tclass_bratio[k] >= 0.05 && d->tclass_bratio[k] <= 20.0))
+                return fail(c, KRT_EINVAL, "tclass_bratio[%d] = %g outside [0.05, 20]", k, d->tclass_bratio[k]);
+    }
     HIPCHK(c, hipSetDevice(c->device));
     free_grid(c);
     c->grid = *d;
+    c->cls_line = -1;
     c->ncell = ncell;
     c->alias_prob.assign(d->n_lines, nullptr);
     c->alias_idx.assign(d->n_lines, nullptr);
@@ -315,6 +357,8 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
     if (o->esc_evals != 0) return fail(c, KRT_EINVAL, "esc_evals is reserved (0)");
     if (o->profile_mode < 0 || o->profile_mode > 2) return fail(c, KRT_EINVAL, "profile_mode %d", o->profile_mode);
     if (o->profile_mode != 0 && esc) return fail(c, KRT_EINVAL, "profile_mode %d is for the plain walk", o->profile_mode);
+    if (c->have_grid && c->grid.tclass_dev && (esc || o->profile_mode != 0))
+        return fail(c, KRT_EINVAL, "temperature classes need the plain walk with profile_mode 0");
 
     HIPCHK(c, hipSetDevice(c->device));
     const krt_grid_desc &g = c->grid;
@@ -392,6 +436,16 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
     P.esc_tail_lanes = o->esc_tail_lanes > 0 ? o->esc_tail_lanes : 1;
     P.tail_lanes = o->tail_lanes == 0 ? 32 : (o->tail_lanes < 0 ? 0 : std::min(o->tail_lanes, 64));
     P.profile_mode = o->profile_mode;
+    P.tclass = nullptr;
+    P.cls_par = nullptr;
+    P.cls_tab = nullptr;
+    if (c->grid.tclass_dev) {
+        int rc = ensure_class_tables(c, l);
+        if (rc) return rc;
+        P.tclass = c->grid.tclass_dev;
+        P.cls_par = c->cls_par;
+        P.cls_tab = c->cls_tab;
+    }
     P.voigt_u0 = (float)voigt_crossing(c->lines[l].a);
     int grid = c->cus * per_cu;
     HIPCHK(c, hipEventRecord(c->ev0, c->stream));

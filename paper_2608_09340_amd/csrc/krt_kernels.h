@@ -95,6 +95,12 @@ struct RunParams {
     // global memory, 2 analytic blend (voigt_analytic, crossing point voigt_u0)
     int profile_mode;
     float voigt_u0;
+    // per-cell temperature classes (null: every cell at the reference width):
+    // class per cell, per class (b_ref / b, damping, sampler threshold,
+    // b / b_ref), and the class table sets [class][kTabFloats] in global memory
+    const uint8_t *tclass;
+    const float4 *cls_par;
+    const float *cls_tab;
 };
 
 hipError_t launch_transport(const RunParams &P, int grid, int block, hipStream_t s);

@@ -152,7 +152,11 @@ __device__ __forceinline__ void scatter_draws(uint4 B, bool dipole, SDraws &d) {
 // kProf: 0 tables in LDS (production); 1 the same tables read from global
 // memory (the workgroup still stages them, so occupancy is unchanged and only
 // the memory space of the lookups differs); 2 analytic opacity profile in the
-// flights, tables for the redistribution.
+// flights, tables for the redistribution; 3 per-cell temperature classes: in a
+// cell of Doppler width b the gas-frame frequency is (x - n.v) b_ref / b, the
+// damping a b_ref / b, and the class's own tables (global memory) serve the
+// opacity and the redistribution; frequencies return to reference units on
+// leaving the cell's frame.
 template <bool kEsc, int kMaxThreads, int kProf = 0>
 __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) {
     extern __shared__ float4 lds4[];
@@ -180,6 +184,8 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
     const float a = P.a, thd = P.thd;
 
     // lane state
+    float sc = 1.0f, isc = 1.0f, ac = a, thdc = thd;  // cell temperature (kProf 3)
+    int toff = 0;
     bool have = false, done = false;
     uint64_t pid = 0;
     int ci = 0, cj = 0, ck = 0, cell = 0;
@@ -199,11 +205,24 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
     uint32_t *status = P.status;
     const float jscale = P.jbar_scale * kInvSqrtPiF;
 
+    // entering a cell with temperature classes: its frequency scale, damping,
+    // sampler threshold and table set
+    auto enter_cell = [&]() {
+        if constexpr (kProf == 3) {
+            const int k = P.tclass[cell];
+            const float4 cp = P.cls_par[k];
+            sc = cp.x; ac = cp.y; thdc = cp.z; isc = cp.w;
+            toff = k * kTabFloats;
+        }
+    };
+
     // one flight segment of a live lane: to the next interaction (scat = true,
     // or destruction) or across one cell face (escape / periodic wrap / next cell)
     auto flight = [&](float ue, bool &scat, float &xc) {
         xc = x - (nx * vxc + ny * vyc + nz * vzc);
-        float H = (k0c > 0.0f) ? ((kProf == 2) ? voigt_analytic(a, P.voigt_u0, fabsf(xc)) : voigt_lds(T, fabsf(xc)))
+        if constexpr (kProf == 3) xc *= sc;
+        float H = (k0c > 0.0f) ? ((kProf == 2) ? voigt_analytic(a, P.voigt_u0, fabsf(xc))
+                                               : voigt_lds((kProf == 3) ? P.cls_tab + toff : T, fabsf(xc)))
                                : 0.0f;
         float kap = k0c * H;
         float tx = (nx > 0.0f) ? (1.0f - fx) * P.dx[0] * f_rcp(nx) : ((nx < 0.0f) ? fx * P.dx[0] * f_rcp(-nx) : INFINITY);
@@ -273,6 +292,7 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
                 k0c = P.k0[cell];
                 if (P.vx) { vxc = P.vx[cell]; vyc = P.vy[cell]; vzc = P.vz[cell]; }
                 epsc = P.eps ? P.eps[cell] : 0.0f;
+                enter_cell();
             }
         }
     };
@@ -285,7 +305,7 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
     // scattering.
     auto prepare = [&](float xc, float r1, float r2, const SDraws &b, ScatPrep &q) {
         const float up1 = b.up1, up2 = b.up2, g = b.g, sg = b.sg, cp = b.cp, sp = b.sp;
-        float upar = upar_lds(T, xc, a, thd, r1, r2);
+        float upar = (kProf == 3) ? upar_lds(P.cls_tab + toff, xc, ac, thdc, r1, r2) : upar_lds(T, xc, a, thd, r1, r2);
         // orthonormal basis about n (Duff et al. 2017)
         float sgn = copysignf(1.0f, nz);
         float A_ = -f_rcp(sgn + nz);
@@ -299,14 +319,16 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
         q.ox = ox * rn; q.oy = oy * rn; q.oz = oz * rn;
         // eq. riia-scatter
         q.xo = xc + upar * (g - 1.0f) + sg * (up1 * cp + up2 * sp);
+        if constexpr (kProf == 3) q.xo *= isc;  // back to reference units
         q.kb = -1;
         q.wq = 0;
         if (P.emis_raw) {
             float gc = nx * P.n_cam[0] + ny * P.n_cam[1] + nz * P.n_cam[2];
             float upc = up1 * (e1x * P.n_cam[0] + e1y * P.n_cam[1] + e1z * P.n_cam[2]) +
                         up2 * (e2x * P.n_cam[0] + e2y * P.n_cam[1] + e2z * P.n_cam[2]);
-            float xcam = xc + upar * (gc - 1.0f) + upc +
-                         (P.n_cam[0] * vxc + P.n_cam[1] * vyc + P.n_cam[2] * vzc);
+            float xcam = xc + upar * (gc - 1.0f) + upc;
+            if constexpr (kProf == 3) xcam *= isc;
+            xcam += P.n_cam[0] * vxc + P.n_cam[1] * vyc + P.n_cam[2] * vzc;
             q.kb = bin_index(xcam, cedges, P.emis_nch, P.ch_inv_w);
             float wph = (P.phase == KRT_PHASE_DIPOLE_I) ? 0.75f * (1.0f + gc * gc) : 1.0f;
             // contributions below 2^32 (F <= 30) convert through 32 bits
@@ -405,6 +427,7 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
                     if (P.vx) { vxc = P.vx[cell]; vyc = P.vy[cell]; vzc = P.vz[cell]; }
                     else { vxc = vyc = vzc = 0.0f; }
                     epsc = P.eps ? P.eps[cell] : 0.0f;
+                    enter_cell();
                     float xg = P.src_x0;
                     if (P.src_profile != KRT_PROF_DELTA_I) {
                         uint4 e2 = philox(make_uint4(0u, plo, phi, 2u), P.key0, P.key1);
@@ -413,8 +436,9 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
                         xg = rr * cos_rev(th);
                         if (P.src_profile == KRT_PROF_VOIGT_I) {
                             float c = u01(e2.z) - 0.5f;  // Cauchy(a): a tan(pi c)
-                            xg += a * sin_rev(0.5f * c) * f_rcp(cos_rev(0.5f * c));
+                            xg += ((kProf == 3) ? ac : a) * sin_rev(0.5f * c) * f_rcp(cos_rev(0.5f * c));
                         }
+                        if constexpr (kProf == 3) xg *= isc;  // the emitting cell's units -> reference
                     }
                     x = xg + nx * vxc + ny * vyc + nz * vzc;
                     ev = 1;
@@ -442,7 +466,7 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
         float xc = 0.0f;
         ScatPrep q;
         if (have) {
-            const float xg = x - (nx * vxc + ny * vyc + nz * vzc);
+            const float xg = (x - (nx * vxc + ny * vyc + nz * vzc)) * ((kProf == 3) ? sc : 1.0f);
             SDraws b;
             scatter_draws(philox(make_uint4(ev, (uint32_t)pid, (uint32_t)(pid >> 32), 1u), P.key0, P.key1),
                           P.phase == KRT_PHASE_DIPOLE_I, b);
@@ -641,7 +665,7 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
             float xc = 0.0f;
             ScatPrep q;
             if (have) {
-                prepare(x - (nx * vxc + ny * vyc + nz * vzc), dr1, dr2, db, q);
+                prepare((x - (nx * vxc + ny * vyc + nz * vzc)) * ((kProf == 3) ? sc : 1.0f), dr1, dr2, db, q);
                 flight(due, scat, xc);
             }
             if (scat) {
@@ -753,14 +777,15 @@ hipError_t launch_transport(const RunParams &P, int grid, int block, hipStream_t
     // spills, 3 waves; the default), above that 128 (4 waves, heavy spills).
     // Profile modes 1 and 2 exist for the plain walk only.
     const int variant = esc ? (block <= 512 ? 2 : (block <= 768 ? 5 : 1))
-                            : (P.profile_mode == 1 ? 3 : (P.profile_mode == 2 ? 4 : 0));
-    static bool attr_set[6] = {false, false, false, false, false, false};
-    const void *fns[6] = {reinterpret_cast<const void *>(mc_transport_kernel<false, 1024>),
+                            : (P.tclass ? 6 : (P.profile_mode == 1 ? 3 : (P.profile_mode == 2 ? 4 : 0)));
+    static bool attr_set[7] = {false, false, false, false, false, false, false};
+    const void *fns[7] = {reinterpret_cast<const void *>(mc_transport_kernel<false, 1024>),
                           reinterpret_cast<const void *>(mc_transport_kernel<true, 1024>),
                           reinterpret_cast<const void *>(mc_transport_kernel<true, 512>),
                           reinterpret_cast<const void *>(mc_transport_kernel<false, 1024, 1>),
                           reinterpret_cast<const void *>(mc_transport_kernel<false, 1024, 2>),
-                          reinterpret_cast<const void *>(mc_transport_kernel<true, 768>)};
+                          reinterpret_cast<const void *>(mc_transport_kernel<true, 768>),
+                          reinterpret_cast<const void *>(mc_transport_kernel<false, 1024, 3>)};
     if (!attr_set[variant]) {
         hipError_t e = hipFuncSetAttribute(fns[variant], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -772,6 +797,7 @@ hipError_t launch_transport(const RunParams &P, int grid, int block, hipStream_t
         case 2: hipLaunchKernelGGL((mc_transport_kernel<true, 512>), dim3(grid), dim3(block), lds, s, P); break;
         case 3: hipLaunchKernelGGL((mc_transport_kernel<false, 1024, 1>), dim3(grid), dim3(block), lds, s, P); break;
         case 5: hipLaunchKernelGGL((mc_transport_kernel<true, 768>), dim3(grid), dim3(block), lds, s, P); break;
+        case 6: hipLaunchKernelGGL((mc_transport_kernel<false, 1024, 3>), dim3(grid), dim3(block), lds, s, P); break;
         default: hipLaunchKernelGGL((mc_transport_kernel<false, 1024, 2>), dim3(grid), dim3(block), lds, s, P); break;
     }
     return hipGetLastError();

@@ -24,7 +24,8 @@ class krt_grid_desc(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
                 ("bc", C.c_int32 * 3), ("n_lines", C.c_int32),
                 ("k0_dev", C.c_void_p), ("vel_dev", C.c_void_p), ("eps_dev", C.c_void_p),
-                ("emis_dev", C.c_void_p)]
+                ("emis_dev", C.c_void_p), ("tclass_dev", C.c_void_p), ("n_tclass", C.c_int32),
+                ("tclass_bratio", C.c_double * 8)]
 
 
 class krt_line_desc(C.Structure):
@@ -180,7 +181,10 @@ class Context:
         return self.L.krt_last_transport_ms(self.h)
 
     # ------------------------------------------------------------- calls
-    def krt_grid_upload(self, n, lo, hi, bc, k0, vel=None, eps=None, emis=None, n_lines=1):
+    def krt_grid_upload(self, n, lo, hi, bc, k0, vel=None, eps=None, emis=None, n_lines=1, tclass=None,
+                        tclass_bratio=None):
+        """tclass: device uint8 [ncell] temperature class per cell (or None);
+        tclass_bratio: the Doppler width of each class over the reference."""
         d = krt_grid_desc()
         d.n[:] = [int(v) for v in n]
         d.lo[:] = [float(v) for v in lo]
@@ -191,7 +195,12 @@ class Context:
         d.vel_dev = None if vel is None else vel.data_ptr()
         d.eps_dev = None if eps is None else eps.data_ptr()
         d.emis_dev = None if emis is None else emis.data_ptr()
-        self._keep["grid"] = (k0, vel, eps, emis)  # borrowed by the library
+        if tclass is not None:
+            br = [float(v) for v in tclass_bratio]
+            d.tclass_dev = tclass.data_ptr()
+            d.n_tclass = len(br)
+            d.tclass_bratio[:len(br)] = br
+        self._keep["grid"] = (k0, vel, eps, emis, tclass)  # borrowed by the library
         self._check(self.L.krt_grid_upload(self.h, C.byref(d)))
 
     def krt_tables_build(self, lines):
@@ -332,8 +341,11 @@ class Transport:
         self.vel = f32(g.get("vel"))
         self.eps = f32(g.get("eps"))
         self.emis_w = f32(g.get("emis"))
+        tcl = g.get("tclass")
+        self.tclass = None if tcl is None else torch.from_numpy(
+            np.ascontiguousarray(tcl, dtype=np.uint8).reshape(-1)).to(dev)
         self.ctx.krt_grid_upload(self.n, g["lo"], g["hi"], g["bc"], self.k0, self.vel, self.eps, self.emis_w,
-                                 n_lines=self.n_lines)
+                                 n_lines=self.n_lines, tclass=self.tclass, tclass_bratio=g.get("tclass_bratio"))
         ln = prob["line"]
         if lines is None:
             lines = [(ln["a"], ln.get("phase", 0))]

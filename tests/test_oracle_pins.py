@@ -505,3 +505,62 @@ def test_imaging_order_and_velocity_shift():
     # camera -x: the emitting cell is now the near one, nothing in front of it
     I2 = imaging.image((2, 1, 1), (0, 0, 0), (2.0, 1.0, 1.0), k0, vel, a, emis, -2.0, 2.0, 3)
     assert np.allclose(I2[0], 1.0, rtol=1e-12)
+
+
+# ------------------------------------------------- per-cell temperature --
+def _temp_cube(a, bratio, scale):
+    """4^3 cube, line-centre depth 50 centre to face, point source at the
+    centre emitting x = 0 (delta) or a Voigt profile; tally ranges times scale."""
+    p = W._problem((4, 4, 4), (-1.0,) * 3, (1.0,) * 3, (0, 0, 0), np.full(64, 50.0), a,
+                   source={"kind": W.SRC_POINT, "pos": (0.1, 0.05, -0.02), "profile": W.PROF_VOIGT, "x0": 0.0},
+                   tally={"spec_nbins": 64, "spec_lo": -8.0 * scale, "spec_hi": 8.0 * scale, "emis_nch": 16,
+                          "ch_lo": -6.0 * scale, "ch_hi": 6.0 * scale, "n_cam": (1.0, 0.0, 0.0)})
+    if bratio is not None:
+        p["grid"]["bratio"] = np.full(64, bratio, dtype=np.float32)
+    return p
+
+
+def test_temperature_scaling_is_exact():
+    """Frequencies are in units of the local Doppler width (Sec. 2.1): a medium
+    whose Doppler width is twice the reference, damping a at the reference, is
+    the reference-width medium with damping a/2 with every frequency doubled.
+    Scaling by 2 is exact in binary, so spectra, emissivities and counters are
+    equal and every escaped frequency is exactly twice, packet by packet."""
+    ra = oracle.mc_run(_temp_cube(2e-3, 2.0, 2.0), 2000, seed=3, packet_log=True)
+    rb = oracle.mc_run(_temp_cube(1e-3, None, 1.0), 2000, seed=3, packet_log=True)
+    assert np.array_equal(ra["spec"], rb["spec"])
+    assert np.array_equal(ra["emis"], rb["emis"])
+    assert ra["counters"] == rb["counters"]
+    la, lb = ra["packet_log"], rb["packet_log"]
+    assert np.array_equal(la[:, 0], 2.0 * lb[:, 0]) and np.array_equal(la[:, 1:], lb[:, 1:])
+
+
+def test_two_temperature_thin_slab_channels():
+    """An optically thin two-cell slab lit along x by a beam of x = 0 photons,
+    cell 0 at the reference Doppler width and cell 1 three times wider, camera
+    along z (g = 0): each cell's emissivity over the channels is the channel
+    integral of the R_IIA kernel at g = 0 in that cell's own units (incoming
+    frequency 0, damping a b_ref / b_cell, channel edges times b_ref / b_cell),
+    within Poisson noise; the scatterings split between the cells in the ratio
+    of their line-centre opacities k0 H(a_c, 0)."""
+    a = 0.01
+    nch, lo, hi = 24, -6.0, 6.0
+    k0 = np.array([0.005, 0.005])
+    p = W._problem((2, 1, 1), (-1.0,) * 3, (1.0,) * 3, (0, 0, 0), k0, a,
+                   source={"kind": W.SRC_BEAM, "pos": (-1.0, 0.0, 0.0), "dir": (1.0, 0.0, 0.0),
+                           "profile": W.PROF_DELTA, "x0": 0.0},
+                   tally={"spec_nbins": 16, "spec_lo": -8.0, "spec_hi": 8.0, "emis_nch": nch, "ch_lo": lo,
+                          "ch_hi": hi, "n_cam": (0.0, 0.0, 1.0)})
+    p["grid"]["bratio"] = np.array([1.0, 3.0], dtype=np.float32)
+    r = oracle.mc_run(p, 4_000_000, seed=5)
+    em = r["emis"]
+    edges = lo + (hi - lo) * np.arange(nch + 1) / nch
+    H0 = [Q.voigt_scipy(a * s, 0.0) for s in (1.0, 1.0 / 3.0)]
+    for cell, s in ((0, 1.0), (1, 1.0 / 3.0)):
+        prob = Q.riia_channel_probs(0.0, a * s, 0.0, edges * s)
+        expect = prob / prob.sum() * em[cell].sum()
+        m = expect > 30
+        z = (em[cell][m] - expect[m]) / np.sqrt(expect[m])
+        assert np.max(np.abs(z)) < 5.0, (cell, np.max(np.abs(z)))
+    ratio = em[1].sum() / em[0].sum()
+    assert abs(ratio / (H0[1] / H0[0]) - 1) < 0.05, (ratio, H0[1] / H0[0])
