@@ -94,3 +94,20 @@ def test_classes_refused_with_learned_or_profile_modes(gpu_ctx):
     T = krt.Transport(_cube(2e-3, 1.0, tclass=np.zeros(216), bratio=[1.0]), ctx=gpu_ctx)
     with pytest.raises(Exception, match="temperature classes"):
         T.run(1000, seed=0, profile_mode=1)
+
+
+def test_unit_ratio_class_reproduces_plain_walk(gpu_ctx):
+    """Every cell in one class of Doppler width b_ref: the class tables equal
+    the line tables and every frequency scale is 1, so the temperature-class
+    transport (its own kernel instance, tables in global memory) reproduces
+    the plain walk's tallies bit for bit on a moving grid."""
+    from paper_2608_09340_amd import krt
+    n = 6
+    TA = krt.Transport(_cube(2e-3, 1.0, tclass=np.zeros(n ** 3), bratio=[1.0], vel=1.5, tau=200.0), ctx=gpu_ctx)
+    ra = TA.run(200_000, seed=11)
+    TB = krt.Transport(_cube(2e-3, 1.0, vel=1.5, tau=200.0), ctx=gpu_ctx)
+    rb = TB.run(200_000, seed=11)
+    assert ra["rc"] == 0 and rb["rc"] == 0
+    assert np.array_equal(ra["spec_raw"], rb["spec_raw"])
+    assert np.array_equal(ra["emis_raw"], rb["emis_raw"])
+    assert ra["counters"] == rb["counters"]
