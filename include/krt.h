@@ -79,9 +79,9 @@ double krt_last_transport_ms(const krt_ctx *ctx);
  * krt_destroy; the library copies nothing except the volume-emission weights,
  * from which it builds an alias table (Walker/Vose) on the device.
  * Errors: KRT_EINVAL for n <= 0, hi <= lo, bad bc, n_lines outside 1..8,
- * k0 == NULL, ncell >= 2^31, or (with tclass_dev) n_tclass outside 1..8 or a
- * ratio outside [0.05, 20].  The class indices themselves are not read back:
- * the caller guarantees tclass_dev[i] < n_tclass. */
+ * k0 == NULL, ncell >= 2^31, or (with tclass_dev) n_tclass outside 1..8, a
+ * ratio outside [0.05, 20] or a class index >= n_tclass (the indices are
+ * copied to the host once and checked at upload). */
 typedef struct {
     int32_t n[3];
     double lo[3], hi[3];

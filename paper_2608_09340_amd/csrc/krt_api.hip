@@ -227,6 +227,14 @@ extern "C" int krt_grid_upload(krt_ctx *c, const krt_grid_desc *d) {
                 return fail(c, KRT_EINVAL, "tclass_bratio[%d] = %g outside [0.05, 20]", k, d->tclass_bratio[k]);
     }
     HIPCHK(c, hipSetDevice(c->device));
+    if (d->tclass_dev) {
+        // every class index must name a class: the transport indexes the class
+        // parameters and table sets with it
+        std::vector<uint8_t> cls((size_t)ncell);
+        HIPCHK(c, hipMemcpy(cls.data(), d->tclass_dev, (size_t)ncell, hipMemcpyDeviceToHost));
+        const uint8_t mx = *std::max_element(cls.begin(), cls.end());
+        if (mx >= d->n_tclass) return fail(c, KRT_EINVAL, "class index %d >= n_tclass %d", (int)mx, d->n_tclass);
+    }
     free_grid(c);
     c->grid = *d;
     c->cls_line = -1;

@@ -96,6 +96,16 @@ def test_classes_refused_with_learned_or_profile_modes(gpu_ctx):
         T.run(1000, seed=0, profile_mode=1)
 
 
+def test_class_index_out_of_range_refused_at_upload(gpu_ctx):
+    """A class index naming no class is refused when the grid is uploaded,
+    before any kernel could index the class tables with it."""
+    from paper_2608_09340_amd import krt
+    tcl = np.zeros(216, dtype=np.uint8)
+    tcl[17] = 2
+    with pytest.raises(Exception, match="class index"):
+        krt.Transport(_cube(2e-3, 1.0, tclass=tcl, bratio=[1.0, 2.0]), ctx=gpu_ctx)
+
+
 def test_unit_ratio_class_reproduces_plain_walk(gpu_ctx):
     """Every cell in one class of Doppler width b_ref: the class tables equal
     the line tables and every frequency scale is 1, so the temperature-class
