@@ -237,7 +237,8 @@ typedef struct {
     const float *kabs_dev;     /* absorption coefficient per cell (units of k0), or NULL */
 } krt_image_desc;
 int krt_image(krt_ctx *ctx, const krt_image_desc *desc);
-/* Duration in ms of the last krt_image kernel (HIP events on the library stream). */
+/* Duration in ms of the last krt_image kernel, from HIP events that its dispatch records at the
+ * kernel's start and end (host launch latency excluded). */
 float krt_last_image_ms(const krt_ctx *ctx);
 
 /* --------------------------------------------------------------- levels --- */

@@ -12,6 +12,7 @@
 
 #include "krt.h"
 #include "krt_internal.h"
+#include "krt_image.h"
 #include "krt_kernels.h"
 #include "krt_mlp.h"
 
@@ -518,9 +519,7 @@ extern "C" int krt_image(krt_ctx *c, const krt_image_desc *d) {
     Q.kabs = d->kabs_dev;
     Q.out = d->image_dev;
     HIPCHK(c, hipSetDevice(c->device));
-    HIPCHK(c, hipEventRecord(c->ev0, c->stream));
-    HIPCHK(c, launch_image(Q, c->stream));
-    HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+    HIPCHK(c, launch_image_timed(Q, c->stream, c->ev0, c->ev1));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipEventElapsedTime(&c->last_image_ms, c->ev0, c->ev1));
     return KRT_OK;

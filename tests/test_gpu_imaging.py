@@ -56,6 +56,49 @@ def test_image_vs_oracle(gpu_ctx, axis, with_src, with_abs):
     assert np.allclose(g, ref, rtol=2e-4, atol=1e-6 * scale)
 
 
+def _image_case(gpu_ctx, n, axis, moving, with_src, with_abs, seed):
+    import torch
+    from paper_2608_09340_amd import krt
+    nc = n[0] * n[1] * n[2]
+    rng = np.random.default_rng(seed)
+    k0 = (10.0 ** rng.uniform(-3, 1.5, nc)) / 0.1
+    vel = rng.normal(0, 1.5, (3, nc)) if moving else None
+    a, nch, ch = 1e-2, 13, (-6.0, 5.0)
+    T = krt.Transport(_grid_problem(n, k0, vel, a, nch, ch), ctx=gpu_ctx)
+    emis = rng.uniform(0, 1, (nc, nch)).astype(np.float32)
+    src = rng.uniform(0, 0.5, (nc, nch)).astype(np.float32) if with_src else None
+    kabs = (10.0 ** rng.uniform(-2, 1.3, nc) / 0.1).astype(np.float32) if with_abs else None
+    e_d = torch.from_numpy(emis).cuda()
+    s_d = None if src is None else torch.from_numpy(src).cuda()
+    a_d = None if kabs is None else torch.from_numpy(kabs).cuda()
+    npix = {0: n[1] * n[2], 1: n[0] * n[2], 2: n[0] * n[1]}[axis % 3]
+    out = torch.zeros((npix, nch), dtype=torch.float32, device="cuda")
+    d = krt.krt_image_desc()
+    d.line, d.axis, d.nch, d.ch_lo, d.ch_hi = 0, axis, nch, ch[0], ch[1]
+    d.emis_dev, d.src_dev, d.image_dev = e_d.data_ptr(), (None if s_d is None else s_d.data_ptr()), out.data_ptr()
+    d.kabs_dev = None if a_d is None else a_d.data_ptr()
+    gpu_ctx.krt_image(d)
+    g = out.cpu().numpy().astype(np.float64)
+    ref = oimg.image(n, (0.0, 0.0, 0.0), (1.2, 0.9, 0.7), k0.astype(np.float32),
+                     None if vel is None else vel.astype(np.float32), a, emis, ch[0], ch[1], axis, src=src, kabs=kabs)
+    return g, ref
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("moving,with_src", [(False, False), (True, False), (True, True)])
+def test_image_long_rays_in_segments(gpu_ctx, axis, moving, with_src):
+    """A 100 x 7 x 5 grid with 13 channels is small enough that the pass cuts
+    each ray into segments whose affine maps are composed in order: eight of
+    13 cells (the last one 9) along x, two along y (4 and 3 cells), one along
+    z; every segment along x has a full chunk of cells and a ragged end.  The
+    image matches the oracle's cell-by-cell march from the far side."""
+    n = (100, 7, 5)
+    g, ref = _image_case(gpu_ctx, n, axis, moving, with_src, True, 40 + axis)
+    scale = np.abs(ref).max()
+    assert np.max(np.abs(g - ref)) < 2e-5 * scale, np.max(np.abs(g - ref)) / scale
+    assert np.allclose(g, ref, rtol=2e-4, atol=1e-6 * scale)
+
+
 def test_image_full_size_sampled_columns(gpu_ctx):
     """64^3 sphere (line-centre depth 1e4 centre to face), emissivity of 1e5
     Monte Carlo packets in 32 channels: the GPU image toward +x vs the oracle on
