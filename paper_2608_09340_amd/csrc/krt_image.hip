@@ -40,7 +40,8 @@ constexpr int kImgMaxSeg = kImgWaves;   // segments of one ray (waves of one blo
 constexpr int kImgMinSegCells = 4;      // shortest segment worth a wave
 constexpr int64_t kImgTargetWaves = 16384;  // twice the chip's resident waves at 8 per SIMD
 
-template <bool kVel, bool kAbs, bool kSrc>
+// fields of a chunk of cells along the ray (the arrays a kernel instance does
+// not read are never written and cost nothing)
 struct ImgChunk {
     float k0[kImgChunk], v[kImgChunk], ab[kImgChunk], j[kImgChunk], s[kImgChunk];
 };
@@ -49,7 +50,7 @@ struct ImgChunk {
 // in the full-chunk path); cell t sits at offset o (fields) and o * nch (channels)
 template <bool kVel, bool kAbs, bool kSrc, int M>
 __device__ __forceinline__ void img_load(const ImageParams &Q, int64_t o, int64_t step, int64_t cstep,
-                                         const float *pe, const float *ps, ImgChunk<kVel, kAbs, kSrc> &b) {
+                                         const float *pe, const float *ps, ImgChunk &b) {
 #pragma unroll
     for (int u = 0; u < M; ++u) {
         const int64_t oc = o + u * step;
@@ -77,7 +78,7 @@ __device__ __forceinline__ float img_voigt(const float *T, float xa) {
 
 template <bool kVel, bool kAbs, bool kSrc, int M>
 __device__ __forceinline__ void img_fold(const ImageParams &Q, const float *TV, float xk,
-                                         const ImgChunk<kVel, kAbs, kSrc> &b, float &A, float &B) {
+                                         const ImgChunk &b, float &A, float &B) {
 #pragma unroll
     for (int u = 0; u < M; ++u) {
         const float xg = kVel ? xk - Q.sgnf * b.v[u] : xk;
@@ -126,7 +127,7 @@ __device__ __forceinline__ void image_body(const ImageParams &Q, int nseg, int s
         const float *ps = kSrc ? Q.srcf + o * Q.nch + c : nullptr;
         const float xk = Q.ch_lo + ((float)c + 0.5f) * Q.ch_w;
         const int nfull = max(0, t1 - t0) / kImgChunk;
-        ImgChunk<kVel, kAbs, kSrc> cur{};
+        ImgChunk cur{};
         for (int i = 0; i < nfull; ++i) {
             img_load<kVel, kAbs, kSrc, kImgChunk>(Q, o, step, cstep, pe, ps, cur);
             img_fold<kVel, kAbs, kSrc, kImgChunk>(Q, TV, xk, cur, A, B);
