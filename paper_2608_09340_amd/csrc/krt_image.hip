@@ -10,8 +10,8 @@
 // with x_k the lab-frame centre of channel k.
 //
 // Layout.  One lane per (pixel, channel); a wave holds 64 consecutive
-// (pixel, channel) pairs, so its lanes read a cell's fields at one or two
-// addresses (broadcast) and the emissivity of consecutive channels from
+// (pixel, channel) pairs, so its lanes read a cell's fields at one address
+// per pixel of the wave (one or two at 32 channels or more) and the emissivity of consecutive channels from
 // consecutive addresses: the pass streams the emissivity array once.  The
 // Voigt table sits in LDS.  The recurrence is affine in I, so a ray can be
 // cut into segments: the wave of segment s folds its cells into a map
@@ -20,8 +20,8 @@
 // launch still fills the chip; long ones take one.  A wave issues the loads
 // of a chunk of cells together and then folds them in order (the march is a
 // dependent chain, its memory is not); memory latency is hidden by the other
-// waves, eight per SIMD, which a second register buffer for the next chunk
-// would halve.
+// waves on the SIMD (eight without a source function), whose number a second
+// register buffer for the next chunk would halve.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
