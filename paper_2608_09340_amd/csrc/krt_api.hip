@@ -530,81 +530,128 @@ extern "C" float krt_last_image_ms(const krt_ctx *c) { return c ? c->last_image_
 // --------------------------------------------------------------- levels ---
 // Per-cell rate matrix, FP64 Gaussian elimination with partial pivoting.
 // consts: E[nl] g[nl] A[nl*nl] Cd[nl*nl] sigma0[nl-1]
-__global__ void levels_kernel(int nl, int64_t ncell, const double *K, const double *ncoll,
-                              const double *ntot, const float *jbar, double *pops, float *k0_out,
-                              float *eps_out) {
+// The level count is a template argument: every index into the matrices is
+// then a compile-time constant after unrolling (the pivot row is swapped by
+// selects over the candidate rows), so they live in registers; a run-time
+// count would index them dynamically and put them in scratch memory.
+template <int NL>
+__global__ void __launch_bounds__(256) levels_kernel(int64_t ncell, const double *K, const double *ncoll,
+                                                     const double *ntot, const float *jbar, double *pops,
+                                                     float *k0_out, float *eps_out) {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
-    const double *E = K, *g = K + nl, *A = K + 2 * nl, *Cd = K + 2 * nl + nl * nl, *s0 = K + 2 * nl + 2 * nl * nl;
-    double R[8][8], M[8][8], b[8];
+    const double *E = K, *g = K + NL, *A = K + 2 * NL, *Cd = K + 2 * NL + NL * NL, *s0 = K + 2 * NL + 2 * NL * NL;
+    double R[NL][NL], M[NL][NL], b[NL];
     const double nc = ncoll[c];
-    for (int i = 0; i < nl; ++i)
-        for (int j = 0; j < nl; ++j) R[i][j] = 0.0;
-    for (int u = 1; u < nl; ++u)
+#pragma unroll
+    for (int i = 0; i < NL; ++i)
+#pragma unroll
+        for (int j = 0; j < NL; ++j) R[i][j] = 0.0;
+#pragma unroll
+    for (int u = 1; u < NL; ++u)
+#pragma unroll
         for (int l = 0; l < u; ++l) {
-            double cd = Cd[u * nl + l] * nc;
+            double cd = Cd[u * NL + l] * nc;
             double cu = cd * (g[u] / g[l]) * exp(-(E[u] - E[l]));
-            R[u][l] += A[u * nl + l] + cd;
+            R[u][l] += A[u * NL + l] + cd;
             R[l][u] += cu;
         }
     const double kGam = 4.0 * 3.14159265358979323846 * 1.77245385090551602730;
-    if (jbar)
-        for (int l = 0; l + 1 < nl; ++l) {
+    if (jbar) {
+#pragma unroll
+        for (int l = 0; l + 1 < NL; ++l) {
             double G = kGam * s0[l] * (double)jbar[(int64_t)l * ncell + c];
             R[l][l + 1] += G;
             R[l + 1][l] += (g[l] / g[l + 1]) * G;
         }
-    for (int i = 0; i < nl; ++i) {
+    }
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
         double out = 0.0;
-        for (int j = 0; j < nl; ++j) {
+#pragma unroll
+        for (int j = 0; j < NL; ++j) {
             M[i][j] = (j != i) ? R[j][i] : 0.0;
             if (j != i) out += R[i][j];
         }
         M[i][i] = -out;
         b[i] = 0.0;
     }
-    for (int j = 0; j < nl; ++j) M[nl - 1][j] = 1.0;
-    b[nl - 1] = ntot[c];
-    for (int k = 0; k < nl; ++k) {
+#pragma unroll
+    for (int j = 0; j < NL; ++j) M[NL - 1][j] = 1.0;
+    b[NL - 1] = ntot[c];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
         int p = k;
         double mx = fabs(M[k][k]);
-        for (int i = k + 1; i < nl; ++i) if (fabs(M[i][k]) > mx) { mx = fabs(M[i][k]); p = i; }
-        if (p != k) {
-            for (int j = 0; j < nl; ++j) { double t = M[k][j]; M[k][j] = M[p][j]; M[p][j] = t; }
-            double t = b[k]; b[k] = b[p]; b[p] = t;
+#pragma unroll
+        for (int i = k + 1; i < NL; ++i) if (fabs(M[i][k]) > mx) { mx = fabs(M[i][k]); p = i; }
+#pragma unroll
+        for (int i = k + 1; i < NL; ++i) {
+            const bool sw = (i == p);
+#pragma unroll
+            for (int j = 0; j < NL; ++j) {
+                const double t = M[k][j];
+                M[k][j] = sw ? M[i][j] : t;
+                M[i][j] = sw ? t : M[i][j];
+            }
+            const double t = b[k];
+            b[k] = sw ? b[i] : t;
+            b[i] = sw ? t : b[i];
         }
-        for (int i = k + 1; i < nl; ++i) {
+#pragma unroll
+        for (int i = k + 1; i < NL; ++i) {
             double f = M[i][k] / M[k][k];
-            for (int j = k; j < nl; ++j) M[i][j] -= f * M[k][j];
+#pragma unroll
+            for (int j = k; j < NL; ++j) M[i][j] -= f * M[k][j];
             b[i] -= f * b[k];
         }
     }
-    for (int i = nl - 1; i >= 0; --i) {
+#pragma unroll
+    for (int i = NL - 1; i >= 0; --i) {
         double s = b[i];
-        for (int j = i + 1; j < nl; ++j) s -= M[i][j] * b[j];
+#pragma unroll
+        for (int j = i + 1; j < NL; ++j) s -= M[i][j] * b[j];
         b[i] = s / M[i][i];
     }
-    for (int i = 0; i < nl; ++i) pops[c * nl + i] = b[i];
-    for (int l = 0; l + 1 < nl; ++l) {
+#pragma unroll
+    for (int i = 0; i < NL; ++i) pops[c * NL + i] = b[i];
+#pragma unroll
+    for (int l = 0; l + 1 < NL; ++l) {
         int u = l + 1;
         if (k0_out) k0_out[(int64_t)l * ncell + c] = (float)(b[l] * s0[l]);
         if (eps_out) {
             double ctot = 0.0;
-            for (int j = 0; j < nl; ++j) if (j != u) {
-                double cd = (j < u) ? Cd[u * nl + j] * nc : Cd[j * nl + u] * nc * (g[j] / g[u]) * exp(-(E[j] - E[u]));
+#pragma unroll
+            for (int j = 0; j < NL; ++j) if (j != u) {
+                double cd = (j < u) ? Cd[u * NL + j] * nc : Cd[j * NL + u] * nc * (g[j] / g[u]) * exp(-(E[j] - E[u]));
                 ctot += cd;
             }
-            eps_out[(int64_t)l * ncell + c] = (float)(ctot / (A[u * nl + l] + ctot));
+            eps_out[(int64_t)l * ncell + c] = (float)(ctot / (A[u * NL + l] + ctot));
         }
     }
+}
+
+template <int NL>
+static void launch_levels_t(int64_t ncell, const double *consts, const double *ncoll, const double *ntot,
+                            const float *jbar, double *pops, float *k0_out, float *eps_out, hipStream_t s) {
+    int grid = (int)((ncell + 255) / 256);
+    hipLaunchKernelGGL(levels_kernel<NL>, dim3(grid), dim3(256), 0, s, ncell, consts, ncoll, ntot, jbar, pops,
+                       k0_out, eps_out);
 }
 
 hipError_t krt::launch_levels(int nl, int64_t ncell, const double *consts, const double *ncoll,
                               const double *ntot, const float *jbar, double *pops, float *k0_out,
                               float *eps_out, hipStream_t s) {
-    int grid = (int)((ncell + 255) / 256);
-    hipLaunchKernelGGL(levels_kernel, dim3(grid), dim3(256), 0, s, nl, ncell, consts, ncoll, ntot, jbar, pops,
-                       k0_out, eps_out);
+    switch (nl) {
+        case 2: launch_levels_t<2>(ncell, consts, ncoll, ntot, jbar, pops, k0_out, eps_out, s); break;
+        case 3: launch_levels_t<3>(ncell, consts, ncoll, ntot, jbar, pops, k0_out, eps_out, s); break;
+        case 4: launch_levels_t<4>(ncell, consts, ncoll, ntot, jbar, pops, k0_out, eps_out, s); break;
+        case 5: launch_levels_t<5>(ncell, consts, ncoll, ntot, jbar, pops, k0_out, eps_out, s); break;
+        case 6: launch_levels_t<6>(ncell, consts, ncoll, ntot, jbar, pops, k0_out, eps_out, s); break;
+        case 7: launch_levels_t<7>(ncell, consts, ncoll, ntot, jbar, pops, k0_out, eps_out, s); break;
+        case 8: launch_levels_t<8>(ncell, consts, ncoll, ntot, jbar, pops, k0_out, eps_out, s); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -68,3 +68,55 @@ def test_lambda_iteration_levels(lam):
     k0 = lam.k0.cpu().numpy().reshape(nl - 1, nc)
     assert np.allclose(k0, (P[:, :nl - 1] * s0[None, :]).T, rtol=1e-6)
     assert hist[-1]["max_rel_change"] < hist[0]["max_rel_change"] * 1.5
+
+
+@pytest.mark.parametrize("nl", [2, 3, 4, 5, 6, 7, 8])
+def test_level_solve_every_level_count(gpu_ctx, nl):
+    """The level solve at every level count the library accepts (a kernel
+    instance per count, its matrices in registers), on 3000 cells with
+    collision rates over six decades and mean intensities over four: the
+    populations equal the oracle's solve of the same rate equations, sum to
+    n_tot, and give k0 = n_l sigma0.  The two eliminations round in different
+    orders; their difference is of order the machine epsilon times the
+    largest entries (so times n_tot) in absolute terms, which at eight levels
+    is up to 2e-8 of the smallest populations (4e-9 of n_tot): the bound is
+    1e-9 relative plus 1e-13 n_tot absolute."""
+    import torch
+    from paper_2608_09340_amd import krt
+    rng = np.random.default_rng(100 + nl)
+    nc = 3000
+    j = np.arange(nl, dtype=np.float64)
+    E = 0.4 * j * (j + 1)                     # rotor ladder in units of kT
+    g = 2 * j + 1
+    A = np.zeros((nl, nl))
+    Cd = np.zeros((nl, nl))
+    for u in range(1, nl):
+        A[u, u - 1] = 1e-2 * u ** 3
+        for l in range(u):
+            Cd[u, l] = 3e-3 / (u - l)
+    s0 = rng.uniform(0.5, 2.0, nl - 1)
+    ncoll = 10.0 ** rng.uniform(-2, 4, nc)
+    ntot = rng.uniform(0.5, 2.0, nc)
+    jbar = (10.0 ** rng.uniform(-3, 1, (nl - 1, nc))).astype(np.float32)
+    keep = [np.ascontiguousarray(v, dtype=np.float64).reshape(-1) for v in (E, g, A, Cd, s0)]
+    nc_d = torch.from_numpy(ncoll).cuda()
+    nt_d = torch.from_numpy(ntot).cuda()
+    jb_d = torch.from_numpy(jbar).cuda()
+    pops = torch.zeros(nc * nl, dtype=torch.float64, device="cuda")
+    k0 = torch.zeros((nl - 1) * nc, dtype=torch.float32, device="cuda")
+    eps = torch.zeros((nl - 1) * nc, dtype=torch.float32, device="cuda")
+    d = krt.krt_levels_desc()
+    d.n_levels, d.ncell = nl, nc
+    d.E, d.g, d.A, d.Cd, d.sigma0 = [k.ctypes.data for k in keep]
+    d.ncoll_dev, d.ntot_dev, d.pops_dev = nc_d.data_ptr(), nt_d.data_ptr(), pops.data_ptr()
+    d.k0_out_dev, d.eps_out_dev = k0.data_ptr(), eps.data_ptr()
+    gpu_ctx.krt_levels_update(d, jb_d)
+    P = pops.cpu().numpy().reshape(nc, nl)
+    gamma = 4 * np.pi * np.sqrt(np.pi) * s0[:, None] * jbar.astype(np.float64)
+    ref = oracle.levels_solve(E, g, A, Cd, ncoll, ntot, gamma=gamma)
+    assert np.all(P > 0)
+    assert np.allclose(P.sum(1), ntot, rtol=1e-10)
+    assert np.all(np.abs(P - ref) <= 1e-9 * np.abs(ref) + 1e-13 * ntot[:, None]), np.max(np.abs(P - ref) / np.abs(ref))
+    e = eps.cpu().numpy()
+    assert np.allclose(k0.cpu().numpy().reshape(nl - 1, nc), (P[:, :nl - 1] * s0[None, :]).T, rtol=1e-6)
+    assert np.all((e > 0) & (e < 1))
