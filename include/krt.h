@@ -224,8 +224,9 @@ int krt_mc_run(krt_ctx *ctx, uint64_t n_packets, uint64_t seed, const krt_run_op
  * y -> k*nx + i, z -> j*nx + i.  Device arrays, caller-owned:
  *   emis_dev [ncell][nch], src_dev [ncell][nch] or NULL, kabs_dev [ncell] or
  *   NULL (no absorption), image_dev [npix][nch].
- * Errors: KRT_EINVAL (axis, nch outside 1..256, empty range, NULL arrays),
- * KRT_ESTATE (no grid, no tables or opacity slice for the line). */
+ * Errors: KRT_EINVAL (axis, nch outside 1..256, empty range, NULL arrays,
+ * npix * nch above 2^31), KRT_ESTATE (no grid, no tables or opacity slice for
+ * the line). */
 typedef struct {
     int32_t line;
     int32_t axis;              /* camera direction: 0 +x, 1 +y, 2 +z, 3 -x, 4 -y, 5 -z */

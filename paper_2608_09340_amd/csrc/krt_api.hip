@@ -509,6 +509,11 @@ extern "C" int krt_image(krt_ctx *c, const krt_image_desc *d) {
     else if (Q.d == 1) { Q.n0 = g.n[0]; Q.npix = (int64_t)g.n[0] * g.n[2]; Q.stride = g.n[0]; }
     else { Q.n0 = g.n[0]; Q.npix = (int64_t)g.n[0] * g.n[1]; Q.stride = (int64_t)g.n[0] * g.n[1]; }
     Q.nch = d->nch;
+    // one launch covers every (pixel, channel) pair with a work-item (a few
+    // more when rays are cut into segments, which happens only for small images)
+    if (Q.npix * (int64_t)Q.nch > (int64_t(1) << 31))
+        return fail(c, KRT_EINVAL, "image of %lld pixels x %d channels exceeds 2^31 (pixel, channel) pairs",
+                    (long long)Q.npix, Q.nch);
     Q.ch_lo = (float)d->ch_lo;
     Q.ch_w = (float)((d->ch_hi - d->ch_lo) / d->nch);
     Q.tab = c->tab[d->line];
