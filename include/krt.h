@@ -333,7 +333,7 @@ int krt_levels_update(krt_ctx *ctx, const krt_levels_desc *desc,
  * krt_escape_get_weights / put_weights: [35466 + 280] FP32 device buffers.
  * krt_escape_forward: in_dev [n][8] raw (log10 tau_R, log10 a, x_in, u_a, u_b,
  *   u_c or (flag 1) x_out, r, flag) -> out_dev [n][10] in physical units (output 6 as a logit,
- *   output 4 with its calibration term).
+ *   output 4 with its calibration term); n < 2^30.
  * Errors: KRT_EINVAL (sizes, ranges), KRT_ESTATE (no init / no tables). */
 int krt_escape_init(krt_ctx *ctx, uint64_t seed);
 int krt_escape_record(krt_ctx *ctx, int32_t line, uint64_t n, uint64_t seed, uint64_t offset,
@@ -357,7 +357,8 @@ int krt_escape_forward(krt_ctx *ctx, const float *in_dev, int64_t n, float *out_
  *   nb+1 at/above, -1 NaN), the index rule of every tally.
  * krt_debug_voigt: out[i] = H(a_line, x[i]) from the staged tables.
  * krt_debug_upar: out[i] = u_par drawn for gas-frame frequency x from event
- *   ev0 + i of packet `packet` (the words the transport uses). */
+ *   ev0 + i of packet `packet` (the words the transport uses).
+ * Every diagnostic takes 1 <= n <= 2^31 elements, else KRT_EINVAL. */
 int krt_debug_philox(krt_ctx *ctx, const uint32_t *ctr_dev, const uint32_t *key_dev,
                      uint32_t *out_dev, int64_t n);
 int krt_debug_bins(krt_ctx *ctx, const float *x_dev, int64_t n, int32_t nb, double lo,

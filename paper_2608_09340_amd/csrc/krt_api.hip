@@ -684,9 +684,13 @@ extern "C" int krt_levels_update(krt_ctx *c, const krt_levels_desc *d, const flo
 }
 
 // ----------------------------------------------------------- diagnostics ---
+// The diagnostics launch one work-item per element: at most 2^31 of them
+// keeps a launch within the 2^32 work-items of a grid dimension.
+constexpr int64_t kMaxDebugElems = int64_t(1) << 31;
+
 extern "C" int krt_debug_philox(krt_ctx *c, const uint32_t *ctr, const uint32_t *key, uint32_t *out, int64_t n) {
     if (!c) return KRT_EINVAL;
-    if (!ctr || !key || !out || n <= 0) return fail(c, KRT_EINVAL, "bad philox args");
+    if (!ctr || !key || !out || n <= 0 || n > kMaxDebugElems) return fail(c, KRT_EINVAL, "bad philox args");
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, launch_debug_philox(ctr, key, out, n, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -695,7 +699,7 @@ extern "C" int krt_debug_philox(krt_ctx *c, const uint32_t *ctr, const uint32_t 
 
 extern "C" int krt_debug_bins(krt_ctx *c, const float *x, int64_t n, int32_t nb, double lo, double hi, int32_t *out) {
     if (!c) return KRT_EINVAL;
-    if (!x || !out || n <= 0 || !valid_bins(nb, lo, hi) || nb > kMaxSpecBins)
+    if (!x || !out || n <= 0 || n > kMaxDebugElems || !valid_bins(nb, lo, hi) || nb > kMaxSpecBins)
         return fail(c, KRT_EINVAL, "bad bins args");
     HIPCHK(c, hipSetDevice(c->device));
     std::vector<float> e(nb + 1);
@@ -708,7 +712,7 @@ extern "C" int krt_debug_bins(krt_ctx *c, const float *x, int64_t n, int32_t nb,
 
 extern "C" int krt_debug_voigt_analytic(krt_ctx *c, double a, const float *x, int64_t n, float *out) {
     if (!c) return KRT_EINVAL;
-    if (!x || !out || n <= 0 || !(a > 0.0 && a < 1.0)) return fail(c, KRT_EINVAL, "bad voigt args");
+    if (!x || !out || n <= 0 || n > kMaxDebugElems || !(a > 0.0 && a < 1.0)) return fail(c, KRT_EINVAL, "bad voigt args");
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, launch_debug_voigt_analytic((float)a, (float)voigt_crossing(a), x, n, out, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -718,7 +722,7 @@ extern "C" int krt_debug_voigt_analytic(krt_ctx *c, double a, const float *x, in
 extern "C" int krt_debug_voigt(krt_ctx *c, int32_t line, const float *x, int64_t n, float *out) {
     if (!c) return KRT_EINVAL;
     if (line < 0 || line >= (int)c->tab.size()) return fail(c, KRT_ESTATE, "line %d has no tables", line);
-    if (!x || !out || n <= 0) return fail(c, KRT_EINVAL, "bad voigt args");
+    if (!x || !out || n <= 0 || n > kMaxDebugElems) return fail(c, KRT_EINVAL, "bad voigt args");
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, launch_debug_voigt(c->tab[line], x, n, out, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -729,7 +733,7 @@ extern "C" int krt_debug_upar(krt_ctx *c, int32_t line, float x, uint64_t seed, 
                               int64_t n, float *out) {
     if (!c) return KRT_EINVAL;
     if (line < 0 || line >= (int)c->tab.size()) return fail(c, KRT_ESTATE, "line %d has no tables", line);
-    if (!out || n <= 0 || !std::isfinite(x)) return fail(c, KRT_EINVAL, "bad upar args");
+    if (!out || n <= 0 || n > kMaxDebugElems || !std::isfinite(x)) return fail(c, KRT_EINVAL, "bad upar args");
     HIPCHK(c, hipSetDevice(c->device));
     float a = (float)c->lines[line].a, thd = (float)std::atan(kDelta / c->lines[line].a);
     HIPCHK(c, launch_debug_upar(c->tab[line], a, thd, x, (uint32_t)seed, (uint32_t)(seed >> 32), packet, ev0, n,
@@ -923,7 +927,8 @@ extern "C" int krt_escape_put_weights(krt_ctx *c, const float *dev, uint64_t nfl
 extern "C" int krt_escape_forward(krt_ctx *c, const float *in_dev, int64_t n, float *out_dev) {
     if (!c) return KRT_EINVAL;
     if (!c->mlp_ready) return fail(c, KRT_ESTATE, "call krt_escape_init first");
-    if (!in_dev || !out_dev || n <= 0) return fail(c, KRT_EINVAL, "bad forward args");
+    if (!in_dev || !out_dev || n <= 0 || n >= (int64_t(1) << 30))  // four work-items per row
+        return fail(c, KRT_EINVAL, "bad forward args");
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, launch_mlp_forward(c->mlp_blob, in_dev, n, out_dev, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
