@@ -313,23 +313,24 @@ int krt_levels_update(krt_ctx *ctx, const krt_levels_desc *desc,
  * core.
  *
  * krt_escape_init: He-uniform parameters from Philox(seed), Adam state zeroed.
- * krt_escape_record: n single-cell escapes for line `line`, log10 tau_R uniform
+ * krt_escape_record: 1 <= n <= 2^31 single-cell escapes for line `line`, log10 tau_R uniform
  *   in [lo, hi], x_in fixed (x_fixed = 1) or 1/2 N(0, 1/2) + 1/2 U[-3, 3];
  *   samples_dev [n][11] FP32: (log10 tau_R, log10 a, x_in, x_out, s, t, mu,
  *   ln N_s, ln <x^2>, valid, alpha).
  * krt_escape_fit_norm: target mean / scale and the log10 a range from valid
  *   records; clears the calibration.
- * krt_escape_calibrate: per (log10 tau_R, |x_in|) bin with at least 100 valid records
- *   with |x_in| <= 2,
+ * krt_escape_calibrate: n < 2^30 records; per (log10 tau_R, |x_in|) bin with at
+ *   least 100 valid records with |x_in| <= 2,
  *   the calibration term ln(sum N_s / sum exp(network ln E[N_s])) over the
  *   records (marginal rows, quantile levels drawn per record), so that the
  *   predicted mean count is unbiased bin by bin; other bins get 0.
  * krt_escape_grad: gradient of the mean loss over the batch given by
- *   idx_dev [batch] (record indices) and u_dev [batch][4] = (u_a, u_b, u_c,
+ *   idx_dev [batch] (record indices, 1 <= batch <= 2^20) and u_dev [batch][4] = (u_a, u_b, u_c,
  *   1 for a conditional row else 0); grad_out_dev [35466], loss_out_dev [1]
  *   (may be NULL).
  * krt_escape_train: `steps` Adam steps (lr, betas 0.9/0.999) on random batches
- *   (Philox(seed)); loss_hist_dev [steps] or NULL.
+ *   (Philox(seed)) of 1 <= batch <= 2^20 out of n < 2^31 records;
+ *   loss_hist_dev [steps] or NULL.
  * krt_escape_get_weights / put_weights: [35466 + 280] FP32 device buffers.
  * krt_escape_forward: in_dev [n][8] raw (log10 tau_R, log10 a, x_in, u_a, u_b,
  *   u_c or (flag 1) x_out, r, flag) -> out_dev [n][10] in physical units (output 6 as a logit,

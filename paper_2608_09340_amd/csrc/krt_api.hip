@@ -847,7 +847,8 @@ extern "C" int krt_escape_fit_norm(krt_ctx *c, const float *samples_dev, uint64_
 extern "C" int krt_escape_calibrate(krt_ctx *c, const float *samples_dev, uint64_t n) {
     if (!c) return KRT_EINVAL;
     if (!c->mlp_ready) return fail(c, KRT_ESTATE, "call krt_escape_init first");
-    if (!samples_dev || n == 0 || n >= (1ull << 31)) return fail(c, KRT_EINVAL, "bad calibration args");
+    if (!samples_dev || n == 0 || n >= (1ull << 30))  // four work-items per record
+        return fail(c, KRT_EINVAL, "bad calibration args");
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(c->mlp_calsum), 3 * kNCal, c->stream));
     HIPCHK(c, launch_mlp_calib(c->mlp_blob, samples_dev, (int64_t)n, c->mlp_calsum, c->mlp_norm, c->stream));
@@ -860,7 +861,8 @@ extern "C" int krt_escape_grad(krt_ctx *c, const float *samples_dev, const int32
                                int32_t batch, float *grad_out_dev, float *loss_out_dev) {
     if (!c) return KRT_EINVAL;
     if (!c->mlp_ready) return fail(c, KRT_ESTATE, "call krt_escape_init first");
-    if (!samples_dev || !idx_dev || !u_dev || !grad_out_dev || batch <= 0) return fail(c, KRT_EINVAL, "bad grad args");
+    if (!samples_dev || !idx_dev || !u_dev || !grad_out_dev || batch <= 0 || batch > (1 << 20))
+        return fail(c, KRT_EINVAL, "bad grad args");
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(c->mlp_g), kNParams / 2, c->stream));
     HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(c->mlp_loss), 1, c->stream));
