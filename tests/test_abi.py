@@ -68,3 +68,39 @@ def _load_fresh(krt, path):
         return krt.load(path)
     finally:
         krt._lib = saved
+
+
+def test_binding_structs_match_header_layout(tmp_path):
+    """Every structure the binding mirrors has the header's size and the
+    header's offset for each of its fields (a C program built against
+    include/krt.h prints them; the binding's ctypes layout must agree)."""
+    import shutil
+    import subprocess
+    from paper_2608_09340_amd import krt
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = [krt.krt_grid_desc, krt.krt_line_desc, krt.krt_run_opts, krt.krt_tallies, krt.krt_levels_desc,
+               krt.krt_image_desc]
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "krt.h"', "int main(void) {"]
+    for S in structs:
+        name = S.__name__
+        lines.append(f'  printf("{name} sizeof %zu\\n", sizeof({name}));')
+        for fname, _ in S._fields_:
+            lines.append(f'  printf("{name} {fname} %zu\\n", offsetof({name}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    exe = tmp_path / "layout"
+    src.write_text("\n".join(lines) + "\n")
+    r = subprocess.run([cc, "-std=c11", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    got = {}
+    for row in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        sname, field, value = row.split()
+        got[(sname, field)] = int(value)
+    for S in structs:
+        name = S.__name__
+        assert got[(name, "sizeof")] == ctypes.sizeof(S), name
+        for fname, _ in S._fields_:
+            assert got[(name, fname)] == getattr(S, fname).offset, (name, fname)
