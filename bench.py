@@ -30,7 +30,8 @@ sys.path.insert(0, ROOT)
 # VALU issue slots per scattering of the plain transport, from the step list of
 # the method (one flight segment ending in an interaction, one resonant
 # scattering, its tallies).  Quarter-rate instructions (32x32->64 integer
-# multiply, transcendental) cost 4 slots.  Itemised in the design doc.
+# multiply, transcendental) cost 4 slots; the terms of each item are listed
+# beside it.
 LEDGER = {
     "philox_2_blocks": 2 * 10 * (2 * 4 + 4),     # 2 wide multiplies + 4 xor/add per round
     "uniform_maps_8": 8 * 3,
@@ -292,8 +293,8 @@ def main():
                     help="only run a device-to-device copy of MIB MiB (calibrates FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(packets shard with one int64 all-reduce of the tallies; see DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (packet ranges would "
+              "shard across GPUs, joined by one int64 all-reduce of the tallies)", file=sys.stderr)
         sys.exit(2)
 
     import torch
