@@ -1,18 +1,35 @@
 """Benchmark of the Monte Carlo line-transfer pass on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--packets N] [--workload sphere64]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--packets N] [--budget-s S]
+                    [--legs c0,c1,c2,c3,profile,cube]
 
-A step is one krt_mc_run over a batch of packets of the static-sphere workload
-(64^3 grid, radial line-centre depth 1e6, a = 4.7e-4, dipole phase, central
-point source, escaped spectrum 256 bins on [-80, 80), emissivity 64^3 x 32
-channels on [-24, 24) toward +x): emission, flights, resonant scatterings,
-int64 tallies and the FP32 finalise, with grid and tables already resident in
-HBM.  The default batch is the full 1e6 packets of that workload.  Warmup steps
-are full-size batches from a disjoint packet range.
+Headline workload: the turbulent cloud (128^3, lognormal density with
+sigma_ln rho = 1.5 from a P(k) ~ k^-4 Gaussian random field, solenoidal
+P(k) ~ k^-4 velocity of 3-D rms 3 v_th), density scaled so 30% of cells have a
+line-centre depth k0 dx in [1e2, ~1e5], one line a = 1e-3, Voigt volume source
+proportional to density, escaped spectrum 512 bins on [-64, 64), emissivity
+128^3 x 32 channels on [-16, 16) toward +x, 1e8 packets per step.
 
-Prints one JSON line: whole-job scatterings/s, the ALU roofline of the
-transport kernel (HIP-event duration of that kernel, from the library), and the
-FP64 CPU oracle timed on a bounded sample of the same workload.
+Before the timed region (not counted): the escape network is trained on the
+GPU from single-cell escapes the plain walk records, and the same workload is
+run twice with the plain random walk (packet ranges [0, N) and [2^40, 2^40+N))
+for the reference tallies, the plain throughput and the plain-vs-plain noise
+floor.  A step is one krt_mc_run of N packets with the learned escape
+(emission, flights, resonant scatterings, network calls in thick cells, int64
+tallies, FP32 finalise), inputs resident in HBM; step s runs packets
+[2^41 + s N, 2^41 + (s+1) N).  `value` is scatterings-equivalent per second:
+the plain walk's scatterings for N packets of this workload per learned step
+time.  The learned tallies of the first timed step are compared with the plain
+ones (spectrum and emissivity L1, emissivity total).
+
+The timed loop stops starting steps once the next one would end past
+--budget-s (warmup likewise past --warmup-budget-s): `steps` and `warmup` in
+the JSON line are the steps actually run.
+
+Prints one JSON line as soon as the headline is done: roofline of the learned
+transport kernel (HIP-event duration from the library), and the FP64 CPU oracle
+timed on a bounded sample of the same workload with the plain walk.  Optional
+legs (--legs) run after that line and print a second JSON line.
 """
 from __future__ import annotations
 
@@ -20,7 +37,6 @@ import argparse
 import json
 import os
 import platform
-import subprocess
 import sys
 import time
 
@@ -46,17 +62,20 @@ LEDGER = {
 LEDGER_DIPOLE = 4 * 4 + 6          # log, sqrt, exp, rcp of the dipole inversion + FMAs
 LEDGER_EMIS = 6 + 5 + 8 + 3 + 2 + 8  # camera projection, x_cam, channel, phase weight, fixed point, cache
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12  # 39.32 T lane-slots/s (non-packed 32-bit VALU)
+PEAK_MFMA_BF16_TFLOPS = 2500.0            # dense BF16 matrix cores
 
 
 def ledger_per_scatter(dipole: bool, emis: bool) -> int:
     return sum(LEDGER.values()) + (LEDGER_DIPOLE if dipole else 0) + (LEDGER_EMIS if emis else 0)
 
 
-# Sources compiled into the transport kernel; the HBM traffic measured by the
-# profiler (profiles/mc_transport_sphere64.md) is reported only while these are
-# byte-identical to the ones it was measured on.
+# Sources compiled into the transport kernels; HBM traffic measured by the
+# profiler is reported only while these are byte-identical to the ones the
+# counters were taken on.
 KERNEL_SOURCES = ["krt_transport.hip", "krt_device.h", "krt_kernels.h", "krt_mlp.h", "krt_internal.h"]
-PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "mc_transport_sphere64.md")
+PROFILES = os.path.join(ROOT, "profiles")
+PROFILE_SUMMARY = os.path.join(PROFILES, "mc_transport_sphere64.md")
+PROFILE_SUMMARY_LEARNED = os.path.join(PROFILES, "mc_transport_learned_cloud128.md")
 
 
 def kernel_source_sha256() -> str:
@@ -68,12 +87,13 @@ def kernel_source_sha256() -> str:
     return h.hexdigest()
 
 
-def profiled_traffic():
-    """HBM bytes per transport launch from the committed counter summary, or
-    None when the kernel sources changed since it was taken."""
+def profiled_traffic(path=None):
+    """HBM bytes per launch from a committed counter summary, or None when the
+    kernel sources changed since it was taken."""
+    path = path or PROFILE_SUMMARY
     try:
         kv = {}
-        for line in open(PROFILE_SUMMARY):
+        for line in open(path):
             if ":" in line and line.startswith("- "):
                 k, v = line[2:].split(":", 1)
                 kv[k.strip()] = v.strip().strip("`")
@@ -100,27 +120,29 @@ def cpu_info():
     return model, os.cpu_count() or 1
 
 
-def cpu_baseline(prob, seconds_target=40.0):
-    """The FP64 oracle as it stands, on all host cores, on a bounded sample."""
+def cpu_baseline(prob, seconds_target=20.0, workload=""):
+    """The FP64 oracle as it stands, on all host cores (at most 16, the box's
+    share), on a bounded sample of the same workload with the plain walk:
+    consecutive batches of packets, each sized from the rate so far, until
+    about `seconds_target` seconds of oracle work have run."""
     import oracle
     model, ncpu = cpu_info()
-    threads = ncpu
-    n = threads  # first: one packet per thread to size the sample
-    t = time.perf_counter()
-    r = oracle.mc_run(prob, n, seed=0, packet_offset=1 << 40, threads=threads)
-    dt = time.perf_counter() - t
-    if dt < seconds_target / 4:
-        n2 = int(max(n, min(64 * threads, n * seconds_target / max(dt, 1e-3) * 0.8)))
+    threads = max(1, min(ncpu, 16))
+    n_done, sc, dt = 0, 0, 0.0
+    n = 4 * threads  # first batch: a few packets per thread to measure the rate
+    while dt < 0.75 * seconds_target:
         t = time.perf_counter()
-        r = oracle.mc_run(prob, n2, seed=0, packet_offset=1 << 40, threads=threads)
-        dt = time.perf_counter() - t
-        n = n2
-    sc = r["counters"]["scatterings"]
-    log(f"cpu baseline: {n} packets in {dt:.1f} s")
+        r = oracle.mc_run(prob, n, seed=0, packet_offset=(1 << 42) + n_done, threads=threads)
+        dt += time.perf_counter() - t
+        sc += r["counters"]["scatterings"]
+        n_done += n
+        rate = n_done / max(dt, 1e-3)
+        n = int(max(threads, min(4096 * threads, rate * (seconds_target - dt))))
+    log(f"cpu baseline: {n_done} packets in {dt:.1f} s")
     return {"value": sc / dt, "unit": "scatterings/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} packets (ids from 2^40, seed 0) of the same workload, {sc} scatterings, "
+            "sample": f"{n_done} packets (ids from 2^42, seed 0) of {workload}, plain walk, {sc} scatterings, "
                       f"{dt:.1f} s on {threads} threads of {model}",
-            "packets_per_s": n / dt}
+            "packets_per_s": n_done / dt}
 
 
 def _agg_blocks(em, n, b=8):
@@ -129,72 +151,171 @@ def _agg_blocks(em, n, b=8):
     return em.reshape(b, f, b, f, b, f, nch).sum(axis=(1, 3, 5)).reshape(-1)
 
 
-def learned_escape_leg(ctx, n=128, packets=10_000_000, settings=((50.0, 16), (30.0, 16), (100.0, 8))):
-    """Turbulent cloud rescaled for the learned escape (n^3, 30% of cells with
-    line-centre depth >= 1e2): train the escape network on GPU-recorded
-    single-cell escapes, then run the same packets with the plain random walk
-    (twice, for the noise floor) and with the learned escape at each
-    (tau_R threshold, lanes a wave needs to call) setting.  Reports kernel
-    times, the speedup in scatterings-equivalent per second and the spectrum
-    and emissivity L1 of each learned run against the plain one; the first
-    setting is the headline."""
+def _l1(u, v):
+    import numpy as np
+    u = np.asarray(u, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    return float(np.abs(u - v).sum() / u.sum())
+
+
+C4_WORKLOAD = ("turbulent cloud 128^3 (lognormal density sigma_ln rho = 1.5 from a P(k)~k^-4 random field, "
+               "solenoidal P(k)~k^-4 velocity rms 3 v_th), density scaled so 30% of cells have line-centre "
+               "depth k0 dx in [1e2, ~1e5]; a = 1e-3, isotropic phase, Voigt volume source ~ density; "
+               "spectrum 512 bins [-64, 64), emissivity 128^3 x 32 channels [-16, 16) toward +x")
+
+
+def headline_c4(ctx, args):
+    """Plain vs learned escape on the cloud: training and plain references
+    before the timed region, then timed learned steps."""
     import numpy as np
     import torch
     from paper_2608_09340_amd import krt, workloads as W
-    from paper_2608_09340_amd.escape import train_escape
+    from paper_2608_09340_amd.escape import train_escape, DEFAULT_RUN, DEFAULT_LOG10_TAU
+    N = args.packets
+    prob = W.cloud_c4(n=128)
     t0 = time.perf_counter()
     krt.Transport(W.slab(10.0, 1e-3, 4), ctx=ctx)  # line tables for a = 1e-3
-    tr = train_escape(ctx, 0, seed=1, log10_tau=(1.0, 5.0))
+    tr = train_escape(ctx, 0, seed=1, log10_tau=DEFAULT_LOG10_TAU)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     hist = tr["hist"]
     del tr
-    log(f"learned escape: trained in {t_train:.1f} s")
-    T = krt.Transport(W.cloud_c4(n=n), ctx=ctx)
-    pa = T.run(packets, seed=0)
+    log(f"escape network trained in {t_train:.1f} s")
+    T = krt.Transport(prob, ctx=ctx)
+    pa = T.run(N, seed=0)
     ms_plain = ctx.krt_last_transport_ms()
-    pb = T.run(packets, seed=0, packet_offset=1 << 40)
+    log(f"plain reference: {ms_plain:.0f} ms")
+    pb = T.run(N, seed=0, packet_offset=1 << 40)
     ms_plain2 = ctx.krt_last_transport_ms()
+    log(f"plain repeat: {ms_plain2:.0f} ms")
     if pa["rc"] or pb["rc"]:
-        raise RuntimeError("learned-escape leg: plain runs failed")
+        raise RuntimeError("plain reference runs failed")
+    ea, eb = (_agg_blocks(r["emis_raw"].astype(np.float64), 128) for r in (pa, pb))
+    scat_plain = pa["counters"]["scatterings"]
+    run_kw = dict(DEFAULT_RUN)
 
-    def l1(u, v):
-        u = np.asarray(u, dtype=np.float64)
-        v = np.asarray(v, dtype=np.float64)
-        return float(np.abs(u - v).sum() / u.sum())
+    def step(s):
+        r = T.run(N, seed=0, packet_offset=(1 << 41) + s * N, escape_mode=1, **run_kw)
+        if r["rc"]:
+            raise RuntimeError(f"learned step failed rc={r['rc']} counters={r['counters']}")
+        return r, ctx.krt_last_transport_ms()
 
-    ea, eb = (_agg_blocks(r["emis_raw"].astype(np.float64), n) for r in (pa, pb))
-    sa = pa["counters"]["scatterings"]
-    runs = []
-    for tau_min, lanes in settings:
-        ml = T.run(packets, seed=0, escape_mode=1, esc_tau_min=tau_min, esc_min_lanes=lanes)
-        ms_mlp = ctx.krt_last_transport_ms()
-        if ml["rc"]:
-            raise RuntimeError("learned-escape leg: learned run failed")
-        em = _agg_blocks(ml["emis_raw"].astype(np.float64), n)
-        c = ml["counters"]
-        log(f"learned escape tau_R >= {tau_min:g}, {lanes} lanes: plain {ms_plain:.0f} ms, learned {ms_mlp:.0f} ms")
-        runs.append({"esc_tau_min": tau_min, "esc_min_lanes": lanes, "learned_kernel_ms": ms_mlp,
-                     "speedup": ms_plain / ms_mlp, "scatterings_equivalent_per_s": sa / (ms_mlp * 1e-3),
-                     "scatterings": c["scatterings"], "network_calls": c["mlp_calls"],
-                     "skipped_scatterings": c["skipped_scatterings"],
-                     "spectrum_L1": l1(pa["spec_raw"], ml["spec_raw"]), "emissivity_L1": l1(ea, em),
-                     "emissivity_total_ratio": float(em.sum() / ea.sum())})
-    head = runs[0]
+    warm = 0
+    tw = time.perf_counter()
+    while warm < args.warmup:
+        step(-1 - warm)
+        warm += 1
+        if time.perf_counter() - tw > args.warmup_budget_s:
+            break
+    torch.cuda.synchronize()
+    runs, kms = [], []
+    t_start = time.perf_counter()
+    while len(runs) < args.steps:
+        r, ms = step(len(runs))
+        runs.append(r)
+        kms.append(ms)
+        log(f"timed step {len(runs) - 1}: learned {ms:.0f} ms")
+        el = time.perf_counter() - t_start
+        if el + el / len(runs) > args.budget_s:
+            break
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    K = len(runs)
+    r0 = runs[0]
+    em = _agg_blocks(r0["emis_raw"].astype(np.float64), 128)
+    c = r0["counters"]
+    km = sum(kms) / K
+    # roofline of the learned transport kernel: plain scatterings it still runs
+    # on the VALU ledger, network evaluations on the BF16 matrix cores
+    calls = sum(r["counters"]["mlp_calls"] for r in runs) / K
+    scat_l = sum(r["counters"]["scatterings"] for r in runs) / K
+    valu = scat_l * ledger_per_scatter(False, True) / (km * 1e-3) / 1e12
+    mfma = calls * 2 * MLP_FLOP_PER_EVAL / (km * 1e-3) / 1e12
     return {
-        "workload": f"turbulent cloud {n}^3 (lognormal density sigma_ln=1.5, P(k)~k^-4 velocity rms 3, "
-                    f"70th-percentile cell depth 1e2), a=1e-3, Voigt volume source, {packets} packets",
-        "train_s": t_train, "train_loss_first_last": [float(hist[:5].mean()), float(hist[-200:].mean())],
-        "plain_kernel_ms": ms_plain, "plain_kernel_ms_repeat": ms_plain2, "learned_kernel_ms": head["learned_kernel_ms"],
-        "speedup": head["speedup"],
-        "plain_scatterings_per_s": sa / (ms_plain * 1e-3),
-        "scatterings_equivalent_per_s": head["scatterings_equivalent_per_s"],
-        "spectrum_L1": head["spectrum_L1"], "spectrum_L1_floor": l1(pa["spec_raw"], pb["spec_raw"]),
-        "emissivity_L1": head["emissivity_L1"], "emissivity_L1_floor": l1(ea, eb),
-        "emissivity_total_ratio": head["emissivity_total_ratio"],
-        "settings": runs,
-        "L1_definition": "sum |learned - plain| / sum plain; emissivity aggregated to 8^3 blocks x channels",
+        "value": scat_plain * K / wall, "K": K, "W": warm, "wall": wall,
+        "kernel_ms": km,
+        "roofline": {"bound": "alu", "achieved": valu, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
+                     "frac": valu / PEAK_VALU_TOPS, "traffic": profiled_traffic(PROFILE_SUMMARY_LEARNED),
+                     "kernel": "mc_transport_kernel<true, 768> (learned escape)",
+                     "ops_per_scattering": ledger_per_scatter(False, True),
+                     "mfma": {"achieved": mfma, "peak": PEAK_MFMA_BF16_TFLOPS, "unit": "TFLOP/s",
+                              "frac": mfma / PEAK_MFMA_BF16_TFLOPS,
+                              "flop_per_call": 2 * MLP_FLOP_PER_EVAL}},
+        "learned": {
+            "plain_kernel_ms": ms_plain, "plain_kernel_ms_repeat": ms_plain2,
+            "plain_scatterings": scat_plain, "plain_scatterings_per_s": scat_plain / (ms_plain * 1e-3),
+            "learned_kernel_ms": km, "learned_kernel_ms_steps": kms,
+            "speedup_kernel": ms_plain / km,
+            "scatterings_equivalent_per_s_kernel": scat_plain / (km * 1e-3),
+            "learned_scatterings_run": c["scatterings"], "network_calls": c["mlp_calls"],
+            "skipped_scatterings": c["skipped_scatterings"],
+            "spectrum_L1": _l1(pa["spec_raw"], r0["spec_raw"]),
+            "spectrum_L1_floor": _l1(pa["spec_raw"], pb["spec_raw"]),
+            "emissivity_L1": _l1(ea, em), "emissivity_L1_floor": _l1(ea, eb),
+            "emissivity_total_ratio": float(em.sum() / ea.sum()),
+            "L1_definition": "sum |x - plain| / sum plain over the 514 spectrum bins and over 8^3 blocks x 32 "
+                             "channels of emissivity; learned step 0 (packets 2^41 + [0, N)) against plain "
+                             "(packets [0, N)); floor = plain [0, N) against plain 2^40 + [0, N)",
+            "train_s": t_train, "train_loss_first_last": [float(hist[:5].mean()), float(hist[-200:].mean())],
+            "run_options": run_kw,
+        },
+        "prob": prob,
     }
+
+
+MLP_FLOP_PER_EVAL = 2 * (8 * 128 + 128 * 128 + 128 * 128 + 128 * 10)  # one sample through 8->3x128->10
+
+
+def sphere_c1_leg(ctx, packets=1_000_000):
+    """64^3 static sphere (tau0 = 1e6, a = 4.7e-4, dipole, central point source,
+    256-bin spectrum, 64^3 x 32-channel emissivity): one plain transport of
+    `packets` packets with its VALU roofline, then the imaging pass."""
+    from paper_2608_09340_amd import krt, workloads as W
+    prob = W.sphere_c1()
+    T = krt.Transport(prob, ctx=ctx)
+    r = T.run(packets, seed=0)
+    ms = ctx.krt_last_transport_ms()
+    if r["rc"]:
+        raise RuntimeError("sphere leg failed")
+    c = r["counters"]
+    lps = ledger_per_scatter(True, True)
+    ach = c["scatterings"] * lps / (ms * 1e-3) / 1e12
+    log(f"static sphere: {ms:.0f} ms")
+    T.image(axis=0)
+    im = []
+    for _ in range(5):
+        T.image(axis=0)
+        im.append(ctx.krt_last_image_ms())
+    nx, ny, nz = T.n
+    nb = T.ncell * T.nch * 4 + T.ncell * 4 + ny * nz * T.nch * 4  # emissivity, k0 (static), image
+    t_im = min(im) * 1e-3
+    return {"workload": "static uniform sphere 64^3, radial line-centre tau0=1e6, a=4.7e-4, dipole phase, "
+                        "central point source x=0, spectrum 256 bins [-80,80), emissivity 64^3 x 32 channels "
+                        f"[-24,24) toward +x, plain random walk, {packets} packets",
+            "kernel_ms": ms, "scatterings": c["scatterings"], "scatterings_per_s": c["scatterings"] / (ms * 1e-3),
+            "packets_per_s": packets / (ms * 1e-3),
+            "mean_scatterings_per_packet": c["scatterings"] / packets,
+            "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
+                         "frac": ach / PEAK_VALU_TOPS, "traffic": profiled_traffic(PROFILE_SUMMARY),
+                         "ops_per_scattering": lps},
+            "imaging": {"what": f"image toward +x, {ny}x{nz} pixels x {T.nch} channels", "kernel_ms": min(im),
+                        "roofline": {"bound": "hbm", "achieved": nb / t_im / 1e9, "peak": 8000.0, "unit": "GB/s",
+                                     "frac": nb / t_im / 8e12, "bytes_per_launch": nb}}}
+
+
+def slab_c0_leg(ctx, packets=10_000):
+    """1x1x32 static slab, tau0 = 1e3, a = 1e-2, plane source at x = 0, 200 bins."""
+    from paper_2608_09340_amd import krt, workloads as W
+    T = krt.Transport(W.slab_c0(), ctx=ctx)
+    T.run(packets, seed=0, packet_offset=1 << 40)
+    r = T.run(packets, seed=0)
+    ms = ctx.krt_last_transport_ms()
+    if r["rc"]:
+        raise RuntimeError("slab leg failed")
+    c = r["counters"]
+    return {"workload": f"static slab 1x1x32, tau0=1e3, a=1e-2, isotropic, plane source x=0, {packets} packets",
+            "kernel_ms": ms, "scatterings": c["scatterings"], "mean_scatterings_per_packet": c["scatterings"] / packets,
+            "scatterings_per_s": c["scatterings"] / (ms * 1e-3), "packets_per_s": packets / (ms * 1e-3)}
 
 
 def expanding_sphere_leg(ctx, packets=10_000_000):
@@ -215,16 +336,14 @@ def expanding_sphere_leg(ctx, packets=10_000_000):
         im.append(ctx.krt_last_image_ms())
     nb = T.ncell * T.nch * 4 + T.ncell * 8 + T.n[1] * T.n[2] * T.nch * 4  # emissivity, k0 + v_x, image
     t_im = min(im) * 1e-3
+    lps = ledger_per_scatter(False, True)
+    ach = c["scatterings"] * lps / (ms * 1e-3) / 1e12
     return {"workload": "expanding sphere 128^3, v = 20 r, tau0=1e5, a=1e-3, isotropic R_IIA, Voigt volume "
                         f"source, spectrum 512 bins, emissivity 128^3 x 64 channels, {packets} packets",
             "kernel_ms": ms, "scatterings": c["scatterings"], "scatterings_per_s": c["scatterings"] / (ms * 1e-3),
             "packets_per_s": packets / (ms * 1e-3), "crossings": c["crossings"],
-            # the same VALU ledger as the headline (isotropic, emissivity tally): this
-            # workload has no long-packet tail, so it shows the transport's bulk rate
-            "roofline": {"bound": "alu", "achieved": c["scatterings"] * ledger_per_scatter(False, True) / (ms * 1e-3) / 1e12,
-                         "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
-                         "frac": c["scatterings"] * ledger_per_scatter(False, True) / (ms * 1e-3) / 1e12 / PEAK_VALU_TOPS,
-                         "ops_per_scattering": ledger_per_scatter(False, True)},
+            "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
+                         "frac": ach / PEAK_VALU_TOPS, "ops_per_scattering": lps},
             "imaging": {"what": "image toward +x, 128x128 pixels x 64 channels", "kernel_ms": min(im),
                         "roofline": {"bound": "hbm", "achieved": nb / t_im / 1e9, "peak": 8000.0, "unit": "GB/s",
                                      "frac": nb / t_im / 8e12, "bytes_per_launch": nb}}}
@@ -254,41 +373,68 @@ def profile_mode_leg(ctx, packets=10_000_000):
     return res
 
 
-def lambda_leg(ctx, n=128, packets=10_000_000):
-    """One Lambda-iteration cycle on the 128^3 turbulent cloud with the 5-level
-    rotor: transport of each of the 4 lines with the mean-intensity tally, then
-    the FP64 level solve of every cell."""
+def lambda_leg(ctx, n=128, packets=10_000_000, iterations=10):
+    """Lambda iteration on the 128^3 turbulent cloud with the 5-level rotor:
+    `iterations` cycles of transport of each of the 4 lines with the
+    mean-intensity tally, then the FP64 level solve of every cell."""
     import torch
     from paper_2608_09340_amd import workloads as W
     from paper_2608_09340_amd.lambda_iter import LambdaIteration
     lam = LambdaIteration(W.cloud_c3(n=n), ctx)
-    runs = [lam.transport_line(l, packets, seed=l) for l in range(lam.nlines)]
     torch.cuda.synchronize()
     t = time.perf_counter()
-    lam._levels(lam.jbar)
+    hist = lam.iterate(iterations, packets, seed=0)
     torch.cuda.synchronize()
-    t_lev = time.perf_counter() - t
-    if any(r["rc"] for r in runs):
+    wall = time.perf_counter() - t
+    if any(any(h["rc"]) for h in hist):
         raise RuntimeError("lambda leg failed")
-    log(f"lambda iteration: {sum(r['kernel_ms'] for r in runs):.0f} ms transport")
-    return {"workload": f"turbulent cloud {n}^3, 5-level rotor, 4 lines, {packets} packets per line, "
-                        "one transport + level-solve cycle",
-            "transport_kernel_ms_per_line": [r["kernel_ms"] for r in runs],
-            "scatterings_per_line": [r["counters"]["scatterings"] for r in runs],
-            "destroyed_per_line": [r["counters"]["destroyed"] for r in runs],
-            "level_solve_ms": t_lev * 1e3, "cells": lam.ncell}
+    log(f"lambda iteration: {iterations} cycles in {wall:.1f} s")
+    return {"workload": f"turbulent cloud {n}^3, 5-level rotor, 4 lines, {packets} packets per line per cycle, "
+                        f"{iterations} cycles of transport + FP64 level solve",
+            "wall_s": wall, "transport_kernel_ms_per_cycle": [h["kernel_ms"] for h in hist],
+            "level_solve_ms_per_cycle": [h.get("levels_ms") for h in hist],
+            "max_rel_change_per_cycle": [h["max_rel_change"] for h in hist],
+            "scatterings_per_cycle": [h["scatterings"] for h in hist], "cells": lam.ncell}
+
+
+def cube_context_leg(ctx, packets=(1_000, 10_000, 100_000, 1_000_000, 10_000_000)):
+    """The paper's code-comparison cube (32^3, line-centre tau0 = 1e3 centre to
+    face, a = 4.73e-3, uniform volume source with a thermal Gaussian profile):
+    kernel time and scatterings per packet at the paper's packet counts, so
+    its packets/s can be turned into scatterings/s (context only)."""
+    from paper_2608_09340_amd import krt, workloads as W
+    T = krt.Transport(W.cube(), ctx=ctx)
+    out = []
+    for n in packets:
+        r = T.run(n, seed=0)
+        ms = ctx.krt_last_transport_ms()
+        if r["rc"]:
+            raise RuntimeError("cube leg failed")
+        c = r["counters"]
+        out.append({"packets": n, "kernel_ms": ms, "scatterings": c["scatterings"],
+                    "mean_scatterings_per_packet": c["scatterings"] / n,
+                    "packets_per_s": n / (ms * 1e-3), "scatterings_per_s": c["scatterings"] / (ms * 1e-3)})
+        log(f"cube {n} packets: {ms:.1f} ms")
+    return {"workload": "uniform cube 32^3, tau0=1e3, a=4.73e-3, volume source, Gaussian profile, plain walk",
+            "runs": out}
+
+
+LEGS = {"c0": slab_c0_leg, "c1": sphere_c1_leg, "c2": expanding_sphere_leg, "c3": lambda_leg,
+        "profile": profile_mode_leg, "cube": cube_context_leg}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed learned steps (at most; see --budget-s)")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--packets", type=int, default=1_000_000)
+    ap.add_argument("--packets", type=int, default=100_000_000)
+    ap.add_argument("--budget-s", type=float, default=60.0,
+                    help="no timed step is started that would end past this many seconds of timed work")
+    ap.add_argument("--warmup-budget-s", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-escape", action="store_true", help="skip the learned-escape comparison leg")
-    ap.add_argument("--no-extra", action="store_true", help="skip the expanding-sphere and Lambda-iteration legs")
-    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--legs", default="", help="comma-separated extra legs run after the headline line: "
+                                               + ",".join(LEGS))
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (calibrates FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
@@ -296,9 +442,14 @@ def main():
         print("bench.py runs on one GPU only: the library has no multi-GPU path (packet ranges would "
               "shard across GPUs, joined by one int64 all-reduce of the tallies)", file=sys.stderr)
         sys.exit(2)
+    legs = [s for s in args.legs.split(",") if s]
+    bad = [s for s in legs if s not in LEGS]
+    if bad:
+        print(f"unknown legs {bad}; choose from {sorted(LEGS)}", file=sys.stderr)
+        sys.exit(2)
 
     import torch
-    from paper_2608_09340_amd import krt, workloads as W
+    from paper_2608_09340_amd import krt
 
     if args.copy_probe:
         n = args.copy_probe * (1 << 20) // 4
@@ -310,86 +461,41 @@ def main():
         print(json.dumps({"copy_probe_bytes": n * 4}), flush=True)
         return
 
-    prob = W.sphere_c1()
     ctx = krt.Context(0)
-    T = krt.Transport(prob, ctx=ctx)
-    dipole = prob["line"]["phase"] == 1
-    emis = prob["tally"].get("emis_nch", 0) > 0
-
-    for w in range(args.warmup):
-        T.run(args.packets, seed=args.seed, packet_offset=(1 << 36) + w * args.packets)
-        log(f"warmup step {w} done: {ctx.krt_last_transport_ms():.0f} ms")
-    torch.cuda.synchronize()
-
-    scat = 0
-    kern_ms = []
-    emitted = 0
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        r = T.run(args.packets, seed=args.seed, packet_offset=s * args.packets)
-        if r["rc"] != 0:
-            raise RuntimeError(f"krt_mc_run rc={r['rc']} counters={r['counters']}")
-        scat += r["counters"]["scatterings"]
-        emitted += r["counters"]["emitted"]
-        kern_ms.append(ctx.krt_last_transport_ms())
-        log(f"timed step {s} done: {kern_ms[-1]:.0f} ms")
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-
-    # imaging pass over the step's emissivity toward the camera (+x)
-    T.image(axis=0)
-    img_ms = []
-    for _ in range(5):
-        T.image(axis=0)
-        img_ms.append(ctx.krt_last_image_ms())
-    nx, ny, nz = T.n
-    ncell, nch = T.ncell, T.nch
-    img_bytes = ncell * nch * 4 + ncell * 4 + ny * nz * nch * 4  # emissivity, k0 (static medium), image
-    img_t = min(img_ms) * 1e-3
-    log(f"imaging: {min(img_ms):.3f} ms")
-
-    lps = ledger_per_scatter(dipole, emis)
-    kms = sum(kern_ms) / len(kern_ms)
-    achieved = (scat / args.steps) * lps / (kms * 1e-3) / 1e12
+    h = headline_c4(ctx, args)
     out = {
         "metric": "scatterings/s on 1 MI355X, plain vs MLP-escape at spectrum L1<=2% vs oracle",
-        "value": scat / wall,
+        "value": h["value"],
         "unit": "scatterings/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
+        "steps": h["K"],
+        "warmup": h["W"],
+        "ms_per_step": h["wall"] * 1e3 / h["K"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "static uniform sphere 64^3, radial line-centre tau0=1e6, a=4.7e-4, "
-                               "dipole phase, central point source x=0, spectrum 256 bins [-80,80), "
-                               "emissivity 64^3 x 32 channels [-24,24) toward +x, plain random walk",
-                   "packets_per_step": args.packets, "grid": [64, 64, 64], "seed": args.seed,
-                   "mean_scatterings_per_packet": scat / max(emitted, 1)},
-        "packets_per_s": emitted / wall,
-        "transport_kernel_ms": kms,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
-                     "frac": achieved / PEAK_VALU_TOPS, "traffic": profiled_traffic(),
-                     "ops_per_scattering": lps},
+        "config": {"workload": C4_WORKLOAD + f", {args.packets} packets per step, learned escape "
+                                             "(plain walk below threshold); value = plain-walk scatterings "
+                                             "for the same packets per learned step time",
+                   "packets_per_step": args.packets, "grid": [128, 128, 128], "seed": 0,
+                   "network": "BF16 weights and activations, FP32 accumulation on MFMA",
+                   "steps_requested": args.steps, "warmup_requested": args.warmup,
+                   "budget_s": args.budget_s},
+        "packets_per_s": args.packets * h["K"] / h["wall"],
+        "transport_kernel_ms": h["kernel_ms"],
+        "roofline": h["roofline"],
+        "learned_vs_plain": h["learned"],
     }
-    out["imaging"] = {
-        "what": f"ray-traced image toward +x of the step's emissivity, {ny}x{nz} pixels x {nch} channels",
-        "kernel_ms": min(img_ms),
-        "roofline": {"bound": "hbm", "achieved": img_bytes / img_t / 1e9, "peak": 8000.0, "unit": "GB/s",
-                     "frac": img_bytes / img_t / 8e12, "bytes_per_launch": img_bytes},
-    }
-    if not args.no_extra:
-        out["expanding_sphere"] = expanding_sphere_leg(ctx)
-        out["profile_modes"] = profile_mode_leg(ctx)
-        out["lambda_iteration"] = lambda_leg(ctx)
-    if not args.no_escape:
-        out["learned_escape"] = learned_escape_leg(ctx)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob)
+        out["cpu_baseline"] = cpu_baseline(h["prob"], workload="the same cloud")
     print(json.dumps(out), flush=True)
+    if legs:
+        extra = {}
+        for name in legs:
+            extra[name] = LEGS[name](ctx)
+        print(json.dumps({"legs": extra}), flush=True)
 
 
 if __name__ == "__main__":

@@ -57,7 +57,7 @@ enum {
     KRT_NCOUNTERS = 16
 };
 /* bits of counters[KRT_C_STATUS] */
-enum { KRT_ST_NAN = 1, KRT_ST_STUCK = 2, KRT_ST_SATURATE = 4, KRT_ST_CANCEL = 8 };
+enum { KRT_ST_NAN = 1, KRT_ST_STUCK = 2, KRT_ST_SATURATE = 4 };
 
 typedef struct krt_ctx krt_ctx;
 
@@ -138,7 +138,9 @@ typedef struct {
     uint64_t packet_offset;    /* first packet id (resume / sharding) */
     uint64_t max_events;       /* per packet; 0 = unlimited (2^32 - 2) */
     int32_t escape_mode;       /* 0 = plain random walk; 1 = learned escape in thick cells (needs
-                                  krt_escape_init/train or put_weights; a in [1e-4, 1e-2]; no jbar) */
+                                  krt_escape_init/train or put_weights; a in [1e-4, 1e-2]; no jbar;
+                                  isotropic phase and no destruction field, else KRT_EINVAL: the
+                                  network is trained on isotropic re-emission without destruction) */
     int32_t wg_size;           /* launch geometry: threads per workgroup (0 = 1024 plain, 768
                                   learned; the learned kernel is built for 256 VGPRs at <= 512
                                   lanes, 168 at <= 768, 128 above) */
@@ -161,7 +163,7 @@ typedef struct {
                                   this many live lanes lets its idle lanes precompute the live
                                   packets' random draws (0 = 32, negative = never); the tallies
                                   are the same either way */
-    int32_t profile_mode;      /* opacity profile of the flights (Sec. 2.3.1, the paper's profile
+    int32_t profile_mode;      /* opacity profile of the flights (Sec. 2.2.1, the paper's profile
                                   modes; plain walk only): 0 tables in LDS (production); 1 the
                                   same tables read from global memory (identical tallies, an A/B
                                   of the table placement); 2 analytic blend of the Doppler core

@@ -231,3 +231,40 @@ def escape_record(n: int, tau_R: float, a: float, x_in: float, seed: int = 0, of
     L.orc_escape_record(int(n), float(tau_R), float(a), float(x_in), int(seed), int(offset),
                         int(threads or os.cpu_count() or 1), _ptr(out))
     return out
+
+
+# ---------------------------------------------------------------- finalise
+FOUR_PI = 4.0 * np.pi
+
+
+def finalize(spec=None, emis=None, jbar=None, *, n_packets, luminosity=1.0, spec_bins=None, channels=None,
+             cell_volume=None, emis_frac_bits=0, jbar_frac_bits=0):
+    """Step O7, the FP64 normalisation of the tallies (Sec. 2.3: the reductions
+    are FP64; Sec. 2.2.1 eq. scat-line: the emissivity is the scattered power
+    per unit volume, solid angle and frequency), as the plain definitions:
+
+      spectrum   L * count / (N dx_bin)                         per unit x
+      emissivity L * w 2^-F / (4 pi N V_cell dx_ch)             per volume, steradian, unit x
+      J-bar      L * s 2^-Fj / (4 pi N V_cell)                  s = sum dl H(a, x)/sqrt(pi)
+
+    N packets carry total luminosity L, so one packet carries L/N.  Raw tallies
+    may be FP64 weights (the oracle's own, F = 0) or fixed-point integers of
+    F fraction bits (values times 2^F); they are converted to FP64 before
+    scaling.  spec_bins = (nb, lo, hi), channels = (nch, lo, hi).  Returns a
+    dict of FP64 arrays for the tallies given."""
+    N = float(n_packets)
+    L = float(luminosity)
+    out = {}
+    if spec is not None:
+        nb, lo, hi = spec_bins
+        dxb = (float(hi) - float(lo)) / float(nb)
+        out["spec"] = np.asarray(spec, dtype=np.float64) * (L / (N * dxb))
+    if emis is not None:
+        nch, lo, hi = channels
+        dxc = (float(hi) - float(lo)) / float(nch)
+        w = np.asarray(emis, dtype=np.float64) * 2.0 ** (-int(emis_frac_bits))
+        out["emis"] = w * (L / (FOUR_PI * N * float(cell_volume) * dxc))
+    if jbar is not None:
+        s = np.asarray(jbar, dtype=np.float64) * 2.0 ** (-int(jbar_frac_bits))
+        out["jbar"] = s * (L / (FOUR_PI * N * float(cell_volume)))
+    return out

@@ -346,6 +346,13 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
     if (esc) {
         if (!c->mlp_ready) return fail(c, KRT_ESTATE, "escape_mode 1 needs trained escape weights");
         if (o->jbar) return fail(c, KRT_EINVAL, "escape_mode 1 does not tally the mean intensity");
+        // the network is trained on isotropic re-emission without destruction:
+        // the scatterings it skips would apply neither the dipole phase nor
+        // the survival probability (1 - eps)^N_s
+        if (c->lines[o->line].phase != KRT_PHASE_ISO)
+            return fail(c, KRT_EINVAL, "escape_mode 1 needs isotropic phase (line %d is dipole)", o->line);
+        if (c->grid.eps_dev)
+            return fail(c, KRT_EINVAL, "escape_mode 1 needs a grid without destruction (eps_dev is set)");
         double al = c->lines[o->line].a;
         if (al < 1e-4 * (1 - 1e-9) || al > 1e-2 * (1 + 1e-9))
             return fail(c, KRT_EINVAL, "learned escape covers a in [1e-4, 1e-2] (line a = %g)", al);

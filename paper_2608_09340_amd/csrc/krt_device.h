@@ -85,7 +85,7 @@ __device__ __forceinline__ float voigt_lds(const float *T, float xa) {
 // Analytic approximation of H(a, u) that blends the Doppler core exp(-u^2) and
 // the damping wing a / (sqrt(pi) (u^2 + a^2)) with the switch
 // w = (1 + tanh(2|u| - 2 u0)) / 2 centred at the crossing point u0 of the two
-// asymptotes (Sec. 2.3.1, the third profile mode).  Accurate in the core and
+// asymptotes (Sec. 2.2.1, the third profile mode).  Accurate in the core and
 // the wing, rough between them: offered to show why the opacity profile must
 // be the one the redistribution sampler assumes, not for production runs.
 __device__ __forceinline__ float voigt_analytic(float a, float u0, float ua) {

@@ -17,6 +17,14 @@ DEFAULT_STAGES = ((6000, 4096, 2e-3), (6000, 8192, 1e-3), (6000, 16384, 5e-4), (
                   (6000, 32768, 1.25e-4))
 
 
+# Run options of the learned escape on the benchmark cloud: network calls where
+# the cube about the scattering point is at least 50 line-centre mean free paths
+# deep, once 16 lanes of a wave ask.
+DEFAULT_RUN = {"esc_tau_min": 50.0, "esc_min_lanes": 16}
+# log10 tau_R range of the training records for that setting
+DEFAULT_LOG10_TAU = (1.0, 5.0)
+
+
 def train_escape(ctx: "krt.Context", line: int = 0, n_records: int = 8_000_000, seed: int = 1,
                  log10_tau=(2.0, 5.0), stages=DEFAULT_STAGES, record_offset: int = 0, lines=None) -> dict:
     """Record `n_records` escapes from cubes with log10 tau_R uniform in

@@ -1,0 +1,62 @@
+"""GPU (through the C ABI) vs the FP64 oracle: the finalised FP32 outputs
+(step a7) against the oracle's FP64 normalisation of the GPU's own raw int64
+tallies, and the gas-frame emission profiles packet by packet."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2608_09340_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("lum,norm", [(0.0, 0), (3.7e5, 0), (2.0, 123_457)])
+def test_finalised_outputs_equal_oracle_normalisation(gpu_ctx, lum, norm):
+    """spec = L spec_raw / (N dx_bin), emis = L emis_raw 2^-F / (4 pi N V dx_ch),
+    jbar = L jbar_raw 2^-Fj / (4 pi N V) (Sec. 2.3, FP64 reductions): the
+    library's FP32 outputs equal the oracle's FP64 normalisation of the same
+    raw integers, rounded to binary32, element by element (at most one unit
+    in the last place: the two evaluate the scale factor in different
+    orders); luminosity 0 means 1 and norm_packets 0 means n_packets."""
+    from paper_2608_09340_amd import krt
+    p = W.sphere(12, 20.0, 1e-2, phase=0, emis=(16, -6.0, 6.0), jbar=True, spec=(40, -10.0, 10.0))
+    T = krt.Transport(p, ctx=gpu_ctx)
+    N = 40_000
+    r = T.run(N, seed=3, luminosity=lum, norm_packets=norm, emis_frac_bits=18, jbar_frac_bits=34)
+    assert r["rc"] == 0
+    t = p["tally"]
+    vcell = (2.0 / 12) ** 3
+    f = oracle.finalize(spec=r["spec_raw"], emis=r["emis_raw"], jbar=r["jbar_raw"], n_packets=norm or N,
+                        luminosity=lum or 1.0, spec_bins=(t["spec_nbins"], t["spec_lo"], t["spec_hi"]),
+                        channels=(t["emis_nch"], t["ch_lo"], t["ch_hi"]), cell_volume=vcell,
+                        emis_frac_bits=18, jbar_frac_bits=34)
+    for name, got in (("spec", T.spec), ("emis", T.emis), ("jbar", T.jbar)):
+        g = got.cpu().numpy().astype(np.float64).reshape(-1)
+        want = f[name].reshape(-1)
+        w32 = want.astype(np.float32).astype(np.float64)
+        ulp = np.spacing(np.abs(w32).astype(np.float32)).astype(np.float64)
+        assert np.all(np.abs(g - w32) <= ulp), (name, np.max(np.abs(g - w32) / np.maximum(ulp, 1e-300)))
+        assert np.count_nonzero(want) > 0.3 * want.size, name
+
+
+@pytest.mark.parametrize("profile,a", [(W.PROF_VOIGT, 1e-2), (W.PROF_VOIGT, 4.7e-4), (W.PROF_GAUSS, 4.73e-3)])
+def test_emission_profile_per_packet(gpu_ctx, profile, a):
+    """Emission frequencies (Sec. 2.1: Voigt as a Gaussian of variance 1/2 plus
+    a Cauchy of half-width a; the thermal Gaussian of the code-comparison
+    cube): in a zero-opacity box every packet leaves with its gas-frame
+    emission frequency, and the GPU and the oracle draw it from the same
+    Philox words, so they agree packet by packet to FP32 rounding."""
+    from paper_2608_09340_amd import krt
+    n = 8
+    p = W._problem((n, n, n), (-1.0,) * 3, (1.0,) * 3, (0, 0, 0), np.zeros(n ** 3), a,
+                   emis=np.ones(n ** 3, dtype=np.float32),
+                   source={"kind": W.SRC_VOLUME, "pos": (0.0, 0.0, 0.0), "profile": profile, "x0": 0.0},
+                   tally={"spec_nbins": 64, "spec_lo": -8.0, "spec_hi": 8.0})
+    T = krt.Transport(p, ctx=gpu_ctx)
+    N = 100_000
+    g = T.run(N, seed=9, packet_log=True)["packet_log"][:, 0].astype(np.float64)
+    o = oracle.mc_run(p, N, seed=9, packet_log=True)["packet_log"][:, 0]
+    d = np.abs(g - o) / (1.0 + np.abs(o))
+    assert np.percentile(d, 99.9) < 2e-5 and np.median(d) < 1e-6, (np.percentile(d, 99.9), np.median(d))

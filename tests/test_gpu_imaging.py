@@ -166,7 +166,7 @@ def test_thin_moving_slab_image_closed_form(gpu_ctx):
 
 @pytest.mark.parametrize("tau0", [1e4, 1e5])
 def test_slab_image_peaks_neufeld(gpu_ctx, tau0):
-    """Sec. 3.5 imaging of thick profiles: a static slab (|z| <= 1, periodic in
+    """Sec. 3.4 imaging of thick profiles: a static slab (|z| <= 1, periodic in
     x and y, line-centre depth tau0 midplane to face, a = 0.01, plane source at
     z = 0) imaged face-on; the image's blue and red peaks lie within 10% of the
     +-1.066 (a tau0)^(1/3) of Neufeld's solution, and the image is symmetric."""

@@ -1,4 +1,4 @@
-"""The paper's opacity-profile modes as ablations of the plain walk (Sec. 2.3.1):
+"""The paper's opacity-profile modes as ablations of the plain walk (Sec. 2.2.1):
 tables read from global memory instead of LDS give bit-identical tallies, and
 the analytic blended profile of the third mode, evaluated on the device,
 follows its definition, is accurate in the core and the far wing but not in
