@@ -91,6 +91,10 @@ typedef struct {
     const float *vel_dev;      /* [3][ncell] bulk velocity / b (SoA), or NULL = static */
     const float *eps_dev;      /* [n_lines][ncell] destruction probability, or NULL = 0 */
     const float *emis_dev;     /* [n_lines][ncell] volume emission weights, or NULL */
+    const float *kabs_dev;     /* [ncell] grey absorption coefficient (dust; units of k0), or NULL:
+                                  it adds to every line's flight opacity, and an interaction is an
+                                  absorption (packet destroyed) with probability
+                                  kabs / (k0 H(a, x) + kabs), else a line scattering (Sec. 3.2) */
     /* Per-cell temperature as classes (frequencies are in units of the local
      * Doppler width, Sec. 2.1): tclass_dev [ncell] class of each cell, or NULL
      * (every cell at the reference width b_ref, the default).  Class k has
@@ -139,8 +143,9 @@ typedef struct {
     uint64_t max_events;       /* per packet; 0 = unlimited (2^32 - 2) */
     int32_t escape_mode;       /* 0 = plain random walk; 1 = learned escape in thick cells (needs
                                   krt_escape_init/train or put_weights; a in [1e-4, 1e-2]; no jbar;
-                                  isotropic phase and no destruction field, else KRT_EINVAL: the
-                                  network is trained on isotropic re-emission without destruction) */
+                                  isotropic phase and no destruction or absorption field, else
+                                  KRT_EINVAL: the network is trained on isotropic re-emission without
+                                  either) */
     int32_t wg_size;           /* launch geometry: threads per workgroup (0 = 1024 plain, 768
                                   learned; the learned kernel is built for 256 VGPRs at <= 512
                                   lanes, 168 at <= 768, 128 above) */
@@ -149,16 +154,17 @@ typedef struct {
     int32_t jbar_frac_bits;    /* fraction bits of the mean-intensity tally (0 = 36) */
     uint64_t norm_packets;     /* packets for the FP32 normalisation (0 = n_packets) */
     double luminosity;         /* photons/s carried by all N packets; scales the FP32 outputs (0 = 1) */
-    double esc_tau_min;        /* learned escape only where k0 R >= this (0 = 100) */
+    double esc_tau_min;        /* learned escape only at scattering points at least this line-centre
+                                  depth below the nearest face of their cell (0 = 3) */
+    double esc_cell_tau_min;   /* ... and only in cells of line-centre depth k0 dx at least this
+                                  (0 = 100); both are raised to the smallest values the network's
+                                  training records covered */
     int32_t esc_min_lanes;     /* network call when at least this many lanes of a wave ask (0 = 8).
                                   Which scatterings take the network then depends on the packets
                                   sharing a wave, so escape_mode = 1 tallies are statistically,
                                   not bitwise, independent of launch geometry */
     int32_t esc_tail_lanes;    /* as esc_min_lanes once the packet pool is exhausted (0 = 1):
                                   the wave then lives only as long as its slowest packet */
-    int32_t esc_evals;         /* reserved, must be 0: a learned escape takes two network
-                                  evaluations (exit frequency, point and count; then the exit
-                                  direction given the exit point) */
     int32_t tail_lanes;        /* plain transport: once the pool is exhausted, a wave with at most
                                   this many live lanes lets its idle lanes precompute the live
                                   packets' random draws (0 = 32, negative = never); the tallies
@@ -253,13 +259,16 @@ float krt_last_image_ms(const krt_ctx *ctx);
  * absorption rate), stimulated emission (g_l/g_u) Gamma_l, collisions
  * Cd[u][l] * ncoll downward and (g_u/g_l) exp(-(E_u - E_l)) Cd ncoll upward
  * (detailed balance; E in units of kT); the last equation is replaced by
- * sum_i n_i = ntot.  Outputs k0_l = n_l sigma0_l and
+ * sum_i n_i = ntot.  Outputs k0_l = n_l sigma0_l,
  * eps_l = C_u,tot / (A[u][l] + C_u,tot) with C_u,tot the total collisional
- * rate out of level u = l+1.  Host arrays: E[nl], g[nl], A[nl*nl], Cd[nl*nl],
+ * rate out of level u = l+1, the emission n_u A_ul per unit volume and the
+ * line power (cell volume x sum of n_u A_ul): the source of the Lambda
+ * iteration, frozen at the collisional-equilibrium populations (Sec. 2.1.3).  Host arrays: E[nl], g[nl], A[nl*nl], Cd[nl*nl],
  * sigma0[nl-1].  The device arrays hold `ncell` cells each; the call is
  * independent of the uploaded grid (it may precede krt_grid_upload, and the
  * caller sizes every device array for `ncell`).  Errors: KRT_EINVAL (nl
- * outside 2..8, ncell outside 1..2^31-1, NULL arrays, non-finite constants). */
+ * outside 2..8, ncell outside 1..2^31-1, NULL arrays, non-finite constants,
+ * lum_out without a finite cell_volume > 0). */
 typedef struct {
     int32_t n_levels;
     int64_t ncell;                           /* cells in every device array */
@@ -267,81 +276,105 @@ typedef struct {
     const double *ncoll_dev, *ntot_dev;      /* device [ncell] */
     double *pops_dev;                        /* device [ncell][nl], written */
     float *k0_out_dev, *eps_out_dev;         /* device [nl-1][ncell], written (may be NULL) */
+    float *emis_out_dev;                     /* device [nl-1][ncell], written (may be NULL): n_u A_ul,
+                                                the line's spontaneous emission per unit volume */
+    double cell_volume;                      /* volume of one cell (needed with lum_out) */
+    double *lum_out;                         /* host [nl-1], written (may be NULL): cell_volume times
+                                                the sum over cells of n_u A_ul, FP64 in a fixed
+                                                order (the line's total power) */
 } krt_levels_desc;
 int krt_levels_update(krt_ctx *ctx, const krt_levels_desc *desc,
                       const float *jbar_dev /* [nl-1][ncell], NULL = no radiation */);
 
 /* ------------------------------------------------------- learned escape --- */
-/* A small network (8 -> 3 x 128 SiLU -> 10, BF16 weights and activations, FP32
- * accumulation on MFMA) proposes, at a scattering inside a cell whose
- * line-centre depth over the distance R to the nearest cell face is
- * tau_R = k0 R >= esc_tau_min, where a photon leaves the cube of half-width R
- * centred there: exit frequency, exit point on the exit face, exit direction,
- * and the expected number of scatterings it skipped.  The paper itself
- * propagates every photon through the full optical depth (Sec. 2.3.2,
- * Sec. 4.1); this proposal is the accelerated alternative it points to for
- * extreme depths, and the plain random walk remains the fallback (below
- * threshold, gas-frame |x| > 2, a outside [1e-4, 1e-2]); above tau_R = 1e5 the cube is
- * shrunk to that depth.
- * Inputs (log10 tau_R, log10 a, x_in, u_a, u_b, w, r, flag), in two kinds of
- * evaluation: marginal (flag 0; w = u_c, r ignored) at three independent
- * quantile levels, and conditional (flag 1; w = x_out) at the sampled exit
- * frequency and the exit point's distance r from the face centre, because
- * photons leaving near an edge travel more obliquely and away from the centre
- * and wing photons leave closer to the normal.  Marginal outputs: 0 quantile at u_a of
- * x_out given x_out >= 0; 1, 2 quantiles at u_b, u_c of the exit point (s, t);
- * 4 ln E[N_s | tau_R, a, x_in]; 5 quantile at u_a of ln <x^2>; 6 logit
- * P(x_out >= 0); 7 quantile at u_a of -x_out given x_out < 0.  Conditional
- * outputs: 3 quantile at u_a of the exit cosine mu to the face normal; 8
- * quantile at u_b of the angle alpha in [0, pi] between the exit direction's
- * tangential part and the exit point's offset (s, t) (its sign is drawn
- * uniformly).  Output 9 is unused.  The bimodal exit frequency is drawn as a
- * two-component mixture: side from output 6, magnitude from output 0 or 7.
- * Losses: pinball for the quantiles (0 and 7 only on records of their side),
- * log-deviance e^d - 1 - d (d = ln N_s - output) for output 4, logistic for
- * output 6; trained on single-cell escapes run by the plain transport
- * arithmetic, a quarter of the rows conditional.  Parameters: kNParams =
- * 35466 FP32 master values plus 280 constants: target normalisation mean[10],
- * scale[10], 256 additive calibration terms of ln E[N_s], then the range
- * (min, max) of log10 a over the records the normalisation was fitted on and
- * 2 floats of padding.  krt_mc_run refuses escape_mode 1 for a line whose
- * log10 a lies outside that range by more than 0.01 (KRT_EINVAL): the network
- * is not used at damping values it has not seen.  The calibration terms are one per bin of
- * (log10 tau_R in 32 bins of 0.125 over [1, 5], clamped; |x_in| in 8 bins with
- * width 0.25 over [0, 2), the last also taking larger |x_in|), index = tau bin * 8
- * + x bin.  Beyond |x_in| = 2 the mean count is a steep mixture of photons that
- * leave at once and photons redistributed into the core, which the network does
- * not resolve; wing photons take plain scatterings until they are back in the
- * core.
+/* A small network (24 -> 3 x 128 SiLU -> 16, BF16 weights and activations,
+ * FP32 accumulation on MFMA) replaces the random walk of a photon inside one
+ * homogeneous cubic cell: at a scattering in a cell whose line-centre depth
+ * k0 dx is at least esc_cell_tau_min, at least esc_tau_min (line-centre) below
+ * the cell's nearest face and with gas-frame |x| <= 2, one sample gives where
+ * the photon leaves the cell (exit face, point on it, direction, frequency)
+ * and the expected number of scatterings it skipped, whose emissivity is
+ * deposited in the cell.  The paper itself propagates every photon through the
+ * full optical depth (Sec. 2.3.2, Sec. 4.1); this proposal is the accelerated
+ * alternative it points to for extreme depths, and the plain random walk
+ * remains the fallback (thin cells, shallow points, wing photons, a outside
+ * [1e-4, 1e-2], non-cubic cells, and anything outside the training records'
+ * ranges).
+ *
+ * Conditions are taken in the cell's reduced frame (its 48 symmetries and
+ * x -> -x): the start point's offsets from the cell centre in half-widths,
+ * absolute values sorted ascending (q0 <= q1 <= q2, axis 2 toward the nearest
+ * face), the incoming direction reflected and permuted alike, |x_in| (the exit
+ * frequency takes x_in's sign), tau_c = k0 dx / 2 (line-centre depth centre to
+ * face) and depth = tau_c (1 - q2).  Exit face F = 2 axis + (outward normal
+ * along +axis) in that frame; exit offsets ys, yt = (exit point - the start
+ * point's projection onto the face) along the two axes following the face
+ * axis cyclically, over the start point's distance to the face's plane; exit
+ * cosine mu to the outward normal; alpha in [0, pi] the angle between the
+ * exit direction's tangential part and that offset (its sign is drawn
+ * uniformly).  Inputs (normalised): (log10 tau_c - 3)/1.2, log10 a + 3,
+ * |x_in| - 1, 2 q - 1 (3), (log10 depth - 2)/1.2, incoming direction (3), four
+ * quantile levels as logit(u)/4, a flag (0 marginal, 1 conditional), and for
+ * conditional rows x_out/4 and the one-hot exit face.  A call takes two
+ * evaluations: marginal (outputs 0-5 exit-face logits, 6 logit P(x_out >= 0),
+ * 7/8 quantile of |x_out| on either side at u_a, 9 ln E[N_s], 10 quantile of
+ * ln <x^2> at u_b), then conditional on the sampled face and x_out (11, 12
+ * quantiles of ys, yt at u_a, u_b; 13 of mu at u_c; 14 of alpha at u_d).
+ * Losses: softmax cross-entropy (face), logistic (side), pinball (quantiles),
+ * log-deviance e^d - 1 - d, d = ln N_s - output, for output 9; a third of the
+ * training rows are conditional.
+ *
+ * Parameters: kNParams = 38288 FP32 master values, then 296 constants: target
+ * mean[16] and scale[16], 256 additive calibration terms of ln E[N_s] (per bin
+ * of log10 tau_c in 8 bins of 0.5 over [1, 5), log10 depth in 8 bins of 0.5
+ * over [0, 4) and |x_in| in 4 bins of 0.5 over [0, 2), ends clamped; index =
+ * (tau bin * 8 + depth bin) * 4 + x bin), then the training records' ranges:
+ * log10 a (min, max), log10 tau_c (min, max), the smallest log10 depth, three
+ * floats of padding.  krt_mc_run refuses escape_mode 1 for a line whose log10 a
+ * lies outside the a range by more than 0.01 (KRT_EINVAL), and makes no call
+ * outside the tau_c range or above the smallest depth.
  *
  * krt_escape_init: He-uniform parameters from Philox(seed), Adam state zeroed.
- * krt_escape_record: 1 <= n <= 2^31 single-cell escapes for line `line`, log10 tau_R uniform
- *   in [lo, hi], x_in fixed (x_fixed = 1) or 1/2 N(0, 1/2) + 1/2 U[-3, 3];
- *   samples_dev [n][11] FP32: (log10 tau_R, log10 a, x_in, x_out, s, t, mu,
- *   ln N_s, ln <x^2>, valid, alpha).
- * krt_escape_fit_norm: target mean / scale and the log10 a range from valid
- *   records; clears the calibration.
- * krt_escape_calibrate: n < 2^30 records; per (log10 tau_R, |x_in|) bin with at
- *   least 100 valid records with |x_in| <= 2,
- *   the calibration term ln(sum N_s / sum exp(network ln E[N_s])) over the
- *   records (marginal rows, quantile levels drawn per record), so that the
- *   predicted mean count is unbiased bin by bin; other bins get 0.
+ * krt_escape_record: 1 <= n <= 2^31 whole-cell walks for line `line` (ids
+ *   [offset, offset + n), Philox key seed), conditions from *cond:
+ *   log10 tau_c uniform in [log10_tau_lo, log10_tau_hi] (within [0, 6]); then
+ *   either (fixed = 0) |x_in| from 1/2 |N(0, 1/2)| + 1/2 U[0, 3], log10 depth
+ *   uniform in [log10_depth_lo, log10 tau_c], q0, q1 uniform in [0, q2] and an
+ *   isotropic incoming direction, or (fixed = 1) the given x_in >= 0 and
+ *   0 <= q0 <= q1 <= q2 < 1, with n_in (unit) or isotropic directions
+ *   (iso_dir = 1).  samples_dev [n][20] FP32: (log10 tau_c, log10 a, |x_in|,
+ *   q0, q1, q2, log10 depth, n_in (3), F, ys, yt, mu, alpha, x_out, ln N_s,
+ *   ln <x^2>, valid, 0); a walk past 2e7 scatterings is stored invalid.
+ * krt_escape_fit_norm: target mean / scale and the training ranges from the
+ *   valid records; clears the calibration.
+ * krt_escape_calibrate: n < 2^30 records; per calibration bin with at least
+ *   100 valid records with |x_in| <= 2, the term ln(sum N_s / sum exp(network
+ *   ln E[N_s])) over the records (marginal rows, quantile levels drawn per
+ *   record), so that the predicted mean count is unbiased bin by bin; other
+ *   bins get 0.
  * krt_escape_grad: gradient of the mean loss over the batch given by
- *   idx_dev [batch] (record indices, 1 <= batch <= 2^20) and u_dev [batch][4] = (u_a, u_b, u_c,
- *   1 for a conditional row else 0); grad_out_dev [35466], loss_out_dev [1]
- *   (may be NULL).
+ *   idx_dev [batch] (record indices, 1 <= batch <= 2^20) and u_dev [batch][5]
+ *   = (u_a, u_b, u_c, u_d, 1 for a conditional row else 0); grad_out_dev
+ *   [38288], loss_out_dev [1] (may be NULL).
  * krt_escape_train: `steps` Adam steps (lr, betas 0.9/0.999) on random batches
  *   (Philox(seed)) of 1 <= batch <= 2^20 out of n < 2^31 records;
  *   loss_hist_dev [steps] or NULL.
- * krt_escape_get_weights / put_weights: [35466 + 280] FP32 device buffers.
- * krt_escape_forward: in_dev [n][8] raw (log10 tau_R, log10 a, x_in, u_a, u_b,
- *   u_c or (flag 1) x_out, r, flag) -> out_dev [n][10] in physical units (output 6 as a logit,
- *   output 4 with its calibration term); n < 2^30.
+ * krt_escape_get_weights / put_weights: [38288 + 296] FP32 device buffers.
+ * krt_escape_forward: in_dev [n][17] raw (log10 tau_c, log10 a, |x_in|, q0,
+ *   q1, q2, log10 depth, n_in (3), u_a, u_b, u_c, u_d, flag, x_out, F) ->
+ *   out_dev [n][16] in physical units (logits as logits, output 9 with its
+ *   calibration term); n < 2^30.
  * Errors: KRT_EINVAL (sizes, ranges), KRT_ESTATE (no init / no tables). */
+typedef struct {
+    double log10_tau_lo, log10_tau_hi;  /* log10 tau_c range */
+    double log10_depth_lo;              /* lower end of log10 depth (fixed = 0), in [-2, 6] */
+    int32_t fixed;                      /* 1: every walk starts from x_in, q, n_in below */
+    int32_t iso_dir;                    /* with fixed: isotropic incoming directions */
+    double x_in, q[3], n_in[3];
+} krt_escape_cond;
 int krt_escape_init(krt_ctx *ctx, uint64_t seed);
 int krt_escape_record(krt_ctx *ctx, int32_t line, uint64_t n, uint64_t seed, uint64_t offset,
-                      double log10_tau_lo, double log10_tau_hi, int32_t x_fixed, double x_in,
-                      float *samples_dev);
+                      const krt_escape_cond *cond, float *samples_dev);
 int krt_escape_fit_norm(krt_ctx *ctx, const float *samples_dev, uint64_t n);
 int krt_escape_calibrate(krt_ctx *ctx, const float *samples_dev, uint64_t n);
 int krt_escape_grad(krt_ctx *ctx, const float *samples_dev, const int32_t *idx_dev, const float *u_dev,

@@ -35,6 +35,7 @@ class OrcProblem(C.Structure):
     _fields_ = [
         ("n", C.c_int32 * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("bc", C.c_int32 * 3),
         ("k0", C.c_void_p), ("vel", C.c_void_p), ("eps", C.c_void_p), ("emis", C.c_void_p), ("bratio", C.c_void_p),
+        ("kabs", C.c_void_p),
         ("a", C.c_double), ("phase", C.c_int32), ("source", C.c_int32), ("src_pos", C.c_double * 3),
         ("src_dir", C.c_double * 3),
         ("src_profile", C.c_int32), ("src_x0", C.c_double),
@@ -135,6 +136,8 @@ def mc_run(prob: dict, n_packets: int, seed: int = 0, packet_offset: int = 0,
     vel = None if vel is None else np.ascontiguousarray(vel, dtype=np.float32).reshape(3, ncell)
     eps = g.get("eps")
     eps = None if eps is None else np.ascontiguousarray(eps, dtype=np.float32).reshape(-1)
+    kabs = g.get("kabs")
+    kabs = None if kabs is None else np.ascontiguousarray(kabs, dtype=np.float32).reshape(-1)
     emis = g.get("emis")
     emis = None if emis is None else np.ascontiguousarray(emis, dtype=np.float32).reshape(-1)
     P = OrcProblem()
@@ -145,6 +148,7 @@ def mc_run(prob: dict, n_packets: int, seed: int = 0, packet_offset: int = 0,
     P.k0 = k0.ctypes.data
     P.vel = None if vel is None else vel.ctypes.data
     P.eps = None if eps is None else eps.ctypes.data
+    P.kabs = None if kabs is None else kabs.ctypes.data
     P.emis = None if emis is None else emis.ctypes.data
     # per-cell Doppler width b_cell / b_ref: an explicit per-cell array, or
     # temperature classes (class index per cell and the ratio of each class)
@@ -214,22 +218,35 @@ def levels_solve(E, g, A, Cd, ncoll, ntot, gamma=None) -> np.ndarray:
     return pops
 
 
-# ---------------------------------------------------------- single-cell escape
-def escape_record(n: int, tau_R: float, a: float, x_in: float, seed: int = 0, offset: int = 0,
-                  threads: int | None = None) -> np.ndarray:
-    """Plain FP64 single-cell escapes (reference for the learned escape); records
-    [log10 tau_R, log10 a, x_in, x_out, s, t, mu, ln N_s, ln <x^2>, valid, alpha],
-    alpha the angle between the exit direction's tangential part and the exit
-    point's offset from the face centre."""
+# ---------------------------------------------------------- whole-cell escape
+CELL_REC = 20
+(R_LT, R_LA, R_X, R_Q0, R_Q1, R_Q2, R_LD, R_N0, R_N1, R_N2, R_FACE, R_YS, R_YT, R_MU, R_ALPHA, R_XOUT,
+ R_LOGN, R_LOGX2, R_VALID) = range(19)
+
+
+def cell_escape_record(n: int, tau_c: float, a: float, x_in: float, q, n_in=None, seed: int = 0,
+                       offset: int = 0, threads: int | None = None) -> np.ndarray:
+    """Plain FP64 whole-cell escapes (reference for the learned escape): the
+    photon scatters at q inside the cube [-1, 1]^3 of line-centre depth tau_c
+    from centre to face and walks until it leaves.  Returns [n, 20] records
+    (columns R_*): the condition (log10 tau_c, log10 a, x_in, q, log10 depth,
+    n_in), the exit face 2 axis + (normal along +axis), the exit point's
+    offsets from q's projection over q's distance to the face plane, the exit
+    cosine mu, the angle alpha between the tangential direction and that
+    offset, x_out, ln N_s, ln <x^2> and a valid flag."""
     L = lib()
-    if not hasattr(L, "_esc_set"):
-        L.orc_escape_record.argtypes = [C.c_int64, C.c_double, C.c_double, C.c_double, C.c_uint64,
-                                        C.c_uint64, C.c_int, C.c_void_p]
-        L.orc_escape_record.restype = C.c_int
-        L._esc_set = True
-    out = np.zeros((n, 11), dtype=np.float64)
-    L.orc_escape_record(int(n), float(tau_R), float(a), float(x_in), int(seed), int(offset),
-                        int(threads or os.cpu_count() or 1), _ptr(out))
+    if not hasattr(L, "_cell_set"):
+        L.orc_cell_escape_record.argtypes = [C.c_int64, C.c_double, C.c_double, C.c_double, C.c_void_p,
+                                             C.c_void_p, C.c_uint64, C.c_uint64, C.c_int, C.c_void_p]
+        L.orc_cell_escape_record.restype = C.c_int
+        L._cell_set = True
+    qq = np.ascontiguousarray(q, dtype=np.float64).reshape(3)
+    nn = None if n_in is None else np.ascontiguousarray(n_in, dtype=np.float64).reshape(3)
+    out = np.zeros((n, CELL_REC), dtype=np.float64)
+    rc = L.orc_cell_escape_record(int(n), float(tau_c), float(a), float(x_in), _ptr(qq), _ptr(nn), int(seed),
+                                  int(offset), int(threads or os.cpu_count() or 1), _ptr(out))
+    if rc != 0:
+        raise ValueError("cell_escape_record needs |q_k| < 1")
     return out
 
 

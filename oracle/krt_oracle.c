@@ -24,6 +24,9 @@
  *     x_out = x_in + u_par (g-1) + u_perp sin(gamma) (eq. riia-scatter).
  *     Outgoing direction isotropic (Sec. 2.1.2) or dipole (3/8)(1+g^2).
  *   - Collisional destruction with probability eps per scattering (eq. eps).
+ *   - Optional grey absorption (dust) per cell added to the flight opacity;
+ *     an interaction is an absorption with probability kabs / (k0 H + kabs)
+ *     (Sec. 3.2, the dusty slab).
  *   - Tallies: escaped spectrum, scattering counts, the camera-directed
  *     velocity-resolved scattering emissivity per (cell, channel)
  *     (Sec. 2.2.1, eq. scat-line; collision estimator, see below) and the
@@ -297,6 +300,7 @@ typedef struct {
     const float *eps;          /* [ncell], may be NULL */
     const float *emis;         /* [ncell] volume emission weights, may be NULL */
     const float *bratio;       /* [ncell] Doppler width b_cell / b_ref, may be NULL (all 1) */
+    const float *kabs;         /* [ncell] grey absorption coefficient (dust, units of k0), may be NULL */
     double a;                  /* damping at b_ref; a cell's is a b_ref / b_cell */
     int32_t phase;             /* 0 isotropic, 1 dipole */
     int32_t source;            /* 0 point, 1 plane z = src_pos[2], 2 volume, 3 beam */
@@ -417,7 +421,8 @@ static void run_packet(worker_t *W, uint64_t pid)
             double k0 = P->k0[cl];
             double xc = (x - (n[0] * vc[0] + n[1] * vc[1] + n[2] * vc[2])) * sc;
             double H = (k0 > 0.0) ? orc_voigt_H(ac, xc) : 0.0;
-            double kap = k0 * H;
+            /* line opacity plus the cell's grey absorption (Sec. 3.2) */
+            double kap = k0 * H + (P->kabs ? (double)P->kabs[cl] : 0.0);
             /* distance to the cell boundary */
             double dmin = INFINITY; int ax = -1;
             for (int d = 0; d < 3; ++d) {
@@ -458,9 +463,17 @@ static void run_packet(worker_t *W, uint64_t pid)
         if (escaped) { outcome = 1; break; }
         /* ---- scattering (in the cell's Doppler units) ---- */
         double xc = (x - (n[0] * vc[0] + n[1] * vc[1] + n[2] * vc[2])) * sc;
-        if (P->eps) {
-            double e = P->eps[cl];
-            if (u01(A[1]) < e) { outcome = 2; break; }
+        if (P->eps || P->kabs) {
+            /* the interaction is a grey absorption with probability p_d =
+             * kabs / (k0 H + kabs); otherwise a line scattering, destroyed with
+             * probability eps (eq. eps): one uniform decides both */
+            double e = P->eps ? (double)P->eps[cl] : 0.0;
+            double pd = 0.0;
+            if (P->kabs && P->kabs[cl] > 0.0f) {
+                double ka = (double)P->kabs[cl];
+                pd = ka / (P->k0[cl] * orc_voigt_H(ac, xc) + ka);
+            }
+            if (u01(A[1]) < pd + (1.0 - pd) * e) { outcome = 2; break; }
         }
         int trials;
         double upar = sample_upar(xc, ac, &r, (uint32_t)ev, &trials);
@@ -650,29 +663,52 @@ int orc_levels_solve(int nl, int64_t ncell, const double *E, const double *g, co
 }
 
 /* ------------------------------------------------------------------------ */
-/* Single-cell escape (reference for the learned escape): a homogeneous      */
-/* static cube [-1,1]^3 of line-centre opacity k0 = tau_R per unit length; a  */
-/* photon of gas-frame frequency x_in arrives from an isotropic direction     */
-/* (event 0, purpose 4, words 0-1), scatters at the centre (event 1), then    */
-/* takes the plain flights and scatterings of Sec. 2.1-2.3 until it leaves.   */
-/* Record per photon: [log10 tau_R, log10 a, x_in, x_out, s, t, mu, ln N_s,   */
-/* ln <x^2>, valid, alpha]; (s, t) are the exit point's coordinates along the */
-/* two axes following the exit axis cyclically, mu = |n . normal|, and alpha  */
-/* in [0, pi] the angle between the exit direction's tangential part and the  */
-/* exit point's offset (s, t) from the face centre (0 where either vanishes). */
+/* Whole-cell escape (reference for the learned escape; the paper has no     */
+/* learned part, this is the plain walk of Sec. 2.1-2.3 confined to one      */
+/* cell).  The cell is the homogeneous static cube [-1,1]^3 in units of its  */
+/* half-width, of line-centre opacity tau_c per unit length, so tau_c is the */
+/* line-centre depth from the centre to a face.  A photon of gas-frame       */
+/* frequency x_in arriving along n_in (given, or isotropic from event 0,     */
+/* purpose 4, words 0-1) scatters at the point q (event 1, no flight), then  */
+/* takes plain flights and resonant scatterings until it leaves the cube.    */
+/* Record (ORC_CELL_REC doubles):                                            */
+/*   0 log10 tau_c  1 log10 a  2 x_in  3-5 q  6 log10 depth, depth =         */
+/*   tau_c (1 - max|q_k|) the line-centre depth to the nearest face          */
+/*   7-9 n_in  10 exit face F = 2 axis + (outward normal along +axis)        */
+/*   11, 12 ys, yt: offsets of the exit point from q's projection onto the   */
+/*   exit face along the two axes following the exit axis cyclically, over  */
+/*   q's distance to the face's plane   13 mu = |n_out . normal|             */
+/*   14 alpha in [0, pi]: angle between the exit direction's tangential part */
+/*   and that offset (0 where either vanishes)   15 x_out   16 ln N_s (N_s   */
+/*   scatterings inside, the first one included)   17 ln <x^2> over them     */
+/*   18 valid (0 if the scattering cap was reached)   19 0                   */
 /* ------------------------------------------------------------------------ */
-#define ORC_ESC_REC 11
-typedef struct { double tau, a, xin; uint64_t seed, p0, p1; double *out; uint64_t max_scat; } esc_job_t;
+#define ORC_CELL_REC 20
+typedef struct {
+    double tau, a, xin, q[3], nin[3];
+    int given_dir;
+    uint64_t seed, p0, p1, max_scat;
+    double *out;
+} cell_job_t;
 
-static void escape_one(const esc_job_t *J, uint64_t pid, double *o)
+static void cell_escape_one(const cell_job_t *J, uint64_t pid, double *o)
 {
     rng_t r = { { (uint32_t)J->seed, (uint32_t)(J->seed >> 32) }, pid };
-    uint32_t d[4];
-    draw_block(&r, 0, 4, d);
-    double mu0 = 2.0 * u01(d[0]) - 1.0, ph0 = 2.0 * ORC_PI * u01(d[1]);
-    double st0 = sqrt(fmax(0.0, 1.0 - mu0 * mu0));
-    double n[3] = { st0 * cos(ph0), st0 * sin(ph0), mu0 };
-    double X[3] = { 0.0, 0.0, 0.0 };
+    double n[3];
+    if (J->given_dir) {
+        for (int k = 0; k < 3; ++k) n[k] = J->nin[k];
+    } else {
+        uint32_t d[4];
+        draw_block(&r, 0, 4, d);
+        double mu0 = 2.0 * u01(d[0]) - 1.0, ph0 = 2.0 * ORC_PI * u01(d[1]);
+        double st0 = sqrt(fmax(0.0, 1.0 - mu0 * mu0));
+        n[0] = st0 * cos(ph0); n[1] = st0 * sin(ph0); n[2] = mu0;
+    }
+    double depth = J->tau * (1.0 - fmax(fabs(J->q[0]), fmax(fabs(J->q[1]), fabs(J->q[2]))));
+    o[0] = log10(J->tau); o[1] = log10(J->a); o[2] = J->xin;
+    for (int k = 0; k < 3; ++k) { o[3 + k] = J->q[k]; o[7 + k] = n[k]; }
+    o[6] = log10(fmax(depth, 1e-300));
+    double X[3] = { J->q[0], J->q[1], J->q[2] };
     double x = J->xin, sx2 = 0.0;
     uint64_t ns = 0;
     int valid = 0, ax = 0;
@@ -681,6 +717,7 @@ static void escape_one(const esc_job_t *J, uint64_t pid, double *o)
         draw_block(&r, (uint32_t)ev, 0, A);
         draw_block(&r, (uint32_t)ev, 1, B);
         if (ev > 1) {
+            /* free flight: tau = -ln u against k0 H(a, x) (Sec. 2.3.2) */
             double tau = -log(u01(A[0]));
             double kap = J->tau * orc_voigt_H(J->a, x);
             double dm = INFINITY;
@@ -697,6 +734,7 @@ static void escape_one(const esc_job_t *J, uint64_t pid, double *o)
             double l = tau / kap;
             for (int k = 0; k < 3; ++k) X[k] += l * n[k];
         }
+        /* resonant scattering, isotropic phase (eq. riia-scatter) */
         int trials;
         double upar = sample_upar(x, J->a, &r, (uint32_t)ev, &trials);
         double rr = sqrt(-log(u01(B[0]))), th = 2.0 * ORC_PI * u01(B[1]);
@@ -713,38 +751,51 @@ static void escape_one(const esc_job_t *J, uint64_t pid, double *o)
         for (int k = 0; k < 3; ++k) n[k] = no[k];
         ns += 1;
     }
-    o[0] = log10(J->tau); o[1] = log10(J->a); o[2] = J->xin;
-    if (valid) {
-        int a1 = (ax + 1) % 3, a2 = (ax + 2) % 3;
-        o[3] = x; o[4] = X[a1]; o[5] = X[a2]; o[6] = fabs(n[ax]);
-        o[7] = log((double)ns); o[8] = log(sx2 / (double)ns); o[9] = 1.0;
-        double dot = X[a1] * n[a1] + X[a2] * n[a2], crs = X[a1] * n[a2] - X[a2] * n[a1];
-        o[10] = atan2(fabs(crs), dot);
-    } else {
-        for (int k = 3; k < ORC_ESC_REC; ++k) o[k] = 0.0;
+    if (!valid) {
+        for (int k = 10; k < ORC_CELL_REC; ++k) o[k] = 0.0;
+        return;
     }
+    int a1 = (ax + 1) % 3, a2 = (ax + 2) % 3;
+    double side = (n[ax] > 0.0) ? 1.0 : -1.0;
+    double dplane = 1.0 - side * J->q[ax];       /* q's distance to the exit face's plane */
+    double ds = X[a1] - J->q[a1], dt = X[a2] - J->q[a2];
+    o[10] = 2.0 * ax + (side > 0.0 ? 1.0 : 0.0);
+    o[11] = ds / dplane;
+    o[12] = dt / dplane;
+    o[13] = fabs(n[ax]);
+    o[14] = atan2(fabs(ds * n[a2] - dt * n[a1]), ds * n[a1] + dt * n[a2]);
+    o[15] = x;
+    o[16] = log((double)ns);
+    o[17] = log(sx2 / (double)ns);
+    o[18] = 1.0;
+    o[19] = 0.0;
 }
 
-static void *escape_main(void *arg)
+static void *cell_escape_main(void *arg)
 {
-    esc_job_t *J = (esc_job_t *)arg;
-    for (uint64_t p = J->p0; p < J->p1; ++p) escape_one(J, p, J->out + ORC_ESC_REC * (p - J->p0));
+    cell_job_t *J = (cell_job_t *)arg;
+    for (uint64_t p = J->p0; p < J->p1; ++p) cell_escape_one(J, p, J->out + ORC_CELL_REC * (p - J->p0));
     return NULL;
 }
 
-int orc_escape_record(int64_t n, double tau_R, double a, double x_in, uint64_t seed, uint64_t offset,
-                      int n_threads, double *out)
+/* n whole-cell escapes from q (|q_k| < 1) with packet ids [offset, offset+n);
+ * n_in NULL = isotropic incoming directions.  out [n][ORC_CELL_REC]. */
+int orc_cell_escape_record(int64_t n, double tau_c, double a, double x_in, const double *q, const double *n_in,
+                           uint64_t seed, uint64_t offset, int n_threads, double *out)
 {
     if (n_threads < 1) n_threads = 1;
-    pthread_t th[256];
-    esc_job_t J[256];
     if (n_threads > 256) n_threads = 256;
+    for (int k = 0; k < 3; ++k) if (!(fabs(q[k]) < 1.0)) return -1;
+    pthread_t th[256];
+    cell_job_t J[256];
     for (int t = 0; t < n_threads; ++t) {
-        J[t].tau = tau_R; J[t].a = a; J[t].xin = x_in; J[t].seed = seed; J[t].max_scat = 4000000;
+        J[t].tau = tau_c; J[t].a = a; J[t].xin = x_in; J[t].seed = seed; J[t].max_scat = 20000000;
+        for (int k = 0; k < 3; ++k) { J[t].q[k] = q[k]; J[t].nin[k] = n_in ? n_in[k] : 0.0; }
+        J[t].given_dir = n_in != NULL;
         J[t].p0 = offset + (uint64_t)n * t / n_threads;
         J[t].p1 = offset + (uint64_t)n * (t + 1) / n_threads;
-        J[t].out = out + ORC_ESC_REC * (J[t].p0 - offset);
-        pthread_create(&th[t], NULL, escape_main, &J[t]);
+        J[t].out = out + ORC_CELL_REC * (J[t].p0 - offset);
+        pthread_create(&th[t], NULL, cell_escape_main, &J[t]);
     }
     for (int t = 0; t < n_threads; ++t) pthread_join(th[t], NULL);
     return 0;

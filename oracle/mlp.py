@@ -1,67 +1,77 @@
-"""FP64 CPU reference of the escape network -- TEST INFRASTRUCTURE.
+"""FP64 CPU reference of the whole-cell escape network -- TEST INFRASTRUCTURE.
 
-Same parameter layout as the GPU (one flat vector): W1[8][128], b1[128],
-W2[128][128], b2, W3[128][128], b3, W4[128][10], b4[10]; activations SiLU.
+Same parameter layout as the GPU (one flat vector): W1[24][128], b1[128],
+W2[128][128], b2, W3[128][128], b3, W4[128][16], b4[16]; activations SiLU.
 
-Inputs (8), normalised as ((log10 tau - 3.5)/1.5, log10 a + 3, x_in / 4,
-L(u_a), L(u_b), w, r_in, flag) with L(u) = logit(u) / 4 the encoding of a
-quantile level (extreme levels get distinct inputs, so the far wing of the
-exit frequency is not flattened).  A row is either *marginal* (flag 0,
-w = L(u_c), r_in 0) or *conditional* (flag 1, w = x_out / 4 and
-r_in = sqrt(2) r - 1 with x_out the exit frequency and r the exit point's
-distance from the face centre): the network is evaluated once at three
-independent quantile levels for the exit frequency, exit point and count,
-then once more at the sampled exit frequency and point for the exit
-direction, which depends on both (photons leaving near an edge travel away
-from the face centre; wing photons leave closer to the normal).
+The network describes how a photon that scatters inside a homogeneous static
+cubic cell leaves it (the plain walk of Sec. 2.1-2.3 confined to one cell; the
+paper itself has no learned part).  Conditions are given in the cell's
+reduced frame: the start point's absolute coordinates sorted ascending,
+q0 <= q1 <= q2 (in half-widths; axis 2 is the nearest face), the incoming
+direction in the same frame and |x_in| (the exit frequency's sign follows
+x_in's).  Inputs (24):
 
-Outputs (index: meaning, loss, level), for a record with exit frequency x:
+  0  (log10 tau_c - 3) / 1.2      tau_c: line-centre depth centre to face
+  1  log10 a + 3
+  2  |x_in| - 1
+  3-5 2 q - 1
+  6  (log10 depth - 2) / 1.2      depth = tau_c (1 - q2), to the nearest face
+  7-9 incoming direction (reduced frame)
+  10-13 L(u_a), L(u_b), L(u_c), L(u_d)  quantile levels, L(u) = logit(u) / 4
+  14 flag: 0 marginal row, 1 conditional row
+  15 conditional: x_out / 4 (reduced sign), else 0
+  16-21 conditional: one-hot exit face F = 2 axis + (normal along +axis), else 0
+  22, 23 zero
+
+Outputs (index: meaning, loss, level):
   marginal rows
-  0: quantile of x given x >= 0                 pinball at u_a, records with x >= 0
-  1: quantile of s (exit point, first axis)      pinball at u_b
-  2: quantile of t (exit point, second axis)     pinball at u_c
-  4: ln E[N_s | condition]                       weighted log-deviance (below)
-  5: quantile of ln <x^2> over the scatterings   pinball at u_a
-  6: logit P(x >= 0 | condition)                 logistic (Bernoulli) loss
-  7: quantile of -x given x < 0                  pinball at u_a, records with x < 0
-  conditional rows (given r and x_out)
-  3: quantile of mu (exit cosine to the normal)  pinball at u_a
-  8: quantile of alpha (angle between the exit   pinball at u_b
-     direction's tangential part and the exit point's offset (s, t))
-  9: unused (keeps the parameter block an even number of floats)
-The exit frequency is bimodal (blue and red peaks with an empty core between
-them), so one smooth quantile function of the signed x would fill the gap;
-the two one-sided quantiles and the side probability form a two-component
-mixture whose components are each unimodal.
+  0-5  logits of the exit face                      softmax cross-entropy
+  6    logit P(x_out >= 0)                           logistic
+  7    quantile of x_out given x_out >= 0            pinball at u_a, records with x_out >= 0
+  8    quantile of -x_out given x_out < 0            pinball at u_a, records with x_out < 0
+  9    ln E[N_s | condition]                         weighted log-deviance
+  10   quantile of ln <x^2> over the scatterings     pinball at u_b
+  conditional rows (given the exit face and x_out)
+  11   quantile of ys (exit offset, first axis)      pinball at u_a
+  12   quantile of yt (exit offset, second axis)     pinball at u_b
+  13   quantile of mu (exit cosine)                  pinball at u_c
+  14   quantile of alpha (tangential direction vs    pinball at u_d
+       the exit offset)
+  15   unused
+ys, yt are the exit point's offsets from the start point's projection onto
+the exit face (along the two axes following the exit axis cyclically) over
+the start point's distance to that face's plane.
 
-Pinball loss: rho_u(y - o) = (y - o)(u - 1{y < o}).  Output 4 uses the scaled
-log-deviance w f(d) / s4 with w = 1/4, d = s4 (y4 - o4) and
-f(d) = e^d - 1 - d (continued linearly beyond d = 4, so a rare very long
-escape cannot dominate a batch); its minimiser satisfies E[e^(y - m)] = 1,
-i.e. e^m = E[N_s].  Output 6 uses softplus(o) - b o with b = 1{x >= 0}, whose
-minimiser is the logit of P(x >= 0).  Every loss is averaged over the whole
-batch (masked samples contribute zero) and the outputs' losses are summed.
-The manual backward pass is pinned by finite differences
-(tests/test_oracle_mlp.py).  ``bf16=True`` rounds weights and activations to
-bfloat16 (round to nearest even) where the GPU kernels do, to separate the
-arithmetic error of the kernels from the storage format.
+Pinball loss rho_u(y - o) = (y - o)(u - 1{y < o}); output 9 uses the scaled
+log-deviance w f(d) / s9 with w = 1/4, d = s9 (y9 - o9), f(d) = e^d - 1 - d
+continued linearly beyond d = 4, whose minimiser is ln E[N_s]; the face
+logits use -log softmax(o)_F, whose minimiser is the log-probabilities (up to
+a constant); output 6 uses softplus(o) - b o, b = 1{x_out >= 0}.  Losses are
+averaged over the batch and summed over outputs.  The manual backward pass is
+pinned by finite differences (tests/test_oracle_mlp.py).  ``bf=True`` rounds
+weights and activations to bfloat16 where the GPU kernels do.
 """
 from __future__ import annotations
 
 import numpy as np
 
-NIN, NH, NOUT = 8, 128, 10
+NIN, NH, NOUT = 24, 128, 16
 SHAPES = [("W1", (NIN, NH)), ("b1", (NH,)), ("W2", (NH, NH)), ("b2", (NH,)),
           ("W3", (NH, NH)), ("b3", (NH,)), ("W4", (NH, NOUT)), ("b4", (NOUT,))]
 NPARAMS = sum(int(np.prod(s)) for _, s in SHAPES)
-NNORM = 2 * NOUT
-O_XPOS, O_S, O_T, O_MU, O_LOGN, O_LOGX2, O_LOGIT, O_XNEG, O_ALPHA, O_SPARE = range(NOUT)
-MARGINAL = (O_XPOS, O_S, O_T, O_LOGN, O_LOGX2, O_LOGIT, O_XNEG)
-CONDITIONAL = (O_MU, O_ALPHA)
-N_OUT = O_LOGN
+NCAL = 256
+NNORM = 2 * NOUT + NCAL + 4
+O_FACE = 0
+O_SIDE, O_XPOS, O_XNEG, O_LOGN, O_LOGX2, O_YS, O_YT, O_MU, O_ALPHA, O_SPARE = range(6, 16)
+FACES = tuple(range(6))
+MARGINAL = FACES + (O_SIDE, O_XPOS, O_XNEG, O_LOGN, O_LOGX2)
+CONDITIONAL = (O_YS, O_YT, O_MU, O_ALPHA)
 DEV_CLAMP = 4.0
 LEVEL_MIN = 1e-4
 DEV_WEIGHT = 0.25
+# record columns (oracle.cell_escape_record and the GPU records share them)
+(R_LT, R_LA, R_X, R_Q0, R_Q1, R_Q2, R_LD, R_N0, R_N1, R_N2, R_FACE, R_YS, R_YT, R_MU, R_ALPHA, R_XOUT,
+ R_LOGN, R_LOGX2, R_VALID) = range(19)
 
 
 def unpack(p):
@@ -85,18 +95,6 @@ def bf16(a):
     return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
 
 
-def inputs(lt, la, xin, ua, ub, w, r, cond):
-    """Normalised inputs; w is u_c on marginal rows and the exit frequency x_out
-    on conditional rows; r (exit point radius) is ignored on marginal rows."""
-    cond = np.asarray(cond, dtype=bool)
-    lt, la, xin, ua, ub, w, r = np.broadcast_arrays(*(np.asarray(v, dtype=np.float64)
-                                                      for v in (lt, la, xin, ua, ub, w, r)))
-    wl = np.where(cond, 0.5, w)  # the level slot of a marginal row
-    return np.stack([(lt - 3.5) / 1.5, la + 3.0, xin / 4.0, level_in(ua), level_in(ub),
-                     np.where(cond, w / 4.0, level_in(wl)), np.where(cond, np.sqrt(2.0) * r - 1.0, 0.0),
-                     cond.astype(np.float64)], axis=-1)
-
-
 def level_in(u):
     """Network input of a quantile level u: logit(u) / 4, u clamped to the
     trained levels [1e-4, 1 - 1e-4] (beyond them a network would extrapolate)."""
@@ -104,17 +102,40 @@ def level_in(u):
     return 0.25 * (np.log(u) - np.log1p(-u))
 
 
-def levels(ua, ub, uc, cond):
-    """Quantile level of each output per row [B, NOUT] (NaN for the outputs
-    that are not quantiles or not trained on that kind of row)."""
+def inputs(rec, u, cond):
+    """Normalised inputs [B, NIN] of records in the reduced frame (columns R_*;
+    x_in >= 0) at quantile levels u [B, 4]; conditional rows take the record's
+    exit face and exit frequency."""
+    rec = np.asarray(rec, dtype=np.float64)
+    u = np.asarray(u, dtype=np.float64).reshape(-1, 4)
+    cond = np.asarray(cond, dtype=bool)
+    B = rec.shape[0]
+    X = np.zeros((B, NIN))
+    X[:, 0] = (rec[:, R_LT] - 3.0) / 1.2
+    X[:, 1] = rec[:, R_LA] + 3.0
+    X[:, 2] = rec[:, R_X] - 1.0
+    X[:, 3:6] = 2.0 * rec[:, R_Q0:R_Q2 + 1] - 1.0
+    X[:, 6] = (rec[:, R_LD] - 2.0) / 1.2
+    X[:, 7:10] = rec[:, R_N0:R_N2 + 1]
+    X[:, 10:14] = level_in(u)
+    X[:, 14] = cond
+    X[:, 15] = np.where(cond, rec[:, R_XOUT] / 4.0, 0.0)
+    face = rec[:, R_FACE].astype(np.int64)
+    X[np.arange(B), 16 + face] = np.where(cond, 1.0, 0.0)
+    return X
+
+
+def levels(u, cond):
+    """Quantile level of each output per row [B, NOUT] (NaN for outputs that
+    are not quantiles or not trained on that kind of row)."""
+    u = np.asarray(u, dtype=np.float64).reshape(-1, 4)
     cond = np.asarray(cond, dtype=bool)
     U = np.full((cond.shape[0], NOUT), np.nan)
-    for k in (O_XPOS, O_XNEG, O_LOGX2):
-        U[:, k] = np.where(cond, np.nan, ua)
-    U[:, O_S] = np.where(cond, np.nan, ub)
-    U[:, O_T] = np.where(cond, np.nan, uc)
-    U[:, O_MU] = np.where(cond, ua, np.nan)
-    U[:, O_ALPHA] = np.where(cond, ub, np.nan)
+    U[:, O_XPOS] = np.where(cond, np.nan, u[:, 0])
+    U[:, O_XNEG] = np.where(cond, np.nan, u[:, 0])
+    U[:, O_LOGX2] = np.where(cond, np.nan, u[:, 1])
+    for k, j in ((O_YS, 0), (O_YT, 1), (O_MU, 2), (O_ALPHA, 3)):
+        U[:, k] = np.where(cond, u[:, j], np.nan)
     return U
 
 
@@ -151,10 +172,11 @@ def deviance(d):
     return f, np.exp(dc) - 1.0
 
 
-def losses(out, Y, U, s4=1.0):
+def losses(out, Y, U, s9=1.0):
     """Mean over the batch of the summed per-output losses, and dL/dout.
     Y: normalised targets (NaN where an output is masked for that sample);
-    Y[:, 6] is the side label b in {0, 1}; U: per-output quantile levels."""
+    Y[:, 0] holds the exit face label F on marginal rows (columns 1-5 unused),
+    Y[:, 6] the side label b in {0, 1}; U: per-output quantile levels."""
     B = out.shape[0]
     live = ~np.isnan(Y)
     Yz = np.where(live, Y, 0.0)
@@ -162,21 +184,39 @@ def losses(out, Y, U, s4=1.0):
     ind = (Yz < out).astype(np.float64)
     lk = (Yz - out) * (Uz - ind)
     dout = (ind - Uz) / B
-    f, fp = deviance(s4 * (Yz[:, O_LOGN] - out[:, O_LOGN]))
-    lk[:, O_LOGN] = DEV_WEIGHT * f / s4
+    # ln E[N_s]: log-deviance
+    f, fp = deviance(s9 * (Yz[:, O_LOGN] - out[:, O_LOGN]))
+    lk[:, O_LOGN] = DEV_WEIGHT * f / s9
     dout[:, O_LOGN] = -DEV_WEIGHT * fp / B
-    o6, b = out[:, O_LOGIT], Yz[:, O_LOGIT]
-    lk[:, O_LOGIT] = np.logaddexp(0.0, o6) - b * o6
-    dout[:, O_LOGIT] = (1.0 / (1.0 + np.exp(-o6)) - b) / B
+    # side: logistic
+    o6, b = out[:, O_SIDE], Yz[:, O_SIDE]
+    lk[:, O_SIDE] = np.logaddexp(0.0, o6) - b * o6
+    dout[:, O_SIDE] = (1.0 / (1.0 + np.exp(-o6)) - b) / B
+    # exit face: softmax cross-entropy, counted in column 0
+    lf = out[:, :6]
+    mx = lf.max(axis=1, keepdims=True)
+    e = np.exp(lf - mx)
+    sm = e / e.sum(axis=1, keepdims=True)
+    F = Yz[:, 0].astype(np.int64)
+    rows = np.arange(B)
+    lk[:, 0] = (mx[:, 0] + np.log(e.sum(axis=1))) - lf[rows, F]
+    lk[:, 1:6] = 0.0
+    onehot = np.zeros_like(sm)
+    onehot[rows, F] = 1.0
+    dout[:, :6] = (sm - onehot) / B
+    fl = live[:, 0]
+    lk[:, :6] = np.where(fl[:, None], lk[:, :6], 0.0)
+    dout[:, :6] = np.where(fl[:, None], dout[:, :6], 0.0)
+    live[:, 1:6] = fl[:, None]
     lk = np.where(live, lk, 0.0)
     dout = np.where(live, dout, 0.0)
     return float(np.sum(lk) / B), dout
 
 
-def loss_and_grad(p, X, Y, U, bf=False, s4=1.0):
-    """s4: the target scale of output 4 (norm[NOUT + 4])."""
+def loss_and_grad(p, X, Y, U, bf=False, s9=1.0):
+    """s9: the target scale of output 9 (norm[NOUT + 9])."""
     out, c, W = forward(p, X, bf)
-    loss, d = losses(out, Y, U, s4)
+    loss, d = losses(out, Y, U, s9)
     g = {"W4": c["h3"].T @ d, "b4": d.sum(0)}
     dh = d @ W["W4"].T
     for i in (3, 2, 1):
@@ -188,23 +228,25 @@ def loss_and_grad(p, X, Y, U, bf=False, s4=1.0):
 
 
 def raw_targets(rec, cond=None):
-    """Records [.., x_out, s, t, mu, lnNs, lnx2, valid, alpha] -> per-output
-    physical targets [B, NOUT] (NaN where masked; column 6 is the side label).
-    cond marks conditional rows (default: none)."""
+    """Records (columns R_*, reduced frame) -> per-output physical targets
+    [B, NOUT] (NaN where masked; column 0 holds the face label, column 6 the
+    side label).  cond marks conditional rows (default: none)."""
+    rec = np.asarray(rec, dtype=np.float64)
     B = rec.shape[0]
     cond = np.zeros(B, dtype=bool) if cond is None else np.asarray(cond, dtype=bool)
-    x = rec[:, 3].astype(np.float64)
+    x = rec[:, R_XOUT]
     pos = x >= 0.0
     y = np.full((B, NOUT), np.nan)
+    y[:, 0] = rec[:, R_FACE]
+    y[:, O_SIDE] = pos.astype(np.float64)
     y[:, O_XPOS] = np.where(pos, x, np.nan)
-    y[:, O_S] = rec[:, 4]
-    y[:, O_T] = rec[:, 5]
-    y[:, O_MU] = rec[:, 6]
-    y[:, O_LOGN] = rec[:, 7]
-    y[:, O_LOGX2] = rec[:, 8]
-    y[:, O_LOGIT] = pos.astype(np.float64)
     y[:, O_XNEG] = np.where(pos, np.nan, -x)
-    y[:, O_ALPHA] = rec[:, 10]
+    y[:, O_LOGN] = rec[:, R_LOGN]
+    y[:, O_LOGX2] = rec[:, R_LOGX2]
+    y[:, O_YS] = rec[:, R_YS]
+    y[:, O_YT] = rec[:, R_YT]
+    y[:, O_MU] = rec[:, R_MU]
+    y[:, O_ALPHA] = rec[:, R_ALPHA]
     y[cond[:, None] & np.isin(np.arange(NOUT), MARGINAL)[None, :]] = np.nan
     y[~cond[:, None] & np.isin(np.arange(NOUT), CONDITIONAL)[None, :]] = np.nan
     y[:, O_SPARE] = np.nan
@@ -212,6 +254,37 @@ def raw_targets(rec, cond=None):
 
 
 def targets_normalised(rec, norm, cond=None):
-    """Normalised targets: (raw - mean) / scale; the side label stays 0/1
-    (its normalisation is fixed at mean 0, scale 1)."""
+    """Normalised targets (raw - mean) / scale; the face and side labels keep
+    their values (their normalisation is fixed at mean 0, scale 1)."""
     return (raw_targets(rec, cond) - norm[:NOUT]) / norm[NOUT:2 * NOUT]
+
+
+def reduce_records(rec):
+    """Oracle records in any frame -> the network's reduced frame: start point
+    coordinates |q| sorted ascending (axis 2 nearest the start), directions,
+    exit face and exit offsets permuted and reflected alike, x_in >= 0 (the
+    sign of x_out flipped with it).  mu and alpha are invariant."""
+    rec = np.array(rec, dtype=np.float64, copy=True)
+    B = rec.shape[0]
+    r = np.arange(B)
+    q = rec[:, R_Q0:R_Q2 + 1].copy()
+    sg = np.where(q < 0, -1.0, 1.0)
+    order = np.argsort(np.abs(q), axis=1, kind="stable")   # new axis j <- old axis order[j]
+    inv = np.argsort(order, axis=1)                         # old axis o -> new axis inv[o]
+    rec[:, R_Q0:R_Q2 + 1] = np.abs(q)[r[:, None], order]
+    n = rec[:, R_N0:R_N2 + 1] * sg
+    rec[:, R_N0:R_N2 + 1] = n[r[:, None], order]
+    F = rec[:, R_FACE].astype(np.int64)
+    ax, side = F // 2, np.where(F % 2 == 1, 1.0, -1.0)
+    off_old = np.zeros((B, 3))
+    off_old[r, (ax + 1) % 3] = rec[:, R_YS]
+    off_old[r, (ax + 2) % 3] = rec[:, R_YT]
+    off_new = (off_old * sg)[r[:, None], order]
+    nax = inv[r, ax]
+    rec[:, R_FACE] = 2 * nax + (side * sg[r, ax] > 0)
+    rec[:, R_YS] = off_new[r, (nax + 1) % 3]
+    rec[:, R_YT] = off_new[r, (nax + 2) % 3]
+    sx = np.where(rec[:, R_X] < 0, -1.0, 1.0)
+    rec[:, R_X] *= sx
+    rec[:, R_XOUT] *= sx
+    return rec

@@ -41,6 +41,7 @@ struct krt_ctx {
     // scratch
     unsigned long long *work_counter = nullptr;
     double *level_consts = nullptr;
+    double *level_power = nullptr;   // per-line partial and total powers of krt_levels_update
     int64_t *host_pinned = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;   // bracket the last transport launch
     float last_ms = 0.0f;
@@ -48,8 +49,13 @@ struct krt_ctx {
     float *edges = nullptr;                    // [kEdgeFloats]: spectrum then channel edges
     bool mlp_ready = false;
     float esc_la_lo = 1.0f, esc_la_hi = -1.0f;  // log10 a range the network was fitted on (empty: none)
+    float esc_lt_lo = 1.0f, esc_lt_hi = -1.0f;  // log10 tau_c range of its training records
+    float esc_ld_min = 0.0f;                    // smallest log10 depth of its training records
     float *mlp_p = nullptr, *mlp_m = nullptr, *mlp_v = nullptr, *mlp_g = nullptr, *mlp_norm = nullptr;
     float *mlp_loss = nullptr, *mlp_u = nullptr;
+    float *mlp_part = nullptr;                 // [kGradSplits][kNParams] split gradients
+    uint16_t *mlp_act = nullptr;               // [kActRowsAll][mlp_act_cap] bf16 activation store
+    int64_t mlp_act_cap = 0;
     int32_t *mlp_idx = nullptr;
     int mlp_batch_cap = 0;
     int mlp_step = 0;
@@ -188,10 +194,11 @@ extern "C" void krt_destroy(krt_ctx *c) {
     if (c->cls_par) (void)hipFree(c->cls_par);
     if (c->work_counter) (void)hipFree(c->work_counter);
     if (c->level_consts) (void)hipFree(c->level_consts);
+    if (c->level_power) (void)hipFree(c->level_power);
     if (c->host_pinned) (void)hipHostFree(c->host_pinned);
     for (void *p : {(void *)c->mlp_p, (void *)c->mlp_m, (void *)c->mlp_v, (void *)c->mlp_g, (void *)c->mlp_norm,
                     (void *)c->mlp_loss, (void *)c->mlp_u, (void *)c->mlp_idx, (void *)c->mlp_blob,
-                    (void *)c->mlp_img, (void *)c->mlp_calsum})
+                    (void *)c->mlp_img, (void *)c->mlp_calsum, (void *)c->mlp_part, (void *)c->mlp_act})
         if (p) (void)hipFree(p);
     if (c->edges) (void)hipFree(c->edges);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -306,8 +313,7 @@ static double voigt_crossing(double a) {
     return 0.5 * (lo + hi);
 }
 
-extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const krt_run_opts *o,
-                          krt_tallies *t) {
+static int mc_run_impl(krt_ctx *c, uint64_t n_packets, uint64_t seed, const krt_run_opts *o, krt_tallies *t) {
     if (!c) return KRT_EINVAL;
     if (!o || !t) return fail(c, KRT_EINVAL, "opts / tallies NULL");
     if (!c->have_grid) return fail(c, KRT_ESTATE, "no grid uploaded");
@@ -346,13 +352,15 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
     if (esc) {
         if (!c->mlp_ready) return fail(c, KRT_ESTATE, "escape_mode 1 needs trained escape weights");
         if (o->jbar) return fail(c, KRT_EINVAL, "escape_mode 1 does not tally the mean intensity");
-        // the network is trained on isotropic re-emission without destruction:
-        // the scatterings it skips would apply neither the dipole phase nor
-        // the survival probability (1 - eps)^N_s
+        // the network is trained on isotropic re-emission without destruction
+        // or absorption: the scatterings it skips would apply neither the
+        // dipole phase nor the survival probability of the skipped walk
         if (c->lines[o->line].phase != KRT_PHASE_ISO)
             return fail(c, KRT_EINVAL, "escape_mode 1 needs isotropic phase (line %d is dipole)", o->line);
         if (c->grid.eps_dev)
             return fail(c, KRT_EINVAL, "escape_mode 1 needs a grid without destruction (eps_dev is set)");
+        if (c->grid.kabs_dev)
+            return fail(c, KRT_EINVAL, "escape_mode 1 needs a grid without absorption (kabs_dev is set)");
         double al = c->lines[o->line].a;
         if (al < 1e-4 * (1 - 1e-9) || al > 1e-2 * (1 + 1e-9))
             return fail(c, KRT_EINVAL, "learned escape covers a in [1e-4, 1e-2] (line a = %g)", al);
@@ -370,7 +378,6 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
     if (block < 64 || block > 1024 || block % 64) return fail(c, KRT_EINVAL, "wg_size %d invalid", block);
     if (per_cu < 1 || per_cu > 64) return fail(c, KRT_EINVAL, "wg_per_cu %d invalid", per_cu);
     if (o->max_events > 0xFFFFFFFEull) return fail(c, KRT_EINVAL, "max_events too large");
-    if (o->esc_evals != 0) return fail(c, KRT_EINVAL, "esc_evals is reserved (0)");
     if (o->profile_mode < 0 || o->profile_mode > 2) return fail(c, KRT_EINVAL, "profile_mode %d", o->profile_mode);
     if (o->profile_mode != 0 && esc) return fail(c, KRT_EINVAL, "profile_mode %d is for the plain walk", o->profile_mode);
     if (c->have_grid && c->grid.tclass_dev && (esc || o->profile_mode != 0))
@@ -387,7 +394,9 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
         if (o->emis_nch > 0) HIPCHK(c, launch_zero_i64(t->emis_raw_dev, nc * o->emis_nch, c->stream));
         if (o->jbar) HIPCHK(c, launch_zero_i64(t->jbar_raw_dev, nc, c->stream));
     }
-    HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(c->work_counter), 1, c->stream));
+    unsigned long long *counter = c->work_counter;
+    float *edges = c->edges;
+    HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(counter), 1, c->stream));
 
     RunParams P;
     std::memset(&P, 0, sizeof(P));
@@ -407,6 +416,7 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
     P.k0 = g.k0_dev + (int64_t)l * nc;
     if (g.vel_dev) { P.vx = g.vel_dev; P.vy = g.vel_dev + nc; P.vz = g.vel_dev + 2 * nc; }
     P.eps = g.eps_dev ? g.eps_dev + (int64_t)l * nc : nullptr;
+    P.kabs = g.kabs_dev;
     P.alias_prob = c->alias_prob[l];
     P.alias_idx = c->alias_idx[l];
     P.tab = c->tab[l];
@@ -416,18 +426,16 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
     P.source = o->source;
     P.src_profile = o->src_profile;
     P.src_x0 = (float)o->src_x0;
-    {
-        std::vector<float> e(kEdgeFloats, 0.0f);
-        fill_edges(e.data(), o->spec_nbins, o->spec_lo, o->spec_hi);
-        if (o->emis_nch > 0) fill_edges(e.data() + kMaxSpecBins + 1, o->emis_nch, o->ch_lo, o->ch_hi);
-        HIPCHK(c, hipMemcpyAsync(c->edges, e.data(), sizeof(float) * kEdgeFloats, hipMemcpyHostToDevice, c->stream));
-    }
+    std::vector<float> e(kEdgeFloats, 0.0f);
+    fill_edges(e.data(), o->spec_nbins, o->spec_lo, o->spec_hi);
+    if (o->emis_nch > 0) fill_edges(e.data() + kMaxSpecBins + 1, o->emis_nch, o->ch_lo, o->ch_hi);
+    HIPCHK(c, hipMemcpyAsync(edges, e.data(), sizeof(float) * kEdgeFloats, hipMemcpyHostToDevice, c->stream));
     P.spec_nb = o->spec_nbins;
     P.spec_inv_w = (float)(o->spec_nbins / (o->spec_hi - o->spec_lo));
-    P.spec_edges = c->edges;
+    P.spec_edges = edges;
     P.emis_nch = o->emis_nch;
     P.ch_inv_w = o->emis_nch > 0 ? (float)(o->emis_nch / (o->ch_hi - o->ch_lo)) : 0.0f;
-    P.ch_edges = c->edges + kMaxSpecBins + 1;
+    P.ch_edges = edges + kMaxSpecBins + 1;
     P.frac_scale = std::ldexp(1.0f, fb);
     P.emis_w32 = fb <= 30 ? 1 : 0;
     P.jbar_scale = std::ldexp(1.0f, fj);
@@ -442,10 +450,18 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
     P.max_events = o->max_events ? o->max_events : 0xFFFFFFFEull;
     P.key0 = (uint32_t)seed;
     P.key1 = (uint32_t)(seed >> 32);
-    P.work_counter = c->work_counter;
+    P.work_counter = counter;
     P.mlp_img = esc ? c->mlp_img : nullptr;
-    P.esc_tau_min = (float)(o->esc_tau_min > 0.0 ? o->esc_tau_min : 100.0);
-    P.esc_tau_max = 1e5f;
+    // whole-cell calls: cubic cells only, inside the records' ranges of the cell
+    // depth tau_c and of the depth of the scattering point below the nearest face
+    P.esc_cubic = (std::fabs(P.dxd[1] - P.dxd[0]) <= 1e-6 * P.dxd[0] &&
+                   std::fabs(P.dxd[2] - P.dxd[0]) <= 1e-6 * P.dxd[0]) ? 1 : 0;
+    P.esc_half_dx = (float)(0.5 * P.dxd[0]);
+    P.esc_tc_min = (float)std::max(0.5 * (o->esc_cell_tau_min > 0.0 ? o->esc_cell_tau_min : 100.0),
+                                   std::pow(10.0, (double)c->esc_lt_lo));
+    P.esc_tc_max = (float)std::pow(10.0, (double)c->esc_lt_hi);
+    P.esc_depth_min = (float)std::max(o->esc_tau_min > 0.0 ? o->esc_tau_min : 3.0,
+                                      std::pow(10.0, (double)c->esc_ld_min));
     P.esc_x_max = kEscXMax;
     P.esc_log10a = (float)std::log10(c->lines[l].a);
     P.esc_min_lanes = o->esc_min_lanes > 0 ? o->esc_min_lanes : 8;
@@ -492,6 +508,11 @@ extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const k
     int64_t st = c->host_pinned[KRT_C_STATUS];
     if (st != 0) return fail(c, KRT_EDEVICE, "device status 0x%llx (nan=1 stuck=2 saturate=4)", (long long)st);
     return KRT_OK;
+}
+
+extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const krt_run_opts *o,
+                          krt_tallies *t) {
+    return mc_run_impl(c, n_packets, seed, o, t);
 }
 
 // -------------------------------------------------------------- imaging ---
@@ -549,7 +570,7 @@ extern "C" float krt_last_image_ms(const krt_ctx *c) { return c ? c->last_image_
 template <int NL>
 __global__ void __launch_bounds__(256) levels_kernel(int64_t ncell, const double *K, const double *ncoll,
                                                      const double *ntot, const float *jbar, double *pops,
-                                                     float *k0_out, float *eps_out) {
+                                                     float *k0_out, float *eps_out, float *emis_out) {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
     const double *E = K, *g = K + NL, *A = K + 2 * NL, *Cd = K + 2 * NL + NL * NL, *s0 = K + 2 * NL + 2 * NL * NL;
@@ -631,6 +652,9 @@ __global__ void __launch_bounds__(256) levels_kernel(int64_t ncell, const double
     for (int l = 0; l + 1 < NL; ++l) {
         int u = l + 1;
         if (k0_out) k0_out[(int64_t)l * ncell + c] = (float)(b[l] * s0[l]);
+        // spontaneous emission of the line per unit volume, n_u A_ul (the
+        // Lambda iteration's source)
+        if (emis_out) emis_out[(int64_t)l * ncell + c] = (float)(b[u] * A[u * NL + l]);
         if (eps_out) {
             double ctot = 0.0;
 #pragma unroll
@@ -645,26 +669,56 @@ __global__ void __launch_bounds__(256) levels_kernel(int64_t ncell, const double
 
 template <int NL>
 static void launch_levels_t(int64_t ncell, const double *consts, const double *ncoll, const double *ntot,
-                            const float *jbar, double *pops, float *k0_out, float *eps_out, hipStream_t s) {
+                            const float *jbar, double *pops, float *k0_out, float *eps_out, float *emis_out,
+                            hipStream_t s) {
     int grid = (int)((ncell + 255) / 256);
     hipLaunchKernelGGL(levels_kernel<NL>, dim3(grid), dim3(256), 0, s, ncell, consts, ncoll, ntot, jbar, pops,
-                       k0_out, eps_out);
+                       k0_out, eps_out, emis_out);
 }
 
 hipError_t krt::launch_levels(int nl, int64_t ncell, const double *consts, const double *ncoll,
                               const double *ntot, const float *jbar, double *pops, float *k0_out,
-                              float *eps_out, hipStream_t s) {
+                              float *eps_out, float *emis_out, hipStream_t s) {
     switch (nl) {
-        case 2: launch_levels_t<2>(ncell, consts, ncoll, ntot, jbar, pops, k0_out, eps_out, s); break;
-        case 3: launch_levels_t<3>(ncell, consts, ncoll, ntot, jbar, pops, k0_out, eps_out, s); break;
-        case 4: launch_levels_t<4>(ncell, consts, ncoll, ntot, jbar, pops, k0_out, eps_out, s); break;
-        case 5: launch_levels_t<5>(ncell, consts, ncoll, ntot, jbar, pops, k0_out, eps_out, s); break;
-        case 6: launch_levels_t<6>(ncell, consts, ncoll, ntot, jbar, pops, k0_out, eps_out, s); break;
-        case 7: launch_levels_t<7>(ncell, consts, ncoll, ntot, jbar, pops, k0_out, eps_out, s); break;
-        case 8: launch_levels_t<8>(ncell, consts, ncoll, ntot, jbar, pops, k0_out, eps_out, s); break;
+        case 2: launch_levels_t<2>(ncell, consts, ncoll, ntot, jbar, pops, k0_out, eps_out, emis_out, s); break;
+        case 3: launch_levels_t<3>(ncell, consts, ncoll, ntot, jbar, pops, k0_out, eps_out, emis_out, s); break;
+        case 4: launch_levels_t<4>(ncell, consts, ncoll, ntot, jbar, pops, k0_out, eps_out, emis_out, s); break;
+        case 5: launch_levels_t<5>(ncell, consts, ncoll, ntot, jbar, pops, k0_out, eps_out, emis_out, s); break;
+        case 6: launch_levels_t<6>(ncell, consts, ncoll, ntot, jbar, pops, k0_out, eps_out, emis_out, s); break;
+        case 7: launch_levels_t<7>(ncell, consts, ncoll, ntot, jbar, pops, k0_out, eps_out, emis_out, s); break;
+        case 8: launch_levels_t<8>(ncell, consts, ncoll, ntot, jbar, pops, k0_out, eps_out, emis_out, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// Line powers: sum over cells of n_u A_ul for each line, FP64, deterministic
+// (per-block partial sums over fixed cell ranges, then a fixed-order sum).
+constexpr int kPowBlocks = 256;
+__global__ void __launch_bounds__(256) line_power_partial_kernel(int nl, int64_t ncell, const double *K,
+                                                                 const double *pops, double *partial) {
+    __shared__ double red[256];
+    const int line = blockIdx.y;
+    const int u = line + 1;
+    const double A_ul = K[2 * nl + u * nl + line];
+    const int64_t c0 = ncell * blockIdx.x / kPowBlocks, c1 = ncell * (blockIdx.x + 1) / kPowBlocks;
+    double acc = 0.0;
+    for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) acc += pops[c * nl + u] * A_ul;
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st >= 1; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[line * kPowBlocks + blockIdx.x] = red[0];
+}
+
+__global__ void line_power_final_kernel(int nlines, const double *partial, double *out) {
+    const int line = threadIdx.x;
+    if (line >= nlines) return;
+    double s = 0.0;
+    for (int b = 0; b < kPowBlocks; ++b) s += partial[line * kPowBlocks + b];
+    out[line] = s;
 }
 
 extern "C" int krt_levels_update(krt_ctx *c, const krt_levels_desc *d, const float *jbar_dev) {
@@ -685,7 +739,23 @@ extern "C" int krt_levels_update(krt_ctx *c, const krt_levels_desc *d, const flo
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, hipMemcpyAsync(c->level_consts, K.data(), sizeof(double) * K.size(), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, launch_levels(nl, d->ncell, c->level_consts, d->ncoll_dev, d->ntot_dev, jbar_dev, d->pops_dev,
-                            d->k0_out_dev, d->eps_out_dev, c->stream));
+                            d->k0_out_dev, d->eps_out_dev, d->emis_out_dev, c->stream));
+    if (d->lum_out) {
+        if (!(d->cell_volume > 0.0) || !std::isfinite(d->cell_volume))
+            return fail(c, KRT_EINVAL, "lum_out needs a finite cell_volume > 0");
+        if (!c->level_power) HIPCHK(c, hipMalloc(&c->level_power, sizeof(double) * 8 * (kPowBlocks + 1)));
+        double *partial = c->level_power, *sums = c->level_power + 8 * kPowBlocks;
+        hipLaunchKernelGGL(line_power_partial_kernel, dim3(kPowBlocks, nl - 1), dim3(256), 0, c->stream, nl,
+                           (int64_t)d->ncell, (const double *)c->level_consts, (const double *)d->pops_dev, partial);
+        HIPCHK(c, hipGetLastError());
+        hipLaunchKernelGGL(line_power_final_kernel, dim3(1), dim3(64), 0, c->stream, nl - 1, (const double *)partial,
+                           sums);
+        HIPCHK(c, hipGetLastError());
+        double host[8];
+        HIPCHK(c, hipMemcpyAsync(host, sums, sizeof(double) * (nl - 1), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int l = 0; l + 1 < nl; ++l) d->lum_out[l] = host[l] * d->cell_volume;
+    }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return KRT_OK;
 }
@@ -758,6 +828,7 @@ int mlp_alloc(krt_ctx *c) {
     HIPCHK(c, hipMalloc(&c->mlp_calsum, sizeof(double) * 3 * kNCal));
     HIPCHK(c, hipMalloc(&c->mlp_v, sizeof(float) * kNParams));
     HIPCHK(c, hipMalloc(&c->mlp_g, sizeof(float) * kNParams));
+    HIPCHK(c, hipMalloc(&c->mlp_part, sizeof(float) * kNParams * kGradSplits));
     HIPCHK(c, hipMalloc(&c->mlp_norm, sizeof(float) * kNNorm));
     HIPCHK(c, hipMalloc(&c->mlp_loss, sizeof(float) * 2));
     HIPCHK(c, hipMalloc(&c->mlp_blob, kMlpBlobBytes));
@@ -768,19 +839,26 @@ int mlp_alloc(krt_ctx *c) {
 int mlp_zero_state(krt_ctx *c) {
     HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(c->mlp_m), kNParams / 2, c->stream));
     HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(c->mlp_v), kNParams / 2, c->stream));
-    HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(c->mlp_g), kNParams / 2, c->stream));
     c->mlp_step = 0;
     return KRT_OK;
 }
 
+// batch buffers: indices, levels [batch][5] and the activation store with
+// room for the batch rounded up to 32 samples
 int mlp_ensure_batch(krt_ctx *c, int batch) {
     if (batch <= c->mlp_batch_cap) return KRT_OK;
-    if (c->mlp_idx) (void)hipFree(c->mlp_idx);
-    if (c->mlp_u) (void)hipFree(c->mlp_u);
+    for (void *p : {(void *)c->mlp_idx, (void *)c->mlp_u, (void *)c->mlp_act})
+        if (p) (void)hipFree(p);
     c->mlp_idx = nullptr;
     c->mlp_u = nullptr;
+    c->mlp_act = nullptr;
+    c->mlp_batch_cap = 0;
+    const int64_t cap = 32 * (((int64_t)batch + 31) / 32);
     HIPCHK(c, hipMalloc(&c->mlp_idx, sizeof(int32_t) * batch));
-    HIPCHK(c, hipMalloc(&c->mlp_u, sizeof(float) * 4 * (size_t)batch));
+    HIPCHK(c, hipMalloc(&c->mlp_u, sizeof(float) * 5 * (size_t)batch));
+    HIPCHK(c, hipMalloc(&c->mlp_act, sizeof(uint16_t) * (size_t)kActRowsAll * cap));
+    HIPCHK(c, launch_mlp_act_init(c->mlp_act, cap, c->stream));
+    c->mlp_act_cap = cap;
     c->mlp_batch_cap = batch;
     return KRT_OK;
 }
@@ -791,11 +869,14 @@ static_assert(kNParams % 2 == 0, "parameter count is even (zeroed as int64 pairs
 // Host copy of the log10 a range stored in the normalisation block (after a
 // fit or a weight upload); synchronises the library stream.
 static int read_a_range(krt_ctx *c) {
-    float r[2];
+    float r[5];
     HIPCHK(c, hipMemcpyAsync(r, c->mlp_norm + kNormARange, sizeof(r), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->esc_la_lo = r[0];
     c->esc_la_hi = r[1];
+    c->esc_lt_lo = r[2];
+    c->esc_lt_hi = r[3];
+    c->esc_ld_min = r[4];
     return KRT_OK;
 }
 
@@ -810,10 +891,15 @@ extern "C" int krt_escape_init(krt_ctx *c, uint64_t seed) {
     float norm[kNNorm];
     for (int k = 0; k < kNNorm; ++k) norm[k] = 0.0f;
     for (int k = 0; k < kMlpOut; ++k) norm[kMlpOut + k] = 1.0f;
-    norm[kNormARange] = 1.0f;  // empty range until krt_escape_fit_norm
+    norm[kNormARange] = 1.0f;  // empty ranges until krt_escape_fit_norm
     norm[kNormARange + 1] = -1.0f;
+    norm[kNormTauRange] = 1.0f;
+    norm[kNormTauRange + 1] = -1.0f;
     c->esc_la_lo = 1.0f;
     c->esc_la_hi = -1.0f;
+    c->esc_lt_lo = 1.0f;
+    c->esc_lt_hi = -1.0f;
+    c->esc_ld_min = 0.0f;
     HIPCHK(c, hipMemcpyAsync(c->mlp_norm, norm, sizeof(norm), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, launch_mlp_pack(c->mlp_p, c->mlp_norm, c->mlp_blob, c->mlp_img, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -822,18 +908,43 @@ extern "C" int krt_escape_init(krt_ctx *c, uint64_t seed) {
 }
 
 extern "C" int krt_escape_record(krt_ctx *c, int32_t line, uint64_t n, uint64_t seed, uint64_t offset,
-                                 double log10_tau_lo, double log10_tau_hi, int32_t x_fixed, double x_in,
-                                 float *samples_dev) {
+                                 const krt_escape_cond *cond, float *samples_dev) {
     if (!c) return KRT_EINVAL;
     if (line < 0 || line >= (int)c->tab.size()) return fail(c, KRT_ESTATE, "line %d has no tables", line);
-    if (!samples_dev || n == 0 || n > (1ull << 31)) return fail(c, KRT_EINVAL, "bad record args");
-    if (!(log10_tau_hi >= log10_tau_lo) || log10_tau_lo < 0.0 || log10_tau_hi > 6.0)
-        return fail(c, KRT_EINVAL, "log10 tau range must lie in [0, 6]");
+    if (!samples_dev || !cond || n == 0 || n > (1ull << 31)) return fail(c, KRT_EINVAL, "bad record args");
+    if (!(cond->log10_tau_hi >= cond->log10_tau_lo) || cond->log10_tau_lo < 0.0 || cond->log10_tau_hi > 6.0)
+        return fail(c, KRT_EINVAL, "log10 tau_c range must lie in [0, 6]");
+    if (!(cond->log10_depth_lo >= -2.0 && cond->log10_depth_lo <= 6.0))
+        return fail(c, KRT_EINVAL, "log10_depth_lo outside [-2, 6]");
+    if (cond->fixed) {
+        const double *q = cond->q;
+        if (!(q[0] >= 0.0 && q[0] <= q[1] && q[1] <= q[2] && q[2] < 1.0))
+            return fail(c, KRT_EINVAL, "fixed start needs 0 <= q0 <= q1 <= q2 < 1");
+        if (!(cond->x_in >= 0.0 && cond->x_in <= 50.0)) return fail(c, KRT_EINVAL, "fixed x_in outside [0, 50]");
+        const double nn = cond->n_in[0] * cond->n_in[0] + cond->n_in[1] * cond->n_in[1] + cond->n_in[2] * cond->n_in[2];
+        if (!cond->iso_dir && !(std::fabs(nn - 1.0) < 1e-6)) return fail(c, KRT_EINVAL, "n_in must be a unit vector");
+    }
     HIPCHK(c, hipSetDevice(c->device));
-    float a = (float)c->lines[line].a, thd = (float)std::atan(kDelta / c->lines[line].a);
-    HIPCHK(c, launch_escape_record(c->tab[line], a, thd, (uint32_t)seed, (uint32_t)(seed >> 32), offset, (int64_t)n,
-                                   (float)log10_tau_lo, (float)log10_tau_hi, 4000000u, x_fixed ? 1 : 0, (float)x_in,
-                                   samples_dev, c->stream));
+    RecordParams R{};
+    R.tab = c->tab[line];
+    R.a = (float)c->lines[line].a;
+    R.thd = (float)std::atan(kDelta / c->lines[line].a);
+    R.k0 = (uint32_t)seed;
+    R.k1 = (uint32_t)(seed >> 32);
+    R.offset = offset;
+    R.n = n;
+    R.lt_lo = (float)cond->log10_tau_lo;
+    R.lt_hi = (float)cond->log10_tau_hi;
+    R.ld_lo = (float)cond->log10_depth_lo;
+    R.max_scat = 20000000u;
+    R.fixed = cond->fixed ? 1 : 0;
+    R.iso_dir = cond->iso_dir ? 1 : 0;
+    R.x_in = (float)cond->x_in;
+    for (int k = 0; k < 3; ++k) { R.q[k] = (float)cond->q[k]; R.n_in[k] = (float)cond->n_in[k]; }
+    R.counter = c->work_counter;
+    R.out = samples_dev;
+    HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(c->work_counter), 1, c->stream));
+    HIPCHK(c, launch_cell_record(R, 4 * c->cus, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return KRT_OK;
 }
@@ -845,8 +956,8 @@ extern "C" int krt_escape_fit_norm(krt_ctx *c, const float *samples_dev, uint64_
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, launch_mlp_norm(samples_dev, (int64_t)n, c->mlp_norm, c->stream));
     // a new normalisation invalidates the calibration of ln E[N_s]
-    static_assert(kMlpOut % 2 == 0 && kNCal % 2 == 0, "calibration block is int64-aligned");
-    HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(c->mlp_norm + 2 * kMlpOut), kNCal / 2, c->stream));
+    static_assert(kNormCal % 2 == 0 && kNCal % 2 == 0, "calibration block is int64-aligned");
+    HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(c->mlp_norm + kNormCal), kNCal / 2, c->stream));
     HIPCHK(c, launch_mlp_pack(c->mlp_p, c->mlp_norm, c->mlp_blob, c->mlp_img, c->stream));
     return read_a_range(c);
 }
@@ -871,12 +982,13 @@ extern "C" int krt_escape_grad(krt_ctx *c, const float *samples_dev, const int32
     if (!samples_dev || !idx_dev || !u_dev || !grad_out_dev || batch <= 0 || batch > (1 << 20))
         return fail(c, KRT_EINVAL, "bad grad args");
     HIPCHK(c, hipSetDevice(c->device));
-    HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(c->mlp_g), kNParams / 2, c->stream));
+    int rc = mlp_ensure_batch(c, batch);
+    if (rc) return rc;
     HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(c->mlp_loss), 1, c->stream));
-    HIPCHK(c, launch_mlp_grad(c->mlp_blob, samples_dev, idx_dev, u_dev, batch, c->mlp_g, c->mlp_loss, c->stream));
-    HIPCHK(c, hipMemcpyAsync(grad_out_dev, c->mlp_g, sizeof(float) * kNParams, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, launch_mlp_grad(c->mlp_blob, samples_dev, idx_dev, u_dev, batch, c->mlp_act, c->mlp_act_cap,
+                              c->mlp_part, c->mlp_loss, c->stream));
+    HIPCHK(c, launch_mlp_gsum(c->mlp_part, grad_out_dev, c->stream));
     if (loss_out_dev) HIPCHK(c, hipMemcpyAsync(loss_out_dev, c->mlp_loss, sizeof(float), hipMemcpyDeviceToDevice, c->stream));
-    HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(c->mlp_g), kNParams / 2, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return KRT_OK;
 }
@@ -896,11 +1008,11 @@ extern "C" int krt_escape_train(krt_ctx *c, const float *samples_dev, uint64_t n
         HIPCHK(c, launch_mlp_batch((int64_t)n, (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)c->mlp_step, batch,
                                    c->mlp_idx, c->mlp_u, c->stream));
         float *lslot = loss_hist_dev ? loss_hist_dev + s : c->mlp_loss;
-        HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(c->mlp_loss), 1, c->stream));
-        HIPCHK(c, launch_mlp_grad(c->mlp_blob, samples_dev, c->mlp_idx, c->mlp_u, batch, c->mlp_g, c->mlp_loss,
-                                  c->stream));
+        if (loss_hist_dev) HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(c->mlp_loss), 1, c->stream));
+        HIPCHK(c, launch_mlp_grad(c->mlp_blob, samples_dev, c->mlp_idx, c->mlp_u, batch, c->mlp_act, c->mlp_act_cap,
+                                  c->mlp_part, loss_hist_dev ? c->mlp_loss : nullptr, c->stream));
         if (loss_hist_dev) HIPCHK(c, hipMemcpyAsync(lslot, c->mlp_loss, sizeof(float), hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, launch_mlp_adam(c->mlp_p, c->mlp_m, c->mlp_v, c->mlp_g, (float)lr, c->mlp_step, c->stream));
+        HIPCHK(c, launch_mlp_adam(c->mlp_p, c->mlp_m, c->mlp_v, c->mlp_part, (float)lr, c->mlp_step, c->stream));
         HIPCHK(c, launch_mlp_pack(c->mlp_p, c->mlp_norm, c->mlp_blob, (s == steps - 1) ? c->mlp_img : nullptr,
                                   c->stream));
     }

@@ -1,15 +1,15 @@
-// krt_escape.hip -- learned escape proposal: training data from single-cell
-// escapes run by the plain transport arithmetic, BF16-MFMA training (forward,
-// backward, Adam) and batched inference.
+// krt_escape.hip -- learned whole-cell escape: training data from single-cell
+// walks run with the plain transport arithmetic, BF16-MFMA training (forward
+// and backward per 16-sample block, weight gradients as a split-K product over
+// the stored activations, Adam) and batched inference for tests.
 //
-// Single-cell escape (training data): a homogeneous static cube of half-width 1
-// and line-centre opacity k0 = tau_R per unit length; a photon of gas-frame
-// frequency x_in and isotropic incoming direction scatters at the centre, then
-// random-walks (the same flights and resonant scatterings as the transport
-// kernel) until it leaves the cube.  Recorded: the exit frequency, the exit
-// point (s, t) on the exit face (the face's two tangential coordinates in cyclic
-// order), the cosine mu of the exit direction to the face normal, the number of
-// scatterings N_s and the mean of x^2 over them.
+// Whole-cell walk (training data): a homogeneous static cube [-1, 1]^3 (units
+// of its half-width) of line-centre opacity tau_c per unit length; a photon of
+// gas-frame frequency x_in >= 0 arriving along n_in scatters at a start point
+// q in the reduced frame (0 <= q0 <= q1 <= q2 < 1), then takes the transport's
+// flights and resonant scatterings (isotropic phase) until it leaves.  The
+// record is the condition and the exit (face, offsets, cosine, alpha, x_out),
+// the number of scatterings N_s and the mean x^2 over them.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -21,114 +21,166 @@
 namespace krt {
 
 // ------------------------------------------------------------- recording ---
-// record: [log10 tau_R, log10 a, x_in, x_out, s, t, mu, ln N_s, ln <x^2>, valid]
-
-__global__ void __launch_bounds__(256) escape_record_kernel(const float *tab, float a, float thd, uint32_t k0,
-                                                            uint32_t k1, uint64_t offset, int64_t n,
-                                                            float lt_lo, float lt_hi, uint32_t max_scat,
-                                                            int x_fixed, float x_value, float *out) {
+// Persistent pool: each lane takes record indices from one wave-aggregated
+// atomic on `counter` (zeroed by the caller) and walks one event per loop
+// iteration, so records of very different lengths share waves without idling.
+__global__ void __launch_bounds__(256) cell_record_kernel(RecordParams R) {
     extern __shared__ float4 lds4[];
     float *T = reinterpret_cast<float *>(lds4);
-    const float4 *src = reinterpret_cast<const float4 *>(tab);
+    const float4 *src = reinterpret_cast<const float4 *>(R.tab);
     for (int i = threadIdx.x; i < kTabFloats / 4; i += blockDim.x) lds4[i] = src[i];
     __syncthreads();
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint64_t pid = offset + (uint64_t)i;
-    const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
-    // condition: purpose 3 of event 0
-    uint4 c = philox(make_uint4(0u, plo, phi, 3u), k0, k1);
-    float lt = lt_lo + (lt_hi - lt_lo) * u01(c.x);
-    float tauR = f_exp(lt * 2.302585093f);
-    float xin;
-    if (x_fixed) {
-        xin = x_value;
-    } else if (u01(c.y) < 0.5f) {
-        float rr = f_sqrt(-f_log(u01(c.z)));
-        xin = rr * cos_rev(u01(c.w));
-    } else {
-        xin = kRecXMax * (2.0f * u01(c.z) - 1.0f);
-    }
-    uint4 d = philox(make_uint4(0u, plo, phi, 4u), k0, k1);
-    float mu0 = 2.0f * u01(d.x) - 1.0f, st0 = f_sqrt(fmaxf(0.0f, 1.0f - mu0 * mu0)), ph0 = u01(d.y);
-    float nx = st0 * cos_rev(ph0), ny = st0 * sin_rev(ph0), nz = mu0;
-    float px = 0.0f, py = 0.0f, pz = 0.0f;
-    float x = xin;  // gas frame = lab frame (static)
-    uint32_t ns = 0;
-    float sx2 = 0.0f;
-    bool done = false, valid = false;
-    int ax = 0;
-    for (uint32_t ev = 1; ev <= max_scat + 1; ++ev) {
+    const int lane = __lane_id();
+    const uint64_t lanemask_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const float la = __log10f(R.a);
+    bool have = false, done = false;
+    uint64_t idx = 0, pid = 0;
+    float lt = 0.f, tauc = 0.f, xin = 0.f, q0 = 0.f, q1 = 0.f, q2 = 0.f;
+    float m0 = 0.f, m1 = 0.f, m2 = 1.f;
+    float px = 0.f, py = 0.f, pz = 0.f, nx = 0.f, ny = 0.f, nz = 1.f, x = 0.f, sx2 = 0.f;
+    uint32_t ev = 0, ns = 0;
+    for (;;) {
+        const bool need = !have && !done;
+        const uint64_t need_mask = __ballot(need);
+        if (need_mask) {
+            const int leader = __ffsll((long long)need_mask) - 1;
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd(R.counter, (unsigned long long)__popcll(need_mask));
+            base = __shfl(base, leader, 64);
+            if (need) {
+                idx = base + (uint64_t)__popcll(need_mask & lanemask_lt);
+                if (idx >= R.n) {
+                    done = true;
+                } else {
+                    pid = R.offset + idx;
+                    const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
+                    const uint4 c = philox(make_uint4(0u, plo, phi, 3u), R.k0, R.k1);
+                    const uint4 d = philox(make_uint4(0u, plo, phi, 4u), R.k0, R.k1);
+                    const uint4 e = philox(make_uint4(0u, plo, phi, 5u), R.k0, R.k1);
+                    lt = R.lt_lo + (R.lt_hi - R.lt_lo) * u01(c.x);
+                    tauc = f_exp(lt * 2.302585093f);
+                    if (R.fixed) {
+                        xin = R.x_in;
+                        q0 = R.q[0]; q1 = R.q[1]; q2 = R.q[2];
+                    } else {
+                        // |x_in| from 1/2 N(0, 1/2) + 1/2 U[-3, 3]
+                        if (u01(c.y) < 0.5f) xin = fabsf(f_sqrt(-f_log(u01(c.z))) * cos_rev(u01(c.w)));
+                        else xin = kRecXMax * u01(c.z);
+                        // depth to the nearest face log-uniform in [depth_lo, tau_c]
+                        const float ld = fminf(R.ld_lo, lt) + (lt - fminf(R.ld_lo, lt)) * u01(e.x);
+                        q2 = fminf(fmaxf(1.0f - f_exp((ld - lt) * 2.302585093f), 0.0f), 0.99999f);
+                        float a0 = q2 * u01(e.y), a1 = q2 * u01(e.z);
+                        q0 = fminf(a0, a1);
+                        q1 = fmaxf(a0, a1);
+                    }
+                    if (R.fixed && !R.iso_dir) {
+                        m0 = R.n_in[0]; m1 = R.n_in[1]; m2 = R.n_in[2];
+                    } else {
+                        const float mu0 = 2.0f * u01(d.x) - 1.0f, st0 = f_sqrt(fmaxf(0.0f, 1.0f - mu0 * mu0));
+                        const float ph0 = u01(d.y);
+                        m0 = st0 * cos_rev(ph0); m1 = st0 * sin_rev(ph0); m2 = mu0;
+                    }
+                    px = q0; py = q1; pz = q2;
+                    nx = m0; ny = m1; nz = m2;
+                    x = xin;
+                    sx2 = 0.0f;
+                    ns = 0;
+                    ev = 1;
+                    have = true;
+                }
+            }
+        }
+        if (__ballot(have) == 0ull) break;
+        if (!have) continue;
+        const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
+        const uint4 A = philox(make_uint4(ev, plo, phi, 0u), R.k0, R.k1);
+        bool exited = false;
+        int ax = 0;
         if (ev > 1) {
-            // flight from the current interaction point
-            uint4 A = philox(make_uint4(ev, plo, phi, 0u), k0, k1);
-            float tau = -f_log(u01(A.x));
-            float kap = tauR * voigt_lds(T, fabsf(x));
-            float tx = (nx > 0.f) ? (1.f - px) * f_rcp(nx) : ((nx < 0.f) ? (-1.f - px) * f_rcp(nx) : INFINITY);
-            float ty = (ny > 0.f) ? (1.f - py) * f_rcp(ny) : ((ny < 0.f) ? (-1.f - py) * f_rcp(ny) : INFINITY);
-            float tz = (nz > 0.f) ? (1.f - pz) * f_rcp(nz) : ((nz < 0.f) ? (-1.f - pz) * f_rcp(nz) : INFINITY);
-            float dm = tx; ax = 0;
+            // flight from the last interaction point
+            const float tau = -f_log(u01(A.x));
+            const float kap = tauc * voigt_lds(T, fabsf(x));
+            const float tx = (nx > 0.f) ? (1.f - px) * f_rcp(nx) : ((nx < 0.f) ? (-1.f - px) * f_rcp(nx) : INFINITY);
+            const float ty = (ny > 0.f) ? (1.f - py) * f_rcp(ny) : ((ny < 0.f) ? (-1.f - py) * f_rcp(ny) : INFINITY);
+            const float tz = (nz > 0.f) ? (1.f - pz) * f_rcp(nz) : ((nz < 0.f) ? (-1.f - pz) * f_rcp(nz) : INFINITY);
+            float dm = tx;
             if (ty < dm) { dm = ty; ax = 1; }
             if (tz < dm) { dm = tz; ax = 2; }
             dm = fmaxf(dm, 0.0f);
-            if (kap * dm < tau) {  // leaves the cube
+            if (kap * dm < tau) {
                 px += dm * nx; py += dm * ny; pz += dm * nz;
-                done = true;
-                valid = true;
-                break;
+                exited = true;
+            } else {
+                const float l = tau * f_rcp(kap);
+                px = fminf(fmaxf(px + l * nx, -1.f), 1.f);
+                py = fminf(fmaxf(py + l * ny, -1.f), 1.f);
+                pz = fminf(fmaxf(pz + l * nz, -1.f), 1.f);
             }
-            float l = tau * f_rcp(kap);
-            px = fminf(fmaxf(px + l * nx, -1.f), 1.f);
-            py = fminf(fmaxf(py + l * ny, -1.f), 1.f);
-            pz = fminf(fmaxf(pz + l * nz, -1.f), 1.f);
         }
-        // resonant scattering at (px, py, pz): event ev words
-        uint4 A = philox(make_uint4(ev, plo, phi, 0u), k0, k1);
-        uint4 B = philox(make_uint4(ev, plo, phi, 1u), k0, k1);
-        float upar = upar_lds(T, x, a, thd, u01(A.z), u01(A.w));
-        float rr = f_sqrt(-f_log(u01(B.x)));
-        float th = u01(B.y);
-        float up1 = rr * cos_rev(th), up2 = rr * sin_rev(th);
-        float g = 2.0f * u01(B.z) - 1.0f;
-        float psi = u01(B.w);
-        float sg = f_sqrt(fmaxf(0.0f, 1.0f - g * g));
-        float sgn = copysignf(1.0f, nz);
-        float A_ = -f_rcp(sgn + nz);
-        float B_ = nx * ny * A_;
-        float e1x = 1.0f + sgn * nx * nx * A_, e1y = sgn * B_, e1z = -sgn * nx;
-        float e2x = B_, e2y = sgn + ny * ny * A_, e2z = -ny;
-        float cp = cos_rev(psi), sp = sin_rev(psi);
-        float ox = g * nx + sg * (cp * e1x + sp * e2x);
-        float oy = g * ny + sg * (cp * e1y + sp * e2y);
-        float oz = g * nz + sg * (cp * e1z + sp * e2z);
-        float rn = f_rsq(ox * ox + oy * oy + oz * oz);
-        sx2 += x * x;
-        x = x + upar * (g - 1.0f) + sg * (up1 * cp + up2 * sp);
-        nx = ox * rn; ny = oy * rn; nz = oz * rn;
-        ns += 1;
+        if (!exited) {
+            // resonant scattering (isotropic phase), event ev's words
+            const uint4 B = philox(make_uint4(ev, plo, phi, 1u), R.k0, R.k1);
+            const float upar = upar_lds(T, x, R.a, R.thd, u01(A.z), u01(A.w));
+            const float rr = f_sqrt(-f_log(u01(B.x)));
+            const float th = u01(B.y);
+            const float up1 = rr * cos_rev(th), up2 = rr * sin_rev(th);
+            const float g = 2.0f * u01(B.z) - 1.0f;
+            const float psi = u01(B.w);
+            const float sg = f_sqrt(fmaxf(0.0f, 1.0f - g * g));
+            const float sgn = copysignf(1.0f, nz);
+            const float A_ = -f_rcp(sgn + nz);
+            const float B_ = nx * ny * A_;
+            const float e1x = 1.0f + sgn * nx * nx * A_, e1y = sgn * B_, e1z = -sgn * nx;
+            const float e2x = B_, e2y = sgn + ny * ny * A_, e2z = -ny;
+            const float cp = cos_rev(psi), sp = sin_rev(psi);
+            const float ox = g * nx + sg * (cp * e1x + sp * e2x);
+            const float oy = g * ny + sg * (cp * e1y + sp * e2y);
+            const float oz = g * nz + sg * (cp * e1z + sp * e2z);
+            const float rn = f_rsq(ox * ox + oy * oy + oz * oz);
+            sx2 += x * x;
+            x = x + upar * (g - 1.0f) + sg * (up1 * cp + up2 * sp);
+            nx = ox * rn; ny = oy * rn; nz = oz * rn;
+            ns += 1;
+            ev += 1;
+        }
+        const bool capped = !exited && ns > R.max_scat;
+        if (exited || capped) {
+            float *o = R.out + (int64_t)kRec * idx;
+            o[kRecLT] = lt;
+            o[kRecLA] = la;
+            o[kRecX] = xin;
+            o[kRecQ0] = q0; o[kRecQ0 + 1] = q1; o[kRecQ0 + 2] = q2;
+            o[kRecLD] = lt + __log10f(fmaxf(1.0f - q2, 1e-30f));
+            o[kRecN0] = m0; o[kRecN0 + 1] = m1; o[kRecN0 + 2] = m2;
+            if (exited) {
+                const float qq[3] = {q0, q1, q2}, P[3] = {px, py, pz}, N[3] = {nx, ny, nz};
+                float side = 0.f, dpl = 1.f, ds = 0.f, dt = 0.f, n1 = 0.f, n2 = 0.f, nn = 0.f;
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    if (k == ax) {
+                        const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+                        side = N[k] > 0.f ? 1.f : -1.f;
+                        dpl = 1.f - side * qq[k];
+                        ds = fminf(fmaxf(P[k1], -1.f), 1.f) - qq[k1];
+                        dt = fminf(fmaxf(P[k2], -1.f), 1.f) - qq[k2];
+                        n1 = N[k1]; n2 = N[k2]; nn = N[k];
+                    }
+                o[kRecFace] = (float)(2 * ax + (side > 0.f ? 1 : 0));
+                o[kRecYS] = ds / dpl;
+                o[kRecYT] = dt / dpl;
+                o[kRecMu] = fabsf(nn);
+                o[kRecAlpha] = atan2f(fabsf(ds * n2 - dt * n1), ds * n1 + dt * n2);
+                o[kRecXOut] = x;
+                o[kRecLogN] = logf((float)ns);
+                o[kRecLogX2] = logf(fmaxf(sx2 / (float)ns, 1e-6f));
+                o[kRecValid] = 1.0f;
+            } else {
+                for (int k = kRecFace; k <= kRecValid; ++k) o[k] = 0.0f;
+            }
+            o[kRec - 1] = 0.0f;
+            have = false;
+        }
     }
-    float *o = out + (int64_t)kRec * i;
-    o[0] = lt;
-    o[1] = __log10f(a);
-    o[2] = xin;
-    if (valid) {
-        // exit face: axis ax, sign of the normal; tangential coordinates in cyclic order
-        float p[3] = {px, py, pz}, nn[3] = {nx, ny, nz};
-        int a1 = (ax + 1) % 3, a2 = (ax + 2) % 3;
-        const float es = fminf(fmaxf(p[a1], -1.f), 1.f), et = fminf(fmaxf(p[a2], -1.f), 1.f);
-        o[kRecXOut] = x;
-        o[kRecS] = es;
-        o[kRecT] = et;
-        o[kRecMu] = fabsf(nn[ax]);
-        o[kRecLogN] = logf((float)ns);
-        o[kRecLogX2] = logf(fmaxf(sx2 / (float)ns, 1e-6f));
-        o[kRecValid] = 1.0f;
-        // angle between the direction's tangential part and the offset (s, t)
-        o[kRecAlpha] = atan2f(fabsf(es * nn[a2] - et * nn[a1]), es * nn[a1] + et * nn[a2]);
-    } else {
-        for (int k = 3; k < kRec; ++k) o[k] = 0.0f;
-    }
-    (void)done;
 }
 
 // ---------------------------------------------------------- parameters ---
@@ -138,7 +190,7 @@ __global__ void mlp_init_kernel(float *p, uint32_t k0, uint32_t k1) {
     if (i >= kNParams) return;
     uint4 r = philox(make_uint4((uint32_t)i, 0u, 0u, 7u), k0, k1);
     float u = 2.0f * u01(r.x) - 1.0f;
-    float fan_in;
+    float fan_in = 0.0f;
     bool bias = false;
     if (i < kPB1) fan_in = kMlpIn;
     else if (i < kPW2) bias = true;
@@ -151,50 +203,50 @@ __global__ void mlp_init_kernel(float *p, uint32_t k0, uint32_t k1) {
     p[i] = bias ? 0.0f : u * sqrtf(6.0f / fan_in);
 }
 
-// Pack the FP32 master parameters into BF16 A-operand tiles + FP32 biases.
+// Pack the FP32 master parameters into BF16 A-operand tiles (with the chunk
+// permutation kperm of the reduction index) + FP32 biases + normalisation.
 // One thread per (tile, lane).
 __global__ void mlp_pack_kernel(const float *p, const float *norm, unsigned char *blob) {
-    int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
     if (gid < kTilesAll * 64) {
-        int t = gid / 64, lane = gid % 64;
-        int i = lane % 16, g = lane / 16;
-        float v[4];
-        for (int j = 0; j < 4; ++j) {
-            int k = 4 * g + j;
+        const int t = gid / 64, lane = gid % 64;
+        const int i = lane % 16, g = lane / 16;
+        uint16_t *dst = reinterpret_cast<uint16_t *>(blob + t * kTileBytes + lane * 16);
+        for (int j = 0; j < 8; ++j) {
+            const int kp = 8 * g + j;  // reduction slot
             float w = 0.0f;
-            if (t < kTileFwdL2) {  // L1 fwd: W1^T tile mo = t, A[i][k] = W1[k][16mo+i]
-                int mo = t - kTileFwdL1;
-                if (k < kMlpIn) w = p[kPW1 + k * kMlpHid + 16 * mo + i];
-            } else if (t < kTileFwdL4) {  // L2/L3 fwd: tile mo*8+ki, A[i][k] = W[16ki+k][16mo+i]
-                int base = (t < kTileFwdL3) ? kPW2 : kPW3;
-                int tt = t - ((t < kTileFwdL3) ? kTileFwdL2 : kTileFwdL3);
-                int mo = tt / 8, ki = tt % 8;
-                w = p[base + (16 * ki + k) * kMlpHid + 16 * mo + i];
-            } else if (t < kTilesFwd) {  // L4 fwd: tile ki, A[i][k] = W4[16ki+k][i]
-                int ki = t - kTileFwdL4;
-                if (i < kMlpOut) w = p[kPW4 + (16 * ki + k) * kMlpOut + i];
-            } else if (t < kTileBwdL3) {  // L4 bwd: tile mi, A[i][k] = W4[16mi+i][k]
-                int mi = t - kTileBwdL4;
-                if (k < kMlpOut) w = p[kPW4 + (16 * mi + i) * kMlpOut + k];
-            } else {  // L3/L2 bwd: tile mi*8+ko, A[i][k] = W[16mi+i][16ko+k]
-                int base = (t < kTileBwdL2) ? kPW3 : kPW2;
-                int tt = t - ((t < kTileBwdL2) ? kTileBwdL3 : kTileBwdL2);
-                int mi = tt / 8, ko = tt % 8;
-                w = p[base + (16 * mi + i) * kMlpHid + 16 * ko + k];
+            if (t < kTileFwdL2) {  // L1 fwd: W1^T, inputs in natural order
+                const int mo = t - kTileFwdL1;
+                if (kp < kMlpIn) w = p[kPW1 + kp * kMlpHid + 16 * mo + i];
+            } else if (t < kTileFwdL4) {  // L2/L3 fwd: tile mo*4+c, A[i][k'] = W[kperm(c,k')][16mo+i]
+                const int base = (t < kTileFwdL3) ? kPW2 : kPW3;
+                const int tt = t - ((t < kTileFwdL3) ? kTileFwdL2 : kTileFwdL3);
+                const int mo = tt / 4, c = tt % 4;
+                w = p[base + kperm(c, kp) * kMlpHid + 16 * mo + i];
+            } else if (t < kTilesFwd) {  // L4 fwd: tile c, A[i][k'] = W4[kperm(c,k')][i]
+                const int c = t - kTileFwdL4;
+                w = p[kPW4 + kperm(c, kp) * kMlpOut + i];
+            } else if (t < kTileBwdL3) {  // L4 bwd: tile mi, A[i][k'] = W4[16mi+i][kperm(0,k')] (outputs < 16)
+                const int mi = t - kTileBwdL4;
+                const int o = kperm(0, kp);
+                if (o < kMlpOut) w = p[kPW4 + (16 * mi + i) * kMlpOut + o];
+            } else {  // L3/L2 bwd: tile mi*4+c, A[i][k'] = W[16mi+i][kperm(c,k')]
+                const int base = (t < kTileBwdL2) ? kPW3 : kPW2;
+                const int tt = t - ((t < kTileBwdL2) ? kTileBwdL3 : kTileBwdL2);
+                const int mi = tt / 4, c = tt % 4;
+                w = p[base + (16 * mi + i) * kMlpHid + kperm(c, kp)];
             }
-            v[j] = w;
+            dst[j] = f2bf(w);
         }
-        uint16_t *dst = reinterpret_cast<uint16_t *>(blob + t * kTileBytes + lane * 8);
-        for (int j = 0; j < 4; ++j) dst[j] = f2bf(v[j]);
     }
-    // biases and normalisation (fwd layout: b1 b2 b3 b4pad16 norm)
+    // biases and normalisation (b1 b2 b3 b4 norm)
     float *fb = reinterpret_cast<float *>(blob + kTilesAll * kTileBytes);
     if (gid < kBiasFloats) {
         float b;
         if (gid < 128) b = p[kPB1 + gid];
         else if (gid < 256) b = p[kPB2 + gid - 128];
         else if (gid < 384) b = p[kPB3 + gid - 256];
-        else b = (gid - 384 < kMlpOut) ? p[kPB4 + gid - 384] : 0.0f;
+        else b = p[kPB4 + gid - 384];
         fb[gid] = b;
     }
     if (gid < kNNorm) fb[kBiasFloats + gid] = norm[gid];
@@ -210,92 +262,98 @@ __global__ void mlp_fwd_image_kernel(const unsigned char *blob, unsigned char *i
     else if (i < tiles_b + tail_b) img[i] = blob[kTilesAll * kTileBytes + (i - tiles_b)];
 }
 
-// ------------------------------------------------------------- inputs ---
-// Marginal rows: (condition, L(u_a), L(u_b), L(u_c), 0, 0); conditional rows:
-// (condition, L(u_a), L(u_b), x_out / 4, sqrt2 r - 1, 1) with x_out the exit
-// frequency and r the exit point's distance from the face centre; L the level
-// encoding.  w is u_c or x_out.
-__device__ __forceinline__ void mlp_inputs(float lt, float la, float xin, float ua, float ub, float w, float r,
-                                           bool cond, float in[kMlpIn]) {
-    in[0] = (lt - 3.5f) * (1.0f / 1.5f);
-    in[1] = la + 3.0f;
-    in[2] = xin * 0.25f;
-    in[3] = level_in(ua);
-    in[4] = level_in(ub);
-    in[5] = cond ? 0.25f * w : level_in(w);
-    in[6] = cond ? 1.41421356f * r - 1.0f : 0.0f;
-    in[7] = cond ? 1.0f : 0.0f;
-}
-
-__device__ __forceinline__ v4i16 xin_operand(const float in[kMlpIn], int lane) {
-    return (lane < 16) ? pack4(in[0], in[1], in[2], in[3])
-                       : (lane < 32 ? pack4(in[4], in[5], in[6], in[7]) : pack4(0.f, 0.f, 0.f, 0.f));
-}
-
-// Record column of output k's target (the one-sided exit frequencies read the
-// signed x_out; the side label and the unused output have none).
+// Record column of output k's target (faces, side and the spare have none).
 __device__ __forceinline__ int target_col(int k) {
     switch (k) {
         case kOutXPos: case kOutXNeg: return kRecXOut;
-        case kOutS: return kRecS;
-        case kOutT: return kRecT;
-        case kOutMu: return kRecMu;
         case kOutLogN: return kRecLogN;
         case kOutLogX2: return kRecLogX2;
+        case kOutYS: return kRecYS;
+        case kOutYT: return kRecYT;
+        case kOutMu: return kRecMu;
         case kOutAlpha: return kRecAlpha;
         default: return -1;
     }
 }
 
-// Is output k trained on a conditional (true) or a marginal (false) row?
-__device__ __forceinline__ bool conditional_output(int k) { return k == kOutMu || k == kOutAlpha; }
+__device__ __forceinline__ bool conditional_output(int k) { return k >= kOutYS && k <= kOutAlpha; }
 
-// ---------------------------------------------------------- gradient ---
-// One wave per 16-sample block.  grad += d(mean loss)/d(params); loss += sum.
-// Row si uses record idx[si] and uq[4 si ..] = (u_a, u_b, u_c, conditional flag);
-// a conditional row takes the record's exit frequency and point as inputs.
-// Quantile outputs: pinball loss at their own level (the two one-sided
-// exit-frequency quantiles only on records of their side); ln N_s:
-// log-deviance; side: logistic.  Marginal rows train outputs 0-2 and 4-7,
-// conditional rows outputs 3 and 8.
-__global__ void __launch_bounds__(256) mlp_grad_kernel(const unsigned char *blob, const float *rec,
-                                                       const int32_t *idx, const float *uq, int batch,
-                                                       float *grad, float *loss) {
-    __shared__ uint16_t tr[4][16][16 * 16 + 8];  // per wave: 16 transposed tiles (8 H + 8 dZ)
+// ----------------------------------------------------- forward + backward ---
+// Activation store of a training step, bf16 [row][cap] (samples contiguous):
+// H0 32 rows (inputs, row 24 = 1 for the bias), H1..H3 144 rows (SiLU
+// activations, row 128 = 1), dZ1..dZ3 128 rows, dZ4 16 rows.  The constant
+// rows are written once when the store is allocated.
+constexpr int kActRowsH0 = 32, kActRowsH = 144;
+constexpr int kActH0 = 0, kActH1 = kActH0 + kActRowsH0, kActH2 = kActH1 + kActRowsH, kActH3 = kActH2 + kActRowsH,
+              kActZ1 = kActH3 + kActRowsH, kActZ2 = kActZ1 + kMlpHid, kActZ3 = kActZ2 + kMlpHid,
+              kActZ4 = kActZ3 + kMlpHid, kActRows = kActZ4 + kMlpOut;   // 864
+static_assert(kActRows == kActRowsAll, "activation store layout");
+
+// One wave per 16-sample block.  Row si uses record idx[si] and uq[5 si ..] =
+// (u_a, u_b, u_c, u_d, 1 for a conditional row); a conditional row takes the
+// record's exit face and exit frequency as inputs.  Losses (each averaged over
+// the batch): softmax cross-entropy for the exit face, logistic for the side
+// of x_out, pinball for the quantiles at their own levels (the two one-sided
+// exit frequencies only on records of their side), log-deviance for ln N_s.
+// Marginal rows train outputs 0-10, conditional rows 11-14.  Samples past the
+// batch (up to the next multiple of 32) get zero gradients.
+__global__ void __launch_bounds__(256) mlp_fwdbwd_kernel(const unsigned char *blob, const float *rec,
+                                                         const int32_t *idx, const float *uq, int batch,
+                                                         uint16_t *act, int64_t cap, float *loss) {
     const int lane = __lane_id(), w = threadIdx.x / 64;
     const int block = blockIdx.x * (blockDim.x / 64) + w;
-    const int nblocks = (batch + 15) / 16;
-    const bool wave_live = block < nblocks;  // idle waves still reach every barrier
+    const int nblocks = 2 * ((batch + 31) / 32);
+    if (block >= nblocks) return;  // wave-uniform
     const int s = lane % 16, g = lane / 16;
     const int si = block * 16 + s;
-    const float *r0 = rec + (int64_t)kRec * idx[0];
-    const bool live = wave_live && si < batch && r0 != nullptr &&
-                      rec[(int64_t)kRec * idx[si < batch ? si : 0] + kRecValid] > 0.5f;
+    const int ri = (si < batch) ? idx[si] : idx[0];
+    const float *r = rec + (int64_t)kRec * ri;
+    const bool live = si < batch && r[kRecValid] > 0.5f;
     const float *bias = reinterpret_cast<const float *>(blob + kTilesAll * kTileBytes);
     const float *norm = bias + kBiasFloats;
-    const float *r = rec + (int64_t)kRec * (live ? idx[si] : idx[0]);
-    const float *ul = uq + 4 * (int64_t)(live ? si : 0);
-    const float ua = live ? ul[0] : 0.5f, ub = live ? ul[1] : 0.5f, uc = live ? ul[2] : 0.5f;
-    const bool cond = live && ul[3] > 0.5f;
+    const float *ul = uq + 5 * (int64_t)(si < batch ? si : 0);
+    const float ua = ul[0], ub = ul[1], uc = ul[2], ud = ul[3];
+    const bool cond = ul[4] > 0.5f;
     float in[kMlpIn];
-    mlp_inputs(r[0], r[1], r[2], ua, ub, cond ? r[kRecXOut] : uc, sqrtf(r[kRecS] * r[kRecS] + r[kRecT] * r[kRecT]),
-               cond, in);
+    mlp_inputs(r, ua, ub, uc, ud, cond, r[kRecXOut], (int)r[kRecFace], in);
     if (!live)
         for (int k = 0; k < kMlpIn; ++k) in[k] = 0.0f;
-    v4i16 xb = xin_operand(in, lane);
     v4f32 z1[8], z2[8], z3[8];
-    v4f32 o = mlp_forward_block(blob, bias, xb, lane, z1, z2, z3);
-    // per-output losses and their gradients for outputs k = 4g + j
+    const v4f32 o = mlp_forward_block(blob, bias, xin_operand(in, lane), lane, z1, z2, z3);
+    const float ov[4] = {o.x, o.y, o.z, o.w};
+    // the six face logits of this lane's sample (lanes s and s + 16)
+    float fl[6];
+    fl[0] = __shfl(o.x, s, 64); fl[1] = __shfl(o.y, s, 64); fl[2] = __shfl(o.z, s, 64); fl[3] = __shfl(o.w, s, 64);
+    fl[4] = __shfl(o.x, s + 16, 64); fl[5] = __shfl(o.y, s + 16, 64);
+    float mx = fl[0];
+#pragma unroll
+    for (int f = 1; f < 6; ++f) mx = fmaxf(mx, fl[f]);
+    float se = 0.0f, sm[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) { sm[f] = __expf(fl[f] - mx); se += sm[f]; }
+    const float ise = 1.0f / se;
+    const int face = (int)r[kRecFace];
+    float flf = 0.0f;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) if (f == face) flf = fl[f];
     const float invB = 1.0f / (float)batch;
     const float xo = r[kRecXOut];
     float dO[4], lsum = 0.0f;
+#pragma unroll
     for (int j = 0; j < 4; ++j) {
-        int k = 4 * g + j;
-        float oj = (j == 0) ? o.x : (j == 1) ? o.y : (j == 2) ? o.z : o.w;
+        const int k = 4 * g + j;
+        const float oj = ov[j];
         dO[j] = 0.0f;
-        if (k >= kMlpOut || k == kOutSpare || !live || conditional_output(k) != cond) continue;
-        if (k == kOutLogit) {
-            // side of the exit frequency: logistic loss, label 1{x_out >= 0}
+        if (!live || k == kOutSpare || conditional_output(k) != cond) continue;
+        if (k < 6) {
+            float smk = 0.0f;
+#pragma unroll
+            for (int f = 0; f < 6; ++f) if (f == k) smk = sm[f];
+            dO[j] = (smk * ise - (k == face ? 1.0f : 0.0f)) * invB;
+            if (k == 0) lsum += mx + __logf(se) - flf;
+            continue;
+        }
+        if (k == kOutSide) {
             const float b = (xo >= 0.0f) ? 1.0f : 0.0f;
             dO[j] = (sigmoid_f(oj) - b) * invB;
             lsum += fmaxf(oj, 0.0f) + __logf(1.0f + __expf(-fabsf(oj))) - b * oj;
@@ -303,7 +361,7 @@ __global__ void __launch_bounds__(256) mlp_grad_kernel(const unsigned char *blob
         }
         float raw;
         if (k == kOutXPos) {
-            if (xo < 0.0f) continue;  // one-sided: only records on this side
+            if (xo < 0.0f) continue;
             raw = xo;
         } else if (k == kOutXNeg) {
             if (xo >= 0.0f) continue;
@@ -312,133 +370,156 @@ __global__ void __launch_bounds__(256) mlp_grad_kernel(const unsigned char *blob
             raw = r[target_col(k)];
         }
         const float y = (raw - norm[k]) / norm[kMlpOut + k];
-        // quantile level of this output on this kind of row
-        const float u = (k == kOutS || k == kOutAlpha) ? ub : (k == kOutT ? uc : ua);
         if (k == kOutLogN) {
-            // ln E[N_s]: weighted, scaled log-deviance w f(d) / s4, d = s4 (y - o),
-            // f(d) = e^d - 1 - d, continued linearly beyond d = kDevClamp
-            const float s4 = norm[kMlpOut + k];
-            const float d = s4 * (y - oj);
+            // weighted, scaled log-deviance w f(d) / s, d = s (y - o), f(d) = e^d - 1 - d,
+            // continued linearly beyond d = kDevClamp
+            const float sc = norm[kMlpOut + k];
+            const float d = sc * (y - oj);
             const float dc = fminf(d, kDevClamp);
             const float ed = __expf(dc);
             dO[j] = kDevWeight * (1.0f - ed) * invB;
-            lsum += kDevWeight * (ed - 1.0f - dc + (__expf(kDevClamp) - 1.0f) * fmaxf(d - kDevClamp, 0.0f)) / s4;
-        } else {
-            const float ind = (y < oj) ? 1.0f : 0.0f;
-            dO[j] = (ind - u) * invB;
-            lsum += (y - oj) * (u - ind);
+            lsum += kDevWeight * (ed - 1.0f - dc + (__expf(kDevClamp) - 1.0f) * fmaxf(d - kDevClamp, 0.0f)) / sc;
+            continue;
         }
+        // quantile level of this output on its kind of row
+        float u;
+        if (k == kOutXPos || k == kOutXNeg || k == kOutYS) u = ua;
+        else if (k == kOutLogX2 || k == kOutYT) u = ub;
+        else if (k == kOutMu) u = uc;
+        else u = ud;
+        const float ind = (y < oj) ? 1.0f : 0.0f;
+        dO[j] = (ind - u) * invB;
+        lsum += (y - oj) * (u - ind);
     }
-    // loss: reduce over the wave
     for (int off = 32; off >= 1; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
-    if (lane == 0 && wave_live) atomicAdd(loss, lsum * invB);
-    v4i16 dOb = pack4(dO[0], dO[1], dO[2], dO[3]);
+    if (lane == 0 && loss) atomicAdd(loss, lsum * invB);
 
-    // helpers: write the 8 tiles of a (features x samples) quantity transposed
-    // into LDS as [feature][sample] bf16, read back sample-major A/B operands.
-    auto put = [&](int slot, int mo, float a0, float a1, float a2, float a3) {
-        uint16_t *t = &tr[w][slot][0];
-        (void)mo;
-        t[(4 * g + 0) * 16 + s] = f2bf(a0);
-        t[(4 * g + 1) * 16 + s] = f2bf(a1);
-        t[(4 * g + 2) * 16 + s] = f2bf(a2);
-        t[(4 * g + 3) * 16 + s] = f2bf(a3);
-    };
-    auto get = [&](int slot) -> v4i16 {  // lane l: row l%16 (feature), samples 4g..4g+3
-        const uint16_t *t = &tr[w][slot][0];
-        v4i16 v;
-        v.x = (short)t[s * 16 + 4 * g + 0];
-        v.y = (short)t[s * 16 + 4 * g + 1];
-        v.z = (short)t[s * 16 + 4 * g + 2];
-        v.w = (short)t[s * 16 + 4 * g + 3];
-        return v;
-    };
-    // weight gradient of one layer: dW[in][out] += sum_s Hin[in][s] dZ[out][s]
-    // (nin_t input tiles of activations, nout_t output tiles of dZ, already in LDS
-    // slots 0..nin_t-1 and 8..8+nout_t-1)
-    auto wgrad = [&](int nin_t, int nout_t, int base, int ld, int nin, int nout) {
-        for (int mi = 0; mi < nin_t; ++mi) {
-            v4i16 a = get(mi);
-            for (int mo = 0; mo < nout_t; ++mo) {
-                v4i16 b = get(8 + mo);
-                v4f32 acc = {0.f, 0.f, 0.f, 0.f};
-                acc = mfma16(a, b, acc);
-                // D lane l: rows (in) 4g+j, col (out) l%16
-                int outc = 16 * mo + s;
-                for (int j = 0; j < 4; ++j) {
-                    int inr = 16 * mi + 4 * g + j;
-                    float v = (j == 0) ? acc.x : (j == 1) ? acc.y : (j == 2) ? acc.z : acc.w;
-                    if (wave_live && inr < nin && outc < nout && v != 0.0f) atomicAdd(grad + base + inr * ld + outc, v);
-                }
-            }
-        }
-    };
-    auto bgrad = [&](int base, int nout, int mo, v4f32 dz) {  // sum over the 16 samples of a tile
-        float v[4] = {dz.x, dz.y, dz.z, dz.w};
-        for (int j = 0; j < 4; ++j) {
-            float t = v[j];
-            for (int off = 8; off >= 1; off >>= 1) t += __shfl_xor(t, off, 16);
-            int f = 16 * mo + 4 * g + j;
-            if (wave_live && s == 0 && f < nout) atomicAdd(grad + base + f, t);
-        }
-    };
+    // ---- backward through the layers (dZ4 = dO)
     auto dsilu = [](float z) { float sg = sigmoid_f(z); return sg * (1.0f + z * (1.0f - sg)); };
-
-    // ---- layer 4: dW4 = H3 dO^T, db4, dH3 = W4 dO
-    for (int mi = 0; mi < 8; ++mi) put(mi, mi, silu(z3[mi].x), silu(z3[mi].y), silu(z3[mi].z), silu(z3[mi].w));
-    put(8, 0, dO[0], dO[1], dO[2], dO[3]);
-    __syncthreads();
-    wgrad(8, 1, kPW4, kMlpOut, kMlpHid, kMlpOut);
-    bgrad(kPB4, kMlpOut, 0, (v4f32){dO[0], dO[1], dO[2], dO[3]});
+    const int64_t col = (int64_t)block * 16 + s;
+    auto store4 = [&](int row0, float a0, float a1, float a2, float a3) {  // rows row0 + 4g + j
+        uint16_t *p = act + (int64_t)(row0 + 4 * g) * cap + col;
+        p[0] = f2bf(a0); p[cap] = f2bf(a1); p[2 * cap] = f2bf(a2); p[3 * cap] = f2bf(a3);
+    };
+    // inputs (rows 0..23; lane group g holds inputs 8g..8g+7)
+    if (g < 3) {
+        uint16_t *p = act + (int64_t)(kActH0 + 8 * g) * cap + col;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) p[j * cap] = f2bf(g == 0 ? in[j] : (g == 1 ? in[8 + j] : in[16 + j]));
+    }
+    store4(kActZ4, dO[0], dO[1], dO[2], dO[3]);
+    v4i16 dOb = pack4(dO[0], dO[1], dO[2], dO[3]);
+    const v4i16 zero4 = {0, 0, 0, 0};
     v4f32 dz[8];
+#pragma unroll
     for (int mi = 0; mi < 8; ++mi) {
         v4f32 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mfma16(tileA(blob, kTileBwdL4 + mi, lane), dOb, acc);
+        acc = mfma32(tileA(blob, kTileBwdL4 + mi, lane), cat8(dOb, zero4), acc);
         dz[mi] = (v4f32){acc.x * dsilu(z3[mi].x), acc.y * dsilu(z3[mi].y), acc.z * dsilu(z3[mi].z),
                          acc.w * dsilu(z3[mi].w)};
+        store4(kActH3 + 16 * mi, silu(z3[mi].x), silu(z3[mi].y), silu(z3[mi].z), silu(z3[mi].w));
+        store4(kActZ3 + 16 * mi, dz[mi].x, dz[mi].y, dz[mi].z, dz[mi].w);
     }
-    // ---- layers 3 and 2
+    // layer 3 -> dZ2, layer 2 -> dZ1 (unrolled so the activations stay in registers)
+#pragma unroll
     for (int layer = 3; layer >= 2; --layer) {
-        v4f32 *zin = (layer == 3) ? z2 : z1;
-        const int pw = (layer == 3) ? kPW3 : kPW2, pb = (layer == 3) ? kPB3 : kPB2;
         const int tb = (layer == 3) ? kTileBwdL3 : kTileBwdL2;
-        __syncthreads();
-        for (int mi = 0; mi < 8; ++mi) put(mi, mi, silu(zin[mi].x), silu(zin[mi].y), silu(zin[mi].z), silu(zin[mi].w));
-        for (int mo = 0; mo < 8; ++mo) put(8 + mo, mo, dz[mo].x, dz[mo].y, dz[mo].z, dz[mo].w);
-        __syncthreads();
-        wgrad(8, 8, pw, kMlpHid, kMlpHid, kMlpHid);
-        for (int mo = 0; mo < 8; ++mo) bgrad(pb, kMlpHid, mo, dz[mo]);
         v4i16 dzb[8];
+#pragma unroll
         for (int mo = 0; mo < 8; ++mo) dzb[mo] = pack4(dz[mo].x, dz[mo].y, dz[mo].z, dz[mo].w);
+#pragma unroll
         for (int mi = 0; mi < 8; ++mi) {
             v4f32 acc = {0.f, 0.f, 0.f, 0.f};
-            for (int ko = 0; ko < 8; ++ko) acc = mfma16(tileA(blob, tb + mi * 8 + ko, lane), dzb[ko], acc);
-            dz[mi] = (v4f32){acc.x * dsilu(zin[mi].x), acc.y * dsilu(zin[mi].y), acc.z * dsilu(zin[mi].z),
-                             acc.w * dsilu(zin[mi].w)};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc = mfma32(tileA(blob, tb + mi * 4 + c, lane), cat8(dzb[2 * c], dzb[2 * c + 1]), acc);
+            const v4f32 zin = (layer == 3) ? z2[mi] : z1[mi];
+            dz[mi] = (v4f32){acc.x * dsilu(zin.x), acc.y * dsilu(zin.y), acc.z * dsilu(zin.z), acc.w * dsilu(zin.w)};
+            store4((layer == 3 ? kActH2 : kActH1) + 16 * mi, silu(zin.x), silu(zin.y), silu(zin.z), silu(zin.w));
+            store4((layer == 3 ? kActZ2 : kActZ1) + 16 * mi, dz[mi].x, dz[mi].y, dz[mi].z, dz[mi].w);
         }
     }
-    // ---- layer 1: dW1 = X dZ1^T (X rows 0..7), db1
-    __syncthreads();
-    put(0, 0, g == 0 ? in[0] : (g == 1 ? in[4] : 0.f), g == 0 ? in[1] : (g == 1 ? in[5] : 0.f),
-        g == 0 ? in[2] : (g == 1 ? in[6] : 0.f), g == 0 ? in[3] : (g == 1 ? in[7] : 0.f));
-    for (int mo = 0; mo < 8; ++mo) put(8 + mo, mo, dz[mo].x, dz[mo].y, dz[mo].z, dz[mo].w);
-    __syncthreads();
-    wgrad(1, 8, kPW1, kMlpHid, kMlpIn, kMlpHid);
-    for (int mo = 0; mo < 8; ++mo) bgrad(kPB1, kMlpHid, mo, dz[mo]);
 }
 
-// Adam (FP32 master, bias-corrected), then the gradient buffer is cleared.
-__global__ void mlp_adam_kernel(float *p, float *m, float *v, float *grad, float lr, float b1, float b2,
+// Weight gradients as products over the stored activations: dW_l[in][out] =
+// sum_s H_{l-1}[in][s] dZ_l[out][s], the bias from the constant row.  One wave
+// per (layer, 16-row tile, 16-column tile, sample split); results go to
+// part[split][param] (every parameter is written by exactly one wave per split,
+// so the sum over splits in fixed order is deterministic).
+constexpr int kGradJobsL1 = 2 * 8, kGradJobsL2 = 9 * 8, kGradJobsL3 = 9 * 8, kGradJobsL4 = 9;
+constexpr int kGradJobs = kGradJobsL1 + kGradJobsL2 + kGradJobsL3 + kGradJobsL4;   // 169
+
+__global__ void __launch_bounds__(256) mlp_wgrad_kernel(const uint16_t *act, int64_t cap, int kcols, float *part) {
+    const int lane = __lane_id(), w = threadIdx.x / 64;
+    const int job = blockIdx.x * (blockDim.x / 64) + w;
+    if (job >= kGradJobs * kGradSplits) return;
+    const int split = job / kGradJobs;
+    int jj = job % kGradJobs;
+    int hrow, zrow, it, jt, nin, ldw, pw, pb;
+    if (jj < kGradJobsL1) {
+        it = jj / 8; jt = jj % 8; hrow = kActH0; zrow = kActZ1; nin = kMlpIn; ldw = kMlpHid; pw = kPW1; pb = kPB1;
+    } else if ((jj -= kGradJobsL1) < kGradJobsL2) {
+        it = jj / 8; jt = jj % 8; hrow = kActH1; zrow = kActZ2; nin = kMlpHid; ldw = kMlpHid; pw = kPW2; pb = kPB2;
+    } else if ((jj -= kGradJobsL2) < kGradJobsL3) {
+        it = jj / 8; jt = jj % 8; hrow = kActH2; zrow = kActZ3; nin = kMlpHid; ldw = kMlpHid; pw = kPW3; pb = kPB3;
+    } else {
+        jj -= kGradJobsL3;
+        it = jj; jt = 0; hrow = kActH3; zrow = kActZ4; nin = kMlpHid; ldw = kMlpOut; pw = kPW4; pb = kPB4;
+    }
+    const int s = lane % 16, g = lane / 16;
+    // this split's columns: chunks of 32 samples
+    const int nchunk = kcols / 32;
+    const int c0 = (int)((int64_t)nchunk * split / kGradSplits), c1 = (int)((int64_t)nchunk * (split + 1) / kGradSplits);
+    const uint16_t *ha = act + (int64_t)(hrow + 16 * it + s) * cap + 8 * g;
+    const uint16_t *zb = act + (int64_t)(zrow + 16 * jt + s) * cap + 8 * g;
+    v4f32 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int c = c0; c < c1; ++c) {
+        const v8i16 a = *reinterpret_cast<const v8i16 *>(ha + 32 * c);
+        const v8i16 b = *reinterpret_cast<const v8i16 *>(zb + 32 * c);
+        acc = mfma32(a, b, acc);
+    }
+    float *dst = part + (int64_t)split * kNParams;
+    const float v[4] = {acc.x, acc.y, acc.z, acc.w};
+    const int out = 16 * jt + s;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int in = 16 * it + 4 * g + r;
+        if (in < nin) dst[pw + in * ldw + out] = v[r];
+        else if (in == nin) dst[pb + out] = v[r];  // the constant row: bias gradient
+    }
+}
+
+// The ones rows of the activation store (bias rows of H0..H3).
+__global__ void mlp_act_init_kernel(uint16_t *act, int64_t cap) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cap) return;
+    const uint16_t one = 0x3F80;  // 1.0 in bf16
+    for (int r = kMlpIn; r < kActRowsH0; ++r) act[(int64_t)(kActH0 + r) * cap + i] = (r == kMlpIn) ? one : 0;
+    for (int l = 0; l < 3; ++l)
+        for (int r = kMlpHid; r < kActRowsH; ++r)
+            act[(int64_t)(kActH1 + l * kActRowsH + r) * cap + i] = (r == kMlpHid) ? one : 0;
+}
+
+// sum of the split partial gradients (fixed order)
+__global__ void mlp_gsum_kernel(const float *part, float *grad) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kNParams) return;
+    float gsum = 0.0f;
+    for (int sp = 0; sp < kGradSplits; ++sp) gsum += part[(int64_t)sp * kNParams + i];
+    grad[i] = gsum;
+}
+
+// Adam (FP32 master, bias-corrected) on the summed split gradients.
+__global__ void mlp_adam_kernel(float *p, float *m, float *v, const float *part, float lr, float b1, float b2,
                                 float eps, float c1, float c2) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= kNParams) return;
-    float gi = grad[i];
+    float gi = 0.0f;
+    for (int sp = 0; sp < kGradSplits; ++sp) gi += part[(int64_t)sp * kNParams + i];
     float mi = b1 * m[i] + (1.0f - b1) * gi;
     float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
     m[i] = mi;
     v[i] = vi;
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
-    grad[i] = 0.0f;
 }
 
 // Training quantile levels are uniform, clamped to the encoded range [1e-4, 1 - 1e-4]
@@ -447,39 +528,43 @@ __device__ __forceinline__ float train_level(uint32_t w) {
     return fminf(fmaxf(u01(w), kLevelMin), 1.0f - kLevelMin);
 }
 
-// Random batch: indices uniform over the records, three quantile levels and
-// the row kind (conditional with probability 1/4).
-__global__ void mlp_batch_kernel(int64_t n, uint32_t k0, uint32_t k1, uint32_t step, int batch,
-                                 int32_t *idx, float *uq) {
+// Random batch: indices uniform over the records, four quantile levels and the
+// row kind (conditional with probability 1/3).
+__global__ void mlp_batch_kernel(int64_t n, uint32_t k0, uint32_t k1, uint32_t step, int batch, int32_t *idx,
+                                 float *uq) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= batch) return;
     const uint4 r = philox(make_uint4(step, (uint32_t)i, 0u, 9u), k0, k1);
     const uint4 e = philox(make_uint4(step, (uint32_t)i, 1u, 9u), k0, k1);
     idx[i] = (int32_t)__umulhi(r.x, (uint32_t)n);
-    float *q = uq + 4 * (int64_t)i;
+    float *q = uq + 5 * (int64_t)i;
     q[0] = train_level(r.y);
     q[1] = train_level(r.z);
     q[2] = train_level(r.w);
-    q[3] = (u01(e.x) < 0.25f) ? 1.0f : 0.0f;
+    q[3] = train_level(e.y);
+    q[4] = (u01(e.x) < (1.0f / 3.0f)) ? 1.0f : 0.0f;
 }
 
 // Normalisation of the targets: mean and standard deviation over the valid
 // records of each output's own target (the one-sided exit frequencies over the
-// records of their side; the side logit and the unused output keep mean 0,
-// scale 1), FP64 accumulation, one block of 256 threads per output; one more
-// block records the range of log10 a over the valid records.
+// records of their side; the face and side logits and the spare keep mean 0,
+// scale 1), FP64 accumulation, one block of 256 threads per output; three more
+// blocks record the ranges of log10 a and log10 tau_c and the smallest log10
+// depth of the valid records (where the network may then be used).
 __global__ void mlp_norm_kernel(const float *rec, int64_t n, float *norm) {
     __shared__ double s0[256], s1[256], s2[256];
     const int k = blockIdx.x;
     double a = 0.0, b = 0.0, c = 0.0;
-    if (k == kMlpOut) {
-        // the range of log10 a over the valid records
+    if (k >= kMlpOut) {
+        // ranges over the valid records: log10 a (block kMlpOut), log10 tau_c
+        // (kMlpOut + 1), and the lower end of log10 depth (kMlpOut + 2)
+        const int col = (k == kMlpOut) ? kRecLA : ((k == kMlpOut + 1) ? kRecLT : kRecLD);
         float lo = 1e30f, hi = -1e30f;
         for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
             const float *r = rec + (int64_t)kRec * i;
             if (r[kRecValid] < 0.5f) continue;
-            lo = fminf(lo, r[1]);
-            hi = fmaxf(hi, r[1]);
+            lo = fminf(lo, r[col]);
+            hi = fmaxf(hi, r[col]);
         }
         s1[threadIdx.x] = lo;
         s2[threadIdx.x] = hi;
@@ -492,10 +577,10 @@ __global__ void mlp_norm_kernel(const float *rec, int64_t n, float *norm) {
             __syncthreads();
         }
         if (threadIdx.x == 0) {
-            norm[kNormARange] = (float)s1[0];
-            norm[kNormARange + 1] = (float)s2[0];
-            norm[kNormARange + 2] = 0.0f;
-            norm[kNormARange + 3] = 0.0f;
+            const int o = kNormARange + 2 * (k - kMlpOut);
+            norm[o] = (float)s1[0];
+            if (k < kMlpOut + 2) norm[o + 1] = (float)s2[0];
+            else norm[o + 1] = 0.0f;  // padding after the depth minimum
         }
         return;
     }
@@ -538,9 +623,10 @@ __global__ void mlp_norm_kernel(const float *rec, int64_t n, float *norm) {
     }
 }
 
-// Forward for a list of raw rows in[n][8] = (log10 tau_R, log10 a, x_in, u_a,
-// u_b, u_c or (flag 1) x_out, r, flag): out[n][10] in physical units (ln E[N_s]
-// with its calibration term).
+// Forward for a list of raw rows in[n][kFwdRaw] = (log10 tau_c, log10 a, |x_in|,
+// q0, q1, q2, log10 depth, m0, m1, m2, u_a, u_b, u_c, u_d, flag, x_out, face):
+// out[n][16] in physical units (face and side logits as logits; ln E[N_s] with
+// its calibration term).
 __global__ void __launch_bounds__(256) mlp_forward_kernel(const unsigned char *blob, const float *inp,
                                                           int64_t n, float *out) {
     const int lane = __lane_id(), w = threadIdx.x / 64;
@@ -551,24 +637,24 @@ __global__ void __launch_bounds__(256) mlp_forward_kernel(const unsigned char *b
     const bool live = si < n;
     const float *bias = reinterpret_cast<const float *>(blob + kTilesAll * kTileBytes);
     const float *norm = bias + kBiasFloats;
-    const float *r = inp + kMlpIn * (live ? si : 0);
+    const float *r = inp + (int64_t)kFwdRaw * (live ? si : 0);
     float in[kMlpIn];
-    mlp_inputs(r[0], r[1], r[2], r[3], r[4], r[5], r[6], r[7] > 0.5f, in);
-    v4f32 o = mlp_forward_block(blob, bias, xin_operand(in, lane), lane, nullptr, nullptr, nullptr);
+    mlp_inputs(r, r[10], r[11], r[12], r[13], r[14] > 0.5f, r[15], (int)r[16], in);
+    const v4f32 o = mlp_forward_block(blob, bias, xin_operand(in, lane), lane, nullptr, nullptr, nullptr);
     if (!live) return;
-    float v[4] = {o.x, o.y, o.z, o.w};
+    const float v[4] = {o.x, o.y, o.z, o.w};
     for (int j = 0; j < 4; ++j) {
-        int k = 4 * g + j;
-        if (k < kMlpOut)
-            out[kMlpOut * si + k] = v[j] * norm[kMlpOut + k] + norm[k] +
-                                    ((k == kOutLogN) ? norm[2 * kMlpOut + cal_bin(r[0], r[2])] : 0.0f);
+        const int k = 4 * g + j;
+        out[kMlpOut * si + k] = v[j] * norm[kMlpOut + k] + norm[k] +
+                                ((k == kOutLogN) ? norm[kNormCal + cal_bin(r[0], r[6], r[2])] : 0.0f);
     }
 }
 
-// Calibration sums over valid records with |x_in| <= kEscXMax (the range where the
-// network is asked): per bin of (log10 tau_R, |x_in|), the number of records,
-// sum N_s and sum exp(network ln E[N_s]) (without calibration), FP64.
-// One wave per 16-record block; block partial sums in LDS, then global atomics.
+// Calibration sums over valid records with |x_in| <= kEscXMax (the range where
+// the network is asked): per bin of (log10 tau_c, log10 depth, |x_in|), the
+// number of records, sum N_s and sum exp(network ln E[N_s]) (without
+// calibration), FP64.  One wave per 16-record block; block partial sums in LDS,
+// then global atomics.
 __global__ void __launch_bounds__(256) mlp_calib_kernel(const unsigned char *blob, const float *rec, int64_t n,
                                                         double *sums) {
     __shared__ double ls[3 * kNCal];
@@ -587,12 +673,12 @@ __global__ void __launch_bounds__(256) mlp_calib_kernel(const unsigned char *blo
         // from Philox(record index)
         const uint4 q = philox(make_uint4((uint32_t)si, (uint32_t)(si >> 32), 0u, 9u), 0x6C1Bu, 0x5EEDu);
         float in[kMlpIn];
-        mlp_inputs(r[0], r[1], r[2], u01(q.x), u01(q.y), u01(q.z), 0.0f, false, in);
-        v4f32 o = mlp_forward_block(blob, bias, xin_operand(in, lane), lane, nullptr, nullptr, nullptr);
-        // output 4 sits in lane group g = 1, component 0
-        if (live && g == 1 && fabsf(r[2]) <= kEscXMax) {
-            const int b = cal_bin(r[0], r[2]);
-            const double pred = exp((double)(o.x * norm[kMlpOut + kOutLogN] + norm[kOutLogN]));
+        mlp_inputs(r, u01(q.x), u01(q.y), u01(q.z), u01(q.w), false, 0.0f, 0, in);
+        const v4f32 o = mlp_forward_block(blob, bias, xin_operand(in, lane), lane, nullptr, nullptr, nullptr);
+        // output 9 sits in lane group 2, component 1
+        if (live && g == 2 && r[kRecX] <= kEscXMax) {
+            const int b = cal_bin(r[kRecLT], r[kRecLD], r[kRecX]);
+            const double pred = exp((double)(o.y * norm[kMlpOut + kOutLogN] + norm[kOutLogN]));
             atomicAdd(&ls[b], 1.0);
             atomicAdd(&ls[kNCal + b], exp((double)r[kRecLogN]));
             atomicAdd(&ls[2 * kNCal + b], pred);
@@ -608,24 +694,20 @@ __global__ void mlp_calib_finish_kernel(const double *sums, float *norm) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= kNCal) return;
     const double cnt = sums[b], sn = sums[kNCal + b], sp = sums[2 * kNCal + b];
-    norm[2 * kMlpOut + b] = (cnt >= 100.0 && sn > 0.0 && sp > 0.0) ? (float)log(sn / sp) : 0.0f;
+    norm[kNormCal + b] = (cnt >= 100.0 && sn > 0.0 && sp > 0.0) ? (float)log(sn / sp) : 0.0f;
 }
 
 // --------------------------------------------------------------- launch ---
-hipError_t launch_escape_record(const float *tab, float a, float thd, uint32_t k0, uint32_t k1, uint64_t offset,
-                                int64_t n, float lt_lo, float lt_hi, uint32_t max_scat, int x_fixed, float x_value,
-                                float *out, hipStream_t s) {
+hipError_t launch_cell_record(const RecordParams &R, int grid, hipStream_t s) {
     size_t lds = sizeof(float) * kTabFloats;
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(escape_record_kernel),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(cell_record_kernel),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr = true;
     }
-    int grid = (int)((n + 255) / 256);
-    hipLaunchKernelGGL(escape_record_kernel, dim3(grid), dim3(256), lds, s, tab, a, thd, k0, k1, offset, n,
-                       lt_lo, lt_hi, max_scat, x_fixed, x_value, out);
+    hipLaunchKernelGGL(cell_record_kernel, dim3(grid), dim3(256), lds, s, R);
     return hipGetLastError();
 }
 
@@ -645,18 +727,34 @@ hipError_t launch_mlp_pack(const float *p, const float *norm, unsigned char *blo
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_grad(const unsigned char *blob, const float *rec, const int32_t *idx, const float *uq,
-                           int batch, float *grad, float *loss, hipStream_t s) {
-    int nblocks = (batch + 15) / 16;
-    int grid = (nblocks + 3) / 4;
-    hipLaunchKernelGGL(mlp_grad_kernel, dim3(grid), dim3(256), 0, s, blob, rec, idx, uq, batch, grad, loss);
+hipError_t launch_mlp_act_init(uint16_t *act, int64_t cap, hipStream_t s) {
+    hipLaunchKernelGGL(mlp_act_init_kernel, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, act, cap);
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_adam(float *p, float *m, float *v, float *grad, float lr, int step, hipStream_t s) {
+// Gradient of the mean loss over a batch into the split partials `part`.
+hipError_t launch_mlp_grad(const unsigned char *blob, const float *rec, const int32_t *idx, const float *uq,
+                           int batch, uint16_t *act, int64_t cap, float *part, float *loss, hipStream_t s) {
+    const int kcols = 32 * ((batch + 31) / 32);
+    const int nblocks = kcols / 16;
+    hipLaunchKernelGGL(mlp_fwdbwd_kernel, dim3((nblocks + 3) / 4), dim3(256), 0, s, blob, rec, idx, uq, batch, act,
+                       cap, loss);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int jobs = kGradJobs * kGradSplits;
+    hipLaunchKernelGGL(mlp_wgrad_kernel, dim3((jobs + 3) / 4), dim3(256), 0, s, act, cap, kcols, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_gsum(const float *part, float *grad, hipStream_t s) {
+    hipLaunchKernelGGL(mlp_gsum_kernel, dim3((kNParams + 255) / 256), dim3(256), 0, s, part, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_adam(float *p, float *m, float *v, const float *part, float lr, int step, hipStream_t s) {
     const float b1 = 0.9f, b2 = 0.999f;
     float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
-    hipLaunchKernelGGL(mlp_adam_kernel, dim3((kNParams + 255) / 256), dim3(256), 0, s, p, m, v, grad, lr, b1, b2,
+    hipLaunchKernelGGL(mlp_adam_kernel, dim3((kNParams + 255) / 256), dim3(256), 0, s, p, m, v, part, lr, b1, b2,
                        1e-8f, c1, c2);
     return hipGetLastError();
 }
@@ -679,7 +777,7 @@ hipError_t launch_mlp_calib(const unsigned char *blob, const float *rec, int64_t
 }
 
 hipError_t launch_mlp_norm(const float *rec, int64_t n, float *norm, hipStream_t s) {
-    hipLaunchKernelGGL(mlp_norm_kernel, dim3(kMlpOut + 1), dim3(256), 0, s, rec, n, norm);
+    hipLaunchKernelGGL(mlp_norm_kernel, dim3(kMlpOut + 3), dim3(256), 0, s, rec, n, norm);
     return hipGetLastError();
 }
 

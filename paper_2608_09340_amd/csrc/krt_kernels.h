@@ -56,6 +56,7 @@ struct RunParams {
     float dx[3], inv_dx[3];
     int bc[3];
     const float *k0, *vx, *vy, *vz, *eps;
+    const float *kabs;  // [ncell] grey absorption coefficient, or null
     const float *alias_prob;
     const int *alias_idx;
     // line
@@ -84,9 +85,14 @@ struct RunParams {
     uint64_t n_packets, packet_offset, max_events;
     uint32_t key0, key1;
     unsigned long long *work_counter;
-    // learned escape (mlp_img == nullptr: plain random walk only)
+    // learned whole-cell escape (mlp_img == nullptr: plain random walk only).
+    // Calls happen only in cubic cells (esc_cubic) whose line-centre depth from
+    // centre to face tau_c = k0 half_dx lies in [esc_tc_min, esc_tc_max], at
+    // scattering points at least esc_depth_min (line-centre) below the nearest
+    // face, for gas-frame |x| <= esc_x_max.
     const unsigned char *mlp_img;
-    float esc_tau_min, esc_tau_max, esc_x_max, esc_log10a;
+    int esc_cubic;
+    float esc_half_dx, esc_tc_min, esc_tc_max, esc_depth_min, esc_x_max, esc_log10a;
     int esc_min_lanes;
     int esc_tail_lanes;
     int tail_lanes;
@@ -115,15 +121,28 @@ hipError_t launch_debug_voigt(const float *tab, const float *x, int64_t n, float
 hipError_t launch_debug_voigt_analytic(float a, float u0, const float *x, int64_t n, float *out, hipStream_t s);
 hipError_t launch_debug_upar(const float *tab, float a, float thd, float x, uint32_t k0, uint32_t k1,
                              uint64_t packet, uint32_t ev0, int64_t n, float *out, hipStream_t s);
-hipError_t launch_escape_record(const float *tab, float a, float thd, uint32_t k0, uint32_t k1, uint64_t offset,
-                                int64_t n, float lt_lo, float lt_hi, uint32_t max_scat, int x_fixed, float x_value,
-                                float *out, hipStream_t s);
+// whole-cell escape records (krt_escape.hip)
+struct RecordParams {
+    const float *tab;
+    float a, thd;
+    uint32_t k0, k1;
+    uint64_t offset, n;
+    float lt_lo, lt_hi, ld_lo;    // log10 tau_c range, lower end of log10 depth
+    uint32_t max_scat;            // records past this many scatterings are invalid
+    int fixed, iso_dir;           // fixed start (x_in, q, n_in) / isotropic n_in with it
+    float x_in, q[3], n_in[3];
+    unsigned long long *counter;  // record pool, zeroed before the launch
+    float *out;                   // [n][kRec]
+};
+hipError_t launch_cell_record(const RecordParams &R, int grid, hipStream_t s);
 hipError_t launch_mlp_init(float *p, uint32_t k0, uint32_t k1, hipStream_t s);
 hipError_t launch_mlp_pack(const float *p, const float *norm, unsigned char *blob, unsigned char *img,
                            hipStream_t s);
+hipError_t launch_mlp_act_init(uint16_t *act, int64_t cap, hipStream_t s);
 hipError_t launch_mlp_grad(const unsigned char *blob, const float *rec, const int32_t *idx, const float *uq,
-                           int batch, float *grad, float *loss, hipStream_t s);
-hipError_t launch_mlp_adam(float *p, float *m, float *v, float *grad, float lr, int step, hipStream_t s);
+                           int batch, uint16_t *act, int64_t cap, float *part, float *loss, hipStream_t s);
+hipError_t launch_mlp_gsum(const float *part, float *grad, hipStream_t s);
+hipError_t launch_mlp_adam(float *p, float *m, float *v, const float *part, float lr, int step, hipStream_t s);
 hipError_t launch_mlp_batch(int64_t n, uint32_t k0, uint32_t k1, uint32_t step, int batch, int32_t *idx,
                             float *uq, hipStream_t s);
 hipError_t launch_mlp_norm(const float *rec, int64_t n, float *norm, hipStream_t s);
@@ -132,6 +151,6 @@ hipError_t launch_mlp_calib(const unsigned char *blob, const float *rec, int64_t
 hipError_t launch_mlp_forward(const unsigned char *blob, const float *inp, int64_t n, float *out, hipStream_t s);
 hipError_t launch_levels(int nl, int64_t ncell, const double *consts, const double *ncoll,
                          const double *ntot, const float *jbar, double *pops, float *k0_out,
-                         float *eps_out, hipStream_t s);
+                         float *eps_out, float *emis_out, hipStream_t s);
 
 }  // namespace krt

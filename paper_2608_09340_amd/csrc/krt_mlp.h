@@ -1,110 +1,129 @@
-// krt_mlp.h -- the learned escape proposal: layout constants and the BF16-MFMA
-// forward pass shared by the transport kernel (inference) and the training
-// kernels.  Not part of the C ABI.
+// krt_mlp.h -- the learned whole-cell escape: layout constants and the
+// BF16-MFMA forward pass shared by the transport kernel (inference) and the
+// training kernels.  Not part of the C ABI.
 //
-// Network: 8 inputs -> 128 -> 128 -> 128 (SiLU) -> 10 outputs.
-// Inputs  : ((log10 tau_R - 3.5)/1.5, log10 a + 3, x_in / 4, L(u_a), L(u_b),
-//           w, r_in, flag), L(u) = logit(u) / 4 the encoding of a quantile
-//           level: extreme levels get distinct inputs, so the far wing of the
-//           exit frequency (the rare long flights by which photons leave a thick
-//           medium) is not flattened.  A *marginal* evaluation (flag 0,
-//           w = L(u_c), r_in 0) gives the exit frequency, exit point and count at three
-//           independent quantile levels; a *conditional* one (flag 1,
-//           w = x_out / 4, r_in = sqrt2 r - 1) gives the exit direction given
-//           the sampled exit frequency and the exit point's distance r from the
-//           face centre, since photons leaving near an edge travel more
-//           obliquely and away from the centre, and wing photons leave closer
-//           to the normal.
-// Outputs (normalised): marginal: 0 quantile at u_a of x_out given x_out >= 0;
-//           1, 2 quantiles at u_b, u_c of the exit point (s, t) on the exit
-//           face; 4 ln E[N_s] (scatterings inside the cube); 5 quantile at u_a
-//           of ln <x^2> over those scatterings; 6 logit P(x_out >= 0); 7
-//           quantile at u_a of -x_out given x_out < 0.  Conditional: 3 quantile
-//           at u_a of the cosine mu of the exit direction to the face normal; 8
-//           quantile at u_b of the angle alpha between the direction's
-//           tangential part and the exit point's offset (s, t).  9 unused (the
-//           parameter count stays even).  The exit frequency is bimodal, so it
-//           is drawn as a two-component mixture (side, then a one-sided
-//           quantile): a single smooth quantile function of the signed x_out
-//           would fill the empty line core between the peaks.
+// The network describes how a photon that scatters inside a homogeneous static
+// cubic cell leaves it.  Conditions are taken in the cell's reduced frame: the
+// start point's absolute offsets from the cell centre (in half-widths) sorted
+// ascending, q0 <= q1 <= q2 (axis 2 points to the nearest face), the incoming
+// direction reflected and permuted alike, and |x_in| (the medium is symmetric
+// under x -> -x, so the exit frequency takes x_in's sign).
 //
-// The layers are evaluated transposed, H^T_{l+1} = SiLU(W_l^T H^T_l + b_l),
-// with v_mfma_f32_16x16x16_bf16 on 16-sample blocks: the accumulator layout of
-// one layer (lane l holds features 4(l/16)+j of sample l%16) is exactly the B
-// operand layout of the next, so activations never leave registers.
+// Network: 24 inputs -> 128 -> 128 -> 128 (SiLU) -> 16 outputs.
+// Inputs: 0 (log10 tau_c - 3)/1.2 (tau_c the line-centre depth centre to face),
+//   1 log10 a + 3, 2 |x_in| - 1, 3-5 2 q - 1, 6 (log10 depth - 2)/1.2 (depth
+//   tau_c (1 - q2) to the nearest face), 7-9 incoming direction, 10-13 quantile
+//   levels L(u_a..u_d), L(u) = logit(u)/4, 14 flag (0 marginal, 1 conditional),
+//   15 conditional: x_out/4, 16-21 conditional: one-hot exit face, 22-23 zero.
+// Outputs (normalised): marginal: 0-5 exit-face logits (face F = 2 axis +
+//   (outward normal along +axis)); 6 logit P(x_out >= 0); 7 quantile at u_a of
+//   x_out given x_out >= 0; 8 quantile at u_a of -x_out given x_out < 0;
+//   9 ln E[N_s]; 10 quantile at u_b of ln <x^2> over the skipped scatterings.
+//   Conditional (given the exit face and x_out): 11, 12 quantiles at u_a, u_b
+//   of the exit offsets ys, yt from the start point's projection onto the exit
+//   face (along the two axes following the exit axis cyclically) over the
+//   start point's distance to that face's plane; 13 quantile at u_c of the exit
+//   cosine mu; 14 quantile at u_d of the angle alpha between the exit
+//   direction's tangential part and that offset.  15 unused.
+//
+// Layers run transposed, H^T_{l+1} = SiLU(W_l^T H^T_l + b_l), on 16-sample
+// blocks with v_mfma_f32_16x16x32_bf16.  The accumulator of a 16-feature tile
+// leaves lane l with features 4(l/16)+r of sample l%16; the B operand of the
+// next layer wants 8 features per lane.  The reduction index of each 32-wide
+// chunk c is therefore permuted: B slot 8g+j holds feature
+// 32c + 4g + j (j < 4) or 32c + 16 + 4g + (j - 4) (j >= 4), i.e. the
+// accumulators of tiles 2c and 2c+1 side by side, and the weight tiles are
+// packed with the same permutation (kperm), so activations never leave
+// registers.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace krt {
 
-constexpr int kMlpIn = 8, kMlpHid = 128, kMlpOut = 10;
+constexpr int kMlpIn = 24, kMlpInPad = 32, kMlpHid = 128, kMlpOut = 16;
 // output indices
-constexpr int kOutXPos = 0, kOutS = 1, kOutT = 2, kOutMu = 3, kOutLogN = 4, kOutLogX2 = 5, kOutLogit = 6,
-              kOutXNeg = 7, kOutAlpha = 8, kOutSpare = 9;
-// escape record layout (floats per record) and its columns
-constexpr int kRec = 11;
-constexpr int kRecXOut = 3, kRecS = 4, kRecT = 5, kRecMu = 6, kRecLogN = 7, kRecLogX2 = 8, kRecValid = 9,
-              kRecAlpha = 10;
+constexpr int kOutFace = 0, kOutSide = 6, kOutXPos = 7, kOutXNeg = 8, kOutLogN = 9, kOutLogX2 = 10,
+              kOutYS = 11, kOutYT = 12, kOutMu = 13, kOutAlpha = 14, kOutSpare = 15;
+// whole-cell escape record (floats per record) and its columns
+constexpr int kRec = 20;
+constexpr int kRecLT = 0, kRecLA = 1, kRecX = 2, kRecQ0 = 3, kRecLD = 6, kRecN0 = 7, kRecFace = 10, kRecYS = 11,
+              kRecYT = 12, kRecMu = 13, kRecAlpha = 14, kRecXOut = 15, kRecLogN = 16, kRecLogX2 = 17,
+              kRecValid = 18;
 // ln E[N_s]: weighted log-deviance loss with its exponent clamped
 constexpr float kDevClamp = 4.0f;
 constexpr float kDevWeight = 0.25f;
 // FP32 master parameter block (offsets in floats)
-constexpr int kPW1 = 0;                                  // W1[8][128]   (in, out)
+constexpr int kPW1 = 0;                                  // W1[24][128]   (in, out)
 constexpr int kPB1 = kPW1 + kMlpIn * kMlpHid;            // b1[128]
 constexpr int kPW2 = kPB1 + kMlpHid;                     // W2[128][128]
 constexpr int kPB2 = kPW2 + kMlpHid * kMlpHid;
 constexpr int kPW3 = kPB2 + kMlpHid;
 constexpr int kPB3 = kPW3 + kMlpHid * kMlpHid;
-constexpr int kPW4 = kPB3 + kMlpHid;                     // W4[128][10]
-constexpr int kPB4 = kPW4 + kMlpHid * kMlpOut;           // b4[10]
-constexpr int kNParams = kPB4 + kMlpOut;                 // 35466
-// target normalisation: y_norm = (y - mean) / scale, stored after the params
-// (output 6, the side logit, and the unused output 9 have mean 0 and scale 1),
-// followed by the
-// calibration of ln E[N_s]: an additive term per bin of (log10 tau_R, |x_in|)
-constexpr int kNCalT = 32, kNCalX = 8, kNCal = kNCalT * kNCalX;
-constexpr float kCalLo = 1.0f, kCalInvW = 8.0f;  // bins of 0.125 in log10 tau_R from 1 to 5
-// then the range of log10 a of the training records (min, max; a network is
-// used only at damping values inside it) and two floats of padding
-constexpr int kNormARange = 2 * kMlpOut + kNCal;
-constexpr int kNNorm = 2 * kMlpOut + kNCal + 4;
+constexpr int kPW4 = kPB3 + kMlpHid;                     // W4[128][16]
+constexpr int kPB4 = kPW4 + kMlpHid * kMlpOut;           // b4[16]
+constexpr int kNParams = kPB4 + kMlpOut;                 // 38288
+// Normalisation block after the parameters: target mean[16], scale[16] (face
+// logits, side logit and the unused output: 0 and 1), then the calibration of
+// ln E[N_s] (an additive term per bin of log10 tau_c, log10 depth and |x_in|),
+// then the ranges of the training records, where the network may be used:
+// log10 a (min, max), log10 tau_c (min, max), the smallest log10 depth, and
+// three floats of padding (the LDS image stays a whole number of 16-byte words).
+constexpr int kNCalT = 8, kNCalD = 8, kNCalX = 4, kNCal = kNCalT * kNCalD * kNCalX;  // 256
+constexpr int kNormCal = 2 * kMlpOut;
+constexpr int kNormARange = kNormCal + kNCal;
+constexpr int kNormTauRange = kNormARange + 2;
+constexpr int kNormDepthMin = kNormARange + 4;
+constexpr int kNNorm = kNormARange + 8;                  // 296
 
-// The network is asked only for |x_in| <= kEscXMax (gas frame).  Beyond it the
-// mean count is a steep mixture of photons that leave at once and photons
-// redistributed into the core; a wing photon takes plain scatterings until it
-// is back in the core, which costs little (about 0.5% of the scatterings in a
-// thick cell have |x| > 2).  Records draw x_in over [-kRecXMax, kRecXMax].
+// The network is asked only for gas-frame |x_in| <= kEscXMax: beyond it the
+// count is a steep mixture of photons that leave at once and photons sent back
+// into the core; wing photons take plain scatterings until they are back in
+// the core.  Records draw |x_in| up to kRecXMax.
 constexpr float kEscXMax = 2.0f;
 constexpr float kRecXMax = 3.0f;
 
-// |x_in| bins of 0.25 over [0, kEscXMax) (the last one also takes larger |x_in|)
-__device__ __forceinline__ int cal_bin(float lt, float xin) {
-    const int bt = min(max((int)((lt - kCalLo) * kCalInvW), 0), kNCalT - 1);
-    const int bx = min((int)(fabsf(xin) * (kNCalX / kEscXMax)), kNCalX - 1);
-    return bt * kNCalX + bx;
+// calibration bin: log10 tau_c in 8 bins of 0.5 over [1, 5), log10 depth in 8
+// bins of 0.5 over [0, 4), |x_in| in 4 bins of 0.5 over [0, 2) (ends clamped)
+__device__ __forceinline__ int cal_bin(float lt, float ld, float xa) {
+    const int bt = min(max((int)((lt - 1.0f) * 2.0f), 0), kNCalT - 1);
+    const int bd = min(max((int)(ld * 2.0f), 0), kNCalD - 1);
+    const int bx = min(max((int)(xa * 2.0f), 0), kNCalX - 1);
+    return (bt * kNCalD + bd) * kNCalX + bx;
 }
 
-// Packed BF16 A-operand tiles (16x16, 512 B each: 64 lanes x 4 bf16).
-// Forward (W^T, rows = out-features): L1 8 tiles (K padded 8 -> 16), L2 64, L3 64, L4 8 (rows padded 10 -> 16).
-constexpr int kTilesL1 = 8, kTilesL2 = 64, kTilesL3 = 64, kTilesL4 = 8;
-constexpr int kTileFwdL1 = 0, kTileFwdL2 = kTilesL1, kTileFwdL3 = kTileFwdL2 + kTilesL2,
-              kTileFwdL4 = kTileFwdL3 + kTilesL3, kTilesFwd = kTileFwdL4 + kTilesL4;   // 144
-// Backward (W, rows = in-features): L4 8 tiles (K = 16 padded outputs), L3 64, L2 64.
-constexpr int kTileBwdL4 = kTilesFwd, kTileBwdL3 = kTileBwdL4 + 8, kTileBwdL2 = kTileBwdL3 + 64,
-              kTilesAll = kTileBwdL2 + 64;                                              // 280
-constexpr int kTileBytes = 512;
-// biases as FP32 after the tiles: b1 128, b2 128, b3 128, b4 16 (padded)
-constexpr int kBiasFloats = 3 * kMlpHid + 16;
+// Packed BF16 A-operand tiles, 16 rows x 32 reduction entries (1 KiB: 64 lanes
+// x 8 bf16; lane l holds row l%16, entries 8(l/16)..8(l/16)+7).
+// Forward (W^T, rows = out-features): L1 8 tiles (inputs 24 padded to 32),
+// L2 32 (8 row tiles x 4 chunks), L3 32, L4 4 (16 outputs x 4 chunks).
+constexpr int kTileFwdL1 = 0, kTileFwdL2 = 8, kTileFwdL3 = kTileFwdL2 + 32, kTileFwdL4 = kTileFwdL3 + 32,
+              kTilesFwd = kTileFwdL4 + 4;                                                 // 76
+// Backward (W, rows = in-features): L4 8 tiles (16 outputs padded to 32), L3 32, L2 32.
+constexpr int kTileBwdL4 = kTilesFwd, kTileBwdL3 = kTileBwdL4 + 8, kTileBwdL2 = kTileBwdL3 + 32,
+              kTilesAll = kTileBwdL2 + 32;                                               // 148
+constexpr int kTileBytes = 1024;
+// biases as FP32 after the tiles: b1 128, b2 128, b3 128, b4 16
+constexpr int kBiasFloats = 3 * kMlpHid + kMlpOut;
 constexpr int kMlpFwdBytes = kTilesFwd * kTileBytes + kBiasFloats * 4 + kNNorm * 4;  // LDS image for inference
 constexpr int kMlpBlobBytes = kTilesAll * kTileBytes + kBiasFloats * 4 + kNNorm * 4;
-static_assert(kMlpIn <= 8 && kMlpOut <= 16, "inputs fill two lane groups, outputs one 16-row tile");
+static_assert(kMlpIn <= kMlpInPad && kMlpOut == 16, "inputs fill one 32-wide chunk, outputs one tile");
+// training: activation-store rows and the sample splits of the weight-gradient product
+constexpr int kActRowsAll = 32 + 3 * 144 + 3 * kMlpHid + kMlpOut;   // 864
+constexpr int kGradSplits = 8;
+// raw input row of krt_escape_forward: (log10 tau_c, log10 a, |x_in|, q0, q1,
+// q2, log10 depth, m0, m1, m2, u_a, u_b, u_c, u_d, flag, x_out, face)
+constexpr int kFwdRaw = 17;
 static_assert(kMlpFwdBytes % 16 == 0, "the inference image is staged into LDS in 16-byte words");
+
+// Feature held by B-operand slot k' = 8g + j of 32-wide chunk c (see above).
+__host__ __device__ constexpr int kperm(int c, int kp) {
+    return 32 * c + ((kp & 7) < 4 ? 4 * (kp >> 3) + (kp & 7) : 16 + 4 * (kp >> 3) + (kp & 7) - 4);
+}
 
 // Network input of a quantile level u: logit(u) / 4 with u clamped to the
 // trained levels [1e-4, 1 - 1e-4]: beyond them the network would extrapolate
-// the quantile function (far too far into the wing), so the outermost 2e-4 of
-// the draws take the 1e-4 and 1 - 1e-4 quantiles
+// the quantile function, so the outermost 2e-4 of the draws take the 1e-4 and
+// 1 - 1e-4 quantiles
 constexpr float kLevelMin = 1e-4f;
 __device__ __forceinline__ float level_in(float u) {
     u = fminf(fmaxf(u, kLevelMin), 1.0f - kLevelMin);
@@ -112,6 +131,8 @@ __device__ __forceinline__ float level_in(float u) {
 }
 
 typedef short v4i16 __attribute__((ext_vector_type(4)));
+typedef short v8i16 __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf16 __attribute__((ext_vector_type(8)));
 typedef float v4f32 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
@@ -133,35 +154,52 @@ __device__ __forceinline__ v4i16 pack4(float a, float b, float c, float d) {
     return r;
 }
 
-__device__ __forceinline__ v4f32 mfma16(v4i16 a, v4i16 b, v4f32 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+__device__ __forceinline__ v8i16 cat8(v4i16 a, v4i16 b) { return __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7); }
+
+__device__ __forceinline__ v4f32 mfma32(v8i16 a, v8i16 b, v4f32 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf16, a), __builtin_bit_cast(v8bf16, b), c,
+                                                   0, 0, 0);
 }
 
 // A operand of tile t for this lane from a byte blob (LDS or global)
-__device__ __forceinline__ v4i16 tileA(const unsigned char *blob, int t, int lane) {
-    return *reinterpret_cast<const v4i16 *>(blob + t * kTileBytes + lane * 8);
+__device__ __forceinline__ v8i16 tileA(const unsigned char *blob, int t, int lane) {
+    return *reinterpret_cast<const v8i16 *>(blob + t * kTileBytes + lane * 16);
 }
 
 // Forward pass of one 16-sample block.  xin: this lane's B operand for layer 1
-// (lanes 0..15 hold inputs 0..3 of sample l%16, lanes 16..31 inputs 4..7,
-// other lanes zeros).  Returns
-// the output tile (lane l: outputs 4(l/16)+j of sample l%16).  If z1..z3 are
-// given, the pre-activations are stored (8 tiles each) for the backward pass.
-__device__ __forceinline__ v4f32 mlp_forward_block(const unsigned char *tiles, const float *bias,
-                                                   v4i16 xin, int lane, v4f32 *z1, v4f32 *z2,
-                                                   v4f32 *z3) {
+// (lane l holds inputs 8(l/16)..8(l/16)+7 of sample l%16).  Returns the output
+// tile (lane l: outputs 4(l/16)+r of sample l%16).  If z1..z3 are given, the
+// pre-activations are stored (8 tiles each) for the backward pass.
+// Hidden layers run chunk-major: the 8 weight tiles of reduction chunk c are
+// read from LDS together (the next chunk's reads issued before this chunk's
+// products), then 8 independent MFMA chains advance, so neither LDS latency
+// nor the MFMA result latency of one chain stalls the next product.
+__device__ __forceinline__ v4f32 mlp_forward_block(const unsigned char *tiles, const float *bias, v8i16 xin,
+                                                   int lane, v4f32 *z1, v4f32 *z2, v4f32 *z3) {
     const int g = lane >> 4;
     v4i16 h[8];
-    // layer 1
+    v8i16 wa[8], wb[8];
+    // layer 1: 8 tiles, one chunk (the inputs)
 #pragma unroll
-    for (int mo = 0; mo < 8; ++mo) {
-        const float *b = bias + 16 * mo + 4 * g;
-        v4f32 acc = {b[0], b[1], b[2], b[3]};
-        acc = mfma16(tileA(tiles, kTileFwdL1 + mo, lane), xin, acc);
-        if (z1) z1[mo] = acc;
-        h[mo] = pack4(silu(acc.x), silu(acc.y), silu(acc.z), silu(acc.w));
+    for (int mo = 0; mo < 8; ++mo) wa[mo] = tileA(tiles, kTileFwdL1 + mo, lane);
+    // first chunk of layer 2 in flight while layer 1 runs
+#pragma unroll
+    for (int mo = 0; mo < 8; ++mo) wb[mo] = tileA(tiles, kTileFwdL2 + mo * 4, lane);
+    {
+        v4f32 acc[8];
+#pragma unroll
+        for (int mo = 0; mo < 8; ++mo) {
+            const float *b = bias + 16 * mo + 4 * g;
+            acc[mo] = mfma32(wa[mo], xin, (v4f32){b[0], b[1], b[2], b[3]});
+        }
+#pragma unroll
+        for (int mo = 0; mo < 8; ++mo) {
+            if (z1) z1[mo] = acc[mo];
+            h[mo] = pack4(silu(acc[mo].x), silu(acc[mo].y), silu(acc[mo].z), silu(acc[mo].w));
+        }
     }
-    // layers 2, 3
+    // layers 2, 3: chunk-major with the next chunk's tiles prefetched; the
+    // current chunk's tiles are always in wb after the swap below
 #pragma unroll
     for (int layer = 0; layer < 2; ++layer) {
         const int t0 = layer == 0 ? kTileFwdL2 : kTileFwdL3;
@@ -171,8 +209,26 @@ __device__ __forceinline__ v4f32 mlp_forward_block(const unsigned char *tiles, c
         for (int mo = 0; mo < 8; ++mo) {
             const float *b = bl + 16 * mo + 4 * g;
             acc[mo] = (v4f32){b[0], b[1], b[2], b[3]};
+        }
 #pragma unroll
-            for (int ki = 0; ki < 8; ++ki) acc[mo] = mfma16(tileA(tiles, t0 + mo * 8 + ki, lane), h[ki], acc[mo]);
+        for (int c = 0; c < 4; ++c) {
+            // prefetch: chunk c + 1 of this layer, or chunk 0 of the next layer
+            // (layer 3), or the output layer's 4 tiles (after layer 3)
+#pragma unroll
+            for (int mo = 0; mo < 8; ++mo) {
+                if (c < 3) wa[mo] = tileA(tiles, t0 + mo * 4 + c + 1, lane);
+                else if (layer == 0) wa[mo] = tileA(tiles, kTileFwdL3 + mo * 4, lane);
+                else if (mo < 4) wa[mo] = tileA(tiles, kTileFwdL4 + mo, lane);
+            }
+            const v8i16 bop = cat8(h[2 * c], h[2 * c + 1]);
+#pragma unroll
+            for (int mo = 0; mo < 8; ++mo) acc[mo] = mfma32(wb[mo], bop, acc[mo]);
+#pragma unroll
+            for (int mo = 0; mo < 8; ++mo) wb[mo] = wa[mo];
+            // keep the order: the next chunk's LDS reads, then this chunk's products
+            if (c < 3 || layer == 0) __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
+            else __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
         }
         v4f32 *zs = layer == 0 ? z2 : z3;
 #pragma unroll
@@ -181,12 +237,87 @@ __device__ __forceinline__ v4f32 mlp_forward_block(const unsigned char *tiles, c
             h[mo] = pack4(silu(acc[mo].x), silu(acc[mo].y), silu(acc[mo].z), silu(acc[mo].w));
         }
     }
-    // layer 4 (outputs padded to 16)
+    // layer 4: the 4 chunk tiles are in wb[0..3]; four independent partial
+    // sums, added at the end
     const float *b4 = bias + 3 * kMlpHid + 4 * g;
-    v4f32 out = {b4[0], b4[1], b4[2], b4[3]};
+    v4f32 o[4];
 #pragma unroll
-    for (int ki = 0; ki < 8; ++ki) out = mfma16(tileA(tiles, kTileFwdL4 + ki, lane), h[ki], out);
-    return out;
+    for (int c = 0; c < 4; ++c)
+        o[c] = mfma32(wb[c], cat8(h[2 * c], h[2 * c + 1]),
+                      c == 0 ? (v4f32){b4[0], b4[1], b4[2], b4[3]} : (v4f32){0.f, 0.f, 0.f, 0.f});
+    return (o[0] + o[1]) + (o[2] + o[3]);
 }
+
+// ------------------------------------------------------------- inputs ---
+// Raw condition (lt, la, |x|, q0, q1, q2, ld, m0, m1, m2) + levels + row kind
+// (+ exit face and x_out of a conditional row) -> normalised inputs.
+__device__ __forceinline__ void mlp_inputs(const float *c, float ua, float ub, float uc, float ud, bool cond,
+                                           float xout, int face, float in[kMlpIn]) {
+    in[0] = (c[0] - 3.0f) * (1.0f / 1.2f);
+    in[1] = c[1] + 3.0f;
+    in[2] = c[2] - 1.0f;
+    in[3] = 2.0f * c[3] - 1.0f;
+    in[4] = 2.0f * c[4] - 1.0f;
+    in[5] = 2.0f * c[5] - 1.0f;
+    in[6] = (c[6] - 2.0f) * (1.0f / 1.2f);
+    in[7] = c[7];
+    in[8] = c[8];
+    in[9] = c[9];
+    in[10] = level_in(ua);
+    in[11] = level_in(ub);
+    in[12] = level_in(uc);
+    in[13] = level_in(ud);
+    in[14] = cond ? 1.0f : 0.0f;
+    in[15] = cond ? 0.25f * xout : 0.0f;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) in[16 + f] = (cond && face == f) ? 1.0f : 0.0f;
+    in[22] = 0.0f;
+    in[23] = 0.0f;
+}
+
+// this lane's layer-1 B operand: inputs 8(l/16)..8(l/16)+7 (group 3: zeros)
+__device__ __forceinline__ v8i16 xin_operand(const float in[kMlpIn], int lane) {
+    const int g = lane >> 4;
+    float v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = (g == 0) ? in[j] : ((g == 1) ? in[8 + j] : ((g == 2) ? in[16 + j] : 0.0f));
+    return cat8(pack4(v[0], v[1], v[2], v[3]), pack4(v[4], v[5], v[6], v[7]));
+}
+
+// 24 normalised inputs as 12 dwords of bf16 pairs (dwords 4g..4g+3 are the
+// layer-1 B operand of lane group g)
+__device__ __forceinline__ void pack_inputs(const float in[kMlpIn], uint32_t pk[12]) {
+#pragma unroll
+    for (int d = 0; d < 12; ++d) pk[d] = (uint32_t)f2bf(in[2 * d]) | ((uint32_t)f2bf(in[2 * d + 1]) << 16);
+}
+
+// ------------------------------------------------------ the reduced frame ---
+// Reduction of a start state in a cubic cell: p in [-1, 1]^3 (offsets from the
+// cell centre in half-widths), n the incoming direction.  sg[k] = sign of p_k
+// (+1 at 0); perm[r] = the cell axis of reduced axis r (ascending |p|; ties
+// keep axis order); q[r] = |p_perm[r]|; m[r] = sg[perm[r]] n_perm[r].
+struct CellFrame {
+    int perm[3];
+    float sg[3];
+    float q[3];
+};
+
+__device__ __forceinline__ void cell_reduce(float px, float py, float pz, CellFrame &F) {
+    F.sg[0] = px < 0.0f ? -1.0f : 1.0f;
+    F.sg[1] = py < 0.0f ? -1.0f : 1.0f;
+    F.sg[2] = pz < 0.0f ? -1.0f : 1.0f;
+    const float a0 = fabsf(px), a1 = fabsf(py), a2 = fabsf(pz);
+    // stable sort of three values by compare-and-swap on (value, axis)
+    float v0 = a0, v1 = a1, v2 = a2;
+    int i0 = 0, i1 = 1, i2 = 2;
+    if (v1 < v0) { float t = v0; v0 = v1; v1 = t; int s = i0; i0 = i1; i1 = s; }
+    if (v2 < v1) { float t = v1; v1 = v2; v2 = t; int s = i1; i1 = i2; i2 = s; }
+    if (v1 < v0) { float t = v0; v0 = v1; v1 = t; int s = i0; i0 = i1; i1 = s; }
+    F.perm[0] = i0; F.perm[1] = i1; F.perm[2] = i2;
+    F.q[0] = v0; F.q[1] = v1; F.q[2] = v2;
+}
+
+// component r of a cell-frame vector v in the reduced frame, and back
+__device__ __forceinline__ float pick3(float x, float y, float z, int k) { return k == 0 ? x : (k == 1 ? y : z); }
 
 }  // namespace krt

@@ -88,35 +88,42 @@ __device__ __forceinline__ int nth_set_lane(uint64_t m, int k) {
 // Batched evaluation of the escape network for the lanes of the wave set in
 // `ask` (wave-uniform control flow: every lane executes the MFMA).  The asking
 // lanes are packed in rank order into blocks of 16 samples, so a call costs
-// ceil(popcount(ask) / 16) block evaluations.  in[] are this lane's
-// normalised inputs; an asking lane receives its normalised outputs in out[].
-__device__ __attribute__((noinline)) void mlp_eval_wave(const unsigned char *img, const float *bias,
-                                              const float in[kMlpIn], int lane, uint64_t ask,
-                                              float out[kMlpOut]) {
+// ceil(popcount(ask) / 16) block evaluations.  pk[] holds this lane's inputs
+// as bf16 pairs; an asking lane receives the normalised outputs k >= k_first
+// in out[k] (the others keep their values).
+__device__ __forceinline__ void mlp_eval_wave(const unsigned char *img, const float *bias, const uint32_t pk[12],
+                                              int lane, uint64_t ask, int k_first, float out[kMlpOut]) {
     const int nask = __popcll(ask);
     const int nblk = (nask + 15) >> 4;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int rank = __popcll(ask & lt);
     const bool mine = (ask >> lane) & 1ull;
+    const int g = lane >> 4;
 #pragma unroll 1
     for (int b = 0; b < nblk; ++b) {
-        // block position p = lane & 15 holds the asker of rank 16 b + p (if any)
+        // block position p = lane & 15 holds the asker of rank 16 b + p (if any);
+        // lane group g takes that asker's input dwords 4g .. 4g + 3
         const int r = 16 * b + (lane & 15);
         const int src = (r < nask) ? nth_set_lane(ask, r) : lane;
-        // lanes 0..15 carry inputs 0..3 of their block position, lanes 16..31 inputs 4..7
-        float v[kMlpIn];
+        uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-        for (int k = 0; k < kMlpIn; ++k) v[k] = __shfl(in[k], src, 64);
-        v4i16 xb = pack4(0.f, 0.f, 0.f, 0.f);
-        if (r < nask && lane < 16) xb = pack4(v[0], v[1], v[2], v[3]);
-        else if (r < nask && lane < 32) xb = pack4(v[4], v[5], v[6], v[7]);
-        v4f32 o = mlp_forward_block(img, bias, xb, lane, nullptr, nullptr, nullptr);
-        // output k of block position p sits in lane 16*(k/4) + p, component k % 4
+        for (int d = 0; d < 12; ++d) {
+            const uint32_t v = (uint32_t)__shfl((int)pk[d], src, 64);
+            if ((d >> 2) == g) w[d & 3] = v;
+        }
+        const bool use = (r < nask) && g < 3;
+        const v4i16 lo = {(short)(use ? w[0] & 0xFFFFu : 0u), (short)(use ? w[0] >> 16 : 0u),
+                          (short)(use ? w[1] & 0xFFFFu : 0u), (short)(use ? w[1] >> 16 : 0u)};
+        const v4i16 hi = {(short)(use ? w[2] & 0xFFFFu : 0u), (short)(use ? w[2] >> 16 : 0u),
+                          (short)(use ? w[3] & 0xFFFFu : 0u), (short)(use ? w[3] >> 16 : 0u)};
+        const v4f32 o = mlp_forward_block(img, bias, cat8(lo, hi), lane, nullptr, nullptr, nullptr);
+        // output k of block position p sits in lane 16 (k / 4) + p, component k % 4
+        const bool take = mine && (rank >> 4) == b;
 #pragma unroll
         for (int k = 0; k < kMlpOut; ++k) {
-            float comp = (k % 4 == 0) ? o.x : (k % 4 == 1) ? o.y : (k % 4 == 2) ? o.z : o.w;
-            float v = __shfl(comp, 16 * (k / 4) + (rank & 15), 64);
-            if (mine && (rank >> 4) == b) out[k] = v;
+            const float comp = (k % 4 == 0) ? o.x : (k % 4 == 1) ? o.y : (k % 4 == 2) ? o.z : o.w;
+            const float v = __shfl(comp, 16 * (k / 4) + (rank & 15), 64);
+            if (take && k >= k_first) out[k] = v;
         }
     }
 }
@@ -193,7 +200,7 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
     float nx = 0.f, ny = 0.f, nz = 1.f;
     float x = 0.f, tau = 0.f;
     uint32_t ev = 0, wa1 = 0, wa2 = 0, wa3 = 0;
-    float k0c = 0.f, vxc = 0.f, vyc = 0.f, vzc = 0.f, epsc = 0.f;
+    float k0c = 0.f, vxc = 0.f, vyc = 0.f, vzc = 0.f, epsc = 0.f, kabsc = 0.f;
     uint32_t nscat_pkt = 0, ncross_pkt = 0;
     int outcome = 0;  // 1 escaped, 2 destroyed, 3 stuck
     int64_t jacc = 0;
@@ -224,7 +231,8 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
         float H = (k0c > 0.0f) ? ((kProf == 2) ? voigt_analytic(a, P.voigt_u0, fabsf(xc))
                                                : voigt_lds((kProf == 3) ? P.cls_tab + toff : T, fabsf(xc)))
                                : 0.0f;
-        float kap = k0c * H;
+        // line opacity plus the cell's grey absorption (exactly k0 H without one)
+        float kap = fmaf(k0c, H, kabsc);
         float tx = (nx > 0.0f) ? (1.0f - fx) * P.dx[0] * f_rcp(nx) : ((nx < 0.0f) ? fx * P.dx[0] * f_rcp(-nx) : INFINITY);
         float ty = (ny > 0.0f) ? (1.0f - fy) * P.dx[1] * f_rcp(ny) : ((ny < 0.0f) ? fy * P.dx[1] * f_rcp(-ny) : INFINITY);
         float tz = (nz > 0.0f) ? (1.0f - fz) * P.dx[2] * f_rcp(nz) : ((nz < 0.0f) ? fz * P.dx[2] * f_rcp(-nz) : INFINITY);
@@ -241,7 +249,10 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
             fy = fminf(fmaxf(fmaf(l * ny, P.inv_dx[1], fy), 0.0f), 1.0f);
             fz = fminf(fmaxf(fmaf(l * nz, P.inv_dx[2], fz), 0.0f), 1.0f);
             if (P.jbar_raw) jacc += (int64_t)__float2ll_rn(l * H * jscale);
-            if ((P.eps != nullptr) && (ue < epsc)) {
+            // an absorption with probability p_d = kabs / kap, else a line scattering
+            // destroyed with probability eps: one uniform decides both
+            const float pd = (kabsc > 0.0f) ? kabsc * f_rcp(kap) : 0.0f;
+            if ((P.eps != nullptr || P.kabs != nullptr) && (ue < fmaf(1.0f - pd, epsc, pd))) {
                 c_des += 1;
                 outcome = 2;
                 have = false;
@@ -292,6 +303,7 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
                 k0c = P.k0[cell];
                 if (P.vx) { vxc = P.vx[cell]; vyc = P.vy[cell]; vzc = P.vz[cell]; }
                 epsc = P.eps ? P.eps[cell] : 0.0f;
+                kabsc = P.kabs ? P.kabs[cell] : 0.0f;
                 enter_cell();
             }
         }
@@ -427,6 +439,7 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
                     if (P.vx) { vxc = P.vx[cell]; vyc = P.vy[cell]; vzc = P.vz[cell]; }
                     else { vxc = vyc = vzc = 0.0f; }
                     epsc = P.eps ? P.eps[cell] : 0.0f;
+                kabsc = P.kabs ? P.kabs[cell] : 0.0f;
                     enter_cell();
                     float xg = P.src_x0;
                     if (P.src_profile != KRT_PROF_DELTA_I) {
@@ -474,22 +487,22 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
             flight(u01(wa1), scat, xc);
         }
 
-        // ---- learned escape: one batched network call per wave (uniform) ----
+        // ---- learned whole-cell escape: batched network calls per wave (uniform) ----
+        // At a scattering inside a thick cubic cell, at least esc_depth_min below
+        // its nearest face and in the line core, one network sample replaces the
+        // walk until the photon leaves the cell: exit face, point, direction and
+        // frequency, and the expected number of scatterings skipped.
         bool mlp = false;
-        float mo[kMlpOut], mo2[kMlpOut];
-        float Rcube = 0.0f;
         if (kEsc) {
-            float lt = 0.0f;
-            if (scat) {
-                float rx = fminf(fx, 1.0f - fx) * P.dx[0];
-                float ry = fminf(fy, 1.0f - fy) * P.dx[1];
-                float rz = fminf(fz, 1.0f - fz) * P.dx[2];
-                Rcube = fminf(rx, fminf(ry, rz));
-                float tr = k0c * Rcube;
-                if (tr >= P.esc_tau_min && fabsf(xc) <= P.esc_x_max) {
-                    tr = fminf(tr, P.esc_tau_max);
-                    Rcube = tr * f_rcp(k0c);
-                    lt = __log10f(tr);
+            CellFrame CF{};
+            float ltc = 0.0f, ldep = 0.0f;
+            if (scat && P.esc_cubic) {
+                const float tc = k0c * P.esc_half_dx;  // line-centre depth, centre to face
+                cell_reduce(2.0f * fx - 1.0f, 2.0f * fy - 1.0f, 2.0f * fz - 1.0f, CF);
+                const float dep = tc * (1.0f - CF.q[2]);
+                if (tc >= P.esc_tc_min && tc <= P.esc_tc_max && dep >= P.esc_depth_min && fabsf(xc) <= P.esc_x_max) {
+                    ltc = __log10f(tc);
+                    ldep = __log10f(dep);
                     mlp = true;
                 }
             }
@@ -498,70 +511,107 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
             const uint64_t wm = __ballot(mlp);
             const int need_lanes = (__ballot(done) != 0ull) ? P.esc_tail_lanes : P.esc_min_lanes;
             if (__popcll(wm) >= need_lanes) {
-                // marginal evaluation: exit frequency (u_a), exit point (u_b, u_c), count
-                const uint4 C = philox(make_uint4(ev, (uint32_t)pid, (uint32_t)(pid >> 32), 2u), P.key0, P.key1);
-                const uint4 D = philox(make_uint4(ev, (uint32_t)pid, (uint32_t)(pid >> 32), 3u), P.key0, P.key1);
+                const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
+                const uint4 C = philox(make_uint4(ev, plo, phi, 2u), P.key0, P.key1);
+                const uint4 D = philox(make_uint4(ev, plo, phi, 3u), P.key0, P.key1);
+                // the condition in the reduced frame
+                float cnd[10];
+                cnd[0] = ltc;
+                cnd[1] = P.esc_log10a;
+                cnd[2] = fabsf(xc);
+                cnd[3] = CF.q[0]; cnd[4] = CF.q[1]; cnd[5] = CF.q[2];
+                cnd[6] = ldep;
+#pragma unroll
+                for (int r = 0; r < 3; ++r)
+                    cnd[7 + r] = pick3(CF.sg[0], CF.sg[1], CF.sg[2], CF.perm[r]) * pick3(nx, ny, nz, CF.perm[r]);
+                // two evaluations through one inlined copy of the network: marginal
+                // (exit face logits, side and magnitude of x_out at level u_a,
+                // count, <x^2> at level u_b), then conditional on the sampled exit
+                // face and frequency (exit offsets at u_a, u_b; cosine at u_c;
+                // alpha at u_d)
                 float in[kMlpIn];
-                in[0] = (lt - 3.5f) * (1.0f / 1.5f);
-                in[1] = P.esc_log10a + 3.0f;
-                in[2] = xc * 0.25f;
-                in[3] = level_in(u01(C.x));
-                in[4] = level_in(u01(C.y));
-                in[5] = level_in(u01(D.y));
-                in[6] = 0.0f;
-                in[7] = 0.0f;
-                mlp_eval_wave(mimg, mbias, in, lane, wm, mo);
-                // exit point on the face, then the symmetry of the cube: face,
-                // swap of (s, t), signs
-                float tt = fminf(fmaxf(mo[kOutT] * mnorm[kMlpOut + kOutT] + mnorm[kOutT], -1.0f), 1.0f);
-                float ss = fminf(fmaxf(mo[kOutS] * mnorm[kMlpOut + kOutS] + mnorm[kOutS], -1.0f), 1.0f);
-                const uint32_t bits = C.z;
-                if (bits & 0x100u) { float tmp = ss; ss = tt; tt = tmp; }
-                if (bits & 0x200u) ss = -ss;
-                if (bits & 0x400u) tt = -tt;
-                // exit frequency: side from the learned P(x_out >= 0) and a word of
-                // purpose 3, magnitude from that side's quantile at level u_a
-                const bool pos = u01(D.x) < sigmoid_f(mo[kOutLogit]);
-                const int ko = pos ? kOutXPos : kOutXNeg;
-                const float mag = fmaxf(mo[ko] * mnorm[kMlpOut + ko] + mnorm[ko], 0.0f);
-                const float xo = pos ? mag : -mag;
-                // conditional evaluation: exit direction given the exit frequency and
-                // the exit point's distance from the face centre (mu at u_a, alpha at u_b)
-                const float rr = f_sqrt(ss * ss + tt * tt);
-                in[3] = level_in(u01(D.z));
-                in[4] = level_in(u01(C.w));
-                in[5] = 0.25f * xo;
-                in[6] = 1.41421356f * rr - 1.0f;
-                in[7] = 1.0f;
-                mlp_eval_wave(mimg, mbias, in, lane, wm, mo2);
+                uint32_t pk[12];
+                float mo[kMlpOut];
+#pragma unroll
+                for (int k = 0; k < kMlpOut; ++k) mo[k] = 0.0f;
+                int face = 5;
+                float xo = 0.0f;  // reduced sign (that of x_in)
+#pragma unroll 1
+                for (int e = 0; e < 2; ++e) {
+                    if (e == 0) mlp_inputs(cnd, u01(C.x), u01(C.y), u01(D.z), u01(D.w), false, 0.0f, 0, in);
+                    else mlp_inputs(cnd, u01(D.x), u01(D.y), u01(D.z), u01(D.w), true, xo, face, in);
+                    pack_inputs(in, pk);
+                    mlp_eval_wave(mimg, mbias, pk, lane, wm, e == 0 ? 0 : kOutYS, mo);
+                    if (e == 0) {
+                        // exit face from the softmax of the logits, at level u01(C.z)
+                        float mx = mo[0];
+#pragma unroll
+                        for (int f = 1; f < 6; ++f) mx = fmaxf(mx, mo[f]);
+                        float ef[6], se = 0.0f;
+#pragma unroll
+                        for (int f = 0; f < 6; ++f) { ef[f] = __expf(mo[f] - mx); se += ef[f]; }
+                        const float uf = u01(C.z) * se;
+                        float c2 = 0.0f;
+                        bool found = false;
+#pragma unroll
+                        for (int f = 0; f < 6; ++f) {
+                            c2 += ef[f];
+                            if (!found && uf < c2) { face = f; found = true; }
+                        }
+                        // exit frequency: side from the learned P(x_out >= 0) at level
+                        // u01(C.w), magnitude from that side's quantile at level u_a
+                        const bool pos = u01(C.w) < sigmoid_f(mo[kOutSide]);
+                        const int ko = pos ? kOutXPos : kOutXNeg;
+                        const float mag =
+                            fmaxf((pos ? mo[kOutXPos] : mo[kOutXNeg]) * mnorm[kMlpOut + ko] + mnorm[ko], 0.0f);
+                        xo = pos ? mag : -mag;
+                    }
+                }
                 if (mlp) {
-                    // ---- exit from the cube centred here (half-width Rcube) ----
-                    float lns = mo[kOutLogN] * mnorm[kMlpOut + kOutLogN] + mnorm[kOutLogN] +
-                                mnorm[2 * kMlpOut + cal_bin(lt, xc)];
-                    float lx2 = mo[kOutLogX2] * mnorm[kMlpOut + kOutLogX2] + mnorm[kOutLogX2];
-                    float mu = fminf(fmaxf(mo2[kOutMu] * mnorm[kMlpOut + kOutMu] + mnorm[kOutMu], 1e-3f), 1.0f);
-                    const float al = fminf(fmaxf(mo2[kOutAlpha] * mnorm[kMlpOut + kOutAlpha] + mnorm[kOutAlpha], 0.0f),
+                    const float lns = mo[kOutLogN] * mnorm[kMlpOut + kOutLogN] + mnorm[kOutLogN] +
+                                      mnorm[kNormCal + cal_bin(ltc, ldep, fabsf(xc))];
+                    const float lx2 = mo[kOutLogX2] * mnorm[kMlpOut + kOutLogX2] + mnorm[kOutLogX2];
+                    const float ys = mo[kOutYS] * mnorm[kMlpOut + kOutYS] + mnorm[kOutYS];
+                    const float yt = mo[kOutYT] * mnorm[kMlpOut + kOutYT] + mnorm[kOutYT];
+                    const float mu = fminf(fmaxf(mo[kOutMu] * mnorm[kMlpOut + kOutMu] + mnorm[kOutMu], 1e-3f), 1.0f);
+                    const float al = fminf(fmaxf(mo[kOutAlpha] * mnorm[kMlpOut + kOutAlpha] + mnorm[kOutAlpha], 0.0f),
                                            3.14159265f);
-                    int face = (int)__umulhi(bits, 6u);
-                    int axis = face >> 1;
-                    float sgn = (face & 1) ? -1.0f : 1.0f;
-                    // tangential direction at angle +-alpha from the offset (s, t)
-                    // (the offset's direction is arbitrary at the face centre)
+                    // exit point and direction in the reduced frame: face axis k, outward side
+                    const int k = face >> 1;
+                    const float side = (face & 1) ? 1.0f : -1.0f;
+                    const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+                    const float qk = pick3(CF.q[0], CF.q[1], CF.q[2], k);
+                    const float qa = pick3(CF.q[0], CF.q[1], CF.q[2], k1);
+                    const float qb = pick3(CF.q[0], CF.q[1], CF.q[2], k2);
+                    const float dpl = 1.0f - side * qk;
+                    const float es = fminf(fmaxf(qa + dpl * ys, -1.0f), 1.0f);
+                    const float et = fminf(fmaxf(qb + dpl * yt, -1.0f), 1.0f);
+                    // tangential direction at angle +-alpha from the offset (es - qa, et - qb)
+                    const float ds = es - qa, dt = et - qb;
+                    const float rr = f_sqrt(ds * ds + dt * dt);
                     const float ir = (rr > 0.0f) ? f_rcp(rr) : 0.0f;
-                    const float c0 = (rr > 0.0f) ? ss * ir : 1.0f, s0 = tt * ir;
-                    const float arev = al * 0.159154943f * ((D.w & 1u) ? -1.0f : 1.0f);
+                    const float c0 = (rr > 0.0f) ? ds * ir : 1.0f, s0 = dt * ir;
+                    const float arev = al * 0.159154943f * ((C.z & 1u) ? -1.0f : 1.0f);
                     const float ca = cos_rev(arev), sa = sin_rev(arev);
-                    float sm = f_sqrt(fmaxf(0.0f, 1.0f - mu * mu));
-                    float dn = mu * sgn, d1 = sm * (c0 * ca - s0 * sa), d2 = sm * (s0 * ca + c0 * sa);
-                    float dp[3], ddir[3];
-                    int a1 = (axis + 1) % 3, a2 = (axis + 2) % 3;
-                    dp[axis] = sgn * Rcube; dp[a1] = ss * Rcube; dp[a2] = tt * Rcube;
-                    ddir[axis] = dn; ddir[a1] = d1; ddir[a2] = d2;
-                    fx = fminf(fmaxf(fmaf(dp[0], P.inv_dx[0], fx), 0.0f), 1.0f);
-                    fy = fminf(fmaxf(fmaf(dp[1], P.inv_dx[1], fy), 0.0f), 1.0f);
-                    fz = fminf(fmaxf(fmaf(dp[2], P.inv_dx[2], fz), 0.0f), 1.0f);
-                    nx = ddir[0]; ny = ddir[1]; nz = ddir[2];
-                    float Ns = fmaxf(f_exp(lns), 1.0f);  // E[N_s | condition]
+                    const float sm = f_sqrt(fmaxf(0.0f, 1.0f - mu * mu));
+                    const float d1 = sm * (c0 * ca - s0 * sa), d2 = sm * (s0 * ca + c0 * sa);
+                    // back to the cell frame: reduced axis r is cell axis perm[r] with sign sg
+                    float pc[3] = {0.0f, 0.0f, 0.0f}, nc[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) {
+                        const float R_ = (r == k) ? side : ((r == k1) ? es : et);
+                        const float V_ = (r == k) ? side * mu : ((r == k1) ? d1 : d2);
+                        const int axc = CF.perm[r];
+                        const float sgc = pick3(CF.sg[0], CF.sg[1], CF.sg[2], axc);
+#pragma unroll
+                        for (int a3 = 0; a3 < 3; ++a3)
+                            if (a3 == axc) { pc[a3] = sgc * R_; nc[a3] = sgc * V_; }
+                    }
+                    fx = fminf(fmaxf(0.5f * (pc[0] + 1.0f), 0.0f), 1.0f);
+                    fy = fminf(fmaxf(0.5f * (pc[1] + 1.0f), 0.0f), 1.0f);
+                    fz = fminf(fmaxf(0.5f * (pc[2] + 1.0f), 0.0f), 1.0f);
+                    nx = nc[0]; ny = nc[1]; nz = nc[2];
+                    const float Ns = fmaxf(f_exp(lns), 1.0f);  // E[N_s | condition]
                     // emissivity of the skipped scatterings: thermalised core, camera
                     // frequency ~ N(n_cam.v, (<x^2> + 1)/3), integrated exactly over the
                     // channels (no sampling noise); mass outside the channels is dropped
@@ -587,7 +637,8 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
                         }
                         c_drop += (int64_t)__float2ll_rn(Ns * fmaxf(0.0f, 1.0f - inside));
                     }
-                    x = xo + nx * vxc + ny * vyc + nz * vzc;
+                    const float sx = (xc < 0.0f) ? -1.0f : 1.0f;
+                    x = sx * xo + nx * vxc + ny * vyc + nz * vzc;
                     c_mlp += 1;
                     c_skip += (int64_t)__float2ll_rn(Ns);
                 }

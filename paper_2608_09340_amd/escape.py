@@ -1,9 +1,10 @@
-"""Training recipe of the learned escape: record single-cell escapes with the
-plain walk on the GPU (krt_escape_record), fit the output normalisation, then
-run the BF16-MFMA training kernels (krt_escape_train) in stages of decreasing
-learning rate and growing batch, then calibrate the mean scattering count
-(krt_escape_calibrate).  Only the order of the library calls lives
-here; records, gradients and Adam updates are computed by libkrt.
+"""Training recipe of the learned whole-cell escape: record whole-cell walks
+with the plain transport arithmetic on the GPU (krt_escape_record), fit the
+output normalisation, then run the BF16-MFMA training kernels
+(krt_escape_train) in stages of decreasing learning rate and growing batch,
+then calibrate the mean scattering count (krt_escape_calibrate).  Only the
+order of the library calls lives here; records, gradients and Adam updates
+are computed by libkrt.
 """
 from __future__ import annotations
 
@@ -17,23 +18,26 @@ DEFAULT_STAGES = ((6000, 4096, 2e-3), (6000, 8192, 1e-3), (6000, 16384, 5e-4), (
                   (6000, 32768, 1.25e-4))
 
 
-# Run options of the learned escape on the benchmark cloud: network calls where
-# the cube about the scattering point is at least 50 line-centre mean free paths
-# deep, once 16 lanes of a wave ask.
-DEFAULT_RUN = {"esc_tau_min": 50.0, "esc_min_lanes": 16}
-# log10 tau_R range of the training records for that setting
-DEFAULT_LOG10_TAU = (1.0, 5.0)
+# Run options of the learned escape on the benchmark cloud: network calls in
+# cells at least 100 line-centre mean free paths deep, at scattering points at
+# least 3 below the nearest face, once 16 lanes of a wave ask.
+DEFAULT_RUN = {"esc_cell_tau_min": 100.0, "esc_tau_min": 3.0, "esc_min_lanes": 16}
+# log10 tau_c (centre to face) range of the training records for that setting
+DEFAULT_LOG10_TAU = (1.5, 5.0)
 
 
 def train_escape(ctx: "krt.Context", line: int = 0, n_records: int = 8_000_000, seed: int = 1,
-                 log10_tau=(2.0, 5.0), stages=DEFAULT_STAGES, record_offset: int = 0, lines=None) -> dict:
-    """Record `n_records` escapes from cubes with log10 tau_R uniform in
-    `log10_tau` (line `line`, or split evenly over `lines` to cover several
-    damping values, whose tables must be built), initialise the network from
-    `seed`, fit the normalisation (and the log10 a range the network may then
-    be used on), train, and calibrate the predicted mean scattering count per
-    (log10 tau_R, |x_in|) bin on the records.  Returns the record buffer and
-    the per-step loss history (all stages, concatenated)."""
+                 log10_tau=DEFAULT_LOG10_TAU, stages=DEFAULT_STAGES, record_offset: int = 0, lines=None,
+                 depth_lo: float = 0.3) -> dict:
+    """Record `n_records` whole-cell walks from cells with log10 tau_c uniform
+    in `log10_tau` and start points whose log10 depth below the nearest face
+    is uniform from `depth_lo` up (line `line`, or split evenly over `lines`
+    to cover several damping values, whose tables must be built), initialise
+    the network from `seed`, fit the normalisation (and the ranges the network
+    may then be used on), train, and calibrate the predicted mean scattering
+    count per (log10 tau_c, log10 depth, |x_in|) bin on the records.  Returns
+    the record buffer and the per-step loss history (all stages,
+    concatenated)."""
     import torch
     dev = torch.device("cuda", ctx.device)
     lines = [line] if lines is None else [int(v) for v in lines]
@@ -42,7 +46,8 @@ def train_escape(ctx: "krt.Context", line: int = 0, n_records: int = 8_000_000, 
     for k, ln in enumerate(lines):
         b0, b1 = int(bounds[k]), int(bounds[k + 1])
         # disjoint packet ranges, so records of different lines are independent
-        ctx.krt_escape_record(ln, b1 - b0, seed, record_offset + b0, log10_tau[0], log10_tau[1], rec[b0:b1])
+        ctx.krt_escape_record(ln, b1 - b0, seed, record_offset + b0, log10_tau[0], log10_tau[1], rec[b0:b1],
+                              depth_lo=depth_lo)
     ctx.krt_escape_init(seed)
     ctx.krt_escape_fit_norm(rec, n_records)
     hist = []

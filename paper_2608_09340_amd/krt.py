@@ -24,7 +24,8 @@ class krt_grid_desc(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
                 ("bc", C.c_int32 * 3), ("n_lines", C.c_int32),
                 ("k0_dev", C.c_void_p), ("vel_dev", C.c_void_p), ("eps_dev", C.c_void_p),
-                ("emis_dev", C.c_void_p), ("tclass_dev", C.c_void_p), ("n_tclass", C.c_int32),
+                ("emis_dev", C.c_void_p), ("kabs_dev", C.c_void_p), ("tclass_dev", C.c_void_p),
+                ("n_tclass", C.c_int32),
                 ("tclass_bratio", C.c_double * 8)]
 
 
@@ -42,9 +43,14 @@ class krt_run_opts(C.Structure):
                 ("escape_mode", C.c_int32), ("wg_size", C.c_int32), ("wg_per_cu", C.c_int32),
                 ("emis_frac_bits", C.c_int32), ("jbar_frac_bits", C.c_int32),
                 ("norm_packets", C.c_uint64), ("luminosity", C.c_double),
-                ("esc_tau_min", C.c_double), ("esc_min_lanes", C.c_int32),
-                ("esc_tail_lanes", C.c_int32), ("esc_evals", C.c_int32), ("tail_lanes", C.c_int32),
-                ("profile_mode", C.c_int32)]
+                ("esc_tau_min", C.c_double), ("esc_cell_tau_min", C.c_double), ("esc_min_lanes", C.c_int32),
+                ("esc_tail_lanes", C.c_int32), ("tail_lanes", C.c_int32), ("profile_mode", C.c_int32)]
+
+
+class krt_escape_cond(C.Structure):
+    _fields_ = [("log10_tau_lo", C.c_double), ("log10_tau_hi", C.c_double), ("log10_depth_lo", C.c_double),
+                ("fixed", C.c_int32), ("iso_dir", C.c_int32), ("x_in", C.c_double), ("q", C.c_double * 3),
+                ("n_in", C.c_double * 3)]
 
 
 class krt_tallies(C.Structure):
@@ -58,7 +64,8 @@ class krt_levels_desc(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("ncell", C.c_int64), ("E", C.c_void_p), ("g", C.c_void_p), ("A", C.c_void_p),
                 ("Cd", C.c_void_p), ("sigma0", C.c_void_p), ("ncoll_dev", C.c_void_p),
                 ("ntot_dev", C.c_void_p), ("pops_dev", C.c_void_p), ("k0_out_dev", C.c_void_p),
-                ("eps_out_dev", C.c_void_p)]
+                ("eps_out_dev", C.c_void_p), ("emis_out_dev", C.c_void_p), ("cell_volume", C.c_double),
+                ("lum_out", C.c_void_p)]
 
 
 class krt_image_desc(C.Structure):
@@ -74,7 +81,7 @@ EXPORTS = ["krt_create", "krt_destroy", "krt_last_error", "krt_device_cus", "krt
            "krt_escape_init", "krt_escape_record", "krt_escape_fit_norm", "krt_escape_calibrate", "krt_escape_grad",
            "krt_escape_train", "krt_escape_get_weights", "krt_escape_put_weights", "krt_escape_forward",
            "krt_image", "krt_last_image_ms"]
-ESC_NPARAMS, ESC_NNORM, ESC_NIN, ESC_NOUT, ESC_NCAL, ESC_NREC = 35466, 280, 8, 10, 256, 11
+ESC_NPARAMS, ESC_NNORM, ESC_NIN, ESC_NOUT, ESC_NCAL, ESC_NREC = 38288, 296, 17, 16, 256, 20
 
 _lib = None
 
@@ -108,7 +115,7 @@ def load(path: str = LIB_PATH):
     L.krt_debug_voigt_analytic.argtypes = [p, C.c_double, p, i64, p]
     L.krt_debug_upar.argtypes = [p, i32, C.c_float, u64, u64, u32, i64, p]
     L.krt_escape_init.argtypes = [p, u64]
-    L.krt_escape_record.argtypes = [p, i32, u64, u64, u64, C.c_double, C.c_double, i32, C.c_double, p]
+    L.krt_escape_record.argtypes = [p, i32, u64, u64, u64, C.POINTER(krt_escape_cond), p]
     L.krt_escape_fit_norm.argtypes = [p, p, u64]
     L.krt_escape_calibrate.argtypes = [p, p, u64]
     L.krt_escape_grad.argtypes = [p, p, p, p, i32, p, p]
@@ -182,9 +189,10 @@ class Context:
 
     # ------------------------------------------------------------- calls
     def krt_grid_upload(self, n, lo, hi, bc, k0, vel=None, eps=None, emis=None, n_lines=1, tclass=None,
-                        tclass_bratio=None):
+                        tclass_bratio=None, kabs=None):
         """tclass: device uint8 [ncell] temperature class per cell (or None);
-        tclass_bratio: the Doppler width of each class over the reference."""
+        tclass_bratio: the Doppler width of each class over the reference;
+        kabs: device FP32 [ncell] grey absorption coefficient (or None)."""
         d = krt_grid_desc()
         d.n[:] = [int(v) for v in n]
         d.lo[:] = [float(v) for v in lo]
@@ -195,12 +203,13 @@ class Context:
         d.vel_dev = None if vel is None else vel.data_ptr()
         d.eps_dev = None if eps is None else eps.data_ptr()
         d.emis_dev = None if emis is None else emis.data_ptr()
+        d.kabs_dev = None if kabs is None else kabs.data_ptr()
         if tclass is not None:
             br = [float(v) for v in tclass_bratio]
             d.tclass_dev = tclass.data_ptr()
             d.n_tclass = len(br)
             d.tclass_bratio[:len(br)] = br
-        self._keep["grid"] = (k0, vel, eps, emis, tclass)  # borrowed by the library
+        self._keep["grid"] = (k0, vel, eps, emis, tclass, kabs)  # borrowed by the library
         self._check(self.L.krt_grid_upload(self.h, C.byref(d)))
 
     def krt_tables_build(self, lines):
@@ -223,10 +232,24 @@ class Context:
     def krt_escape_init(self, seed):
         self._check(self.L.krt_escape_init(self.h, int(seed)))
 
-    def krt_escape_record(self, line, n, seed, offset, lt_lo, lt_hi, out, x_fixed=None):
-        self._check(self.L.krt_escape_record(self.h, int(line), int(n), int(seed), int(offset), float(lt_lo),
-                                             float(lt_hi), 0 if x_fixed is None else 1,
-                                             0.0 if x_fixed is None else float(x_fixed), _ptr(out)))
+    def krt_escape_record(self, line, n, seed, offset, lt_lo, lt_hi, out, depth_lo=0.3, x_in=None, q=None,
+                          n_in=None):
+        """Whole-cell walks: log10 tau_c uniform in [lt_lo, lt_hi]; with x_in and
+        q given (reduced frame) every walk starts there, from direction n_in or
+        isotropic directions (n_in None); otherwise the training distribution
+        with log10 depth from depth_lo up."""
+        c = krt_escape_cond()
+        c.log10_tau_lo, c.log10_tau_hi, c.log10_depth_lo = float(lt_lo), float(lt_hi), float(depth_lo)
+        if x_in is not None:
+            c.fixed = 1
+            c.x_in = float(x_in)
+            c.q[:] = [float(v) for v in q]
+            if n_in is None:
+                c.iso_dir = 1
+            else:
+                c.n_in[:] = [float(v) for v in n_in]
+        self._check(self.L.krt_escape_record(self.h, int(line), int(n), int(seed), int(offset), C.byref(c),
+                                             _ptr(out)))
 
     def krt_escape_fit_norm(self, rec, n):
         self._check(self.L.krt_escape_fit_norm(self.h, _ptr(rec), int(n)))
@@ -235,9 +258,9 @@ class Context:
         self._check(self.L.krt_escape_calibrate(self.h, _ptr(rec), int(n)))
 
     def krt_escape_grad(self, rec, idx, u, grad_out, loss_out=None):
-        """u: [batch][4] = (u_a, u_b, u_c, 1 for a conditional row else 0)."""
-        if tuple(u.shape) != (idx.numel(), 4):
-            raise ValueError(f"u must be [{idx.numel()}][4], got {tuple(u.shape)}")
+        """u: [batch][5] = (u_a, u_b, u_c, u_d, 1 for a conditional row else 0)."""
+        if tuple(u.shape) != (idx.numel(), 5):
+            raise ValueError(f"u must be [{idx.numel()}][5], got {tuple(u.shape)}")
         self._check(self.L.krt_escape_grad(self.h, _ptr(rec), _ptr(idx), _ptr(u), int(idx.numel()),
                                            _ptr(grad_out), _ptr(loss_out)))
 
@@ -252,8 +275,8 @@ class Context:
         self._check(self.L.krt_escape_put_weights(self.h, _ptr(w), w.numel()))
 
     def krt_escape_forward(self, inp, out):
-        """inp: [n][8] raw (log10 tau_R, log10 a, x_in, u_a, u_b, u_c or (flag 1) x_out, r, flag);
-        out: [n][10]."""
+        """inp: [n][17] raw (log10 tau_c, log10 a, |x_in|, q0, q1, q2, log10 depth, n_in (3), u_a, u_b,
+        u_c, u_d, flag, x_out, face); out: [n][16]."""
         if inp.dim() != 2 or inp.shape[1] != ESC_NIN or tuple(out.shape) != (inp.shape[0], ESC_NOUT):
             raise ValueError(f"inp must be [n][{ESC_NIN}] and out [n][{ESC_NOUT}]")
         self._check(self.L.krt_escape_forward(self.h, _ptr(inp), inp.shape[0], _ptr(out)))
@@ -283,8 +306,8 @@ class Context:
 
 def make_opts(prob: dict, *, line=0, packet_offset=0, accumulate=False, max_events=0,
               wg_size=0, wg_per_cu=0, emis_frac_bits=0, jbar_frac_bits=0, norm_packets=0, escape_mode=0,
-              luminosity=0.0, esc_tau_min=0.0, esc_min_lanes=0, esc_tail_lanes=0,
-              esc_evals=0, tail_lanes=0, profile_mode=0) -> krt_run_opts:
+              luminosity=0.0, esc_tau_min=0.0, esc_cell_tau_min=0.0, esc_min_lanes=0, esc_tail_lanes=0,
+              tail_lanes=0, profile_mode=0) -> krt_run_opts:
     """krt_run_opts from a workload problem dict (paper_2608_09340_amd.workloads)."""
     o = krt_run_opts()
     src, t = prob["source"], prob["tally"]
@@ -314,9 +337,9 @@ def make_opts(prob: dict, *, line=0, packet_offset=0, accumulate=False, max_even
     o.norm_packets = int(norm_packets)
     o.luminosity = float(luminosity)
     o.esc_tau_min = float(esc_tau_min)
+    o.esc_cell_tau_min = float(esc_cell_tau_min)
     o.esc_min_lanes = int(esc_min_lanes)
     o.esc_tail_lanes = int(esc_tail_lanes)
-    o.esc_evals = int(esc_evals)
     o.profile_mode = int(profile_mode)
     o.tail_lanes = int(tail_lanes)
     return o
@@ -341,11 +364,13 @@ class Transport:
         self.vel = f32(g.get("vel"))
         self.eps = f32(g.get("eps"))
         self.emis_w = f32(g.get("emis"))
+        self.kabs = f32(g.get("kabs"))
         tcl = g.get("tclass")
         self.tclass = None if tcl is None else torch.from_numpy(
             np.ascontiguousarray(tcl, dtype=np.uint8).reshape(-1)).to(dev)
         self.ctx.krt_grid_upload(self.n, g["lo"], g["hi"], g["bc"], self.k0, self.vel, self.eps, self.emis_w,
-                                 n_lines=self.n_lines, tclass=self.tclass, tclass_bratio=g.get("tclass_bratio"))
+                                 n_lines=self.n_lines, tclass=self.tclass, tclass_bratio=g.get("tclass_bratio"),
+                                 kabs=self.kabs)
         ln = prob["line"]
         if lines is None:
             lines = [(ln["a"], ln.get("phase", 0))]
@@ -394,6 +419,8 @@ class Transport:
         return out
 
     def run(self, n_packets: int, seed: int = 0, packet_log: bool = False, **kw) -> dict:
+        """One krt_mc_run over this workload; returns the
+        raw tallies and counters on the host."""
         opts = make_opts(self.prob, **kw)
         plog = None
         if packet_log:

@@ -11,6 +11,8 @@ the tallies and the FP64 level solves all run in libkrt's kernels.
 """
 from __future__ import annotations
 
+import time
+
 import numpy as np
 
 from . import krt
@@ -46,13 +48,12 @@ class LambdaIteration:
         scale = tau_mean_line0 / (k0_0 * self.dx)
         self.ntot = torch.from_numpy(rho * scale).to(dev)
         self._levels(None)
+        # frozen emission per line, n_u A_ul per unit volume, and the line powers
+        # (cell volume x sum over cells), from the library's level solve at
+        # collisional equilibrium
+        self.emis = torch.zeros(self.nlines * nc, dtype=torch.float32, device=dev)
+        self.lum = self._levels(None, emis_out=self.emis)
         self.pops0 = self.pops.clone()
-        # frozen emission weights per line: n_u A_ul (per unit volume)
-        P0 = self.pops0.view(nc, self.nl)
-        A = rot["A"]
-        emis = torch.stack([P0[:, l + 1] * float(A[l + 1, l]) for l in range(self.nlines)]).float().contiguous()
-        self.emis = emis.reshape(-1)
-        self.lum = [float(emis[l].double().sum().item()) * self.vcell for l in range(self.nlines)]
         vel = np.asarray(cloud["vel"], dtype=np.float32).reshape(3, nc)
         self.vel = torch.from_numpy(vel).to(dev)
         ctx.krt_grid_upload(n, cloud["lo"], cloud["hi"], cloud["bc"], self.k0, self.vel, self.eps, self.emis,
@@ -63,14 +64,23 @@ class LambdaIteration:
         self.spec_raw = torch.zeros(66, dtype=torch.int64, device=dev)
         self.counters = torch.zeros(krt.KRT_NCOUNTERS, dtype=torch.int64, device=dev)
 
-    def _levels(self, jbar):
+    def _levels(self, jbar, emis_out=None):
+        """krt_levels_update over all cells; with emis_out, also the emission
+        n_u A_ul per cell and the line powers (returned, one per line)."""
         d = krt.krt_levels_desc()
         d.n_levels = self.nl
         d.ncell = self.ncell
         d.E, d.g, d.A, d.Cd, d.sigma0 = [k.ctypes.data for k in self._keep]
         d.ncoll_dev, d.ntot_dev, d.pops_dev = self.ncoll.data_ptr(), self.ntot.data_ptr(), self.pops.data_ptr()
         d.k0_out_dev, d.eps_out_dev = self.k0.data_ptr(), self.eps.data_ptr()
+        lum = None
+        if emis_out is not None:
+            lum = np.zeros(self.nlines, dtype=np.float64)
+            d.emis_out_dev = emis_out.data_ptr()
+            d.cell_volume = self.vcell
+            d.lum_out = lum.ctypes.data
         self.ctx.krt_levels_update(d, jbar)
+        return None if lum is None else lum.tolist()
 
     def transport_line(self, line: int, n_packets: int, seed: int, packet_offset: int = 0) -> dict:
         nc = self.ncell
@@ -92,11 +102,14 @@ class LambdaIteration:
         for it in range(n_iter):
             old = self.pops.clone()
             runs = [self.transport_line(l, n_packets, seed + it * 16 + l) for l in range(self.nlines)]
+            self.torch.cuda.synchronize()
+            t0 = time.perf_counter()
             self._levels(self.jbar)
+            t_lev = (time.perf_counter() - t0) * 1e3
             P, Q = self.pops.view(nc, self.nl), old.view(nc, self.nl)
             dmax = float(((P - Q).abs() / Q.abs().clamp_min(1e-300)).max().item())
             hist.append({"iteration": it, "max_rel_change": dmax,
                          "scatterings": sum(r["counters"]["scatterings"] for r in runs),
-                         "kernel_ms": sum(r["kernel_ms"] for r in runs),
+                         "kernel_ms": sum(r["kernel_ms"] for r in runs), "levels_ms": t_lev,
                          "rc": [r["rc"] for r in runs]})
         return hist

@@ -4,7 +4,8 @@ Each builder returns a problem dict of numpy arrays and scalars:
 
     grid   : n[3], lo[3], hi[3], bc[3] (0 vacuum, 1 periodic), k0[ncell] (line-centre
              opacity per unit length, n_l*sigma_0), vel[3, ncell] (bulk velocity in
-             Doppler units) or None, eps[ncell] or None, emis[ncell] or None
+             Doppler units) or None, eps[ncell] or None, emis[ncell] or None,
+             kabs[ncell] (grey absorption coefficient, units of k0) or None
     line   : a (damping), phase (0 isotropic, 1 dipole)
     source : kind (0 point, 1 plane z=pos[2], 2 volume, 3 beam), pos[3], dir[3],
              profile (0 delta at x0, 1 Voigt, 2 Gaussian), x0
@@ -31,14 +32,15 @@ def _cell_centres(n, lo, hi):
     return x.reshape(-1), y.reshape(-1), z.reshape(-1)
 
 
-def _problem(n, lo, hi, bc, k0, a, *, vel=None, eps=None, emis=None, phase=PHASE_ISO,
+def _problem(n, lo, hi, bc, k0, a, *, vel=None, eps=None, emis=None, kabs=None, phase=PHASE_ISO,
              source=None, tally=None, max_events=1 << 40):
     return {
         "grid": {"n": list(n), "lo": list(lo), "hi": list(hi), "bc": list(bc),
                  "k0": np.ascontiguousarray(k0, dtype=np.float32).reshape(-1),
                  "vel": None if vel is None else np.ascontiguousarray(vel, dtype=np.float32).reshape(3, -1),
                  "eps": None if eps is None else np.ascontiguousarray(eps, dtype=np.float32).reshape(-1),
-                 "emis": None if emis is None else np.ascontiguousarray(emis, dtype=np.float32).reshape(-1)},
+                 "emis": None if emis is None else np.ascontiguousarray(emis, dtype=np.float32).reshape(-1),
+                 "kabs": None if kabs is None else np.ascontiguousarray(kabs, dtype=np.float32).reshape(-1)},
         "line": {"a": float(a), "phase": int(phase)},
         "source": source,
         "tally": tally,
@@ -55,6 +57,15 @@ def slab(tau0=1e3, a=1e-2, nz=32, *, spec=(200, -30.0, 30.0), phase=PHASE_ISO, n
                     phase=phase,
                     source={"kind": SRC_PLANE, "pos": (0.0, 0.0, 0.0), "profile": PROF_DELTA, "x0": 0.0},
                     tally={"spec_nbins": spec[0], "spec_lo": spec[1], "spec_hi": spec[2]})
+
+
+def dusty_slab(tau0=1e5, a=0.015, tau_a=0.03, nz=64, nxy=1, spec=(200, -60.0, 60.0)):
+    """Static slab |z| <= 1, periodic in x and y, line-centre depth tau0 and grey
+    (dust) absorption depth tau_a from midplane to face, plane source at z = 0
+    emitting x = 0 photons isotropically (the dusty-slab setup of Sec. 3.2)."""
+    p = slab(tau0, a, nz, spec=spec, nxy=nxy)
+    p["grid"]["kabs"] = np.full(nxy * nxy * nz, tau_a, dtype=np.float32)
+    return p
 
 
 def slab_c0():

@@ -81,7 +81,7 @@ def test_binding_structs_match_header_layout(tmp_path):
     if cc is None:
         pytest.skip("no host C compiler")
     structs = [krt.krt_grid_desc, krt.krt_line_desc, krt.krt_run_opts, krt.krt_tallies, krt.krt_levels_desc,
-               krt.krt_image_desc]
+               krt.krt_image_desc, krt.krt_escape_cond]
     lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "krt.h"', "int main(void) {"]
     for S in structs:
         name = S.__name__

@@ -1,7 +1,9 @@
-"""Learned escape on the GPU: the BF16-MFMA forward and gradient against the
-FP64 reference network, single-cell escape records against the oracle's plain
-walk, training, and the end-to-end judgement of the learned escape by the
-plain random walk on a turbulent cloud."""
+"""Learned whole-cell escape on the GPU: the BF16-MFMA forward and gradient
+against the FP64 reference network, whole-cell walk records against the
+oracle's plain walk, training, calibration, the network's samples against
+held-out plain walks, and the end-to-end judgement of the learned escape by
+the plain random walk (chained calls through a block of thick cells, the
+turbulent cloud)."""
 from __future__ import annotations
 
 import numpy as np
@@ -15,10 +17,8 @@ from stats_util import l1_shape
 
 pytestmark = pytest.mark.gpu
 NP, NO = mlp.NPARAMS, mlp.NOUT
-
-
-NCAL = 256  # calibration terms of ln E[N_s] stored after the normalisation
-NTAIL = 4   # then the trained log10 a range and padding
+NCAL = 256  # calibration terms of ln E[N_s] stored after mean and scale
+NTAIL = 8   # then the training ranges and padding
 
 
 def _put(ctx, p, norm):
@@ -36,38 +36,58 @@ def _rand_params(seed):
     return mlp.pack(d)
 
 
-# target normalisation (mean[10], scale[10]) for the synthetic checks
-NORM = np.array([2.5, 0, 0, 0.7, 6, 0.1, 0.0, 2.4, 1.0, 0.0,
-                 1.5, 0.5, 0.5, 0.2, 1.5, 1.0, 1.0, 1.4, 0.6, 1.0])
+# target normalisation (mean[16], scale[16]) for the synthetic checks; the face
+# logits, side logit and spare keep 0 / 1
+NORM = np.concatenate([[0, 0, 0, 0, 0, 0, 0, 2.4, 2.2, 5.0, 0.1, 0.0, 0.0, 0.6, 0.9, 0],
+                       [1, 1, 1, 1, 1, 1, 1, 1.4, 1.3, 2.0, 1.0, 0.8, 0.8, 0.25, 0.5, 1]])
 
 
-def _raw_rows(rng, n, cond):
-    """Raw forward rows (log10 tau_R, log10 a, x_in, u_a, u_b, u_c, r, flag)."""
-    return np.stack([rng.uniform(2, 5, n), rng.uniform(-4, -2, n), rng.uniform(-8, 8, n), rng.uniform(0, 1, n),
-                     rng.uniform(0, 1, n), rng.uniform(0, 1, n), rng.uniform(0, np.sqrt(2), n),
-                     cond.astype(np.float64)], 1)
+def _records(rng, n):
+    """Synthetic records in the reduced frame (columns R_*)."""
+    rec = np.zeros((n, 20))
+    rec[:, mlp.R_LT] = rng.uniform(1.5, 5, n)
+    rec[:, mlp.R_LA] = rng.uniform(-4, -2, n)
+    rec[:, mlp.R_X] = rng.uniform(0, 2, n)
+    q = np.sort(rng.uniform(0, 1, (n, 3)), axis=1)
+    rec[:, mlp.R_Q0:mlp.R_Q2 + 1] = q
+    rec[:, mlp.R_LD] = rec[:, mlp.R_LT] + np.log10(1 - q[:, 2])
+    v = rng.normal(size=(n, 3))
+    rec[:, mlp.R_N0:mlp.R_N2 + 1] = v / np.linalg.norm(v, axis=1)[:, None]
+    rec[:, mlp.R_FACE] = rng.integers(0, 6, n)
+    rec[:, mlp.R_YS:mlp.R_YT + 1] = rng.normal(0, 0.8, (n, 2))
+    rec[:, mlp.R_MU] = rng.uniform(0, 1, n)
+    rec[:, mlp.R_ALPHA] = rng.uniform(0, np.pi, n)
+    rec[:, mlp.R_XOUT] = rng.choice([-1.0, 1.0], n) * np.abs(2.4 + 1.4 * rng.normal(0, 1, n))
+    rec[:, mlp.R_LOGN] = 5.0 + 2.0 * rng.normal(0, 1, n)
+    rec[:, mlp.R_LOGX2] = 0.1 + rng.normal(0, 1, n)
+    rec[:, mlp.R_VALID] = 1.0
+    return rec
+
+
+def _raw_rows(rec, u, cond):
+    """krt_escape_forward rows: condition, four levels, flag, x_out, face."""
+    return np.concatenate([rec[:, :10], u, cond[:, None].astype(np.float64), rec[:, [mlp.R_XOUT]],
+                           rec[:, [mlp.R_FACE]]], axis=1)
 
 
 def test_mfma_forward_vs_fp64(gpu_ctx):
-    """BF16-MFMA forward of marginal and conditional rows vs the FP64 network
-    (with and without bfloat16 rounding of weights and activations)."""
+    """BF16-MFMA forward (16x16x32 tiles with the permuted reduction index) of
+    marginal and conditional rows vs the FP64 network, with and without
+    bfloat16 rounding of weights and activations; errors relative to each
+    output's spread.  A wrong input lane, tile or permutation is O(1)."""
     import torch
     p = _rand_params(3)
     _put(gpu_ctx, p, NORM)
     rng = np.random.default_rng(4)
-    n = 3000
+    n = 3001  # a ragged last block
     cond = rng.uniform(0, 1, n) < 0.4
-    raw = _raw_rows(rng, n, cond)
+    rec = _records(rng, n)
+    u = rng.uniform(0, 1, (n, 4))
+    raw = _raw_rows(rec, u, cond)
     out = torch.zeros((n, NO), dtype=torch.float32, device="cuda")
     gpu_ctx.krt_escape_forward(torch.from_numpy(raw.astype(np.float32)).cuda(), out)
     g = out.cpu().numpy().astype(np.float64)
-    X = mlp.inputs(*(raw[:, k] for k in range(7)), cond)
-    # errors relative to each output's spread over the samples.  bf16 storage
-    # of weights and activations alone moves these outputs by 2.4-4.1% of their
-    # spread against FP64 (the emulation vs the unrounded network), so the
-    # unrounded comparison allows twice that; against the emulation only the
-    # accumulation order and rounding flips of activations remain (below 3%).
-    # A wrong input lane or layer is O(1)
+    X = mlp.inputs(rec.astype(np.float32).astype(np.float64), u.astype(np.float32), cond)
     for bf, tol in ((True, 3e-2), (False, 8e-2)):
         o, _, _ = mlp.forward(p, X, bf=bf)
         ref = o * NORM[NO:] + NORM[:NO]
@@ -76,98 +96,137 @@ def test_mfma_forward_vs_fp64(gpu_ctx):
 
 
 def test_mfma_gradient_vs_fp64(gpu_ctx):
-    """d(mean loss)/d(params) from the BF16-MFMA backward vs the FP64 reference
-    on a batch of marginal and conditional rows, each output at its own
-    quantile level: cosine >= 0.999 and relative L2 <= 2e-2 per tensor."""
+    """d(mean loss)/d(params) from the forward/backward kernel and the split
+    weight-gradient products vs the FP64 reference on a batch of marginal and
+    conditional rows (a batch of 1000: a ragged last block of 32 samples),
+    each output at its own quantile level: cosine >= 0.999 and relative L2
+    <= 2e-2 per tensor against the bfloat16 emulation, loss within 1%; the
+    unused output's column gets no gradient."""
     import torch
     p = _rand_params(5)
-    norm = NORM
-    _put(gpu_ctx, p, norm)
+    _put(gpu_ctx, p, NORM)
     rng = np.random.default_rng(6)
-    nrec, B = 5000, 1024
-    rec = np.zeros((nrec, 11))
-    rec[:, 0] = rng.uniform(2, 5, nrec)
-    rec[:, 1] = rng.uniform(-4, -2, nrec)
-    rec[:, 2] = rng.uniform(-8, 8, nrec)
-    rec[:, 3] = rng.choice([-1.0, 1.0], nrec) * np.abs(2.5 + 1.5 * rng.normal(0, 1, nrec))
-    rec[:, 4:6] = rng.uniform(-1, 1, (nrec, 2))
-    rec[:, 6:9] = norm[3:6] + norm[NO + 3:NO + 6] * rng.normal(0, 1, (nrec, 3))
-    rec[:, 9] = 1.0
-    rec[:, 10] = rng.uniform(0, np.pi, nrec)
+    nrec, B = 5000, 1000
+    rec = _records(rng, nrec)
     idx = rng.integers(0, nrec, B).astype(np.int32)
-    ua, ub, uc = rng.uniform(0, 1, (3, B))
-    cond = rng.uniform(0, 1, B) < 0.25
-    u = np.stack([ua, ub, uc, cond.astype(np.float64)], 1)
+    u = rng.uniform(0, 1, (B, 4))
+    cond = rng.uniform(0, 1, B) < 0.3
+    uq = np.concatenate([u, cond[:, None].astype(np.float64)], axis=1)
     grad = torch.zeros(NP, dtype=torch.float32, device="cuda")
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
-    gpu_ctx.krt_escape_grad(torch.from_numpy(rec.astype(np.float32)).cuda(),
-                            torch.from_numpy(idx).cuda(), torch.from_numpy(u.astype(np.float32)).cuda(), grad, loss)
+    gpu_ctx.krt_escape_grad(torch.from_numpy(rec.astype(np.float32)).cuda(), torch.from_numpy(idx).cuda(),
+                            torch.from_numpy(uq.astype(np.float32)).cuda(), grad, loss)
     g = grad.cpu().numpy().astype(np.float64)
     R = rec[idx].astype(np.float32).astype(np.float64)
-    X = mlp.inputs(R[:, 0], R[:, 1], R[:, 2], ua, ub, np.where(cond, R[:, 3], uc), np.hypot(R[:, 4], R[:, 5]), cond)
-    Y = mlp.targets_normalised(R, norm, cond)
-    U = mlp.levels(ua, ub, uc, cond)
+    uf = u.astype(np.float32).astype(np.float64)
+    X = mlp.inputs(R, uf, cond)
+    Y = mlp.targets_normalised(R, NORM, cond)
+    U = mlp.levels(uf, cond)
     for bf in (True, False):
-        l_ref, g_ref = mlp.loss_and_grad(p, X, Y, U, bf=bf, s4=norm[NO + mlp.O_LOGN])
+        l_ref, g_ref = mlp.loss_and_grad(p, X, Y, U, bf=bf, s9=NORM[NO + mlp.O_LOGN])
         o = 0
         for name, shp in mlp.SHAPES:
             k = int(np.prod(shp))
             a, b = g[o:o + k], g_ref[o:o + k]
             o += k
-            if name == "W4" or name == "b4":  # the unused output's column gets no gradient on either side
-                a = a.reshape(-1, NO)[:, :mlp.O_SPARE]
-                b = b.reshape(-1, NO)[:, :mlp.O_SPARE]
-                assert np.all(g[o - k:o].reshape(-1, NO)[:, mlp.O_SPARE] == 0.0)
-                a, b = a.reshape(-1), b.reshape(-1)
+            if name in ("W4", "b4"):
+                assert np.all(a.reshape(-1, NO)[:, mlp.O_SPARE] == 0.0)
+                a = a.reshape(-1, NO)[:, :mlp.O_SPARE].reshape(-1)
+                b = b.reshape(-1, NO)[:, :mlp.O_SPARE].reshape(-1)
             cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-30)
             rel = np.linalg.norm(a - b) / (np.linalg.norm(b) + 1e-30)
             assert cos >= (0.999 if bf else 0.995) and rel <= (2e-2 if bf else 6e-2), (bf, name, cos, rel)
         assert abs(loss.item() / l_ref - 1) < 1e-2
 
 
-@pytest.mark.parametrize("tau,xin", [(1e3, 0.5), (1e4, 2.5)])
-def test_escape_records_vs_oracle(gpu_ctx, tau, xin):
-    """Single-cell escapes from the GPU walk vs the oracle's FP64 walk at the same
-    condition: exit frequency, exit-point and exit-direction distributions (KS,
-    including the alignment angle of the direction with the exit point) and
-    the mean log number of scatterings."""
+def test_gradient_is_deterministic(gpu_ctx):
+    """The weight gradients are summed over fixed sample splits in a fixed
+    order (no floating-point atomics), so two evaluations are bit-identical."""
+    import torch
+    p = _rand_params(8)
+    _put(gpu_ctx, p, NORM)
+    rng = np.random.default_rng(9)
+    rec = torch.from_numpy(_records(rng, 4000).astype(np.float32)).cuda()
+    idx = torch.from_numpy(rng.integers(0, 4000, 4096).astype(np.int32)).cuda()
+    uq = np.concatenate([rng.uniform(0, 1, (4096, 4)), (rng.uniform(0, 1, (4096, 1)) < 0.3)], axis=1)
+    uq = torch.from_numpy(uq.astype(np.float32)).cuda()
+    g1 = torch.zeros(NP, dtype=torch.float32, device="cuda")
+    g2 = torch.zeros(NP, dtype=torch.float32, device="cuda")
+    gpu_ctx.krt_escape_grad(rec, idx, uq, g1)
+    gpu_ctx.krt_escape_grad(rec, idx, uq, g2)
+    assert torch.equal(g1, g2)
+
+
+def _gpu_records(ctx, n, lt, x_in, q, n_in=None, seed=7, offset=0):
     import torch
     from paper_2608_09340_amd import krt
-    a = 1e-3
-    T = krt.Transport(W.slab(10.0, a, 4), ctx=gpu_ctx)
-    n = 40000
     out = torch.zeros((n, krt.ESC_NREC), dtype=torch.float32, device="cuda")
-    lt = np.log10(tau)
-    gpu_ctx.krt_escape_record(0, n, 7, 0, lt, lt, out, x_fixed=xin)
-    g = out.cpu().numpy().astype(np.float64)
-    no = 4000 if tau < 5e3 else 800
-    o = oracle.escape_record(no, tau, a, xin, seed=8, offset=1 << 30)
-    assert g[:, 9].min() == 1 and o[:, 9].min() == 1
-    for col in (3, 4, 6, 10):
-        ks = stats.ks_2samp(g[:, col], o[:, col])
-        assert ks.pvalue > 1e-3, (tau, xin, col, ks)
-    mg, mo = g[:, 7].mean(), o[:, 7].mean()
-    se = np.sqrt(g[:, 7].var() / n + o[:, 7].var() / no)
-    assert abs(mg - mo) < 4.5 * se, (mg, mo, se)
+    ctx.krt_escape_record(0, n, seed, offset, lt, lt, out, x_in=x_in, q=q, n_in=n_in)
+    return out.cpu().numpy().astype(np.float64)
+
+
+CONDITIONS = [  # (tau_c, |x_in|, q in the reduced frame, incoming direction or None = isotropic)
+    (300.0, 0.5, (0.2, 0.4, 0.9), None),
+    (3000.0, 1.5, (0.1, 0.5, 0.995), (0.0, 0.6, 0.8)),
+    (50.0, 0.0, (0.0, 0.0, 0.0), None),
+]
+
+
+@pytest.mark.parametrize("tau,xin,q,nin", CONDITIONS)
+def test_cell_records_vs_oracle(gpu_ctx, tau, xin, q, nin):
+    """Whole-cell walks from the GPU (the transport's FP32 arithmetic, table
+    sampler) vs the oracle's FP64 walk from the same start: exit face
+    frequencies (every |z| < 4.5), and on the two most frequent faces the
+    exit offsets, cosine, alpha and exit frequency (KS p > 1e-3); mean ln N_s
+    within 4.5 standard errors."""
+    from paper_2608_09340_amd import krt
+    a = 1e-3
+    krt.Transport(W.slab(10.0, a, 4), ctx=gpu_ctx)
+    n = 40000
+    g = _gpu_records(gpu_ctx, n, np.log10(tau), xin, q, nin)
+    no = 8000 if tau < 1e3 else 2000
+    o = oracle.cell_escape_record(no, tau, a, xin, q, n_in=nin, seed=8, offset=1 << 30)
+    assert g[:, mlp.R_VALID].min() == 1 and o[:, mlp.R_VALID].min() == 1
+    fg = np.bincount(g[:, mlp.R_FACE].astype(int), minlength=6) / n
+    fo = np.bincount(o[:, mlp.R_FACE].astype(int), minlength=6) / no
+    se = np.sqrt(fo * (1 - fo) / no + fg * (1 - fg) / n) + 1e-12
+    assert np.max(np.abs(fg - fo) / se) < 4.5, (fg, fo)
+    for face in np.argsort(fo)[-2:]:
+        mg, mo = g[:, mlp.R_FACE] == face, o[:, mlp.R_FACE] == face
+        if mo.sum() < 200:
+            continue
+        for col in (mlp.R_YS, mlp.R_YT, mlp.R_MU, mlp.R_ALPHA, mlp.R_XOUT):
+            ks = stats.ks_2samp(g[mg, col], o[mo, col])
+            assert ks.pvalue > 1e-3, (tau, face, col, ks)
+    lg, lo = g[:, mlp.R_LOGN], o[:, mlp.R_LOGN]
+    se = np.sqrt(lg.var() / n + lo.var() / no)
+    assert abs(lg.mean() - lo.mean()) < 4.5 * se, (lg.mean(), lo.mean(), se)
 
 
 @pytest.fixture(scope="module")
 def trained(gpu_ctx):
-    """Train the escape network on 8e6 GPU-recorded single-cell escapes
-    (a = 1e-3, log10 tau_R uniform in [1, 5]) with the staged default recipe."""
+    """Train the escape network on 8e6 GPU-recorded whole-cell walks (a = 1e-3,
+    the default recipe) and time the recording and the training."""
+    import time
+    import torch
     from paper_2608_09340_amd import krt
     from paper_2608_09340_amd.escape import train_escape
     T = krt.Transport(W.slab(10.0, 1e-3, 4), ctx=gpu_ctx)
-    r = train_escape(gpu_ctx, 0, seed=1, log10_tau=(1.0, 5.0))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r = train_escape(gpu_ctx, 0, seed=1)
+    torch.cuda.synchronize()
+    r["train_s"] = time.perf_counter() - t
     r["T"] = T
+    print(f"escape training: {r['train_s']:.1f} s")
     return r
 
 
 def test_training_reduces_loss(trained):
     """The loss falls well below its value at initialisation and keeps falling
-    after the first hundred steps (later stages lower it further).  The
-    quantile outputs' pinball losses do not fall to zero: even the true
-    quantiles leave the spread of the escapes about them."""
+    after the first hundred steps.  The quantile outputs' pinball losses and
+    the face cross-entropy do not fall to zero: even the true conditional
+    laws leave the spread of the walks about them."""
     h = trained["hist"]
     assert np.all(np.isfinite(h))
     early, mid, late = h[:5].mean(), h[50:100].mean(), h[-200:].mean()
@@ -176,96 +235,104 @@ def test_training_reduces_loss(trained):
 
 def test_calibration_unbiased_per_bin(gpu_ctx, trained):
     """After krt_escape_calibrate, the forward pass's calibrated E[N_s] summed
-    over the records (|x_in| <= 2) of each (log10 tau_R, |x_in|) bin equals the records' sum of N_s
-    (the calibration's defining property; FP32 outputs, so within 1e-3)."""
+    over the records (|x_in| <= 2) of each (log10 tau_c, log10 depth, |x_in|)
+    bin equals the records' sum of N_s (the calibration's defining property;
+    FP32 outputs, so within 2%)."""
     import torch
     rec = trained["rec"][:2_000_000]
     r = rec.cpu().numpy().astype(np.float64)
     gpu_ctx.krt_escape_calibrate(rec, rec.shape[0])
     n = rec.shape[0]
-    inp = torch.zeros((n, 8), dtype=torch.float32, device=rec.device)  # marginal rows
-    inp[:, :3] = rec[:, :3]
-    inp[:, 3:6] = torch.rand((n, 3), device=rec.device)
-    out = torch.zeros((n, NO), dtype=torch.float32, device=rec.device)
-    gpu_ctx.krt_escape_forward(inp.contiguous(), out)
+    rng = np.random.default_rng(3)
+    raw = _raw_rows(r, rng.uniform(0, 1, (n, 4)), np.zeros(n, dtype=bool))
+    out = torch.zeros((n, NO), dtype=torch.float32, device="cuda")
+    gpu_ctx.krt_escape_forward(torch.from_numpy(raw.astype(np.float32)).cuda(), out)
     pred = np.exp(out[:, mlp.O_LOGN].cpu().numpy().astype(np.float64))
-    ax = np.abs(r[:, 2])
-    bx = np.minimum((ax * 4.0).astype(int), 7)  # 0.25-wide |x_in| bins over [0, 2]
-    b = np.clip(((r[:, 0] - 1.0) * 8.0).astype(int), 0, 31) * 8 + bx
-    b[ax > 2.0] = -1  # the network is asked only for |x_in| <= 2
+    bt = np.clip(((r[:, mlp.R_LT] - 1.0) * 2.0).astype(int), 0, 7)
+    bd = np.clip((r[:, mlp.R_LD] * 2.0).astype(int), 0, 7)
+    bx = np.clip((r[:, mlp.R_X] * 2.0).astype(int), 0, 3)
+    b = (bt * 8 + bd) * 4 + bx
+    b[r[:, mlp.R_X] > 2.0] = -1  # the network is asked only for |x_in| <= 2
     for k in range(256):
         m = b == k
-        if m.sum() < 1000:
+        if m.sum() < 2000:
             continue
-        ratio = pred[m].sum() / np.exp(r[m, 7]).sum()
+        ratio = pred[m].sum() / np.exp(r[m, mlp.R_LOGN]).sum()
         assert abs(ratio - 1.0) < 0.02, (k, ratio)
     # the full training set again, so later tests see the fixture's calibration
     gpu_ctx.krt_escape_calibrate(trained["rec"], trained["rec"].shape[0])
 
 
-@pytest.mark.parametrize("tau,xin", [(3e1, 0.0), (3e2, 0.0), (3e3, 1.0), (3e4, 2.0)])
-def test_learned_samples_vs_plain(gpu_ctx, trained, tau, xin):
-    """At a fixed condition, the network's samples drawn as the transport draws
-    them (a marginal evaluation at three independent levels, then a
-    conditional one at the sampled exit point) vs held-out plain single-cell
-    escapes: KS distance of exit frequency, exit point, exit cosine and the
-    direction's alignment angle below 0.04; the mean alignment angle per band of
-    exit-point radius within 0.08 of the plain one (the correlation of
-    direction and exit point) and the rank correlation of exit cosine and
-    |x_out| within 0.05 of the plain one; exit-frequency histogram L1 below 0.13
-    (0.25-wide bins); ln E[N_s] within 0.08."""
+def _learned_samples(ctx, n, lt, xin, q, nin, rng):
+    """The network's samples at a fixed condition, drawn as the transport draws
+    them: marginal evaluation (face from the softmax, side, one-sided
+    magnitude at u_a), then the conditional evaluation at the sampled face and
+    exit frequency.  Returns face, x_out, ys, yt, mu, alpha and ln E[N_s]."""
     import torch
-    from paper_2608_09340_amd import krt
-    n = 20000
-    out = torch.zeros((n, krt.ESC_NREC), dtype=torch.float32, device="cuda")
-    lt = np.log10(tau)
-    gpu_ctx.krt_escape_record(0, n, 99, 1 << 32, lt, lt, out, x_fixed=xin)
-    plain = out.cpu().numpy().astype(np.float64)
-    rng = np.random.default_rng(13)
-    ua, ub, uc = rng.uniform(0, 1, (3, n))
-    raw = np.stack([np.full(n, lt), np.full(n, -3.0), np.full(n, xin), ua, ub, uc, np.zeros(n), np.zeros(n)], 1)
-    pred = torch.zeros((n, NO), dtype=torch.float32, device="cuda")
-    gpu_ctx.krt_escape_forward(torch.from_numpy(raw.astype(np.float32)).cuda(), pred)
-    m = pred.cpu().numpy().astype(np.float64)
-    s_l, t_l = np.clip(m[:, mlp.O_S], -1, 1), np.clip(m[:, mlp.O_T], -1, 1)
-    r_l = np.hypot(s_l, t_l)
-    # exit frequency from the mixture head: side, then that side's quantile
-    pos = rng.uniform(0, 1, n) < 1.0 / (1.0 + np.exp(-m[:, mlp.O_LOGIT]))
+    cond = np.zeros((n, 20))
+    cond[:, mlp.R_LT] = lt
+    cond[:, mlp.R_LA] = -3.0
+    cond[:, mlp.R_X] = xin
+    cond[:, mlp.R_Q0:mlp.R_Q2 + 1] = q
+    cond[:, mlp.R_LD] = lt + np.log10(1 - q[2])
+    if nin is None:
+        v = rng.normal(size=(n, 3))
+        cond[:, mlp.R_N0:mlp.R_N2 + 1] = v / np.linalg.norm(v, axis=1)[:, None]
+    else:
+        cond[:, mlp.R_N0:mlp.R_N2 + 1] = nin
+    u = rng.uniform(0, 1, (n, 4))
+    out = torch.zeros((n, NO), dtype=torch.float32, device="cuda")
+    ctx.krt_escape_forward(torch.from_numpy(_raw_rows(cond, u, np.zeros(n, bool)).astype(np.float32)).cuda(), out)
+    m = out.cpu().numpy().astype(np.float64)
+    lg = m[:, :6] - m[:, :6].max(axis=1, keepdims=True)
+    pf = np.exp(lg)
+    pf /= pf.sum(axis=1, keepdims=True)
+    face = (rng.uniform(0, 1, n)[:, None] > np.cumsum(pf, axis=1)).sum(axis=1).clip(0, 5)
+    pos = rng.uniform(0, 1, n) < 1.0 / (1.0 + np.exp(-m[:, mlp.O_SIDE]))
     xo = np.where(pos, np.maximum(m[:, mlp.O_XPOS], 0.0), -np.maximum(m[:, mlp.O_XNEG], 0.0))
-    raw2 = np.stack([np.full(n, lt), np.full(n, -3.0), np.full(n, xin), rng.uniform(0, 1, n), rng.uniform(0, 1, n),
-                     xo, r_l, np.ones(n)], 1)
-    gpu_ctx.krt_escape_forward(torch.from_numpy(raw2.astype(np.float32)).cuda(), pred)
-    m2 = pred.cpu().numpy().astype(np.float64)
-    mu_l = np.clip(m2[:, mlp.O_MU], 1e-3, 1.0)
-    al_l = np.clip(m2[:, mlp.O_ALPHA], 0.0, np.pi)
-    ks = {"x_out": stats.ks_2samp(xo, plain[:, 3]).statistic, "s": stats.ks_2samp(s_l, plain[:, 4]).statistic,
-          "t": stats.ks_2samp(t_l, plain[:, 5]).statistic, "mu": stats.ks_2samp(mu_l, plain[:, 6]).statistic,
-          "alpha": stats.ks_2samp(al_l, plain[:, 10]).statistic}
-    # histogram L1 of the exit frequency (bins of 0.25), against the plain-vs-plain floor
-    edges = np.linspace(-12, 12, 97)
-    hp = np.histogram(plain[:, 3], edges)[0]
-    hm = np.histogram(xo, edges)[0]
-    l1 = np.abs(hp / n - hm / n).sum()
-    # exit cosine against |x_out| (wing photons leave closer to the normal)
-    rho_l = stats.spearmanr(np.abs(xo), mu_l).statistic
-    rho_p = stats.spearmanr(np.abs(plain[:, 3]), plain[:, 6]).statistic
-    r_p = np.hypot(plain[:, 4], plain[:, 5])
-    bands = [(0.0, 0.4), (0.4, 0.8), (0.8, 1.5)]
-    al_band = [(al_l[(r_l >= lo) & (r_l < hi)].mean(), plain[(r_p >= lo) & (r_p < hi), 10].mean()) for lo, hi in bands]
-    print(f"tau={tau} x_in={xin} KS " + " ".join(f"{k} {v:.4f}" for k, v in ks.items()) +
-          f" x_out L1 {l1:.4f} P(x>=0) learned {pos.mean():.3f} plain {(plain[:, 3] >= 0).mean():.3f}"
-          f" mean alpha by r band (learned, plain) " + " ".join(f"({a:.3f}, {b:.3f})" for a, b in al_band) +
-          f" rank corr(|x_out|, mu) learned {rho_l:.3f} plain {rho_p:.3f}")
-    assert max(ks.values()) < 0.04, (tau, xin, ks)
-    assert abs(rho_l - rho_p) < 0.05, (rho_l, rho_p)
-    for a_l, a_p in al_band:
-        assert abs(a_l - a_p) < 0.08, al_band
-    # density level: two plain samples of this size differ by L1 ~ 0.04 in these bins
-    assert l1 < 0.13, l1
-    # output 4 is ln E[N_s]: against the log of the plain mean count (8%)
-    ln_mean = np.log(np.mean(np.exp(plain[:, 7])))
-    print(f"   ln E[N_s]: learned {m[:, 4].mean():.4f} (spread {m[:, 4].std():.1e}) plain {ln_mean:.4f}")
-    assert abs(m[:, 4].mean() - ln_mean) < 0.08
+    cond[:, mlp.R_FACE] = face
+    cond[:, mlp.R_XOUT] = xo
+    u2 = rng.uniform(0, 1, (n, 4))
+    ctx.krt_escape_forward(torch.from_numpy(_raw_rows(cond, u2, np.ones(n, bool)).astype(np.float32)).cuda(), out)
+    m2 = out.cpu().numpy().astype(np.float64)
+    return (face, xo, m2[:, mlp.O_YS], m2[:, mlp.O_YT], np.clip(m2[:, mlp.O_MU], 1e-3, 1.0),
+            np.clip(m2[:, mlp.O_ALPHA], 0.0, np.pi), m[:, mlp.O_LOGN])
+
+
+SAMPLE_CONDITIONS = [(50.0, 0.0, (0.2, 0.3, 0.4), None), (300.0, 0.5, (0.2, 0.4, 0.9), None),
+                     (3000.0, 1.0, (0.1, 0.5, 0.998), None), (3e4, 1.5, (0.3, 0.6, 0.8), None)]
+
+
+@pytest.mark.parametrize("tau,xin,q,nin", SAMPLE_CONDITIONS)
+def test_learned_samples_vs_plain(gpu_ctx, trained, tau, xin, q, nin):
+    """At a fixed condition, the network's samples vs held-out plain walks
+    from the same start: exit-face total variation below 0.03, KS distance of
+    the exit frequency below 0.04 and of the offsets, cosine and alpha on the
+    most frequent face below 0.05; ln E[N_s] within 0.05 of the log of the
+    plain mean count (the plain mean of 20000 walks is itself good to about
+    1-2%)."""
+    n = 20000
+    lt = np.log10(tau)
+    plain = _gpu_records(gpu_ctx, n, lt, xin, q, nin, seed=99, offset=1 << 32)
+    face, xo, ys, yt, mu, al, lnm = _learned_samples(gpu_ctx, n, lt, xin, np.asarray(q), nin,
+                                                     np.random.default_rng(13))
+    fp = np.bincount(plain[:, mlp.R_FACE].astype(int), minlength=6) / n
+    fl = np.bincount(face, minlength=6) / n
+    tv = 0.5 * np.abs(fp - fl).sum()
+    ks = {"x_out": stats.ks_2samp(xo, plain[:, mlp.R_XOUT]).statistic}
+    top = int(np.argmax(fp))
+    mp, ml_ = plain[:, mlp.R_FACE] == top, face == top
+    for name, vl, col in (("ys", ys, mlp.R_YS), ("yt", yt, mlp.R_YT), ("mu", mu, mlp.R_MU),
+                          ("alpha", al, mlp.R_ALPHA)):
+        ks[name] = stats.ks_2samp(vl[ml_], plain[mp, col]).statistic
+    ln_mean = np.log(np.mean(np.exp(plain[:, mlp.R_LOGN])))
+    print(f"tau_c={tau} x={xin} q={q}: face TV {tv:.4f} (plain {np.round(fp, 3)}) KS " +
+          " ".join(f"{k} {v:.4f}" for k, v in ks.items()) +
+          f" ln E[N_s] learned {lnm.mean():.4f} plain {ln_mean:.4f}")
+    assert tv < 0.03, (fp, fl)
+    assert ks["x_out"] < 0.04, ks
+    assert max(ks[k] for k in ("ys", "yt", "mu", "alpha")) < 0.05, ks
+    assert abs(lnm.mean() - ln_mean) < 0.05
 
 
 def _agg_emis(em, n, blocks=8):
@@ -276,21 +343,86 @@ def _agg_emis(em, n, blocks=8):
     return e.reshape(blocks, f, blocks, f, blocks, f, nch).sum(axis=(1, 3, 5)).reshape(-1)
 
 
+def test_single_cell_one_call_per_packet(gpu_ctx, trained):
+    """One cubic cell 1000 line-centre mean free paths across (a = 1e-3) with a
+    point source off centre: every packet's first scattering is deep enough for
+    the network, and leaving the cell is leaving the grid, so each packet takes
+    one call and its escape is the network's sample as the transport applies it
+    (the inverse of the reduction to the cell's frame).  Against the plain
+    walk: escaped-spectrum L1 below 2% (floor about 0.8%), total emissivity
+    (the calibrated E[N_s] deposits) within 1.5%, escape-direction
+    distribution along each axis (KS p > 1e-3 on the x component at 2e5)."""
+    from paper_2608_09340_amd import krt
+    p = W._problem((1, 1, 1), (-1.0,) * 3, (1.0,) * 3, (0, 0, 0), np.array([500.0]), 1e-3,
+                   source={"kind": W.SRC_POINT, "pos": (0.5, 0.3, -0.1), "profile": W.PROF_DELTA, "x0": 0.0},
+                   tally={"spec_nbins": 96, "spec_lo": -12.0, "spec_hi": 12.0, "emis_nch": 16, "ch_lo": -6.0,
+                          "ch_hi": 6.0, "n_cam": (1.0, 0.0, 0.0)})
+    T = krt.Transport(p, ctx=gpu_ctx)
+    N = 200_000
+    pa = T.run(N, seed=0, packet_log=True)
+    pb = T.run(N, seed=0, packet_offset=1 << 32)
+    ml = T.run(N, seed=0, packet_offset=1 << 33, escape_mode=1, esc_min_lanes=1, esc_tail_lanes=1, packet_log=True)
+    assert pa["rc"] == 0 and ml["rc"] == 0
+    c = ml["counters"]
+    ea, eb, em = (r["emis_raw"].astype(np.float64).sum() for r in (pa, pb, ml))
+    l1s, fl1s = l1_shape(pa["spec_raw"], ml["spec_raw"]), l1_shape(pa["spec_raw"], pb["spec_raw"])
+    dirs = [stats.ks_2samp(pa["packet_log"][:, k], ml["packet_log"][:, k]).pvalue for k in (3, 4, 5)]
+    print(f"single cell: calls/pkt {c['mlp_calls'] / N:.3f} total {em / ea:.4f} (plain/plain {eb / ea:.4f}) "
+          f"spec L1 {l1s:.4f} (floor {fl1s:.4f}) direction KS p {np.round(dirs, 4)}")
+    assert c["mlp_calls"] > 0.9 * N
+    assert abs(em / ea - 1.0) < 0.015
+    assert l1s < 0.02
+    assert min(dirs) > 1e-3
+
+
+def test_chained_calls_through_thick_cells(gpu_ctx, trained):
+    """A 6^3 block of uniform cells each 1000 line-centre mean free paths across
+    (a = 1e-3) with a point source off centre: a packet takes many network
+    calls, leaving one cell into the next, with plain walks between them
+    (shallow points, wing photons).  Against the plain walk: total emissivity
+    within 1.5%, emissivity per cell ring (|cell - source| in cells) and
+    channel L1 below 2%, escaped spectrum L1 below 2%."""
+    from paper_2608_09340_amd import krt
+    n = 6
+    k0 = np.full(n ** 3, 1000.0 / (2.0 / n))
+    p = W._problem((n, n, n), (-1.0,) * 3, (1.0,) * 3, (0, 0, 0), k0, 1e-3,
+                   source={"kind": W.SRC_POINT, "pos": (0.11, -0.07, 0.23), "profile": W.PROF_DELTA, "x0": 0.0},
+                   tally={"spec_nbins": 128, "spec_lo": -24.0, "spec_hi": 24.0, "emis_nch": 16, "ch_lo": -6.0,
+                          "ch_hi": 6.0, "n_cam": (1.0, 0.0, 0.0)})
+    T = krt.Transport(p, ctx=gpu_ctx)
+    N = 200_000
+    pa = T.run(N, seed=0)
+    pb = T.run(N, seed=0, packet_offset=1 << 32)
+    ml = T.run(N, seed=0, packet_offset=1 << 33, escape_mode=1, esc_min_lanes=1, esc_tail_lanes=1)
+    assert pa["rc"] == 0 and ml["rc"] == 0
+    c = ml["counters"]
+    assert c["mlp_calls"] > 5 * N
+    ea, eb, em = (r["emis_raw"].astype(np.float64) for r in (pa, pb, ml))
+    ring = np.abs(np.indices((n, n, n)) - 2.5).max(axis=0).reshape(-1).astype(int)
+    agg = [np.stack([e[ring == k].sum(axis=0) for k in range(ring.max() + 1)]).reshape(-1) for e in (ea, eb, em)]
+    tot = em.sum() / ea.sum()
+    l1e, fl1e = l1_shape(agg[0], agg[2]), l1_shape(agg[0], agg[1])
+    l1s, fl1s = l1_shape(pa["spec_raw"], ml["spec_raw"]), l1_shape(pa["spec_raw"], pb["spec_raw"])
+    print(f"chained cells: calls/pkt {c['mlp_calls'] / N:.2f} plain scat/pkt {c['scatterings'] / N:.1f} "
+          f"total {tot:.4f} (plain/plain {eb.sum() / ea.sum():.4f}) emis L1 {l1e:.4f} (floor {fl1e:.4f}) "
+          f"spec L1 {l1s:.4f} (floor {fl1s:.4f})")
+    assert abs(tot - 1.0) < 0.015
+    assert l1e < 0.02 and l1s < 0.02
+
+
 def test_cloud_learned_escape_vs_plain(gpu_ctx, trained):
     """Turbulent cloud (64^3, 30% of cells with line-centre depth >= 1e2): the
-    plain random walk judges the learned escape.  Spectrum and aggregated
-    emissivity L1 <= 2% beyond the plain-vs-plain noise floor, total emissivity
-    within 2%, and the learned run needs fewer transport iterations
-    (scatterings + network calls).  1e6 packets: the per-packet scattering
-    count is heavy-tailed (packets trapped in the thickest cells), so with 1e5
-    two plain runs already differ by about 2% in total."""
+    plain random walk judges the learned escape at 1e6 packets.  Spectrum and
+    aggregated emissivity (8^3 blocks x 16 channels) L1 <= 2% against the
+    plain run, total emissivity within 1.5%, and the learned run needs far
+    fewer transport iterations (plain scatterings + network calls)."""
     from paper_2608_09340_amd import krt
     p = W.cloud_c4(n=64, spec=(256, -40.0, 40.0), emis=(16, -16.0, 16.0))
     T = krt.Transport(p, ctx=gpu_ctx)
     N = 1_000_000
     pa = T.run(N, seed=0)
     pb = T.run(N, seed=0, packet_offset=1 << 32)
-    ml = T.run(N, seed=0, escape_mode=1)
+    ml = T.run(N, seed=0, packet_offset=1 << 33, escape_mode=1)
     assert pa["rc"] == 0 and ml["rc"] == 0, (pa["counters"], ml["counters"])
     c = ml["counters"]
     assert c["mlp_calls"] > 0 and c["emitted"] == N == c["escaped"]
@@ -299,44 +431,13 @@ def test_cloud_learned_escape_vs_plain(gpu_ctx, trained):
     ea, eb, em = (_agg_emis(r["emis_raw"].astype(np.float64), 64) for r in (pa, pb, ml))
     floor_e = l1_shape(ea, eb)
     l1_e = l1_shape(ea, em)
-    print(f"spectrum L1 {l1_s:.4f} (floor {floor_s:.4f}); emissivity L1 {l1_e:.4f} (floor {floor_e:.4f}); "
-          f"plain scat {pa['counters']['scatterings']} mlp scat {c['scatterings']} calls {c['mlp_calls']} "
-          f"skipped {c['skipped_scatterings']}")
     tot = em.sum() / ea.sum()
-    print(f"emissivity total learned / plain {tot:.4f} (plain / plain {eb.sum() / ea.sum():.4f})")
-    assert l1_s <= 0.02 + floor_s
-    assert l1_e <= 0.02 + floor_e
-    assert abs(tot - 1.0) < 0.02
-    assert c["scatterings"] + c["mlp_calls"] < pa["counters"]["scatterings"]
-
-
-@pytest.mark.parametrize("tau_min", [100.0, 740.0])
-def test_chained_escapes_single_cell_count(gpu_ctx, trained, tau_min):
-    """One thick cell (line-centre depth 3000 across, a = 1e-3) with the source
-    off centre, so a packet takes several network calls and plain walks between
-    them: the learned run's total emissivity (skipped scatterings included)
-    matches the plain walk's within 1.2%.  This needs the exit direction drawn
-    given the exit point: with an azimuth independent of it the total is about
-    2% high, since real photons leave near an edge heading away from the face
-    centre."""
-    from paper_2608_09340_amd import krt
-    p = W._problem((1, 1, 1), (-1.0,) * 3, (1.0,) * 3, (0, 0, 0), np.array([1500.0]), 1e-3,
-                   source={"kind": W.SRC_POINT, "pos": (0.5, 0.3, 0.1), "profile": W.PROF_DELTA, "x0": 0.0},
-                   tally={"spec_nbins": 128, "spec_lo": -16.0, "spec_hi": 16.0, "emis_nch": 32, "ch_lo": -8.0,
-                          "ch_hi": 8.0, "n_cam": (1.0, 0.0, 0.0)})
-    T = krt.Transport(p, ctx=gpu_ctx)
-    N = 100_000
-    pa = T.run(N, seed=0)
-    pb = T.run(N, seed=0, packet_offset=1 << 32)
-    ml = T.run(N, seed=0, escape_mode=1, esc_tau_min=tau_min, esc_min_lanes=1, esc_tail_lanes=1)
-    assert pa["rc"] == 0 and ml["rc"] == 0
-    ea, eb, em = (r["emis_raw"][0].astype(np.float64).sum() for r in (pa, pb, ml))
-    c = ml["counters"]
-    print(f"tau_min {tau_min}: calls/pkt {c['mlp_calls'] / N:.3f} learned/plain {em / ea:.4f} "
-          f"(plain/plain {eb / ea:.4f}) spectrum L1 {l1_shape(pa['spec_raw'], ml['spec_raw']):.4f} "
-          f"(floor {l1_shape(pa['spec_raw'], pb['spec_raw']):.4f})")
-    assert c["mlp_calls"] > N
-    assert abs(em / ea - 1.0) < 0.012
+    print(f"spectrum L1 {l1_s:.4f} (floor {floor_s:.4f}); emissivity L1 {l1_e:.4f} (floor {floor_e:.4f}); "
+          f"total {tot:.4f} (plain/plain {eb.sum() / ea.sum():.4f}); plain scat {pa['counters']['scatterings']} "
+          f"learned scat {c['scatterings']} calls {c['mlp_calls']} skipped {c['skipped_scatterings']}")
+    assert l1_s <= 0.02 and l1_e <= 0.02
+    assert abs(tot - 1.0) < 0.015
+    assert c["scatterings"] + c["mlp_calls"] < 0.2 * pa["counters"]["scatterings"]
 
 
 def test_escape_refused_outside_trained_damping(gpu_ctx, trained):
@@ -348,10 +449,29 @@ def test_escape_refused_outside_trained_damping(gpu_ctx, trained):
     from paper_2608_09340_amd import krt
     w = torch.zeros(krt.ESC_NPARAMS + krt.ESC_NNORM, dtype=torch.float32, device="cuda")
     gpu_ctx.krt_escape_get_weights(w)
-    lo, hi = w[krt.ESC_NPARAMS + 2 * NO + NCAL:krt.ESC_NPARAMS + 2 * NO + NCAL + 2].cpu().numpy()
+    o = krt.ESC_NPARAMS + 2 * NO + NCAL
+    lo, hi, tlo, thi = w[o:o + 4].cpu().numpy()
     assert abs(lo + 3.0) < 1e-5 and abs(hi + 3.0) < 1e-5, (lo, hi)
+    assert 1.45 < tlo < 1.6 and 4.9 < thi <= 5.0, (tlo, thi)
     T = krt.Transport(W.cube(n=4, tau0=1e3, a=1e-2), ctx=gpu_ctx)
     with pytest.raises(Exception, match="fitted on log10 a"):
         T.run(1000, seed=0, escape_mode=1)
     T3 = krt.Transport(W.cube(n=4, tau0=1e3, a=1e-3), ctx=gpu_ctx)
     assert T3.run(1000, seed=0, escape_mode=1)["rc"] == 0
+
+
+def test_escape_refused_for_dipole_and_destruction(gpu_ctx, trained):
+    """The network is trained on isotropic re-emission without destruction:
+    a dipole-phase line or a grid with a destruction field is refused (the
+    skipped scatterings could apply neither)."""
+    from paper_2608_09340_amd import krt
+    p = W.cube(n=4, tau0=1e3, a=1e-3)
+    p["line"]["phase"] = W.PHASE_DIPOLE
+    T = krt.Transport(p, ctx=gpu_ctx)
+    with pytest.raises(Exception, match="isotropic phase"):
+        T.run(1000, seed=0, escape_mode=1)
+    p = W.cube(n=4, tau0=1e3, a=1e-3)
+    p["grid"]["eps"] = np.full(64, 1e-3, dtype=np.float32)
+    T = krt.Transport(p, ctx=gpu_ctx)
+    with pytest.raises(Exception, match="destruction"):
+        T.run(1000, seed=0, escape_mode=1)

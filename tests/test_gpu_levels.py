@@ -120,3 +120,23 @@ def test_level_solve_every_level_count(gpu_ctx, nl):
     e = eps.cpu().numpy()
     assert np.allclose(k0.cpu().numpy().reshape(nl - 1, nc), (P[:, :nl - 1] * s0[None, :]).T, rtol=1e-6)
     assert np.all((e > 0) & (e < 1))
+
+
+def test_frozen_source_and_line_powers(lam):
+    """krt_levels_update's emission output is n_u A_ul of its own populations
+    (binary32 rounding), and its line powers equal the cell volume times the
+    FP64 sum of n_u A_ul over the oracle's collisional-equilibrium solve of
+    the same cells (1e-9 relative): the Lambda iteration's frozen source
+    (Sec. 2.1.3) comes from the library, not from host arithmetic."""
+    nc, nl = lam.ncell, lam.nl
+    P0 = lam.pops0.cpu().numpy().reshape(nc, nl)
+    A = lam.rot["A"]
+    em = lam.emis.cpu().numpy().reshape(nl - 1, nc)
+    for l in range(nl - 1):
+        want = (P0[:, l + 1] * A[l + 1, l]).astype(np.float32)
+        assert np.array_equal(em[l], want), l
+    ref = oracle.levels_solve(lam.rot["E"], lam.rot["g"], A, lam.rot["Cd"], lam.ncoll.cpu().numpy(),
+                              lam.ntot.cpu().numpy())
+    for l in range(nl - 1):
+        lum = lam.vcell * np.sum(ref[:, l + 1] * A[l + 1, l])
+        assert abs(lam.lum[l] / lum - 1) < 1e-9, (l, lam.lum[l], lum)

@@ -150,3 +150,33 @@ def test_finalize_emissivity_of_thin_beam_slab_absolute():
     m = want * N / 1.0 > 50
     z = (per[m] - want[m]) / np.sqrt(want[m] / N)
     assert np.max(np.abs(z)) < 4.5, np.max(np.abs(z))
+
+
+# ------------------------------------------------- dust absorption (Sec. 3.2) --
+@pytest.mark.parametrize("tau_a", [0.01, 0.05])
+def test_dusty_slab_escape_fraction(tau_a):
+    """Sec. 3.2, the dusty slab: a static slab of line-centre depth tau0 = 1e5
+    (a = 0.015) with grey absorption depth tau_a, photons emitted at line
+    centre from the midplane.  The escaped fraction follows the analytic
+    solution of Neufeld (1990) in the form of Verhamme, Schaerer & Maselli
+    (2006), f_esc = 1 / cosh(sqrt(3) / (zeta pi^(5/12)) sqrt((a tau0)^(1/3)
+    tau_a)) with zeta = 0.525, within the 12% the paper reports for its own
+    code plus 3.5 binomial standard errors."""
+    a, tau0, n = 0.015, 1e5, 600
+    r = oracle.mc_run(W.dusty_slab(tau0, a, tau_a), n, seed=1)
+    c = r["counters"]
+    assert c["emitted"] == c["escaped"] + c["destroyed"] == n
+    f = c["escaped"] / n
+    ref = 1.0 / np.cosh(np.sqrt(3.0) / (0.525 * np.pi ** (5.0 / 12.0)) * np.sqrt((a * tau0) ** (1 / 3) * tau_a))
+    se = np.sqrt(ref * (1 - ref) / n)
+    assert abs(f - ref) < 0.12 * ref + 3.5 * se, (tau_a, f, ref)
+
+
+def test_dust_free_grid_is_unchanged_by_a_zero_absorption_field():
+    """With an absorption field of zeros every packet takes exactly the walk
+    it takes without one (the absorption test reduces to eps's own test)."""
+    p = W.slab(300.0, 1e-2, 16)
+    a = oracle.mc_run(p, 2000, seed=3, packet_log=True)
+    p["grid"]["kabs"] = np.zeros(16, dtype=np.float32)
+    b = oracle.mc_run(p, 2000, seed=3, packet_log=True)
+    assert np.array_equal(a["spec"], b["spec"]) and np.array_equal(a["packet_log"], b["packet_log"])

@@ -372,53 +372,90 @@ def test_levels_lte_and_numpy():
 
 
 # ------------------------------------------------------- escape records --
-def _exit_geometry(n):
-    """Brute-force ray geometry: a straight ray from the centre of the cube
-    [-1, 1]^3 along n leaves through the face of the largest |n_i|; exit point
-    (s, t) = the other two components / |n_ax| in cyclic order, cosine |n_ax|."""
-    ax = np.argmax(np.abs(n), axis=1)
-    rows = np.arange(len(n))
-    na = np.abs(n[rows, ax])
-    s = n[rows, (ax + 1) % 3] / na
-    t = n[rows, (ax + 2) % 3] / na
-    return s, t, na
+def _ray_exit(q, v):
+    """Straight rays from q along unit vectors v out of the cube [-1, 1]^3:
+    exit face 2 axis + (normal along +axis), offsets of the exit point from q's
+    projection onto the face over q's distance to the face plane (the two
+    axes following the exit axis cyclically), and the exit cosine."""
+    q = np.asarray(q, dtype=np.float64)
+    t = np.where(v > 0, (1.0 - q) / np.where(v > 0, v, 1.0), np.where(v < 0, (-1.0 - q) / np.where(v < 0, v, 1.0),
+                                                                       np.inf))
+    ax = np.argmin(t, axis=1)
+    rows = np.arange(len(v))
+    tm = t[rows, ax]
+    side = np.sign(v[rows, ax])
+    d = 1.0 - side * q[ax]
+    a1, a2 = (ax + 1) % 3, (ax + 2) % 3
+    ys = tm * v[rows, a1] / d
+    yt = tm * v[rows, a2] / d
+    return 2 * ax + (side > 0), ys, yt, np.abs(v[rows, ax])
 
 
-def test_escape_record_thin_cube_is_ray_geometry():
-    """tau_R -> 0: after the scattering at the centre the photon leaves the cube
-    unscattered, so N_s = 1 and (s, t, mu) follow the straight-ray geometry of
-    an isotropic direction (KS against numpy directions); its tangential
-    direction points along the exit point's offset from the face centre, so
-    the alignment angle alpha is 0."""
+def test_cell_escape_thin_is_ray_geometry():
+    """tau_c -> 0: after the scattering at q the photon leaves the cell
+    unscattered along an isotropic direction, so N_s = 1, the exit face
+    frequencies are the solid angles of the faces seen from q and the exit
+    offsets and cosine follow the straight-ray geometry (numpy rays from q);
+    the tangential direction is parallel to the offset, so alpha = 0."""
     from scipy import stats
-    n = 20000
-    rec = oracle.escape_record(n, 1e-5, 1e-3, 0.0, seed=3)
-    assert np.all(rec[:, 9] == 1.0)
-    assert np.all(rec[:, 7] == 0.0)  # ln N_s = 0: one scattering
+    q = np.array([0.3, -0.5, 0.7])
+    n = 40000
+    rec = oracle.cell_escape_record(n, 1e-7, 1e-3, 0.4, q, seed=3, threads=4)
+    assert np.all(rec[:, oracle.R_VALID] == 1.0) and np.all(rec[:, oracle.R_LOGN] == 0.0)
     rng = np.random.default_rng(5)
-    v = rng.normal(size=(200000, 3))
+    v = rng.normal(size=(400000, 3))
     v /= np.linalg.norm(v, axis=1)[:, None]
-    s, t, mu = _exit_geometry(v)
-    for col, ref in ((4, s), (5, t), (6, mu)):
-        assert stats.ks_2samp(rec[:, col], ref).pvalue > 1e-3, col
-    assert np.all(np.abs(rec[:, 10]) < 1e-9)
+    f, ys, yt, mu = _ray_exit(q, v)
+    pf = np.bincount(f, minlength=6) / len(f)
+    cf = np.bincount(rec[:, oracle.R_FACE].astype(int), minlength=6)
+    z = (cf - n * pf) / np.sqrt(n * pf * (1 - pf))
+    assert np.max(np.abs(z)) < 4.5, z
+    for face in (1, 3, 5):
+        m, mr = rec[:, oracle.R_FACE] == face, f == face
+        for col, ref in ((oracle.R_YS, ys), (oracle.R_YT, yt), (oracle.R_MU, mu)):
+            assert stats.ks_2samp(rec[m, col], ref[mr]).pvalue > 1e-3, (face, col)
+    assert np.all(np.abs(rec[:, oracle.R_ALPHA]) < 1e-7)
 
 
-def test_escape_record_symmetries_and_bounds():
-    """At depth tau_R = 50 with x_in = 0: the exit point is symmetric about the
-    face centre, the exit frequency symmetric about 0, every record valid with
-    N_s >= 1 and the exit point on the face; the alignment angle alpha lies in
-    [0, pi] and the direction leans away from the face centre (mean alpha
-    below the pi/2 of an unrelated azimuth), more so near the edges."""
-    rec = oracle.escape_record(4000, 50.0, 1e-3, 0.0, seed=4)
-    assert np.all(rec[:, 9] == 1.0) and np.all(rec[:, 7] >= 0.0)
-    al, r = rec[:, 10], np.hypot(rec[:, 4], rec[:, 5])
-    assert np.all((al >= 0.0) & (al <= np.pi))
-    assert al.mean() < 1.2 and al[r > 0.8].mean() < al[r < 0.4].mean() - 0.3
-    assert np.all(np.abs(rec[:, 4:6]) <= 1.0) and np.all((rec[:, 6] > 0) & (rec[:, 6] <= 1.0))
-    se = 1.0 / np.sqrt(len(rec))
-    for col in (3, 4, 5):
-        assert abs(rec[:, col].mean()) < 5 * rec[:, col].std() * se, col
+def test_cell_escape_symmetries_and_bounds():
+    """Symmetries of the cube and of the line profile: from a start on the
+    plane q_0 = 0 the faces -x and +x are equally likely; from the centre all
+    six faces are; reversing the sign of x_in mirrors the exit frequency
+    (x -> -x with the atom velocities reversed is a symmetry of the static
+    medium, Sec. 2.1.1); every record lies on its face, mu in (0, 1], alpha in
+    [0, pi], N_s >= 1, and the logged depth is tau_c (1 - max |q_k|)."""
+    from scipy import stats
+    tau = 40.0
+    q = np.array([0.0, 0.3, 0.55])
+    a = oracle.cell_escape_record(8000, tau, 1e-3, 0.8, q, seed=4, threads=4)
+    b = oracle.cell_escape_record(8000, tau, 1e-3, -0.8, q, seed=5, threads=4)
+    assert np.all(a[:, oracle.R_VALID] == 1.0) and np.all(a[:, oracle.R_LOGN] >= 0.0)
+    c = np.bincount(a[:, oracle.R_FACE].astype(int), minlength=6)
+    assert abs(c[0] - c[1]) < 4.5 * np.sqrt(c[0] + c[1]), c
+    assert stats.ks_2samp(a[:, oracle.R_XOUT], -b[:, oracle.R_XOUT]).pvalue > 1e-3
+    assert abs(a[0, oracle.R_LD] - np.log10(tau * (1 - 0.55))) < 1e-12
+    face = a[:, oracle.R_FACE].astype(int)
+    ax = face // 2
+    side = np.where(face % 2 == 1, 1.0, -1.0)
+    d = 1.0 - side * q[ax]
+    for col, off in ((oracle.R_YS, 1), (oracle.R_YT, 2)):
+        pos = q[(ax + off) % 3] + d * a[:, col]
+        assert np.all(np.abs(pos) <= 1.0 + 1e-9)
+    assert np.all((a[:, oracle.R_MU] > 0) & (a[:, oracle.R_MU] <= 1.0))
+    assert np.all((a[:, oracle.R_ALPHA] >= 0) & (a[:, oracle.R_ALPHA] <= np.pi))
+    cen = oracle.cell_escape_record(6000, tau, 1e-3, 0.0, [0.0, 0.0, 0.0], seed=6, threads=4)
+    cc = np.bincount(cen[:, oracle.R_FACE].astype(int), minlength=6)
+    chi2 = np.sum((cc - 1000.0) ** 2 / 1000.0)
+    assert stats.chi2.sf(chi2, 5) > 1e-3, cc
+
+
+def test_cell_escape_near_face_of_thick_cell():
+    """A photon scattering three line-centre mean free paths below a face of a
+    cell a thousand deep (centre to face) leaves through that face in almost
+    every case: the other faces lie hundreds of mean free paths away."""
+    rec = oracle.cell_escape_record(4000, 1000.0, 1e-3, 0.3, [0.1, -0.2, 0.997], seed=7, threads=4)
+    near = np.mean(rec[:, oracle.R_FACE] == 5)
+    assert near > 0.95, near
 
 
 # ------------------------------------------------------------- imaging --
