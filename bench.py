@@ -236,7 +236,7 @@ def headline_c4(ctx, args):
         "kernel_ms": km,
         "roofline": {"bound": "alu", "achieved": valu, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
                      "frac": valu / PEAK_VALU_TOPS, "traffic": profiled_traffic(PROFILE_SUMMARY_LEARNED),
-                     "kernel": "mc_transport_kernel<true, 768> (learned escape)",
+                     "kernel": "mc_transport_kernel<true, 512> (learned escape)",
                      "ops_per_scattering": ledger_per_scatter(False, True),
                      "mfma": {"achieved": mfma, "peak": PEAK_MFMA_BF16_TFLOPS, "unit": "TFLOP/s",
                               "frac": mfma / PEAK_MFMA_BF16_TFLOPS,
@@ -263,7 +263,7 @@ def headline_c4(ctx, args):
     }
 
 
-MLP_FLOP_PER_EVAL = 2 * (8 * 128 + 128 * 128 + 128 * 128 + 128 * 10)  # one sample through 8->3x128->10
+MLP_FLOP_PER_EVAL = 2 * (24 * 128 + 128 * 128 + 128 * 128 + 128 * 32)  # one sample through 24->3x128->32
 
 
 def sphere_c1_leg(ctx, packets=1_000_000):

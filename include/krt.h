@@ -146,7 +146,7 @@ typedef struct {
                                   isotropic phase and no destruction or absorption field, else
                                   KRT_EINVAL: the network is trained on isotropic re-emission without
                                   either) */
-    int32_t wg_size;           /* launch geometry: threads per workgroup (0 = 1024 plain, 768
+    int32_t wg_size;           /* launch geometry: threads per workgroup (0 = 1024 plain, 512
                                   learned; the learned kernel is built for 256 VGPRs at <= 512
                                   lanes, 168 at <= 768, 128 above) */
     int32_t wg_per_cu;         /* workgroups per CU (0 = 1) */
@@ -315,17 +315,19 @@ int krt_levels_update(krt_ctx *ctx, const krt_levels_desc *desc,
  * uniformly).  Inputs (normalised): (log10 tau_c - 3)/1.2, log10 a + 3,
  * |x_in| - 1, 2 q - 1 (3), (log10 depth - 2)/1.2, incoming direction (3), four
  * quantile levels as logit(u)/4, a flag (0 marginal, 1 conditional), and for
- * conditional rows x_out/4 and the one-hot exit face.  A call takes two
- * evaluations: marginal (outputs 0-5 exit-face logits, 6 logit P(x_out >= 0),
- * 7/8 quantile of |x_out| on either side at u_a, 9 ln E[N_s], 10 quantile of
- * ln <x^2> at u_b), then conditional on the sampled face and x_out (11, 12
- * quantiles of ys, yt at u_a, u_b; 13 of mu at u_c; 14 of alpha at u_d).
- * Losses: softmax cross-entropy (face), logistic (side), pinball (quantiles),
- * log-deviance e^d - 1 - d, d = ln N_s - output, for output 9; a third of the
- * training rows are conditional.
+ * conditional rows x_out/4 and the one-hot exit face.  The network has 32
+ * outputs; a call takes two evaluations: marginal (outputs 0-5 exit-face
+ * logits, 6 logit P(x_out >= 0), 7 ln E[N_s], 8 quantile of ln <x^2> at u_b,
+ * 16 + F quantile of |x_out| at u_a given exit face F), then conditional on
+ * the sampled face and x_out (9, 10 quantiles of asinh ys, asinh yt at u_a,
+ * u_b; 11 of mu^2 at u_c; 12 of alpha at u_d); 13-15 and 22-31 are unused.
+ * Losses: softmax cross-entropy (face), logistic (side), pinball (quantiles;
+ * output 16 + F only on walks leaving through F), log-deviance e^d - 1 - d,
+ * d = ln N_s - output, for output 7; a third of the training rows are
+ * conditional.
  *
- * Parameters: kNParams = 38288 FP32 master values, then 296 constants: target
- * mean[16] and scale[16], 256 additive calibration terms of ln E[N_s] (per bin
+ * Parameters: kNParams = 40352 FP32 master values, then 328 constants: target
+ * mean[32] and scale[32], 256 additive calibration terms of ln E[N_s] (per bin
  * of log10 tau_c in 8 bins of 0.5 over [1, 5), log10 depth in 8 bins of 0.5
  * over [0, 4) and |x_in| in 4 bins of 0.5 over [0, 2), ends clamped; index =
  * (tau bin * 8 + depth bin) * 4 + x bin), then the training records' ranges:
@@ -355,15 +357,15 @@ int krt_levels_update(krt_ctx *ctx, const krt_levels_desc *desc,
  * krt_escape_grad: gradient of the mean loss over the batch given by
  *   idx_dev [batch] (record indices, 1 <= batch <= 2^20) and u_dev [batch][5]
  *   = (u_a, u_b, u_c, u_d, 1 for a conditional row else 0); grad_out_dev
- *   [38288], loss_out_dev [1] (may be NULL).
+ *   [40352], loss_out_dev [1] (may be NULL).
  * krt_escape_train: `steps` Adam steps (lr, betas 0.9/0.999) on random batches
  *   (Philox(seed)) of 1 <= batch <= 2^20 out of n < 2^31 records;
  *   loss_hist_dev [steps] or NULL.
- * krt_escape_get_weights / put_weights: [38288 + 296] FP32 device buffers.
+ * krt_escape_get_weights / put_weights: [40352 + 328] FP32 device buffers.
  * krt_escape_forward: in_dev [n][17] raw (log10 tau_c, log10 a, |x_in|, q0,
  *   q1, q2, log10 depth, n_in (3), u_a, u_b, u_c, u_d, flag, x_out, F) ->
- *   out_dev [n][16] in physical units (logits as logits, output 9 with its
- *   calibration term); n < 2^30.
+ *   out_dev [n][32] de-normalised (logits as logits, output 7 with its
+ *   calibration term, outputs 9-11 as asinh ys, asinh yt, mu^2); n < 2^30.
  * Errors: KRT_EINVAL (sizes, ranges), KRT_ESTATE (no init / no tables). */
 typedef struct {
     double log10_tau_lo, log10_tau_hi;  /* log10 tau_c range */

@@ -1,7 +1,7 @@
 """FP64 CPU reference of the whole-cell escape network -- TEST INFRASTRUCTURE.
 
 Same parameter layout as the GPU (one flat vector): W1[24][128], b1[128],
-W2[128][128], b2, W3[128][128], b3, W4[128][16], b4[16]; activations SiLU.
+W2[128][128], b2, W3[128][128], b3, W4[128][32], b4[32]; activations SiLU.
 
 The network describes how a photon that scatters inside a homogeneous static
 cubic cell leaves it (the plain walk of Sec. 2.1-2.3 confined to one cell; the
@@ -25,25 +25,32 @@ x_in's).  Inputs (24):
 
 Outputs (index: meaning, loss, level):
   marginal rows
-  0-5  logits of the exit face                      softmax cross-entropy
-  6    logit P(x_out >= 0)                           logistic
-  7    quantile of x_out given x_out >= 0            pinball at u_a, records with x_out >= 0
-  8    quantile of -x_out given x_out < 0            pinball at u_a, records with x_out < 0
-  9    ln E[N_s | condition]                         weighted log-deviance
-  10   quantile of ln <x^2> over the scatterings     pinball at u_b
+  0-5   logits of the exit face                      softmax cross-entropy
+  6     logit P(x_out >= 0)                          logistic
+  7     ln E[N_s | condition]                        weighted log-deviance
+  8     quantile of ln <x^2> over the scatterings    pinball at u_b
+  16-21 quantile of |x_out| given exit face F        pinball at u_a, records
+        (output 16 + F)                              leaving through F
   conditional rows (given the exit face and x_out)
-  11   quantile of ys (exit offset, first axis)      pinball at u_a
-  12   quantile of yt (exit offset, second axis)     pinball at u_b
-  13   quantile of mu (exit cosine)                  pinball at u_c
-  14   quantile of alpha (tangential direction vs    pinball at u_d
-       the exit offset)
-  15   unused
+  9     quantile of asinh(ys)                        pinball at u_a
+  10    quantile of asinh(yt)                        pinball at u_b
+  11    quantile of mu^2 (mu the exit cosine)        pinball at u_c
+  12    quantile of alpha (tangential direction vs   pinball at u_d
+        the exit offset)
+  13-15, 22-31 unused
 ys, yt are the exit point's offsets from the start point's projection onto
 the exit face (along the two axes following the exit axis cyclically) over
-the start point's distance to that face's plane.
+the start point's distance to that face's plane.  The offsets' heavy tails
+(the plane distance can be tiny) are compressed by asinh and the cosine is
+learned as mu^2, whose quantile function near mu = 0 is smooth (the exit
+cosine of an optically thick medium has a density vanishing linearly at 0);
+both maps are monotone, so quantiles transform with them.  The exit
+frequency's magnitude depends strongly on the exit face (photons leaving
+through the near face need a shorter wing excursion), so it has one quantile
+output per face; its sign is nearly independent of the face.
 
-Pinball loss rho_u(y - o) = (y - o)(u - 1{y < o}); output 9 uses the scaled
-log-deviance w f(d) / s9 with w = 1/4, d = s9 (y9 - o9), f(d) = e^d - 1 - d
+Pinball loss rho_u(y - o) = (y - o)(u - 1{y < o}); output 7 uses the scaled
+log-deviance w f(d) / s7 with w = 1/4, d = s7 (y7 - o7), f(d) = e^d - 1 - d
 continued linearly beyond d = 4, whose minimiser is ln E[N_s]; the face
 logits use -log softmax(o)_F, whose minimiser is the log-probabilities (up to
 a constant); output 6 uses softplus(o) - b o, b = 1{x_out >= 0}.  Losses are
@@ -55,17 +62,20 @@ from __future__ import annotations
 
 import numpy as np
 
-NIN, NH, NOUT = 24, 128, 16
+NIN, NH, NOUT = 24, 128, 32
 SHAPES = [("W1", (NIN, NH)), ("b1", (NH,)), ("W2", (NH, NH)), ("b2", (NH,)),
           ("W3", (NH, NH)), ("b3", (NH,)), ("W4", (NH, NOUT)), ("b4", (NOUT,))]
 NPARAMS = sum(int(np.prod(s)) for _, s in SHAPES)
 NCAL = 256
-NNORM = 2 * NOUT + NCAL + 4
+NNORM = 2 * NOUT + NCAL + 8
 O_FACE = 0
-O_SIDE, O_XPOS, O_XNEG, O_LOGN, O_LOGX2, O_YS, O_YT, O_MU, O_ALPHA, O_SPARE = range(6, 16)
+O_SIDE, O_LOGN, O_LOGX2, O_YS, O_YT, O_MU2, O_ALPHA = range(6, 13)
+O_XABS = 16
 FACES = tuple(range(6))
-MARGINAL = FACES + (O_SIDE, O_XPOS, O_XNEG, O_LOGN, O_LOGX2)
-CONDITIONAL = (O_YS, O_YT, O_MU, O_ALPHA)
+XABS = tuple(O_XABS + f for f in FACES)
+MARGINAL = FACES + (O_SIDE, O_LOGN, O_LOGX2) + XABS
+CONDITIONAL = (O_YS, O_YT, O_MU2, O_ALPHA)
+UNUSED = tuple(k for k in range(NOUT) if k not in MARGINAL + CONDITIONAL)
 DEV_CLAMP = 4.0
 LEVEL_MIN = 1e-4
 DEV_WEIGHT = 0.25
@@ -131,10 +141,10 @@ def levels(u, cond):
     u = np.asarray(u, dtype=np.float64).reshape(-1, 4)
     cond = np.asarray(cond, dtype=bool)
     U = np.full((cond.shape[0], NOUT), np.nan)
-    U[:, O_XPOS] = np.where(cond, np.nan, u[:, 0])
-    U[:, O_XNEG] = np.where(cond, np.nan, u[:, 0])
+    for k in XABS:
+        U[:, k] = np.where(cond, np.nan, u[:, 0])
     U[:, O_LOGX2] = np.where(cond, np.nan, u[:, 1])
-    for k, j in ((O_YS, 0), (O_YT, 1), (O_MU, 2), (O_ALPHA, 3)):
+    for k, j in ((O_YS, 0), (O_YT, 1), (O_MU2, 2), (O_ALPHA, 3)):
         U[:, k] = np.where(cond, u[:, j], np.nan)
     return U
 
@@ -214,7 +224,7 @@ def losses(out, Y, U, s9=1.0):
 
 
 def loss_and_grad(p, X, Y, U, bf=False, s9=1.0):
-    """s9: the target scale of output 9 (norm[NOUT + 9])."""
+    """s9: the target scale of the ln E[N_s] output (norm[NOUT + O_LOGN])."""
     out, c, W = forward(p, X, bf)
     loss, d = losses(out, Y, U, s9)
     g = {"W4": c["h3"].T @ d, "b4": d.sum(0)}
@@ -230,26 +240,27 @@ def loss_and_grad(p, X, Y, U, bf=False, s9=1.0):
 def raw_targets(rec, cond=None):
     """Records (columns R_*, reduced frame) -> per-output physical targets
     [B, NOUT] (NaN where masked; column 0 holds the face label, column 6 the
-    side label).  cond marks conditional rows (default: none)."""
+    side label; the exit-frequency magnitude only in its exit face's column;
+    the offsets as asinh, the cosine squared).  cond marks conditional rows
+    (default: none)."""
     rec = np.asarray(rec, dtype=np.float64)
     B = rec.shape[0]
     cond = np.zeros(B, dtype=bool) if cond is None else np.asarray(cond, dtype=bool)
     x = rec[:, R_XOUT]
-    pos = x >= 0.0
+    F = rec[:, R_FACE].astype(np.int64)
     y = np.full((B, NOUT), np.nan)
     y[:, 0] = rec[:, R_FACE]
-    y[:, O_SIDE] = pos.astype(np.float64)
-    y[:, O_XPOS] = np.where(pos, x, np.nan)
-    y[:, O_XNEG] = np.where(pos, np.nan, -x)
+    y[:, O_SIDE] = (x >= 0.0).astype(np.float64)
+    y[np.arange(B), O_XABS + F] = np.abs(x)
     y[:, O_LOGN] = rec[:, R_LOGN]
     y[:, O_LOGX2] = rec[:, R_LOGX2]
-    y[:, O_YS] = rec[:, R_YS]
-    y[:, O_YT] = rec[:, R_YT]
-    y[:, O_MU] = rec[:, R_MU]
+    y[:, O_YS] = np.arcsinh(rec[:, R_YS])
+    y[:, O_YT] = np.arcsinh(rec[:, R_YT])
+    y[:, O_MU2] = rec[:, R_MU] ** 2
     y[:, O_ALPHA] = rec[:, R_ALPHA]
     y[cond[:, None] & np.isin(np.arange(NOUT), MARGINAL)[None, :]] = np.nan
     y[~cond[:, None] & np.isin(np.arange(NOUT), CONDITIONAL)[None, :]] = np.nan
-    y[:, O_SPARE] = np.nan
+    y[:, list(UNUSED)] = np.nan
     return y
 
 

@@ -223,13 +223,12 @@ __global__ void mlp_pack_kernel(const float *p, const float *norm, unsigned char
                 const int tt = t - ((t < kTileFwdL3) ? kTileFwdL2 : kTileFwdL3);
                 const int mo = tt / 4, c = tt % 4;
                 w = p[base + kperm(c, kp) * kMlpHid + 16 * mo + i];
-            } else if (t < kTilesFwd) {  // L4 fwd: tile c, A[i][k'] = W4[kperm(c,k')][i]
-                const int c = t - kTileFwdL4;
-                w = p[kPW4 + kperm(c, kp) * kMlpOut + i];
-            } else if (t < kTileBwdL3) {  // L4 bwd: tile mi, A[i][k'] = W4[16mi+i][kperm(0,k')] (outputs < 16)
+            } else if (t < kTilesFwd) {  // L4 fwd: tile 4 ot + c, A[i][k'] = W4[kperm(c,k')][16 ot + i]
+                const int ot = (t - kTileFwdL4) / 4, c = (t - kTileFwdL4) % 4;
+                w = p[kPW4 + kperm(c, kp) * kMlpOut + 16 * ot + i];
+            } else if (t < kTileBwdL3) {  // L4 bwd: tile mi, A[i][k'] = W4[16mi+i][kperm(0,k')]
                 const int mi = t - kTileBwdL4;
-                const int o = kperm(0, kp);
-                if (o < kMlpOut) w = p[kPW4 + (16 * mi + i) * kMlpOut + o];
+                w = p[kPW4 + (16 * mi + i) * kMlpOut + kperm(0, kp)];
             } else {  // L3/L2 bwd: tile mi*4+c, A[i][k'] = W[16mi+i][kperm(c,k')]
                 const int base = (t < kTileBwdL2) ? kPW3 : kPW2;
                 const int tt = t - ((t < kTileBwdL2) ? kTileBwdL3 : kTileBwdL2);
@@ -243,10 +242,10 @@ __global__ void mlp_pack_kernel(const float *p, const float *norm, unsigned char
     float *fb = reinterpret_cast<float *>(blob + kTilesAll * kTileBytes);
     if (gid < kBiasFloats) {
         float b;
-        if (gid < 128) b = p[kPB1 + gid];
-        else if (gid < 256) b = p[kPB2 + gid - 128];
-        else if (gid < 384) b = p[kPB3 + gid - 256];
-        else b = p[kPB4 + gid - 384];
+        if (gid < kMlpHid) b = p[kPB1 + gid];
+        else if (gid < 2 * kMlpHid) b = p[kPB2 + gid - kMlpHid];
+        else if (gid < 3 * kMlpHid) b = p[kPB3 + gid - 2 * kMlpHid];
+        else b = p[kPB4 + gid - 3 * kMlpHid];
         fb[gid] = b;
     }
     if (gid < kNNorm) fb[kBiasFloats + gid] = norm[gid];
@@ -262,41 +261,49 @@ __global__ void mlp_fwd_image_kernel(const unsigned char *blob, unsigned char *i
     else if (i < tiles_b + tail_b) img[i] = blob[kTilesAll * kTileBytes + (i - tiles_b)];
 }
 
-// Record column of output k's target (faces, side and the spare have none).
-__device__ __forceinline__ int target_col(int k) {
+// Regression target of output k on record r, in the output's own variable
+// (|x_out| only for the record's exit face, asinh of the offsets, the cosine
+// squared); false where the output has none (faces, side, unused outputs,
+// another face's |x_out|).
+__device__ __forceinline__ bool target_value(const float *r, int k, float &y) {
+    if (k >= kOutXAbs && k < kOutXAbs + 6) {
+        if ((int)r[kRecFace] != k - kOutXAbs) return false;
+        y = fabsf(r[kRecXOut]);
+        return true;
+    }
     switch (k) {
-        case kOutXPos: case kOutXNeg: return kRecXOut;
-        case kOutLogN: return kRecLogN;
-        case kOutLogX2: return kRecLogX2;
-        case kOutYS: return kRecYS;
-        case kOutYT: return kRecYT;
-        case kOutMu: return kRecMu;
-        case kOutAlpha: return kRecAlpha;
-        default: return -1;
+        case kOutLogN: y = r[kRecLogN]; return true;
+        case kOutLogX2: y = r[kRecLogX2]; return true;
+        case kOutYS: y = asinhf(r[kRecYS]); return true;
+        case kOutYT: y = asinhf(r[kRecYT]); return true;
+        case kOutMu2: y = r[kRecMu] * r[kRecMu]; return true;
+        case kOutAlpha: y = r[kRecAlpha]; return true;
+        default: return false;
     }
 }
 
 __device__ __forceinline__ bool conditional_output(int k) { return k >= kOutYS && k <= kOutAlpha; }
+__device__ __forceinline__ bool used_output(int k) { return k <= kOutAlpha || (k >= kOutXAbs && k < kOutXAbs + 6); }
 
 // ----------------------------------------------------- forward + backward ---
 // Activation store of a training step, bf16 [row][cap] (samples contiguous):
 // H0 32 rows (inputs, row 24 = 1 for the bias), H1..H3 144 rows (SiLU
-// activations, row 128 = 1), dZ1..dZ3 128 rows, dZ4 16 rows.  The constant
+// activations, row 128 = 1), dZ1..dZ3 128 rows, dZ4 32 rows.  The constant
 // rows are written once when the store is allocated.
 constexpr int kActRowsH0 = 32, kActRowsH = 144;
 constexpr int kActH0 = 0, kActH1 = kActH0 + kActRowsH0, kActH2 = kActH1 + kActRowsH, kActH3 = kActH2 + kActRowsH,
               kActZ1 = kActH3 + kActRowsH, kActZ2 = kActZ1 + kMlpHid, kActZ3 = kActZ2 + kMlpHid,
-              kActZ4 = kActZ3 + kMlpHid, kActRows = kActZ4 + kMlpOut;   // 864
+              kActZ4 = kActZ3 + kMlpHid, kActRows = kActZ4 + kMlpOut;   // 880
 static_assert(kActRows == kActRowsAll, "activation store layout");
 
 // One wave per 16-sample block.  Row si uses record idx[si] and uq[5 si ..] =
 // (u_a, u_b, u_c, u_d, 1 for a conditional row); a conditional row takes the
 // record's exit face and exit frequency as inputs.  Losses (each averaged over
 // the batch): softmax cross-entropy for the exit face, logistic for the side
-// of x_out, pinball for the quantiles at their own levels (the two one-sided
-// exit frequencies only on records of their side), log-deviance for ln N_s.
-// Marginal rows train outputs 0-10, conditional rows 11-14.  Samples past the
-// batch (up to the next multiple of 32) get zero gradients.
+// of x_out, pinball for the quantiles at their own levels (|x_out| of face F
+// only on records leaving through F), log-deviance for ln N_s.  Marginal rows
+// train outputs 0-8 and 16-21, conditional rows 9-12.  Samples past the batch
+// (up to the next multiple of 32) get zero gradients.
 __global__ void __launch_bounds__(256) mlp_fwdbwd_kernel(const unsigned char *blob, const float *rec,
                                                          const int32_t *idx, const float *uq, int batch,
                                                          uint16_t *act, int64_t cap, float *loss) {
@@ -318,9 +325,9 @@ __global__ void __launch_bounds__(256) mlp_fwdbwd_kernel(const unsigned char *bl
     mlp_inputs(r, ua, ub, uc, ud, cond, r[kRecXOut], (int)r[kRecFace], in);
     if (!live)
         for (int k = 0; k < kMlpIn; ++k) in[k] = 0.0f;
-    v4f32 z1[8], z2[8], z3[8];
-    const v4f32 o = mlp_forward_block(blob, bias, xin_operand(in, lane), lane, z1, z2, z3);
-    const float ov[4] = {o.x, o.y, o.z, o.w};
+    v4f32 z1[8], z2[8], z3[8], o, ob;
+    mlp_forward_block(blob, bias, xin_operand(in, lane), lane, z1, z2, z3, o, ob);
+    const float ov[8] = {o.x, o.y, o.z, o.w, ob.x, ob.y, ob.z, ob.w};
     // the six face logits of this lane's sample (lanes s and s + 16)
     float fl[6];
     fl[0] = __shfl(o.x, s, 64); fl[1] = __shfl(o.y, s, 64); fl[2] = __shfl(o.z, s, 64); fl[3] = __shfl(o.w, s, 64);
@@ -338,13 +345,13 @@ __global__ void __launch_bounds__(256) mlp_fwdbwd_kernel(const unsigned char *bl
     for (int f = 0; f < 6; ++f) if (f == face) flf = fl[f];
     const float invB = 1.0f / (float)batch;
     const float xo = r[kRecXOut];
-    float dO[4], lsum = 0.0f;
+    float dO[8], lsum = 0.0f;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int k = 4 * g + j;
+    for (int j = 0; j < 8; ++j) {
+        const int k = (j < 4) ? 4 * g + j : 16 + 4 * g + (j - 4);
         const float oj = ov[j];
         dO[j] = 0.0f;
-        if (!live || k == kOutSpare || conditional_output(k) != cond) continue;
+        if (!live || !used_output(k) || conditional_output(k) != cond) continue;
         if (k < 6) {
             float smk = 0.0f;
 #pragma unroll
@@ -360,15 +367,7 @@ __global__ void __launch_bounds__(256) mlp_fwdbwd_kernel(const unsigned char *bl
             continue;
         }
         float raw;
-        if (k == kOutXPos) {
-            if (xo < 0.0f) continue;
-            raw = xo;
-        } else if (k == kOutXNeg) {
-            if (xo >= 0.0f) continue;
-            raw = -xo;
-        } else {
-            raw = r[target_col(k)];
-        }
+        if (!target_value(r, k, raw)) continue;
         const float y = (raw - norm[k]) / norm[kMlpOut + k];
         if (k == kOutLogN) {
             // weighted, scaled log-deviance w f(d) / s, d = s (y - o), f(d) = e^d - 1 - d,
@@ -383,9 +382,9 @@ __global__ void __launch_bounds__(256) mlp_fwdbwd_kernel(const unsigned char *bl
         }
         // quantile level of this output on its kind of row
         float u;
-        if (k == kOutXPos || k == kOutXNeg || k == kOutYS) u = ua;
+        if (k >= kOutXAbs || k == kOutYS) u = ua;
         else if (k == kOutLogX2 || k == kOutYT) u = ub;
-        else if (k == kOutMu) u = uc;
+        else if (k == kOutMu2) u = uc;
         else u = ud;
         const float ind = (y < oj) ? 1.0f : 0.0f;
         dO[j] = (ind - u) * invB;
@@ -408,13 +407,15 @@ __global__ void __launch_bounds__(256) mlp_fwdbwd_kernel(const unsigned char *bl
         for (int j = 0; j < 8; ++j) p[j * cap] = f2bf(g == 0 ? in[j] : (g == 1 ? in[8 + j] : in[16 + j]));
     }
     store4(kActZ4, dO[0], dO[1], dO[2], dO[3]);
-    v4i16 dOb = pack4(dO[0], dO[1], dO[2], dO[3]);
-    const v4i16 zero4 = {0, 0, 0, 0};
+    store4(kActZ4 + 16, dO[4], dO[5], dO[6], dO[7]);
+    // B operand of the output layer's backward: slots 8g + j hold outputs
+    // 4g + j and 16 + 4g + j, the permutation of the hidden layers' chunks
+    const v8i16 dOb = cat8(pack4(dO[0], dO[1], dO[2], dO[3]), pack4(dO[4], dO[5], dO[6], dO[7]));
     v4f32 dz[8];
 #pragma unroll
     for (int mi = 0; mi < 8; ++mi) {
         v4f32 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mfma32(tileA(blob, kTileBwdL4 + mi, lane), cat8(dOb, zero4), acc);
+        acc = mfma32(tileA(blob, kTileBwdL4 + mi, lane), dOb, acc);
         dz[mi] = (v4f32){acc.x * dsilu(z3[mi].x), acc.y * dsilu(z3[mi].y), acc.z * dsilu(z3[mi].z),
                          acc.w * dsilu(z3[mi].w)};
         store4(kActH3 + 16 * mi, silu(z3[mi].x), silu(z3[mi].y), silu(z3[mi].z), silu(z3[mi].w));
@@ -445,8 +446,8 @@ __global__ void __launch_bounds__(256) mlp_fwdbwd_kernel(const unsigned char *bl
 // per (layer, 16-row tile, 16-column tile, sample split); results go to
 // part[split][param] (every parameter is written by exactly one wave per split,
 // so the sum over splits in fixed order is deterministic).
-constexpr int kGradJobsL1 = 2 * 8, kGradJobsL2 = 9 * 8, kGradJobsL3 = 9 * 8, kGradJobsL4 = 9;
-constexpr int kGradJobs = kGradJobsL1 + kGradJobsL2 + kGradJobsL3 + kGradJobsL4;   // 169
+constexpr int kGradJobsL1 = 2 * 8, kGradJobsL2 = 9 * 8, kGradJobsL3 = 9 * 8, kGradJobsL4 = 9 * 2;
+constexpr int kGradJobs = kGradJobsL1 + kGradJobsL2 + kGradJobsL3 + kGradJobsL4;   // 178
 
 __global__ void __launch_bounds__(256) mlp_wgrad_kernel(const uint16_t *act, int64_t cap, int kcols, float *part) {
     const int lane = __lane_id(), w = threadIdx.x / 64;
@@ -463,7 +464,7 @@ __global__ void __launch_bounds__(256) mlp_wgrad_kernel(const uint16_t *act, int
         it = jj / 8; jt = jj % 8; hrow = kActH2; zrow = kActZ3; nin = kMlpHid; ldw = kMlpHid; pw = kPW3; pb = kPB3;
     } else {
         jj -= kGradJobsL3;
-        it = jj; jt = 0; hrow = kActH3; zrow = kActZ4; nin = kMlpHid; ldw = kMlpOut; pw = kPW4; pb = kPB4;
+        it = jj / 2; jt = jj % 2; hrow = kActH3; zrow = kActZ4; nin = kMlpHid; ldw = kMlpOut; pw = kPW4; pb = kPB4;
     }
     const int s = lane % 16, g = lane / 16;
     // this split's columns: chunks of 32 samples
@@ -546,9 +547,9 @@ __global__ void mlp_batch_kernel(int64_t n, uint32_t k0, uint32_t k1, uint32_t s
 }
 
 // Normalisation of the targets: mean and standard deviation over the valid
-// records of each output's own target (the one-sided exit frequencies over the
-// records of their side; the face and side logits and the spare keep mean 0,
-// scale 1), FP64 accumulation, one block of 256 threads per output; three more
+// records of each output's own target (|x_out| of face F over the records
+// leaving through F; the face and side logits and the unused outputs keep
+// mean 0, scale 1), FP64 accumulation, one block of 256 threads per output; three more
 // blocks record the ranges of log10 a and log10 tau_c and the smallest log10
 // depth of the valid records (where the network may then be used).
 __global__ void mlp_norm_kernel(const float *rec, int64_t n, float *norm) {
@@ -584,19 +585,14 @@ __global__ void mlp_norm_kernel(const float *rec, int64_t n, float *norm) {
         }
         return;
     }
-    const int col = target_col(k);
-    if (col >= 0) {
-        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-            const float *r = rec + (int64_t)kRec * i;
-            if (r[kRecValid] < 0.5f) continue;
-            double y;
-            if (k == kOutXPos) { if (r[col] < 0.0f) continue; y = r[col]; }
-            else if (k == kOutXNeg) { if (r[col] >= 0.0f) continue; y = -r[col]; }
-            else y = r[col];
-            a += y;
-            b += y * y;
-            c += 1.0;
-        }
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const float *r = rec + (int64_t)kRec * i;
+        float yf;
+        if (r[kRecValid] < 0.5f || !target_value(r, k, yf)) continue;
+        const double y = yf;
+        a += y;
+        b += y * y;
+        c += 1.0;
     }
     s1[threadIdx.x] = a;
     s2[threadIdx.x] = b;
@@ -611,7 +607,7 @@ __global__ void mlp_norm_kernel(const float *rec, int64_t n, float *norm) {
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        if (col < 0 || s0[0] < 1.0) {
+        if (s0[0] < 1.0) {
             norm[k] = 0.0f;
             norm[kMlpOut + k] = 1.0f;
         } else {
@@ -625,8 +621,9 @@ __global__ void mlp_norm_kernel(const float *rec, int64_t n, float *norm) {
 
 // Forward for a list of raw rows in[n][kFwdRaw] = (log10 tau_c, log10 a, |x_in|,
 // q0, q1, q2, log10 depth, m0, m1, m2, u_a, u_b, u_c, u_d, flag, x_out, face):
-// out[n][16] in physical units (face and side logits as logits; ln E[N_s] with
-// its calibration term).
+// out[n][32] normalised outputs back in their own variables (face and side
+// logits as logits; ln E[N_s] with its calibration term; asinh of the offsets
+// and mu^2 as learned).
 __global__ void __launch_bounds__(256) mlp_forward_kernel(const unsigned char *blob, const float *inp,
                                                           int64_t n, float *out) {
     const int lane = __lane_id(), w = threadIdx.x / 64;
@@ -640,11 +637,12 @@ __global__ void __launch_bounds__(256) mlp_forward_kernel(const unsigned char *b
     const float *r = inp + (int64_t)kFwdRaw * (live ? si : 0);
     float in[kMlpIn];
     mlp_inputs(r, r[10], r[11], r[12], r[13], r[14] > 0.5f, r[15], (int)r[16], in);
-    const v4f32 o = mlp_forward_block(blob, bias, xin_operand(in, lane), lane, nullptr, nullptr, nullptr);
+    v4f32 o, ob;
+    mlp_forward_block(blob, bias, xin_operand(in, lane), lane, nullptr, nullptr, nullptr, o, ob);
     if (!live) return;
-    const float v[4] = {o.x, o.y, o.z, o.w};
-    for (int j = 0; j < 4; ++j) {
-        const int k = 4 * g + j;
+    const float v[8] = {o.x, o.y, o.z, o.w, ob.x, ob.y, ob.z, ob.w};
+    for (int j = 0; j < 8; ++j) {
+        const int k = (j < 4) ? 4 * g + j : 16 + 4 * g + (j - 4);
         out[kMlpOut * si + k] = v[j] * norm[kMlpOut + k] + norm[k] +
                                 ((k == kOutLogN) ? norm[kNormCal + cal_bin(r[0], r[6], r[2])] : 0.0f);
     }
@@ -674,11 +672,12 @@ __global__ void __launch_bounds__(256) mlp_calib_kernel(const unsigned char *blo
         const uint4 q = philox(make_uint4((uint32_t)si, (uint32_t)(si >> 32), 0u, 9u), 0x6C1Bu, 0x5EEDu);
         float in[kMlpIn];
         mlp_inputs(r, u01(q.x), u01(q.y), u01(q.z), u01(q.w), false, 0.0f, 0, in);
-        const v4f32 o = mlp_forward_block(blob, bias, xin_operand(in, lane), lane, nullptr, nullptr, nullptr);
-        // output 9 sits in lane group 2, component 1
-        if (live && g == 2 && r[kRecX] <= kEscXMax) {
+        v4f32 o, ob;
+        mlp_forward_block(blob, bias, xin_operand(in, lane), lane, nullptr, nullptr, nullptr, o, ob);
+        static_assert(kOutLogN == 7, "ln E[N_s] sits in lane group 1, component 3");
+        if (live && g == 1 && r[kRecX] <= kEscXMax) {
             const int b = cal_bin(r[kRecLT], r[kRecLD], r[kRecX]);
-            const double pred = exp((double)(o.y * norm[kMlpOut + kOutLogN] + norm[kOutLogN]));
+            const double pred = exp((double)(o.w * norm[kMlpOut + kOutLogN] + norm[kOutLogN]));
             atomicAdd(&ls[b], 1.0);
             atomicAdd(&ls[kNCal + b], exp((double)r[kRecLogN]));
             atomicAdd(&ls[2 * kNCal + b], pred);

@@ -28,6 +28,7 @@ enum { KRT_PHASE_ISO_I = 0, KRT_PHASE_DIPOLE_I = 1 };
 // bin-edge tables staged in LDS after the line tables
 constexpr int kMaxSpecBins = 1024, kMaxChannels = 256;
 constexpr int kEdgeFloats = (kMaxSpecBins + 1) + (kMaxChannels + 1) + 2;  // padded to a multiple of 4
+constexpr int kChanEdgeFloats = (kMaxChannels + 1) + 3;                 // channel edges alone, padded
 
 // 1 / ln((300/8)^(1/15)): logarithmic row spacing of the sampler above |x| = 8
 constexpr float kRowInvLog = 4.1386840f;

@@ -9,22 +9,26 @@
 // direction reflected and permuted alike, and |x_in| (the medium is symmetric
 // under x -> -x, so the exit frequency takes x_in's sign).
 //
-// Network: 24 inputs -> 128 -> 128 -> 128 (SiLU) -> 16 outputs.
+// Network: 24 inputs -> 128 -> 128 -> 128 (SiLU) -> 32 outputs.
 // Inputs: 0 (log10 tau_c - 3)/1.2 (tau_c the line-centre depth centre to face),
 //   1 log10 a + 3, 2 |x_in| - 1, 3-5 2 q - 1, 6 (log10 depth - 2)/1.2 (depth
 //   tau_c (1 - q2) to the nearest face), 7-9 incoming direction, 10-13 quantile
 //   levels L(u_a..u_d), L(u) = logit(u)/4, 14 flag (0 marginal, 1 conditional),
 //   15 conditional: x_out/4, 16-21 conditional: one-hot exit face, 22-23 zero.
 // Outputs (normalised): marginal: 0-5 exit-face logits (face F = 2 axis +
-//   (outward normal along +axis)); 6 logit P(x_out >= 0); 7 quantile at u_a of
-//   x_out given x_out >= 0; 8 quantile at u_a of -x_out given x_out < 0;
-//   9 ln E[N_s]; 10 quantile at u_b of ln <x^2> over the skipped scatterings.
-//   Conditional (given the exit face and x_out): 11, 12 quantiles at u_a, u_b
-//   of the exit offsets ys, yt from the start point's projection onto the exit
-//   face (along the two axes following the exit axis cyclically) over the
-//   start point's distance to that face's plane; 13 quantile at u_c of the exit
-//   cosine mu; 14 quantile at u_d of the angle alpha between the exit
-//   direction's tangential part and that offset.  15 unused.
+//   (outward normal along +axis)); 6 logit P(x_out >= 0); 7 ln E[N_s];
+//   8 quantile at u_b of ln <x^2> over the skipped scatterings; 16 + F
+//   quantile at u_a of |x_out| given exit face F (the magnitude depends
+//   strongly on the face, its sign hardly).  Conditional (given the exit face
+//   and x_out): 9, 10 quantiles at u_a, u_b of asinh of the exit offsets ys, yt
+//   from the start point's projection onto the exit face (along the two axes
+//   following the exit axis cyclically) over the start point's distance to
+//   that face's plane; 11 quantile at u_c of mu^2, mu the exit cosine; 12
+//   quantile at u_d of the angle alpha between the exit direction's
+//   tangential part and that offset.  13-15 and 22-31 unused.  asinh and the
+//   square are monotone, so the quantiles map back through their inverses;
+//   they remove the offsets' heavy tails and the steep quantile function of
+//   mu near 0.
 //
 // Layers run transposed, H^T_{l+1} = SiLU(W_l^T H^T_l + b_l), on 16-sample
 // blocks with v_mfma_f32_16x16x32_bf16.  The accumulator of a 16-feature tile
@@ -41,10 +45,10 @@
 
 namespace krt {
 
-constexpr int kMlpIn = 24, kMlpInPad = 32, kMlpHid = 128, kMlpOut = 16;
+constexpr int kMlpIn = 24, kMlpInPad = 32, kMlpHid = 128, kMlpOut = 32;
 // output indices
-constexpr int kOutFace = 0, kOutSide = 6, kOutXPos = 7, kOutXNeg = 8, kOutLogN = 9, kOutLogX2 = 10,
-              kOutYS = 11, kOutYT = 12, kOutMu = 13, kOutAlpha = 14, kOutSpare = 15;
+constexpr int kOutFace = 0, kOutSide = 6, kOutLogN = 7, kOutLogX2 = 8, kOutYS = 9, kOutYT = 10, kOutMu2 = 11,
+              kOutAlpha = 12, kOutXAbs = 16;
 // whole-cell escape record (floats per record) and its columns
 constexpr int kRec = 20;
 constexpr int kRecLT = 0, kRecLA = 1, kRecX = 2, kRecQ0 = 3, kRecLD = 6, kRecN0 = 7, kRecFace = 10, kRecYS = 11,
@@ -60,11 +64,11 @@ constexpr int kPW2 = kPB1 + kMlpHid;                     // W2[128][128]
 constexpr int kPB2 = kPW2 + kMlpHid * kMlpHid;
 constexpr int kPW3 = kPB2 + kMlpHid;
 constexpr int kPB3 = kPW3 + kMlpHid * kMlpHid;
-constexpr int kPW4 = kPB3 + kMlpHid;                     // W4[128][16]
-constexpr int kPB4 = kPW4 + kMlpHid * kMlpOut;           // b4[16]
-constexpr int kNParams = kPB4 + kMlpOut;                 // 38288
-// Normalisation block after the parameters: target mean[16], scale[16] (face
-// logits, side logit and the unused output: 0 and 1), then the calibration of
+constexpr int kPW4 = kPB3 + kMlpHid;                     // W4[128][32]
+constexpr int kPB4 = kPW4 + kMlpHid * kMlpOut;           // b4[32]
+constexpr int kNParams = kPB4 + kMlpOut;                 // 40352
+// Normalisation block after the parameters: target mean[32], scale[32] (face
+// logits, side logit and the unused outputs: 0 and 1), then the calibration of
 // ln E[N_s] (an additive term per bin of log10 tau_c, log10 depth and |x_in|),
 // then the ranges of the training records, where the network may be used:
 // log10 a (min, max), log10 tau_c (min, max), the smallest log10 depth, and
@@ -74,7 +78,7 @@ constexpr int kNormCal = 2 * kMlpOut;
 constexpr int kNormARange = kNormCal + kNCal;
 constexpr int kNormTauRange = kNormARange + 2;
 constexpr int kNormDepthMin = kNormARange + 4;
-constexpr int kNNorm = kNormARange + 8;                  // 296
+constexpr int kNNorm = kNormARange + 8;                  // 328
 
 // The network is asked only for gas-frame |x_in| <= kEscXMax: beyond it the
 // count is a steep mixture of photons that leave at once and photons sent back
@@ -95,20 +99,21 @@ __device__ __forceinline__ int cal_bin(float lt, float ld, float xa) {
 // Packed BF16 A-operand tiles, 16 rows x 32 reduction entries (1 KiB: 64 lanes
 // x 8 bf16; lane l holds row l%16, entries 8(l/16)..8(l/16)+7).
 // Forward (W^T, rows = out-features): L1 8 tiles (inputs 24 padded to 32),
-// L2 32 (8 row tiles x 4 chunks), L3 32, L4 4 (16 outputs x 4 chunks).
+// L2 32 (8 row tiles x 4 chunks), L3 32, L4 8 (2 row tiles of 16 outputs x 4
+// chunks, tile 4 ot + c).
 constexpr int kTileFwdL1 = 0, kTileFwdL2 = 8, kTileFwdL3 = kTileFwdL2 + 32, kTileFwdL4 = kTileFwdL3 + 32,
-              kTilesFwd = kTileFwdL4 + 4;                                                 // 76
-// Backward (W, rows = in-features): L4 8 tiles (16 outputs padded to 32), L3 32, L2 32.
+              kTilesFwd = kTileFwdL4 + 8;                                                 // 80
+// Backward (W, rows = in-features): L4 8 tiles (the 32 outputs are one chunk), L3 32, L2 32.
 constexpr int kTileBwdL4 = kTilesFwd, kTileBwdL3 = kTileBwdL4 + 8, kTileBwdL2 = kTileBwdL3 + 32,
-              kTilesAll = kTileBwdL2 + 32;                                               // 148
+              kTilesAll = kTileBwdL2 + 32;                                               // 152
 constexpr int kTileBytes = 1024;
-// biases as FP32 after the tiles: b1 128, b2 128, b3 128, b4 16
+// biases as FP32 after the tiles: b1 128, b2 128, b3 128, b4 32
 constexpr int kBiasFloats = 3 * kMlpHid + kMlpOut;
 constexpr int kMlpFwdBytes = kTilesFwd * kTileBytes + kBiasFloats * 4 + kNNorm * 4;  // LDS image for inference
 constexpr int kMlpBlobBytes = kTilesAll * kTileBytes + kBiasFloats * 4 + kNNorm * 4;
-static_assert(kMlpIn <= kMlpInPad && kMlpOut == 16, "inputs fill one 32-wide chunk, outputs one tile");
+static_assert(kMlpIn <= kMlpInPad && kMlpOut == 32, "inputs fill one 32-wide chunk, outputs two tiles");
 // training: activation-store rows and the sample splits of the weight-gradient product
-constexpr int kActRowsAll = 32 + 3 * 144 + 3 * kMlpHid + kMlpOut;   // 864
+constexpr int kActRowsAll = 32 + 3 * 144 + 3 * kMlpHid + kMlpOut;   // 880
 constexpr int kGradSplits = 8;
 // raw input row of krt_escape_forward: (log10 tau_c, log10 a, |x_in|, q0, q1,
 // q2, log10 depth, m0, m1, m2, u_a, u_b, u_c, u_d, flag, x_out, face)
@@ -167,85 +172,91 @@ __device__ __forceinline__ v8i16 tileA(const unsigned char *blob, int t, int lan
 }
 
 // Forward pass of one 16-sample block.  xin: this lane's B operand for layer 1
-// (lane l holds inputs 8(l/16)..8(l/16)+7 of sample l%16).  Returns the output
-// tile (lane l: outputs 4(l/16)+r of sample l%16).  If z1..z3 are given, the
-// pre-activations are stored (8 tiles each) for the backward pass.
-// Hidden layers run chunk-major: the 8 weight tiles of reduction chunk c are
-// read from LDS together (the next chunk's reads issued before this chunk's
-// products), then 8 independent MFMA chains advance, so neither LDS latency
-// nor the MFMA result latency of one chain stalls the next product.
-__device__ __forceinline__ v4f32 mlp_forward_block(const unsigned char *tiles, const float *bias, v8i16 xin,
-                                                   int lane, v4f32 *z1, v4f32 *z2, v4f32 *z3) {
+// (lane l holds inputs 8(l/16)..8(l/16)+7 of sample l%16).  Returns the two
+// output tiles: lane l holds outputs 4(l/16)+r (oa) and 16+4(l/16)+r (ob) of
+// sample l%16.  If z1..z3 are given, the pre-activations are stored (8 tiles
+// each) for the backward pass.
+//
+// The 80 products run in one fixed order (fwd_tile): layer 1's 8 row tiles,
+// layers 2 and 3 chunk-major (the 8 row tiles of reduction chunk c, then
+// c + 1, so consecutive products never wait on each other's result), the
+// output layer chunk-major over its 2 row tiles.  Weight tiles stream through
+// a window of 8 registers: product i reads slot i % 8 and the same slot is
+// refilled at once with tile i + 8, so every LDS read is issued 8 products
+// (about 130 cycles of matrix work) before its use and only 8 tiles are live.
+// A layer's epilogue applies SiLU, packs the bf16 activations and loads the
+// next layer's biases into the freed accumulators.
+__host__ __device__ constexpr int fwd_tile(int i) {
+    return i < 8    ? kTileFwdL1 + i
+           : i < 40 ? kTileFwdL2 + ((i - 8) % 8) * 4 + (i - 8) / 8
+           : i < 72 ? kTileFwdL3 + ((i - 40) % 8) * 4 + (i - 40) / 8
+                    : kTileFwdL4 + ((i - 72) % 2) * 4 + (i - 72) / 2;
+}
+constexpr int kFwdSteps = 80;
+static_assert(kTilesFwd == kFwdSteps, "one product per forward tile");
+
+__device__ __forceinline__ v4f32 ld4(const float *p) { return *reinterpret_cast<const v4f32 *>(p); }
+
+__device__ __forceinline__ void mlp_forward_block(const unsigned char *tiles, const float *bias, v8i16 xin,
+                                                  int lane, v4f32 *z1, v4f32 *z2, v4f32 *z3, v4f32 &oa, v4f32 &ob) {
     const int g = lane >> 4;
+    v8i16 w[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) w[i] = tileA(tiles, fwd_tile(i), lane);
+    v4f32 acc[8];
+#pragma unroll
+    for (int mo = 0; mo < 8; ++mo) acc[mo] = ld4(bias + 16 * mo + 4 * g);
     v4i16 h[8];
-    v8i16 wa[8], wb[8];
-    // layer 1: 8 tiles, one chunk (the inputs)
+    // product i (a compile-time index once unrolled) into accumulator c
+#define KRT_FWD_STEP(i, bop, c)                                                         \
+    do {                                                                                \
+        (c) = mfma32(w[(i) % 8], (bop), (c));                                           \
+        if ((i) + 8 < kFwdSteps) {                                                      \
+            w[(i) % 8] = tileA(tiles, fwd_tile((i) + 8), lane);                         \
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                          \
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);                          \
+        } else {                                                                        \
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                          \
+        }                                                                               \
+    } while (0)
+    // layer 1: one chunk (the inputs)
 #pragma unroll
-    for (int mo = 0; mo < 8; ++mo) wa[mo] = tileA(tiles, kTileFwdL1 + mo, lane);
-    // first chunk of layer 2 in flight while layer 1 runs
+    for (int mo = 0; mo < 8; ++mo) KRT_FWD_STEP(mo, xin, acc[mo]);
 #pragma unroll
-    for (int mo = 0; mo < 8; ++mo) wb[mo] = tileA(tiles, kTileFwdL2 + mo * 4, lane);
-    {
-        v4f32 acc[8];
-#pragma unroll
-        for (int mo = 0; mo < 8; ++mo) {
-            const float *b = bias + 16 * mo + 4 * g;
-            acc[mo] = mfma32(wa[mo], xin, (v4f32){b[0], b[1], b[2], b[3]});
-        }
-#pragma unroll
-        for (int mo = 0; mo < 8; ++mo) {
-            if (z1) z1[mo] = acc[mo];
-            h[mo] = pack4(silu(acc[mo].x), silu(acc[mo].y), silu(acc[mo].z), silu(acc[mo].w));
-        }
+    for (int mo = 0; mo < 8; ++mo) {
+        if (z1) z1[mo] = acc[mo];
+        h[mo] = pack4(silu(acc[mo].x), silu(acc[mo].y), silu(acc[mo].z), silu(acc[mo].w));
+        acc[mo] = ld4(bias + kMlpHid + 16 * mo + 4 * g);
     }
-    // layers 2, 3: chunk-major with the next chunk's tiles prefetched; the
-    // current chunk's tiles are always in wb after the swap below
+    // layers 2 and 3
 #pragma unroll
     for (int layer = 0; layer < 2; ++layer) {
-        const int t0 = layer == 0 ? kTileFwdL2 : kTileFwdL3;
-        const float *bl = bias + kMlpHid * (layer + 1);
-        v4f32 acc[8];
-#pragma unroll
-        for (int mo = 0; mo < 8; ++mo) {
-            const float *b = bl + 16 * mo + 4 * g;
-            acc[mo] = (v4f32){b[0], b[1], b[2], b[3]};
-        }
+        const int base = 8 + 32 * layer;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            // prefetch: chunk c + 1 of this layer, or chunk 0 of the next layer
-            // (layer 3), or the output layer's 4 tiles (after layer 3)
-#pragma unroll
-            for (int mo = 0; mo < 8; ++mo) {
-                if (c < 3) wa[mo] = tileA(tiles, t0 + mo * 4 + c + 1, lane);
-                else if (layer == 0) wa[mo] = tileA(tiles, kTileFwdL3 + mo * 4, lane);
-                else if (mo < 4) wa[mo] = tileA(tiles, kTileFwdL4 + mo, lane);
-            }
             const v8i16 bop = cat8(h[2 * c], h[2 * c + 1]);
 #pragma unroll
-            for (int mo = 0; mo < 8; ++mo) acc[mo] = mfma32(wb[mo], bop, acc[mo]);
-#pragma unroll
-            for (int mo = 0; mo < 8; ++mo) wb[mo] = wa[mo];
-            // keep the order: the next chunk's LDS reads, then this chunk's products
-            if (c < 3 || layer == 0) __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
-            else __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+            for (int mo = 0; mo < 8; ++mo) KRT_FWD_STEP(base + 8 * c + mo, bop, acc[mo]);
         }
         v4f32 *zs = layer == 0 ? z2 : z3;
 #pragma unroll
         for (int mo = 0; mo < 8; ++mo) {
             if (zs) zs[mo] = acc[mo];
             h[mo] = pack4(silu(acc[mo].x), silu(acc[mo].y), silu(acc[mo].z), silu(acc[mo].w));
+            if (layer == 0) acc[mo] = ld4(bias + 2 * kMlpHid + 16 * mo + 4 * g);
         }
     }
-    // layer 4: the 4 chunk tiles are in wb[0..3]; four independent partial
-    // sums, added at the end
-    const float *b4 = bias + 3 * kMlpHid + 4 * g;
-    v4f32 o[4];
+    // output layer: two row tiles, biases b4
+    v4f32 o[2] = {ld4(bias + 3 * kMlpHid + 4 * g), ld4(bias + 3 * kMlpHid + 16 + 4 * g)};
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
-        o[c] = mfma32(wb[c], cat8(h[2 * c], h[2 * c + 1]),
-                      c == 0 ? (v4f32){b4[0], b4[1], b4[2], b4[3]} : (v4f32){0.f, 0.f, 0.f, 0.f});
-    return (o[0] + o[1]) + (o[2] + o[3]);
+    for (int c = 0; c < 4; ++c) {
+        const v8i16 bop = cat8(h[2 * c], h[2 * c + 1]);
+#pragma unroll
+        for (int ot = 0; ot < 2; ++ot) KRT_FWD_STEP(72 + 2 * c + ot, bop, o[ot]);
+    }
+#undef KRT_FWD_STEP
+    oa = o[0];
+    ob = o[1];
 }
 
 // ------------------------------------------------------------- inputs ---

@@ -89,10 +89,12 @@ __device__ __forceinline__ int nth_set_lane(uint64_t m, int k) {
 // `ask` (wave-uniform control flow: every lane executes the MFMA).  The asking
 // lanes are packed in rank order into blocks of 16 samples, so a call costs
 // ceil(popcount(ask) / 16) block evaluations.  pk[] holds this lane's inputs
-// as bf16 pairs; an asking lane receives the normalised outputs k >= k_first
-// in out[k] (the others keep their values).
+// as bf16 pairs; an asking lane receives the normalised outputs k set in the
+// wave-uniform `want` (a subset of kMlpFetch) in out[k] (the others keep their
+// values).
+constexpr uint32_t kMlpFetch = 0x003F1FFFu;  // outputs 0-12 and 16-21: all the transport reads
 __device__ __forceinline__ void mlp_eval_wave(const unsigned char *img, const float *bias, const uint32_t pk[12],
-                                              int lane, uint64_t ask, int k_first, float out[kMlpOut]) {
+                                              int lane, uint64_t ask, uint32_t want, float out[kMlpOut]) {
     const int nask = __popcll(ask);
     const int nblk = (nask + 15) >> 4;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -116,14 +118,18 @@ __device__ __forceinline__ void mlp_eval_wave(const unsigned char *img, const fl
                           (short)(use ? w[1] & 0xFFFFu : 0u), (short)(use ? w[1] >> 16 : 0u)};
         const v4i16 hi = {(short)(use ? w[2] & 0xFFFFu : 0u), (short)(use ? w[2] >> 16 : 0u),
                           (short)(use ? w[3] & 0xFFFFu : 0u), (short)(use ? w[3] >> 16 : 0u)};
-        const v4f32 o = mlp_forward_block(img, bias, cat8(lo, hi), lane, nullptr, nullptr, nullptr);
-        // output k of block position p sits in lane 16 (k / 4) + p, component k % 4
+        v4f32 oa, ob;
+        mlp_forward_block(img, bias, cat8(lo, hi), lane, nullptr, nullptr, nullptr, oa, ob);
+        // output k of block position p sits in lane 16 ((k % 16) / 4) + p,
+        // component k % 4, of tile k / 16
         const bool take = mine && (rank >> 4) == b;
 #pragma unroll
         for (int k = 0; k < kMlpOut; ++k) {
+            if (!((kMlpFetch >> k) & 1u) || !((want >> k) & 1u)) continue;  // wave-uniform
+            const v4f32 o = (k < 16) ? oa : ob;
             const float comp = (k % 4 == 0) ? o.x : (k % 4 == 1) ? o.y : (k % 4 == 2) ? o.z : o.w;
-            const float v = __shfl(comp, 16 * (k / 4) + (rank & 15), 64);
-            if (take && k >= k_first) out[k] = v;
+            const float v = __shfl(comp, 16 * ((k % 16) / 4) + (rank & 15), 64);
+            if (take) out[k] = v;
         }
     }
 }
@@ -168,21 +174,28 @@ template <bool kEsc, int kMaxThreads, int kProf = 0>
 __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) {
     extern __shared__ float4 lds4[];
     const float *T = (kProf == 1) ? P.tab : reinterpret_cast<const float *>(lds4);
-    float *sedges = reinterpret_cast<float *>(lds4) + kTabFloats;  // spectrum edges
-    float *cedges = sedges + (kMaxSpecBins + 1);         // channel edges
+    // bin edges after the tables: spectrum then channels; the network variant
+    // reads the spectrum edges (once per escaped packet) from global memory, so
+    // that its LDS holds the tables, the channel edges and the network image
+    constexpr int kLdsSpec = kEsc ? 0 : (kMaxSpecBins + 1);
+    constexpr int kLdsMlp = kTabFloats + kChanEdgeFloats;  // floats before the network image
+    float *ledges = reinterpret_cast<float *>(lds4) + kTabFloats;
+    const float *sedges = kEsc ? P.spec_edges : ledges;  // spectrum edges
+    float *cedges = ledges + kLdsSpec;                    // channel edges
     {
         const float4 *src = reinterpret_cast<const float4 *>(P.tab);
         for (int i = threadIdx.x; i < kTabFloats / 4; i += blockDim.x) lds4[i] = src[i];
-        for (int i = threadIdx.x; i <= P.spec_nb; i += blockDim.x) sedges[i] = P.spec_edges[i];
+        if (!kEsc)
+            for (int i = threadIdx.x; i <= P.spec_nb; i += blockDim.x) ledges[i] = P.spec_edges[i];
         for (int i = threadIdx.x; i <= P.emis_nch; i += blockDim.x) cedges[i] = P.ch_edges[i];
         if (kEsc) {
             const float4 *ms = reinterpret_cast<const float4 *>(P.mlp_img);
-            float4 *md = lds4 + (kTabFloats + kEdgeFloats) / 4;
+            float4 *md = lds4 + kLdsMlp / 4;
             for (int i = threadIdx.x; i < kMlpFwdBytes / 16; i += blockDim.x) md[i] = ms[i];
         }
     }
     __syncthreads();
-    const unsigned char *mimg = reinterpret_cast<const unsigned char *>(lds4 + (kTabFloats + kEdgeFloats) / 4);
+    const unsigned char *mimg = reinterpret_cast<const unsigned char *>(lds4 + kLdsMlp / 4);
     const float *mbias = reinterpret_cast<const float *>(mimg + kTilesFwd * kTileBytes);
     const float *mnorm = mbias + kBiasFloats;
 
@@ -510,7 +523,12 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
             // wave lives only as long as its slowest packet: fewer asking lanes suffice
             const uint64_t wm = __ballot(mlp);
             const int need_lanes = (__ballot(done) != 0ull) ? P.esc_tail_lanes : P.esc_min_lanes;
-            if (__popcll(wm) >= need_lanes) {
+            const bool go = __popcll(wm) >= need_lanes;  // wave-uniform
+            if (!go) mlp = false;
+            // this event's plain scatterings first, so their prepared state is
+            // not live across the network evaluation
+            if (scat && !mlp) commit(q);
+            if (go) {
                 const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
                 const uint4 C = philox(make_uint4(ev, plo, phi, 2u), P.key0, P.key1);
                 const uint4 D = philox(make_uint4(ev, plo, phi, 3u), P.key0, P.key1);
@@ -541,7 +559,7 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
                     if (e == 0) mlp_inputs(cnd, u01(C.x), u01(C.y), u01(D.z), u01(D.w), false, 0.0f, 0, in);
                     else mlp_inputs(cnd, u01(D.x), u01(D.y), u01(D.z), u01(D.w), true, xo, face, in);
                     pack_inputs(in, pk);
-                    mlp_eval_wave(mimg, mbias, pk, lane, wm, e == 0 ? 0 : kOutYS, mo);
+                    mlp_eval_wave(mimg, mbias, pk, lane, wm, e == 0 ? 0x003F01FFu : 0x00001E00u, mo);
                     if (e == 0) {
                         // exit face from the softmax of the logits, at level u01(C.z)
                         float mx = mo[0];
@@ -559,11 +577,17 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
                             if (!found && uf < c2) { face = f; found = true; }
                         }
                         // exit frequency: side from the learned P(x_out >= 0) at level
-                        // u01(C.w), magnitude from that side's quantile at level u_a
+                        // u01(C.w), magnitude from the exit face's quantile at level u_a
                         const bool pos = u01(C.w) < sigmoid_f(mo[kOutSide]);
-                        const int ko = pos ? kOutXPos : kOutXNeg;
-                        const float mag =
-                            fmaxf((pos ? mo[kOutXPos] : mo[kOutXNeg]) * mnorm[kMlpOut + ko] + mnorm[ko], 0.0f);
+                        float ma = mo[kOutXAbs], mm = mnorm[kOutXAbs], ms = mnorm[kMlpOut + kOutXAbs];
+#pragma unroll
+                        for (int f = 1; f < 6; ++f)
+                            if (face == f) {
+                                ma = mo[kOutXAbs + f];
+                                mm = mnorm[kOutXAbs + f];
+                                ms = mnorm[kMlpOut + kOutXAbs + f];
+                            }
+                        const float mag = fmaxf(fmaf(ma, ms, mm), 0.0f);
                         xo = pos ? mag : -mag;
                     }
                 }
@@ -571,9 +595,12 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
                     const float lns = mo[kOutLogN] * mnorm[kMlpOut + kOutLogN] + mnorm[kOutLogN] +
                                       mnorm[kNormCal + cal_bin(ltc, ldep, fabsf(xc))];
                     const float lx2 = mo[kOutLogX2] * mnorm[kMlpOut + kOutLogX2] + mnorm[kOutLogX2];
-                    const float ys = mo[kOutYS] * mnorm[kMlpOut + kOutYS] + mnorm[kOutYS];
-                    const float yt = mo[kOutYT] * mnorm[kMlpOut + kOutYT] + mnorm[kOutYT];
-                    const float mu = fminf(fmaxf(mo[kOutMu] * mnorm[kMlpOut + kOutMu] + mnorm[kOutMu], 1e-3f), 1.0f);
+                    // offsets learned as asinh, the cosine as mu^2
+                    auto sinh_f = [](float v) { const float ev = f_exp(v); return 0.5f * (ev - f_rcp(ev)); };
+                    const float ys = sinh_f(mo[kOutYS] * mnorm[kMlpOut + kOutYS] + mnorm[kOutYS]);
+                    const float yt = sinh_f(mo[kOutYT] * mnorm[kMlpOut + kOutYT] + mnorm[kOutYT]);
+                    const float mu = f_sqrt(
+                        fminf(fmaxf(mo[kOutMu2] * mnorm[kMlpOut + kOutMu2] + mnorm[kOutMu2], 1e-6f), 1.0f));
                     const float al = fminf(fmaxf(mo[kOutAlpha] * mnorm[kMlpOut + kOutAlpha] + mnorm[kOutAlpha], 0.0f),
                                            3.14159265f);
                     // exit point and direction in the reduced frame: face axis k, outward side
@@ -642,15 +669,13 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
                     c_mlp += 1;
                     c_skip += (int64_t)__float2ll_rn(Ns);
                 }
-            } else {
-                mlp = false;
             }
         }
 
         // ---- resonant scattering (event ev), divergent -----------------------
         if (scat) {
             const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
-            if (!mlp) commit(q);
+            if (!kEsc) commit(q);  // the network variant committed above
             // next event
             ev += 1;
             if ((uint64_t)ev > P.max_events) {
@@ -822,10 +847,14 @@ __global__ void debug_upar_kernel(const float *tab, float a, float thd, float x,
 // ---------------------------------------------------------------- launch ---
 hipError_t launch_transport(const RunParams &P, int grid, int block, hipStream_t s) {
     const bool esc = P.mlp_img != nullptr;
-    size_t lds = sizeof(float) * (kTabFloats + kEdgeFloats) + (esc ? (size_t)kMlpFwdBytes : 0);
+    // plain: tables and both edge sets; network: tables, channel edges, image
+    static_assert(sizeof(float) * (kTabFloats + kChanEdgeFloats) + kMlpFwdBytes <= 160 * 1024,
+                  "the network variant's LDS fits one CU (160 KiB)");
+    const size_t lds = esc ? sizeof(float) * (kTabFloats + kChanEdgeFloats) + (size_t)kMlpFwdBytes
+                           : sizeof(float) * (kTabFloats + kEdgeFloats);
     // the network variant is compiled for the block size: up to 512 lanes 256
-    // VGPRs (no spills, 2 waves per SIMD), up to 768 lanes 168 VGPRs (a few
-    // spills, 3 waves; the default), above that 128 (4 waves, heavy spills).
+    // VGPRs (no spills, 2 waves per SIMD; the default), up to 768 lanes 168
+    // VGPRs (spills, 3 waves), above that 128 (4 waves, heavy spills).
     // Profile modes 1 and 2 exist for the plain walk only.
     const int variant = esc ? (block <= 512 ? 2 : (block <= 768 ? 5 : 1))
                             : (P.tclass ? 6 : (P.profile_mode == 1 ? 3 : (P.profile_mode == 2 ? 4 : 0)));

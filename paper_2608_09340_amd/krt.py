@@ -81,7 +81,7 @@ EXPORTS = ["krt_create", "krt_destroy", "krt_last_error", "krt_device_cus", "krt
            "krt_escape_init", "krt_escape_record", "krt_escape_fit_norm", "krt_escape_calibrate", "krt_escape_grad",
            "krt_escape_train", "krt_escape_get_weights", "krt_escape_put_weights", "krt_escape_forward",
            "krt_image", "krt_last_image_ms"]
-ESC_NPARAMS, ESC_NNORM, ESC_NIN, ESC_NOUT, ESC_NCAL, ESC_NREC = 38288, 296, 17, 16, 256, 20
+ESC_NPARAMS, ESC_NNORM, ESC_NIN, ESC_NOUT, ESC_NCAL, ESC_NREC = 40352, 328, 17, 32, 256, 20
 
 _lib = None
 
@@ -210,6 +210,7 @@ class Context:
             d.n_tclass = len(br)
             d.tclass_bratio[:len(br)] = br
         self._keep["grid"] = (k0, vel, eps, emis, tclass, kabs)  # borrowed by the library
+        self.bound = None  # no Transport owns the context's grid until it binds
         self._check(self.L.krt_grid_upload(self.h, C.byref(d)))
 
     def krt_tables_build(self, lines):
@@ -217,6 +218,7 @@ class Context:
         for i, (a, phase) in enumerate(lines):
             arr[i].a = float(a)
             arr[i].phase = int(phase)
+        self.bound = None
         self._check(self.L.krt_tables_build(self.h, arr, len(lines)))
 
     def krt_mc_run(self, n_packets, seed, opts: krt_run_opts, tallies: krt_tallies) -> int:
@@ -276,7 +278,7 @@ class Context:
 
     def krt_escape_forward(self, inp, out):
         """inp: [n][17] raw (log10 tau_c, log10 a, |x_in|, q0, q1, q2, log10 depth, n_in (3), u_a, u_b,
-        u_c, u_d, flag, x_out, face); out: [n][16]."""
+        u_c, u_d, flag, x_out, face); out: [n][32]."""
         if inp.dim() != 2 or inp.shape[1] != ESC_NIN or tuple(out.shape) != (inp.shape[0], ESC_NOUT):
             raise ValueError(f"inp must be [n][{ESC_NIN}] and out [n][{ESC_NOUT}]")
         self._check(self.L.krt_escape_forward(self.h, _ptr(inp), inp.shape[0], _ptr(out)))
@@ -368,13 +370,9 @@ class Transport:
         tcl = g.get("tclass")
         self.tclass = None if tcl is None else torch.from_numpy(
             np.ascontiguousarray(tcl, dtype=np.uint8).reshape(-1)).to(dev)
-        self.ctx.krt_grid_upload(self.n, g["lo"], g["hi"], g["bc"], self.k0, self.vel, self.eps, self.emis_w,
-                                 n_lines=self.n_lines, tclass=self.tclass, tclass_bratio=g.get("tclass_bratio"),
-                                 kabs=self.kabs)
         ln = prob["line"]
-        if lines is None:
-            lines = [(ln["a"], ln.get("phase", 0))]
-        self.ctx.krt_tables_build(lines)
+        self.lines = [(ln["a"], ln.get("phase", 0))] if lines is None else lines
+        self._bind()
         t = prob["tally"]
         self.nsb = int(t["spec_nbins"]) + 2
         self.nch = int(t.get("emis_nch", 0))
@@ -386,6 +384,22 @@ class Transport:
         self.spec = torch.zeros(self.nsb, dtype=torch.float32, device=dev)
         self.emis = torch.zeros(self.ncell * self.nch, dtype=torch.float32, device=dev) if self.nch > 0 else None
         self.jbar = torch.zeros(self.ncell, dtype=torch.float32, device=dev) if self.jbar_raw is not None else None
+
+    def _bind(self):
+        """Upload this workload's grid (borrowed device fields) and build its
+        line tables in the context; a context holds one grid at a time, so a
+        Transport whose context has since taken another grid binds again
+        before its next call."""
+        g = self.prob["grid"]
+        self.ctx.krt_grid_upload(self.n, g["lo"], g["hi"], g["bc"], self.k0, self.vel, self.eps, self.emis_w,
+                                 n_lines=self.n_lines, tclass=self.tclass, tclass_bratio=g.get("tclass_bratio"),
+                                 kabs=self.kabs)
+        self.ctx.krt_tables_build(self.lines)
+        self.ctx.bound = self
+
+    def _ensure_bound(self):
+        if getattr(self.ctx, "bound", None) is not self:
+            self._bind()
 
     def tallies(self, packet_log=None) -> krt_tallies:
         t = krt_tallies()
@@ -404,6 +418,7 @@ class Transport:
         (its FP32 finalised form), with an optional emission source function
         src [ncell][nch] and grey absorption coefficient kabs [ncell] (device
         FP32); returns a [npix][nch] device tensor."""
+        self._ensure_bound()
         t = self.prob["tally"]
         nx, ny, nz = self.n
         npix = {0: ny * nz, 1: nx * nz, 2: nx * ny}[axis % 3]
@@ -421,6 +436,7 @@ class Transport:
     def run(self, n_packets: int, seed: int = 0, packet_log: bool = False, **kw) -> dict:
         """One krt_mc_run over this workload; returns the
         raw tallies and counters on the host."""
+        self._ensure_bound()
         opts = make_opts(self.prob, **kw)
         plog = None
         if packet_log:

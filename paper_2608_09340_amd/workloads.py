@@ -60,10 +60,13 @@ def slab(tau0=1e3, a=1e-2, nz=32, *, spec=(200, -30.0, 30.0), phase=PHASE_ISO, n
 
 
 def dusty_slab(tau0=1e5, a=0.015, tau_a=0.03, nz=64, nxy=1, spec=(200, -60.0, 60.0)):
-    """Static slab |z| <= 1, periodic in x and y, line-centre depth tau0 and grey
-    (dust) absorption depth tau_a from midplane to face, plane source at z = 0
-    emitting x = 0 photons isotropically (the dusty-slab setup of Sec. 3.2)."""
-    p = slab(tau0, a, nz, spec=spec, nxy=nxy)
+    """Static slab |z| <= 1, periodic in x and y, grey (dust) absorption depth
+    tau_a from midplane to face, plane source at z = 0 emitting x = 0 photons
+    isotropically (the dusty-slab setup of Sec. 3.2).  tau0 is the depth in the
+    convention of the analytic escape fraction (Neufeld's), the mean depth
+    sqrt(pi) k0 of the normalised profile, as for the paper's other slab
+    depths in Sec. 3; the line-centre opacity is k0 = tau0 / sqrt(pi)."""
+    p = slab(tau0 / np.sqrt(np.pi), a, nz, spec=spec, nxy=nxy)
     p["grid"]["kabs"] = np.full(nxy * nxy * nz, tau_a, dtype=np.float32)
     return p
 

@@ -36,10 +36,10 @@ def _rand_params(seed):
     return mlp.pack(d)
 
 
-# target normalisation (mean[16], scale[16]) for the synthetic checks; the face
-# logits, side logit and spare keep 0 / 1
-NORM = np.concatenate([[0, 0, 0, 0, 0, 0, 0, 2.4, 2.2, 5.0, 0.1, 0.0, 0.0, 0.6, 0.9, 0],
-                       [1, 1, 1, 1, 1, 1, 1, 1.4, 1.3, 2.0, 1.0, 0.8, 0.8, 0.25, 0.5, 1]])
+# target normalisation (mean[32], scale[32]) for the synthetic checks; the face
+# logits, side logit and unused outputs keep 0 / 1
+NORM = np.concatenate([[0, 0, 0, 0, 0, 0, 0, 5.0, 0.1, 0.0, 0.0, 0.5, 0.9, 0, 0, 0] + [2.4] * 6 + [0] * 10,
+                       [1, 1, 1, 1, 1, 1, 1, 2.0, 1.0, 0.8, 0.8, 0.3, 0.5, 1, 1, 1] + [1.4] * 6 + [1] * 10])
 
 
 def _records(rng, n):
@@ -101,7 +101,7 @@ def test_mfma_gradient_vs_fp64(gpu_ctx):
     conditional rows (a batch of 1000: a ragged last block of 32 samples),
     each output at its own quantile level: cosine >= 0.999 and relative L2
     <= 2e-2 per tensor against the bfloat16 emulation, loss within 1%; the
-    unused output's column gets no gradient."""
+    unused outputs' columns get no gradient."""
     import torch
     p = _rand_params(5)
     _put(gpu_ctx, p, NORM)
@@ -130,9 +130,10 @@ def test_mfma_gradient_vs_fp64(gpu_ctx):
             a, b = g[o:o + k], g_ref[o:o + k]
             o += k
             if name in ("W4", "b4"):
-                assert np.all(a.reshape(-1, NO)[:, mlp.O_SPARE] == 0.0)
-                a = a.reshape(-1, NO)[:, :mlp.O_SPARE].reshape(-1)
-                b = b.reshape(-1, NO)[:, :mlp.O_SPARE].reshape(-1)
+                unused = list(mlp.UNUSED)
+                assert np.all(a.reshape(-1, NO)[:, unused] == 0.0)
+                a = np.delete(a.reshape(-1, NO), unused, axis=1).reshape(-1)
+                b = np.delete(b.reshape(-1, NO), unused, axis=1).reshape(-1)
             cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-30)
             rel = np.linalg.norm(a - b) / (np.linalg.norm(b) + 1e-30)
             assert cos >= (0.999 if bf else 0.995) and rel <= (2e-2 if bf else 6e-2), (bf, name, cos, rel)
@@ -265,9 +266,10 @@ def test_calibration_unbiased_per_bin(gpu_ctx, trained):
 
 def _learned_samples(ctx, n, lt, xin, q, nin, rng):
     """The network's samples at a fixed condition, drawn as the transport draws
-    them: marginal evaluation (face from the softmax, side, one-sided
+    them: marginal evaluation (face from the softmax, side, the sampled face's
     magnitude at u_a), then the conditional evaluation at the sampled face and
-    exit frequency.  Returns face, x_out, ys, yt, mu, alpha and ln E[N_s]."""
+    exit frequency (offsets through sinh, the cosine through the square root).
+    Returns face, x_out, ys, yt, mu, alpha and ln E[N_s]."""
     import torch
     cond = np.zeros((n, 20))
     cond[:, mlp.R_LT] = lt
@@ -289,13 +291,14 @@ def _learned_samples(ctx, n, lt, xin, q, nin, rng):
     pf /= pf.sum(axis=1, keepdims=True)
     face = (rng.uniform(0, 1, n)[:, None] > np.cumsum(pf, axis=1)).sum(axis=1).clip(0, 5)
     pos = rng.uniform(0, 1, n) < 1.0 / (1.0 + np.exp(-m[:, mlp.O_SIDE]))
-    xo = np.where(pos, np.maximum(m[:, mlp.O_XPOS], 0.0), -np.maximum(m[:, mlp.O_XNEG], 0.0))
+    mag = np.maximum(m[np.arange(n), mlp.O_XABS + face], 0.0)
+    xo = np.where(pos, mag, -mag)
     cond[:, mlp.R_FACE] = face
     cond[:, mlp.R_XOUT] = xo
     u2 = rng.uniform(0, 1, (n, 4))
     ctx.krt_escape_forward(torch.from_numpy(_raw_rows(cond, u2, np.ones(n, bool)).astype(np.float32)).cuda(), out)
     m2 = out.cpu().numpy().astype(np.float64)
-    return (face, xo, m2[:, mlp.O_YS], m2[:, mlp.O_YT], np.clip(m2[:, mlp.O_MU], 1e-3, 1.0),
+    return (face, xo, np.sinh(m2[:, mlp.O_YS]), np.sinh(m2[:, mlp.O_YT]), np.sqrt(np.clip(m2[:, mlp.O_MU2], 1e-6, 1.0)),
             np.clip(m2[:, mlp.O_ALPHA], 0.0, np.pi), m[:, mlp.O_LOGN])
 
 

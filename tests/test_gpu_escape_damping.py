@@ -70,7 +70,8 @@ def test_samples_vs_plain_across_damping(gpu_ctx, trained_range, line, a, tau, x
     pf /= pf.sum(axis=1, keepdims=True)
     face = (rng.uniform(0, 1, n)[:, None] > np.cumsum(pf, axis=1)).sum(axis=1).clip(0, 5)
     pos = rng.uniform(0, 1, n) < 1.0 / (1.0 + np.exp(-m[:, mlp.O_SIDE]))
-    xo = np.where(pos, np.maximum(m[:, mlp.O_XPOS], 0.0), -np.maximum(m[:, mlp.O_XNEG], 0.0))
+    mag = np.maximum(m[np.arange(n), mlp.O_XABS + face], 0.0)
+    xo = np.where(pos, mag, -mag)
     cond[:, mlp.R_FACE] = face
     cond[:, mlp.R_XOUT] = xo
     m2 = fwd(cond, 1.0)
@@ -79,9 +80,10 @@ def test_samples_vs_plain_across_damping(gpu_ctx, trained_range, line, a, tau, x
     top = int(np.argmax(fp))
     mp, ml_ = plain[:, mlp.R_FACE] == top, face == top
     ks = {"x_out": stats.ks_2samp(xo, plain[:, mlp.R_XOUT]).statistic}
-    for name, k, col in (("ys", mlp.O_YS, mlp.R_YS), ("yt", mlp.O_YT, mlp.R_YT), ("mu", mlp.O_MU, mlp.R_MU),
-                         ("alpha", mlp.O_ALPHA, mlp.R_ALPHA)):
-        ks[name] = stats.ks_2samp(m2[ml_, k], plain[mp, col]).statistic
+    back = {"ys": np.sinh(m2[:, mlp.O_YS]), "yt": np.sinh(m2[:, mlp.O_YT]),
+            "mu": np.sqrt(np.clip(m2[:, mlp.O_MU2], 1e-6, 1.0)), "alpha": m2[:, mlp.O_ALPHA]}
+    for name, col in (("ys", mlp.R_YS), ("yt", mlp.R_YT), ("mu", mlp.R_MU), ("alpha", mlp.R_ALPHA)):
+        ks[name] = stats.ks_2samp(back[name][ml_], plain[mp, col]).statistic
     ln_mean = np.log(np.mean(np.exp(plain[:, mlp.R_LOGN])))
     print(f"a={a:g} tau_c={tau:g} x_in={xin}: face TV {tv:.4f} KS " + " ".join(f"{k} {v:.4f}" for k, v in ks.items())
           + f"; ln E[N_s] learned {m[:, mlp.O_LOGN].mean():.4f} plain {ln_mean:.4f}")

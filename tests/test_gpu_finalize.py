@@ -38,7 +38,9 @@ def test_finalised_outputs_equal_oracle_normalisation(gpu_ctx, lum, norm):
         w32 = want.astype(np.float32).astype(np.float64)
         ulp = np.spacing(np.abs(w32).astype(np.float32)).astype(np.float64)
         assert np.all(np.abs(g - w32) <= ulp), (name, np.max(np.abs(g - w32) / np.maximum(ulp, 1e-300)))
-        assert np.count_nonzero(want) > 0.3 * want.size, name
+        # not a vacuous comparison: the sphere fills half the grid, and its
+        # outer cells' far channels stay empty at this packet count
+        assert np.count_nonzero(want) > (0.15 if name == "emis" else 0.3) * want.size, name
 
 
 @pytest.mark.parametrize("profile,a", [(W.PROF_VOIGT, 1e-2), (W.PROF_VOIGT, 4.7e-4), (W.PROF_GAUSS, 4.73e-3)])

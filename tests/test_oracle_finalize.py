@@ -155,9 +155,10 @@ def test_finalize_emissivity_of_thin_beam_slab_absolute():
 # ------------------------------------------------- dust absorption (Sec. 3.2) --
 @pytest.mark.parametrize("tau_a", [0.01, 0.05])
 def test_dusty_slab_escape_fraction(tau_a):
-    """Sec. 3.2, the dusty slab: a static slab of line-centre depth tau0 = 1e5
-    (a = 0.015) with grey absorption depth tau_a, photons emitted at line
-    centre from the midplane.  The escaped fraction follows the analytic
+    """Sec. 3.2, the dusty slab: a static slab of depth tau0 = 1e5 in the
+    analytic solution's convention (the mean depth sqrt(pi) times the
+    line-centre depth; a = 0.015) with grey absorption depth tau_a, photons
+    emitted at line centre from the midplane.  The escaped fraction follows the analytic
     solution of Neufeld (1990) in the form of Verhamme, Schaerer & Maselli
     (2006), f_esc = 1 / cosh(sqrt(3) / (zeta pi^(5/12)) sqrt((a tau0)^(1/3)
     tau_a)) with zeta = 0.525, within the 12% the paper reports for its own

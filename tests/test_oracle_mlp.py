@@ -52,9 +52,10 @@ def test_backward_matches_finite_differences():
     s9 = 1.7
     _, g = mlp.loss_and_grad(p, X, Y, U, s9=s9)
     rng = np.random.default_rng(1)
+    used = np.array(sorted(mlp.MARGINAL + mlp.CONDITIONAL))
     idx = np.concatenate([rng.choice(mlp.NPARAMS, 200, replace=False),
-                          mlp.NPARAMS - mlp.NOUT + np.arange(mlp.NOUT - 1)])  # every output bias but the unused
-    h = 1e-6
+                          mlp.NPARAMS - mlp.NOUT + used])  # every used output's bias
+    h = 1e-6  # a pinball kink inside a difference shifts it by a few 1e-5 (relative)
     fd = []
     for i in idx:
         pp, pm = p.copy(), p.copy()
@@ -62,7 +63,7 @@ def test_backward_matches_finite_differences():
         pm[i] -= h
         fd.append((mlp.loss_and_grad(pp, X, Y, U, s9=s9)[0] - mlp.loss_and_grad(pm, X, Y, U, s9=s9)[0]) / (2 * h))
     fd = np.array(fd)
-    assert np.allclose(g[idx], fd, rtol=1e-5, atol=1e-9)
+    assert np.allclose(g[idx], fd, rtol=1e-4, atol=1e-9)
 
 
 def test_pinball_quantile_property():
@@ -122,17 +123,22 @@ def test_raw_targets_masks():
     rng = np.random.default_rng(7)
     rec = _records(rng, 4)
     rec[:, mlp.R_XOUT] = [1.5, -2.0, 0.0, 0.7]
+    rec[:, mlp.R_FACE] = [3, 0, 5, 2]
+    rec[3, mlp.R_YS:mlp.R_ALPHA + 1] = [-2.0, 0.5, 0.6, 1.2]
     cond = np.array([False, False, False, True])
     y = mlp.raw_targets(rec, cond)
-    assert y[0, mlp.O_XPOS] == 1.5 and np.isnan(y[0, mlp.O_XNEG]) and y[0, mlp.O_SIDE] == 1
-    assert np.isnan(y[1, mlp.O_XPOS]) and y[1, mlp.O_XNEG] == 2.0 and y[1, mlp.O_SIDE] == 0
-    assert y[2, mlp.O_XPOS] == 0.0 and y[2, mlp.O_SIDE] == 1
+    # |x_out| only in the exit face's column, the side label from its sign
+    for i, (f, ax, b) in enumerate(((3, 1.5, 1), (0, 2.0, 0), (5, 0.0, 1))):
+        xa = y[i, list(mlp.XABS)]
+        assert xa[f] == ax and np.isnan(np.delete(xa, f)).all() and y[i, mlp.O_SIDE] == b
     assert np.all(y[:3, 0] == rec[:3, mlp.R_FACE])
     assert np.all(y[:3, [mlp.O_LOGN, mlp.O_LOGX2]] == rec[:3][:, [mlp.R_LOGN, mlp.R_LOGX2]])
-    # marginal rows carry no conditional targets, conditional rows only those
-    assert np.all(np.isnan(y[:3, list(mlp.CONDITIONAL) + [mlp.O_SPARE]]))
-    assert np.all(y[3, list(mlp.CONDITIONAL)] == rec[3, mlp.R_YS:mlp.R_ALPHA + 1])
+    # marginal rows carry no conditional targets, conditional rows only those;
+    # unused outputs none
+    assert np.all(np.isnan(y[:3, list(mlp.CONDITIONAL) + list(mlp.UNUSED)]))
+    assert np.allclose(y[3, list(mlp.CONDITIONAL)], [np.arcsinh(-2.0), np.arcsinh(0.5), 0.36, 1.2])
     assert np.all(np.isnan(np.delete(y[3], list(mlp.CONDITIONAL))))
+    assert len(mlp.UNUSED) == mlp.NOUT - 6 - 3 - 6 - 4
 
 
 def test_levels_and_inputs_by_row_kind():
@@ -146,9 +152,9 @@ def test_levels_and_inputs_by_row_kind():
     cond = np.array([False, True])
     u = np.array([[0.1, 0.2, 0.3, 0.4], [0.5, 0.6, 0.7, 0.8]])
     U = mlp.levels(u, cond)
-    assert U[0, mlp.O_XPOS] == U[0, mlp.O_XNEG] == 0.1 and U[0, mlp.O_LOGX2] == 0.2
-    assert np.isnan(U[0, mlp.O_YS]) and np.isnan(U[1, mlp.O_XPOS])
-    assert (U[1, mlp.O_YS], U[1, mlp.O_YT], U[1, mlp.O_MU], U[1, mlp.O_ALPHA]) == (0.5, 0.6, 0.7, 0.8)
+    assert np.all(U[0, list(mlp.XABS)] == 0.1) and U[0, mlp.O_LOGX2] == 0.2
+    assert np.isnan(U[0, mlp.O_YS]) and np.isnan(U[1, list(mlp.XABS)]).all()
+    assert (U[1, mlp.O_YS], U[1, mlp.O_YT], U[1, mlp.O_MU2], U[1, mlp.O_ALPHA]) == (0.5, 0.6, 0.7, 0.8)
     X = mlp.inputs(rec, u, cond)
     assert np.allclose(X[:, [0, 2, 6]], 0.0)
     assert np.all(X[0, 14:] == 0.0)
