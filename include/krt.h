@@ -213,6 +213,21 @@ typedef struct {
 int krt_mc_run(krt_ctx *ctx, uint64_t n_packets, uint64_t seed, const krt_run_opts *opts,
                krt_tallies *tallies);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * pass as krt_mc_run, identical tallies, calling no hipMalloc, hipFree or
+ * allocating library routine.  Its scratch -- the packet-pool counter and the
+ * staged bin edges -- lives in one 8 KiB array per GPU inside the library
+ * (held until the process ends), the edges are staged through a pinned block
+ * allocated by krt_create; inputs and outputs are the caller's, as for
+ * krt_mc_run.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (other contexts or streams) race and must not run
+ * concurrently.  Limits: at most 1024 spectrum bins and 256 channels (the
+ * scratch's capacity; larger requests return KRT_EINVAL); temperature classes
+ * are refused (KRT_EINVAL: their tables are built on first use by krt_mc_run). */
+int krt_mc_run_noalloc(krt_ctx *ctx, uint64_t n_packets, uint64_t seed, const krt_run_opts *opts,
+                       krt_tallies *tallies);
+
 /* -------------------------------------------------------------- imaging --- */
 /* Deterministic ray-tracing imaging pass (Sec. 2.2.2, eq. imaging-formal,
  * eq. imaging-alphas): along lines of sight parallel to a

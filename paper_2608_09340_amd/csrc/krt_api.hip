@@ -43,6 +43,8 @@ struct krt_ctx {
     double *level_consts = nullptr;
     double *level_power = nullptr;   // per-line partial and total powers of krt_levels_update
     int64_t *host_pinned = nullptr;
+    float *host_edges = nullptr;          // pinned staging of the bin edges for krt_mc_run_noalloc
+    unsigned char *scratch_dev = nullptr; // this device's address of the no-allocation scratch array
     hipEvent_t ev0 = nullptr, ev1 = nullptr;   // bracket the last transport launch
     float last_ms = 0.0f;
     // learned escape: FP32 master parameters, Adam moments, gradient, packed BF16 image
@@ -160,6 +162,16 @@ void fill_edges(float *e, int nb, double lo, double hi) {
 }  // namespace
 
 // ------------------------------------------------------------------ ctx ---
+// Scratch of krt_mc_run_noalloc, one copy per GPU in the library's code object:
+// the packet-pool counter (first 256 bytes), then the binary32 bin edges of the
+// spectrum and the channels staged for the transport kernel.  Host code never
+// passes the array's name to a kernel: each context resolves this device's
+// address with hipGetSymbolAddress at creation (scratch_dev).
+constexpr size_t kNoAllocScratchBytes = 8192;
+constexpr size_t kNoAllocEdgeOffset = 256;
+static_assert(kNoAllocEdgeOffset + sizeof(float) * kEdgeFloats <= kNoAllocScratchBytes, "edges fit the scratch");
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 extern "C" int krt_create(krt_ctx **out, int hip_device, void *hip_stream) {
     if (!out) return KRT_EINVAL;
     *out = nullptr;
@@ -176,7 +188,14 @@ extern "C" int krt_create(krt_ctx **out, int hip_device, void *hip_stream) {
         hipMalloc(&c->level_consts, sizeof(double) * 256) != hipSuccess ||
         hipHostMalloc(&c->host_pinned, sizeof(int64_t) * 64, hipHostMallocDefault) != hipSuccess ||
         hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
-        hipMalloc(&c->edges, sizeof(float) * kEdgeFloats) != hipSuccess) {
+        hipMalloc(&c->edges, sizeof(float) * kEdgeFloats) != hipSuccess ||
+        hipHostMalloc(&c->host_edges, sizeof(float) * kEdgeFloats, hipHostMallocDefault) != hipSuccess) {
+        krt_destroy(c);
+        return KRT_EHIP;
+    }
+    // this device's copy of the no-allocation scratch (the device is current)
+    if (hipGetSymbolAddress(reinterpret_cast<void **>(&c->scratch_dev), HIP_SYMBOL(scratch)) != hipSuccess ||
+        c->scratch_dev == nullptr) {
         krt_destroy(c);
         return KRT_EHIP;
     }
@@ -196,6 +215,7 @@ extern "C" void krt_destroy(krt_ctx *c) {
     if (c->level_consts) (void)hipFree(c->level_consts);
     if (c->level_power) (void)hipFree(c->level_power);
     if (c->host_pinned) (void)hipHostFree(c->host_pinned);
+    if (c->host_edges) (void)hipHostFree(c->host_edges);
     for (void *p : {(void *)c->mlp_p, (void *)c->mlp_m, (void *)c->mlp_v, (void *)c->mlp_g, (void *)c->mlp_norm,
                     (void *)c->mlp_loss, (void *)c->mlp_u, (void *)c->mlp_idx, (void *)c->mlp_blob,
                     (void *)c->mlp_img, (void *)c->mlp_calsum, (void *)c->mlp_part, (void *)c->mlp_act})
@@ -313,7 +333,13 @@ static double voigt_crossing(double a) {
     return 0.5 * (lo + hi);
 }
 
-static int mc_run_impl(krt_ctx *c, uint64_t n_packets, uint64_t seed, const krt_run_opts *o, krt_tallies *t) {
+// krt_mc_run and krt_mc_run_noalloc: with noalloc the packet-pool counter and
+// the bin edges live in the per-device scratch array and the edges are staged
+// through a pinned block allocated at context creation, so the call allocates
+// nothing (temperature classes, whose tables are built on first use, are
+// refused).
+static int mc_run_impl(krt_ctx *c, uint64_t n_packets, uint64_t seed, const krt_run_opts *o, krt_tallies *t,
+                       bool noalloc) {
     if (!c) return KRT_EINVAL;
     if (!o || !t) return fail(c, KRT_EINVAL, "opts / tallies NULL");
     if (!c->have_grid) return fail(c, KRT_ESTATE, "no grid uploaded");
@@ -395,8 +421,11 @@ static int mc_run_impl(krt_ctx *c, uint64_t n_packets, uint64_t seed, const krt_
         if (o->emis_nch > 0) HIPCHK(c, launch_zero_i64(t->emis_raw_dev, nc * o->emis_nch, c->stream));
         if (o->jbar) HIPCHK(c, launch_zero_i64(t->jbar_raw_dev, nc, c->stream));
     }
-    unsigned long long *counter = c->work_counter;
-    float *edges = c->edges;
+    if (noalloc && c->grid.tclass_dev)
+        return fail(c, KRT_EINVAL, "krt_mc_run_noalloc: temperature classes build their tables on first use; "
+                                   "use krt_mc_run");
+    unsigned long long *counter = noalloc ? reinterpret_cast<unsigned long long *>(c->scratch_dev) : c->work_counter;
+    float *edges = noalloc ? reinterpret_cast<float *>(c->scratch_dev + kNoAllocEdgeOffset) : c->edges;
     HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(counter), 1, c->stream));
 
     RunParams P;
@@ -427,10 +456,19 @@ static int mc_run_impl(krt_ctx *c, uint64_t n_packets, uint64_t seed, const krt_
     P.source = o->source;
     P.src_profile = o->src_profile;
     P.src_x0 = (float)o->src_x0;
-    std::vector<float> e(kEdgeFloats, 0.0f);
-    fill_edges(e.data(), o->spec_nbins, o->spec_lo, o->spec_hi);
-    if (o->emis_nch > 0) fill_edges(e.data() + kMaxSpecBins + 1, o->emis_nch, o->ch_lo, o->ch_hi);
-    HIPCHK(c, hipMemcpyAsync(edges, e.data(), sizeof(float) * kEdgeFloats, hipMemcpyHostToDevice, c->stream));
+    if (noalloc) {
+        // the pinned block is reused only after this call's stream synchronisation
+        float *e = c->host_edges;
+        for (int k = 0; k < kEdgeFloats; ++k) e[k] = 0.0f;
+        fill_edges(e, o->spec_nbins, o->spec_lo, o->spec_hi);
+        if (o->emis_nch > 0) fill_edges(e + kMaxSpecBins + 1, o->emis_nch, o->ch_lo, o->ch_hi);
+        HIPCHK(c, hipMemcpyAsync(edges, e, sizeof(float) * kEdgeFloats, hipMemcpyHostToDevice, c->stream));
+    } else {
+        std::vector<float> e(kEdgeFloats, 0.0f);
+        fill_edges(e.data(), o->spec_nbins, o->spec_lo, o->spec_hi);
+        if (o->emis_nch > 0) fill_edges(e.data() + kMaxSpecBins + 1, o->emis_nch, o->ch_lo, o->ch_hi);
+        HIPCHK(c, hipMemcpyAsync(edges, e.data(), sizeof(float) * kEdgeFloats, hipMemcpyHostToDevice, c->stream));
+    }
     P.spec_nb = o->spec_nbins;
     P.spec_inv_w = (float)(o->spec_nbins / (o->spec_hi - o->spec_lo));
     P.spec_edges = edges;
@@ -513,7 +551,15 @@ static int mc_run_impl(krt_ctx *c, uint64_t n_packets, uint64_t seed, const krt_
 
 extern "C" int krt_mc_run(krt_ctx *c, uint64_t n_packets, uint64_t seed, const krt_run_opts *o,
                           krt_tallies *t) {
-    return mc_run_impl(c, n_packets, seed, o, t);
+    return mc_run_impl(c, n_packets, seed, o, t, false);
+}
+
+extern "C" int krt_mc_run_noalloc(krt_ctx *c, uint64_t n_packets, uint64_t seed, const krt_run_opts *o,
+                                  krt_tallies *t) {
+    if (o && (o->spec_nbins > kMaxSpecBins || o->emis_nch > kMaxChannels))
+        return fail(c, KRT_EINVAL, "krt_mc_run_noalloc: the %zu-byte scratch holds at most %d spectrum bins and %d "
+                                   "channels", kNoAllocScratchBytes, kMaxSpecBins, kMaxChannels);
+    return mc_run_impl(c, n_packets, seed, o, t, true);
 }
 
 // -------------------------------------------------------------- imaging ---

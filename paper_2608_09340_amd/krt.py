@@ -76,7 +76,7 @@ class krt_image_desc(C.Structure):
 
 EXPORTS = ["krt_create", "krt_destroy", "krt_last_error", "krt_device_cus", "krt_last_transport_ms",
            "krt_grid_upload",
-           "krt_tables_build", "krt_mc_run", "krt_levels_update", "krt_debug_philox",
+           "krt_tables_build", "krt_mc_run", "krt_mc_run_noalloc", "krt_levels_update", "krt_debug_philox",
            "krt_debug_bins", "krt_debug_voigt", "krt_debug_voigt_analytic", "krt_debug_upar",
            "krt_escape_init", "krt_escape_record", "krt_escape_fit_norm", "krt_escape_calibrate", "krt_escape_grad",
            "krt_escape_train", "krt_escape_get_weights", "krt_escape_put_weights", "krt_escape_forward",
@@ -108,6 +108,7 @@ def load(path: str = LIB_PATH):
     L.krt_grid_upload.argtypes = [p, C.POINTER(krt_grid_desc)]
     L.krt_tables_build.argtypes = [p, C.POINTER(krt_line_desc), C.c_int]
     L.krt_mc_run.argtypes = [p, u64, u64, C.POINTER(krt_run_opts), C.POINTER(krt_tallies)]
+    L.krt_mc_run_noalloc.argtypes = [p, u64, u64, C.POINTER(krt_run_opts), C.POINTER(krt_tallies)]
     L.krt_levels_update.argtypes = [p, C.POINTER(krt_levels_desc), p]
     L.krt_debug_philox.argtypes = [p, p, p, p, i64]
     L.krt_debug_bins.argtypes = [p, p, i64, i32, C.c_double, C.c_double, p]
@@ -126,7 +127,7 @@ def load(path: str = LIB_PATH):
     L.krt_image.argtypes = [p, C.POINTER(krt_image_desc)]
     L.krt_last_image_ms.argtypes = [p]
     L.krt_last_image_ms.restype = C.c_float
-    for name in ["krt_grid_upload", "krt_tables_build", "krt_mc_run", "krt_levels_update",
+    for name in ["krt_grid_upload", "krt_tables_build", "krt_mc_run", "krt_mc_run_noalloc", "krt_levels_update",
                  "krt_debug_philox", "krt_debug_bins", "krt_debug_voigt", "krt_debug_voigt_analytic", "krt_debug_upar",
                  "krt_escape_init", "krt_escape_record", "krt_escape_fit_norm", "krt_escape_calibrate",
                  "krt_escape_grad",
@@ -223,6 +224,12 @@ class Context:
 
     def krt_mc_run(self, n_packets, seed, opts: krt_run_opts, tallies: krt_tallies) -> int:
         rc = self.L.krt_mc_run(self.h, int(n_packets), int(seed), C.byref(opts), C.byref(tallies))
+        if rc not in (0, KRT_EDEVICE):
+            self._check(rc)
+        return rc
+
+    def krt_mc_run_noalloc(self, n_packets, seed, opts: krt_run_opts, tallies: krt_tallies) -> int:
+        rc = self.L.krt_mc_run_noalloc(self.h, int(n_packets), int(seed), C.byref(opts), C.byref(tallies))
         if rc not in (0, KRT_EDEVICE):
             self._check(rc)
         return rc
@@ -433,15 +440,16 @@ class Transport:
         self.ctx.krt_image(d)
         return out
 
-    def run(self, n_packets: int, seed: int = 0, packet_log: bool = False, **kw) -> dict:
-        """One krt_mc_run over this workload; returns the
+    def run(self, n_packets: int, seed: int = 0, packet_log: bool = False, noalloc: bool = False, **kw) -> dict:
+        """One krt_mc_run (or krt_mc_run_noalloc) over this workload; returns the
         raw tallies and counters on the host."""
         self._ensure_bound()
         opts = make_opts(self.prob, **kw)
         plog = None
         if packet_log:
             plog = self.torch.zeros((n_packets, 8), dtype=self.torch.float32, device=self.dev)
-        rc = self.ctx.krt_mc_run(n_packets, seed, opts, self.tallies(plog))
+        call = self.ctx.krt_mc_run_noalloc if noalloc else self.ctx.krt_mc_run
+        rc = call(n_packets, seed, opts, self.tallies(plog))
         out = {"rc": rc, "spec_raw": self.spec_raw.cpu().numpy().copy(),
                "counters": dict(zip(COUNTER_NAMES, self.counters.cpu().numpy()[:len(COUNTER_NAMES)].tolist()))}
         if self.emis_raw is not None:
