@@ -170,12 +170,13 @@ def headline_c4(ctx, args):
     import numpy as np
     import torch
     from paper_2608_09340_amd import krt, workloads as W
-    from paper_2608_09340_amd.escape import train_escape, DEFAULT_RUN, DEFAULT_LOG10_TAU
+    from paper_2608_09340_amd.escape import train_escape, DEFAULT_RUN, DEFAULT_LOG10_TAU, DEFAULT_STAGES
     N = args.packets
     prob = W.cloud_c4(n=128)
     t0 = time.perf_counter()
     krt.Transport(W.slab(10.0, 1e-3, 4), ctx=ctx)  # line tables for a = 1e-3
-    tr = train_escape(ctx, 0, seed=1, log10_tau=DEFAULT_LOG10_TAU)
+    stages = tuple((max(1, int(round(st * args.train_scale))), b, lr) for st, b, lr in DEFAULT_STAGES)
+    tr = train_escape(ctx, 0, seed=1, log10_tau=DEFAULT_LOG10_TAU, stages=stages)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     hist = tr["hist"]
@@ -433,6 +434,8 @@ def main():
                     help="no timed step is started that would end past this many seconds of timed work")
     ap.add_argument("--warmup-budget-s", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--train-scale", type=float, default=1.0,
+                    help="scales the training steps (counter-collection runs, where every dispatch is slow)")
     ap.add_argument("--legs", default="", help="comma-separated extra legs run after the headline line: "
                                                + ",".join(LEGS))
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -482,6 +485,7 @@ def main():
                    "packets_per_step": args.packets, "grid": [128, 128, 128], "seed": 0,
                    "network": "BF16 weights and activations, FP32 accumulation on MFMA",
                    "steps_requested": args.steps, "warmup_requested": args.warmup,
+                   "train_scale": args.train_scale,
                    "budget_s": args.budget_s},
         "packets_per_s": args.packets * h["K"] / h["wall"],
         "transport_kernel_ms": h["kernel_ms"],

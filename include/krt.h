@@ -68,9 +68,15 @@ void krt_destroy(krt_ctx *ctx);
 const char *krt_last_error(const krt_ctx *ctx);
 /* Number of compute units of the context's device (launch sizing). */
 int krt_device_cus(const krt_ctx *ctx);
-/* Duration in ms of the transport kernel of the last krt_mc_run, from HIP
- * events recorded on the context's stream around that launch only. */
+/* Duration in ms of the transport of the last krt_mc_run, from HIP events
+ * recorded on the context's stream around its launch (plain and fused
+ * schedules) or around all its rounds, host round trips included (park). */
 double krt_last_transport_ms(const krt_ctx *ctx);
+/* Learned escape in park mode: the summed time of the call-kernel launches of
+ * the last krt_mc_run (ms, HIP events; 0 otherwise) and its number of rounds
+ * (transport launches; 1 for the other schedules). */
+double krt_last_network_ms(const krt_ctx *ctx);
+int64_t krt_last_rounds(const krt_ctx *ctx);
 
 /* ---------------------------------------------------------------- grid --- */
 /* Uniform Cartesian grid with cell-wise constant fields (Sec. 2.2.1: the
@@ -177,6 +183,25 @@ typedef struct {
                                   w = (1 + tanh(2|u| - 2 u0)) / 2, u0 where the two cross, with
                                   the exact redistribution: a demonstration of why the profile
                                   must match the sampler, not for production */
+    int32_t esc_park;          /* learned-escape schedule.  0 (default): fused -- the network runs
+                                  inside the transport kernel, batched over the asking lanes of a
+                                  wave (esc_min_lanes).  1: park -- a packet whose scattering
+                                  qualifies for a network call leaves the transport kernel as a
+                                  64-byte record, a separate kernel evaluates the calls of all
+                                  parked packets over full 16-sample blocks, and the packets resume
+                                  in the next round; every qualifying scattering takes the network,
+                                  so the tallies equal the fused schedule's at esc_min_lanes =
+                                  esc_tail_lanes = 1 bit for bit and do not depend on launch
+                                  geometry.  On the turbulent cloud park is 2-3x slower than fused
+                                  (each round waits on host round trips and short segments).
+                                  krt_mc_run_noalloc always runs fused */
+    uint32_t esc_park_cap;     /* park: packets in flight at most (0 = 2^22; two lists of 64 B per
+                                  packet, [1024, 2^28]) */
+    uint32_t esc_park_tail;    /* park: once every packet is admitted and at most this many are in
+                                  flight, one fused launch finishes them (0 = 65536) */
+    uint32_t esc_park_budget;  /* park: a packet that takes this many plain scatterings in one round
+                                  is parked after the last of them and resumes in the next round
+                                  (0 = 256), so no round waits on one long walk */
 } krt_run_opts;
 
 /* Caller-allocated DEVICE buffers.  Raw tallies are int64 fixed point, so their

@@ -56,7 +56,9 @@ logits use -log softmax(o)_F, whose minimiser is the log-probabilities (up to
 a constant); output 6 uses softplus(o) - b o, b = 1{x_out >= 0}.  Losses are
 averaged over the batch and summed over outputs.  The manual backward pass is
 pinned by finite differences (tests/test_oracle_mlp.py).  ``bf=True`` rounds
-weights and activations to bfloat16 where the GPU kernels do.
+weights and activations to bfloat16 where the GPU kernels do, and adds the
+quantile levels' rounding residuals (rounded again) through their own layer-1
+weights, as the GPU's extra operand slots do.
 """
 from __future__ import annotations
 
@@ -166,6 +168,10 @@ def forward(p, X, bf=False):
     h = r(X)
     for i in (1, 2, 3):
         z = h @ W[f"W{i}"] + W[f"b{i}"]
+        if i == 1 and bf:
+            # the GPU adds the bfloat16 rounding residuals of the four quantile
+            # levels through extra operand slots tied to their weights
+            z = z + r(X[:, 10:14] - h[:, 10:14]) @ W["W1"][10:14]
         cache[f"z{i}"] = z
         cache[f"h{i - 1}"] = h
         h = r(silu(z))

@@ -45,8 +45,14 @@ struct krt_ctx {
     int64_t *host_pinned = nullptr;
     float *host_edges = nullptr;          // pinned staging of the bin edges for krt_mc_run_noalloc
     unsigned char *scratch_dev = nullptr; // this device's address of the no-allocation scratch array
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;   // bracket the last transport launch
-    float last_ms = 0.0f;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;   // bracket the last run's transport launches
+    hipEvent_t evn0 = nullptr, evn1 = nullptr; // bracket one launch of the call kernel
+    float last_ms = 0.0f, last_net_ms = 0.0f;
+    int64_t last_rounds = 0;
+    // learned escape in park mode: two lists of parked packets and their counter
+    uint4 *park_buf[2] = {nullptr, nullptr};
+    uint64_t park_alloc = 0;                   // records per list
+    unsigned long long *park_counter = nullptr;
     // learned escape: FP32 master parameters, Adam moments, gradient, packed BF16 image
     float *edges = nullptr;                    // [kEdgeFloats]: spectrum then channel edges
     bool mlp_ready = false;
@@ -188,6 +194,8 @@ extern "C" int krt_create(krt_ctx **out, int hip_device, void *hip_stream) {
         hipMalloc(&c->level_consts, sizeof(double) * 256) != hipSuccess ||
         hipHostMalloc(&c->host_pinned, sizeof(int64_t) * 64, hipHostMallocDefault) != hipSuccess ||
         hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+        hipEventCreate(&c->evn0) != hipSuccess || hipEventCreate(&c->evn1) != hipSuccess ||
+        hipMalloc(&c->park_counter, sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&c->edges, sizeof(float) * kEdgeFloats) != hipSuccess ||
         hipHostMalloc(&c->host_edges, sizeof(float) * kEdgeFloats, hipHostMallocDefault) != hipSuccess) {
         krt_destroy(c);
@@ -223,6 +231,11 @@ extern "C" void krt_destroy(krt_ctx *c) {
     if (c->edges) (void)hipFree(c->edges);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->evn0) (void)hipEventDestroy(c->evn0);
+    if (c->evn1) (void)hipEventDestroy(c->evn1);
+    if (c->park_counter) (void)hipFree(c->park_counter);
+    for (int k = 0; k < 2; ++k)
+        if (c->park_buf[k]) (void)hipFree(c->park_buf[k]);
     delete c;
 }
 
@@ -231,6 +244,8 @@ extern "C" const char *krt_last_error(const krt_ctx *c) { return c ? c->err.c_st
 extern "C" int krt_device_cus(const krt_ctx *c) { return c ? c->cus : 0; }
 
 extern "C" double krt_last_transport_ms(const krt_ctx *c) { return c ? (double)c->last_ms : -1.0; }
+extern "C" double krt_last_network_ms(const krt_ctx *c) { return c ? (double)c->last_net_ms : -1.0; }
+extern "C" int64_t krt_last_rounds(const krt_ctx *c) { return c ? c->last_rounds : -1; }
 
 // ----------------------------------------------------------------- grid ---
 extern "C" int krt_grid_upload(krt_ctx *c, const krt_grid_desc *d) {
@@ -333,6 +348,87 @@ static double voigt_crossing(double a) {
     return 0.5 * (lo + hi);
 }
 
+// Learned escape in park mode, in rounds: a transport launch walks the
+// packets resumed from the last round's calls and newly admitted ones until
+// each one retires or parks at a qualifying scattering; the call kernel then
+// applies the parked calls in place, and those packets resume in the next
+// round.  At most cap packets are in flight (new ones are admitted as others
+// retire).  Once every packet is admitted and fewer than `tail` are in flight,
+// one fused launch (network inside the transport kernel, a call whenever a
+// scattering qualifies, as here) finishes them, so the last rounds, each a
+// launch pair and a host round trip for few packets, are not run one by one.
+static int run_parked(krt_ctx *c, const RunParams &P0, uint64_t n_packets, uint64_t cap, uint64_t tail, int grid,
+                      int block_fused) {
+    if (c->park_alloc < cap) {
+        for (int k = 0; k < 2; ++k) {
+            if (c->park_buf[k]) (void)hipFree(c->park_buf[k]);
+            c->park_buf[k] = nullptr;
+        }
+        c->park_alloc = 0;
+        for (int k = 0; k < 2; ++k)
+            HIPCHK(c, hipMalloc(&c->park_buf[k], sizeof(uint4) * kParkQuads * cap));
+        c->park_alloc = cap;
+    }
+    HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+    uint64_t n_res = 0, new_done = 0;
+    int cur = 0;
+    int64_t rounds = 0;
+    bool net_pending = false;
+    for (;;) {
+        const uint64_t admit = std::min(n_packets - new_done, cap - n_res);
+        if (n_res + admit == 0) break;
+        RunParams Q = P0;
+        Q.res_in = c->park_buf[cur];
+        Q.n_res = n_res;
+        Q.new_lo = new_done;
+        Q.n_packets = admit;
+        HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(Q.work_counter), 1, c->stream));
+        ++rounds;
+        if (new_done + admit == n_packets && n_res + admit <= tail) {
+            Q.esc_min_lanes = 1;
+            Q.esc_tail_lanes = 1;
+            HIPCHK(c, launch_transport(Q, kModeFused, grid, block_fused, c->stream));
+            break;
+        }
+        Q.park_out = c->park_buf[1 - cur];
+        Q.park_count = c->park_counter;
+        Q.park_cap = cap;
+        HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(c->park_counter), 1, c->stream));
+        HIPCHK(c, launch_transport(Q, kModePark, grid, 1024, c->stream));
+        new_done += admit;
+        HIPCHK(c, hipMemcpyAsync(c->host_pinned, c->park_counter, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (net_pending) {
+            float ms = 0.0f;
+            HIPCHK(c, hipEventElapsedTime(&ms, c->evn0, c->evn1));
+            c->last_net_ms += ms;
+            net_pending = false;
+        }
+        const uint64_t np = (uint64_t)c->host_pinned[0];
+        if (np > cap) return fail(c, KRT_EDEVICE, "park list overflow (%llu > %llu)", (unsigned long long)np,
+                                  (unsigned long long)cap);
+        if (np > 0) {
+            const uint64_t waves = (np + 63) / 64;
+            const int cgrid = (int)std::min<uint64_t>((waves + 7) / 8, (uint64_t)c->cus * 16);
+            HIPCHK(c, hipEventRecord(c->evn0, c->stream));
+            HIPCHK(c, launch_escape_call(Q, c->park_buf[1 - cur], np, cgrid, c->stream));
+            HIPCHK(c, hipEventRecord(c->evn1, c->stream));
+            net_pending = true;
+        }
+        cur = 1 - cur;
+        n_res = np;
+    }
+    HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (net_pending) {
+        float ms = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->evn0, c->evn1));
+        c->last_net_ms += ms;
+    }
+    c->last_rounds = rounds;
+    return KRT_OK;
+}
+
 // krt_mc_run and krt_mc_run_noalloc: with noalloc the packet-pool counter and
 // the bin edges live in the per-device scratch array and the edges are staged
 // through a pinned block allocated at context creation, so the call allocates
@@ -402,6 +498,14 @@ static int mc_run_impl(krt_ctx *c, uint64_t n_packets, uint64_t seed, const krt_
     // 168 VGPRs and spills)
     int block = o->wg_size ? o->wg_size : (esc ? 512 : 1024);
     int per_cu = o->wg_per_cu ? o->wg_per_cu : 1;
+    // learned escape schedule: fused (default) or park; the no-allocation
+    // entry point has no lists to park in
+    const bool park = esc && o->esc_park && !noalloc;
+    const uint64_t park_cap = o->esc_park_cap ? o->esc_park_cap : (1ull << 22);
+    const uint64_t park_tail = o->esc_park_tail ? o->esc_park_tail : 65536;
+    const uint32_t park_budget = o->esc_park_budget ? o->esc_park_budget : 256;
+    if (park && (park_cap < 1024 || park_cap > (1ull << 28)))
+        return fail(c, KRT_EINVAL, "esc_park_cap %llu outside [1024, 2^28]", (unsigned long long)park_cap);
     if (block < 64 || block > 1024 || block % 64) return fail(c, KRT_EINVAL, "wg_size %d invalid", block);
     if (per_cu < 1 || per_cu > 64) return fail(c, KRT_EINVAL, "wg_per_cu %d invalid", per_cu);
     if (o->max_events > 0xFFFFFFFEull) return fail(c, KRT_EINVAL, "max_events too large");
@@ -518,10 +622,20 @@ static int mc_run_impl(krt_ctx *c, uint64_t n_packets, uint64_t seed, const krt_
         P.cls_tab = c->cls_tab;
     }
     P.voigt_u0 = (float)voigt_crossing(c->lines[l].a);
+    P.n_res = 0;
+    P.new_lo = 0;
+    P.park_budget = park_budget;
     int grid = c->cus * per_cu;
-    HIPCHK(c, hipEventRecord(c->ev0, c->stream));
-    HIPCHK(c, launch_transport(P, grid, block, c->stream));
-    HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+    c->last_net_ms = 0.0f;
+    c->last_rounds = 1;
+    if (!park) {
+        HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+        HIPCHK(c, launch_transport(P, esc ? kModeFused : kModePlain, grid, block, c->stream));
+        HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+    } else {
+        int rc = run_parked(c, P, n_packets, park_cap, park_tail, grid, block);
+        if (rc) return rc;
+    }
     // integer tallies that left [0, 2^62] (the transport's atomics return nothing)
     HIPCHK(c, launch_saturation_check(t->spec_raw_dev, nsb, P.status, c->stream));
     if (o->emis_nch > 0) HIPCHK(c, launch_saturation_check(t->emis_raw_dev, nc * o->emis_nch, P.status, c->stream));

@@ -215,9 +215,10 @@ __global__ void mlp_pack_kernel(const float *p, const float *norm, unsigned char
         for (int j = 0; j < 8; ++j) {
             const int kp = 8 * g + j;  // reduction slot
             float w = 0.0f;
-            if (t < kTileFwdL2) {  // L1 fwd: W1^T, inputs in natural order
+            if (t < kTileFwdL2) {  // L1 fwd: W1^T, inputs in natural order, level residual slots tied
                 const int mo = t - kTileFwdL1;
                 if (kp < kMlpIn) w = p[kPW1 + kp * kMlpHid + 16 * mo + i];
+                else if (kp < kMlpOperandIn) w = p[kPW1 + (kMlpLevelIn + kp - kMlpResIn) * kMlpHid + 16 * mo + i];
             } else if (t < kTileFwdL4) {  // L2/L3 fwd: tile mo*4+c, A[i][k'] = W[kperm(c,k')][16mo+i]
                 const int base = (t < kTileFwdL3) ? kPW2 : kPW3;
                 const int tt = t - ((t < kTileFwdL3) ? kTileFwdL2 : kTileFwdL3);

@@ -82,10 +82,20 @@ struct RunParams {
     int64_t *spec_raw, *emis_raw, *jbar_raw, *counters;
     uint32_t *status;
     float *plog;
-    // work
+    // work: packets resumed after a network call (res_in[0, n_res)) come first,
+    // then n_packets new ones with ids packet_offset + new_lo + [0, n_packets)
     uint64_t n_packets, packet_offset, max_events;
     uint32_t key0, key1;
     unsigned long long *work_counter;
+    const uint4 *res_in;
+    uint64_t n_res, new_lo;
+    // parking (kernel mode kModePark): a packet whose scattering qualifies for a
+    // network call leaves its lane as a record in park_out (slot from park_count,
+    // at most park_cap); escape_call_kernel then applies the call to the record
+    uint4 *park_out;
+    unsigned long long *park_count;
+    uint64_t park_cap;
+    uint32_t park_budget;  // plain scatterings of a packet per round before it is parked to continue
     // learned whole-cell escape (mlp_img == nullptr: plain random walk only).
     // Calls happen only in cubic cells (esc_cubic) whose line-centre depth from
     // centre to face tau_c = k0 half_dx lies in [esc_tc_min, esc_tc_max], at
@@ -110,7 +120,21 @@ struct RunParams {
     const float *cls_tab;
 };
 
-hipError_t launch_transport(const RunParams &P, int grid, int block, hipStream_t s);
+// transport kernel modes: plain walk, network calls batched inside the
+// transport kernel, qualifying scatterings parked for escape_call_kernel
+constexpr int kModePlain = 0, kModeFused = 1, kModePark = 2;
+// A parked packet: 4 x uint4 (64 B).  w0 = (id lo, id hi, event of the call or
+// of the last scattering, cell); w1 = (fx, fy, fz, x lab) as float bits;
+// w2 = (nx, ny, nz, scatterings of the packet); w3 = (cell crossings of the
+// packet, the gas-frame frequency the call was qualified at, 1 for a call or 0
+// for a packet parked after its round's budget of plain scatterings, 0).  After the call
+// the record holds the exit point (still in the cell, on the exit face), the
+// exit direction and the lab exit frequency; the transport resumes it with the
+// next event.
+constexpr int kParkQuads = 4;
+hipError_t launch_transport(const RunParams &P, int mode, int grid, int block, hipStream_t s);
+// the network call of each of n parked records, in place (learned escape)
+hipError_t launch_escape_call(const RunParams &P, uint4 *rec, uint64_t n, int grid, hipStream_t s);
 hipError_t launch_finalize(const int64_t *raw, float *out, int64_t n, double scale, hipStream_t s);
 hipError_t launch_zero_i64(int64_t *p, int64_t n, hipStream_t s);
 hipError_t launch_saturation_check(const int64_t *p, int64_t n, uint32_t *status, hipStream_t s);

@@ -46,6 +46,13 @@
 namespace krt {
 
 constexpr int kMlpIn = 24, kMlpInPad = 32, kMlpHid = 128, kMlpOut = 32;
+// Layer 1 sees 28 operand slots: the 24 inputs rounded to bfloat16, then in
+// slots 24-27 the rounding residuals of the four quantile levels (inputs
+// 10-13), whose weights are tied to those levels' rows of W1.  A level then
+// enters with about 16 significant bits instead of 8: with the level alone in
+// bfloat16, the samples of a quantile output would take a few hundred
+// discrete values per condition (a comb in the sampled distributions).
+constexpr int kMlpLevelIn = 10, kMlpResIn = 24, kMlpOperandIn = 28;
 // output indices
 constexpr int kOutFace = 0, kOutSide = 6, kOutLogN = 7, kOutLogX2 = 8, kOutYS = 9, kOutYT = 10, kOutMu2 = 11,
               kOutAlpha = 12, kOutXAbs = 16;
@@ -184,6 +191,11 @@ __device__ __forceinline__ v8i16 tileA(const unsigned char *blob, int t, int lan
 // a window of 8 registers: product i reads slot i % 8 and the same slot is
 // refilled at once with tile i + 8, so every LDS read is issued 8 products
 // (about 130 cycles of matrix work) before its use and only 8 tiles are live.
+// A scheduling barrier after each step keeps that order (kPinned); left free,
+// the compiler sinks each read to just before its product and waits on it.
+// Inside the fused transport kernel, whose packet state fills the register
+// file, the pinned order spills more, so that kernel only asks for alternating
+// products and reads (kPinned = false).
 // A layer's epilogue applies SiLU, packs the bf16 activations and loads the
 // next layer's biases into the freed accumulators.
 __host__ __device__ constexpr int fwd_tile(int i) {
@@ -197,6 +209,7 @@ static_assert(kTilesFwd == kFwdSteps, "one product per forward tile");
 
 __device__ __forceinline__ v4f32 ld4(const float *p) { return *reinterpret_cast<const v4f32 *>(p); }
 
+template <bool kPinned = true>
 __device__ __forceinline__ void mlp_forward_block(const unsigned char *tiles, const float *bias, v8i16 xin,
                                                   int lane, v4f32 *z1, v4f32 *z2, v4f32 *z3, v4f32 &oa, v4f32 &ob) {
     const int g = lane >> 4;
@@ -211,8 +224,10 @@ __device__ __forceinline__ void mlp_forward_block(const unsigned char *tiles, co
 #define KRT_FWD_STEP(i, bop, c)                                                         \
     do {                                                                                \
         (c) = mfma32(w[(i) % 8], (bop), (c));                                           \
-        if ((i) + 8 < kFwdSteps) {                                                      \
-            w[(i) % 8] = tileA(tiles, fwd_tile((i) + 8), lane);                         \
+        if ((i) + 8 < kFwdSteps) w[(i) % 8] = tileA(tiles, fwd_tile((i) + 8), lane);    \
+        if (kPinned) {                                                                  \
+            __builtin_amdgcn_sched_barrier(0);                                          \
+        } else if ((i) + 8 < kFwdSteps) {                                               \
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                          \
             __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);                          \
         } else {                                                                        \
@@ -286,20 +301,35 @@ __device__ __forceinline__ void mlp_inputs(const float *c, float ua, float ub, f
     in[23] = 0.0f;
 }
 
-// this lane's layer-1 B operand: inputs 8(l/16)..8(l/16)+7 (group 3: zeros)
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// operand slot k of layer 1 (k < kMlpOperandIn): the inputs, then the level residuals
+__device__ __forceinline__ float operand_in(const float in[kMlpIn], int k) {
+    if (k < kMlpIn) return in[k];
+    const float l = in[kMlpLevelIn + k - kMlpResIn];
+    return l - bf2f(f2bf(l));
+}
+
+// this lane's layer-1 B operand: slots 8(l/16)..8(l/16)+7 (slots 28-31 zero)
 __device__ __forceinline__ v8i16 xin_operand(const float in[kMlpIn], int lane) {
     const int g = lane >> 4;
     float v[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = (g == 0) ? in[j] : ((g == 1) ? in[8 + j] : ((g == 2) ? in[16 + j] : 0.0f));
+    for (int j = 0; j < 8; ++j) {
+        const float a0 = operand_in(in, j), a1 = operand_in(in, 8 + j), a2 = operand_in(in, 16 + j);
+        const float a3 = (j < 4) ? operand_in(in, 24 + j) : 0.0f;
+        v[j] = (g == 0) ? a0 : ((g == 1) ? a1 : ((g == 2) ? a2 : a3));
+    }
     return cat8(pack4(v[0], v[1], v[2], v[3]), pack4(v[4], v[5], v[6], v[7]));
 }
 
-// 24 normalised inputs as 12 dwords of bf16 pairs (dwords 4g..4g+3 are the
-// layer-1 B operand of lane group g)
-__device__ __forceinline__ void pack_inputs(const float in[kMlpIn], uint32_t pk[12]) {
+// the 28 operand slots as 14 dwords of bf16 pairs (dwords 4g..4g+3 are the
+// layer-1 B operand of lane group g; group 3 has two)
+constexpr int kMlpPackDw = kMlpOperandIn / 2;
+__device__ __forceinline__ void pack_inputs(const float in[kMlpIn], uint32_t pk[kMlpPackDw]) {
 #pragma unroll
-    for (int d = 0; d < 12; ++d) pk[d] = (uint32_t)f2bf(in[2 * d]) | ((uint32_t)f2bf(in[2 * d + 1]) << 16);
+    for (int d = 0; d < kMlpPackDw; ++d)
+        pk[d] = (uint32_t)f2bf(operand_in(in, 2 * d)) | ((uint32_t)f2bf(operand_in(in, 2 * d + 1)) << 16);
 }
 
 // ------------------------------------------------------ the reduced frame ---

@@ -93,7 +93,8 @@ __device__ __forceinline__ int nth_set_lane(uint64_t m, int k) {
 // wave-uniform `want` (a subset of kMlpFetch) in out[k] (the others keep their
 // values).
 constexpr uint32_t kMlpFetch = 0x003F1FFFu;  // outputs 0-12 and 16-21: all the transport reads
-__device__ __forceinline__ void mlp_eval_wave(const unsigned char *img, const float *bias, const uint32_t pk[12],
+template <bool kPinned>
+__device__ __forceinline__ void mlp_eval_wave(const unsigned char *img, const float *bias, const uint32_t pk[kMlpPackDw],
                                               int lane, uint64_t ask, uint32_t want, float out[kMlpOut]) {
     const int nask = __popcll(ask);
     const int nblk = (nask + 15) >> 4;
@@ -109,17 +110,17 @@ __device__ __forceinline__ void mlp_eval_wave(const unsigned char *img, const fl
         const int src = (r < nask) ? nth_set_lane(ask, r) : lane;
         uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-        for (int d = 0; d < 12; ++d) {
+        for (int d = 0; d < kMlpPackDw; ++d) {
             const uint32_t v = (uint32_t)__shfl((int)pk[d], src, 64);
             if ((d >> 2) == g) w[d & 3] = v;
         }
-        const bool use = (r < nask) && g < 3;
+        const bool use = r < nask;
         const v4i16 lo = {(short)(use ? w[0] & 0xFFFFu : 0u), (short)(use ? w[0] >> 16 : 0u),
                           (short)(use ? w[1] & 0xFFFFu : 0u), (short)(use ? w[1] >> 16 : 0u)};
         const v4i16 hi = {(short)(use ? w[2] & 0xFFFFu : 0u), (short)(use ? w[2] >> 16 : 0u),
                           (short)(use ? w[3] & 0xFFFFu : 0u), (short)(use ? w[3] >> 16 : 0u)};
         v4f32 oa, ob;
-        mlp_forward_block(img, bias, cat8(lo, hi), lane, nullptr, nullptr, nullptr, oa, ob);
+        mlp_forward_block<kPinned>(img, bias, cat8(lo, hi), lane, nullptr, nullptr, nullptr, oa, ob);
         // output k of block position p sits in lane 16 ((k % 16) / 4) + p,
         // component k % 4, of tile k / 16
         const bool take = mine && (rank >> 4) == b;
@@ -132,6 +133,186 @@ __device__ __forceinline__ void mlp_eval_wave(const unsigned char *img, const fl
             if (take) out[k] = v;
         }
     }
+}
+
+// ------------------------------------------------------ network call ---
+// The pieces of one learned whole-cell escape, shared by the transport kernel
+// (calls batched inside it) and escape_call_kernel (parked calls), so both
+// apply a call with the same arithmetic.
+
+// Whether a scattering at the cell-frame position (fx, fy, fz) in [0, 1]^3 of a
+// cell of line-centre opacity k0c, at gas-frame frequency xc, qualifies for a
+// call: a cubic cell with tau_c = k0c half_dx in range, the point at least
+// esc_depth_min below its nearest face, |xc| <= esc_x_max.  Returns the reduced
+// frame and log10 tau_c, log10 depth.
+__device__ __forceinline__ void call_frame(const RunParams &P, float k0c, float fx, float fy, float fz,
+                                           CellFrame &CF, float &tc, float &dep) {
+    tc = k0c * P.esc_half_dx;  // line-centre depth, centre to face
+    cell_reduce(2.0f * fx - 1.0f, 2.0f * fy - 1.0f, 2.0f * fz - 1.0f, CF);
+    dep = tc * (1.0f - CF.q[2]);
+}
+__device__ __forceinline__ bool call_eligible(const RunParams &P, float k0c, float fx, float fy, float fz, float xc,
+                                              CellFrame &CF, float &ltc, float &ldep) {
+    if (!P.esc_cubic) return false;
+    float tc, dep;
+    call_frame(P, k0c, fx, fy, fz, CF, tc, dep);
+    if (tc >= P.esc_tc_min && tc <= P.esc_tc_max && dep >= P.esc_depth_min && fabsf(xc) <= P.esc_x_max) {
+        ltc = __log10f(tc);
+        ldep = __log10f(dep);
+        return true;
+    }
+    return false;
+}
+
+// The two evaluations of a call for the lanes in `ask` (wave-uniform): the
+// marginal one (exit face from the softmax at level u01(C.z), side of x_out
+// from the learned P(x_out >= 0) at u01(C.w), |x_out| from the exit face's
+// quantile at u_a = u01(C.x)), then the one conditional on the sampled face and
+// x_out (offsets, cosine, alpha at the levels of D).  cnd: the raw condition
+// (log10 tau_c, log10 a, |x_in|, q0, q1, q2, log10 depth, incoming direction in
+// the reduced frame).  xo carries x_in's sign convention (reduced frame).
+template <bool kPinned>
+__device__ __forceinline__ void call_network(const unsigned char *mimg, const float *mbias, const float *mnorm,
+                                             int lane, uint64_t ask, const float cnd[10], uint4 C, uint4 D,
+                                             int &face, float &xo, float mo[kMlpOut]) {
+    float in[kMlpIn];
+    uint32_t pk[kMlpPackDw];
+#pragma unroll
+    for (int k = 0; k < kMlpOut; ++k) mo[k] = 0.0f;
+    face = 5;
+    xo = 0.0f;
+#pragma unroll 1
+    for (int e = 0; e < 2; ++e) {
+        if (e == 0) mlp_inputs(cnd, u01(C.x), u01(C.y), u01(D.z), u01(D.w), false, 0.0f, 0, in);
+        else mlp_inputs(cnd, u01(D.x), u01(D.y), u01(D.z), u01(D.w), true, xo, face, in);
+        pack_inputs(in, pk);
+        mlp_eval_wave<kPinned>(mimg, mbias, pk, lane, ask, e == 0 ? 0x003F01FFu : 0x00001E00u, mo);
+        if (e == 0) {
+            float mx = mo[0];
+#pragma unroll
+            for (int f = 1; f < 6; ++f) mx = fmaxf(mx, mo[f]);
+            float ef[6], se = 0.0f;
+#pragma unroll
+            for (int f = 0; f < 6; ++f) { ef[f] = __expf(mo[f] - mx); se += ef[f]; }
+            const float uf = u01(C.z) * se;
+            float c2 = 0.0f;
+            bool found = false;
+#pragma unroll
+            for (int f = 0; f < 6; ++f) {
+                c2 += ef[f];
+                if (!found && uf < c2) { face = f; found = true; }
+            }
+            const bool pos = u01(C.w) < sigmoid_f(mo[kOutSide]);
+            float ma = mo[kOutXAbs], mm = mnorm[kOutXAbs], ms = mnorm[kMlpOut + kOutXAbs];
+#pragma unroll
+            for (int f = 1; f < 6; ++f)
+                if (face == f) {
+                    ma = mo[kOutXAbs + f];
+                    mm = mnorm[kOutXAbs + f];
+                    ms = mnorm[kMlpOut + kOutXAbs + f];
+                }
+            const float mag = fmaxf(fmaf(ma, ms, mm), 0.0f);
+            xo = pos ? mag : -mag;
+        }
+    }
+}
+
+// The sampled exit applied to the packet: the exit point on the face (cell
+// frame, fx, fy, fz in [0, 1]), the exit direction, the lab frequency
+// x = sign(xc) xo + n.v, and the expected number of skipped scatterings
+// E[N_s] (calibrated), whose emissivity -- thermalised core, camera frequency
+// ~ N(n_cam.v, (<x^2> + 1)/3), integrated exactly over the channels -- goes to
+// dep(channel, fixed-point weight); mass outside the channels is added to
+// n_drop.  alpha takes its sign from the lowest bit of C.z.
+template <class Dep>
+__device__ __forceinline__ void call_apply(const RunParams &P, const float *mnorm, const float *cedges,
+                                           const CellFrame &CF, const float mo[kMlpOut], int face, float xo,
+                                           uint32_t cz, float ltc, float ldep, float xc, float vxc, float vyc,
+                                           float vzc, float &fx, float &fy, float &fz, float &nx, float &ny,
+                                           float &nz, float &x, int64_t &n_skip, int64_t &n_drop, Dep dep) {
+    const float lns = mo[kOutLogN] * mnorm[kMlpOut + kOutLogN] + mnorm[kOutLogN] +
+                      mnorm[kNormCal + cal_bin(ltc, ldep, fabsf(xc))];
+    const float lx2 = mo[kOutLogX2] * mnorm[kMlpOut + kOutLogX2] + mnorm[kOutLogX2];
+    // offsets learned as asinh, the cosine as mu^2
+    auto sinh_f = [](float v) { const float ev = f_exp(v); return 0.5f * (ev - f_rcp(ev)); };
+    const float ys = sinh_f(mo[kOutYS] * mnorm[kMlpOut + kOutYS] + mnorm[kOutYS]);
+    const float yt = sinh_f(mo[kOutYT] * mnorm[kMlpOut + kOutYT] + mnorm[kOutYT]);
+    const float mu = f_sqrt(fminf(fmaxf(mo[kOutMu2] * mnorm[kMlpOut + kOutMu2] + mnorm[kOutMu2], 1e-6f), 1.0f));
+    const float al = fminf(fmaxf(mo[kOutAlpha] * mnorm[kMlpOut + kOutAlpha] + mnorm[kOutAlpha], 0.0f), 3.14159265f);
+    // exit point and direction in the reduced frame: face axis k, outward side
+    const int k = face >> 1;
+    const float side = (face & 1) ? 1.0f : -1.0f;
+    const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+    const float qk = pick3(CF.q[0], CF.q[1], CF.q[2], k);
+    const float qa = pick3(CF.q[0], CF.q[1], CF.q[2], k1);
+    const float qb = pick3(CF.q[0], CF.q[1], CF.q[2], k2);
+    const float dpl = 1.0f - side * qk;
+    const float es = fminf(fmaxf(qa + dpl * ys, -1.0f), 1.0f);
+    const float et = fminf(fmaxf(qb + dpl * yt, -1.0f), 1.0f);
+    // tangential direction at angle +-alpha from the offset (es - qa, et - qb)
+    const float ds = es - qa, dt = et - qb;
+    const float rr = f_sqrt(ds * ds + dt * dt);
+    const float ir = (rr > 0.0f) ? f_rcp(rr) : 0.0f;
+    const float c0 = (rr > 0.0f) ? ds * ir : 1.0f, s0 = dt * ir;
+    const float arev = al * 0.159154943f * ((cz & 1u) ? -1.0f : 1.0f);
+    const float ca = cos_rev(arev), sa = sin_rev(arev);
+    const float sm = f_sqrt(fmaxf(0.0f, 1.0f - mu * mu));
+    const float d1 = sm * (c0 * ca - s0 * sa), d2 = sm * (s0 * ca + c0 * sa);
+    // back to the cell frame: reduced axis r is cell axis perm[r] with sign sg
+    float pc[3] = {0.0f, 0.0f, 0.0f}, nc[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const float R_ = (r == k) ? side : ((r == k1) ? es : et);
+        const float V_ = (r == k) ? side * mu : ((r == k1) ? d1 : d2);
+        const int axc = CF.perm[r];
+        const float sgc = pick3(CF.sg[0], CF.sg[1], CF.sg[2], axc);
+#pragma unroll
+        for (int a3 = 0; a3 < 3; ++a3)
+            if (a3 == axc) { pc[a3] = sgc * R_; nc[a3] = sgc * V_; }
+    }
+    fx = fminf(fmaxf(0.5f * (pc[0] + 1.0f), 0.0f), 1.0f);
+    fy = fminf(fmaxf(0.5f * (pc[1] + 1.0f), 0.0f), 1.0f);
+    fz = fminf(fmaxf(0.5f * (pc[2] + 1.0f), 0.0f), 1.0f);
+    nx = nc[0]; ny = nc[1]; nz = nc[2];
+    const float Ns = fmaxf(f_exp(lns), 1.0f);  // E[N_s | condition]
+    if (P.emis_raw) {
+        const float sd = f_sqrt((f_exp(lx2) + 1.0f) * (1.0f / 3.0f));
+        const float vc = P.n_cam[0] * vxc + P.n_cam[1] * vyc + P.n_cam[2] * vzc;
+        const float isd = kInvSqrt2F * f_rcp(sd);
+        const float W = Ns * P.frac_scale;
+        int kb0 = bin_index(vc - 6.0f * sd, cedges, P.emis_nch, P.ch_inv_w);
+        int kb1 = bin_index(vc + 6.0f * sd, cedges, P.emis_nch, P.ch_inv_w);
+        kb0 = max(kb0, 1);
+        kb1 = min(kb1, P.emis_nch);
+        float cdf_lo = 0.5f * (1.0f + erff((cedges[kb0 - 1] - vc) * isd));
+        float inside = 0.0f;
+        for (int kb = kb0; kb <= kb1; ++kb) {
+            const float cdf_hi = 0.5f * (1.0f + erff((cedges[kb] - vc) * isd));
+            const float fr = cdf_hi - cdf_lo;
+            cdf_lo = cdf_hi;
+            inside += fr;
+            const int64_t wq = (int64_t)__float2ll_rn(W * fr);
+            if (wq != 0) dep(kb - 1, wq);
+        }
+        n_drop += (int64_t)__float2ll_rn(Ns * fmaxf(0.0f, 1.0f - inside));
+    }
+    const float sx = (xc < 0.0f) ? -1.0f : 1.0f;
+    x = sx * xo + nx * vxc + ny * vyc + nz * vzc;
+    n_skip += (int64_t)__float2ll_rn(Ns);
+}
+
+// raw condition of a call: (log10 tau_c, log10 a, |x_in|, q0, q1, q2, log10
+// depth, incoming direction in the reduced frame)
+__device__ __forceinline__ void call_condition(const RunParams &P, const CellFrame &CF, float ltc, float ldep,
+                                               float xc, float nx, float ny, float nz, float cnd[10]) {
+    cnd[0] = ltc;
+    cnd[1] = P.esc_log10a;
+    cnd[2] = fabsf(xc);
+    cnd[3] = CF.q[0]; cnd[4] = CF.q[1]; cnd[5] = CF.q[2];
+    cnd[6] = ldep;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+        cnd[7 + r] = pick3(CF.sg[0], CF.sg[1], CF.sg[2], CF.perm[r]) * pick3(nx, ny, nz, CF.perm[r]);
 }
 
 // --------------------------------------------------------------- kernel ---
@@ -170,8 +351,9 @@ __device__ __forceinline__ void scatter_draws(uint4 B, bool dipole, SDraws &d) {
 // damping a b_ref / b, and the class's own tables (global memory) serve the
 // opacity and the redistribution; frequencies return to reference units on
 // leaving the cell's frame.
-template <bool kEsc, int kMaxThreads, int kProf = 0>
+template <int kMode, int kMaxThreads, int kProf = 0>
 __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) {
+    constexpr bool kEsc = kMode == kModeFused, kPark = kMode == kModePark;
     extern __shared__ float4 lds4[];
     const float *T = (kProf == 1) ? P.tab : reinterpret_cast<const float *>(lds4);
     // bin edges after the tables: spectrum then channels; the network variant
@@ -215,6 +397,7 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
     uint32_t ev = 0, wa1 = 0, wa2 = 0, wa3 = 0;
     float k0c = 0.f, vxc = 0.f, vyc = 0.f, vzc = 0.f, epsc = 0.f, kabsc = 0.f;
     uint32_t nscat_pkt = 0, ncross_pkt = 0;
+    uint32_t seg = 0;  // plain scatterings of the packet in this launch (park mode)
     int outcome = 0;  // 1 escaped, 2 destroyed, 3 stuck
     int64_t jacc = 0;
     EmisCache E;
@@ -387,6 +570,37 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
         outcome = 0;
     };
 
+    // park mode: lanes with a qualifying scattering (kind 1), or past their
+    // round's budget of plain scatterings (kind 0, after committing one), leave
+    // as records (their cell's register tallies flushed first); one
+    // wave-aggregated atomic takes the slots.  A parked lane is free for new
+    // work, with no outcome.  The budget bounds a round by its slowest packet.
+    auto park = [&](bool want, bool &scat, float xc, uint32_t kind) {
+        const uint64_t pm = __ballot(want);
+        if (pm == 0ull) return;
+        const int leader = __ffsll((long long)pm) - 1;
+        unsigned long long base = 0;
+        if (lane == leader) base = atomicAdd(P.park_count, (unsigned long long)__popcll(pm));
+        base = __shfl(base, leader, 64);
+        if (want) {
+            if (P.jbar_raw && jacc != 0) { tally_add_i64(P.jbar_raw + cell, jacc); jacc = 0; }
+            if (P.emis_raw) emis_flush(E, P.emis_raw + (int64_t)cell * P.emis_nch);
+            const uint64_t slot = base + (uint64_t)__popcll(pm & lanemask_lt);
+            if (slot < P.park_cap) {
+                uint4 *r = P.park_out + kParkQuads * slot;
+                r[0] = make_uint4((uint32_t)pid, (uint32_t)(pid >> 32), ev, (uint32_t)cell);
+                r[1] = make_uint4(__float_as_uint(fx), __float_as_uint(fy), __float_as_uint(fz), __float_as_uint(x));
+                r[2] = make_uint4(__float_as_uint(nx), __float_as_uint(ny), __float_as_uint(nz), nscat_pkt);
+                r[3] = make_uint4(ncross_pkt, __float_as_uint(xc), kind, 0u);
+            } else {
+                atomicOr(status, (uint32_t)KRT_ST_STUCK_BIT);  // the host sizes the list; never expected
+                c_stuck += 1;
+            }
+            have = false;
+            scat = false;
+        }
+    };
+
     bool tail = false;
     for (;;) {
         // ---- refill retired lanes from the global queue -------------------
@@ -400,11 +614,46 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
             base = __shfl(base, leader, 64);
             if (need) {
                 uint64_t idx = base + (uint64_t)__popcll(need_mask & lanemask_lt);
-                if (idx >= P.n_packets) {
+                if (idx < P.n_res) {
+                    // ---- a packet back from a network call: its next event ----
+                    const uint4 *r = P.res_in + kParkQuads * idx;
+                    const uint4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
+                    pid = (uint64_t)r0.x | ((uint64_t)r0.y << 32);
+                    ev = r0.z;
+                    cell = (int)r0.w;
+                    ci = cell % P.n[0];
+                    cj = (cell / P.n[0]) % P.n[1];
+                    ck = cell / (P.n[0] * P.n[1]);
+                    fx = __uint_as_float(r1.x); fy = __uint_as_float(r1.y); fz = __uint_as_float(r1.z);
+                    x = __uint_as_float(r1.w);
+                    nx = __uint_as_float(r2.x); ny = __uint_as_float(r2.y); nz = __uint_as_float(r2.z);
+                    nscat_pkt = r2.w;
+                    ncross_pkt = r3.x;
+                    k0c = P.k0[cell];
+                    if (P.vx) { vxc = P.vx[cell]; vyc = P.vy[cell]; vzc = P.vz[cell]; }
+                    else { vxc = vyc = vzc = 0.0f; }
+                    epsc = P.eps ? P.eps[cell] : 0.0f;
+                    kabsc = P.kabs ? P.kabs[cell] : 0.0f;
+                    enter_cell();
+                    jacc = 0;
+                    seg = 0;
+                    ev += 1;
+                    if ((uint64_t)ev > P.max_events) {
+                        c_stuck += 1;
+                        atomicOr(status, (uint32_t)KRT_ST_STUCK_BIT);
+                        outcome = 3;
+                        have = false;
+                    } else {
+                        const uint4 A = philox(make_uint4(ev, r0.x, r0.y, 0u), P.key0, P.key1);
+                        tau = -f_log(u01(A.x));
+                        wa1 = A.y; wa2 = A.z; wa3 = A.w;
+                        have = true;
+                    }
+                } else if (idx - P.n_res >= P.n_packets) {
                     done = true;
                 } else {
                     // ---- emission (event 0) ----------------------------------
-                    pid = P.packet_offset + idx;
+                    pid = P.packet_offset + P.new_lo + (idx - P.n_res);
                     const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
                     uint4 e0 = philox(make_uint4(0u, plo, phi, 0u), P.key0, P.key1);
                     if (P.source == KRT_SRC_BEAM_I) {
@@ -473,6 +722,7 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
                     wa1 = A.y; wa2 = A.z; wa3 = A.w;
                     nscat_pkt = 0;
                     ncross_pkt = 0;
+                    seg = 0;
                     jacc = 0;
                     have = true;
                     c_emit += 1;
@@ -500,174 +750,52 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
             flight(u01(wa1), scat, xc);
         }
 
-        // ---- learned whole-cell escape: batched network calls per wave (uniform) ----
+        // ---- learned whole-cell escape ---------------------------------------
         // At a scattering inside a thick cubic cell, at least esc_depth_min below
         // its nearest face and in the line core, one network sample replaces the
         // walk until the photon leaves the cell: exit face, point, direction and
-        // frequency, and the expected number of scatterings skipped.
+        // frequency, and the expected number of scatterings skipped.  Fused mode
+        // evaluates the network here, batched over the asking lanes of the wave
+        // (wave-uniform); park mode writes the packet to the park list and frees
+        // the lane, and escape_call_kernel applies the call.
         bool mlp = false;
-        if (kEsc) {
+        if (kEsc || kPark) {
             CellFrame CF{};
             float ltc = 0.0f, ldep = 0.0f;
-            if (scat && P.esc_cubic) {
-                const float tc = k0c * P.esc_half_dx;  // line-centre depth, centre to face
-                cell_reduce(2.0f * fx - 1.0f, 2.0f * fy - 1.0f, 2.0f * fz - 1.0f, CF);
-                const float dep = tc * (1.0f - CF.q[2]);
-                if (tc >= P.esc_tc_min && tc <= P.esc_tc_max && dep >= P.esc_depth_min && fabsf(xc) <= P.esc_x_max) {
-                    ltc = __log10f(tc);
-                    ldep = __log10f(dep);
-                    mlp = true;
+            if (scat) mlp = call_eligible(P, k0c, fx, fy, fz, xc, CF, ltc, ldep);
+            if (kPark) {
+                bool cont = false;
+                if (!mlp && scat) {
+                    commit(q);
+                    cont = ++seg >= P.park_budget;
                 }
-            }
-            // once the packet pool is exhausted (some lane of this wave is done) the
-            // wave lives only as long as its slowest packet: fewer asking lanes suffice
-            const uint64_t wm = __ballot(mlp);
-            const int need_lanes = (__ballot(done) != 0ull) ? P.esc_tail_lanes : P.esc_min_lanes;
-            const bool go = __popcll(wm) >= need_lanes;  // wave-uniform
-            if (!go) mlp = false;
-            // this event's plain scatterings first, so their prepared state is
-            // not live across the network evaluation
-            if (scat && !mlp) commit(q);
-            if (go) {
-                const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
-                const uint4 C = philox(make_uint4(ev, plo, phi, 2u), P.key0, P.key1);
-                const uint4 D = philox(make_uint4(ev, plo, phi, 3u), P.key0, P.key1);
-                // the condition in the reduced frame
-                float cnd[10];
-                cnd[0] = ltc;
-                cnd[1] = P.esc_log10a;
-                cnd[2] = fabsf(xc);
-                cnd[3] = CF.q[0]; cnd[4] = CF.q[1]; cnd[5] = CF.q[2];
-                cnd[6] = ldep;
-#pragma unroll
-                for (int r = 0; r < 3; ++r)
-                    cnd[7 + r] = pick3(CF.sg[0], CF.sg[1], CF.sg[2], CF.perm[r]) * pick3(nx, ny, nz, CF.perm[r]);
-                // two evaluations through one inlined copy of the network: marginal
-                // (exit face logits, side and magnitude of x_out at level u_a,
-                // count, <x^2> at level u_b), then conditional on the sampled exit
-                // face and frequency (exit offsets at u_a, u_b; cosine at u_c;
-                // alpha at u_d)
-                float in[kMlpIn];
-                uint32_t pk[12];
-                float mo[kMlpOut];
-#pragma unroll
-                for (int k = 0; k < kMlpOut; ++k) mo[k] = 0.0f;
-                int face = 5;
-                float xo = 0.0f;  // reduced sign (that of x_in)
-#pragma unroll 1
-                for (int e = 0; e < 2; ++e) {
-                    if (e == 0) mlp_inputs(cnd, u01(C.x), u01(C.y), u01(D.z), u01(D.w), false, 0.0f, 0, in);
-                    else mlp_inputs(cnd, u01(D.x), u01(D.y), u01(D.z), u01(D.w), true, xo, face, in);
-                    pack_inputs(in, pk);
-                    mlp_eval_wave(mimg, mbias, pk, lane, wm, e == 0 ? 0x003F01FFu : 0x00001E00u, mo);
-                    if (e == 0) {
-                        // exit face from the softmax of the logits, at level u01(C.z)
-                        float mx = mo[0];
-#pragma unroll
-                        for (int f = 1; f < 6; ++f) mx = fmaxf(mx, mo[f]);
-                        float ef[6], se = 0.0f;
-#pragma unroll
-                        for (int f = 0; f < 6; ++f) { ef[f] = __expf(mo[f] - mx); se += ef[f]; }
-                        const float uf = u01(C.z) * se;
-                        float c2 = 0.0f;
-                        bool found = false;
-#pragma unroll
-                        for (int f = 0; f < 6; ++f) {
-                            c2 += ef[f];
-                            if (!found && uf < c2) { face = f; found = true; }
-                        }
-                        // exit frequency: side from the learned P(x_out >= 0) at level
-                        // u01(C.w), magnitude from the exit face's quantile at level u_a
-                        const bool pos = u01(C.w) < sigmoid_f(mo[kOutSide]);
-                        float ma = mo[kOutXAbs], mm = mnorm[kOutXAbs], ms = mnorm[kMlpOut + kOutXAbs];
-#pragma unroll
-                        for (int f = 1; f < 6; ++f)
-                            if (face == f) {
-                                ma = mo[kOutXAbs + f];
-                                mm = mnorm[kOutXAbs + f];
-                                ms = mnorm[kMlpOut + kOutXAbs + f];
-                            }
-                        const float mag = fmaxf(fmaf(ma, ms, mm), 0.0f);
-                        xo = pos ? mag : -mag;
+                park(mlp || cont, scat, xc, mlp ? 1u : 0u);
+            } else {
+                // once the packet pool is exhausted (some lane of this wave is done) the
+                // wave lives only as long as its slowest packet: fewer asking lanes suffice
+                const uint64_t wm = __ballot(mlp);
+                const int need_lanes = (__ballot(done) != 0ull) ? P.esc_tail_lanes : P.esc_min_lanes;
+                const bool go = __popcll(wm) >= need_lanes;  // wave-uniform
+                if (!go) mlp = false;
+                // this event's plain scatterings first, so their prepared state is
+                // not live across the network evaluation
+                if (scat && !mlp) commit(q);
+                if (go) {
+                    const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
+                    const uint4 C = philox(make_uint4(ev, plo, phi, 2u), P.key0, P.key1);
+                    const uint4 D = philox(make_uint4(ev, plo, phi, 3u), P.key0, P.key1);
+                    float cnd[10];
+                    call_condition(P, CF, ltc, ldep, xc, nx, ny, nz, cnd);
+                    int face;
+                    float xo, mo[kMlpOut];
+                    call_network<false>(mimg, mbias, mnorm, lane, wm, cnd, C, D, face, xo, mo);
+                    if (mlp) {
+                        int64_t *ebase = P.emis_raw ? P.emis_raw + (int64_t)cell * P.emis_nch : nullptr;
+                        call_apply(P, mnorm, cedges, CF, mo, face, xo, C.z, ltc, ldep, xc, vxc, vyc, vzc, fx, fy,
+                                   fz, nx, ny, nz, x, c_skip, c_drop,
+                                   [&](int ch, int64_t w) __attribute__((always_inline)) { emis_add(E, ch, w, ebase); });
+                        c_mlp += 1;
                     }
-                }
-                if (mlp) {
-                    const float lns = mo[kOutLogN] * mnorm[kMlpOut + kOutLogN] + mnorm[kOutLogN] +
-                                      mnorm[kNormCal + cal_bin(ltc, ldep, fabsf(xc))];
-                    const float lx2 = mo[kOutLogX2] * mnorm[kMlpOut + kOutLogX2] + mnorm[kOutLogX2];
-                    // offsets learned as asinh, the cosine as mu^2
-                    auto sinh_f = [](float v) { const float ev = f_exp(v); return 0.5f * (ev - f_rcp(ev)); };
-                    const float ys = sinh_f(mo[kOutYS] * mnorm[kMlpOut + kOutYS] + mnorm[kOutYS]);
-                    const float yt = sinh_f(mo[kOutYT] * mnorm[kMlpOut + kOutYT] + mnorm[kOutYT]);
-                    const float mu = f_sqrt(
-                        fminf(fmaxf(mo[kOutMu2] * mnorm[kMlpOut + kOutMu2] + mnorm[kOutMu2], 1e-6f), 1.0f));
-                    const float al = fminf(fmaxf(mo[kOutAlpha] * mnorm[kMlpOut + kOutAlpha] + mnorm[kOutAlpha], 0.0f),
-                                           3.14159265f);
-                    // exit point and direction in the reduced frame: face axis k, outward side
-                    const int k = face >> 1;
-                    const float side = (face & 1) ? 1.0f : -1.0f;
-                    const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
-                    const float qk = pick3(CF.q[0], CF.q[1], CF.q[2], k);
-                    const float qa = pick3(CF.q[0], CF.q[1], CF.q[2], k1);
-                    const float qb = pick3(CF.q[0], CF.q[1], CF.q[2], k2);
-                    const float dpl = 1.0f - side * qk;
-                    const float es = fminf(fmaxf(qa + dpl * ys, -1.0f), 1.0f);
-                    const float et = fminf(fmaxf(qb + dpl * yt, -1.0f), 1.0f);
-                    // tangential direction at angle +-alpha from the offset (es - qa, et - qb)
-                    const float ds = es - qa, dt = et - qb;
-                    const float rr = f_sqrt(ds * ds + dt * dt);
-                    const float ir = (rr > 0.0f) ? f_rcp(rr) : 0.0f;
-                    const float c0 = (rr > 0.0f) ? ds * ir : 1.0f, s0 = dt * ir;
-                    const float arev = al * 0.159154943f * ((C.z & 1u) ? -1.0f : 1.0f);
-                    const float ca = cos_rev(arev), sa = sin_rev(arev);
-                    const float sm = f_sqrt(fmaxf(0.0f, 1.0f - mu * mu));
-                    const float d1 = sm * (c0 * ca - s0 * sa), d2 = sm * (s0 * ca + c0 * sa);
-                    // back to the cell frame: reduced axis r is cell axis perm[r] with sign sg
-                    float pc[3] = {0.0f, 0.0f, 0.0f}, nc[3] = {0.0f, 0.0f, 0.0f};
-#pragma unroll
-                    for (int r = 0; r < 3; ++r) {
-                        const float R_ = (r == k) ? side : ((r == k1) ? es : et);
-                        const float V_ = (r == k) ? side * mu : ((r == k1) ? d1 : d2);
-                        const int axc = CF.perm[r];
-                        const float sgc = pick3(CF.sg[0], CF.sg[1], CF.sg[2], axc);
-#pragma unroll
-                        for (int a3 = 0; a3 < 3; ++a3)
-                            if (a3 == axc) { pc[a3] = sgc * R_; nc[a3] = sgc * V_; }
-                    }
-                    fx = fminf(fmaxf(0.5f * (pc[0] + 1.0f), 0.0f), 1.0f);
-                    fy = fminf(fmaxf(0.5f * (pc[1] + 1.0f), 0.0f), 1.0f);
-                    fz = fminf(fmaxf(0.5f * (pc[2] + 1.0f), 0.0f), 1.0f);
-                    nx = nc[0]; ny = nc[1]; nz = nc[2];
-                    const float Ns = fmaxf(f_exp(lns), 1.0f);  // E[N_s | condition]
-                    // emissivity of the skipped scatterings: thermalised core, camera
-                    // frequency ~ N(n_cam.v, (<x^2> + 1)/3), integrated exactly over the
-                    // channels (no sampling noise); mass outside the channels is dropped
-                    if (P.emis_raw) {
-                        const float sd = f_sqrt((f_exp(lx2) + 1.0f) * (1.0f / 3.0f));
-                        const float vc = P.n_cam[0] * vxc + P.n_cam[1] * vyc + P.n_cam[2] * vzc;
-                        const float isd = kInvSqrt2F * f_rcp(sd);
-                        const float W = Ns * P.frac_scale;
-                        int kb0 = bin_index(vc - 6.0f * sd, cedges, P.emis_nch, P.ch_inv_w);
-                        int kb1 = bin_index(vc + 6.0f * sd, cedges, P.emis_nch, P.ch_inv_w);
-                        kb0 = max(kb0, 1);
-                        kb1 = min(kb1, P.emis_nch);
-                        float cdf_lo = 0.5f * (1.0f + erff((cedges[kb0 - 1] - vc) * isd));
-                        float inside = 0.0f;
-                        int64_t *ebase = P.emis_raw + (int64_t)cell * P.emis_nch;
-                        for (int kb = kb0; kb <= kb1; ++kb) {
-                            float cdf_hi = 0.5f * (1.0f + erff((cedges[kb] - vc) * isd));
-                            float fr = cdf_hi - cdf_lo;
-                            cdf_lo = cdf_hi;
-                            inside += fr;
-                            int64_t wq = (int64_t)__float2ll_rn(W * fr);
-                            if (wq != 0) emis_add(E, kb - 1, wq, ebase);
-                        }
-                        c_drop += (int64_t)__float2ll_rn(Ns * fmaxf(0.0f, 1.0f - inside));
-                    }
-                    const float sx = (xc < 0.0f) ? -1.0f : 1.0f;
-                    x = sx * xo + nx * vxc + ny * vyc + nz * vzc;
-                    c_mlp += 1;
-                    c_skip += (int64_t)__float2ll_rn(Ns);
                 }
             }
         }
@@ -675,7 +803,7 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
         // ---- resonant scattering (event ev), divergent -----------------------
         if (scat) {
             const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
-            if (!kEsc) commit(q);  // the network variant committed above
+            if (!kEsc && !kPark) commit(q);  // the network modes committed above
             // next event
             ev += 1;
             if ((uint64_t)ev > P.max_events) {
@@ -744,8 +872,20 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
                 prepare((x - (nx * vxc + ny * vyc + nz * vzc)) * ((kProf == 3) ? sc : 1.0f), dr1, dr2, db, q);
                 flight(due, scat, xc);
             }
+            bool called = false;
+            if (kPark) {
+                CellFrame CF{};
+                float ltc = 0.0f, ldep = 0.0f;
+                called = scat && call_eligible(P, k0c, fx, fy, fz, xc, CF, ltc, ldep);
+                bool cont = false;
+                if (scat && !called) {
+                    commit(q);
+                    cont = ++seg >= P.park_budget;
+                }
+                park(called || cont, scat, xc, called ? 1u : 0u);
+            }
             if (scat) {
-                commit(q);
+                if (!kPark) commit(q);
                 ev += 1;
                 if ((uint64_t)ev > P.max_events) {
                     c_stuck += 1;
@@ -845,41 +985,134 @@ __global__ void debug_upar_kernel(const float *tab, float a, float thd, float x,
 }
 
 // ---------------------------------------------------------------- launch ---
-hipError_t launch_transport(const RunParams &P, int grid, int block, hipStream_t s) {
-    const bool esc = P.mlp_img != nullptr;
-    // plain: tables and both edge sets; network: tables, channel edges, image
+hipError_t launch_transport(const RunParams &P, int mode, int grid, int block, hipStream_t s) {
+    const bool fused = mode == kModeFused;
+    // plain and park: tables and both edge sets; fused: tables, channel edges, image
     static_assert(sizeof(float) * (kTabFloats + kChanEdgeFloats) + kMlpFwdBytes <= 160 * 1024,
                   "the network variant's LDS fits one CU (160 KiB)");
-    const size_t lds = esc ? sizeof(float) * (kTabFloats + kChanEdgeFloats) + (size_t)kMlpFwdBytes
-                           : sizeof(float) * (kTabFloats + kEdgeFloats);
-    // the network variant is compiled for the block size: up to 512 lanes 256
+    const size_t lds = fused ? sizeof(float) * (kTabFloats + kChanEdgeFloats) + (size_t)kMlpFwdBytes
+                             : sizeof(float) * (kTabFloats + kEdgeFloats);
+    // the fused variant is compiled for the block size: up to 512 lanes 256
     // VGPRs (no spills, 2 waves per SIMD; the default), up to 768 lanes 168
     // VGPRs (spills, 3 waves), above that 128 (4 waves, heavy spills).
-    // Profile modes 1 and 2 exist for the plain walk only.
-    const int variant = esc ? (block <= 512 ? 2 : (block <= 768 ? 5 : 1))
-                            : (P.tclass ? 6 : (P.profile_mode == 1 ? 3 : (P.profile_mode == 2 ? 4 : 0)));
-    static bool attr_set[7] = {false, false, false, false, false, false, false};
-    const void *fns[7] = {reinterpret_cast<const void *>(mc_transport_kernel<false, 1024>),
-                          reinterpret_cast<const void *>(mc_transport_kernel<true, 1024>),
-                          reinterpret_cast<const void *>(mc_transport_kernel<true, 512>),
-                          reinterpret_cast<const void *>(mc_transport_kernel<false, 1024, 1>),
-                          reinterpret_cast<const void *>(mc_transport_kernel<false, 1024, 2>),
-                          reinterpret_cast<const void *>(mc_transport_kernel<true, 768>),
-                          reinterpret_cast<const void *>(mc_transport_kernel<false, 1024, 3>)};
+    // Profile modes 1 and 2 exist for the plain walk only; park mode has the
+    // plain walk's register budget (1024 lanes).
+    const int variant = fused ? (block <= 512 ? 2 : (block <= 768 ? 5 : 1))
+                              : (mode == kModePark ? 7
+                                                   : (P.tclass ? 6 : (P.profile_mode == 1 ? 3
+                                                                      : (P.profile_mode == 2 ? 4 : 0))));
+    static bool attr_set[8] = {false, false, false, false, false, false, false, false};
+    const void *fns[8] = {reinterpret_cast<const void *>(mc_transport_kernel<kModePlain, 1024>),
+                          reinterpret_cast<const void *>(mc_transport_kernel<kModeFused, 1024>),
+                          reinterpret_cast<const void *>(mc_transport_kernel<kModeFused, 512>),
+                          reinterpret_cast<const void *>(mc_transport_kernel<kModePlain, 1024, 1>),
+                          reinterpret_cast<const void *>(mc_transport_kernel<kModePlain, 1024, 2>),
+                          reinterpret_cast<const void *>(mc_transport_kernel<kModeFused, 768>),
+                          reinterpret_cast<const void *>(mc_transport_kernel<kModePlain, 1024, 3>),
+                          reinterpret_cast<const void *>(mc_transport_kernel<kModePark, 1024>)};
     if (!attr_set[variant]) {
         hipError_t e = hipFuncSetAttribute(fns[variant], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_set[variant] = true;
     }
     switch (variant) {
-        case 0: hipLaunchKernelGGL((mc_transport_kernel<false, 1024>), dim3(grid), dim3(block), lds, s, P); break;
-        case 1: hipLaunchKernelGGL((mc_transport_kernel<true, 1024>), dim3(grid), dim3(block), lds, s, P); break;
-        case 2: hipLaunchKernelGGL((mc_transport_kernel<true, 512>), dim3(grid), dim3(block), lds, s, P); break;
-        case 3: hipLaunchKernelGGL((mc_transport_kernel<false, 1024, 1>), dim3(grid), dim3(block), lds, s, P); break;
-        case 5: hipLaunchKernelGGL((mc_transport_kernel<true, 768>), dim3(grid), dim3(block), lds, s, P); break;
-        case 6: hipLaunchKernelGGL((mc_transport_kernel<false, 1024, 3>), dim3(grid), dim3(block), lds, s, P); break;
-        default: hipLaunchKernelGGL((mc_transport_kernel<false, 1024, 2>), dim3(grid), dim3(block), lds, s, P); break;
+        case 0: hipLaunchKernelGGL((mc_transport_kernel<kModePlain, 1024>), dim3(grid), dim3(block), lds, s, P); break;
+        case 1: hipLaunchKernelGGL((mc_transport_kernel<kModeFused, 1024>), dim3(grid), dim3(block), lds, s, P); break;
+        case 2: hipLaunchKernelGGL((mc_transport_kernel<kModeFused, 512>), dim3(grid), dim3(block), lds, s, P); break;
+        case 3: hipLaunchKernelGGL((mc_transport_kernel<kModePlain, 1024, 1>), dim3(grid), dim3(block), lds, s, P); break;
+        case 5: hipLaunchKernelGGL((mc_transport_kernel<kModeFused, 768>), dim3(grid), dim3(block), lds, s, P); break;
+        case 6: hipLaunchKernelGGL((mc_transport_kernel<kModePlain, 1024, 3>), dim3(grid), dim3(block), lds, s, P); break;
+        case 7: hipLaunchKernelGGL((mc_transport_kernel<kModePark, 1024>), dim3(grid), dim3(block), lds, s, P); break;
+        default: hipLaunchKernelGGL((mc_transport_kernel<kModePlain, 1024, 2>), dim3(grid), dim3(block), lds, s, P); break;
     }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ call kernel ---
+// The network calls of parked packets, in place.  Every lane takes one record
+// (wave-strided over the list), so each evaluation runs on full 16-sample
+// blocks and no transport state is live around it.  The condition, the two
+// evaluations and the applied exit are the transport's own (call_eligible,
+// call_condition, call_network, call_apply); the skipped scatterings'
+// emissivity goes straight to the int64 tallies.
+constexpr int kCallThreads = 512;
+__global__ void __launch_bounds__(kCallThreads) escape_call_kernel(RunParams P, uint4 *rec, uint64_t n) {
+    extern __shared__ float4 lds4[];
+    float *cedges = reinterpret_cast<float *>(lds4);
+    {
+        for (int i = threadIdx.x; i <= P.emis_nch; i += blockDim.x) cedges[i] = P.ch_edges[i];
+        const float4 *ms = reinterpret_cast<const float4 *>(P.mlp_img);
+        float4 *md = lds4 + kChanEdgeFloats / 4;
+        for (int i = threadIdx.x; i < kMlpFwdBytes / 16; i += blockDim.x) md[i] = ms[i];
+    }
+    __syncthreads();
+    const unsigned char *mimg = reinterpret_cast<const unsigned char *>(lds4 + kChanEdgeFloats / 4);
+    const float *mbias = reinterpret_cast<const float *>(mimg + kTilesFwd * kTileBytes);
+    const float *mnorm = mbias + kBiasFloats;
+    const int lane = __lane_id();
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64);
+    int64_t c_mlp = 0, c_skip = 0, c_drop = 0;
+    for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) * 64; base < n;
+         base += waves * 64) {  // wave-uniform
+        const uint64_t i = base + (uint64_t)lane;
+        const bool live = i < n;
+        uint4 r0 = make_uint4(0u, 0u, 0u, 0u), r1 = r0, r2 = r0, r3 = r0;
+        if (live) {
+            const uint4 *r = rec + kParkQuads * i;
+            r0 = r[0]; r1 = r[1]; r2 = r[2]; r3 = r[3];
+        }
+        const int cell = (int)r0.w;
+        float fx = __uint_as_float(r1.x), fy = __uint_as_float(r1.y), fz = __uint_as_float(r1.z);
+        float x = __uint_as_float(r1.w);
+        float nx = __uint_as_float(r2.x), ny = __uint_as_float(r2.y), nz = __uint_as_float(r2.z);
+        float k0c = 0.0f, vxc = 0.0f, vyc = 0.0f, vzc = 0.0f;
+        if (live) {
+            k0c = P.k0[cell];
+            if (P.vx) { vxc = P.vx[cell]; vyc = P.vy[cell]; vzc = P.vz[cell]; }
+        }
+        // every record qualified when it was parked (the gas-frame frequency the
+        // transport tested is in the record): only the frame and depths are rebuilt
+        const float xc = __uint_as_float(r3.y);
+        CellFrame CF{};
+        float tc = 1.0f, dep = 1.0f;
+        if (live) call_frame(P, k0c, fx, fy, fz, CF, tc, dep);
+        const float ltc = __log10f(tc), ldep = __log10f(dep);
+        const bool ask = live && r3.z == 1u;  // kind 0: parked to continue, no call
+        const uint64_t am = __ballot(ask);
+        if (am == 0ull) continue;
+        const uint4 C = philox(make_uint4(r0.z, r0.x, r0.y, 2u), P.key0, P.key1);
+        const uint4 D = philox(make_uint4(r0.z, r0.x, r0.y, 3u), P.key0, P.key1);
+        float cnd[10];
+        call_condition(P, CF, ltc, ldep, xc, nx, ny, nz, cnd);
+        int face;
+        float xo, mo[kMlpOut];
+        call_network<true>(mimg, mbias, mnorm, lane, am, cnd, C, D, face, xo, mo);
+        if (ask) {
+            int64_t *ebase = P.emis_raw ? P.emis_raw + (int64_t)cell * P.emis_nch : nullptr;
+            call_apply(P, mnorm, cedges, CF, mo, face, xo, C.z, ltc, ldep, xc, vxc, vyc, vzc, fx, fy, fz, nx, ny, nz,
+                       x, c_skip, c_drop, [&](int ch, int64_t w) __attribute__((always_inline)) { tally_add_i64(ebase + ch, w); });
+            c_mlp += 1;
+            uint4 *r = rec + kParkQuads * i;
+            r[1] = make_uint4(__float_as_uint(fx), __float_as_uint(fy), __float_as_uint(fz), __float_as_uint(x));
+            r[2] = make_uint4(__float_as_uint(nx), __float_as_uint(ny), __float_as_uint(nz), r2.w);
+        }
+    }
+    wave_add_counter(P.counters + KRT_C_MLP_I, c_mlp);
+    wave_add_counter(P.counters + KRT_C_SKIPPED_I, c_skip);
+    wave_add_counter(P.counters + KRT_C_EMIS_DROP, c_drop);
+}
+
+hipError_t launch_escape_call(const RunParams &P, uint4 *rec, uint64_t n, int grid, hipStream_t s) {
+    static_assert(sizeof(float) * kChanEdgeFloats + kMlpFwdBytes <= 160 * 1024, "the call kernel's LDS fits one CU");
+    const size_t lds = sizeof(float) * kChanEdgeFloats + (size_t)kMlpFwdBytes;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(escape_call_kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(escape_call_kernel, dim3(grid), dim3(kCallThreads), lds, s, P, rec, n);
     return hipGetLastError();
 }
 

@@ -44,7 +44,9 @@ class krt_run_opts(C.Structure):
                 ("emis_frac_bits", C.c_int32), ("jbar_frac_bits", C.c_int32),
                 ("norm_packets", C.c_uint64), ("luminosity", C.c_double),
                 ("esc_tau_min", C.c_double), ("esc_cell_tau_min", C.c_double), ("esc_min_lanes", C.c_int32),
-                ("esc_tail_lanes", C.c_int32), ("tail_lanes", C.c_int32), ("profile_mode", C.c_int32)]
+                ("esc_tail_lanes", C.c_int32), ("tail_lanes", C.c_int32), ("profile_mode", C.c_int32),
+                ("esc_park", C.c_int32), ("esc_park_cap", C.c_uint32), ("esc_park_tail", C.c_uint32),
+                ("esc_park_budget", C.c_uint32)]
 
 
 class krt_escape_cond(C.Structure):
@@ -75,6 +77,7 @@ class krt_image_desc(C.Structure):
 
 
 EXPORTS = ["krt_create", "krt_destroy", "krt_last_error", "krt_device_cus", "krt_last_transport_ms",
+           "krt_last_network_ms", "krt_last_rounds",
            "krt_grid_upload",
            "krt_tables_build", "krt_mc_run", "krt_mc_run_noalloc", "krt_levels_update", "krt_debug_philox",
            "krt_debug_bins", "krt_debug_voigt", "krt_debug_voigt_analytic", "krt_debug_upar",
@@ -105,6 +108,10 @@ def load(path: str = LIB_PATH):
     L.krt_device_cus.restype = C.c_int
     L.krt_last_transport_ms.argtypes = [p]
     L.krt_last_transport_ms.restype = C.c_double
+    L.krt_last_network_ms.argtypes = [p]
+    L.krt_last_network_ms.restype = C.c_double
+    L.krt_last_rounds.argtypes = [p]
+    L.krt_last_rounds.restype = C.c_int64
     L.krt_grid_upload.argtypes = [p, C.POINTER(krt_grid_desc)]
     L.krt_tables_build.argtypes = [p, C.POINTER(krt_line_desc), C.c_int]
     L.krt_mc_run.argtypes = [p, u64, u64, C.POINTER(krt_run_opts), C.POINTER(krt_tallies)]
@@ -187,6 +194,12 @@ class Context:
 
     def krt_last_transport_ms(self) -> float:
         return self.L.krt_last_transport_ms(self.h)
+
+    def krt_last_network_ms(self) -> float:
+        return self.L.krt_last_network_ms(self.h)
+
+    def krt_last_rounds(self) -> int:
+        return int(self.L.krt_last_rounds(self.h))
 
     # ------------------------------------------------------------- calls
     def krt_grid_upload(self, n, lo, hi, bc, k0, vel=None, eps=None, emis=None, n_lines=1, tclass=None,
@@ -316,7 +329,8 @@ class Context:
 def make_opts(prob: dict, *, line=0, packet_offset=0, accumulate=False, max_events=0,
               wg_size=0, wg_per_cu=0, emis_frac_bits=0, jbar_frac_bits=0, norm_packets=0, escape_mode=0,
               luminosity=0.0, esc_tau_min=0.0, esc_cell_tau_min=0.0, esc_min_lanes=0, esc_tail_lanes=0,
-              tail_lanes=0, profile_mode=0) -> krt_run_opts:
+              tail_lanes=0, profile_mode=0, esc_park=0, esc_park_cap=0, esc_park_tail=0,
+              esc_park_budget=0) -> krt_run_opts:
     """krt_run_opts from a workload problem dict (paper_2608_09340_amd.workloads)."""
     o = krt_run_opts()
     src, t = prob["source"], prob["tally"]
@@ -349,6 +363,10 @@ def make_opts(prob: dict, *, line=0, packet_offset=0, accumulate=False, max_even
     o.esc_cell_tau_min = float(esc_cell_tau_min)
     o.esc_min_lanes = int(esc_min_lanes)
     o.esc_tail_lanes = int(esc_tail_lanes)
+    o.esc_park = int(esc_park)
+    o.esc_park_cap = int(esc_park_cap)
+    o.esc_park_tail = int(esc_park_tail)
+    o.esc_park_budget = int(esc_park_budget)
     o.profile_mode = int(profile_mode)
     o.tail_lanes = int(tail_lanes)
     return o
