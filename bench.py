@@ -87,9 +87,11 @@ def kernel_source_sha256() -> str:
     return h.hexdigest()
 
 
-def profiled_traffic(path=None):
+def profiled_traffic(path=None, packets=None):
     """HBM bytes per launch from a committed counter summary, or None when the
-    kernel sources changed since it was taken."""
+    kernel sources changed since it was taken.  A summary taken at fewer
+    packets than the timed launch gives bytes per packet (the transport's
+    traffic is per packet: its tallies and field gathers), scaled to `packets`."""
     path = path or PROFILE_SUMMARY
     try:
         kv = {}
@@ -99,6 +101,8 @@ def profiled_traffic(path=None):
                 kv[k.strip()] = v.strip().strip("`")
         if kv.get("kernel_source_sha256") != kernel_source_sha256():
             return None
+        if packets is not None and "hbm_bytes_per_packet" in kv:
+            return float(kv["hbm_bytes_per_packet"]) * packets
         return float(kv["hbm_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         return None
@@ -236,8 +240,8 @@ def headline_c4(ctx, args):
         "value": scat_plain * K / wall, "K": K, "W": warm, "wall": wall,
         "kernel_ms": km,
         "roofline": {"bound": "alu", "achieved": valu, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
-                     "frac": valu / PEAK_VALU_TOPS, "traffic": profiled_traffic(PROFILE_SUMMARY_LEARNED),
-                     "kernel": "mc_transport_kernel<true, 512> (learned escape)",
+                     "frac": valu / PEAK_VALU_TOPS, "traffic": profiled_traffic(PROFILE_SUMMARY_LEARNED, N),
+                     "kernel": "mc_transport_kernel<1, 512> (learned escape, fused)",
                      "ops_per_scattering": ledger_per_scatter(False, True),
                      "mfma": {"achieved": mfma, "peak": PEAK_MFMA_BF16_TFLOPS, "unit": "TFLOP/s",
                               "frac": mfma / PEAK_MFMA_BF16_TFLOPS,

@@ -327,7 +327,7 @@ int krt_levels_update(krt_ctx *ctx, const krt_levels_desc *desc,
                       const float *jbar_dev /* [nl-1][ncell], NULL = no radiation */);
 
 /* ------------------------------------------------------- learned escape --- */
-/* A small network (24 -> 3 x 128 SiLU -> 16, BF16 weights and activations,
+/* A small network (24 -> 3 x 128 leaky ReLU -> 32, BF16 weights and activations,
  * FP32 accumulation on MFMA) replaces the random walk of a photon inside one
  * homogeneous cubic cell: at a scattering in a cell whose line-centre depth
  * k0 dx is at least esc_cell_tau_min, at least esc_tau_min (line-centre) below

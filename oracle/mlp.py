@@ -1,7 +1,8 @@
 """FP64 CPU reference of the whole-cell escape network -- TEST INFRASTRUCTURE.
 
 Same parameter layout as the GPU (one flat vector): W1[24][128], b1[128],
-W2[128][128], b2, W3[128][128], b3, W4[128][32], b4[32]; activations SiLU.
+W2[128][128], b2, W3[128][128], b3, W4[128][32], b4[32]; hidden activations
+leaky ReLU max(z, z/16).
 
 The network describes how a photon that scatters inside a homogeneous static
 cubic cell leaves it (the plain walk of Sec. 2.1-2.3 confined to one cell; the
@@ -151,13 +152,16 @@ def levels(u, cond):
     return U
 
 
-def silu(z):
-    return z / (1.0 + np.exp(-z))
+LEAK = 0.0625
 
 
-def dsilu(z):
-    s = 1.0 / (1.0 + np.exp(-z))
-    return s * (1.0 + z * (1.0 - s))
+def act(z):
+    """Hidden activation: leaky ReLU max(z, z / 16)."""
+    return np.maximum(z, LEAK * z)
+
+
+def dact(z):
+    return np.where(z > 0.0, 1.0, LEAK)
 
 
 def forward(p, X, bf=False):
@@ -174,7 +178,7 @@ def forward(p, X, bf=False):
             z = z + r(X[:, 10:14] - h[:, 10:14]) @ W["W1"][10:14]
         cache[f"z{i}"] = z
         cache[f"h{i - 1}"] = h
-        h = r(silu(z))
+        h = r(act(z))
     cache["h3"] = h
     out = h @ W["W4"] + W["b4"]
     return out, cache, W
@@ -236,7 +240,7 @@ def loss_and_grad(p, X, Y, U, bf=False, s9=1.0):
     g = {"W4": c["h3"].T @ d, "b4": d.sum(0)}
     dh = d @ W["W4"].T
     for i in (3, 2, 1):
-        dz = dh * dsilu(c[f"z{i}"])
+        dz = dh * dact(c[f"z{i}"])
         g[f"W{i}"] = c[f"h{i - 1}"].T @ dz
         g[f"b{i}"] = dz.sum(0)
         dh = dz @ W[f"W{i}"].T

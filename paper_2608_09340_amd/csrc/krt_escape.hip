@@ -288,7 +288,7 @@ __device__ __forceinline__ bool used_output(int k) { return k <= kOutAlpha || (k
 
 // ----------------------------------------------------- forward + backward ---
 // Activation store of a training step, bf16 [row][cap] (samples contiguous):
-// H0 32 rows (inputs, row 24 = 1 for the bias), H1..H3 144 rows (SiLU
+// H0 32 rows (inputs, row 24 = 1 for the bias), H1..H3 144 rows (leaky ReLU
 // activations, row 128 = 1), dZ1..dZ3 128 rows, dZ4 32 rows.  The constant
 // rows are written once when the store is allocated.
 constexpr int kActRowsH0 = 32, kActRowsH = 144;
@@ -395,7 +395,6 @@ __global__ void __launch_bounds__(256) mlp_fwdbwd_kernel(const unsigned char *bl
     if (lane == 0 && loss) atomicAdd(loss, lsum * invB);
 
     // ---- backward through the layers (dZ4 = dO)
-    auto dsilu = [](float z) { float sg = sigmoid_f(z); return sg * (1.0f + z * (1.0f - sg)); };
     const int64_t col = (int64_t)block * 16 + s;
     auto store4 = [&](int row0, float a0, float a1, float a2, float a3) {  // rows row0 + 4g + j
         uint16_t *p = act + (int64_t)(row0 + 4 * g) * cap + col;
@@ -417,9 +416,9 @@ __global__ void __launch_bounds__(256) mlp_fwdbwd_kernel(const unsigned char *bl
     for (int mi = 0; mi < 8; ++mi) {
         v4f32 acc = {0.f, 0.f, 0.f, 0.f};
         acc = mfma32(tileA(blob, kTileBwdL4 + mi, lane), dOb, acc);
-        dz[mi] = (v4f32){acc.x * dsilu(z3[mi].x), acc.y * dsilu(z3[mi].y), acc.z * dsilu(z3[mi].z),
-                         acc.w * dsilu(z3[mi].w)};
-        store4(kActH3 + 16 * mi, silu(z3[mi].x), silu(z3[mi].y), silu(z3[mi].z), silu(z3[mi].w));
+        dz[mi] = (v4f32){acc.x * dleaky(z3[mi].x), acc.y * dleaky(z3[mi].y), acc.z * dleaky(z3[mi].z),
+                         acc.w * dleaky(z3[mi].w)};
+        store4(kActH3 + 16 * mi, leaky(z3[mi].x), leaky(z3[mi].y), leaky(z3[mi].z), leaky(z3[mi].w));
         store4(kActZ3 + 16 * mi, dz[mi].x, dz[mi].y, dz[mi].z, dz[mi].w);
     }
     // layer 3 -> dZ2, layer 2 -> dZ1 (unrolled so the activations stay in registers)
@@ -435,8 +434,8 @@ __global__ void __launch_bounds__(256) mlp_fwdbwd_kernel(const unsigned char *bl
 #pragma unroll
             for (int c = 0; c < 4; ++c) acc = mfma32(tileA(blob, tb + mi * 4 + c, lane), cat8(dzb[2 * c], dzb[2 * c + 1]), acc);
             const v4f32 zin = (layer == 3) ? z2[mi] : z1[mi];
-            dz[mi] = (v4f32){acc.x * dsilu(zin.x), acc.y * dsilu(zin.y), acc.z * dsilu(zin.z), acc.w * dsilu(zin.w)};
-            store4((layer == 3 ? kActH2 : kActH1) + 16 * mi, silu(zin.x), silu(zin.y), silu(zin.z), silu(zin.w));
+            dz[mi] = (v4f32){acc.x * dleaky(zin.x), acc.y * dleaky(zin.y), acc.z * dleaky(zin.z), acc.w * dleaky(zin.w)};
+            store4((layer == 3 ? kActH2 : kActH1) + 16 * mi, leaky(zin.x), leaky(zin.y), leaky(zin.z), leaky(zin.w));
             store4((layer == 3 ? kActZ2 : kActZ1) + 16 * mi, dz[mi].x, dz[mi].y, dz[mi].z, dz[mi].w);
         }
     }

@@ -9,7 +9,7 @@
 // direction reflected and permuted alike, and |x_in| (the medium is symmetric
 // under x -> -x, so the exit frequency takes x_in's sign).
 //
-// Network: 24 inputs -> 128 -> 128 -> 128 (SiLU) -> 32 outputs.
+// Network: 24 inputs -> 128 -> 128 -> 128 (leaky ReLU) -> 32 outputs.
 // Inputs: 0 (log10 tau_c - 3)/1.2 (tau_c the line-centre depth centre to face),
 //   1 log10 a + 3, 2 |x_in| - 1, 3-5 2 q - 1, 6 (log10 depth - 2)/1.2 (depth
 //   tau_c (1 - q2) to the nearest face), 7-9 incoming direction, 10-13 quantile
@@ -30,7 +30,7 @@
 //   they remove the offsets' heavy tails and the steep quantile function of
 //   mu near 0.
 //
-// Layers run transposed, H^T_{l+1} = SiLU(W_l^T H^T_l + b_l), on 16-sample
+// Layers run transposed, H^T_{l+1} = leaky(W_l^T H^T_l + b_l), on 16-sample
 // blocks with v_mfma_f32_16x16x32_bf16.  The accumulator of a 16-feature tile
 // leaves lane l with features 4(l/16)+r of sample l%16; the B operand of the
 // next layer wants 8 features per lane.  The reduction index of each 32-wide
@@ -147,23 +147,30 @@ typedef short v8i16 __attribute__((ext_vector_type(8)));
 typedef __bf16 v8bf16 __attribute__((ext_vector_type(8)));
 typedef float v4f32 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint16_t f2bf(float f) {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
-    return (uint16_t)(u >> 16);
-}
+typedef __bf16 v2bf16 __attribute__((ext_vector_type(2)));
+typedef float v2f32 __attribute__((ext_vector_type(2)));
 
-// logistic(z) from the hardware exp2 and reciprocal (about 1 ulp each; the
-// activations are stored as bfloat16, 8 significant bits)
+// float -> bfloat16, round to nearest even: one v_cvt_pk_bf16_f32 per pair
+__device__ __forceinline__ uint32_t pack2(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((v2f32){a, b}, v2bf16));
+}
+__device__ __forceinline__ uint16_t f2bf(float f) { return (uint16_t)(pack2(f, 0.0f) & 0xFFFFu); }
+
+// logistic(z) from the hardware exp2 and reciprocal (about 1 ulp each)
 __device__ __forceinline__ float sigmoid_f(float z) {
     return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.44269504088896f * z));
 }
-__device__ __forceinline__ float silu(float z) { return z * sigmoid_f(z); }
+// Hidden activation: leaky ReLU, max(z, z / 16), and its derivative.  Two
+// full-rate instructions per value: the network runs inside the transport
+// kernel, where a transcendental activation (SiLU: an exp and a reciprocal,
+// quarter rate each) cost more issue cycles than the matrix products.
+constexpr float kLeak = 0.0625f;
+__device__ __forceinline__ float leaky(float z) { return fmaxf(z, kLeak * z); }
+__device__ __forceinline__ float dleaky(float z) { return z > 0.0f ? 1.0f : kLeak; }
 
 __device__ __forceinline__ v4i16 pack4(float a, float b, float c, float d) {
-    v4i16 r;
-    r.x = (short)f2bf(a); r.y = (short)f2bf(b); r.z = (short)f2bf(c); r.w = (short)f2bf(d);
-    return r;
+    const uint32_t lo = pack2(a, b), hi = pack2(c, d);
+    return (v4i16){(short)(lo & 0xFFFFu), (short)(lo >> 16), (short)(hi & 0xFFFFu), (short)(hi >> 16)};
 }
 
 __device__ __forceinline__ v8i16 cat8(v4i16 a, v4i16 b) { return __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7); }
@@ -191,12 +198,11 @@ __device__ __forceinline__ v8i16 tileA(const unsigned char *blob, int t, int lan
 // a window of 8 registers: product i reads slot i % 8 and the same slot is
 // refilled at once with tile i + 8, so every LDS read is issued 8 products
 // (about 130 cycles of matrix work) before its use and only 8 tiles are live.
-// A scheduling barrier after each step keeps that order (kPinned); left free,
-// the compiler sinks each read to just before its product and waits on it.
-// Inside the fused transport kernel, whose packet state fills the register
-// file, the pinned order spills more, so that kernel only asks for alternating
-// products and reads (kPinned = false).
-// A layer's epilogue applies SiLU, packs the bf16 activations and loads the
+// A scheduling barrier after each step keeps that order; left free, the
+// compiler sinks each read to just before its product and waits on it (on the
+// turbulent cloud the pinned order makes the fused transport kernel 7% faster
+// for 20 bytes of spill per lane).
+// A layer's epilogue applies the activation, packs the bf16 activations and loads the
 // next layer's biases into the freed accumulators.
 __host__ __device__ constexpr int fwd_tile(int i) {
     return i < 8    ? kTileFwdL1 + i
@@ -209,7 +215,6 @@ static_assert(kTilesFwd == kFwdSteps, "one product per forward tile");
 
 __device__ __forceinline__ v4f32 ld4(const float *p) { return *reinterpret_cast<const v4f32 *>(p); }
 
-template <bool kPinned = true>
 __device__ __forceinline__ void mlp_forward_block(const unsigned char *tiles, const float *bias, v8i16 xin,
                                                   int lane, v4f32 *z1, v4f32 *z2, v4f32 *z3, v4f32 &oa, v4f32 &ob) {
     const int g = lane >> 4;
@@ -225,14 +230,7 @@ __device__ __forceinline__ void mlp_forward_block(const unsigned char *tiles, co
     do {                                                                                \
         (c) = mfma32(w[(i) % 8], (bop), (c));                                           \
         if ((i) + 8 < kFwdSteps) w[(i) % 8] = tileA(tiles, fwd_tile((i) + 8), lane);    \
-        if (kPinned) {                                                                  \
-            __builtin_amdgcn_sched_barrier(0);                                          \
-        } else if ((i) + 8 < kFwdSteps) {                                               \
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                          \
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);                          \
-        } else {                                                                        \
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                          \
-        }                                                                               \
+        __builtin_amdgcn_sched_barrier(0);                                              \
     } while (0)
     // layer 1: one chunk (the inputs)
 #pragma unroll
@@ -240,7 +238,7 @@ __device__ __forceinline__ void mlp_forward_block(const unsigned char *tiles, co
 #pragma unroll
     for (int mo = 0; mo < 8; ++mo) {
         if (z1) z1[mo] = acc[mo];
-        h[mo] = pack4(silu(acc[mo].x), silu(acc[mo].y), silu(acc[mo].z), silu(acc[mo].w));
+        h[mo] = pack4(leaky(acc[mo].x), leaky(acc[mo].y), leaky(acc[mo].z), leaky(acc[mo].w));
         acc[mo] = ld4(bias + kMlpHid + 16 * mo + 4 * g);
     }
     // layers 2 and 3
@@ -257,7 +255,7 @@ __device__ __forceinline__ void mlp_forward_block(const unsigned char *tiles, co
 #pragma unroll
         for (int mo = 0; mo < 8; ++mo) {
             if (zs) zs[mo] = acc[mo];
-            h[mo] = pack4(silu(acc[mo].x), silu(acc[mo].y), silu(acc[mo].z), silu(acc[mo].w));
+            h[mo] = pack4(leaky(acc[mo].x), leaky(acc[mo].y), leaky(acc[mo].z), leaky(acc[mo].w));
             if (layer == 0) acc[mo] = ld4(bias + 2 * kMlpHid + 16 * mo + 4 * g);
         }
     }
@@ -329,7 +327,7 @@ constexpr int kMlpPackDw = kMlpOperandIn / 2;
 __device__ __forceinline__ void pack_inputs(const float in[kMlpIn], uint32_t pk[kMlpPackDw]) {
 #pragma unroll
     for (int d = 0; d < kMlpPackDw; ++d)
-        pk[d] = (uint32_t)f2bf(operand_in(in, 2 * d)) | ((uint32_t)f2bf(operand_in(in, 2 * d + 1)) << 16);
+        pk[d] = pack2(operand_in(in, 2 * d), operand_in(in, 2 * d + 1));
 }
 
 // ------------------------------------------------------ the reduced frame ---

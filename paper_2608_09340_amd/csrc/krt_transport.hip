@@ -93,7 +93,6 @@ __device__ __forceinline__ int nth_set_lane(uint64_t m, int k) {
 // wave-uniform `want` (a subset of kMlpFetch) in out[k] (the others keep their
 // values).
 constexpr uint32_t kMlpFetch = 0x003F1FFFu;  // outputs 0-12 and 16-21: all the transport reads
-template <bool kPinned>
 __device__ __forceinline__ void mlp_eval_wave(const unsigned char *img, const float *bias, const uint32_t pk[kMlpPackDw],
                                               int lane, uint64_t ask, uint32_t want, float out[kMlpOut]) {
     const int nask = __popcll(ask);
@@ -120,7 +119,7 @@ __device__ __forceinline__ void mlp_eval_wave(const unsigned char *img, const fl
         const v4i16 hi = {(short)(use ? w[2] & 0xFFFFu : 0u), (short)(use ? w[2] >> 16 : 0u),
                           (short)(use ? w[3] & 0xFFFFu : 0u), (short)(use ? w[3] >> 16 : 0u)};
         v4f32 oa, ob;
-        mlp_forward_block<kPinned>(img, bias, cat8(lo, hi), lane, nullptr, nullptr, nullptr, oa, ob);
+        mlp_forward_block(img, bias, cat8(lo, hi), lane, nullptr, nullptr, nullptr, oa, ob);
         // output k of block position p sits in lane 16 ((k % 16) / 4) + p,
         // component k % 4, of tile k / 16
         const bool take = mine && (rank >> 4) == b;
@@ -171,7 +170,6 @@ __device__ __forceinline__ bool call_eligible(const RunParams &P, float k0c, flo
 // x_out (offsets, cosine, alpha at the levels of D).  cnd: the raw condition
 // (log10 tau_c, log10 a, |x_in|, q0, q1, q2, log10 depth, incoming direction in
 // the reduced frame).  xo carries x_in's sign convention (reduced frame).
-template <bool kPinned>
 __device__ __forceinline__ void call_network(const unsigned char *mimg, const float *mbias, const float *mnorm,
                                              int lane, uint64_t ask, const float cnd[10], uint4 C, uint4 D,
                                              int &face, float &xo, float mo[kMlpOut]) {
@@ -186,7 +184,7 @@ __device__ __forceinline__ void call_network(const unsigned char *mimg, const fl
         if (e == 0) mlp_inputs(cnd, u01(C.x), u01(C.y), u01(D.z), u01(D.w), false, 0.0f, 0, in);
         else mlp_inputs(cnd, u01(D.x), u01(D.y), u01(D.z), u01(D.w), true, xo, face, in);
         pack_inputs(in, pk);
-        mlp_eval_wave<kPinned>(mimg, mbias, pk, lane, ask, e == 0 ? 0x003F01FFu : 0x00001E00u, mo);
+        mlp_eval_wave(mimg, mbias, pk, lane, ask, e == 0 ? 0x003F01FFu : 0x00001E00u, mo);
         if (e == 0) {
             float mx = mo[0];
 #pragma unroll
@@ -215,6 +213,19 @@ __device__ __forceinline__ void call_network(const unsigned char *mimg, const fl
             xo = pos ? mag : -mag;
         }
     }
+}
+
+// erf by the rational approximation of Abramowitz & Stegun (Handbook of
+// Mathematical Functions, 7.1.26; absolute error at most 1.5e-7): one
+// reciprocal and one exp instead of the library's longer evaluation.  It
+// integrates the skipped scatterings' Gaussian over the channels, whose
+// weights carry about 1e-7 of their own rounding.
+__device__ __forceinline__ float erf_fast(float x) {
+    const float ax = fabsf(x);
+    const float t = f_rcp(fmaf(0.3275911f, ax, 1.0f));
+    const float p = fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f),
+                         0.254829592f);
+    return copysignf(1.0f - t * p * f_exp(-ax * ax), x);
 }
 
 // The sampled exit applied to the packet: the exit point on the face (cell
@@ -284,10 +295,10 @@ __device__ __forceinline__ void call_apply(const RunParams &P, const float *mnor
         int kb1 = bin_index(vc + 6.0f * sd, cedges, P.emis_nch, P.ch_inv_w);
         kb0 = max(kb0, 1);
         kb1 = min(kb1, P.emis_nch);
-        float cdf_lo = 0.5f * (1.0f + erff((cedges[kb0 - 1] - vc) * isd));
+        float cdf_lo = 0.5f * (1.0f + erf_fast((cedges[kb0 - 1] - vc) * isd));
         float inside = 0.0f;
         for (int kb = kb0; kb <= kb1; ++kb) {
-            const float cdf_hi = 0.5f * (1.0f + erff((cedges[kb] - vc) * isd));
+            const float cdf_hi = 0.5f * (1.0f + erf_fast((cedges[kb] - vc) * isd));
             const float fr = cdf_hi - cdf_lo;
             cdf_lo = cdf_hi;
             inside += fr;
@@ -788,7 +799,7 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
                     call_condition(P, CF, ltc, ldep, xc, nx, ny, nz, cnd);
                     int face;
                     float xo, mo[kMlpOut];
-                    call_network<false>(mimg, mbias, mnorm, lane, wm, cnd, C, D, face, xo, mo);
+                    call_network(mimg, mbias, mnorm, lane, wm, cnd, C, D, face, xo, mo);
                     if (mlp) {
                         int64_t *ebase = P.emis_raw ? P.emis_raw + (int64_t)cell * P.emis_nch : nullptr;
                         call_apply(P, mnorm, cedges, CF, mo, face, xo, C.z, ltc, ldep, xc, vxc, vyc, vzc, fx, fy,
@@ -1086,7 +1097,7 @@ __global__ void __launch_bounds__(kCallThreads) escape_call_kernel(RunParams P, 
         call_condition(P, CF, ltc, ldep, xc, nx, ny, nz, cnd);
         int face;
         float xo, mo[kMlpOut];
-        call_network<true>(mimg, mbias, mnorm, lane, am, cnd, C, D, face, xo, mo);
+        call_network(mimg, mbias, mnorm, lane, am, cnd, C, D, face, xo, mo);
         if (ask) {
             int64_t *ebase = P.emis_raw ? P.emis_raw + (int64_t)cell * P.emis_nch : nullptr;
             call_apply(P, mnorm, cedges, CF, mo, face, xo, C.z, ltc, ldep, xc, vxc, vyc, vzc, fx, fy, fz, nx, ny, nz,

