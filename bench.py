@@ -442,6 +442,8 @@ def main():
                     help="scales the training steps (counter-collection runs, where every dispatch is slow)")
     ap.add_argument("--legs", default="", help="comma-separated extra legs run after the headline line: "
                                                + ",".join(LEGS))
+    ap.add_argument("--legs-only", action="store_true",
+                    help="run only the --legs (no headline line; counter runs of one leg)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (calibrates FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
@@ -469,6 +471,9 @@ def main():
         return
 
     ctx = krt.Context(0)
+    if args.legs_only:
+        print(json.dumps({"legs": {name: LEGS[name](ctx) for name in legs}}), flush=True)
+        return
     h = headline_c4(ctx, args)
     out = {
         "metric": "scatterings/s on 1 MI355X, plain vs MLP-escape at spectrum L1<=2% vs oracle",

@@ -87,7 +87,8 @@ int64_t krt_last_rounds(const krt_ctx *ctx);
  * Errors: KRT_EINVAL for n <= 0, hi <= lo, bad bc, n_lines outside 1..8,
  * k0 == NULL, ncell >= 2^31, or (with tclass_dev) n_tclass outside 1..8, a
  * ratio outside [0.05, 20] or a class index >= n_tclass (the indices are
- * copied to the host once and checked at upload). */
+ * copied to the host once and checked at upload), or (with bratio_dev) a
+ * ratio outside [0.05, 20] or tclass_dev set as well. */
 typedef struct {
     int32_t n[3];
     double lo[3], hi[3];
@@ -112,6 +113,16 @@ typedef struct {
     const uint8_t *tclass_dev;
     int32_t n_tclass;          /* 1..8 when tclass_dev is set */
     double tclass_bratio[8];
+    /* Per-cell temperature as a continuum (Sec. 2.2.1: the two-dimensional Voigt
+     * table over 64 logarithmically spaced damping values): bratio_dev [ncell]
+     * b_cell / b_ref per cell (finite, 0.05..20), or NULL; not together with
+     * tclass_dev.  Frequencies, damping and units as for the classes, each cell
+     * with its own width; the opacity H(a_cell, x) is interpolated linearly in
+     * ln a between 64 Voigt tables at log-spaced damping values spanning the
+     * grid's range, and u_par is drawn from the sampler tables at the nearest
+     * of 16 log-spaced damping values.  Plain walk with profile_mode 0 only;
+     * the values are copied to the host once at upload, for their range. */
+    const float *bratio_dev;
 } krt_grid_desc;
 int krt_grid_upload(krt_ctx *ctx, const krt_grid_desc *desc);
 
@@ -165,10 +176,8 @@ typedef struct {
     double esc_cell_tau_min;   /* ... and only in cells of line-centre depth k0 dx at least this
                                   (0 = 100); both are raised to the smallest values the network's
                                   training records covered */
-    int32_t esc_min_lanes;     /* network call when at least this many lanes of a wave ask (0 = 8).
-                                  Which scatterings take the network then depends on the packets
-                                  sharing a wave, so escape_mode = 1 tallies are statistically,
-                                  not bitwise, independent of launch geometry */
+    int32_t esc_min_lanes;     /* network call when at least this many lanes of a wave ask (0 = 24);
+                                  see esc_wait for the lanes that find fewer */
     int32_t esc_tail_lanes;    /* as esc_min_lanes once the packet pool is exhausted (0 = 1):
                                   the wave then lives only as long as its slowest packet */
     int32_t tail_lanes;        /* plain transport: once the pool is exhausted, a wave with at most
@@ -202,6 +211,17 @@ typedef struct {
     uint32_t esc_park_budget;  /* park: a packet that takes this many plain scatterings in one round
                                   is parked after the last of them and resumes in the next round
                                   (0 = 256), so no round waits on one long walk */
+    int32_t esc_wait;          /* fused: a lane whose scattering qualifies while fewer than
+                                  esc_min_lanes lanes of its wave ask holds the scattering and
+                                  waits for a batch, for at most this many loop iterations (0 = 16;
+                                  a batch also goes when every live lane of the wave asks).  Every
+                                  qualifying scattering then takes the network with its own
+                                  event's draws, so the tallies do not depend on launch geometry
+                                  or batching and equal esc_min_lanes = 1's bit for bit.
+                                  Negative: no waiting -- the lane walks that scattering and asks
+                                  again at its next one, so which scatterings take the network
+                                  depends on the packets sharing a wave (tallies statistically,
+                                  not bitwise, reproducible) */
 } krt_run_opts;
 
 /* Caller-allocated DEVICE buffers.  Raw tallies are int64 fixed point, so their
@@ -445,6 +465,14 @@ int krt_debug_bins(krt_ctx *ctx, const float *x_dev, int64_t n, int32_t nb, doub
  * x[i] for damping a (u0 from a as krt_mc_run computes it); device arrays. */
 int krt_debug_voigt_analytic(krt_ctx *ctx, double a, const float *x, int64_t n, float *out);
 int krt_debug_voigt(krt_ctx *ctx, int32_t line, const float *x_dev, int64_t n, float *out_dev);
+/* krt_debug_voigt_cont: out[i] = H(a_line b_ref / b, x[i]) at the width ratio
+ * r[i] = b / b_ref (within the uploaded grid's range) as the transport of a
+ * grid with per-cell widths (bratio_dev) evaluates it: the two neighbouring
+ * Voigt tables of the 64 log-spaced damping nodes, interpolated linearly in
+ * ln a (Sec. 2.2.1's two-dimensional table).  Device arrays of n floats;
+ * KRT_ESTATE without such a grid or tables for the line. */
+int krt_debug_voigt_cont(krt_ctx *ctx, int32_t line, const float *r_dev, const float *x_dev, int64_t n,
+                         float *out_dev);
 int krt_debug_upar(krt_ctx *ctx, int32_t line, float x, uint64_t seed, uint64_t packet,
                    uint32_t ev0, int64_t n, float *out_dev);
 

@@ -7,7 +7,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "krt.h"
@@ -37,6 +39,15 @@ struct krt_ctx {
     float4 *cls_par = nullptr;
     int cls_line = -1;
     double cls_key[9] = {0};
+    // continuous per-cell temperature: the grid's range of b / b_ref, the Voigt
+    // blocks [kContVoigtN + 1][kVoigtFloats], sampler blocks [kContSampN][kTabFloats]
+    // and their (damping, threshold), built for one line (cache key: a, range)
+    float br_lo = 1.0f, br_hi = 1.0f;
+    float *cv_tab = nullptr, *cs_tab = nullptr;
+    float2 *cs_par = nullptr;
+    int cont_n_v = 0, cont_n_s = 0;
+    double cont_lna0 = 0.0, cont_inv_v = 0.0, cont_inv_s = 0.0;
+    double cont_key[3] = {-1.0, 0.0, 0.0};
     std::vector<krt_line_desc> lines;
     // scratch
     unsigned long long *work_counter = nullptr;
@@ -104,6 +115,7 @@ void free_tables(krt_ctx *c) {
     c->tab.clear();
     c->lines.clear();
     c->cls_line = -1;  // class tables follow the line tables
+    c->cont_key[0] = -1.0;  // and so do the continuum's
 }
 
 // Table sets of the grid's temperature classes for line l (damping
@@ -129,6 +141,73 @@ static int ensure_class_tables(krt_ctx *c, int l) {
     c->cls_line = l;
     std::copy(key, key + 9, c->cls_key);
     return KRT_OK;
+}
+
+// Table blocks of a continuum of cell temperatures for line l: kContVoigtN
+// Voigt blocks and kContSampN sampler blocks at damping values log-spaced over
+// [a_l / br_hi, a_l / br_lo] (one node of each when the grid has one width),
+// built on the host threads in parallel (the FP64 Voigt quadrature takes
+// seconds per damping value), then copied to the device.
+constexpr int kContVoigtN = 64, kContSampN = 16;
+static int ensure_cont_tables(krt_ctx *c, int l) {
+    const double a_l = c->lines[l].a;
+    const double key[3] = {a_l, (double)c->br_lo, (double)c->br_hi};
+    if (std::equal(key, key + 3, c->cont_key)) return KRT_OK;
+    const double lna0 = std::log(a_l / c->br_hi), span = std::log((double)c->br_hi / (double)c->br_lo);
+    const bool one = !(span > 1e-9);
+    const int nv = one ? 1 : kContVoigtN, ns = one ? 1 : kContSampN;
+    std::vector<float> hv((size_t)(nv + 1) * kVoigtFloats), hs((size_t)ns * kTabFloats, 0.0f);
+    std::vector<float2> hp(ns);
+    auto node_a = [&](int k, int n) { return n == 1 ? a_l / c->br_hi : std::exp(lna0 + span * k / (n - 1)); };
+    std::atomic<int> next{0};
+    auto work = [&]() {
+        std::vector<float> tmp(kTabFloats);
+        for (int j = next++; j < nv + ns; j = next++) {
+            if (j < nv) {
+                build_voigt_block(node_a(j, nv), tmp.data());
+                std::copy(tmp.begin(), tmp.begin() + kVoigtFloats, hv.begin() + (size_t)j * kVoigtFloats);
+            } else {
+                const int k = j - nv;
+                build_sampler_block(node_a(k, ns), hs.data() + (size_t)k * kTabFloats);
+            }
+        }
+    };
+    const int nt = std::max(1, std::min<int>((int)std::thread::hardware_concurrency(), nv + ns));
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+    work();
+    for (auto &t : pool) t.join();
+    std::copy(hv.begin() + (size_t)(nv - 1) * kVoigtFloats, hv.begin() + (size_t)nv * kVoigtFloats,
+              hv.begin() + (size_t)nv * kVoigtFloats);  // the upper neighbour of the last node
+    for (int k = 0; k < ns; ++k) {
+        const double ak = node_a(k, ns);
+        hp[k] = make_float2((float)ak, (float)std::atan(kDelta / ak));
+    }
+    if (!c->cv_tab) HIPCHK(c, hipMalloc(&c->cv_tab, sizeof(float) * (size_t)(kContVoigtN + 1) * kVoigtFloats));
+    if (!c->cs_tab) HIPCHK(c, hipMalloc(&c->cs_tab, sizeof(float) * (size_t)kContSampN * kTabFloats));
+    if (!c->cs_par) HIPCHK(c, hipMalloc(&c->cs_par, sizeof(float2) * kContSampN));
+    HIPCHK(c, hipMemcpy(c->cv_tab, hv.data(), sizeof(float) * hv.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->cs_tab, hs.data(), sizeof(float) * hs.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->cs_par, hp.data(), sizeof(float2) * ns, hipMemcpyHostToDevice));
+    c->cont_n_v = nv;
+    c->cont_n_s = ns;
+    c->cont_lna0 = lna0;
+    c->cont_inv_v = one ? 0.0 : (nv - 1) / span;
+    c->cont_inv_s = one ? 0.0 : (ns - 1) / span;
+    std::copy(key, key + 3, c->cont_key);
+    return KRT_OK;
+}
+
+static void set_cont_params(const krt_ctx *c, RunParams &P) {
+    P.bratio = c->grid.bratio_dev;
+    P.cv_tab = c->cv_tab;
+    P.cs_tab = c->cs_tab;
+    P.cs_par = c->cs_par;
+    P.cv_lna0 = (float)c->cont_lna0;
+    P.cv_inv_step = (float)c->cont_inv_v;
+    P.cs_inv_step = (float)c->cont_inv_s;
+    P.cv_n = c->cont_n_v;
+    P.cs_n = c->cont_n_s;
 }
 
 // Walker/Vose alias table over non-negative weights (FP64 build).
@@ -219,6 +298,9 @@ extern "C" void krt_destroy(krt_ctx *c) {
     free_tables(c);
     if (c->cls_tab) (void)hipFree(c->cls_tab);
     if (c->cls_par) (void)hipFree(c->cls_par);
+    if (c->cv_tab) (void)hipFree(c->cv_tab);
+    if (c->cs_tab) (void)hipFree(c->cs_tab);
+    if (c->cs_par) (void)hipFree(c->cs_par);
     if (c->work_counter) (void)hipFree(c->work_counter);
     if (c->level_consts) (void)hipFree(c->level_consts);
     if (c->level_power) (void)hipFree(c->level_power);
@@ -269,7 +351,20 @@ extern "C" int krt_grid_upload(krt_ctx *c, const krt_grid_desc *d) {
             if (!(d->tclass_bratio[k] >= 0.05 && d->tclass_bratio[k] <= 20.0))
                 return fail(c, KRT_EINVAL, "tclass_bratio[%d] = %g outside [0.05, 20]", k, d->tclass_bratio[k]);
     }
+    if (d->bratio_dev && d->tclass_dev) return fail(c, KRT_EINVAL, "bratio and temperature classes are exclusive");
     HIPCHK(c, hipSetDevice(c->device));
+    float br_lo = 1.0f, br_hi = 1.0f;
+    if (d->bratio_dev) {
+        // the range of widths sets the damping nodes of the tables
+        std::vector<float> br((size_t)ncell);
+        HIPCHK(c, hipMemcpy(br.data(), d->bratio_dev, sizeof(float) * (size_t)ncell, hipMemcpyDeviceToHost));
+        br_lo = br_hi = br[0];
+        for (float v : br) {
+            if (!(v >= 0.05f && v <= 20.0f)) return fail(c, KRT_EINVAL, "bratio %g outside [0.05, 20]", (double)v);
+            br_lo = std::min(br_lo, v);
+            br_hi = std::max(br_hi, v);
+        }
+    }
     if (d->tclass_dev) {
         // every class index must name a class: the transport indexes the class
         // parameters and table sets with it
@@ -281,6 +376,8 @@ extern "C" int krt_grid_upload(krt_ctx *c, const krt_grid_desc *d) {
     free_grid(c);
     c->grid = *d;
     c->cls_line = -1;
+    c->br_lo = br_lo;
+    c->br_hi = br_hi;
     c->ncell = ncell;
     c->alias_prob.assign(d->n_lines, nullptr);
     c->alias_idx.assign(d->n_lines, nullptr);
@@ -387,6 +484,7 @@ static int run_parked(krt_ctx *c, const RunParams &P0, uint64_t n_packets, uint6
         if (new_done + admit == n_packets && n_res + admit <= tail) {
             Q.esc_min_lanes = 1;
             Q.esc_tail_lanes = 1;
+            Q.esc_wait = 0;
             HIPCHK(c, launch_transport(Q, kModeFused, grid, block_fused, c->stream));
             break;
         }
@@ -513,6 +611,8 @@ static int mc_run_impl(krt_ctx *c, uint64_t n_packets, uint64_t seed, const krt_
     if (o->profile_mode != 0 && esc) return fail(c, KRT_EINVAL, "profile_mode %d is for the plain walk", o->profile_mode);
     if (c->have_grid && c->grid.tclass_dev && (esc || o->profile_mode != 0))
         return fail(c, KRT_EINVAL, "temperature classes need the plain walk with profile_mode 0");
+    if (c->have_grid && c->grid.bratio_dev && (esc || o->profile_mode != 0))
+        return fail(c, KRT_EINVAL, "per-cell widths (bratio) need the plain walk with profile_mode 0");
 
     HIPCHK(c, hipSetDevice(c->device));
     const krt_grid_desc &g = c->grid;
@@ -525,8 +625,8 @@ static int mc_run_impl(krt_ctx *c, uint64_t n_packets, uint64_t seed, const krt_
         if (o->emis_nch > 0) HIPCHK(c, launch_zero_i64(t->emis_raw_dev, nc * o->emis_nch, c->stream));
         if (o->jbar) HIPCHK(c, launch_zero_i64(t->jbar_raw_dev, nc, c->stream));
     }
-    if (noalloc && c->grid.tclass_dev)
-        return fail(c, KRT_EINVAL, "krt_mc_run_noalloc: temperature classes build their tables on first use; "
+    if (noalloc && (c->grid.tclass_dev || c->grid.bratio_dev))
+        return fail(c, KRT_EINVAL, "krt_mc_run_noalloc: per-cell temperatures build their tables on first use; "
                                    "use krt_mc_run");
     unsigned long long *counter = noalloc ? reinterpret_cast<unsigned long long *>(c->scratch_dev) : c->work_counter;
     float *edges = noalloc ? reinterpret_cast<float *>(c->scratch_dev + kNoAllocEdgeOffset) : c->edges;
@@ -607,8 +707,9 @@ static int mc_run_impl(krt_ctx *c, uint64_t n_packets, uint64_t seed, const krt_
                                       std::pow(10.0, (double)c->esc_ld_min));
     P.esc_x_max = kEscXMax;
     P.esc_log10a = (float)std::log10(c->lines[l].a);
-    P.esc_min_lanes = o->esc_min_lanes > 0 ? o->esc_min_lanes : 8;
+    P.esc_min_lanes = o->esc_min_lanes > 0 ? o->esc_min_lanes : 24;
     P.esc_tail_lanes = o->esc_tail_lanes > 0 ? o->esc_tail_lanes : 1;
+    P.esc_wait = o->esc_wait > 0 ? (uint32_t)o->esc_wait : (o->esc_wait == 0 ? 16u : 0u);
     P.tail_lanes = o->tail_lanes == 0 ? 32 : (o->tail_lanes < 0 ? 0 : std::min(o->tail_lanes, 64));
     P.profile_mode = o->profile_mode;
     P.tclass = nullptr;
@@ -620,6 +721,12 @@ static int mc_run_impl(krt_ctx *c, uint64_t n_packets, uint64_t seed, const krt_
         P.tclass = c->grid.tclass_dev;
         P.cls_par = c->cls_par;
         P.cls_tab = c->cls_tab;
+    }
+    P.bratio = nullptr;
+    if (c->grid.bratio_dev) {
+        int rc = ensure_cont_tables(c, l);
+        if (rc) return rc;
+        set_cont_params(c, P);
     }
     P.voigt_u0 = (float)voigt_crossing(c->lines[l].a);
     P.n_res = 0;
@@ -963,6 +1070,22 @@ extern "C" int krt_debug_voigt(krt_ctx *c, int32_t line, const float *x, int64_t
     if (!x || !out || n <= 0 || n > kMaxDebugElems) return fail(c, KRT_EINVAL, "bad voigt args");
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, launch_debug_voigt(c->tab[line], x, n, out, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return KRT_OK;
+}
+
+extern "C" int krt_debug_voigt_cont(krt_ctx *c, int32_t line, const float *r, const float *x, int64_t n, float *out) {
+    if (!c) return KRT_EINVAL;
+    if (line < 0 || line >= (int)c->tab.size()) return fail(c, KRT_ESTATE, "line %d has no tables", line);
+    if (!c->have_grid || !c->grid.bratio_dev) return fail(c, KRT_ESTATE, "the grid has no per-cell widths (bratio)");
+    if (!r || !x || !out || n <= 0 || n > kMaxDebugElems) return fail(c, KRT_EINVAL, "bad voigt_cont args");
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc = ensure_cont_tables(c, line);
+    if (rc) return rc;
+    RunParams P;
+    std::memset(&P, 0, sizeof(P));
+    set_cont_params(c, P);
+    HIPCHK(c, launch_debug_voigt_cont(P, (float)c->lines[line].a, r, x, n, out, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return KRT_OK;
 }

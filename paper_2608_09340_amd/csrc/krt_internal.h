@@ -37,6 +37,7 @@ constexpr int kOffL1 = kOffSpike + kRows * kQS;                         // 6660
 constexpr int kOffL2 = kOffL1 + kRows * kQL1;                           // 10756
 constexpr int kOffRight = kOffL2 + kRows * kQL2;                        // 14852
 constexpr int kTabFloats = kOffRight + kRows * kQR;                     // 18948
+constexpr int kVoigtFloats = kOffMass;                                  // the Voigt part: 2560
 static_assert(kOffMass % 4 == 0 && kOffSpike % 4 == 0 && kOffL1 % 4 == 0 && kOffL2 % 4 == 0 &&
               kOffRight % 4 == 0 && kTabFloats % 4 == 0, "16-byte aligned blocks");
 static_assert(kQL1 == kQL2 && kQL2 == kQR, "one node count for the wing pieces");
@@ -45,6 +46,10 @@ static_assert(kTabFloats * 4 <= 80 * 1024, "two workgroups' tables fit the 160 K
 // host side (krt_tables.cpp)
 double row_x(int j);
 void build_line_tables(double a, std::vector<float> &tab);
+// the two parts of one table block: the Voigt lookup (floats [0, kVoigtFloats))
+// and the sampler (mass table and quantile rows), each into a block of kTabFloats
+void build_voigt_block(double a, float *tab);
+void build_sampler_block(double a, float *tab);
 double table_voigt(const std::vector<float> &tab, double x);
 double voigt_reference(double a, double x);
 

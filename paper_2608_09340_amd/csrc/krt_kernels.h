@@ -106,6 +106,7 @@ struct RunParams {
     float esc_half_dx, esc_tc_min, esc_tc_max, esc_depth_min, esc_x_max, esc_log10a;
     int esc_min_lanes;
     int esc_tail_lanes;
+    uint32_t esc_wait;  // fused: iterations a qualifying lane may hold its scattering for a batch (0 = never)
     int tail_lanes;
     int emis_w32;  // emissivity contributions fit 32 bits (fraction bits <= 30)
     // opacity profile of the flights: 0 LDS tables, 1 the same tables read from
@@ -118,6 +119,17 @@ struct RunParams {
     const uint8_t *tclass;
     const float4 *cls_par;
     const float *cls_tab;
+    // continuous per-cell temperature (null: none): b / b_ref per cell; Voigt
+    // blocks [cv_n + 1][kVoigtFloats] at damping exp(cv_lna0 + k / cv_inv_step)
+    // (the last block repeats the one before it, so the upper neighbour of
+    // any node exists), sampler blocks [cs_n][kTabFloats] at
+    // exp(cv_lna0 + k / cs_inv_step) with (a, sampler threshold) per node
+    const float *bratio;
+    const float *cv_tab;
+    const float *cs_tab;
+    const float2 *cs_par;
+    float cv_lna0, cv_inv_step, cs_inv_step;
+    int cv_n, cs_n;
 };
 
 // transport kernel modes: plain walk, network calls batched inside the
@@ -143,6 +155,8 @@ hipError_t launch_debug_philox(const uint32_t *ctr, const uint32_t *key, uint32_
 hipError_t launch_debug_bins(const float *x, int64_t n, int nb, const float *edges, float inv_w, int32_t *out,
                              hipStream_t s);
 hipError_t launch_debug_voigt(const float *tab, const float *x, int64_t n, float *out, hipStream_t s);
+hipError_t launch_debug_voigt_cont(const RunParams &P, float a, const float *r, const float *x, int64_t n, float *out,
+                                   hipStream_t s);
 hipError_t launch_debug_voigt_analytic(float a, float u0, const float *x, int64_t n, float *out, hipStream_t s);
 hipError_t launch_debug_upar(const float *tab, float a, float thd, float x, uint32_t k0, uint32_t k1,
                              uint64_t packet, uint32_t ev0, int64_t n, float *out, hipStream_t s);

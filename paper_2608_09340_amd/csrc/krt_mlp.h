@@ -163,9 +163,11 @@ __device__ __forceinline__ float sigmoid_f(float z) {
 // Hidden activation: leaky ReLU, max(z, z / 16), and its derivative.  Two
 // full-rate instructions per value: the network runs inside the transport
 // kernel, where a transcendental activation (SiLU: an exp and a reciprocal,
-// quarter rate each) cost more issue cycles than the matrix products.
+// quarter rate each) cost more issue cycles than the matrix products.  The max
+// is the median of (z, z / 16, +inf): fmaxf would first quiet a possible
+// signalling NaN in the MFMA result with one more instruction per value.
 constexpr float kLeak = 0.0625f;
-__device__ __forceinline__ float leaky(float z) { return fmaxf(z, kLeak * z); }
+__device__ __forceinline__ float leaky(float z) { return __builtin_amdgcn_fmed3f(z, kLeak * z, 3.40282347e38f); }
 __device__ __forceinline__ float dleaky(float z) { return z > 0.0f ? 1.0f : kLeak; }
 
 __device__ __forceinline__ v4i16 pack4(float a, float b, float c, float d) {

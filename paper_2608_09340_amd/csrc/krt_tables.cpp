@@ -226,8 +226,7 @@ double row_x(int j) {
     return kXLin * std::pow(kXMax / kXLin, (double)(j - kRowsLin) / (kRows - kRowsLin - 1));
 }
 
-void build_line_tables(double a, std::vector<float> &tab) {
-    tab.assign(kTabFloats, 0.0f);
+void build_voigt_block(double a, float *tab) {
     // (i) Voigt core: nodes x_i = i / 64, i = 0..512
     {
         std::vector<double> H(kVoigtCoreN + 1), D(kVoigtCoreN + 1);
@@ -252,6 +251,9 @@ void build_line_tables(double a, std::vector<float> &tab) {
             hermite_coefs(G[j], Gd[j] / kVoigtWingN, G[j + 1], Gd[j + 1] / kVoigtWingN,
                           &tab[kOffVoigtWing + 4 * j]);
     }
+}
+
+void build_sampler_block(double a, float *tab) {
     // (ii) cumulative piece probabilities on x_i = i / 64, i = 0..512
     for (int i = 0; i <= kMassN; ++i) {
         double xa = i * (kXLin / kMassN);
@@ -290,6 +292,12 @@ void build_line_tables(double a, std::vector<float> &tab) {
             }
         }
     }
+}
+
+void build_line_tables(double a, std::vector<float> &tab) {
+    tab.assign(kTabFloats, 0.0f);
+    build_voigt_block(a, tab.data());
+    build_sampler_block(a, tab.data());
 }
 
 // ---- host reference evaluation of the staged tables (same arithmetic as the

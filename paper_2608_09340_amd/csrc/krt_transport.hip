@@ -326,6 +326,38 @@ __device__ __forceinline__ void call_condition(const RunParams &P, const CellFra
         cnd[7 + r] = pick3(CF.sg[0], CF.sg[1], CF.sg[2], CF.perm[r]) * pick3(nx, ny, nz, CF.perm[r]);
 }
 
+// ------------------------------------------------ continuous temperature ---
+// A cell of Doppler width r b_ref: frequency scale sc = 1 / r (and back, isc),
+// its damping ac = a / r, the Voigt blocks around ac with the weight of the
+// upper one (linear in ln a), and the nearest sampler node (block offset, its
+// damping and sampler threshold).
+struct ContCell {
+    float sc, isc, ac, tv, sa, sthd;
+    int voff, toff;
+};
+__device__ __forceinline__ ContCell cont_cell(const RunParams &P, float a, float r) {
+    ContCell c;
+    c.isc = r;
+    c.sc = 1.0f / r;
+    c.ac = a * c.sc;
+    const float s = logf(c.ac) - P.cv_lna0;
+    const float uv = fminf(fmaxf(s * P.cv_inv_step, 0.0f), (float)(P.cv_n - 1));
+    const int kv = min((int)uv, max(P.cv_n - 2, 0));
+    c.tv = uv - (float)kv;
+    c.voff = kv * kVoigtFloats;
+    const int ks = min((int)(fmaxf(s * P.cs_inv_step, 0.0f) + 0.5f), P.cs_n - 1);
+    c.toff = ks * kTabFloats;
+    const float2 sp = P.cs_par[ks];
+    c.sa = sp.x;
+    c.sthd = sp.y;
+    return c;
+}
+// H(ac, |x|) between the two Voigt blocks
+__device__ __forceinline__ float cont_voigt(const RunParams &P, int voff, float tv, float xa) {
+    const float h0 = voigt_lds(P.cv_tab + voff, xa);
+    return fmaf(tv, voigt_lds(P.cv_tab + voff + kVoigtFloats, xa) - h0, h0);
+}
+
 // --------------------------------------------------------------- kernel ---
 // Draws of the second random block of an event: the two u_perp components
 // (Box-Muller, N(0, 1/2) each), the cosine g of the scattering angle
@@ -365,6 +397,7 @@ __device__ __forceinline__ void scatter_draws(uint4 B, bool dipole, SDraws &d) {
 template <int kMode, int kMaxThreads, int kProf = 0>
 __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) {
     constexpr bool kEsc = kMode == kModeFused, kPark = kMode == kModePark;
+    constexpr bool kTemp = kProf == 3 || kProf == 4;  // per-cell temperature: classes or continuum
     extern __shared__ float4 lds4[];
     const float *T = (kProf == 1) ? P.tab : reinterpret_cast<const float *>(lds4);
     // bin edges after the tables: spectrum then channels; the network variant
@@ -397,8 +430,9 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
     const float a = P.a, thd = P.thd;
 
     // lane state
-    float sc = 1.0f, isc = 1.0f, ac = a, thdc = thd;  // cell temperature (kProf 3)
-    int toff = 0;
+    float sc = 1.0f, isc = 1.0f, ac = a, thdc = thd;  // cell temperature (kProf 3, 4)
+    float sac = a, tv = 0.0f;  // continuum (kProf 4): the sampler node's damping, upper Voigt weight
+    int toff = 0, voff = 0;
     bool have = false, done = false;
     uint64_t pid = 0;
     int ci = 0, cj = 0, ck = 0, cell = 0;
@@ -409,6 +443,8 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
     float k0c = 0.f, vxc = 0.f, vyc = 0.f, vzc = 0.f, epsc = 0.f, kabsc = 0.f;
     uint32_t nscat_pkt = 0, ncross_pkt = 0;
     uint32_t seg = 0;  // plain scatterings of the packet in this launch (park mode)
+    bool pend = false;   // fused mode: a qualifying scattering waits for its wave's next call batch
+    uint32_t pwait = 0;  // ... for this many loop iterations so far
     int outcome = 0;  // 1 escaped, 2 destroyed, 3 stuck
     int64_t jacc = 0;
     EmisCache E;
@@ -419,14 +455,21 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
     uint32_t *status = P.status;
     const float jscale = P.jbar_scale * kInvSqrtPiF;
 
-    // entering a cell with temperature classes: its frequency scale, damping,
-    // sampler threshold and table set
+    // entering a cell with temperature classes or a continuum of widths: its
+    // frequency scale, damping, sampler threshold and table set
     auto enter_cell = [&]() {
         if constexpr (kProf == 3) {
             const int k = P.tclass[cell];
             const float4 cp = P.cls_par[k];
             sc = cp.x; ac = cp.y; thdc = cp.z; isc = cp.w;
+            sac = ac;
             toff = k * kTabFloats;
+        }
+        if constexpr (kProf == 4) {
+            const ContCell cc = cont_cell(P, a, P.bratio[cell]);
+            sc = cc.sc; isc = cc.isc; ac = cc.ac; tv = cc.tv;
+            sac = cc.sa; thdc = cc.sthd;
+            voff = cc.voff; toff = cc.toff;
         }
     };
 
@@ -434,10 +477,13 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
     // or destruction) or across one cell face (escape / periodic wrap / next cell)
     auto flight = [&](float ue, bool &scat, float &xc) {
         xc = x - (nx * vxc + ny * vyc + nz * vzc);
-        if constexpr (kProf == 3) xc *= sc;
-        float H = (k0c > 0.0f) ? ((kProf == 2) ? voigt_analytic(a, P.voigt_u0, fabsf(xc))
-                                               : voigt_lds((kProf == 3) ? P.cls_tab + toff : T, fabsf(xc)))
-                               : 0.0f;
+        if constexpr (kTemp) xc *= sc;
+        float H = 0.0f;
+        if (k0c > 0.0f) {
+            if constexpr (kProf == 2) H = voigt_analytic(a, P.voigt_u0, fabsf(xc));
+            else if constexpr (kProf == 4) H = cont_voigt(P, voff, tv, fabsf(xc));
+            else H = voigt_lds((kProf == 3) ? P.cls_tab + toff : T, fabsf(xc));
+        }
         // line opacity plus the cell's grey absorption (exactly k0 H without one)
         float kap = fmaf(k0c, H, kabsc);
         float tx = (nx > 0.0f) ? (1.0f - fx) * P.dx[0] * f_rcp(nx) : ((nx < 0.0f) ? fx * P.dx[0] * f_rcp(-nx) : INFINITY);
@@ -524,7 +570,8 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
     // scattering.
     auto prepare = [&](float xc, float r1, float r2, const SDraws &b, ScatPrep &q) {
         const float up1 = b.up1, up2 = b.up2, g = b.g, sg = b.sg, cp = b.cp, sp = b.sp;
-        float upar = (kProf == 3) ? upar_lds(P.cls_tab + toff, xc, ac, thdc, r1, r2) : upar_lds(T, xc, a, thd, r1, r2);
+        float upar = kTemp ? upar_lds(((kProf == 4) ? P.cs_tab : P.cls_tab) + toff, xc, sac, thdc, r1, r2)
+                           : upar_lds(T, xc, a, thd, r1, r2);
         // orthonormal basis about n (Duff et al. 2017)
         float sgn = copysignf(1.0f, nz);
         float A_ = -f_rcp(sgn + nz);
@@ -538,7 +585,7 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
         q.ox = ox * rn; q.oy = oy * rn; q.oz = oz * rn;
         // eq. riia-scatter
         q.xo = xc + upar * (g - 1.0f) + sg * (up1 * cp + up2 * sp);
-        if constexpr (kProf == 3) q.xo *= isc;  // back to reference units
+        if constexpr (kTemp) q.xo *= isc;  // back to reference units
         q.kb = -1;
         q.wq = 0;
         if (P.emis_raw) {
@@ -546,7 +593,7 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
             float upc = up1 * (e1x * P.n_cam[0] + e1y * P.n_cam[1] + e1z * P.n_cam[2]) +
                         up2 * (e2x * P.n_cam[0] + e2y * P.n_cam[1] + e2z * P.n_cam[2]);
             float xcam = xc + upar * (gc - 1.0f) + upc;
-            if constexpr (kProf == 3) xcam *= isc;
+            if constexpr (kTemp) xcam *= isc;
             xcam += P.n_cam[0] * vxc + P.n_cam[1] * vyc + P.n_cam[2] * vzc;
             q.kb = bin_index(xcam, cedges, P.emis_nch, P.ch_inv_w);
             float wph = (P.phase == KRT_PHASE_DIPOLE_I) ? 0.75f * (1.0f + gc * gc) : 1.0f;
@@ -722,9 +769,9 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
                         xg = rr * cos_rev(th);
                         if (P.src_profile == KRT_PROF_VOIGT_I) {
                             float c = u01(e2.z) - 0.5f;  // Cauchy(a): a tan(pi c)
-                            xg += ((kProf == 3) ? ac : a) * sin_rev(0.5f * c) * f_rcp(cos_rev(0.5f * c));
+                            xg += (kTemp ? ac : a) * sin_rev(0.5f * c) * f_rcp(cos_rev(0.5f * c));
                         }
-                        if constexpr (kProf == 3) xg *= isc;  // the emitting cell's units -> reference
+                        if constexpr (kTemp) xg *= isc;  // the emitting cell's units -> reference
                     }
                     x = xg + nx * vxc + ny * vyc + nz * vzc;
                     ev = 1;
@@ -752,8 +799,9 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
         bool scat = false;
         float xc = 0.0f;
         ScatPrep q;
-        if (have) {
-            const float xg = (x - (nx * vxc + ny * vyc + nz * vzc)) * ((kProf == 3) ? sc : 1.0f);
+        if (kEsc && pend) xc = x - (nx * vxc + ny * vyc + nz * vzc);  // held at its scattering
+        if (have && !pend) {
+            const float xg = (x - (nx * vxc + ny * vyc + nz * vzc)) * (kTemp ? sc : 1.0f);
             SDraws b;
             scatter_draws(philox(make_uint4(ev, (uint32_t)pid, (uint32_t)(pid >> 32), 1u), P.key0, P.key1),
                           P.phase == KRT_PHASE_DIPOLE_I, b);
@@ -773,7 +821,7 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
         if (kEsc || kPark) {
             CellFrame CF{};
             float ltc = 0.0f, ldep = 0.0f;
-            if (scat) mlp = call_eligible(P, k0c, fx, fy, fz, xc, CF, ltc, ldep);
+            if (scat || pend) mlp = call_eligible(P, k0c, fx, fy, fz, xc, CF, ltc, ldep);
             if (kPark) {
                 bool cont = false;
                 if (!mlp && scat) {
@@ -783,14 +831,24 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
                 park(mlp || cont, scat, xc, mlp ? 1u : 0u);
             } else {
                 // once the packet pool is exhausted (some lane of this wave is done) the
-                // wave lives only as long as its slowest packet: fewer asking lanes suffice
+                // wave lives only as long as its slowest packet: fewer asking lanes suffice.
+                // With waiting on (esc_wait > 0) a qualifying lane that finds too few
+                // others holds its scattering (pend) instead of walking it, for at most
+                // esc_wait iterations; the batch also goes when every live lane asks.
                 const uint64_t wm = __ballot(mlp);
                 const int need_lanes = (__ballot(done) != 0ull) ? P.esc_tail_lanes : P.esc_min_lanes;
-                const bool go = __popcll(wm) >= need_lanes;  // wave-uniform
-                if (!go) mlp = false;
+                const bool go = wm != 0ull && (__popcll(wm) >= need_lanes || wm == __ballot(have) ||
+                                               __ballot(pend && pwait >= P.esc_wait) != 0ull);  // wave-uniform
+                if (!go) {
+                    if (mlp && P.esc_wait > 0) {
+                        pwait = pend ? pwait + 1 : 1;
+                        pend = true;
+                    }
+                    mlp = false;
+                }
                 // this event's plain scatterings first, so their prepared state is
                 // not live across the network evaluation
-                if (scat && !mlp) commit(q);
+                if (scat && !mlp && !pend) commit(q);
                 if (go) {
                     const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
                     const uint4 C = philox(make_uint4(ev, plo, phi, 2u), P.key0, P.key1);
@@ -802,12 +860,17 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
                     call_network(mimg, mbias, mnorm, lane, wm, cnd, C, D, face, xo, mo);
                     if (mlp) {
                         int64_t *ebase = P.emis_raw ? P.emis_raw + (int64_t)cell * P.emis_nch : nullptr;
+                        // the deposit spans consecutive channels, each once: direct atomics
                         call_apply(P, mnorm, cedges, CF, mo, face, xo, C.z, ltc, ldep, xc, vxc, vyc, vzc, fx, fy,
                                    fz, nx, ny, nz, x, c_skip, c_drop,
-                                   [&](int ch, int64_t w) __attribute__((always_inline)) { emis_add(E, ch, w, ebase); });
+                                   [&](int ch, int64_t w) __attribute__((always_inline)) { tally_add_i64(ebase + ch, w); });
                         c_mlp += 1;
                     }
                 }
+                // an event is consumed by a walked scattering or a call; a held one waits
+                const bool served = go && mlp;
+                if (served) pend = false;
+                scat = (scat && !pend) || served;
             }
         }
 
@@ -880,7 +943,7 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
             float xc = 0.0f;
             ScatPrep q;
             if (have) {
-                prepare((x - (nx * vxc + ny * vyc + nz * vzc)) * ((kProf == 3) ? sc : 1.0f), dr1, dr2, db, q);
+                prepare((x - (nx * vxc + ny * vyc + nz * vzc)) * (kTemp ? sc : 1.0f), dr1, dr2, db, q);
                 flight(due, scat, xc);
             }
             bool called = false;
@@ -965,6 +1028,14 @@ __global__ void debug_bins_kernel(const float *x, int64_t n, int nb, const float
     out[i] = bin_index(x[i], e, nb, inv_w);
 }
 
+// H(a / r, |x|) for the widths r[i] as the continuum transport evaluates it
+__global__ void debug_voigt_cont_kernel(RunParams P, float a, const float *r, const float *x, int64_t n, float *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const ContCell cc = cont_cell(P, a, r[i]);
+    out[i] = cont_voigt(P, cc.voff, cc.tv, fabsf(x[i]));
+}
+
 __global__ void debug_voigt_kernel(const float *tab, const float *x, int64_t n, float *out) {
     extern __shared__ float4 lds4[];
     float *T = reinterpret_cast<float *>(lds4);
@@ -1010,17 +1081,18 @@ hipError_t launch_transport(const RunParams &P, int mode, int grid, int block, h
     // plain walk's register budget (1024 lanes).
     const int variant = fused ? (block <= 512 ? 2 : (block <= 768 ? 5 : 1))
                               : (mode == kModePark ? 7
-                                                   : (P.tclass ? 6 : (P.profile_mode == 1 ? 3
-                                                                      : (P.profile_mode == 2 ? 4 : 0))));
-    static bool attr_set[8] = {false, false, false, false, false, false, false, false};
-    const void *fns[8] = {reinterpret_cast<const void *>(mc_transport_kernel<kModePlain, 1024>),
+                                                   : (P.bratio ? 8 : (P.tclass ? 6 : (P.profile_mode == 1 ? 3
+                                                                      : (P.profile_mode == 2 ? 4 : 0)))));
+    static bool attr_set[9] = {false, false, false, false, false, false, false, false, false};
+    const void *fns[9] = {reinterpret_cast<const void *>(mc_transport_kernel<kModePlain, 1024>),
                           reinterpret_cast<const void *>(mc_transport_kernel<kModeFused, 1024>),
                           reinterpret_cast<const void *>(mc_transport_kernel<kModeFused, 512>),
                           reinterpret_cast<const void *>(mc_transport_kernel<kModePlain, 1024, 1>),
                           reinterpret_cast<const void *>(mc_transport_kernel<kModePlain, 1024, 2>),
                           reinterpret_cast<const void *>(mc_transport_kernel<kModeFused, 768>),
                           reinterpret_cast<const void *>(mc_transport_kernel<kModePlain, 1024, 3>),
-                          reinterpret_cast<const void *>(mc_transport_kernel<kModePark, 1024>)};
+                          reinterpret_cast<const void *>(mc_transport_kernel<kModePark, 1024>),
+                          reinterpret_cast<const void *>(mc_transport_kernel<kModePlain, 1024, 4>)};
     if (!attr_set[variant]) {
         hipError_t e = hipFuncSetAttribute(fns[variant], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -1034,6 +1106,7 @@ hipError_t launch_transport(const RunParams &P, int mode, int grid, int block, h
         case 5: hipLaunchKernelGGL((mc_transport_kernel<kModeFused, 768>), dim3(grid), dim3(block), lds, s, P); break;
         case 6: hipLaunchKernelGGL((mc_transport_kernel<kModePlain, 1024, 3>), dim3(grid), dim3(block), lds, s, P); break;
         case 7: hipLaunchKernelGGL((mc_transport_kernel<kModePark, 1024>), dim3(grid), dim3(block), lds, s, P); break;
+        case 8: hipLaunchKernelGGL((mc_transport_kernel<kModePlain, 1024, 4>), dim3(grid), dim3(block), lds, s, P); break;
         default: hipLaunchKernelGGL((mc_transport_kernel<kModePlain, 1024, 2>), dim3(grid), dim3(block), lds, s, P); break;
     }
     return hipGetLastError();
@@ -1165,6 +1238,12 @@ hipError_t launch_debug_bins(const float *x, int64_t n, int nb, const float *edg
                              hipStream_t s) {
     int grid = (int)((n + 255) / 256);
     hipLaunchKernelGGL(debug_bins_kernel, dim3(grid), dim3(256), 0, s, x, n, nb, edges, inv_w, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_voigt_cont(const RunParams &P, float a, const float *r, const float *x, int64_t n, float *out,
+                                   hipStream_t s) {
+    hipLaunchKernelGGL(debug_voigt_cont_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, P, a, r, x, n, out);
     return hipGetLastError();
 }
 

@@ -26,7 +26,7 @@ class krt_grid_desc(C.Structure):
                 ("k0_dev", C.c_void_p), ("vel_dev", C.c_void_p), ("eps_dev", C.c_void_p),
                 ("emis_dev", C.c_void_p), ("kabs_dev", C.c_void_p), ("tclass_dev", C.c_void_p),
                 ("n_tclass", C.c_int32),
-                ("tclass_bratio", C.c_double * 8)]
+                ("tclass_bratio", C.c_double * 8), ("bratio_dev", C.c_void_p)]
 
 
 class krt_line_desc(C.Structure):
@@ -46,7 +46,7 @@ class krt_run_opts(C.Structure):
                 ("esc_tau_min", C.c_double), ("esc_cell_tau_min", C.c_double), ("esc_min_lanes", C.c_int32),
                 ("esc_tail_lanes", C.c_int32), ("tail_lanes", C.c_int32), ("profile_mode", C.c_int32),
                 ("esc_park", C.c_int32), ("esc_park_cap", C.c_uint32), ("esc_park_tail", C.c_uint32),
-                ("esc_park_budget", C.c_uint32)]
+                ("esc_park_budget", C.c_uint32), ("esc_wait", C.c_int32)]
 
 
 class krt_escape_cond(C.Structure):
@@ -80,7 +80,7 @@ EXPORTS = ["krt_create", "krt_destroy", "krt_last_error", "krt_device_cus", "krt
            "krt_last_network_ms", "krt_last_rounds",
            "krt_grid_upload",
            "krt_tables_build", "krt_mc_run", "krt_mc_run_noalloc", "krt_levels_update", "krt_debug_philox",
-           "krt_debug_bins", "krt_debug_voigt", "krt_debug_voigt_analytic", "krt_debug_upar",
+           "krt_debug_bins", "krt_debug_voigt", "krt_debug_voigt_analytic", "krt_debug_voigt_cont", "krt_debug_upar",
            "krt_escape_init", "krt_escape_record", "krt_escape_fit_norm", "krt_escape_calibrate", "krt_escape_grad",
            "krt_escape_train", "krt_escape_get_weights", "krt_escape_put_weights", "krt_escape_forward",
            "krt_image", "krt_last_image_ms"]
@@ -121,6 +121,7 @@ def load(path: str = LIB_PATH):
     L.krt_debug_bins.argtypes = [p, p, i64, i32, C.c_double, C.c_double, p]
     L.krt_debug_voigt.argtypes = [p, i32, p, i64, p]
     L.krt_debug_voigt_analytic.argtypes = [p, C.c_double, p, i64, p]
+    L.krt_debug_voigt_cont.argtypes = [p, i32, p, p, i64, p]
     L.krt_debug_upar.argtypes = [p, i32, C.c_float, u64, u64, u32, i64, p]
     L.krt_escape_init.argtypes = [p, u64]
     L.krt_escape_record.argtypes = [p, i32, u64, u64, u64, C.POINTER(krt_escape_cond), p]
@@ -135,8 +136,8 @@ def load(path: str = LIB_PATH):
     L.krt_last_image_ms.argtypes = [p]
     L.krt_last_image_ms.restype = C.c_float
     for name in ["krt_grid_upload", "krt_tables_build", "krt_mc_run", "krt_mc_run_noalloc", "krt_levels_update",
-                 "krt_debug_philox", "krt_debug_bins", "krt_debug_voigt", "krt_debug_voigt_analytic", "krt_debug_upar",
-                 "krt_escape_init", "krt_escape_record", "krt_escape_fit_norm", "krt_escape_calibrate",
+                 "krt_debug_philox", "krt_debug_bins", "krt_debug_voigt", "krt_debug_voigt_analytic",
+                 "krt_debug_voigt_cont", "krt_debug_upar", "krt_escape_init", "krt_escape_record", "krt_escape_fit_norm", "krt_escape_calibrate",
                  "krt_escape_grad",
                  "krt_escape_train", "krt_escape_get_weights", "krt_escape_put_weights",
                  "krt_escape_forward", "krt_image"]:
@@ -203,10 +204,12 @@ class Context:
 
     # ------------------------------------------------------------- calls
     def krt_grid_upload(self, n, lo, hi, bc, k0, vel=None, eps=None, emis=None, n_lines=1, tclass=None,
-                        tclass_bratio=None, kabs=None):
+                        tclass_bratio=None, kabs=None, bratio=None):
         """tclass: device uint8 [ncell] temperature class per cell (or None);
         tclass_bratio: the Doppler width of each class over the reference;
-        kabs: device FP32 [ncell] grey absorption coefficient (or None)."""
+        kabs: device FP32 [ncell] grey absorption coefficient (or None);
+        bratio: device FP32 [ncell] Doppler width of each cell over the
+        reference (a continuum of temperatures; or None)."""
         d = krt_grid_desc()
         d.n[:] = [int(v) for v in n]
         d.lo[:] = [float(v) for v in lo]
@@ -223,7 +226,8 @@ class Context:
             d.tclass_dev = tclass.data_ptr()
             d.n_tclass = len(br)
             d.tclass_bratio[:len(br)] = br
-        self._keep["grid"] = (k0, vel, eps, emis, tclass, kabs)  # borrowed by the library
+        d.bratio_dev = None if bratio is None else bratio.data_ptr()
+        self._keep["grid"] = (k0, vel, eps, emis, tclass, kabs, bratio)  # borrowed by the library
         self.bound = None  # no Transport owns the context's grid until it binds
         self._check(self.L.krt_grid_upload(self.h, C.byref(d)))
 
@@ -318,6 +322,9 @@ class Context:
     def krt_debug_voigt_analytic(self, a, x, out):
         self._check(self.L.krt_debug_voigt_analytic(self.h, float(a), _ptr(x), x.numel(), _ptr(out)))
 
+    def krt_debug_voigt_cont(self, line, r, x, out):
+        self._check(self.L.krt_debug_voigt_cont(self.h, int(line), _ptr(r), _ptr(x), x.numel(), _ptr(out)))
+
     def krt_debug_voigt(self, line, x, out):
         self._check(self.L.krt_debug_voigt(self.h, int(line), _ptr(x), x.numel(), _ptr(out)))
 
@@ -330,7 +337,7 @@ def make_opts(prob: dict, *, line=0, packet_offset=0, accumulate=False, max_even
               wg_size=0, wg_per_cu=0, emis_frac_bits=0, jbar_frac_bits=0, norm_packets=0, escape_mode=0,
               luminosity=0.0, esc_tau_min=0.0, esc_cell_tau_min=0.0, esc_min_lanes=0, esc_tail_lanes=0,
               tail_lanes=0, profile_mode=0, esc_park=0, esc_park_cap=0, esc_park_tail=0,
-              esc_park_budget=0) -> krt_run_opts:
+              esc_park_budget=0, esc_wait=0) -> krt_run_opts:
     """krt_run_opts from a workload problem dict (paper_2608_09340_amd.workloads)."""
     o = krt_run_opts()
     src, t = prob["source"], prob["tally"]
@@ -367,6 +374,7 @@ def make_opts(prob: dict, *, line=0, packet_offset=0, accumulate=False, max_even
     o.esc_park_cap = int(esc_park_cap)
     o.esc_park_tail = int(esc_park_tail)
     o.esc_park_budget = int(esc_park_budget)
+    o.esc_wait = int(esc_wait)
     o.profile_mode = int(profile_mode)
     o.tail_lanes = int(tail_lanes)
     return o
@@ -395,6 +403,7 @@ class Transport:
         tcl = g.get("tclass")
         self.tclass = None if tcl is None else torch.from_numpy(
             np.ascontiguousarray(tcl, dtype=np.uint8).reshape(-1)).to(dev)
+        self.bratio = f32(g.get("bratio"))
         ln = prob["line"]
         self.lines = [(ln["a"], ln.get("phase", 0))] if lines is None else lines
         self._bind()
@@ -418,7 +427,7 @@ class Transport:
         g = self.prob["grid"]
         self.ctx.krt_grid_upload(self.n, g["lo"], g["hi"], g["bc"], self.k0, self.vel, self.eps, self.emis_w,
                                  n_lines=self.n_lines, tclass=self.tclass, tclass_bratio=g.get("tclass_bratio"),
-                                 kabs=self.kabs)
+                                 kabs=self.kabs, bratio=self.bratio)
         self.ctx.krt_tables_build(self.lines)
         self.ctx.bound = self
 

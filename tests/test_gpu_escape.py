@@ -481,6 +481,36 @@ def test_park_schedule_equals_fused(gpu_ctx, trained):
     assert np.array_equal(fu["packet_log"], pk["packet_log"])
 
 
+def test_held_scatterings_equal_immediate_calls(gpu_ctx, trained):
+    """Waiting (esc_wait > 0): a qualifying scattering that finds too few asking
+    lanes in its wave is held, not walked, until a batch goes, and the call
+    then uses the draws of that same event.  So every qualifying scattering
+    takes the network exactly as when each calls at once (esc_min_lanes = 1):
+    tallies, counters and every packet's end state are identical whatever the
+    batch threshold and the wait limit, including a threshold of 64 lanes that
+    only the every-live-lane-asks rule can meet."""
+    from paper_2608_09340_amd import krt
+    n = 6
+    k0 = np.full(n ** 3, 1000.0 / (2.0 / n))
+    k0[::5] = 30.0 / (2.0 / n)  # some thin cells: walked scatterings between calls
+    p = W._problem((n, n, n), (-1.0,) * 3, (1.0,) * 3, (0, 0, 0), k0, 1e-3,
+                   source={"kind": W.SRC_POINT, "pos": (0.11, -0.07, 0.23), "profile": W.PROF_DELTA, "x0": 0.0},
+                   tally={"spec_nbins": 128, "spec_lo": -24.0, "spec_hi": 24.0, "emis_nch": 16, "ch_lo": -6.0,
+                          "ch_hi": 6.0, "n_cam": (1.0, 0.0, 0.0)})
+    T = krt.Transport(p, ctx=gpu_ctx)
+    N = 150_000
+    ref = T.run(N, seed=5, packet_offset=77, escape_mode=1, esc_min_lanes=1, esc_tail_lanes=1, packet_log=True)
+    assert ref["rc"] == 0 and ref["counters"]["mlp_calls"] > 5 * N
+    for lanes, wait in ((32, 8), (48, 1000), (64, 1 << 30)):
+        held = T.run(N, seed=5, packet_offset=77, escape_mode=1, esc_min_lanes=lanes, esc_wait=wait,
+                     packet_log=True)
+        print(f"min lanes {lanes} wait {wait}: calls {held['counters']['mlp_calls']}")
+        assert held["rc"] == 0
+        assert held["counters"] == ref["counters"], (lanes, wait)
+        assert np.array_equal(held["spec_raw"], ref["spec_raw"]) and np.array_equal(held["emis_raw"], ref["emis_raw"])
+        assert np.array_equal(held["packet_log"], ref["packet_log"])
+
+
 def test_escape_refused_outside_trained_damping(gpu_ctx, trained):
     """The fixture's network was fitted on records at a = 1e-3 only: the
     normalisation block carries that log10 a range, and a learned run on a line
