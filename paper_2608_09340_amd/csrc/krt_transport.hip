@@ -163,6 +163,17 @@ __device__ __forceinline__ bool call_eligible(const RunParams &P, float k0c, flo
     return false;
 }
 
+// call_eligible's test without the frame: the transport kernel tests every
+// scattering and reduces the frame only inside a call batch (same decisions:
+// the largest |offset| is the last of the sorted three)
+__device__ __forceinline__ bool call_ok(const RunParams &P, float k0c, float fx, float fy, float fz, float xc) {
+    if (!P.esc_cubic) return false;
+    const float tc = k0c * P.esc_half_dx;
+    const float qm = fmaxf(fabsf(2.0f * fx - 1.0f), fmaxf(fabsf(2.0f * fy - 1.0f), fabsf(2.0f * fz - 1.0f)));
+    const float dep = tc * (1.0f - qm);
+    return tc >= P.esc_tc_min && tc <= P.esc_tc_max && dep >= P.esc_depth_min && fabsf(xc) <= P.esc_x_max;
+}
+
 // The two evaluations of a call for the lanes in `ask` (wave-uniform): the
 // marginal one (exit face from the softmax at level u01(C.z), side of x_out
 // from the learned P(x_out >= 0) at u01(C.w), |x_out| from the exit face's
@@ -821,7 +832,8 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
         if (kEsc || kPark) {
             CellFrame CF{};
             float ltc = 0.0f, ldep = 0.0f;
-            if (scat || pend) mlp = call_eligible(P, k0c, fx, fy, fz, xc, CF, ltc, ldep);
+            if (kPark && scat) mlp = call_eligible(P, k0c, fx, fy, fz, xc, CF, ltc, ldep);
+            if (kEsc && (scat || pend)) mlp = call_ok(P, k0c, fx, fy, fz, xc);
             if (kPark) {
                 bool cont = false;
                 if (!mlp && scat) {
@@ -850,6 +862,12 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
                 // not live across the network evaluation
                 if (scat && !mlp && !pend) commit(q);
                 if (go) {
+                    {
+                        float tc, dep;
+                        call_frame(P, k0c, fx, fy, fz, CF, tc, dep);
+                        ltc = __log10f(tc);
+                        ldep = __log10f(dep);
+                    }
                     const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
                     const uint4 C = philox(make_uint4(ev, plo, phi, 2u), P.key0, P.key1);
                     const uint4 D = philox(make_uint4(ev, plo, phi, 3u), P.key0, P.key1);
