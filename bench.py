@@ -61,6 +61,18 @@ LEDGER = {
 }
 LEDGER_DIPOLE = 4 * 4 + 6          # log, sqrt, exp, rcp of the dipole inversion + FMAs
 LEDGER_EMIS = 6 + 5 + 8 + 3 + 2 + 8  # camera projection, x_cam, channel, phase weight, fixed point, cache
+# VALU issue slots of one network call of the learned escape for its asking
+# lane (the matrix products run on the matrix cores and count as FLOP):
+LEDGER_CALL = {
+    "philox_2_blocks": 2 * 10 * (2 * 4 + 4),                 # the call's draws
+    "frame_condition": 20 + 2 * 4 + 10,                      # sorted |offsets|, two log10, reduced direction
+    "inputs_2_evals": 2 * (24 * 2 + 4 * (4 + 4) + 14),       # normalise, logit levels (log, rcp), bf16 + residuals
+    "hidden_epilogues_2_evals": 2 * 3 * 128 * 5 // 2,        # leaky ReLU (mul, median) + bf16 pair per value
+    "outputs": 23 * 2,                                       # de-normalise the outputs read
+    "face_side_xabs": 6 * (4 + 2) + 4 * 2 + 6,               # softmax, face and side choices, |x| of the face
+    "exit_geometry": 2 * (4 + 4 + 2) + 4 + 2 * 4 + 40,       # sinh x2, sqrt, sincos alpha, back to the cell frame
+    "deposit": 12 * (2 * 4 + 10 + 12 + 4) + 2 * 4,           # ~12 channels: erf (rcp, exp, poly), int64, atomic
+}
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12  # 39.32 T lane-slots/s (non-packed 32-bit VALU)
 PEAK_MFMA_BF16_TFLOPS = 2500.0            # dense BF16 matrix cores
 
@@ -230,11 +242,13 @@ def headline_c4(ctx, args):
     em = _agg_blocks(r0["emis_raw"].astype(np.float64), 128)
     c = r0["counters"]
     km = sum(kms) / K
-    # roofline of the learned transport kernel: plain scatterings it still runs
-    # on the VALU ledger, network evaluations on the BF16 matrix cores
+    # roofline of the learned transport kernel: the scatterings it still walks
+    # and its network calls on the VALU ledgers, network products on the BF16
+    # matrix cores
     calls = sum(r["counters"]["mlp_calls"] for r in runs) / K
     scat_l = sum(r["counters"]["scatterings"] for r in runs) / K
-    valu = scat_l * ledger_per_scatter(False, True) / (km * 1e-3) / 1e12
+    ops_call = sum(LEDGER_CALL.values())
+    valu = (scat_l * ledger_per_scatter(False, True) + calls * ops_call) / (km * 1e-3) / 1e12
     mfma = calls * 2 * MLP_FLOP_PER_EVAL / (km * 1e-3) / 1e12
     return {
         "value": scat_plain * K / wall, "K": K, "W": warm, "wall": wall,
@@ -242,7 +256,7 @@ def headline_c4(ctx, args):
         "roofline": {"bound": "alu", "achieved": valu, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
                      "frac": valu / PEAK_VALU_TOPS, "traffic": profiled_traffic(PROFILE_SUMMARY_LEARNED, N),
                      "kernel": "mc_transport_kernel<1, 512> (learned escape, fused)",
-                     "ops_per_scattering": ledger_per_scatter(False, True),
+                     "ops_per_scattering": ledger_per_scatter(False, True), "ops_per_call": ops_call,
                      "mfma": {"achieved": mfma, "peak": PEAK_MFMA_BF16_TFLOPS, "unit": "TFLOP/s",
                               "frac": mfma / PEAK_MFMA_BF16_TFLOPS,
                               "flop_per_call": 2 * MLP_FLOP_PER_EVAL}},
