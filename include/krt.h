@@ -176,7 +176,7 @@ typedef struct {
     double esc_cell_tau_min;   /* ... and only in cells of line-centre depth k0 dx at least this
                                   (0 = 100); both are raised to the smallest values the network's
                                   training records covered */
-    int32_t esc_min_lanes;     /* network call when at least this many lanes of a wave ask (0 = 24);
+    int32_t esc_min_lanes;     /* network call when at least this many lanes of a wave ask (0 = 16);
                                   see esc_wait for the lanes that find fewer */
     int32_t esc_tail_lanes;    /* as esc_min_lanes once the packet pool is exhausted (0 = 1):
                                   the wave then lives only as long as its slowest packet */
@@ -213,8 +213,10 @@ typedef struct {
                                   (0 = 256), so no round waits on one long walk */
     int32_t esc_wait;          /* fused: a lane whose scattering qualifies while fewer than
                                   esc_min_lanes lanes of its wave ask holds the scattering and
-                                  waits for a batch, for at most this many loop iterations (0 = 16;
-                                  a batch also goes when every live lane of the wave asks).  Every
+                                  waits for a batch, for at most this many loop iterations (0 = 32;
+                                  a batch also goes when every live lane of the wave asks; while
+                                  the packet pool lasts a batch of 16 or more takes whole
+                                  16-sample blocks and the askers past them stay held).  Every
                                   qualifying scattering then takes the network with its own
                                   event's draws, so the tallies do not depend on launch geometry
                                   or batching and equal esc_min_lanes = 1's bit for bit.

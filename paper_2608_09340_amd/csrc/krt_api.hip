@@ -707,9 +707,9 @@ static int mc_run_impl(krt_ctx *c, uint64_t n_packets, uint64_t seed, const krt_
                                       std::pow(10.0, (double)c->esc_ld_min));
     P.esc_x_max = kEscXMax;
     P.esc_log10a = (float)std::log10(c->lines[l].a);
-    P.esc_min_lanes = o->esc_min_lanes > 0 ? o->esc_min_lanes : 24;
+    P.esc_min_lanes = o->esc_min_lanes > 0 ? o->esc_min_lanes : 16;
     P.esc_tail_lanes = o->esc_tail_lanes > 0 ? o->esc_tail_lanes : 1;
-    P.esc_wait = o->esc_wait > 0 ? (uint32_t)o->esc_wait : (o->esc_wait == 0 ? 16u : 0u);
+    P.esc_wait = o->esc_wait > 0 ? (uint32_t)o->esc_wait : (o->esc_wait == 0 ? 32u : 0u);
     P.tail_lanes = o->tail_lanes == 0 ? 32 : (o->tail_lanes < 0 ? 0 : std::min(o->tail_lanes, 64));
     P.profile_mode = o->profile_mode;
     P.tclass = nullptr;

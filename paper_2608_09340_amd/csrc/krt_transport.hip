@@ -847,17 +847,24 @@ __global__ void __launch_bounds__(kMaxThreads) mc_transport_kernel(RunParams P) 
                 // With waiting on (esc_wait > 0) a qualifying lane that finds too few
                 // others holds its scattering (pend) instead of walking it, for at most
                 // esc_wait iterations; the batch also goes when every live lane asks.
-                const uint64_t wm = __ballot(mlp);
-                const int need_lanes = (__ballot(done) != 0ull) ? P.esc_tail_lanes : P.esc_min_lanes;
-                const bool go = wm != 0ull && (__popcll(wm) >= need_lanes || wm == __ballot(have) ||
-                                               __ballot(pend && pwait >= P.esc_wait) != 0ull);  // wave-uniform
-                if (!go) {
+                // While the pool lasts and nothing forces the batch, it takes whole
+                // 16-sample blocks only: the askers past them, in lane order, stay held.
+                uint64_t wm = __ballot(mlp);
+                const bool tailw = __ballot(done) != 0ull;
+                const int need_lanes = tailw ? P.esc_tail_lanes : P.esc_min_lanes;
+                const bool forced = wm == __ballot(have) || __ballot(pend && pwait >= P.esc_wait) != 0ull;
+                const bool go = wm != 0ull && (__popcll(wm) >= need_lanes || forced);  // wave-uniform
+                bool held = !go;
+                if (go && !tailw && !forced && P.esc_wait > 0 && mlp && __popcll(wm) >= 16)
+                    held = __popcll(wm & lanemask_lt) >= (__popcll(wm) & ~15);
+                if (held) {
                     if (mlp && P.esc_wait > 0) {
                         pwait = pend ? pwait + 1 : 1;
                         pend = true;
                     }
                     mlp = false;
                 }
+                wm = __ballot(mlp);  // the lanes this batch serves
                 // this event's plain scatterings first, so their prepared state is
                 // not live across the network evaluation
                 if (scat && !mlp && !pend) commit(q);

@@ -25,7 +25,7 @@ DEFAULT_STAGES = ((18000, 4096, 2e-3), (18000, 8192, 1e-3), (18000, 16384, 5e-4)
 # cells at least 50 line-centre mean free paths deep (raised to the training
 # records' smallest tau_c, 10^1.5 from centre to face), at scattering points at
 # least 3 below the nearest face, once 16 lanes of a wave ask (fused schedule).
-DEFAULT_RUN = {"esc_cell_tau_min": 50.0, "esc_tau_min": 3.0, "esc_min_lanes": 24, "esc_wait": 16}
+DEFAULT_RUN = {"esc_cell_tau_min": 50.0, "esc_tau_min": 3.0, "esc_min_lanes": 16, "esc_wait": 32}
 # log10 tau_c (centre to face) range of the training records for that setting
 DEFAULT_LOG10_TAU = (1.5, 5.0)
 
