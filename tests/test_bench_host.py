@@ -40,3 +40,21 @@ def test_ledger_totals():
     the emissivity tally."""
     assert bench.ledger_per_scatter(True, True) == 508
     assert bench.ledger_per_scatter(False, True) == 486
+
+
+def test_call_ledger_total_and_per_packet_traffic(tmp_path, monkeypatch):
+    """The learned kernel's call ledger sums to the 2970 lane-slots its
+    roofline uses, and a counter summary taken at fewer packets than the timed
+    launch scales its traffic per packet."""
+    assert sum(bench.LEDGER_CALL.values()) == 2970
+    s = tmp_path / "learned.md"
+    s.write_text(f"- kernel_source_sha256: `{bench.kernel_source_sha256()}`\n- hbm_bytes_per_launch: `2e+9`\n"
+                 "- hbm_bytes_per_packet: `200`\n")
+    assert bench.profiled_traffic(str(s), 10 ** 8) == 2e10
+    assert bench.profiled_traffic(str(s)) == 2e9
+
+
+def test_unknown_leg_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--legs", "nope", "--legs-only"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "unknown legs" in r.stderr
