@@ -13,18 +13,20 @@ import numpy as np
 from . import krt
 
 # (steps, batch, learning rate): Adam, learning rate halved per stage, batch
-# doubled up to 32768; 90000 steps, about 210 passes over 8e6 records (three
-# times the first recipe: on a block of chained thick cells the spectrum error
-# against the plain walk falls from L1 0.10 to 0.085, on one cell from 0.063 to
-# 0.046, for 10 s of training instead of 5)
-DEFAULT_STAGES = ((18000, 4096, 2e-3), (18000, 8192, 1e-3), (18000, 16384, 5e-4), (18000, 32768, 2.5e-4),
-                  (18000, 32768, 1.25e-4))
+# doubled up to 32768; 180000 steps, about 420 passes over 8e6 records (six
+# times the first recipe; on the 128^3 cloud at 1e7 packets the emissivity
+# error against the plain walk falls from L1 0.0125 at half as many steps to
+# 0.010, for 17 s of training instead of 10; four times as many steps gain
+# nothing more)
+DEFAULT_STAGES = ((36000, 4096, 2e-3), (36000, 8192, 1e-3), (36000, 16384, 5e-4), (36000, 32768, 2.5e-4),
+                  (36000, 32768, 1.25e-4))
 
 
 # Run options of the learned escape on the benchmark cloud: network calls in
 # cells at least 50 line-centre mean free paths deep (raised to the training
 # records' smallest tau_c, 10^1.5 from centre to face), at scattering points at
-# least 3 below the nearest face, once 16 lanes of a wave ask (fused schedule).
+# least 3 below the nearest face, in batches of whole 16-sample blocks, a
+# qualifying scattering held for at most 32 iterations (fused schedule).
 DEFAULT_RUN = {"esc_cell_tau_min": 50.0, "esc_tau_min": 3.0, "esc_min_lanes": 16, "esc_wait": 32}
 # log10 tau_c (centre to face) range of the training records for that setting
 DEFAULT_LOG10_TAU = (1.5, 5.0)
