@@ -326,8 +326,25 @@ __global__ void __launch_bounds__(256) mlp_fwdbwd_kernel(const unsigned char *bl
     mlp_inputs(r, ua, ub, uc, ud, cond, r[kRecXOut], (int)r[kRecFace], in);
     if (!live)
         for (int k = 0; k < kMlpIn; ++k) in[k] = 0.0f;
-    v4f32 z1[8], z2[8], z3[8], o, ob;
-    mlp_forward_block(blob, bias, xin_operand(in, lane), lane, z1, z2, z3, o, ob);
+    // the hidden activations go to the activation store as the forward pass
+    // makes them; the backward pass keeps only the sign of each
+    // pre-activation (bit 4 tile + component of zpos[layer]), all that the
+    // derivative of the leaky ReLU needs
+    const int64_t col = (int64_t)block * 16 + s;
+    auto store4 = [&](int row0, float a0, float a1, float a2, float a3) {  // rows row0 + 4g + j
+        uint16_t *p = act + (int64_t)(row0 + 4 * g) * cap + col;
+        p[0] = f2bf(a0); p[cap] = f2bf(a1); p[2 * cap] = f2bf(a2); p[3 * cap] = f2bf(a3);
+    };
+    uint32_t zpos[3] = {0u, 0u, 0u};
+    auto epi = [&](int layer, int mo, const v4f32 &z) __attribute__((always_inline)) {
+        store4((layer == 0 ? kActH1 : (layer == 1 ? kActH2 : kActH3)) + 16 * mo, leaky(z.x), leaky(z.y), leaky(z.z),
+               leaky(z.w));
+        const uint32_t b = (z.x > 0.0f ? 1u : 0u) | (z.y > 0.0f ? 2u : 0u) | (z.z > 0.0f ? 4u : 0u) |
+                           (z.w > 0.0f ? 8u : 0u);
+        zpos[layer] |= b << (4 * mo);
+    };
+    v4f32 o, ob;
+    mlp_forward_block(blob, bias, xin_operand(in, lane), lane, epi, o, ob);
     const float ov[8] = {o.x, o.y, o.z, o.w, ob.x, ob.y, ob.z, ob.w};
     // the six face logits of this lane's sample (lanes s and s + 16)
     float fl[6];
@@ -395,11 +412,8 @@ __global__ void __launch_bounds__(256) mlp_fwdbwd_kernel(const unsigned char *bl
     if (lane == 0 && loss) atomicAdd(loss, lsum * invB);
 
     // ---- backward through the layers (dZ4 = dO)
-    const int64_t col = (int64_t)block * 16 + s;
-    auto store4 = [&](int row0, float a0, float a1, float a2, float a3) {  // rows row0 + 4g + j
-        uint16_t *p = act + (int64_t)(row0 + 4 * g) * cap + col;
-        p[0] = f2bf(a0); p[cap] = f2bf(a1); p[2 * cap] = f2bf(a2); p[3 * cap] = f2bf(a3);
-    };
+    // the leaky ReLU's derivative at pre-activation component j of tile mi
+    auto dl = [&](int layer, int mi, int j) { return ((zpos[layer] >> (4 * mi + j)) & 1u) ? 1.0f : kLeak; };
     // inputs (rows 0..23; lane group g holds inputs 8g..8g+7)
     if (g < 3) {
         uint16_t *p = act + (int64_t)(kActH0 + 8 * g) * cap + col;
@@ -416,9 +430,7 @@ __global__ void __launch_bounds__(256) mlp_fwdbwd_kernel(const unsigned char *bl
     for (int mi = 0; mi < 8; ++mi) {
         v4f32 acc = {0.f, 0.f, 0.f, 0.f};
         acc = mfma32(tileA(blob, kTileBwdL4 + mi, lane), dOb, acc);
-        dz[mi] = (v4f32){acc.x * dleaky(z3[mi].x), acc.y * dleaky(z3[mi].y), acc.z * dleaky(z3[mi].z),
-                         acc.w * dleaky(z3[mi].w)};
-        store4(kActH3 + 16 * mi, leaky(z3[mi].x), leaky(z3[mi].y), leaky(z3[mi].z), leaky(z3[mi].w));
+        dz[mi] = (v4f32){acc.x * dl(2, mi, 0), acc.y * dl(2, mi, 1), acc.z * dl(2, mi, 2), acc.w * dl(2, mi, 3)};
         store4(kActZ3 + 16 * mi, dz[mi].x, dz[mi].y, dz[mi].z, dz[mi].w);
     }
     // layer 3 -> dZ2, layer 2 -> dZ1 (unrolled so the activations stay in registers)
@@ -433,9 +445,8 @@ __global__ void __launch_bounds__(256) mlp_fwdbwd_kernel(const unsigned char *bl
             v4f32 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int c = 0; c < 4; ++c) acc = mfma32(tileA(blob, tb + mi * 4 + c, lane), cat8(dzb[2 * c], dzb[2 * c + 1]), acc);
-            const v4f32 zin = (layer == 3) ? z2[mi] : z1[mi];
-            dz[mi] = (v4f32){acc.x * dleaky(zin.x), acc.y * dleaky(zin.y), acc.z * dleaky(zin.z), acc.w * dleaky(zin.w)};
-            store4((layer == 3 ? kActH2 : kActH1) + 16 * mi, leaky(zin.x), leaky(zin.y), leaky(zin.z), leaky(zin.w));
+            const int zl = (layer == 3) ? 1 : 0;
+            dz[mi] = (v4f32){acc.x * dl(zl, mi, 0), acc.y * dl(zl, mi, 1), acc.z * dl(zl, mi, 2), acc.w * dl(zl, mi, 3)};
             store4((layer == 3 ? kActZ2 : kActZ1) + 16 * mi, dz[mi].x, dz[mi].y, dz[mi].z, dz[mi].w);
         }
     }
@@ -638,7 +649,7 @@ __global__ void __launch_bounds__(256) mlp_forward_kernel(const unsigned char *b
     float in[kMlpIn];
     mlp_inputs(r, r[10], r[11], r[12], r[13], r[14] > 0.5f, r[15], (int)r[16], in);
     v4f32 o, ob;
-    mlp_forward_block(blob, bias, xin_operand(in, lane), lane, nullptr, nullptr, nullptr, o, ob);
+    mlp_forward_block(blob, bias, xin_operand(in, lane), lane, NoEpi{}, o, ob);
     if (!live) return;
     const float v[8] = {o.x, o.y, o.z, o.w, ob.x, ob.y, ob.z, ob.w};
     for (int j = 0; j < 8; ++j) {
@@ -673,7 +684,7 @@ __global__ void __launch_bounds__(256) mlp_calib_kernel(const unsigned char *blo
         float in[kMlpIn];
         mlp_inputs(r, u01(q.x), u01(q.y), u01(q.z), u01(q.w), false, 0.0f, 0, in);
         v4f32 o, ob;
-        mlp_forward_block(blob, bias, xin_operand(in, lane), lane, nullptr, nullptr, nullptr, o, ob);
+        mlp_forward_block(blob, bias, xin_operand(in, lane), lane, NoEpi{}, o, ob);
         static_assert(kOutLogN == 7, "ln E[N_s] sits in lane group 1, component 3");
         if (live && g == 1 && r[kRecX] <= kEscXMax) {
             const int b = cal_bin(r[kRecLT], r[kRecLD], r[kRecX]);

@@ -160,7 +160,7 @@ __device__ __forceinline__ uint16_t f2bf(float f) { return (uint16_t)(pack2(f, 0
 __device__ __forceinline__ float sigmoid_f(float z) {
     return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.44269504088896f * z));
 }
-// Hidden activation: leaky ReLU, max(z, z / 16), and its derivative.  Two
+// Hidden activation: leaky ReLU, max(z, z / 16) (derivative 1 or 1/16).  Two
 // full-rate instructions per value: the network runs inside the transport
 // kernel, where a transcendental activation (SiLU: an exp and a reciprocal,
 // quarter rate each) cost more issue cycles than the matrix products.  The max
@@ -168,7 +168,6 @@ __device__ __forceinline__ float sigmoid_f(float z) {
 // signalling NaN in the MFMA result with one more instruction per value.
 constexpr float kLeak = 0.0625f;
 __device__ __forceinline__ float leaky(float z) { return __builtin_amdgcn_fmed3f(z, kLeak * z, 3.40282347e38f); }
-__device__ __forceinline__ float dleaky(float z) { return z > 0.0f ? 1.0f : kLeak; }
 
 __device__ __forceinline__ v4i16 pack4(float a, float b, float c, float d) {
     const uint32_t lo = pack2(a, b), hi = pack2(c, d);
@@ -190,8 +189,9 @@ __device__ __forceinline__ v8i16 tileA(const unsigned char *blob, int t, int lan
 // Forward pass of one 16-sample block.  xin: this lane's B operand for layer 1
 // (lane l holds inputs 8(l/16)..8(l/16)+7 of sample l%16).  Returns the two
 // output tiles: lane l holds outputs 4(l/16)+r (oa) and 16+4(l/16)+r (ob) of
-// sample l%16.  If z1..z3 are given, the pre-activations are stored (8 tiles
-// each) for the backward pass.
+// sample l%16.  epi(layer, tile, z) sees each hidden layer's pre-activations
+// (layer 0..2, row tile 0..7) before the activation: the training pass stores
+// what its backward pass needs; inference passes NoEpi.
 //
 // The 80 products run in one fixed order (fwd_tile): layer 1's 8 row tiles,
 // layers 2 and 3 chunk-major (the 8 row tiles of reduction chunk c, then
@@ -217,8 +217,13 @@ static_assert(kTilesFwd == kFwdSteps, "one product per forward tile");
 
 __device__ __forceinline__ v4f32 ld4(const float *p) { return *reinterpret_cast<const v4f32 *>(p); }
 
+struct NoEpi {
+    __device__ __forceinline__ void operator()(int, int, const v4f32 &) const {}
+};
+
+template <class Epi>
 __device__ __forceinline__ void mlp_forward_block(const unsigned char *tiles, const float *bias, v8i16 xin,
-                                                  int lane, v4f32 *z1, v4f32 *z2, v4f32 *z3, v4f32 &oa, v4f32 &ob) {
+                                                  int lane, Epi epi, v4f32 &oa, v4f32 &ob) {
     const int g = lane >> 4;
     v8i16 w[8];
 #pragma unroll
@@ -239,7 +244,7 @@ __device__ __forceinline__ void mlp_forward_block(const unsigned char *tiles, co
     for (int mo = 0; mo < 8; ++mo) KRT_FWD_STEP(mo, xin, acc[mo]);
 #pragma unroll
     for (int mo = 0; mo < 8; ++mo) {
-        if (z1) z1[mo] = acc[mo];
+        epi(0, mo, acc[mo]);
         h[mo] = pack4(leaky(acc[mo].x), leaky(acc[mo].y), leaky(acc[mo].z), leaky(acc[mo].w));
         acc[mo] = ld4(bias + kMlpHid + 16 * mo + 4 * g);
     }
@@ -253,10 +258,9 @@ __device__ __forceinline__ void mlp_forward_block(const unsigned char *tiles, co
 #pragma unroll
             for (int mo = 0; mo < 8; ++mo) KRT_FWD_STEP(base + 8 * c + mo, bop, acc[mo]);
         }
-        v4f32 *zs = layer == 0 ? z2 : z3;
 #pragma unroll
         for (int mo = 0; mo < 8; ++mo) {
-            if (zs) zs[mo] = acc[mo];
+            epi(1 + layer, mo, acc[mo]);
             h[mo] = pack4(leaky(acc[mo].x), leaky(acc[mo].y), leaky(acc[mo].z), leaky(acc[mo].w));
             if (layer == 0) acc[mo] = ld4(bias + 2 * kMlpHid + 16 * mo + 4 * g);
         }

@@ -119,7 +119,7 @@ __device__ __forceinline__ void mlp_eval_wave(const unsigned char *img, const fl
         const v4i16 hi = {(short)(use ? w[2] & 0xFFFFu : 0u), (short)(use ? w[2] >> 16 : 0u),
                           (short)(use ? w[3] & 0xFFFFu : 0u), (short)(use ? w[3] >> 16 : 0u)};
         v4f32 oa, ob;
-        mlp_forward_block(img, bias, cat8(lo, hi), lane, nullptr, nullptr, nullptr, oa, ob);
+        mlp_forward_block(img, bias, cat8(lo, hi), lane, NoEpi{}, oa, ob);
         // output k of block position p sits in lane 16 ((k % 16) / 4) + p,
         // component k % 4, of tile k / 16
         const bool take = mine && (rank >> 4) == b;
