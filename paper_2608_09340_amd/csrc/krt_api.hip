@@ -1287,15 +1287,14 @@ extern "C" int krt_escape_train(krt_ctx *c, const float *samples_dev, uint64_t n
     HIPCHK(c, hipSetDevice(c->device));
     int rc = mlp_ensure_batch(c, batch);
     if (rc) return rc;
+    // each step's loss is summed straight into its slot of the history
+    if (loss_hist_dev) HIPCHK(c, hipMemsetAsync(loss_hist_dev, 0, sizeof(float) * (size_t)steps, c->stream));
     for (int s = 0; s < steps; ++s) {
         c->mlp_step += 1;
         HIPCHK(c, launch_mlp_batch((int64_t)n, (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)c->mlp_step, batch,
                                    c->mlp_idx, c->mlp_u, c->stream));
-        float *lslot = loss_hist_dev ? loss_hist_dev + s : c->mlp_loss;
-        if (loss_hist_dev) HIPCHK(c, launch_zero_i64(reinterpret_cast<int64_t *>(c->mlp_loss), 1, c->stream));
         HIPCHK(c, launch_mlp_grad(c->mlp_blob, samples_dev, c->mlp_idx, c->mlp_u, batch, c->mlp_act, c->mlp_act_cap,
-                                  c->mlp_part, loss_hist_dev ? c->mlp_loss : nullptr, c->stream));
-        if (loss_hist_dev) HIPCHK(c, hipMemcpyAsync(lslot, c->mlp_loss, sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+                                  c->mlp_part, loss_hist_dev ? loss_hist_dev + s : nullptr, c->stream));
         HIPCHK(c, launch_mlp_adam(c->mlp_p, c->mlp_m, c->mlp_v, c->mlp_part, (float)lr, c->mlp_step, c->stream));
         HIPCHK(c, launch_mlp_pack(c->mlp_p, c->mlp_norm, c->mlp_blob, (s == steps - 1) ? c->mlp_img : nullptr,
                                   c->stream));
