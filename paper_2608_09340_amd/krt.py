@@ -467,9 +467,11 @@ class Transport:
         self.ctx.krt_image(d)
         return out
 
-    def run(self, n_packets: int, seed: int = 0, packet_log: bool = False, noalloc: bool = False, **kw) -> dict:
+    def run(self, n_packets: int, seed: int = 0, packet_log: bool = False, noalloc: bool = False,
+            host: bool = True, **kw) -> dict:
         """One krt_mc_run (or krt_mc_run_noalloc) over this workload; returns the
-        raw tallies and counters on the host."""
+        raw tallies and counters on the host (host=False: the counters only, the
+        tallies stay in this object's device tensors until the next run)."""
         self._ensure_bound()
         opts = make_opts(self.prob, **kw)
         plog = None
@@ -477,8 +479,10 @@ class Transport:
             plog = self.torch.zeros((n_packets, 8), dtype=self.torch.float32, device=self.dev)
         call = self.ctx.krt_mc_run_noalloc if noalloc else self.ctx.krt_mc_run
         rc = call(n_packets, seed, opts, self.tallies(plog))
-        out = {"rc": rc, "spec_raw": self.spec_raw.cpu().numpy().copy(),
-               "counters": dict(zip(COUNTER_NAMES, self.counters.cpu().numpy()[:len(COUNTER_NAMES)].tolist()))}
+        out = {"rc": rc, "counters": dict(zip(COUNTER_NAMES, self.counters.cpu().numpy()[:len(COUNTER_NAMES)].tolist()))}
+        if not host:
+            return out
+        out["spec_raw"] = self.spec_raw.cpu().numpy().copy()
         if self.emis_raw is not None:
             out["emis_raw"] = self.emis_raw.cpu().numpy().reshape(self.ncell, self.nch).copy()
         if self.jbar_raw is not None:
