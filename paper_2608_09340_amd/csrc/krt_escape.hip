@@ -483,28 +483,11 @@ __global__ void __launch_bounds__(256) mlp_wgrad_kernel(const uint16_t *act, int
     const int c0 = (int)((int64_t)nchunk * split / kGradSplits), c1 = (int)((int64_t)nchunk * (split + 1) / kGradSplits);
     const uint16_t *ha = act + (int64_t)(hrow + 16 * it + s) * cap + 8 * g;
     const uint16_t *zb = act + (int64_t)(zrow + 16 * jt + s) * cap + 8 * g;
-    // the products accumulate in chunk order; the operands of the next four
-    // chunks are in flight while one is multiplied
     v4f32 acc = {0.f, 0.f, 0.f, 0.f};
-    constexpr int kAhead = 4;
-    v8i16 a[kAhead], b[kAhead];
-#pragma unroll
-    for (int k = 0; k < kAhead; ++k)
-        if (c0 + k < c1) {
-            a[k] = *reinterpret_cast<const v8i16 *>(ha + 32 * (c0 + k));
-            b[k] = *reinterpret_cast<const v8i16 *>(zb + 32 * (c0 + k));
-        }
-    for (int c = c0; c < c1; c += kAhead) {  // wave-uniform
-#pragma unroll
-        for (int k = 0; k < kAhead; ++k) {
-            if (c + k < c1) {
-                acc = mfma32(a[k], b[k], acc);
-                if (c + k + kAhead < c1) {
-                    a[k] = *reinterpret_cast<const v8i16 *>(ha + 32 * (c + k + kAhead));
-                    b[k] = *reinterpret_cast<const v8i16 *>(zb + 32 * (c + k + kAhead));
-                }
-            }
-        }
+    for (int c = c0; c < c1; ++c) {
+        const v8i16 a = *reinterpret_cast<const v8i16 *>(ha + 32 * c);
+        const v8i16 b = *reinterpret_cast<const v8i16 *>(zb + 32 * c);
+        acc = mfma32(a, b, acc);
     }
     float *dst = part + (int64_t)split * kNParams;
     const float v[4] = {acc.x, acc.y, acc.z, acc.w};
