@@ -10,6 +10,7 @@
 #include <atomic>
 #include <string>
 #include <thread>
+#include <system_error>
 #include <vector>
 
 #include "krt.h"
@@ -174,7 +175,13 @@ static int ensure_cont_tables(krt_ctx *c, int l) {
     };
     const int nt = std::max(1, std::min<int>((int)std::thread::hardware_concurrency(), nv + ns));
     std::vector<std::thread> pool;
-    for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+    for (int t = 1; t < nt; ++t) {
+        try {
+            pool.emplace_back(work);
+        } catch (const std::system_error &) {
+            break;  // no more threads: the ones started (and this one) take the rest
+        }
+    }
     work();
     for (auto &t : pool) t.join();
     std::copy(hv.begin() + (size_t)(nv - 1) * kVoigtFloats, hv.begin() + (size_t)nv * kVoigtFloats,
