@@ -72,7 +72,8 @@ LEDGER_CALL = {
     "outputs": 23 * 2,                                       # de-normalise the outputs read
     "face_side_xabs": 6 * (4 + 2) + 4 * 2 + 6,               # softmax, face and side choices, |x| of the face
     "exit_geometry": 2 * (4 + 4 + 2) + 4 + 2 * 4 + 40,       # sinh x2, sqrt, sincos alpha, back to the cell frame
-    "deposit": 12 * (2 * 4 + 10 + 12 + 4) + 2 * 4,           # ~12 channels: erf (rcp, exp, poly), int64, atomic
+    "deposit": 6 * (2 * 4 + 10 + 12 + 4) + 2 * 4 + 2 * 26,   # ~6 channels within 3 sd: erf (rcp, exp, poly), int64,
+                                                             # atomic; two more erf for the coverage
 }
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12  # 39.32 T lane-slots/s (non-packed 32-bit VALU)
 PEAK_MFMA_BF16_TFLOPS = 2500.0            # dense BF16 matrix cores

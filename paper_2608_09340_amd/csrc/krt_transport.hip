@@ -243,9 +243,11 @@ __device__ __forceinline__ float erf_fast(float x) {
 // frame, fx, fy, fz in [0, 1]), the exit direction, the lab frequency
 // x = sign(xc) xo + n.v, and the expected number of skipped scatterings
 // E[N_s] (calibrated), whose emissivity -- thermalised core, camera frequency
-// ~ N(n_cam.v, (<x^2> + 1)/3), integrated exactly over the channels -- goes to
-// dep(channel, fixed-point weight); mass outside the channels is added to
-// n_drop.  alpha takes its sign from the lowest bit of C.z.
+// ~ N(n_cam.v, (<x^2> + 1)/3), integrated exactly over the whole channels that
+// meet the central +-3 sd and renormalised to their share of it (the tails
+// beyond hold 0.27%) -- goes to dep(channel, fixed-point weight); mass outside
+// the channel grid is added to n_drop.  alpha takes its sign from the lowest
+// bit of C.z.
 template <class Dep>
 __device__ __forceinline__ void call_apply(const RunParams &P, const float *mnorm, const float *cedges,
                                            const CellFrame &CF, const float mo[kMlpOut], int face, float xo,
@@ -301,12 +303,18 @@ __device__ __forceinline__ void call_apply(const RunParams &P, const float *mnor
         const float sd = f_sqrt((f_exp(lx2) + 1.0f) * (1.0f / 3.0f));
         const float vc = P.n_cam[0] * vxc + P.n_cam[1] * vyc + P.n_cam[2] * vzc;
         const float isd = kInvSqrt2F * f_rcp(sd);
-        const float W = Ns * P.frac_scale;
-        int kb0 = bin_index(vc - 6.0f * sd, cedges, P.emis_nch, P.ch_inv_w);
-        int kb1 = bin_index(vc + 6.0f * sd, cedges, P.emis_nch, P.ch_inv_w);
-        kb0 = max(kb0, 1);
-        kb1 = min(kb1, P.emis_nch);
-        float cdf_lo = 0.5f * (1.0f + erf_fast((cedges[kb0 - 1] - vc) * isd));
+        auto cdf = [&](float e) { return 0.5f * (1.0f + erf_fast((e - vc) * isd)); };
+        const float wlo = vc - 3.0f * sd, whi = vc + 3.0f * sd;
+        const int kb0u = bin_index(wlo, cedges, P.emis_nch, P.ch_inv_w);
+        const int kb1u = bin_index(whi, cedges, P.emis_nch, P.ch_inv_w);
+        const int kb0 = max(kb0u, 1), kb1 = min(kb1u, P.emis_nch);
+        float cdf_lo = cdf(cedges[kb0 - 1]);
+        // the Gaussian's mass over the channels met (the window's own ends where
+        // it leaves the grid): the deposits are scaled by its inverse
+        const float c_first = (kb0u >= 1) ? cdf_lo : cdf(wlo);
+        const float c_last = cdf((kb1u >= 0 && kb1u <= P.emis_nch) ? cedges[kb1] : whi);
+        const float inv_cov = f_rcp(fmaxf(c_last - c_first, 0.5f));
+        const float W = Ns * P.frac_scale * inv_cov;
         float inside = 0.0f;
         for (int kb = kb0; kb <= kb1; ++kb) {
             const float cdf_hi = 0.5f * (1.0f + erf_fast((cedges[kb] - vc) * isd));
@@ -316,7 +324,7 @@ __device__ __forceinline__ void call_apply(const RunParams &P, const float *mnor
             const int64_t wq = (int64_t)__float2ll_rn(W * fr);
             if (wq != 0) dep(kb - 1, wq);
         }
-        n_drop += (int64_t)__float2ll_rn(Ns * fmaxf(0.0f, 1.0f - inside));
+        n_drop += (int64_t)__float2ll_rn(Ns * fmaxf(0.0f, 1.0f - inside * inv_cov));
     }
     const float sx = (xc < 0.0f) ? -1.0f : 1.0f;
     x = sx * xo + nx * vxc + ny * vyc + nz * vzc;

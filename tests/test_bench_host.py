@@ -43,10 +43,10 @@ def test_ledger_totals():
 
 
 def test_call_ledger_total_and_per_packet_traffic(tmp_path, monkeypatch):
-    """The learned kernel's call ledger sums to the 2970 lane-slots its
+    """The learned kernel's call ledger sums to the 2818 lane-slots its
     roofline uses, and a counter summary taken at fewer packets than the timed
     launch scales its traffic per packet."""
-    assert sum(bench.LEDGER_CALL.values()) == 2970
+    assert sum(bench.LEDGER_CALL.values()) == 2818
     s = tmp_path / "learned.md"
     s.write_text(f"- kernel_source_sha256: `{bench.kernel_source_sha256()}`\n- hbm_bytes_per_launch: `2e+9`\n"
                  "- hbm_bytes_per_packet: `200`\n")
