@@ -139,8 +139,8 @@ def cpu_info():
 
 
 def cpu_baseline(prob, seconds_target=20.0, workload=""):
-    """The FP64 oracle as it stands, on all host cores (at most 16, the box's
-    share), on a bounded sample of the same workload with the plain walk:
+    """The FP64 oracle as it stands, on the host's cores (at most 16 threads,
+    one GPU's share of a shared host), on a bounded sample of the same workload with the plain walk:
     consecutive batches of packets, each sized from the rate so far, until
     about `seconds_target` seconds of oracle work have run."""
     import oracle
