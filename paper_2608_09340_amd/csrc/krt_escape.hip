@@ -454,11 +454,12 @@ __global__ void __launch_bounds__(256) mlp_fwdbwd_kernel(const unsigned char *bl
 
 // Weight gradients as products over the stored activations: dW_l[in][out] =
 // sum_s H_{l-1}[in][s] dZ_l[out][s], the bias from the constant row.  One wave
-// per (layer, 16-row tile, 16-column tile, sample split); results go to
-// part[split][param] (every parameter is written by exactly one wave per split,
-// so the sum over splits in fixed order is deterministic).
-constexpr int kGradJobsL1 = 2 * 8, kGradJobsL2 = 9 * 8, kGradJobsL3 = 9 * 8, kGradJobsL4 = 9 * 2;
-constexpr int kGradJobs = kGradJobsL1 + kGradJobsL2 + kGradJobsL3 + kGradJobsL4;   // 178
+// per (layer, 16-row tile, pair of 16-column tiles, sample split): the H
+// operand of a chunk feeds both tiles' products.  Results go to
+// part[split][param] (every parameter is written by exactly one wave per
+// split, so the sum over splits in fixed order is deterministic).
+constexpr int kGradJobsL1 = 2 * 4, kGradJobsL2 = 9 * 4, kGradJobsL3 = 9 * 4, kGradJobsL4 = 9 * 1;
+constexpr int kGradJobs = kGradJobsL1 + kGradJobsL2 + kGradJobsL3 + kGradJobsL4;   // 89
 
 __global__ void __launch_bounds__(256) mlp_wgrad_kernel(const uint16_t *act, int64_t cap, int kcols, float *part) {
     const int lane = __lane_id(), w = threadIdx.x / 64;
@@ -466,37 +467,44 @@ __global__ void __launch_bounds__(256) mlp_wgrad_kernel(const uint16_t *act, int
     if (job >= kGradJobs * kGradSplits) return;
     const int split = job / kGradJobs;
     int jj = job % kGradJobs;
-    int hrow, zrow, it, jt, nin, ldw, pw, pb;
+    int hrow, zrow, it, jp, nin, ldw, pw, pb;
     if (jj < kGradJobsL1) {
-        it = jj / 8; jt = jj % 8; hrow = kActH0; zrow = kActZ1; nin = kMlpIn; ldw = kMlpHid; pw = kPW1; pb = kPB1;
+        it = jj / 4; jp = jj % 4; hrow = kActH0; zrow = kActZ1; nin = kMlpIn; ldw = kMlpHid; pw = kPW1; pb = kPB1;
     } else if ((jj -= kGradJobsL1) < kGradJobsL2) {
-        it = jj / 8; jt = jj % 8; hrow = kActH1; zrow = kActZ2; nin = kMlpHid; ldw = kMlpHid; pw = kPW2; pb = kPB2;
+        it = jj / 4; jp = jj % 4; hrow = kActH1; zrow = kActZ2; nin = kMlpHid; ldw = kMlpHid; pw = kPW2; pb = kPB2;
     } else if ((jj -= kGradJobsL2) < kGradJobsL3) {
-        it = jj / 8; jt = jj % 8; hrow = kActH2; zrow = kActZ3; nin = kMlpHid; ldw = kMlpHid; pw = kPW3; pb = kPB3;
+        it = jj / 4; jp = jj % 4; hrow = kActH2; zrow = kActZ3; nin = kMlpHid; ldw = kMlpHid; pw = kPW3; pb = kPB3;
     } else {
         jj -= kGradJobsL3;
-        it = jj / 2; jt = jj % 2; hrow = kActH3; zrow = kActZ4; nin = kMlpHid; ldw = kMlpOut; pw = kPW4; pb = kPB4;
+        it = jj; jp = 0; hrow = kActH3; zrow = kActZ4; nin = kMlpHid; ldw = kMlpOut; pw = kPW4; pb = kPB4;
     }
     const int s = lane % 16, g = lane / 16;
     // this split's columns: chunks of 32 samples
     const int nchunk = kcols / 32;
     const int c0 = (int)((int64_t)nchunk * split / kGradSplits), c1 = (int)((int64_t)nchunk * (split + 1) / kGradSplits);
     const uint16_t *ha = act + (int64_t)(hrow + 16 * it + s) * cap + 8 * g;
-    const uint16_t *zb = act + (int64_t)(zrow + 16 * jt + s) * cap + 8 * g;
-    v4f32 acc = {0.f, 0.f, 0.f, 0.f};
+    const uint16_t *zb0 = act + (int64_t)(zrow + 32 * jp + s) * cap + 8 * g;
+    const uint16_t *zb1 = zb0 + 16 * cap;
+    v4f32 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
     for (int c = c0; c < c1; ++c) {
         const v8i16 a = *reinterpret_cast<const v8i16 *>(ha + 32 * c);
-        const v8i16 b = *reinterpret_cast<const v8i16 *>(zb + 32 * c);
-        acc = mfma32(a, b, acc);
+        const v8i16 b0 = *reinterpret_cast<const v8i16 *>(zb0 + 32 * c);
+        const v8i16 b1 = *reinterpret_cast<const v8i16 *>(zb1 + 32 * c);
+        acc0 = mfma32(a, b0, acc0);
+        acc1 = mfma32(a, b1, acc1);
     }
     float *dst = part + (int64_t)split * kNParams;
-    const float v[4] = {acc.x, acc.y, acc.z, acc.w};
-    const int out = 16 * jt + s;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int in = 16 * it + 4 * g + r;
-        if (in < nin) dst[pw + in * ldw + out] = v[r];
-        else if (in == nin) dst[pb + out] = v[r];  // the constant row: bias gradient
+    for (int t = 0; t < 2; ++t) {
+        const v4f32 acc = t ? acc1 : acc0;
+        const float v[4] = {acc.x, acc.y, acc.z, acc.w};
+        const int out = 16 * (2 * jp + t) + s;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int in = 16 * it + 4 * g + r;
+            if (in < nin) dst[pw + in * ldw + out] = v[r];
+            else if (in == nin) dst[pb + out] = v[r];  // the constant row: bias gradient
+        }
     }
 }
 
